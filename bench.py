@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Throughput of the nested-grid PM step on one MI355X.
+
+Workload (the one the metric is quoted on): the disc-bulge-halo galaxy on
+3 nested 128^3 grids (half-extents 1, 4, 20; inner two flattened to q = 1/4),
+8.5M particles (2M disc, 0.5M bulge, 6M halo), FP32 with FP64 diagnostics
+every 10 steps, dt = 0.01.  One step = loss test and centre of mass, mass
+assignment, the 5 isolated 128^3 solves, Eq. 8 forces with the
+grid-selection rule, kick and drift.
+
+Prints one JSON line: particle-steps/s of the FP32 form (value), the FP64 form
+on the same workload, standalone batched 128^3 solves/s in both precisions,
+per-phase GPU times from HIP events recorded on the library's stream during
+the timed region, the roofline of the dominant kernel, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def phase_bytes(phase, N, nsolves, n_live, esz):
+    """Algorithmic HBM bytes of one launch of a phase (the data it must read
+    and write once): FFT passes per the pruned layout, particle kernels per
+    the SoA fields they touch."""
+    cplx = 2 * esz
+    cells = N ** 3
+    X = (N + 1) * N * N * cplx       # half spectrum after the x pass
+    Cb = (N + 1) * 2 * N * N * cplx  # after the y pass (z < N kept)
+    H = (N + 1) ** 3 * esz
+    per_solve = {
+        "fwd_x": cells * esz + X,
+        "fwd_y": X + Cb,
+        "zpass": 2 * Cb + H,
+        "inv_y": Cb + X,
+        "inv_x": X + cells * esz,
+    }
+    if phase in per_solve:
+        return per_solve[phase] * nsolves
+    grids = nsolves * cells * esz
+    if phase == "zero":
+        return grids
+    if phase == "pre":      # x, m, gal, lost
+        return n_live * (4 * esz + 2)
+    if phase == "deposit":  # x, m, gal, lost read; grids written once
+        return n_live * (4 * esz + 2) + grids
+    if phase == "force":    # x, v, gal, lost read; x, v written; fields read once
+        return n_live * (12 * esz + 2) + grids
+    return 0
+
+
+def time_solves(sbx, torch, N, R, q, prec, batch, iters):
+    dt = torch.float64 if prec == sbx.SBX_FP64 else torch.float32
+    g = torch.Generator(device="cuda").manual_seed(1736)
+    rho = torch.rand((batch, N, N, N), dtype=dt, device="cuda", generator=g)
+    phi = torch.empty_like(rho)
+    stream = torch.cuda.current_stream()
+    p = sbx.Poisson(N, R, q, prec=prec, stream=stream.cuda_stream)
+    for _ in range(3):
+        p.sbx_poisson_solve(batch, rho.data_ptr(), phi.data_ptr())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(iters):
+        p.sbx_poisson_solve(batch, rho.data_ptr(), phi.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    p.close()
+    del rho, phi
+    return batch / (ms * 1e-3), ms
+
+
+def make_ctx(sbx, w, prec):
+    from paper_1210_1736_amd import sbx as S
+    cent = {"com": S.SBX_CENTRE_COM, "fixed": S.SBX_CENTRE_FIXED}
+    hs = [S.make_hierarchy([(L.N, L.R, L.q) for L in h.levels], cent[h.centring], h.centre,
+                           h.outer_centre) for h in w.hier]
+    ctx = S.Context(prec=prec, G=w.G)
+    ctx.sbx_build_grids(hs)
+    ctx.sbx_load_particles(w.x, w.v, w.m, w.comp, w.gal)
+    return ctx
+
+
+def timed_steps(sbx, torch, w, prec, steps, warmup, diag_every, profile=True):
+    ctx = make_ctx(sbx, w, prec)
+    ctx.sbx_step(w.dt, warmup, diag_every)
+    ctx.sbx_sync()
+    live0 = ctx.sbx_count_live()
+    if profile:
+        ctx.sbx_profile_begin(64 * (steps + 2))
+    torch.cuda.synchronize()
+    ctx.sbx_sync()
+    t0 = time.perf_counter()
+    ctx.sbx_step(w.dt, steps, diag_every)
+    ctx.sbx_sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = ctx.sbx_profile_end() if profile else {}
+    live1 = ctx.sbx_count_live()
+    ctx.close()
+    return t1 - t0, 0.5 * (live0 + live1), phases
+
+
+def cpu_baseline(w, frac):
+    """The FP64 oracle, as it stands, on a bounded sample: one step of the
+    same galaxy with a random `frac` of its particles (same grids)."""
+    from oracle import pm_oracle as O
+    rng = np.random.default_rng(1736)
+    n = int(w.n * frac)
+    s = rng.choice(w.n, n, replace=False)
+    hs = []
+    for h in w.hier:
+        lv = [O.Level(L.N, L.R, L.q) for L in h.levels[:2]]
+        lv.append(O.Level(h.levels[2].N, h.levels[2].R, h.levels[2].q, centre=h.outer_centre))
+        hs.append(O.Hierarchy(lv, h.centring, h.centre))
+    sysm = O.System(hs, G=w.G)
+    x, v, m = w.x[s], w.v[s], w.m[s]
+    gal = w.gal[s]
+    lost = np.zeros(n, bool)
+    t0 = time.perf_counter()
+    sysm.step(x, v, m, gal, lost, w.dt)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 step of the same galaxy and grids with {n} of its {w.n} particles "
+                      f"(random {frac:.0%}), numpy float64 single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--fp64-steps", type=int, default=20)
+    ap.add_argument("--solve-iters", type=int, default=20)
+    ap.add_argument("--diag-every", type=int, default=10)
+    ap.add_argument("--cpu-frac", type=float, default=0.3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1210_1736_amd import sbx
+
+    _log("generating the 3 x 128^3 disc-galaxy workload (8.5M particles)")
+    w = synth.disc_galaxy(scale=1.0)
+    N = w.hier[0].levels[0].N
+    nsolves = 5
+
+    _log(f"FP32: {args.warmup} warmup + {args.steps} timed steps")
+    t32, live32, ph32 = timed_steps(sbx, torch, w, sbx.SBX_FP32, args.steps, args.warmup,
+                                    args.diag_every)
+    value = live32 * args.steps / t32
+    _log(f"FP32 {value:.4g} particle-steps/s ({1e3 * t32 / args.steps:.3f} ms/step)")
+
+    fp64 = None
+    if not args.no_fp64:
+        _log(f"FP64: {args.fp64_steps} timed steps")
+        t64, live64, ph64 = timed_steps(sbx, torch, w, sbx.SBX_FP64, args.fp64_steps, 2,
+                                        args.diag_every)
+        fp64 = {"particle_steps_per_s": live64 * args.fp64_steps / t64,
+                "ms_per_step": 1e3 * t64 / args.fp64_steps,
+                "phases_ms_per_step": {k: v[0] / args.fp64_steps for k, v in ph64.items() if v[1]}}
+
+    _log("standalone 128^3 solves")
+    solves = {}
+    for name, prec in (("fp32", sbx.SBX_FP32), ("fp64", sbx.SBX_FP64)):
+        for batch in (5, 20):
+            rate, ms = time_solves(sbx, torch, 128, 4.0, 0.25, prec, batch, args.solve_iters)
+            solves[f"{name}_batch{batch}"] = {"solves_per_s": rate, "ms_per_batch": ms}
+    torch.cuda.synchronize()
+
+    # roofline of the dominant kernel of the FP32 step
+    steps = args.steps
+    per_step = {k: v[0] / steps for k, v in ph32.items() if v[1]}
+    dom = max(per_step, key=per_step.get)
+    launches = ph32[dom][1]
+    avg_ms = ph32[dom][0] / launches
+    by = phase_bytes(dom, N, nsolves, live32, 4)
+    achieved = by / (avg_ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": by, "avg_launch_ms": avg_ms}
+    step_bytes = sum(phase_bytes(k, N, nsolves, live32, 4) for k in per_step)
+    step_roof = step_bytes / (t32 / steps) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        _log("oracle CPU baseline")
+        cpu = cpu_baseline(w, args.cpu_frac)
+
+    out = {
+        "metric": "particle-steps/s and 3D-FFT Poisson solves/s (128^3 grids), FP32 vs FP64",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "disc-bulge-halo galaxy, 3 nested 128^3 grids (R = 1, 4, 20; "
+                               "q = 1/4, 1/4, 1), 8.5M particles, dt 0.01, FP64 diagnostics "
+                               "every 10 steps",
+                   "particles_live": live32, "solves_per_step": nsolves},
+        "fp64": fp64,
+        "solves": solves,
+        "phases_ms_per_step": per_step,
+        "step_effective_GBs": step_roof,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

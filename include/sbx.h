@@ -1,0 +1,225 @@
+/*
+ * sbx.h -- C ABI of the MI355X nested-grid particle-mesh field solve.
+ *
+ * Method: Bien, Brandt & Just (2012), "Simulating sinking satellites with
+ * Superbox-10", Sec. 2: nearest-grid-point mass assignment (Eq. 7), the
+ * isolated-boundary potential by a zero-padded 3D FFT convolution with the
+ * Green's function of Eq. 2 (Eqs. 1-5), force differencing with the Taylor
+ * terms of Eq. 8, the five grids per galaxy with their grid-selection rule
+ * (Sec. 2.1, Fig. 2), flattened grids (Sec. 2.2.2, Eq. 9), individual masses
+ * (Sec. 2.2.1) and the leapfrog of Eq. 6.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: SBX_OK (0) or a negative sbx_status.  No exception or
+ *     abort crosses the ABI.  sbx_last_error() gives a message for the last
+ *     failing call on the calling thread.
+ *   - Host pointers are borrowed for the duration of the call only.  Device
+ *     pointers passed to sbx_poisson_solve are borrowed for that call and must
+ *     stay valid until the work on the plan's stream has finished.
+ *   - The context owns every device buffer it allocates; sbx_destroy frees
+ *     them.  A context is not thread-safe: calls on one context must not
+ *     overlap.
+ *   - Grids are stored x-fastest: element (ix, iy, iz) of an N^3 grid is at
+ *     (iz * N + iy) * N + ix.
+ *   - Particle arrays on the host are n x 3 row-major (x, y, z per particle).
+ *   - Units: G is a parameter; lengths and masses are the caller's.  The
+ *     potential the API reports is the physical one, phi = -Phi, where
+ *     Phi = +G sum M H is the positive field of Eq. 1; accelerations are
+ *     +grad Phi as in Eq. 8.
+ *   - Readings of points the paper leaves open: cell length l = 2R/(N-4)
+ *     (usable cells [2, N-3] per axis, Table 3); z cell length q*l; cell of
+ *     Eq. 7 = floor(((x - c) * gamma + N/2) + 0.5) in float64 with each
+ *     operation rounded; membership by the spheroidal radius
+ *     (dx^2 + dy^2) + (dz/q)^2 < R^2; H(0,0,0) = H(1,0,0) unless h0_mode = 2
+ *     (zero); velocities are staggered, v = v(t - dt/2).
+ */
+#ifndef SBX_H
+#define SBX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SBX_OK = 0,
+  SBX_EINVAL = -1,   /* bad argument (NULL, size, NaN, negative mass, ...)   */
+  SBX_ENOMEM = -2,   /* device or host allocation failed                     */
+  SBX_EDEVICE = -3,  /* HIP runtime error (no device, launch failure, ...)   */
+  SBX_EQCRIT = -4,   /* flattening below q_crit of Eq. 9                     */
+  SBX_ESTATE = -5    /* call out of order (e.g. step before build_grids)     */
+} sbx_status;
+
+typedef enum { SBX_FP32 = 0, SBX_FP64 = 1 } sbx_prec;
+typedef enum { SBX_CENTRE_FIXED = 0, SBX_CENTRE_COM = 1 } sbx_centring;
+
+/* Particle classes relative to one galaxy's grids (Sec. 2.1 list of grids). */
+typedef enum { SBX_CORE = 0, SBX_RING = 1, SBX_OUTER = 2, SBX_LOST = 3 } sbx_class;
+
+/* One grid geometry: n cells per axis (power of two, 8..256), half-extent R
+ * of the usable region, flattening q in (0, 1] of the z cell length. */
+typedef struct {
+  int32_t n;
+  double R;
+  double q;
+} sbx_level;
+
+/* Grids of one galaxy (Sec. 2.1, Fig. 2).
+ * n_levels = 3: lv[0] inner (grid 1), lv[1] middle (grids 2 and 3), lv[2]
+ *   outer = the fixed global grid (grids 4 and 5), centred at outer_centre.
+ *   The inner and middle levels follow the galaxy centre: `centre` when
+ *   centring = SBX_CENTRE_FIXED, the centre of mass of the galaxy's live
+ *   particles (recomputed every step) when SBX_CENTRE_COM.
+ * n_levels = 1: one isolated grid lv[0], fixed at `centre`, holding every
+ *   particle (centring must be SBX_CENTRE_FIXED). */
+typedef struct {
+  int32_t n_levels;
+  sbx_level lv[3];
+  int32_t centring;
+  double centre[3];
+  double outer_centre[3];
+} sbx_hierarchy;
+
+typedef struct {
+  int32_t prec;     /* sbx_prec: arithmetic of grids, FFT, forces, particles */
+  double G;         /* gravitational constant                                 */
+  int32_t h0_mode;  /* H(0,0,0): 0 = H(1,0,0) = 1/l (default), 2 = 0          */
+  int32_t taylor;   /* 1 = full Eq. 8, 0 = central differences only           */
+  int32_t device;   /* HIP device ordinal                                     */
+  void* stream;     /* hipStream_t to run on, or NULL for a private stream    */
+} sbx_config;
+
+/* FP64 diagnostics (per particle component id 0..7). */
+typedef struct {
+  double ekin[8];     /* sum 1/2 m |v_sync|^2, v_sync = v + dt/2 a(t)       */
+  double epot[8];     /* 1/2 sum m phi(x), phi = -Phi at the particle       */
+  double L[8][3];     /* sum m x cross v_sync about the origin              */
+  double disc_sigR;   /* component 0 of galaxy 0: sigma_R about galaxy 0's  */
+  double disc_sigz;   /*   centre, and sigma_z                              */
+  int64_t n_lost;     /* particles flagged lost                             */
+  int64_t n_live[8];  /* live particles per component                       */
+} sbx_diag;
+
+typedef struct sbx_ctx sbx_ctx;
+typedef struct sbx_poisson sbx_poisson;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* sbx_last_error(void);
+
+/* Host-only check of a set of hierarchies (nesting, q in (0,1], Eq. 9
+ * q >= q_crit = max(R1/R2, 4/(N-4) * R3/R2) for the middle level, q < 1 only
+ * for galaxy 0, several galaxies share one global outer level).  Needs no GPU.
+ * Returns SBX_EQCRIT below q_crit, SBX_EINVAL otherwise when invalid. */
+sbx_status sbx_validate_hierarchies(int32_t n_galaxies, const sbx_hierarchy* h);
+
+/* q_crit of Eq. 9 (host-only). */
+double sbx_q_crit(int32_t n, double R_core, double R_out, double R_sys);
+
+/* ---- context: particles, grids, forces, steps ---------------------------- */
+
+/* Create a context on cfg->device.  *out receives the handle. */
+sbx_status sbx_create(const sbx_config* cfg, sbx_ctx** out);
+void sbx_destroy(sbx_ctx* ctx);
+
+/* Copy n particles from the host (x, v: n*3; m: n; comp, gal: n; comp in
+ * 0..7, gal < n_galaxies of build_grids).  Converted to the context precision
+ * on the device.  Masses must be finite and >= 0.  Lost flags are cleared. */
+sbx_status sbx_load_particles(sbx_ctx* ctx, int64_t n, const double* x, const double* v,
+                              const double* m, const int8_t* comp, const int8_t* gal);
+
+/* Validate the hierarchies and build the Green's tables (Sec. 2.1: the
+ * transformed H is computed once): H of Eq. 2 on lags 0..N, mirrored to
+ * (2N)^3 by Eq. 5, transformed by an FP64 FFT, scaled by G/(2N)^3 and stored
+ * on (N+1)^3 (it is real and even per axis).  Allocates the grids. */
+sbx_status sbx_build_grids(sbx_ctx* ctx, int32_t n_galaxies, const sbx_hierarchy* h);
+
+/* One field solve at the current positions, no motion: loss test, centres,
+ * mass assignment, the isolated solves, Eq. 8 with the grid-selection rule.
+ * acc (n*3) and pot (n, physical phi) are host outputs; either may be NULL.
+ * Lost particles get zeros. */
+sbx_status sbx_compute_forces(sbx_ctx* ctx, double* acc, double* pot);
+
+/* nsteps integration cycles of Eq. 6 with constant dt (stream-ordered, does
+ * not synchronise).  When diag_every > 0 the FP64 diagnostics are taken at the
+ * start of every diag_every-th step and appended to the context's log. */
+sbx_status sbx_step(sbx_ctx* ctx, double dt, int32_t nsteps, int32_t diag_every);
+
+/* Read back positions, velocities (v(t - dt/2)) and lost flags (any may be
+ * NULL).  Synchronises the context stream. */
+sbx_status sbx_get_particles(sbx_ctx* ctx, double* x, double* v, uint8_t* lost);
+
+/* Centres used by the last solve: n_galaxies * 3 doubles. */
+sbx_status sbx_get_centres(sbx_ctx* ctx, double* centres);
+
+/* Class of every particle relative to galaxy `galaxy` and its cell on level
+ * `level` (idx: n*3 int32, cls: n int8; either may be NULL), at the current
+ * positions and the centres of the last solve (or the fixed centres). */
+sbx_status sbx_get_indices(sbx_ctx* ctx, int32_t galaxy, int32_t level, int32_t* idx,
+                           int8_t* cls);
+
+/* Grid `which` of galaxy `galaxy` after the last solve, as N^3 float64.
+ * kind 0 = cell masses, 1 = field Phi (positive, Eq. 1).  Three levels:
+ * which 0 = grid 1 (core, inner level), 1 = grid 3 (ring, middle level),
+ * 2 = grids 2+3 (core and ring, middle level), 3 = grid 5 (outer, global
+ * level), 4 = grids 4+5 (all, global level).  One level: which 0 only.
+ * kind 1 is valid after sbx_compute_forces (sbx_step reuses the buffers). */
+sbx_status sbx_get_grid(sbx_ctx* ctx, int32_t galaxy, int32_t which, int32_t kind, double* out);
+
+/* FP64 diagnostics at the current state (a solve without motion). */
+sbx_status sbx_diagnostics(sbx_ctx* ctx, double dt, sbx_diag* out);
+
+/* Number of entries in the diagnostics log of sbx_step, and a copy of up to
+ * max entries (oldest first).  Synchronises. */
+sbx_status sbx_diag_log(sbx_ctx* ctx, int32_t max, sbx_diag* out, int32_t* count);
+
+/* Block until all work queued on the context stream has finished. */
+sbx_status sbx_sync(sbx_ctx* ctx);
+
+/* Number of live particles (synchronises). */
+sbx_status sbx_count_live(sbx_ctx* ctx, int64_t* live);
+
+/* ---- tracing: per-phase timing with HIP events ---------------------------- */
+
+/* Phases: 0 step start (not a kernel), 1 zero grids, 2 loss test and centres,
+ * 3 mass assignment, 4 fwd_x, 5 fwd_y, 6 z pass with the Green multiply,
+ * 7 inv_y, 8 inv_x (the five FFT passes of all solves of a step), 9 force,
+ * kick and drift, 10 particle reordering. */
+#define SBX_N_PHASES 11
+
+/* Start recording an event after every phase launched on the context stream
+ * (at most max_marks events; later marks are dropped).  Synchronises. */
+sbx_status sbx_profile_begin(sbx_ctx* ctx, int32_t max_marks);
+
+/* Stop recording, synchronise, and return per phase the summed GPU time in
+ * milliseconds (out_ms) and the number of launches (out_count); arrays of
+ * n_phases >= SBX_N_PHASES entries. */
+sbx_status sbx_profile_end(sbx_ctx* ctx, int32_t n_phases, double* out_ms, int64_t* out_count);
+
+/* ---- standalone isolated Poisson solves (Eqs. 1-5) ------------------------ */
+
+/* Plan for isolated solves on one geometry (n, R, q) in precision prec.
+ * Builds the Green's table as sbx_build_grids does. */
+sbx_status sbx_poisson_create(int32_t n, double R, double q, double G, int32_t h0_mode,
+                              int32_t prec, int32_t device, void* stream, sbx_poisson** out);
+void sbx_poisson_destroy(sbx_poisson* p);
+
+/* Solve `batch` independent grids: rho and phi are device pointers to
+ * batch * n^3 elements of the plan precision (x-fastest per grid, grids
+ * back to back); phi = Phi of Eq. 1 for cell masses rho.  rho and phi may be
+ * the same buffer.  batch <= 64.  Stream-ordered on the plan's stream. */
+sbx_status sbx_poisson_solve(sbx_poisson* p, int32_t batch, const void* rho, void* phi);
+
+/* The stored transformed Green's function, (n+1)^3 float64, index
+ * (kx * (n+1) + ky) * (n+1) + kz, scaled by G/(2n)^3; rel_imag receives
+ * max|Im| / max|Re| of the FP64 transform before folding (may be NULL). */
+sbx_status sbx_poisson_green(sbx_poisson* p, double* out, double* rel_imag);
+
+/* Device bytes the plan holds. */
+int64_t sbx_poisson_bytes(sbx_poisson* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBX_H */

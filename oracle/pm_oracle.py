@@ -455,7 +455,15 @@ class System:
         acc = np.zeros((n, 3))
         phi = np.zeros(n)
         live = ~lost
-        xl = x[live]
+        a_l, p_l = self.field_at(x[live], centres, pots)
+        acc[live] = a_l
+        phi[live] = p_l
+        if want_pot:
+            return acc, phi
+        return acc
+
+    def field_at(self, xl, centres, pots):
+        """Acceleration and Phi_paper at positions xl from solved fields."""
         a_l = np.zeros((xl.shape[0], 3))
         p_l = np.zeros(xl.shape[0])
         for g, hh in enumerate(self.h):
@@ -476,13 +484,8 @@ class System:
                 ii = idx[k][mask]
                 dl = cell_offset(xl[mask] - c, ii, L)
                 a_l[mask] += eq8_accel(F, ii, dl, L.lengths, self.taylor)
-                if want_pot:
-                    p_l[mask] += taylor_potential(F, ii, dl, L.lengths, self.taylor)
-        acc[live] = a_l
-        phi[live] = p_l
-        if want_pot:
-            return acc, phi
-        return acc
+                p_l[mask] += taylor_potential(F, ii, dl, L.lengths, self.taylor)
+        return a_l, p_l
 
     # -- loss and stepping ---------------------------------------------------
     def lost_now(self, x):

@@ -1,0 +1,994 @@
+// C ABI of the library: contexts (particles, grids, forces, steps) and
+// standalone Poisson plans.  Host code only orchestrates: every step of the
+// method runs in the kernels of fft.hip and particles.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fft.h"
+#include "particles.h"
+
+namespace sbx {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+static bool is_pow2_grid(int n) { return n >= 8 && n <= 256 && (n & (n - 1)) == 0; }
+
+// Geometry of one level as the method reads it: the usable N-4 cells span
+// 2R, so l = 2R/(N-4); the z cell length of a flattened grid is q*l.
+static LevelDev make_level(const sbx_level& s) {
+  LevelDev L;
+  L.N = s.n;
+  L.half = (double)s.n / 2.0;
+  L.l = (2.0 * s.R) / (double)(s.n - 4);
+  L.lz = s.q * L.l;
+  L.gx = 1.0 / L.l;
+  L.gz = 1.0 / L.lz;
+  L.inv_q = 1.0 / s.q;
+  L.R2 = s.R * s.R;
+  return L;
+}
+
+static double q_crit_of(int n, double Rc, double Ro, double Rs) {
+  const double a = Rc / Ro;
+  const double b = 4.0 / (n - 4) * Rs / Ro;
+  return a > b ? a : b;
+}
+
+static bool same_level(const sbx_level& a, const sbx_level& b) {
+  return a.n == b.n && a.R == b.R && a.q == b.q;
+}
+
+static sbx_status validate(int ng, const sbx_hierarchy* h) {
+  if (!h || ng < 1 || ng > kMaxGal) {
+    set_error("1 to 4 galaxies required");
+    return SBX_EINVAL;
+  }
+  const int N0 = h[0].lv[0].n;
+  for (int g = 0; g < ng; ++g) {
+    const sbx_hierarchy& hh = h[g];
+    if (hh.n_levels != 1 && hh.n_levels != 3) {
+      set_error("a hierarchy has 1 or 3 levels");
+      return SBX_EINVAL;
+    }
+    if (hh.centring != SBX_CENTRE_FIXED && hh.centring != SBX_CENTRE_COM) {
+      set_error("unknown centring");
+      return SBX_EINVAL;
+    }
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(hh.centre[k]) || !std::isfinite(hh.outer_centre[k])) {
+        set_error("centres must be finite");
+        return SBX_EINVAL;
+      }
+    for (int k = 0; k < hh.n_levels; ++k) {
+      const sbx_level& L = hh.lv[k];
+      if (!is_pow2_grid(L.n)) {
+        set_error("grid size must be a power of two in 8..256");
+        return SBX_EINVAL;
+      }
+      if (L.n != N0) {
+        set_error("all grids have the same number of cells (Sec. 2.1)");
+        return SBX_EINVAL;
+      }
+      if (!(L.R > 0.0) || !std::isfinite(L.R) || !(L.q > 0.0) || !(L.q <= 1.0)) {
+        set_error("need R > 0 and 0 < q <= 1");
+        return SBX_EINVAL;
+      }
+    }
+    if (hh.n_levels == 1) {
+      if (ng != 1 || hh.centring != SBX_CENTRE_FIXED) {
+        set_error("a single grid is the fixed global grid of one galaxy");
+        return SBX_EINVAL;
+      }
+      continue;
+    }
+    const sbx_level &L1 = hh.lv[0], &L2 = hh.lv[1], &L3 = hh.lv[2];
+    if (!(L1.R < L2.R && L2.R < L3.R)) {
+      set_error("levels must nest: R1 < R2 < R3");
+      return SBX_EINVAL;
+    }
+    if (L3.q != 1.0) {
+      set_error("the global grid is not flattened");
+      return SBX_EINVAL;
+    }
+    if (g > 0 && (L1.q != 1.0 || L2.q != 1.0)) {
+      set_error("q < 1 applies only to the first galaxy (Sec. 2.2.2)");
+      return SBX_EINVAL;
+    }
+    const double qc = q_crit_of(L2.n, L1.R, L2.R, L3.R);
+    if (L2.q < qc) {
+      set_error("flattening q = " + std::to_string(L2.q) + " below q_crit = " +
+                std::to_string(qc) + " (Eq. 9)");
+      return SBX_EQCRIT;
+    }
+    if (L2.q * L2.R < L1.q * L1.R) {
+      set_error("flattened middle grid must still cover the inner grid");
+      return SBX_EINVAL;
+    }
+    if (g > 0) {
+      const sbx_hierarchy& h0 = h[0];
+      if (!same_level(L3, h0.lv[2]) || std::memcmp(hh.outer_centre, h0.outer_centre,
+                                                   sizeof(hh.outer_centre)) != 0) {
+        set_error("several galaxies share one global grid");
+        return SBX_EINVAL;
+      }
+    }
+  }
+  return SBX_OK;
+}
+
+// ------------------------------------------------------------------ ctx ----
+struct Green {
+  sbx_level geo;
+  void* H;
+  double rel_imag;
+};
+
+}  // namespace sbx
+
+using namespace sbx;
+
+struct sbx_ctx {
+  sbx_config cfg;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t esz = 4;  // bytes per real
+  // particles
+  int64_t n = 0;
+  void* x[3] = {};
+  void* v[3] = {};
+  void* m = nullptr;
+  int8_t* comp = nullptr;
+  int8_t* gal = nullptr;
+  uint8_t* lost = nullptr;
+  // grids
+  bool built = false;
+  int ngal = 0;
+  int N = 0;
+  sbx_hierarchy hh[kMaxGal];
+  SysDev sys;
+  int nslots[kMaxGal] = {};
+  void* grid_block = nullptr;  // all grids back to back
+  void* grid[kMaxGal][kSlots] = {};
+  int slot_level[kMaxGal][kSlots] = {};
+  std::vector<Green> greens;
+  void* X = nullptr;
+  void* C = nullptr;
+  int nsolves = 0;
+  double* centres = nullptr;  // kMaxGal * 3
+  double* partial = nullptr;  // kRedBlocks * kNDiag + kNDiag
+  double* diag_one = nullptr; // kNDiag
+  double* diag_log = nullptr; // kDiagCap * kNDiag
+  int64_t diag_count = 0;
+  double* acc = nullptr;      // n * 3, lazily
+  double* pot = nullptr;      // n, lazily
+  int64_t acc_n = 0;
+  int64_t step_count = 0;
+  bool solved = false;        // centres computed by a solve
+  bool grids_fields = false;  // grids hold fields (not cell masses)
+  Recorder rec;
+};
+
+struct sbx_poisson {
+  int N = 0, prec = 0, device = 0;
+  sbx_level geo;
+  double G = 1.0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* H = nullptr;
+  void* X = nullptr;
+  void* C = nullptr;
+  int cap = 0;
+  double rel_imag = 0.0;
+  int64_t bytes = 0;
+};
+
+namespace {
+
+constexpr int kDiagCap = 4096;
+
+template <typename T>
+PartDev<T> part_of(sbx_ctx* c) {
+  PartDev<T> p;
+  for (int k = 0; k < 3; ++k) {
+    p.x[k] = (T*)c->x[k];
+    p.v[k] = (T*)c->v[k];
+  }
+  p.m = (T*)c->m;
+  p.comp = c->comp;
+  p.gal = c->gal;
+  p.lost = c->lost;
+  p.n = c->n;
+  return p;
+}
+
+template <typename T>
+GridsDev<T> grids_of(sbx_ctx* c) {
+  GridsDev<T> G;
+  for (int g = 0; g < kMaxGal; ++g)
+    for (int k = 0; k < kSlots; ++k) G.g[g][k] = (T*)c->grid[g][k];
+  return G;
+}
+
+void free_ptr(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+template <typename P>
+void free_typed(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+sbx_status dev_alloc(void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    set_error("out of device memory (" + std::to_string(bytes) + " bytes)");
+    return SBX_ENOMEM;
+  }
+  return SBX_OK;
+}
+
+void free_particles(sbx_ctx* c) {
+  for (int k = 0; k < 3; ++k) {
+    free_ptr(c->x[k]);
+    free_ptr(c->v[k]);
+  }
+  free_ptr(c->m);
+  free_typed(c->comp);
+  free_typed(c->gal);
+  free_typed(c->lost);
+  free_typed(c->acc);
+  free_typed(c->pot);
+  c->acc_n = 0;
+  c->n = 0;
+}
+
+void free_grids(sbx_ctx* c) {
+  free_ptr(c->grid_block);
+  for (auto& g : c->greens) free_ptr(g.H);
+  c->greens.clear();
+  free_ptr(c->X);
+  free_ptr(c->C);
+  std::memset(c->grid, 0, sizeof(c->grid));
+  c->built = false;
+  c->solved = false;
+}
+
+sbx_status set_device(int dev) {
+  SBX_HIP(hipSetDevice(dev));
+  return SBX_OK;
+}
+
+int slot_count(const sbx_hierarchy& h) { return h.n_levels == 3 ? kSlots : 1; }
+int slot_level_of(const sbx_hierarchy& h, int slot) {
+  if (h.n_levels == 1) return 0;
+  static const int lv[kSlots] = {0, 1, 1, 2, 2};
+  return lv[slot];
+}
+
+template <typename T>
+sbx_status build_grids_t(sbx_ctx* c) {
+  const int N = c->N;
+  const size_t cells = (size_t)N * N * N;
+  int total = 0;
+  for (int g = 0; g < c->ngal; ++g) total += c->nslots[g];
+  c->nsolves = total;
+  SBX_TRY(dev_alloc(&c->grid_block, cells * sizeof(T) * total));
+  int s = 0;
+  for (int g = 0; g < c->ngal; ++g)
+    for (int k = 0; k < c->nslots[g]; ++k) c->grid[g][k] = (T*)c->grid_block + cells * (s++);
+  // Green's tables, one per distinct level geometry
+  for (int g = 0; g < c->ngal; ++g)
+    for (int lv = 0; lv < c->hh[g].n_levels; ++lv) {
+      const sbx_level& geo = c->hh[g].lv[lv];
+      bool have = false;
+      for (auto& e : c->greens) have = have || same_level(e.geo, geo);
+      if (have) continue;
+      Green e{geo, nullptr, 0.0};
+      SBX_TRY(dev_alloc(&e.H, h_elems(N) * sizeof(T)));
+      c->greens.push_back(e);
+      const LevelDev L = make_level(geo);
+      SBX_TRY(build_green<T>(N, L.l, L.lz, c->cfg.G, c->cfg.h0_mode, (T*)c->greens.back().H,
+                             &c->greens.back().rel_imag, c->stream));
+    }
+  SBX_TRY(dev_alloc(&c->X, x_elems(N) * sizeof(C2<T>) * total));
+  SBX_TRY(dev_alloc(&c->C, c_elems(N) * sizeof(C2<T>) * total));
+  return SBX_OK;
+}
+
+const void* green_for(sbx_ctx* c, const sbx_level& geo) {
+  for (auto& e : c->greens)
+    if (same_level(e.geo, geo)) return e.H;
+  return nullptr;
+}
+
+// Loss test, centres, mass assignment and all isolated solves of one step.
+template <typename T>
+sbx_status field_solve_t(sbx_ctx* c) {
+  const size_t cells = (size_t)c->N * c->N * c->N;
+  c->rec.mark(PH_START, c->stream);
+  SBX_TRY(launch_zero<T>((T*)c->grid_block, cells * c->nsolves, c->stream));
+  c->rec.mark(PH_ZERO, c->stream);
+  const PartDev<T> p = part_of<T>(c);
+  SBX_TRY(launch_pre<T>(p, c->sys, c->partial, c->centres, c->stream));
+  c->rec.mark(PH_PRE, c->stream);
+  SBX_TRY(launch_deposit<T>(p, c->sys, c->centres, grids_of<T>(c), c->stream));
+  c->rec.mark(PH_DEPOSIT, c->stream);
+  SolveBatch<T> b;
+  int s = 0;
+  for (int g = 0; g < c->ngal; ++g)
+    for (int k = 0; k < c->nslots[g]; ++k, ++s) {
+      SolveDesc<T>& d = b.d[s];
+      d.rho = (const T*)c->grid[g][k];
+      d.phi = (T*)c->grid[g][k];
+      d.X = (C2<T>*)c->X + x_elems(c->N) * s;
+      d.C = (C2<T>*)c->C + c_elems(c->N) * s;
+      d.H = (const T*)green_for(c, c->hh[g].lv[c->slot_level[g][k]]);
+    }
+  SBX_TRY(solve_batch<T>(c->N, s, b, c->stream, &c->rec));
+  c->solved = true;
+  c->grids_fields = true;
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status force_t(sbx_ctx* c, double dt, int mode, double* diag_out) {
+  SBX_TRY(launch_force<T>(part_of<T>(c), c->sys, c->centres, grids_of<T>(c), dt, mode, c->acc,
+                          c->pot, c->partial, diag_out, c->stream));
+  c->rec.mark(PH_FORCE, c->stream);
+  return SBX_OK;
+}
+
+void free_recorder(Recorder& r) {
+  for (int i = 0; i < r.cap; ++i) (void)hipEventDestroy(r.ev[i]);
+  delete[] r.ev;
+  delete[] r.tag;
+  r = Recorder();
+}
+
+sbx_status field_solve(sbx_ctx* c) {
+  return c->cfg.prec == SBX_FP64 ? field_solve_t<double>(c) : field_solve_t<float>(c);
+}
+sbx_status force(sbx_ctx* c, double dt, int mode, double* diag_out) {
+  return c->cfg.prec == SBX_FP64 ? force_t<double>(c, dt, mode, diag_out)
+                                 : force_t<float>(c, dt, mode, diag_out);
+}
+
+sbx_status check_ready(sbx_ctx* c) {
+  if (!c) {
+    set_error("null context");
+    return SBX_EINVAL;
+  }
+  if (!c->built) {
+    set_error("build_grids has not been called");
+    return SBX_ESTATE;
+  }
+  if (c->n == 0 || !c->x[0]) {
+    set_error("no particles loaded");
+    return SBX_ESTATE;
+  }
+  return set_device(c->cfg.device);
+}
+
+sbx_status ensure_acc(sbx_ctx* c) {
+  if (c->acc_n == c->n && c->acc) return SBX_OK;
+  free_typed(c->acc);
+  free_typed(c->pot);
+  SBX_TRY(dev_alloc((void**)&c->acc, sizeof(double) * 3 * c->n));
+  SBX_TRY(dev_alloc((void**)&c->pot, sizeof(double) * c->n));
+  c->acc_n = c->n;
+  return SBX_OK;
+}
+
+void to_diag(const double* r, sbx_diag* d) {
+  std::memset(d, 0, sizeof(*d));
+  for (int c = 0; c < kNComp; ++c) {
+    d->ekin[c] = r[kDiagComp * c + 0];
+    d->epot[c] = r[kDiagComp * c + 1];
+    d->L[c][0] = r[kDiagComp * c + 2];
+    d->L[c][1] = r[kDiagComp * c + 3];
+    d->L[c][2] = r[kDiagComp * c + 4];
+    d->n_live[c] = (int64_t)llround(r[kDiagComp * c + 5]);
+  }
+  const double* q = r + kDiagDisc;
+  if (q[4] > 0) {
+    const double mR = q[0] / q[4], mz = q[2] / q[4];
+    d->disc_sigR = std::sqrt(std::fmax(q[1] / q[4] - mR * mR, 0.0));
+    d->disc_sigz = std::sqrt(std::fmax(q[3] / q[4] - mz * mz, 0.0));
+  }
+  d->n_lost = (int64_t)llround(r[kDiagLost]);
+}
+
+template <typename T>
+sbx_status poisson_solve_t(sbx_poisson* p, int batch, const void* rho, void* phi) {
+  const size_t cells = (size_t)p->N * p->N * p->N;
+  if (batch > p->cap) {
+    SBX_HIP(hipStreamSynchronize(p->stream));
+    free_ptr(p->X);
+    free_ptr(p->C);
+    p->cap = 0;
+    const int cap = std::min(batch, kMaxBatch);
+    SBX_TRY(dev_alloc(&p->X, x_elems(p->N) * sizeof(C2<T>) * cap));
+    SBX_TRY(dev_alloc(&p->C, c_elems(p->N) * sizeof(C2<T>) * cap));
+    p->cap = cap;
+    p->bytes = (int64_t)(h_elems(p->N) * sizeof(T) +
+                         (x_elems(p->N) + c_elems(p->N)) * sizeof(C2<T>) * cap);
+  }
+  for (int b0 = 0; b0 < batch; b0 += p->cap) {
+    const int nb = std::min(p->cap, batch - b0);
+    SolveBatch<T> sb;
+    for (int i = 0; i < nb; ++i) {
+      sb.d[i].rho = (const T*)rho + cells * (b0 + i);
+      sb.d[i].phi = (T*)phi + cells * (b0 + i);
+      sb.d[i].X = (C2<T>*)p->X + x_elems(p->N) * i;
+      sb.d[i].C = (C2<T>*)p->C + c_elems(p->N) * i;
+      sb.d[i].H = (const T*)p->H;
+    }
+    SBX_TRY(solve_batch<T>(p->N, nb, sb, p->stream));
+  }
+  return SBX_OK;
+}
+
+}  // namespace
+
+// ============================================================== the ABI ====
+extern "C" {
+
+const char* sbx_last_error(void) { return g_err.c_str(); }
+
+double sbx_q_crit(int32_t n, double R_core, double R_out, double R_sys) {
+  return q_crit_of(n, R_core, R_out, R_sys);
+}
+
+sbx_status sbx_validate_hierarchies(int32_t n_galaxies, const sbx_hierarchy* h) {
+  return validate(n_galaxies, h);
+}
+
+sbx_status sbx_create(const sbx_config* cfg, sbx_ctx** out) {
+  if (!cfg || !out) {
+    set_error("null argument");
+    return SBX_EINVAL;
+  }
+  *out = nullptr;
+  if (cfg->prec != SBX_FP32 && cfg->prec != SBX_FP64) {
+    set_error("prec must be SBX_FP32 or SBX_FP64");
+    return SBX_EINVAL;
+  }
+  if (cfg->h0_mode != 0 && cfg->h0_mode != 2) {
+    set_error("h0_mode must be 0 or 2");
+    return SBX_EINVAL;
+  }
+  if (!std::isfinite(cfg->G) || !(cfg->G > 0.0)) {
+    set_error("G must be positive");
+    return SBX_EINVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    set_error("no HIP device available");
+    return SBX_EDEVICE;
+  }
+  if (cfg->device < 0 || cfg->device >= ndev) {
+    set_error("device ordinal out of range");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(cfg->device));
+  sbx_ctx* c = new (std::nothrow) sbx_ctx();
+  if (!c) {
+    set_error("out of host memory");
+    return SBX_ENOMEM;
+  }
+  c->cfg = *cfg;
+  c->esz = cfg->prec == SBX_FP64 ? 8 : 4;
+  if (cfg->stream) {
+    c->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      set_error("hipStreamCreate failed");
+      return SBX_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  sbx_status rc = SBX_OK;
+  if ((rc = dev_alloc((void**)&c->centres, sizeof(double) * 3 * kMaxGal)) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->partial, sizeof(double) * ((size_t)kRedBlocks * kNDiag + kNDiag))) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->diag_one, sizeof(double) * kNDiag)) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->diag_log, sizeof(double) * kNDiag * kDiagCap)) != SBX_OK) {
+    sbx_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return SBX_OK;
+}
+
+void sbx_destroy(sbx_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->cfg.device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_particles(c);
+  free_grids(c);
+  free_typed(c->centres);
+  free_typed(c->partial);
+  free_typed(c->diag_one);
+  free_typed(c->diag_log);
+  free_recorder(c->rec);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+sbx_status sbx_profile_begin(sbx_ctx* c, int32_t max_marks) {
+  if (!c || max_marks <= 0 || max_marks > (1 << 20)) {
+    set_error("bad profile arguments");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  if (c->rec.cap < max_marks) {
+    free_recorder(c->rec);
+    c->rec.ev = new hipEvent_t[max_marks];
+    c->rec.tag = new int[max_marks];
+    for (int i = 0; i < max_marks; ++i) {
+      if (hipEventCreate(&c->rec.ev[i]) != hipSuccess) {
+        c->rec.cap = i;
+        free_recorder(c->rec);
+        set_error("hipEventCreate failed");
+        return SBX_EDEVICE;
+      }
+      c->rec.cap = i + 1;
+    }
+  }
+  c->rec.used = 0;
+  c->rec.on = true;
+  return SBX_OK;
+}
+
+sbx_status sbx_profile_end(sbx_ctx* c, int32_t n_phases, double* out_ms, int64_t* out_count) {
+  if (!c || !out_ms || !out_count || n_phases < PH_COUNT) {
+    set_error("bad profile arguments");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < n_phases; ++i) {
+    out_ms[i] = 0.0;
+    out_count[i] = 0;
+  }
+  for (int i = 1; i < c->rec.used; ++i) {
+    if (c->rec.tag[i] == PH_START) continue;
+    float ms = 0.f;
+    SBX_HIP(hipEventElapsedTime(&ms, c->rec.ev[i - 1], c->rec.ev[i]));
+    out_ms[c->rec.tag[i]] += ms;
+    out_count[c->rec.tag[i]] += 1;
+  }
+  c->rec.on = false;
+  c->rec.used = 0;
+  return SBX_OK;
+}
+
+sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const double* v,
+                              const double* m, const int8_t* comp, const int8_t* gal) {
+  if (!c || n <= 0 || !x || !v || !m || !comp || !gal) {
+    set_error("null argument or n <= 0");
+    return SBX_EINVAL;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(m[i]) || m[i] < 0.0) {
+      set_error("masses must be finite and >= 0 (particle " + std::to_string(i) + ")");
+      return SBX_EINVAL;
+    }
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(x[3 * i + k]) || !std::isfinite(v[3 * i + k])) {
+        set_error("positions and velocities must be finite (particle " + std::to_string(i) + ")");
+        return SBX_EINVAL;
+      }
+    if (comp[i] < 0 || comp[i] >= kNComp || gal[i] < 0 || gal[i] >= kMaxGal) {
+      set_error("component id in 0..7 and galaxy id in 0..3 required");
+      return SBX_EINVAL;
+    }
+    if (c->built && gal[i] >= c->ngal) {
+      set_error("galaxy id beyond the built hierarchies");
+      return SBX_EINVAL;
+    }
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  free_particles(c);
+  const size_t es = c->esz;
+  for (int k = 0; k < 3; ++k) {
+    SBX_TRY(dev_alloc(&c->x[k], es * n));
+    SBX_TRY(dev_alloc(&c->v[k], es * n));
+  }
+  SBX_TRY(dev_alloc(&c->m, es * n));
+  SBX_TRY(dev_alloc((void**)&c->comp, n));
+  SBX_TRY(dev_alloc((void**)&c->gal, n));
+  SBX_TRY(dev_alloc((void**)&c->lost, n));
+  c->n = n;
+  double* stage = nullptr;
+  SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 3 * n));
+  sbx_status rc = SBX_OK;
+  auto run = [&]() -> sbx_status {
+    SBX_HIP(hipMemcpy(stage, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    if (c->cfg.prec == SBX_FP64)
+      SBX_TRY(launch_split3<double>(stage, (double*)c->x[0], (double*)c->x[1], (double*)c->x[2], n, c->stream));
+    else
+      SBX_TRY(launch_split3<float>(stage, (float*)c->x[0], (float*)c->x[1], (float*)c->x[2], n, c->stream));
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    SBX_HIP(hipMemcpy(stage, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    if (c->cfg.prec == SBX_FP64)
+      SBX_TRY(launch_split3<double>(stage, (double*)c->v[0], (double*)c->v[1], (double*)c->v[2], n, c->stream));
+    else
+      SBX_TRY(launch_split3<float>(stage, (float*)c->v[0], (float*)c->v[1], (float*)c->v[2], n, c->stream));
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    SBX_HIP(hipMemcpy(stage, m, sizeof(double) * n, hipMemcpyHostToDevice));
+    if (c->cfg.prec == SBX_FP64)
+      SBX_TRY(launch_convert_in<double>(stage, (double*)c->m, n, c->stream));
+    else
+      SBX_TRY(launch_convert_in<float>(stage, (float*)c->m, n, c->stream));
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    SBX_HIP(hipMemcpy(c->comp, comp, n, hipMemcpyHostToDevice));
+    SBX_HIP(hipMemcpy(c->gal, gal, n, hipMemcpyHostToDevice));
+    SBX_HIP(hipMemset(c->lost, 0, n));
+    return SBX_OK;
+  };
+  rc = run();
+  (void)hipFree(stage);
+  c->solved = false;
+  c->grids_fields = false;
+  c->step_count = 0;
+  return rc;
+}
+
+sbx_status sbx_build_grids(sbx_ctx* c, int32_t n_galaxies, const sbx_hierarchy* h) {
+  if (!c) {
+    set_error("null context");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(validate(n_galaxies, h));
+  SBX_TRY(set_device(c->cfg.device));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  free_grids(c);
+  c->ngal = n_galaxies;
+  c->N = h[0].lv[0].n;
+  std::memset(&c->sys, 0, sizeof(c->sys));
+  c->sys.ngal = n_galaxies;
+  c->sys.taylor = c->cfg.taylor ? 1 : 0;
+  for (int g = 0; g < n_galaxies; ++g) {
+    c->hh[g] = h[g];
+    HierDev& d = c->sys.h[g];
+    d.n_levels = h[g].n_levels;
+    d.centring = h[g].centring;
+    for (int k = 0; k < h[g].n_levels; ++k) d.lv[k] = make_level(h[g].lv[k]);
+    for (int k = 0; k < 3; ++k) {
+      d.centre[k] = h[g].centre[k];
+      d.outer_c[k] = h[g].outer_centre[k];
+    }
+    c->nslots[g] = slot_count(h[g]);
+    for (int s = 0; s < c->nslots[g]; ++s) c->slot_level[g][s] = slot_level_of(h[g], s);
+  }
+  sbx_status rc = c->cfg.prec == SBX_FP64 ? build_grids_t<double>(c) : build_grids_t<float>(c);
+  if (rc != SBX_OK) {
+    free_grids(c);
+    return rc;
+  }
+  c->built = true;
+  return SBX_OK;
+}
+
+sbx_status sbx_compute_forces(sbx_ctx* c, double* acc, double* pot) {
+  SBX_TRY(check_ready(c));
+  SBX_TRY(ensure_acc(c));
+  SBX_TRY(field_solve(c));
+  SBX_TRY(force(c, 0.0, 2, nullptr));
+  if (acc) SBX_HIP(hipMemcpyAsync(acc, c->acc, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
+  if (pot) SBX_HIP(hipMemcpyAsync(pot, c->pot, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  return SBX_OK;
+}
+
+sbx_status sbx_step(sbx_ctx* c, double dt, int32_t nsteps, int32_t diag_every) {
+  SBX_TRY(check_ready(c));
+  if (!std::isfinite(dt) || nsteps < 0) {
+    set_error("dt must be finite and nsteps >= 0");
+    return SBX_EINVAL;
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    SBX_TRY(field_solve(c));
+    const bool diag = diag_every > 0 && (c->step_count % diag_every) == 0;
+    if (diag && c->diag_count < kDiagCap) {
+      SBX_TRY(force(c, dt, 1 | 4, c->diag_log + (size_t)kNDiag * c->diag_count));
+      ++c->diag_count;
+    } else {
+      SBX_TRY(force(c, dt, 1, nullptr));
+    }
+    ++c->step_count;
+  }
+  return SBX_OK;
+}
+
+sbx_status sbx_get_particles(sbx_ctx* c, double* x, double* v, uint8_t* lost) {
+  if (!c || c->n == 0) {
+    set_error("no particles loaded");
+    return c ? SBX_ESTATE : SBX_EINVAL;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  double* stage = nullptr;
+  SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 3 * c->n));
+  auto run = [&]() -> sbx_status {
+    for (int which = 0; which < 2; ++which) {
+      double* out = which == 0 ? x : v;
+      void** src = which == 0 ? c->x : c->v;
+      if (!out) continue;
+      if (c->cfg.prec == SBX_FP64)
+        SBX_TRY(launch_join3<double>((double*)src[0], (double*)src[1], (double*)src[2], stage, c->n, c->stream));
+      else
+        SBX_TRY(launch_join3<float>((float*)src[0], (float*)src[1], (float*)src[2], stage, c->n, c->stream));
+      SBX_HIP(hipMemcpyAsync(out, stage, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
+      SBX_HIP(hipStreamSynchronize(c->stream));
+    }
+    if (lost) {
+      SBX_HIP(hipMemcpyAsync(lost, c->lost, c->n, hipMemcpyDeviceToHost, c->stream));
+    }
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    return SBX_OK;
+  };
+  const sbx_status rc = run();
+  (void)hipFree(stage);
+  return rc;
+}
+
+sbx_status sbx_get_centres(sbx_ctx* c, double* centres) {
+  SBX_TRY(check_ready(c));
+  if (!centres) {
+    set_error("null output");
+    return SBX_EINVAL;
+  }
+  if (!c->solved) {
+    for (int g = 0; g < c->ngal; ++g)
+      for (int k = 0; k < 3; ++k) centres[3 * g + k] = c->hh[g].centre[k];
+    return SBX_OK;
+  }
+  SBX_HIP(hipMemcpyAsync(centres, c->centres, sizeof(double) * 3 * c->ngal, hipMemcpyDeviceToHost,
+                         c->stream));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  return SBX_OK;
+}
+
+sbx_status sbx_get_indices(sbx_ctx* c, int32_t galaxy, int32_t level, int32_t* idx, int8_t* cls) {
+  SBX_TRY(check_ready(c));
+  if (galaxy < 0 || galaxy >= c->ngal || level < 0 || level >= c->hh[galaxy].n_levels) {
+    set_error("galaxy or level out of range");
+    return SBX_EINVAL;
+  }
+  if (!c->solved) {
+    // fixed centres until the first solve has computed them
+    double hc[3 * kMaxGal];
+    for (int g = 0; g < c->ngal; ++g)
+      for (int k = 0; k < 3; ++k) hc[3 * g + k] = c->hh[g].centre[k];
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    SBX_HIP(hipMemcpy(c->centres, hc, sizeof(double) * 3 * c->ngal, hipMemcpyHostToDevice));
+  }
+  int32_t* di = nullptr;
+  int8_t* dc = nullptr;
+  SBX_TRY(dev_alloc((void**)&di, sizeof(int32_t) * 3 * c->n));
+  if (dev_alloc((void**)&dc, c->n) != SBX_OK) {
+    (void)hipFree(di);
+    return SBX_ENOMEM;
+  }
+  auto run = [&]() -> sbx_status {
+    if (c->cfg.prec == SBX_FP64)
+      SBX_TRY(launch_indices<double>(part_of<double>(c), c->sys, c->centres, galaxy, level, di, dc, c->stream));
+    else
+      SBX_TRY(launch_indices<float>(part_of<float>(c), c->sys, c->centres, galaxy, level, di, dc, c->stream));
+    if (idx) SBX_HIP(hipMemcpyAsync(idx, di, sizeof(int32_t) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
+    if (cls) SBX_HIP(hipMemcpyAsync(cls, dc, c->n, hipMemcpyDeviceToHost, c->stream));
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    return SBX_OK;
+  };
+  const sbx_status rc = run();
+  (void)hipFree(di);
+  (void)hipFree(dc);
+  return rc;
+}
+
+sbx_status sbx_get_grid(sbx_ctx* c, int32_t galaxy, int32_t which, int32_t kind, double* out) {
+  SBX_TRY(check_ready(c));
+  if (galaxy < 0 || galaxy >= c->ngal || which < 0 || which >= c->nslots[galaxy] || !out ||
+      (kind != 0 && kind != 1)) {
+    set_error("galaxy, grid or kind out of range");
+    return SBX_EINVAL;
+  }
+  if (!c->solved || (kind == 1 && !c->grids_fields)) {
+    set_error("no solve has run since the last change of the grids");
+    return SBX_ESTATE;
+  }
+  const size_t cells = (size_t)c->N * c->N * c->N;
+  if (kind == 0) {
+    // cell masses: re-run the assignment only (the solve overwrote them)
+    if (c->cfg.prec == SBX_FP64) {
+      SBX_TRY(launch_zero<double>((double*)c->grid_block, cells * c->nsolves, c->stream));
+      SBX_TRY(launch_deposit<double>(part_of<double>(c), c->sys, c->centres, grids_of<double>(c), c->stream));
+    } else {
+      SBX_TRY(launch_zero<float>((float*)c->grid_block, cells * c->nsolves, c->stream));
+      SBX_TRY(launch_deposit<float>(part_of<float>(c), c->sys, c->centres, grids_of<float>(c), c->stream));
+    }
+    c->grids_fields = false;
+  }
+  double* stage = nullptr;
+  SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * cells));
+  auto run = [&]() -> sbx_status {
+    if (c->cfg.prec == SBX_FP64)
+      SBX_TRY(launch_convert_out<double>((double*)c->grid[galaxy][which], stage, cells, c->stream));
+    else
+      SBX_TRY(launch_convert_out<float>((float*)c->grid[galaxy][which], stage, cells, c->stream));
+    SBX_HIP(hipMemcpyAsync(out, stage, sizeof(double) * cells, hipMemcpyDeviceToHost, c->stream));
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    return SBX_OK;
+  };
+  const sbx_status rc = run();
+  (void)hipFree(stage);
+  return rc;
+}
+
+sbx_status sbx_diagnostics(sbx_ctx* c, double dt, sbx_diag* out) {
+  SBX_TRY(check_ready(c));
+  if (!out || !std::isfinite(dt)) {
+    set_error("null output or non-finite dt");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(field_solve(c));
+  SBX_TRY(force(c, dt, 4, c->diag_one));
+  double r[kNDiag];
+  SBX_HIP(hipMemcpyAsync(r, c->diag_one, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  to_diag(r, out);
+  return SBX_OK;
+}
+
+sbx_status sbx_diag_log(sbx_ctx* c, int32_t max, sbx_diag* out, int32_t* count) {
+  if (!c || !count || max < 0 || (max > 0 && !out)) {
+    set_error("bad argument");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  *count = (int32_t)c->diag_count;
+  const int64_t k = std::min<int64_t>(max, c->diag_count);
+  if (k <= 0) return SBX_OK;
+  std::vector<double> r((size_t)k * kNDiag);
+  SBX_HIP(hipMemcpyAsync(r.data(), c->diag_log, sizeof(double) * r.size(), hipMemcpyDeviceToHost, c->stream));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  for (int64_t i = 0; i < k; ++i) to_diag(r.data() + i * kNDiag, out + i);
+  return SBX_OK;
+}
+
+sbx_status sbx_sync(sbx_ctx* c) {
+  if (!c) {
+    set_error("null context");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  return SBX_OK;
+}
+
+sbx_status sbx_count_live(sbx_ctx* c, int64_t* live) {
+  if (!c || !live) {
+    set_error("null argument");
+    return SBX_EINVAL;
+  }
+  if (c->n == 0) {
+    *live = 0;
+    return SBX_OK;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  std::vector<uint8_t> l((size_t)c->n);
+  SBX_HIP(hipMemcpyAsync(l.data(), c->lost, c->n, hipMemcpyDeviceToHost, c->stream));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  int64_t k = 0;
+  for (uint8_t b : l) k += b ? 0 : 1;
+  *live = k;
+  return SBX_OK;
+}
+
+// ------------------------------------------------------- Poisson plans -----
+sbx_status sbx_poisson_create(int32_t n, double R, double q, double G, int32_t h0_mode, int32_t prec,
+                              int32_t device, void* stream, sbx_poisson** out) {
+  if (!out || !is_pow2_grid(n) || !(R > 0.0) || !(q > 0.0) || !(q <= 1.0) || !(G > 0.0) ||
+      (h0_mode != 0 && h0_mode != 2) || (prec != SBX_FP32 && prec != SBX_FP64)) {
+    set_error("bad Poisson plan arguments");
+    return SBX_EINVAL;
+  }
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    set_error("no HIP device available");
+    return SBX_EDEVICE;
+  }
+  SBX_TRY(set_device(device));
+  sbx_poisson* p = new (std::nothrow) sbx_poisson();
+  if (!p) return SBX_ENOMEM;
+  p->N = n;
+  p->prec = prec;
+  p->device = device;
+  p->geo = sbx_level{n, R, q};
+  p->G = G;
+  if (stream) {
+    p->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreate(&p->stream) != hipSuccess) {
+      delete p;
+      set_error("hipStreamCreate failed");
+      return SBX_EDEVICE;
+    }
+    p->own_stream = true;
+  }
+  const size_t es = prec == SBX_FP64 ? 8 : 4;
+  sbx_status rc = dev_alloc(&p->H, h_elems(n) * es);
+  if (rc == SBX_OK) {
+    const LevelDev L = make_level(p->geo);
+    rc = prec == SBX_FP64 ? build_green<double>(n, L.l, L.lz, G, h0_mode, (double*)p->H, &p->rel_imag, p->stream)
+                          : build_green<float>(n, L.l, L.lz, G, h0_mode, (float*)p->H, &p->rel_imag, p->stream);
+  }
+  if (rc != SBX_OK) {
+    sbx_poisson_destroy(p);
+    return rc;
+  }
+  p->bytes = (int64_t)(h_elems(n) * es);
+  *out = p;
+  return SBX_OK;
+}
+
+void sbx_poisson_destroy(sbx_poisson* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  free_ptr(p->H);
+  free_ptr(p->X);
+  free_ptr(p->C);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+sbx_status sbx_poisson_solve(sbx_poisson* p, int32_t batch, const void* rho, void* phi) {
+  if (!p || !rho || !phi || batch <= 0 || batch > 64) {
+    set_error("bad Poisson solve arguments");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(p->device));
+  return p->prec == SBX_FP64 ? poisson_solve_t<double>(p, batch, rho, phi)
+                             : poisson_solve_t<float>(p, batch, rho, phi);
+}
+
+sbx_status sbx_poisson_green(sbx_poisson* p, double* out, double* rel_imag) {
+  if (!p || !out) {
+    set_error("null argument");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(p->device));
+  const size_t n = h_elems(p->N);
+  double* stage = nullptr;
+  SBX_TRY(dev_alloc((void**)&stage, n * sizeof(double)));
+  sbx_status rc = p->prec == SBX_FP64 ? launch_convert_out<double>((double*)p->H, stage, n, p->stream)
+                                      : launch_convert_out<float>((float*)p->H, stage, n, p->stream);
+  if (rc == SBX_OK) {
+    if (hipMemcpyAsync(out, stage, n * sizeof(double), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+        hipStreamSynchronize(p->stream) != hipSuccess) {
+      set_error("copy of the Green's table failed");
+      rc = SBX_EDEVICE;
+    }
+  }
+  (void)hipFree(stage);
+  if (rel_imag) *rel_imag = p->rel_imag;
+  return rc;
+}
+
+int64_t sbx_poisson_bytes(sbx_poisson* p) { return p ? p->bytes : 0; }
+
+}  // extern "C"

@@ -1,0 +1,529 @@
+// Particle-side kernels: loss test and centre of mass, classification and
+// nearest-grid-point mass assignment, the Eq. 8 force with the grid-selection
+// rule fused with the leapfrog kick and drift (Eq. 6), and the FP64
+// diagnostic reductions.
+//
+// Cell indices and classes are integers decided by float64 arithmetic with
+// every operation rounded separately (no fused multiply-add), so that any
+// other implementation following the same formulas gets identical integers.
+#include "particles.h"
+
+namespace sbx {
+
+// ------------------------------------------------------------ cell index --
+// Eq. 7: a = [gamma (x - c) + N/2], nearest integer = floor(u + 0.5).
+__device__ __forceinline__ int ngp_cell(double x, double c, double gamma, double half) {
+#pragma clang fp contract(off)
+  const double d = x - c;
+  double u = d * gamma;
+  u = u + half;
+  const double f = floor(u + 0.5);
+  // keep the integer conversion defined far outside the grid (and for NaN)
+  if (!(f >= -1073741824.0)) return -1073741824;
+  if (f > 1073741824.0) return 1073741824;
+  return (int)f;
+}
+
+// (dx^2 + dy^2) + (dz/q)^2, each operation rounded
+__device__ __forceinline__ double sph_r2(double dx, double dy, double dz, double inv_q) {
+#pragma clang fp contract(off)
+  const double dzq = dz * inv_q;
+  const double a = dx * dx;
+  const double b = dy * dy;
+  const double c = dzq * dzq;
+  return (a + b) + c;
+}
+
+__device__ __forceinline__ bool usable(const int* i, int N) {
+  return i[0] >= 2 && i[0] <= N - 3 && i[1] >= 2 && i[1] <= N - 3 && i[2] >= 2 && i[2] <= N - 3;
+}
+
+__device__ __forceinline__ void cell3(const LevelDev& L, const double* c, double x, double y,
+                                      double z, int* i) {
+  i[0] = ngp_cell(x, c[0], L.gx, L.half);
+  i[1] = ngp_cell(y, c[1], L.gx, L.half);
+  i[2] = ngp_cell(z, c[2], L.gz, L.half);
+}
+
+struct Classified {
+  int cls;         // sbx_class
+  int idx[3][3];   // cell per level
+};
+
+// Class relative to one galaxy's grids (Sec. 2.1): core (inside R1, usable on
+// all levels), ring (inside R2, usable on middle and outer), outer (usable on
+// the global grid), else lost.
+__device__ __forceinline__ void classify(const HierDev& h, const double* c, double x, double y,
+                                         double z, Classified& o) {
+  if (h.n_levels == 1) {
+    cell3(h.lv[0], c, x, y, z, o.idx[0]);
+    o.cls = usable(o.idx[0], h.lv[0].N) ? SBX_OUTER : SBX_LOST;
+    return;
+  }
+  cell3(h.lv[0], c, x, y, z, o.idx[0]);
+  cell3(h.lv[1], c, x, y, z, o.idx[1]);
+  cell3(h.lv[2], h.outer_c, x, y, z, o.idx[2]);
+  const bool ok1 = usable(o.idx[0], h.lv[0].N);
+  const bool ok2 = usable(o.idx[1], h.lv[1].N);
+  const bool ok3 = usable(o.idx[2], h.lv[2].N);
+  const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+  if (ok1 && ok2 && ok3 && sph_r2(dx, dy, dz, h.lv[0].inv_q) < h.lv[0].R2) o.cls = SBX_CORE;
+  else if (ok2 && ok3 && sph_r2(dx, dy, dz, h.lv[1].inv_q) < h.lv[1].R2) o.cls = SBX_RING;
+  else if (ok3) o.cls = SBX_OUTER;
+  else o.cls = SBX_LOST;
+}
+
+// Outside the usable cells of the fixed global grid (the outer level of
+// galaxy 0, shared by all galaxies, or the single grid).
+__device__ __forceinline__ bool outside_global(const SysDev& sys, double x, double y, double z) {
+  const HierDev& h = sys.h[0];
+  int i[3];
+  if (h.n_levels == 1) {
+    cell3(h.lv[0], h.centre, x, y, z, i);
+    return !usable(i, h.lv[0].N);
+  }
+  cell3(h.lv[2], h.outer_c, x, y, z, i);
+  return !usable(i, h.lv[2].N);
+}
+
+// ------------------------------------------------------------ reductions --
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum vals[0..nv) over the block (256 threads) in a fixed order; thread k
+// writes total k to out[k].
+template <int NV>
+__device__ __forceinline__ void block_sum_store(const double* vals, double* out) {
+  __shared__ double red[4][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum(vals[k]);
+    if (lane == 0) red[wave][k] = s;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NV; k += blockDim.x)
+    out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+}
+
+// out[k] = sum over b of partial[b * nv + k], b in increasing order
+__global__ void k_reduce_rows(const double* __restrict__ partial, int nrows, int nv,
+                              double* __restrict__ out) {
+  for (int k = threadIdx.x; k < nv; k += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nrows; ++b) s += partial[(size_t)b * nv + k];
+    out[k] = s;
+  }
+}
+
+// ------------------------------------------------------ loss test and COM --
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_pre(PartDev<T> p, SysDev sys, double* __restrict__ partial) {
+  double acc[kPreVals];
+#pragma unroll
+  for (int k = 0; k < kPreVals; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+    if (p.lost[i]) continue;
+    const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+    if (outside_global(sys, x, y, z)) {
+      p.lost[i] = 1;
+      continue;
+    }
+    const int g = p.gal[i];
+#pragma unroll
+    for (int gg = 0; gg < kMaxGal; ++gg) {
+      if (gg == g && sys.h[gg].centring == SBX_CENTRE_COM) {
+        const double m = (double)p.m[i];
+        acc[4 * gg + 0] += m;
+        acc[4 * gg + 1] += m * x;
+        acc[4 * gg + 2] += m * y;
+        acc[4 * gg + 3] += m * z;
+      }
+    }
+  }
+  block_sum_store<kPreVals>(acc, partial + (size_t)blockIdx.x * kPreVals);
+}
+
+__global__ void k_centres(const double* __restrict__ sums, SysDev sys, double* __restrict__ centres) {
+  const int g = threadIdx.x;
+  if (g >= sys.ngal) return;
+  const HierDev& h = sys.h[g];
+  double c[3] = {h.centre[0], h.centre[1], h.centre[2]};
+  if (h.centring == SBX_CENTRE_COM && sums[4 * g] > 0.0) {
+    c[0] = sums[4 * g + 1] / sums[4 * g];
+    c[1] = sums[4 * g + 2] / sums[4 * g];
+    c[2] = sums[4 * g + 3] / sums[4 * g];
+  }
+  centres[3 * g + 0] = c[0];
+  centres[3 * g + 1] = c[1];
+  centres[3 * g + 2] = c[2];
+}
+
+// ---------------------------------------------------------- mass deposit --
+template <typename T>
+__device__ __forceinline__ void add_cell(T* grid, const LevelDev& L, const int* i, T m) {
+  const size_t o = ((size_t)i[2] * L.N + i[1]) * L.N + i[0];
+  unsafeAtomicAdd(grid + o, m);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_deposit(PartDev<T> p, SysDev sys, const double* __restrict__ centres, GridsDev<T> G) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n || p.lost[i]) return;
+  const int g = p.gal[i];
+  const HierDev& h = sys.h[g];
+  const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+  Classified c;
+  classify(h, centres + 3 * g, x, y, z, c);
+  const T m = p.m[i];
+  if (h.n_levels == 1) {
+    if (c.cls == SBX_OUTER) add_cell(G.g[g][0], h.lv[0], c.idx[0], m);
+    return;
+  }
+  switch (c.cls) {
+    case SBX_CORE:
+      add_cell(G.g[g][0], h.lv[0], c.idx[0], m);   // grid 1
+      add_cell(G.g[g][2], h.lv[1], c.idx[1], m);   // grid 2 (in 2+3)
+      add_cell(G.g[g][4], h.lv[2], c.idx[2], m);   // grid 4 (in 4+5)
+      break;
+    case SBX_RING:
+      add_cell(G.g[g][1], h.lv[1], c.idx[1], m);   // grid 3
+      add_cell(G.g[g][2], h.lv[1], c.idx[1], m);   // grid 3 (in 2+3)
+      add_cell(G.g[g][4], h.lv[2], c.idx[2], m);   // grid 4 (in 4+5)
+      break;
+    case SBX_OUTER:
+      add_cell(G.g[g][3], h.lv[2], c.idx[2], m);   // grid 5
+      add_cell(G.g[g][4], h.lv[2], c.idx[2], m);   // grid 5 (in 4+5)
+      break;
+    default:
+      break;
+  }
+}
+
+// ------------------------------------------------------------------ Eq. 8 --
+// Acceleration (+grad Phi) and Phi at the particle from one field on one
+// level: central differences plus the second-order Taylor terms, the offset
+// Delta = (x - c) - (i - N/2) * l measured from the cell centre.
+template <typename T>
+__device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, const int* id,
+                                    double dx, double dy, double dz, int taylor, T* a, T& phi,
+                                    bool want_phi) {
+  const ptrdiff_t sy = L.N, sz = (ptrdiff_t)L.N * L.N;
+  const T* P = F + (ptrdiff_t)id[2] * sz + (ptrdiff_t)id[1] * sy + id[0];
+  const T Dx = (T)(dx - ((double)id[0] - L.half) * L.l);
+  const T Dy = (T)(dy - ((double)id[1] - L.half) * L.l);
+  const T Dz = (T)(dz - ((double)id[2] - L.half) * L.lz);
+  const T i2l = (T)(0.5 / L.l), i2lz = (T)(0.5 / L.lz);
+  const T p0 = P[0];
+  const T xp = P[1], xm = P[-1], yp = P[sy], ym = P[-sy], zp = P[sz], zm = P[-sz];
+  const T gx = (xp - xm) * i2l, gy = (yp - ym) * i2l, gz = (zp - zm) * i2lz;
+  if (!taylor) {
+    a[0] += gx;
+    a[1] += gy;
+    a[2] += gz;
+    if (want_phi) phi += p0 + gx * Dx + gy * Dy + gz * Dz;
+    return;
+  }
+  const T il2 = (T)(1.0 / (L.l * L.l)), ilz2 = (T)(1.0 / (L.lz * L.lz));
+  const T i4xy = (T)(1.0 / (4.0 * L.l * L.l)), i4xz = (T)(1.0 / (4.0 * L.l * L.lz));
+  const T hxx = (xp + xm - (T)2 * p0) * il2;
+  const T hyy = (yp + ym - (T)2 * p0) * il2;
+  const T hzz = (zp + zm - (T)2 * p0) * ilz2;
+  const T hxy = (P[1 + sy] - P[-1 + sy] + P[-1 - sy] - P[1 - sy]) * i4xy;
+  const T hxz = (P[1 + sz] - P[-1 + sz] + P[-1 - sz] - P[1 - sz]) * i4xz;
+  const T hyz = (P[sy + sz] - P[-sy + sz] + P[-sy - sz] - P[sy - sz]) * i4xz;
+  a[0] += gx + hxx * Dx + hxy * Dy + hxz * Dz;
+  a[1] += gy + hyy * Dy + hxy * Dx + hyz * Dz;
+  a[2] += gz + hzz * Dz + hxz * Dx + hyz * Dy;
+  if (want_phi)
+    phi += p0 + gx * Dx + gy * Dy + gz * Dz +
+           (T)0.5 * (hxx * Dx * Dx + hyy * Dy * Dy + hzz * Dz * Dz) + hxy * Dx * Dy +
+           hxz * Dx * Dz + hyz * Dy * Dz;
+}
+
+// Sum over galaxies of the fields the grid-selection rule gives each class:
+// core -> grid 1 + grid 3 + grid 5, ring -> (2 + 3) + grid 5, outer -> (4 + 5).
+template <typename T>
+__device__ __forceinline__ void particle_field(const SysDev& sys, const double* centres,
+                                               const GridsDev<T>& F, double x, double y,
+                                               double z, T* a, T& phi, bool want_phi) {
+  for (int g = 0; g < sys.ngal; ++g) {
+    const HierDev& h = sys.h[g];
+    const double* c = centres + 3 * g;
+    Classified cl;
+    classify(h, c, x, y, z, cl);
+    const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+    if (h.n_levels == 1) {
+      if (cl.cls == SBX_OUTER) eq8(F.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, sys.taylor, a, phi, want_phi);
+      continue;
+    }
+    const double ox = x - h.outer_c[0], oy = y - h.outer_c[1], oz = z - h.outer_c[2];
+    switch (cl.cls) {
+      case SBX_CORE:
+        eq8(F.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, sys.taylor, a, phi, want_phi);
+        eq8(F.g[g][1], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, a, phi, want_phi);
+        eq8(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
+        break;
+      case SBX_RING:
+        eq8(F.g[g][2], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, a, phi, want_phi);
+        eq8(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
+        break;
+      case SBX_OUTER:
+        eq8(F.g[g][4], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
+        break;
+      default:
+        break;
+    }
+  }
+}
+
+// MODE bits: 1 move, 2 write acc/pot, 4 diagnostics
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256)
+    k_force(PartDev<T> p, SysDev sys, const double* __restrict__ centres, GridsDev<T> F, T dt,
+            double dtd, double* __restrict__ acc_out, double* __restrict__ pot_out,
+            double* __restrict__ partial) {
+  constexpr bool MOVE = MODE & 1, OUT = MODE & 2, DIAG = MODE & 4;
+  double dg[DIAG ? kNDiag : 1];
+  if constexpr (DIAG) {
+    for (int k = 0; k < kNDiag; ++k) dg[k] = 0.0;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+    if (p.lost[i]) {
+      if constexpr (OUT) {
+        acc_out[3 * i] = acc_out[3 * i + 1] = acc_out[3 * i + 2] = 0.0;
+        pot_out[i] = 0.0;
+      }
+      if constexpr (DIAG) dg[kDiagLost] += 1.0;
+      continue;
+    }
+    const T xs = p.x[0][i], ys = p.x[1][i], zs = p.x[2][i];
+    const double x = (double)xs, y = (double)ys, z = (double)zs;
+    T a[3] = {(T)0, (T)0, (T)0};
+    T phi = (T)0;
+    particle_field(sys, centres, F, x, y, z, a, phi, OUT || DIAG);
+    if constexpr (OUT) {
+      acc_out[3 * i] = (double)a[0];
+      acc_out[3 * i + 1] = (double)a[1];
+      acc_out[3 * i + 2] = (double)a[2];
+      pot_out[i] = -(double)phi;
+    }
+    if constexpr (DIAG) {
+      const double m = (double)p.m[i];
+      const double vx = (double)p.v[0][i] + 0.5 * dtd * (double)a[0];
+      const double vy = (double)p.v[1][i] + 0.5 * dtd * (double)a[1];
+      const double vz = (double)p.v[2][i] + 0.5 * dtd * (double)a[2];
+      const int c = p.comp[i] & (kNComp - 1);
+      double* d = dg + kDiagComp * c;
+      d[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+      d[1] += 0.5 * m * (-(double)phi);
+      d[2] += m * (y * vz - z * vy);
+      d[3] += m * (z * vx - x * vz);
+      d[4] += m * (x * vy - y * vx);
+      d[5] += 1.0;
+      if (c == 0 && p.gal[i] == 0) {
+        const double rx = x - centres[0], ry = y - centres[1];
+        const double R = sqrt(rx * rx + ry * ry);
+        const double vR = R > 0.0 ? (rx * vx + ry * vy) / R : 0.0;
+        dg[kDiagDisc + 0] += vR;
+        dg[kDiagDisc + 1] += vR * vR;
+        dg[kDiagDisc + 2] += vz;
+        dg[kDiagDisc + 3] += vz * vz;
+        dg[kDiagDisc + 4] += 1.0;
+      }
+    }
+    if constexpr (MOVE) {
+      const T vx = p.v[0][i] + dt * a[0];
+      const T vy = p.v[1][i] + dt * a[1];
+      const T vz = p.v[2][i] + dt * a[2];
+      const T nx = xs + dt * vx, ny = ys + dt * vy, nz = zs + dt * vz;
+      p.v[0][i] = vx;
+      p.v[1][i] = vy;
+      p.v[2][i] = vz;
+      p.x[0][i] = nx;
+      p.x[1][i] = ny;
+      p.x[2][i] = nz;
+      if (outside_global(sys, (double)nx, (double)ny, (double)nz)) p.lost[i] = 1;
+    }
+  }
+  if constexpr (DIAG) block_sum_store<kNDiag>(dg, partial + (size_t)blockIdx.x * kNDiag);
+}
+
+// ------------------------------------------------------------- readouts ---
+template <typename T>
+__global__ void k_indices(PartDev<T> p, SysDev sys, const double* __restrict__ centres, int g,
+                          int level, int32_t* __restrict__ idx, int8_t* __restrict__ cls) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  Classified c;
+  classify(sys.h[g], centres + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
+  if (idx) {
+    idx[3 * i] = c.idx[level][0];
+    idx[3 * i + 1] = c.idx[level][1];
+    idx[3 * i + 2] = c.idx[level][2];
+  }
+  if (cls) cls[i] = (int8_t)c.cls;
+}
+
+template <typename T>
+__global__ void k_zero(T* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = (T)0;
+}
+
+template <typename A, typename B>
+__global__ void k_convert(const A* __restrict__ s, B* __restrict__ d, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    d[i] = (B)s[i];
+}
+
+template <typename T>
+__global__ void k_split3(const double* __restrict__ s, T* x0, T* x1, T* x2, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x0[i] = (T)s[3 * i];
+    x1[i] = (T)s[3 * i + 1];
+    x2[i] = (T)s[3 * i + 2];
+  }
+}
+
+template <typename T>
+__global__ void k_join3(const T* x0, const T* x1, const T* x2, double* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    d[3 * i] = (double)x0[i];
+    d[3 * i + 1] = (double)x1[i];
+    d[3 * i + 2] = (double)x2[i];
+  }
+}
+
+// ------------------------------------------------------------- launchers --
+static inline unsigned blocks_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+template <typename T>
+sbx_status launch_zero(T* p, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_zero<T>), dim3(2048), dim3(256), 0, s, p, n);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_pre(const PartDev<T>& p, const SysDev& sys, double* partial, double* centres,
+                      hipStream_t s) {
+  hipLaunchKernelGGL((k_pre<T>), dim3(kRedBlocks), dim3(256), 0, s, p, sys, partial);
+  double* sums = partial + (size_t)kRedBlocks * kPreVals;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(64), 0, s, partial, kRedBlocks, kPreVals, sums);
+  hipLaunchKernelGGL(k_centres, dim3(1), dim3(64), 0, s, sums, sys, centres);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_deposit(const PartDev<T>& p, const SysDev& sys, const double* centres,
+                          const GridsDev<T>& grids, hipStream_t s) {
+  if (p.n == 0) return SBX_OK;
+  hipLaunchKernelGGL((k_deposit<T>), dim3(blocks_for(p.n)), dim3(256), 0, s, p, sys, centres, grids);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_force(const PartDev<T>& p, const SysDev& sys, const double* centres,
+                        const GridsDev<T>& F, double dt, int mode, double* acc, double* pot,
+                        double* partial, double* diag_out, hipStream_t s) {
+  const T dtt = (T)dt;
+  const dim3 b(256);
+  const dim3 g = (mode & 4) ? dim3(kRedBlocks) : dim3(blocks_for(p.n));
+#define SBX_FORCE(M)                                                                          \
+  case M:                                                                                     \
+    hipLaunchKernelGGL((k_force<T, M>), g, b, 0, s, p, sys, centres, F, dtt, dt, acc, pot,   \
+                       partial);                                                              \
+    break;
+  switch (mode) {
+    SBX_FORCE(1)
+    SBX_FORCE(2)
+    SBX_FORCE(4)
+    SBX_FORCE(5)
+    SBX_FORCE(6)
+    default:
+      set_error("bad force mode");
+      return SBX_EINVAL;
+  }
+#undef SBX_FORCE
+  if (mode & 4)
+    hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(64), 0, s, partial, kRedBlocks, kNDiag,
+                       diag_out);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_indices(const PartDev<T>& p, const SysDev& sys, const double* centres, int galaxy,
+                          int level, int32_t* idx, int8_t* cls, hipStream_t s) {
+  if (p.n == 0) return SBX_OK;
+  hipLaunchKernelGGL((k_indices<T>), dim3(blocks_for(p.n)), dim3(256), 0, s, p, sys, centres, galaxy,
+                     level, idx, cls);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_convert_in(const double* src, T* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(2048), dim3(256), 0, s, src, dst, n);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_convert_out(const T* src, double* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(2048), dim3(256), 0, s, src, dst, n);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_split3(const double* src, T* x0, T* x1, T* x2, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_split3<T>), dim3(2048), dim3(256), 0, s, src, x0, x1, x2, n);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_join3(const T* x0, const T* x1, const T* x2, double* dst, int64_t n,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((k_join3<T>), dim3(2048), dim3(256), 0, s, x0, x1, x2, dst, n);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+#define SBX_INST(T)                                                                              \
+  template sbx_status launch_zero<T>(T*, size_t, hipStream_t);                                   \
+  template sbx_status launch_pre<T>(const PartDev<T>&, const SysDev&, double*, double*,          \
+                                    hipStream_t);                                                \
+  template sbx_status launch_deposit<T>(const PartDev<T>&, const SysDev&, const double*,         \
+                                        const GridsDev<T>&, hipStream_t);                        \
+  template sbx_status launch_force<T>(const PartDev<T>&, const SysDev&, const double*,           \
+                                      const GridsDev<T>&, double, int, double*, double*,         \
+                                      double*, double*, hipStream_t);                            \
+  template sbx_status launch_indices<T>(const PartDev<T>&, const SysDev&, const double*, int,    \
+                                        int, int32_t*, int8_t*, hipStream_t);                    \
+  template sbx_status launch_convert_in<T>(const double*, T*, size_t, hipStream_t);              \
+  template sbx_status launch_convert_out<T>(const T*, double*, size_t, hipStream_t);             \
+  template sbx_status launch_split3<T>(const double*, T*, T*, T*, int64_t, hipStream_t);         \
+  template sbx_status launch_join3<T>(const T*, const T*, const T*, double*, int64_t, hipStream_t);
+SBX_INST(float)
+SBX_INST(double)
+#undef SBX_INST
+
+}  // namespace sbx
