@@ -97,8 +97,10 @@ def make_ctx(sbx, w, prec):
     return ctx
 
 
-def timed_steps(sbx, torch, w, prec, steps, warmup, diag_every, profile=True):
+def timed_steps(sbx, torch, w, prec, steps, warmup, diag_every, profile=True, sort_every=None):
     ctx = make_ctx(sbx, w, prec)
+    if sort_every is not None:
+        ctx.sbx_set_sort_interval(sort_every)
     ctx.sbx_step(w.dt, warmup, diag_every)
     ctx.sbx_sync()
     live0 = ctx.sbx_count_live()
@@ -152,6 +154,9 @@ def main():
     ap.add_argument("--cpu-frac", type=float, default=0.3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only the FP32 step loop (for profiler runs)")
+    ap.add_argument("--sort-every", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -169,22 +174,25 @@ def main():
 
     _log(f"FP32: {args.warmup} warmup + {args.steps} timed steps")
     t32, live32, ph32 = timed_steps(sbx, torch, w, sbx.SBX_FP32, args.steps, args.warmup,
-                                    args.diag_every)
+                                    args.diag_every, sort_every=args.sort_every)
     value = live32 * args.steps / t32
     _log(f"FP32 {value:.4g} particle-steps/s ({1e3 * t32 / args.steps:.3f} ms/step)")
 
+    if args.step_only:
+        args.no_fp64 = True
+        args.no_cpu_baseline = True
     fp64 = None
     if not args.no_fp64:
         _log(f"FP64: {args.fp64_steps} timed steps")
         t64, live64, ph64 = timed_steps(sbx, torch, w, sbx.SBX_FP64, args.fp64_steps, 2,
-                                        args.diag_every)
+                                        args.diag_every, sort_every=args.sort_every)
         fp64 = {"particle_steps_per_s": live64 * args.fp64_steps / t64,
                 "ms_per_step": 1e3 * t64 / args.fp64_steps,
                 "phases_ms_per_step": {k: v[0] / args.fp64_steps for k, v in ph64.items() if v[1]}}
 
     _log("standalone 128^3 solves")
     solves = {}
-    for name, prec in (("fp32", sbx.SBX_FP32), ("fp64", sbx.SBX_FP64)):
+    for name, prec in (() if args.step_only else (("fp32", sbx.SBX_FP32), ("fp64", sbx.SBX_FP64))):
         for batch in (5, 20):
             rate, ms = time_solves(sbx, torch, 128, 4.0, 0.25, prec, batch, args.solve_iters)
             solves[f"{name}_batch{batch}"] = {"solves_per_s": rate, "ms_per_batch": ms}

@@ -173,6 +173,12 @@ sbx_status sbx_diagnostics(sbx_ctx* ctx, double dt, sbx_diag* out);
  * max entries (oldest first).  Synchronises. */
 sbx_status sbx_diag_log(sbx_ctx* ctx, int32_t max, sbx_diag* out, int32_t* count);
 
+/* Reorder the particles in device memory by the cell of their finest grid
+ * every `every` steps (at the start of the step; 0 = never; default 8).  A
+ * performance setting only: every output is returned in the caller's
+ * particle order. */
+sbx_status sbx_set_sort_interval(sbx_ctx* ctx, int32_t every);
+
 /* Block until all work queued on the context stream has finished. */
 sbx_status sbx_sync(sbx_ctx* ctx);
 

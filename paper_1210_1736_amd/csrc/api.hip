@@ -9,6 +9,7 @@
 
 #include "fft.h"
 #include "particles.h"
+#include "scan.h"
 
 namespace sbx {
 
@@ -29,6 +30,12 @@ static LevelDev make_level(const sbx_level& s) {
   L.gz = 1.0 / L.lz;
   L.inv_q = 1.0 / s.q;
   L.R2 = s.R * s.R;
+  L.c_2l = 0.5 / L.l;
+  L.c_2lz = 0.5 / L.lz;
+  L.c_l2 = 1.0 / (L.l * L.l);
+  L.c_lz2 = 1.0 / (L.lz * L.lz);
+  L.c_4ll = 1.0 / (4.0 * L.l * L.l);
+  L.c_4llz = 1.0 / (4.0 * L.l * L.lz);
   return L;
 }
 
@@ -144,6 +151,22 @@ struct sbx_ctx {
   int8_t* comp = nullptr;
   int8_t* gal = nullptr;
   uint8_t* lost = nullptr;
+  int32_t* id = nullptr;
+  // second set of particle arrays: target of the cell sort
+  void* x2[3] = {};
+  void* v2[3] = {};
+  void* m2 = nullptr;
+  int8_t* comp2 = nullptr;
+  int8_t* gal2 = nullptr;
+  uint8_t* lost2 = nullptr;
+  int32_t* id2 = nullptr;
+  uint32_t* key = nullptr;
+  uint32_t* count = nullptr;   // bins + 1
+  uint32_t* scan_tmp = nullptr;
+  size_t bins = 0;
+  int sort_every = 8;
+  double* com_partial = nullptr;  // kForceBlocksMax * kPreVals
+  bool com_fresh = false;         // com_partial holds the current positions' sums
   // grids
   bool built = false;
   int ngal = 0;
@@ -159,7 +182,7 @@ struct sbx_ctx {
   void* C = nullptr;
   int nsolves = 0;
   double* centres = nullptr;  // kMaxGal * 3
-  double* partial = nullptr;  // kRedBlocks * kNDiag + kNDiag
+  double* partial = nullptr;  // kForceBlocksMax * kNDiag + kNDiag
   double* diag_one = nullptr; // kNDiag
   double* diag_log = nullptr; // kDiagCap * kNDiag
   int64_t diag_count = 0;
@@ -201,8 +224,37 @@ PartDev<T> part_of(sbx_ctx* c) {
   p.comp = c->comp;
   p.gal = c->gal;
   p.lost = c->lost;
+  p.id = c->id;
   p.n = c->n;
   return p;
+}
+
+template <typename T>
+PartDev<T> part2_of(sbx_ctx* c) {
+  PartDev<T> p;
+  for (int k = 0; k < 3; ++k) {
+    p.x[k] = (T*)c->x2[k];
+    p.v[k] = (T*)c->v2[k];
+  }
+  p.m = (T*)c->m2;
+  p.comp = c->comp2;
+  p.gal = c->gal2;
+  p.lost = c->lost2;
+  p.id = c->id2;
+  p.n = c->n;
+  return p;
+}
+
+void swap_particles(sbx_ctx* c) {
+  for (int k = 0; k < 3; ++k) {
+    std::swap(c->x[k], c->x2[k]);
+    std::swap(c->v[k], c->v2[k]);
+  }
+  std::swap(c->m, c->m2);
+  std::swap(c->comp, c->comp2);
+  std::swap(c->gal, c->gal2);
+  std::swap(c->lost, c->lost2);
+  std::swap(c->id, c->id2);
 }
 
 template <typename T>
@@ -238,11 +290,21 @@ void free_particles(sbx_ctx* c) {
   for (int k = 0; k < 3; ++k) {
     free_ptr(c->x[k]);
     free_ptr(c->v[k]);
+    free_ptr(c->x2[k]);
+    free_ptr(c->v2[k]);
   }
   free_ptr(c->m);
   free_typed(c->comp);
   free_typed(c->gal);
   free_typed(c->lost);
+  free_typed(c->id);
+  free_ptr(c->m2);
+  free_typed(c->comp2);
+  free_typed(c->gal2);
+  free_typed(c->lost2);
+  free_typed(c->id2);
+  free_typed(c->key);
+  c->com_fresh = false;
   free_typed(c->acc);
   free_typed(c->pot);
   c->acc_n = 0;
@@ -251,6 +313,9 @@ void free_particles(sbx_ctx* c) {
 
 void free_grids(sbx_ctx* c) {
   free_ptr(c->grid_block);
+  free_typed(c->count);
+  free_typed(c->scan_tmp);
+  c->bins = 0;
   for (auto& g : c->greens) free_ptr(g.H);
   c->greens.clear();
   free_ptr(c->X);
@@ -299,6 +364,10 @@ sbx_status build_grids_t(sbx_ctx* c) {
     }
   SBX_TRY(dev_alloc(&c->X, x_elems(N) * sizeof(C2<T>) * total));
   SBX_TRY(dev_alloc(&c->C, c_elems(N) * sizeof(C2<T>) * total));
+  // counting-sort bins: one per cell of every level of every galaxy
+  c->bins = (size_t)c->ngal * 3 * N * N * N;
+  SBX_TRY(dev_alloc((void**)&c->count, sizeof(uint32_t) * (c->bins + 1)));
+  SBX_TRY(dev_alloc((void**)&c->scan_tmp, sizeof(uint32_t) * scan_tmp_elems(c->bins + 1)));
   return SBX_OK;
 }
 
@@ -316,7 +385,11 @@ sbx_status field_solve_t(sbx_ctx* c) {
   SBX_TRY(launch_zero<T>((T*)c->grid_block, cells * c->nsolves, c->stream));
   c->rec.mark(PH_ZERO, c->stream);
   const PartDev<T> p = part_of<T>(c);
-  SBX_TRY(launch_pre<T>(p, c->sys, c->partial, c->centres, c->stream));
+  if (c->com_fresh)
+    SBX_TRY(launch_centres(c->com_partial, force_blocks(c->n), c->sys,
+                           c->partial + (size_t)kRedBlocks * kPreVals, c->centres, c->stream));
+  else
+    SBX_TRY(launch_pre<T>(p, c->sys, c->partial, c->centres, c->stream));
   c->rec.mark(PH_PRE, c->stream);
   SBX_TRY(launch_deposit<T>(p, c->sys, c->centres, grids_of<T>(c), c->stream));
   c->rec.mark(PH_DEPOSIT, c->stream);
@@ -340,9 +413,31 @@ sbx_status field_solve_t(sbx_ctx* c) {
 template <typename T>
 sbx_status force_t(sbx_ctx* c, double dt, int mode, double* diag_out) {
   SBX_TRY(launch_force<T>(part_of<T>(c), c->sys, c->centres, grids_of<T>(c), dt, mode, c->acc,
-                          c->pot, c->partial, diag_out, c->stream));
+                          c->pot, c->partial, diag_out, c->com_partial, c->stream));
   c->rec.mark(PH_FORCE, c->stream);
+  if (mode & 1) c->com_fresh = true;
   return SBX_OK;
+}
+
+// Reorder the particles by the cell of their finest grid, at the centres of
+// the last solve (or the fixed centres).
+template <typename T>
+sbx_status sort_t(sbx_ctx* c) {
+  c->rec.mark(PH_START, c->stream);
+  if (!c->key) SBX_TRY(dev_alloc((void**)&c->key, sizeof(uint32_t) * c->n));
+  if (!c->solved) {
+    // centres are needed for the keys: take them from the current positions
+    SBX_TRY(launch_pre<T>(part_of<T>(c), c->sys, c->partial, c->centres, c->stream));
+  }
+  SBX_TRY(launch_sort<T>(part_of<T>(c), part2_of<T>(c), c->sys, c->centres, c->key, c->count,
+                         c->bins, c->scan_tmp, c->stream));
+  swap_particles(c);
+  c->rec.mark(PH_SORT, c->stream);
+  return SBX_OK;
+}
+
+sbx_status sort_particles(sbx_ctx* c) {
+  return c->cfg.prec == SBX_FP64 ? sort_t<double>(c) : sort_t<float>(c);
 }
 
 void free_recorder(Recorder& r) {
@@ -498,9 +593,10 @@ sbx_status sbx_create(const sbx_config* cfg, sbx_ctx** out) {
   }
   sbx_status rc = SBX_OK;
   if ((rc = dev_alloc((void**)&c->centres, sizeof(double) * 3 * kMaxGal)) != SBX_OK ||
-      (rc = dev_alloc((void**)&c->partial, sizeof(double) * ((size_t)kRedBlocks * kNDiag + kNDiag))) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->partial, sizeof(double) * ((size_t)kForceBlocksMax * kNDiag + kNDiag))) != SBX_OK ||
       (rc = dev_alloc((void**)&c->diag_one, sizeof(double) * kNDiag)) != SBX_OK ||
-      (rc = dev_alloc((void**)&c->diag_log, sizeof(double) * kNDiag * kDiagCap)) != SBX_OK) {
+      (rc = dev_alloc((void**)&c->diag_log, sizeof(double) * kNDiag * kDiagCap)) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->com_partial, sizeof(double) * kForceBlocksMax * kPreVals)) != SBX_OK) {
     sbx_destroy(c);
     return rc;
   }
@@ -518,6 +614,7 @@ void sbx_destroy(sbx_ctx* c) {
   free_typed(c->partial);
   free_typed(c->diag_one);
   free_typed(c->diag_log);
+  free_typed(c->com_partial);
   free_recorder(c->rec);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -604,11 +701,19 @@ sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const doub
   for (int k = 0; k < 3; ++k) {
     SBX_TRY(dev_alloc(&c->x[k], es * n));
     SBX_TRY(dev_alloc(&c->v[k], es * n));
+    SBX_TRY(dev_alloc(&c->x2[k], es * n));
+    SBX_TRY(dev_alloc(&c->v2[k], es * n));
   }
   SBX_TRY(dev_alloc(&c->m, es * n));
   SBX_TRY(dev_alloc((void**)&c->comp, n));
   SBX_TRY(dev_alloc((void**)&c->gal, n));
   SBX_TRY(dev_alloc((void**)&c->lost, n));
+  SBX_TRY(dev_alloc((void**)&c->id, sizeof(int32_t) * n));
+  SBX_TRY(dev_alloc(&c->m2, es * n));
+  SBX_TRY(dev_alloc((void**)&c->comp2, n));
+  SBX_TRY(dev_alloc((void**)&c->gal2, n));
+  SBX_TRY(dev_alloc((void**)&c->lost2, n));
+  SBX_TRY(dev_alloc((void**)&c->id2, sizeof(int32_t) * n));
   c->n = n;
   double* stage = nullptr;
   SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 3 * n));
@@ -635,12 +740,15 @@ sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const doub
     SBX_HIP(hipMemcpy(c->comp, comp, n, hipMemcpyHostToDevice));
     SBX_HIP(hipMemcpy(c->gal, gal, n, hipMemcpyHostToDevice));
     SBX_HIP(hipMemset(c->lost, 0, n));
+    SBX_TRY(launch_iota(c->id, n, c->stream));
+    SBX_HIP(hipStreamSynchronize(c->stream));
     return SBX_OK;
   };
   rc = run();
   (void)hipFree(stage);
   c->solved = false;
   c->grids_fields = false;
+  c->com_fresh = false;
   c->step_count = 0;
   return rc;
 }
@@ -686,10 +794,24 @@ sbx_status sbx_compute_forces(sbx_ctx* c, double* acc, double* pot) {
   SBX_TRY(ensure_acc(c));
   SBX_TRY(field_solve(c));
   SBX_TRY(force(c, 0.0, 2, nullptr));
-  if (acc) SBX_HIP(hipMemcpyAsync(acc, c->acc, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
-  if (pot) SBX_HIP(hipMemcpyAsync(pot, c->pot, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
-  SBX_HIP(hipStreamSynchronize(c->stream));
-  return SBX_OK;
+  double* stage = nullptr;
+  SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 3 * c->n));
+  auto run = [&]() -> sbx_status {
+    if (acc) {
+      SBX_TRY(launch_unpermute<double>(c->acc, c->id, stage, c->n, 3, c->stream));
+      SBX_HIP(hipMemcpyAsync(acc, stage, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
+      SBX_HIP(hipStreamSynchronize(c->stream));
+    }
+    if (pot) {
+      SBX_TRY(launch_unpermute<double>(c->pot, c->id, stage, c->n, 1, c->stream));
+      SBX_HIP(hipMemcpyAsync(pot, stage, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
+    }
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    return SBX_OK;
+  };
+  const sbx_status rc = run();
+  (void)hipFree(stage);
+  return rc;
 }
 
 sbx_status sbx_step(sbx_ctx* c, double dt, int32_t nsteps, int32_t diag_every) {
@@ -699,6 +821,7 @@ sbx_status sbx_step(sbx_ctx* c, double dt, int32_t nsteps, int32_t diag_every) {
     return SBX_EINVAL;
   }
   for (int s = 0; s < nsteps; ++s) {
+    if (c->sort_every > 0 && (c->step_count % c->sort_every) == 0) SBX_TRY(sort_particles(c));
     SBX_TRY(field_solve(c));
     const bool diag = diag_every > 0 && (c->step_count % diag_every) == 0;
     if (diag && c->diag_count < kDiagCap) {
@@ -719,7 +842,8 @@ sbx_status sbx_get_particles(sbx_ctx* c, double* x, double* v, uint8_t* lost) {
   }
   SBX_TRY(set_device(c->cfg.device));
   double* stage = nullptr;
-  SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 3 * c->n));
+  SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 6 * c->n));
+  double* stage2 = stage + 3 * c->n;
   auto run = [&]() -> sbx_status {
     for (int which = 0; which < 2; ++which) {
       double* out = which == 0 ? x : v;
@@ -729,11 +853,13 @@ sbx_status sbx_get_particles(sbx_ctx* c, double* x, double* v, uint8_t* lost) {
         SBX_TRY(launch_join3<double>((double*)src[0], (double*)src[1], (double*)src[2], stage, c->n, c->stream));
       else
         SBX_TRY(launch_join3<float>((float*)src[0], (float*)src[1], (float*)src[2], stage, c->n, c->stream));
-      SBX_HIP(hipMemcpyAsync(out, stage, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
+      SBX_TRY(launch_unpermute<double>(stage, c->id, stage2, c->n, 3, c->stream));
+      SBX_HIP(hipMemcpyAsync(out, stage2, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
       SBX_HIP(hipStreamSynchronize(c->stream));
     }
     if (lost) {
-      SBX_HIP(hipMemcpyAsync(lost, c->lost, c->n, hipMemcpyDeviceToHost, c->stream));
+      SBX_TRY(launch_unpermute<uint8_t>(c->lost, c->id, (uint8_t*)stage, c->n, 1, c->stream));
+      SBX_HIP(hipMemcpyAsync(lost, stage, c->n, hipMemcpyDeviceToHost, c->stream));
     }
     SBX_HIP(hipStreamSynchronize(c->stream));
     return SBX_OK;
@@ -776,18 +902,22 @@ sbx_status sbx_get_indices(sbx_ctx* c, int32_t galaxy, int32_t level, int32_t* i
   }
   int32_t* di = nullptr;
   int8_t* dc = nullptr;
-  SBX_TRY(dev_alloc((void**)&di, sizeof(int32_t) * 3 * c->n));
-  if (dev_alloc((void**)&dc, c->n) != SBX_OK) {
+  SBX_TRY(dev_alloc((void**)&di, sizeof(int32_t) * 6 * c->n));
+  if (dev_alloc((void**)&dc, 2 * c->n) != SBX_OK) {
     (void)hipFree(di);
     return SBX_ENOMEM;
   }
+  int32_t* di2 = di + 3 * c->n;
+  int8_t* dc2 = dc + c->n;
   auto run = [&]() -> sbx_status {
     if (c->cfg.prec == SBX_FP64)
       SBX_TRY(launch_indices<double>(part_of<double>(c), c->sys, c->centres, galaxy, level, di, dc, c->stream));
     else
       SBX_TRY(launch_indices<float>(part_of<float>(c), c->sys, c->centres, galaxy, level, di, dc, c->stream));
-    if (idx) SBX_HIP(hipMemcpyAsync(idx, di, sizeof(int32_t) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
-    if (cls) SBX_HIP(hipMemcpyAsync(cls, dc, c->n, hipMemcpyDeviceToHost, c->stream));
+    SBX_TRY(launch_unpermute<int32_t>(di, c->id, di2, c->n, 3, c->stream));
+    SBX_TRY(launch_unpermute<int8_t>(dc, c->id, dc2, c->n, 1, c->stream));
+    if (idx) SBX_HIP(hipMemcpyAsync(idx, di2, sizeof(int32_t) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
+    if (cls) SBX_HIP(hipMemcpyAsync(cls, dc2, c->n, hipMemcpyDeviceToHost, c->stream));
     SBX_HIP(hipStreamSynchronize(c->stream));
     return SBX_OK;
   };
@@ -864,6 +994,15 @@ sbx_status sbx_diag_log(sbx_ctx* c, int32_t max, sbx_diag* out, int32_t* count) 
   SBX_HIP(hipMemcpyAsync(r.data(), c->diag_log, sizeof(double) * r.size(), hipMemcpyDeviceToHost, c->stream));
   SBX_HIP(hipStreamSynchronize(c->stream));
   for (int64_t i = 0; i < k; ++i) to_diag(r.data() + i * kNDiag, out + i);
+  return SBX_OK;
+}
+
+sbx_status sbx_set_sort_interval(sbx_ctx* c, int32_t every) {
+  if (!c || every < 0) {
+    set_error("bad argument");
+    return SBX_EINVAL;
+  }
+  c->sort_every = every;
   return SBX_OK;
 }
 

@@ -15,7 +15,8 @@ constexpr int kDiagDisc = kNComp * kDiagComp;
 constexpr int kDiagLost = kDiagDisc + 5;
 constexpr int kNDiag = kDiagLost + 1;
 constexpr int kPreVals = kMaxGal * 4;  // per galaxy [m, m x, m y, m z]
-constexpr int kRedBlocks = 1024;       // fixed grid of the deterministic reductions
+constexpr int kRedBlocks = 1024;       // grid of the loss-test / centre-of-mass pass
+constexpr int kForceBlocksMax = 4096;  // grid cap of the force pass (partial rows)
 
 // One grid geometry as the kernels use it (all float64, computed on the host
 // exactly as the method's formulas read: l = 2R/(N-4), lz = q l, gamma = 1/l).
@@ -26,6 +27,8 @@ struct LevelDev {
   double gx, gz; // 1/l, 1/lz
   double inv_q;  // 1/q
   double R2;     // R*R
+  // Eq. 8 coefficients: 1/(2l), 1/(2lz), 1/l^2, 1/lz^2, 1/(4 l l), 1/(4 l lz)
+  double c_2l, c_2lz, c_l2, c_lz2, c_4ll, c_4llz;
 };
 
 struct HierDev {
@@ -50,6 +53,7 @@ struct PartDev {
   int8_t* comp;
   int8_t* gal;
   uint8_t* lost;
+  int32_t* id;   // caller's index of the particle held in this slot
   int64_t n;
 };
 
@@ -64,21 +68,47 @@ struct GridsDev {
 template <typename T>
 sbx_status launch_zero(T* p, size_t n, hipStream_t s);
 
+// Loss test at the current positions plus centre-of-mass partial sums
+// (kRedBlocks rows of kPreVals into partial), then the centres.
 template <typename T>
 sbx_status launch_pre(const PartDev<T>& p, const SysDev& sys, double* partial, double* centres,
                       hipStream_t s);
+
+// Centres from centre-of-mass partial sums (rows x kPreVals) written by the
+// previous moving force pass; `sums` receives the kPreVals column totals.
+sbx_status launch_centres(const double* partial, int rows, const SysDev& sys, double* sums,
+                          double* centres, hipStream_t s);
+
+int force_blocks(int64_t n);
+
+// Counting sort of the particles by the cell of their finest grid (relative
+// to their own galaxy): src -> dst.  key: n uint32; count: bins + 1 uint32
+// (bins = ngal * 3 * N^3); tmp: scan_tmp_elems(bins + 1).
+template <typename T>
+sbx_status launch_sort(const PartDev<T>& src, const PartDev<T>& dst, const SysDev& sys,
+                       const double* centres, uint32_t* key, uint32_t* count, size_t bins,
+                       uint32_t* tmp, hipStream_t s);
+
+sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s);
+
+// dst[id[i] * width + w] = src[i * width + w]
+template <typename A>
+sbx_status launch_unpermute(const A* src, const int32_t* id, A* dst, int64_t n, int width,
+                            hipStream_t s);
 
 template <typename T>
 sbx_status launch_deposit(const PartDev<T>& p, const SysDev& sys, const double* centres,
                           const GridsDev<T>& grids, hipStream_t s);
 
-// mode bits: 1 = move (kick + drift + loss test), 2 = write acc/pot (float64,
-// acc n*3 row-major, pot = physical phi), 4 = diagnostics record into
-// diag_out (kNDiag doubles) from partial (kRedBlocks * kNDiag).
+// mode bits: 1 = move (kick + drift + loss test; centre-of-mass partial sums
+// of the new positions into com_partial, force_blocks(n) rows of kPreVals),
+// 2 = write acc/pot (float64, acc n*3 row-major, pot = physical phi),
+// 4 = diagnostics record into diag_out (kNDiag doubles) via partial
+// (force_blocks(n) rows of kNDiag).
 template <typename T>
 sbx_status launch_force(const PartDev<T>& p, const SysDev& sys, const double* centres,
                         const GridsDev<T>& fields, double dt, int mode, double* acc, double* pot,
-                        double* partial, double* diag_out, hipStream_t s);
+                        double* partial, double* diag_out, double* com_partial, hipStream_t s);
 
 template <typename T>
 sbx_status launch_indices(const PartDev<T>& p, const SysDev& sys, const double* centres, int galaxy,

@@ -7,6 +7,7 @@
 // every operation rounded separately (no fused multiply-add), so that any
 // other implementation following the same formulas gets identical integers.
 #include "particles.h"
+#include "scan.h"
 
 namespace sbx {
 
@@ -95,27 +96,38 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Sum vals[0..nv) over the block (256 threads) in a fixed order; thread k
 // writes total k to out[k].
+// Only the first nv (<= NV) values are reduced; the rest are written as 0.
 template <int NV>
-__device__ __forceinline__ void block_sum_store(const double* vals, double* out) {
+__device__ __forceinline__ void block_sum_store(const double* vals, double* out, int nv = NV) {
   __shared__ double red[4][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
   for (int k = 0; k < NV; ++k) {
-    const double s = wave_sum(vals[k]);
-    if (lane == 0) red[wave][k] = s;
+    if (k < nv) {
+      const double s = wave_sum(vals[k]);
+      if (lane == 0) red[wave][k] = s;
+    }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < NV; k += blockDim.x)
-    out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    out[k] = k < nv ? ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k] : 0.0;
 }
 
-// out[k] = sum over b of partial[b * nv + k], b in increasing order
-__global__ void k_reduce_rows(const double* __restrict__ partial, int nrows, int nv,
-                              double* __restrict__ out) {
-  for (int k = threadIdx.x; k < nv; k += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nrows; ++b) s += partial[(size_t)b * nv + k];
-    out[k] = s;
+// out[k] = sum over rows of partial[row * nv + k]; block k, 256 threads, a
+// fixed summation order (strided per thread, then a fixed tree).
+__global__ void __launch_bounds__(256)
+    k_reduce_cols(const double* __restrict__ partial, int nrows, int nv, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < nrows; r += 256) s += partial[(size_t)r * nv + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[k] = red[0];
 }
 
 // ------------------------------------------------------ loss test and COM --
@@ -145,7 +157,7 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  block_sum_store<kPreVals>(acc, partial + (size_t)blockIdx.x * kPreVals);
+  block_sum_store<kPreVals>(acc, partial + (size_t)blockIdx.x * kPreVals, 4 * sys.ngal);
 }
 
 __global__ void k_centres(const double* __restrict__ sums, SysDev sys, double* __restrict__ centres) {
@@ -165,43 +177,134 @@ __global__ void k_centres(const double* __restrict__ sums, SysDev sys, double* _
 
 // ---------------------------------------------------------- mass deposit --
 template <typename T>
-__device__ __forceinline__ void add_cell(T* grid, const LevelDev& L, const int* i, T m) {
-  const size_t o = ((size_t)i[2] * L.N + i[1]) * L.N + i[0];
-  unsafeAtomicAdd(grid + o, m);
+__device__ __forceinline__ T* cell_ptr(T* grid, const LevelDev& L, const int* i) {
+  return grid + ((size_t)i[2] * L.N + i[1]) * L.N + i[0];
+}
+
+// Segmented sum over runs of equal keys in consecutive lanes: returns, in the
+// last lane of each run (tail = true), the run's total.  All 64 lanes call it.
+template <typename T>
+__device__ __forceinline__ T wave_run_sum(uint32_t key, T val, bool& tail) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t kprev = __shfl_up(key, 1, 64);
+  const uint32_t knext = __shfl_down(key, 1, 64);
+  int f = (lane == 0) || (kprev != key);
+  T s = val;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T su = __shfl_up(s, o, 64);
+    const int fu = __shfl_up(f, o, 64);
+    if (lane >= o) {
+      if (!f) s += su;
+      f |= fu;
+    }
+  }
+  tail = (lane == 63) || (knext != key);
+  return s;
+}
+
+// Key of a deposit target: grid slot (galaxy * 5 + slot) in the top bits,
+// cell index in the low 24 bits (N <= 256).
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+__device__ __forceinline__ uint32_t dep_key(int g, int slot, const LevelDev& L, const int* i) {
+  return ((uint32_t)(g * kSlots + slot) << 24) |
+         (uint32_t)(((i[2] * L.N) + i[1]) * L.N + i[0]);
+}
+
+// LDS-binned mass assignment.  Each block takes a contiguous chunk of the
+// (cell-sorted) particles; the three deposits of every particle are first
+// combined across lanes of a wavefront that hit the same cell (segmented
+// wave sum), then accumulated in an LDS hash table of the block's cells, and
+// finally flushed with one global atomic add per distinct cell.  Targets that
+// find no free LDS entry within a few probes go straight to global memory.
+//
+// Sources of the five grids (Sec. 2.1): core -> grid 1, grid 2, grid 4;
+// ring -> grid 3, grid 4; outer -> grid 5.  Grids 2+3 and 4+5 are assigned
+// as sums directly (their potentials are only used summed, and the solve is
+// linear).  Round 0 = the finest grid of the class, round 1 = middle (2+3)
+// or global (4+5), round 2 = global (4+5).
+constexpr int kDepChunk = 4096;     // particles per block
+constexpr int kDepTable = 4096;     // LDS hash entries (power of two)
+constexpr int kDepProbes = 8;
+
+template <typename T>
+__device__ __forceinline__ T* slot_ptr(const GridsDev<T>& G, const SysDev& sys, uint32_t key) {
+  const int gs = (int)(key >> 24);
+  const int g = gs / kSlots, slot = gs - g * kSlots;
+  return G.g[g][slot] + (key & 0xFFFFFFu);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_deposit(PartDev<T> p, SysDev sys, const double* __restrict__ centres, GridsDev<T> G) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n || p.lost[i]) return;
-  const int g = p.gal[i];
-  const HierDev& h = sys.h[g];
-  const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
-  Classified c;
-  classify(h, centres + 3 * g, x, y, z, c);
-  const T m = p.m[i];
-  if (h.n_levels == 1) {
-    if (c.cls == SBX_OUTER) add_cell(G.g[g][0], h.lv[0], c.idx[0], m);
-    return;
+    k_deposit(PartDev<T> p, SysDev sys_arg, const double* __restrict__ centres, GridsDev<T> G_arg) {
+  __shared__ uint32_t tkey[kDepTable];
+  __shared__ T tval[kDepTable];
+  // per-galaxy data staged in LDS: lanes index it by their own galaxy
+  __shared__ SysDev sys;
+  __shared__ GridsDev<T> G;
+  __shared__ double cen[3 * kMaxGal];
+  if (threadIdx.x == 0) {
+    sys = sys_arg;
+    G = G_arg;
   }
-  switch (c.cls) {
-    case SBX_CORE:
-      add_cell(G.g[g][0], h.lv[0], c.idx[0], m);   // grid 1
-      add_cell(G.g[g][2], h.lv[1], c.idx[1], m);   // grid 2 (in 2+3)
-      add_cell(G.g[g][4], h.lv[2], c.idx[2], m);   // grid 4 (in 4+5)
-      break;
-    case SBX_RING:
-      add_cell(G.g[g][1], h.lv[1], c.idx[1], m);   // grid 3
-      add_cell(G.g[g][2], h.lv[1], c.idx[1], m);   // grid 3 (in 2+3)
-      add_cell(G.g[g][4], h.lv[2], c.idx[2], m);   // grid 4 (in 4+5)
-      break;
-    case SBX_OUTER:
-      add_cell(G.g[g][3], h.lv[2], c.idx[2], m);   // grid 5
-      add_cell(G.g[g][4], h.lv[2], c.idx[2], m);   // grid 5 (in 4+5)
-      break;
-    default:
-      break;
+  if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = threadIdx.x < 3 * sys_arg.ngal ? centres[threadIdx.x] : 0.0;
+  for (int k = threadIdx.x; k < kDepTable; k += 256) {
+    tkey[k] = kNoKey;
+    tval[k] = (T)0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kDepChunk;
+  for (int j = 0; j < kDepChunk / 256; ++j) {
+    const int64_t i = base + j * 256 + threadIdx.x;
+    uint32_t k0 = kNoKey, k1 = kNoKey, k2 = kNoKey;
+    T m = (T)0;
+    if (i < p.n && !p.lost[i]) {
+      const int g = p.gal[i];
+      const HierDev& h = sys.h[g];
+      const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+      Classified c;
+      classify(h, cen + 3 * g, x, y, z, c);
+      m = p.m[i];
+      if (h.n_levels == 1) {
+        if (c.cls == SBX_OUTER) k0 = dep_key(g, 0, h.lv[0], c.idx[0]);
+      } else if (c.cls == SBX_CORE) {
+        k0 = dep_key(g, 0, h.lv[0], c.idx[0]);   // grid 1
+        k1 = dep_key(g, 2, h.lv[1], c.idx[1]);   // grid 2 (in 2+3)
+        k2 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 4 (in 4+5)
+      } else if (c.cls == SBX_RING) {
+        k0 = dep_key(g, 1, h.lv[1], c.idx[1]);   // grid 3
+        k1 = dep_key(g, 2, h.lv[1], c.idx[1]);   // grid 3 (in 2+3)
+        k2 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 4 (in 4+5)
+      } else if (c.cls == SBX_OUTER) {
+        k0 = dep_key(g, 3, h.lv[2], c.idx[2]);   // grid 5
+        k1 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 5 (in 4+5)
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const uint32_t key = r == 0 ? k0 : (r == 1 ? k1 : k2);
+      bool tail;
+      const T s = wave_run_sum(key, m, tail);
+      if (tail && key != kNoKey) {
+        uint32_t hslot = (key * 2654435761u) >> (32 - 12);
+        bool done = false;
+        for (int q = 0; q < kDepProbes && !done; ++q) {
+          const uint32_t old = atomicCAS(tkey + hslot, kNoKey, key);
+          if (old == kNoKey || old == key) {
+            atomicAdd(tval + hslot, s);
+            done = true;
+          } else {
+            hslot = (hslot + 1) & (kDepTable - 1);
+          }
+        }
+        if (!done) unsafeAtomicAdd(slot_ptr(G, sys, key), s);
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kDepTable; k += 256) {
+    const uint32_t key = tkey[k];
+    if (key != kNoKey) unsafeAtomicAdd(slot_ptr(G, sys, key), tval[k]);
   }
 }
 
@@ -218,7 +321,7 @@ __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, 
   const T Dx = (T)(dx - ((double)id[0] - L.half) * L.l);
   const T Dy = (T)(dy - ((double)id[1] - L.half) * L.l);
   const T Dz = (T)(dz - ((double)id[2] - L.half) * L.lz);
-  const T i2l = (T)(0.5 / L.l), i2lz = (T)(0.5 / L.lz);
+  const T i2l = (T)L.c_2l, i2lz = (T)L.c_2lz;
   const T p0 = P[0];
   const T xp = P[1], xm = P[-1], yp = P[sy], ym = P[-sy], zp = P[sz], zm = P[-sz];
   const T gx = (xp - xm) * i2l, gy = (yp - ym) * i2l, gz = (zp - zm) * i2lz;
@@ -229,8 +332,8 @@ __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, 
     if (want_phi) phi += p0 + gx * Dx + gy * Dy + gz * Dz;
     return;
   }
-  const T il2 = (T)(1.0 / (L.l * L.l)), ilz2 = (T)(1.0 / (L.lz * L.lz));
-  const T i4xy = (T)(1.0 / (4.0 * L.l * L.l)), i4xz = (T)(1.0 / (4.0 * L.l * L.lz));
+  const T il2 = (T)L.c_l2, ilz2 = (T)L.c_lz2;
+  const T i4xy = (T)L.c_4ll, i4xz = (T)L.c_4llz;
   const T hxx = (xp + xm - (T)2 * p0) * il2;
   const T hyy = (yp + ym - (T)2 * p0) * il2;
   const T hzz = (zp + zm - (T)2 * p0) * ilz2;
@@ -287,11 +390,16 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(256)
     k_force(PartDev<T> p, SysDev sys, const double* __restrict__ centres, GridsDev<T> F, T dt,
             double dtd, double* __restrict__ acc_out, double* __restrict__ pot_out,
-            double* __restrict__ partial) {
+            double* __restrict__ partial, double* __restrict__ com_partial) {
   constexpr bool MOVE = MODE & 1, OUT = MODE & 2, DIAG = MODE & 4;
   double dg[DIAG ? kNDiag : 1];
   if constexpr (DIAG) {
     for (int k = 0; k < kNDiag; ++k) dg[k] = 0.0;
+  }
+  double com[MOVE ? kPreVals : 1];
+  if constexpr (MOVE) {
+#pragma unroll
+    for (int k = 0; k < kPreVals; ++k) com[k] = 0.0;
   }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
@@ -349,10 +457,30 @@ __global__ void __launch_bounds__(256)
       p.x[0][i] = nx;
       p.x[1][i] = ny;
       p.x[2][i] = nz;
-      if (outside_global(sys, (double)nx, (double)ny, (double)nz)) p.lost[i] = 1;
+      const double ex = (double)nx, ey = (double)ny, ez = (double)nz;
+      if (outside_global(sys, ex, ey, ez)) {
+        p.lost[i] = 1;
+      } else {
+        // centre-of-mass sums of the new positions for the next step
+        const int g = p.gal[i];
+        const double m = (double)p.m[i];
+#pragma unroll
+        for (int gg = 0; gg < kMaxGal; ++gg) {
+          if (gg == g && sys.h[gg].centring == SBX_CENTRE_COM) {
+            com[4 * gg + 0] += m;
+            com[4 * gg + 1] += m * ex;
+            com[4 * gg + 2] += m * ey;
+            com[4 * gg + 3] += m * ez;
+          }
+        }
+      }
     }
   }
   if constexpr (DIAG) block_sum_store<kNDiag>(dg, partial + (size_t)blockIdx.x * kNDiag);
+  if constexpr (MOVE) {
+    if constexpr (DIAG) __syncthreads();
+    block_sum_store<kPreVals>(com, com_partial + (size_t)blockIdx.x * kPreVals, 4 * sys.ngal);
+  }
 }
 
 // ------------------------------------------------------------- readouts ---
@@ -405,6 +533,92 @@ __global__ void k_join3(const T* x0, const T* x1, const T* x2, double* __restric
   }
 }
 
+// ------------------------------------------------------------ cell sort ---
+// Key: cell of the particle's finest grid (relative to its own galaxy),
+// bins ordered by galaxy, then class level, then z, y, x.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_sort_key(PartDev<T> p, SysDev sys_arg, const double* __restrict__ centres,
+               uint32_t* __restrict__ key, uint32_t* __restrict__ count, uint32_t lost_bin) {
+  __shared__ SysDev sys;
+  if (threadIdx.x == 0) sys = sys_arg;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t k = kNoKey;  // lanes past the end keep a key of their own
+  if (i < p.n) {
+    k = lost_bin;
+    if (!p.lost[i]) {
+      const int g = p.gal[i];
+      const HierDev& h = sys.h[g];
+      Classified c;
+      classify(h, centres + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
+      if (c.cls != SBX_LOST) {
+        const int lev = h.n_levels == 1 ? 0 : c.cls;
+        const int N = h.lv[0].N;
+        const int* id = lev == 0 ? c.idx[0] : (lev == 1 ? c.idx[1] : c.idx[2]);
+        k = (uint32_t)((((size_t)(g * 3 + lev) * N + id[2]) * N + id[1]) * N + id[0]);
+      }
+    }
+    key[i] = k;
+  }
+  // every lane takes part in the wave sum (no divergent shuffles)
+  bool tail;
+  const uint32_t run = wave_run_sum<uint32_t>(k, 1u, tail);
+  if (tail && k != kNoKey) atomicAdd(count + k, run);
+}
+
+// Slots are reserved per run of equal keys in a wavefront: the run's last
+// lane reserves the whole run with one atomic add, the others take the
+// following slots in lane order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_sort_scatter(PartDev<T> s, PartDev<T> d, const uint32_t* __restrict__ key,
+                   uint32_t* __restrict__ offs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint32_t k = i < s.n ? key[i] : kNoKey;
+  bool tail;
+  const uint32_t rank1 = wave_run_sum<uint32_t>(k, 1u, tail);  // 1-based rank in the run
+  uint32_t start = 0;
+  if (tail && k != kNoKey) start = atomicAdd(offs + k, rank1);
+  // nearest tail at or after this lane: suffix minimum of tail lane ids
+  int tl = tail ? lane : 64;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t2 = __shfl_down(tl, o, 64);
+    if (lane + o < 64) tl = min(tl, t2);
+  }
+  const uint32_t run_start = __shfl(start, tl & 63, 64);
+  if (i >= s.n) return;
+  const uint32_t j = run_start + rank1 - 1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d.x[k][j] = s.x[k][i];
+    d.v[k][j] = s.v[k][i];
+  }
+  d.m[j] = s.m[i];
+  d.comp[j] = s.comp[i];
+  d.gal[j] = s.gal[i];
+  d.lost[j] = s.lost[i];
+  d.id[j] = s.id[i];
+}
+
+__global__ void k_iota(int32_t* id, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    id[i] = (int32_t)i;
+}
+
+template <typename A>
+__global__ void k_unpermute(const A* __restrict__ src, const int32_t* __restrict__ id,
+                            A* __restrict__ dst, int64_t n, int width) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = id[i];
+    for (int w = 0; w < width; ++w) dst[j * width + w] = src[i * width + w];
+  }
+}
+
 // ------------------------------------------------------------- launchers --
 static inline unsigned blocks_for(int64_t n) {
   int64_t b = (n + 255) / 256;
@@ -418,22 +632,67 @@ sbx_status launch_zero(T* p, size_t n, hipStream_t s) {
   return SBX_OK;
 }
 
-template <typename T>
-sbx_status launch_pre(const PartDev<T>& p, const SysDev& sys, double* partial, double* centres,
-                      hipStream_t s) {
-  hipLaunchKernelGGL((k_pre<T>), dim3(kRedBlocks), dim3(256), 0, s, p, sys, partial);
-  double* sums = partial + (size_t)kRedBlocks * kPreVals;
-  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(64), 0, s, partial, kRedBlocks, kPreVals, sums);
+int force_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > kForceBlocksMax ? kForceBlocksMax : b));
+}
+
+sbx_status launch_centres(const double* partial, int rows, const SysDev& sys, double* sums,
+                          double* centres, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3(kPreVals), dim3(256), 0, s, partial, rows, kPreVals, sums);
   hipLaunchKernelGGL(k_centres, dim3(1), dim3(64), 0, s, sums, sys, centres);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
 
 template <typename T>
+sbx_status launch_pre(const PartDev<T>& p, const SysDev& sys, double* partial, double* centres,
+                      hipStream_t s) {
+  hipLaunchKernelGGL((k_pre<T>), dim3(kRedBlocks), dim3(256), 0, s, p, sys, partial);
+  SBX_HIP(hipGetLastError());
+  return launch_centres(partial, kRedBlocks, sys, partial + (size_t)kRedBlocks * kPreVals, centres, s);
+}
+
+template <typename T>
+sbx_status launch_sort(const PartDev<T>& src, const PartDev<T>& dst, const SysDev& sys,
+                       const double* centres, uint32_t* key, uint32_t* count, size_t bins,
+                       uint32_t* tmp, hipStream_t s) {
+  if (src.n == 0) return SBX_OK;
+  SBX_TRY(launch_zero<uint32_t>(count, bins + 1, s));
+  hipLaunchKernelGGL((k_sort_key<T>), dim3(blocks_for(src.n)), dim3(256), 0, s, src, sys, centres, key,
+                     count, (uint32_t)bins);
+  SBX_HIP(hipGetLastError());
+  SBX_TRY(exclusive_scan_u32(count, bins + 1, tmp, s));
+  hipLaunchKernelGGL((k_sort_scatter<T>), dim3(blocks_for(src.n)), dim3(256), 0, s, src, dst, key, count);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, dim3(2048), dim3(256), 0, s, id, n);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename A>
+sbx_status launch_unpermute(const A* src, const int32_t* id, A* dst, int64_t n, int width,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((k_unpermute<A>), dim3(2048), dim3(256), 0, s, src, id, dst, n, width);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template sbx_status launch_unpermute<double>(const double*, const int32_t*, double*, int64_t, int, hipStream_t);
+template sbx_status launch_unpermute<int32_t>(const int32_t*, const int32_t*, int32_t*, int64_t, int, hipStream_t);
+template sbx_status launch_unpermute<int8_t>(const int8_t*, const int32_t*, int8_t*, int64_t, int, hipStream_t);
+template sbx_status launch_unpermute<uint8_t>(const uint8_t*, const int32_t*, uint8_t*, int64_t, int, hipStream_t);
+
+template <typename T>
 sbx_status launch_deposit(const PartDev<T>& p, const SysDev& sys, const double* centres,
                           const GridsDev<T>& grids, hipStream_t s) {
   if (p.n == 0) return SBX_OK;
-  hipLaunchKernelGGL((k_deposit<T>), dim3(blocks_for(p.n)), dim3(256), 0, s, p, sys, centres, grids);
+  const unsigned nb = (unsigned)((p.n + kDepChunk - 1) / kDepChunk);
+  hipLaunchKernelGGL((k_deposit<T>), dim3(nb), dim3(256), 0, s, p, sys, centres, grids);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
@@ -441,14 +700,15 @@ sbx_status launch_deposit(const PartDev<T>& p, const SysDev& sys, const double* 
 template <typename T>
 sbx_status launch_force(const PartDev<T>& p, const SysDev& sys, const double* centres,
                         const GridsDev<T>& F, double dt, int mode, double* acc, double* pot,
-                        double* partial, double* diag_out, hipStream_t s) {
+                        double* partial, double* diag_out, double* com_partial, hipStream_t s) {
   const T dtt = (T)dt;
   const dim3 b(256);
-  const dim3 g = (mode & 4) ? dim3(kRedBlocks) : dim3(blocks_for(p.n));
+  const int nb = force_blocks(p.n);
+  const dim3 g(nb);
 #define SBX_FORCE(M)                                                                          \
   case M:                                                                                     \
     hipLaunchKernelGGL((k_force<T, M>), g, b, 0, s, p, sys, centres, F, dtt, dt, acc, pot,   \
-                       partial);                                                              \
+                       partial, com_partial);                                                 \
     break;
   switch (mode) {
     SBX_FORCE(1)
@@ -462,8 +722,7 @@ sbx_status launch_force(const PartDev<T>& p, const SysDev& sys, const double* ce
   }
 #undef SBX_FORCE
   if (mode & 4)
-    hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(64), 0, s, partial, kRedBlocks, kNDiag,
-                       diag_out);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(kNDiag), dim3(256), 0, s, partial, nb, kNDiag, diag_out);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
@@ -515,7 +774,10 @@ sbx_status launch_join3(const T* x0, const T* x1, const T* x2, double* dst, int6
                                         const GridsDev<T>&, hipStream_t);                        \
   template sbx_status launch_force<T>(const PartDev<T>&, const SysDev&, const double*,           \
                                       const GridsDev<T>&, double, int, double*, double*,         \
-                                      double*, double*, hipStream_t);                            \
+                                      double*, double*, double*, hipStream_t);                   \
+  template sbx_status launch_sort<T>(const PartDev<T>&, const PartDev<T>&, const SysDev&,        \
+                                     const double*, uint32_t*, uint32_t*, size_t, uint32_t*,     \
+                                     hipStream_t);                                               \
   template sbx_status launch_indices<T>(const PartDev<T>&, const SysDev&, const double*, int,    \
                                         int, int32_t*, int8_t*, hipStream_t);                    \
   template sbx_status launch_convert_in<T>(const double*, T*, size_t, hipStream_t);              \
@@ -524,6 +786,7 @@ sbx_status launch_join3(const T* x0, const T* x1, const T* x2, double* dst, int6
   template sbx_status launch_join3<T>(const T*, const T*, const T*, double*, int64_t, hipStream_t);
 SBX_INST(float)
 SBX_INST(double)
+template sbx_status launch_zero<uint32_t>(uint32_t*, size_t, hipStream_t);
 #undef SBX_INST
 
 }  // namespace sbx

@@ -89,6 +89,7 @@ def _load():
         "sbx_diagnostics": (S, [P, D, C.POINTER(sbx_diag)]),
         "sbx_diag_log": (S, [P, I32, C.POINTER(sbx_diag), C.POINTER(I32)]),
         "sbx_sync": (S, [P]),
+        "sbx_set_sort_interval": (S, [P, I32]),
         "sbx_count_live": (S, [P, C.POINTER(I64)]),
         "sbx_profile_begin": (S, [P, I32]),
         "sbx_profile_end": (S, [P, I32, P, P]),
@@ -208,6 +209,9 @@ class Context:
 
     def sbx_sync(self):
         _check(_lib.sbx_sync(self._h))
+
+    def sbx_set_sort_interval(self, every):
+        _check(_lib.sbx_set_sort_interval(self._h, int(every)))
 
     # -- outputs --------------------------------------------------------------
     def sbx_get_particles(self):
