@@ -181,6 +181,8 @@ struct sbx_ctx {
   void* X = nullptr;
   void* C = nullptr;
   int nsolves = 0;
+  SolvePlan<float> plan32;
+  SolvePlan<double> plan64;
   double* centres = nullptr;  // kMaxGal * 3
   double* partial = nullptr;  // kForceBlocksMax * kNDiag + kNDiag
   double* diag_one = nullptr; // kNDiag
@@ -195,6 +197,16 @@ struct sbx_ctx {
   Recorder rec;
 };
 
+// Solve plans of a Poisson object are cached per (rho, phi, batch) so that a
+// loop over the same buffers reuses its device tables.
+struct PoissonPlan {
+  const void* rho;
+  void* phi;
+  int batch;
+  SolvePlan<float> p32;
+  SolvePlan<double> p64;
+};
+
 struct sbx_poisson {
   int N = 0, prec = 0, device = 0;
   sbx_level geo;
@@ -207,11 +219,13 @@ struct sbx_poisson {
   int cap = 0;
   double rel_imag = 0.0;
   int64_t bytes = 0;
+  std::vector<PoissonPlan*> plans;
 };
 
 namespace {
 
 constexpr int kDiagCap = 4096;
+constexpr int kMaxSolves = 40;  // solves per Poisson plan launch
 
 template <typename T>
 PartDev<T> part_of(sbx_ctx* c) {
@@ -312,6 +326,8 @@ void free_particles(sbx_ctx* c) {
 }
 
 void free_grids(sbx_ctx* c) {
+  plan_destroy(c->plan32);
+  plan_destroy(c->plan64);
   free_ptr(c->grid_block);
   free_typed(c->count);
   free_typed(c->scan_tmp);
@@ -364,6 +380,24 @@ sbx_status build_grids_t(sbx_ctx* c) {
     }
   SBX_TRY(dev_alloc(&c->X, x_elems(N) * sizeof(C2<T>) * total));
   SBX_TRY(dev_alloc(&c->C, c_elems(N) * sizeof(C2<T>) * total));
+  // one persistent plan for all solves of a step
+  std::vector<SolveDesc<T>> descs;
+  int s2 = 0;
+  for (int g = 0; g < c->ngal; ++g)
+    for (int k = 0; k < c->nslots[g]; ++k, ++s2) {
+      SolveDesc<T> d;
+      d.rho = (const T*)c->grid[g][k];
+      d.phi = (T*)c->grid[g][k];
+      d.X = (C2<T>*)c->X + x_elems(N) * s2;
+      d.C = (C2<T>*)c->C + c_elems(N) * s2;
+      d.H = nullptr;
+      d.N = N;
+      for (auto& e : c->greens)
+        if (same_level(e.geo, c->hh[g].lv[c->slot_level[g][k]])) d.H = (const T*)e.H;
+      descs.push_back(d);
+    }
+  if constexpr (sizeof(T) == 8) SBX_TRY(plan_create<T>(c->plan64, descs.data(), (int)descs.size(), c->stream));
+  else SBX_TRY(plan_create<T>(c->plan32, descs.data(), (int)descs.size(), c->stream));
   // counting-sort bins: one per cell of every level of every galaxy
   c->bins = (size_t)c->ngal * 3 * N * N * N;
   SBX_TRY(dev_alloc((void**)&c->count, sizeof(uint32_t) * (c->bins + 1)));
@@ -393,18 +427,8 @@ sbx_status field_solve_t(sbx_ctx* c) {
   c->rec.mark(PH_PRE, c->stream);
   SBX_TRY(launch_deposit<T>(p, c->sys, c->centres, grids_of<T>(c), c->stream));
   c->rec.mark(PH_DEPOSIT, c->stream);
-  SolveBatch<T> b;
-  int s = 0;
-  for (int g = 0; g < c->ngal; ++g)
-    for (int k = 0; k < c->nslots[g]; ++k, ++s) {
-      SolveDesc<T>& d = b.d[s];
-      d.rho = (const T*)c->grid[g][k];
-      d.phi = (T*)c->grid[g][k];
-      d.X = (C2<T>*)c->X + x_elems(c->N) * s;
-      d.C = (C2<T>*)c->C + c_elems(c->N) * s;
-      d.H = (const T*)green_for(c, c->hh[g].lv[c->slot_level[g][k]]);
-    }
-  SBX_TRY(solve_batch<T>(c->N, s, b, c->stream, &c->rec));
+  if constexpr (sizeof(T) == 8) SBX_TRY(plan_run<T>(c->plan64, c->stream, &c->rec));
+  else SBX_TRY(plan_run<T>(c->plan32, c->stream, &c->rec));
   c->solved = true;
   c->grids_fields = true;
   return SBX_OK;
@@ -501,14 +525,26 @@ void to_diag(const double* r, sbx_diag* d) {
 }
 
 template <typename T>
+SolvePlan<T>& plan_of(PoissonPlan* q) {
+  if constexpr (sizeof(T) == 8) return q->p64;
+  else return q->p32;
+}
+
+template <typename T>
 sbx_status poisson_solve_t(sbx_poisson* p, int batch, const void* rho, void* phi) {
   const size_t cells = (size_t)p->N * p->N * p->N;
-  if (batch > p->cap) {
+  const int cap = std::min(batch, kMaxSolves);
+  if (cap > p->cap) {
     SBX_HIP(hipStreamSynchronize(p->stream));
+    for (auto* q : p->plans) {
+      plan_destroy(q->p32);
+      plan_destroy(q->p64);
+      delete q;
+    }
+    p->plans.clear();
     free_ptr(p->X);
     free_ptr(p->C);
     p->cap = 0;
-    const int cap = std::min(batch, kMaxBatch);
     SBX_TRY(dev_alloc(&p->X, x_elems(p->N) * sizeof(C2<T>) * cap));
     SBX_TRY(dev_alloc(&p->C, c_elems(p->N) * sizeof(C2<T>) * cap));
     p->cap = cap;
@@ -517,15 +553,48 @@ sbx_status poisson_solve_t(sbx_poisson* p, int batch, const void* rho, void* phi
   }
   for (int b0 = 0; b0 < batch; b0 += p->cap) {
     const int nb = std::min(p->cap, batch - b0);
-    SolveBatch<T> sb;
-    for (int i = 0; i < nb; ++i) {
-      sb.d[i].rho = (const T*)rho + cells * (b0 + i);
-      sb.d[i].phi = (T*)phi + cells * (b0 + i);
-      sb.d[i].X = (C2<T>*)p->X + x_elems(p->N) * i;
-      sb.d[i].C = (C2<T>*)p->C + c_elems(p->N) * i;
-      sb.d[i].H = (const T*)p->H;
+    const void* r = (const T*)rho + cells * b0;
+    void* f = (T*)phi + cells * b0;
+    PoissonPlan* hit = nullptr;
+    for (auto* q : p->plans)
+      if (q->rho == r && q->phi == f && q->batch == nb) hit = q;
+    if (!hit) {
+      auto descs = [&](const T* rr, T* ff) {
+        std::vector<SolveDesc<T>> d(nb);
+        for (int i = 0; i < nb; ++i) {
+          d[i].rho = rr + cells * i;
+          d[i].phi = ff + cells * i;
+          d[i].X = (C2<T>*)p->X + x_elems(p->N) * i;
+          d[i].C = (C2<T>*)p->C + c_elems(p->N) * i;
+          d[i].H = (const T*)p->H;
+          d[i].N = p->N;
+        }
+        return d;
+      };
+      if (!tuning_cached((int)sizeof(T), std::vector<int>(nb, p->N))) {
+        // tune on scratch grids, never on the caller's buffers
+        T* scratch = nullptr;
+        SBX_TRY(dev_alloc((void**)&scratch, sizeof(T) * cells * nb));
+        SolvePlan<T> tmp;
+        auto d = descs(scratch, scratch);
+        const sbx_status rc = plan_create<T>(tmp, d.data(), nb, p->stream);
+        plan_destroy(tmp);
+        (void)hipFree(scratch);
+        SBX_TRY(rc);
+      }
+      if (p->plans.size() >= 8) {
+        SBX_HIP(hipStreamSynchronize(p->stream));
+        plan_destroy(p->plans.front()->p32);
+        plan_destroy(p->plans.front()->p64);
+        delete p->plans.front();
+        p->plans.erase(p->plans.begin());
+      }
+      hit = new PoissonPlan{r, f, nb, {}, {}};
+      p->plans.push_back(hit);
+      auto d = descs((const T*)r, (T*)f);
+      SBX_TRY(plan_create<T>(plan_of<T>(hit), d.data(), nb, p->stream));
     }
-    SBX_TRY(solve_batch<T>(p->N, nb, sb, p->stream));
+    SBX_TRY(plan_run<T>(plan_of<T>(hit), p->stream));
   }
   return SBX_OK;
 }
@@ -1088,6 +1157,12 @@ void sbx_poisson_destroy(sbx_poisson* p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
   if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (auto* q : p->plans) {
+    plan_destroy(q->p32);
+    plan_destroy(q->p64);
+    delete q;
+  }
+  p->plans.clear();
   free_ptr(p->H);
   free_ptr(p->X);
   free_ptr(p->C);

@@ -10,7 +10,14 @@
 //   inv_x : X[kx][z][y]    (kx <= N)    -> phi[z][y][x] (complex-to-real, keep x < N)
 // Zero halves of the padded inputs are never read, unused halves of the
 // outputs never written.  Hhat (real, even per axis) is stored on (N+1)^3.
+//
+// Every pass is one persistent launch over all solves of a plan, whatever
+// their grid sizes: blocks pull (solve, tile) work items from a counter and
+// dispatch on the line length.  Block size and grid size of each pass are
+// chosen by timing candidates the first time a mix of sizes is planned.
 #pragma once
+
+#include <vector>
 
 #include "common.h"
 
@@ -23,30 +30,66 @@ struct SolveDesc {
   C2<T>* X;       // (N+1) * N * N
   C2<T>* C;       // (N+1) * 2N * N
   const T* H;     // (N+1)^3 transformed Green's function, scaled by G/(2N)^3
+  int N;
 };
 
-// Up to kMaxBatch solves of one grid size per launch; passed by value as a
-// kernel argument (block-uniform index, read through scalar loads).
-constexpr int kMaxBatch = 40;
-template <typename T>
-struct SolveBatch {
-  SolveDesc<T> d[kMaxBatch];
+constexpr int kPasses = 5;
+
+// Launch shape of one pass.
+struct PassShape {
+  int nt;     // threads per block
+  int grid;   // persistent blocks (0: one block per tile)
 };
 
-// Per-precision, per-length twiddle tables (device), built once per device.
+constexpr int kMaxGroups = 6;  // distinct grid sizes 8..256
+
+// Solves of one grid size inside a plan.
+struct SolveGroup {
+  int first = 0, count = 0, N = 0;
+  const void* tw = nullptr;          // twiddle table of line length 2N
+  PassShape shape[kPasses] = {};
+};
+
 template <typename T>
-const C2<T>* twiddles(int L, hipStream_t s);
+struct SolvePlan {
+  int nsolves = 0;
+  std::vector<SolveDesc<T>> host;    // grouped by grid size
+  SolveDesc<T>* d_solves = nullptr;
+  int* d_counter = nullptr;          // kPasses * kMaxGroups work counters
+  int ngroups = 0;
+  SolveGroup groups[kMaxGroups];
+};
 
 // Workspace sizes in elements of C2<T>.
 inline size_t x_elems(int N) { return (size_t)(N + 1) * N * N; }
 inline size_t c_elems(int N) { return (size_t)(N + 1) * 2 * N * N; }
 inline size_t h_elems(int N) { return (size_t)(N + 1) * (N + 1) * (N + 1); }
 
-// Launch the five passes for the first `nsolves` (<= kMaxBatch) descriptors
-// of one grid size N.  Returns SBX_OK or an error status.
+// Prepare a plan for the given solves (device tables, twiddles, launch
+// shapes from the tuning cache; tunes on the plan's own buffers when the mix
+// of grid sizes is new -- rho/phi/X/C are then overwritten with zeros).
 template <typename T>
-sbx_status solve_batch(int N, int nsolves, const SolveBatch<T>& b, hipStream_t s,
-                       Recorder* rec = nullptr);
+sbx_status plan_create(SolvePlan<T>& plan, const SolveDesc<T>* descs, int n, hipStream_t s);
+
+// Run all solves of the plan (zeroes the work counters, five launches).
+template <typename T>
+sbx_status plan_run(const SolvePlan<T>& plan, hipStream_t s, Recorder* rec = nullptr);
+
+// One pass (0..4) of one size group, for callers that schedule the groups
+// themselves (e.g. as concurrent branches of a graph).  The work counters are
+// zeroed by plan_run; callers of plan_run_pass zero p.d_counter themselves.
+template <typename T>
+sbx_status plan_run_pass(const SolvePlan<T>& plan, int pass, int group, hipStream_t s);
+
+template <typename T>
+void plan_destroy(SolvePlan<T>& plan);
+
+// Whether launch shapes for this precision and mix of grid sizes are cached.
+bool tuning_cached(int esz, std::vector<int> mix);
+
+// Tuned launch shapes of every mix planned so far, as text (one line per
+// pass and mix), for reports.
+std::string tuning_report();
 
 // Build the transformed Green's function for geometry (N, l, lz) into H
 // ((N+1)^3 elements of T): FP64 H of Eq. 2 mirrored by Eq. 5, FP64 3D FFT,

@@ -7,6 +7,8 @@
 // table.  Global loads and stores are arranged so that consecutive threads
 // touch consecutive addresses: along the line when the line is contiguous,
 // across the W lines of a tile when it is strided.
+#include <algorithm>
+#include <array>
 #include <cstring>
 #include <mutex>
 
@@ -16,35 +18,26 @@ namespace sbx {
 
 __device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
 
-template <typename T, int L>
-struct Cfg {
-  static constexpr int N = L / 2;
-  static constexpr int TL = L / 16;                  // threads per line
-  static constexpr int P = L + L / 16 + 1;           // LDS pitch of one line
-  static constexpr int WCAP = (40960 / (P * (int)sizeof(C2<T>))) >= 16 ? 16
-                              : (40960 / (P * (int)sizeof(C2<T>))) >= 8 ? 8 : 4;
-  static constexpr int WMAX = sizeof(T) == 4 ? 16 : 8;
-  static constexpr int W0 = WCAP < WMAX ? WCAP : WMAX;
-  static constexpr int W = N < W0 ? N : W0;          // lines per block
-  static constexpr int NT = W * TL;                  // threads per block
-};
-
 // ------------------------------------------------------------- Stockham ---
 // One pass of radix R with stride NS over a line in LDS (in place).
+// Threads without a line (act = false) only take part in the barriers.
 template <typename T, int L, int R, int NS, bool INV, bool PIN, bool POUT>
-__device__ __forceinline__ void st_pass(C2<T>* line, int t, const C2<T>* __restrict__ tw) {
+__device__ __forceinline__ void st_pass(C2<T>* line, int t, const C2<T>* __restrict__ tw, bool act) {
   constexpr int TL = L / 16, NB = L / R, BPT = NB / TL;
   C2<T> v[BPT][R];
+  if (act) {
 #pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int j = t + b * TL;
+    for (int b = 0; b < BPT; ++b) {
+      const int j = t + b * TL;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (PIN && r >= R / 2) v[b][r] = C2<T>{(T)0, (T)0};
-      else v[b][r] = line[pad(j + r * NB)];
+      for (int r = 0; r < R; ++r) {
+        if (PIN && r >= R / 2) v[b][r] = C2<T>{(T)0, (T)0};
+        else v[b][r] = line[pad(j + r * NB)];
+      }
     }
   }
   __syncthreads();
+  if (act) {
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     const int j = t + b * TL;
@@ -65,32 +58,34 @@ __device__ __forceinline__ void st_pass(C2<T>* line, int t, const C2<T>* __restr
       line[pad(base + r * NS)] = v[b][r];
     }
   }
+  }
   __syncthreads();
 }
 
 // Full length-L transform of one line by the TL threads t = 0..TL-1.
 // PIN: input is zero in [L/2, L); POUT: only [0, L/2) of the output is kept.
 template <typename T, int L, bool INV, bool PIN, bool POUT>
-__device__ __forceinline__ void fft_line(C2<T>* line, int t, const C2<T>* __restrict__ tw) {
+__device__ __forceinline__ void fft_line(C2<T>* line, int t, const C2<T>* __restrict__ tw,
+                                         bool act) {
   if constexpr (L == 16) {
-    st_pass<T, L, 16, 1, INV, PIN, POUT>(line, t, tw);
+    st_pass<T, L, 16, 1, INV, PIN, POUT>(line, t, tw, act);
   } else if constexpr (L == 32) {
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw);
-    st_pass<T, L, 2, 16, INV, false, POUT>(line, t, tw);
+    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
+    st_pass<T, L, 2, 16, INV, false, POUT>(line, t, tw, act);
   } else if constexpr (L == 64) {
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw);
-    st_pass<T, L, 4, 16, INV, false, POUT>(line, t, tw);
+    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
+    st_pass<T, L, 4, 16, INV, false, POUT>(line, t, tw, act);
   } else if constexpr (L == 128) {
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw);
-    st_pass<T, L, 8, 16, INV, false, POUT>(line, t, tw);
+    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
+    st_pass<T, L, 8, 16, INV, false, POUT>(line, t, tw, act);
   } else if constexpr (L == 256) {
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw);
-    st_pass<T, L, 16, 16, INV, false, POUT>(line, t, tw);
+    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
+    st_pass<T, L, 16, 16, INV, false, POUT>(line, t, tw, act);
   } else {
     static_assert(L == 512, "L in 16..512");
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw);
-    st_pass<T, L, 16, 16, INV, false, false>(line, t, tw);
-    st_pass<T, L, 2, 256, INV, false, POUT>(line, t, tw + 240);
+    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
+    st_pass<T, L, 16, 16, INV, false, false>(line, t, tw, act);
+    st_pass<T, L, 2, 256, INV, false, POUT>(line, t, tw + 240, act);
   }
 }
 
@@ -156,72 +151,99 @@ const C2<T>* twiddles(int L, hipStream_t st) {
 template const C2<float>* twiddles<float>(int, hipStream_t);
 template const C2<double>* twiddles<double>(int, hipStream_t);
 
+// ------------------------------------------------------------ tile shape ---
+// A block of NT threads transforms W lines of length L; TL = L/16 threads
+// per line.  W is capped by the tile dimension (N) and by 64 KB of LDS;
+// threads beyond W * TL only help with loads, stores and barriers.
+template <typename T, int L, int NT>
+struct TC {
+  static constexpr int N = L / 2;
+  static constexpr int TL = L / 16;
+  static constexpr int P = L + L / 16 + 1;  // LDS pitch of one line
+  static constexpr int W0 = NT / TL < N ? NT / TL : N;
+  static constexpr int WLDS = 65536 / (P * (int)sizeof(C2<T>));
+  static constexpr int W1 = W0 <= WLDS ? W0 : (WLDS >= 16 ? 16 : (WLDS >= 8 ? 8 : (WLDS >= 4 ? 4 : 2)));
+  static constexpr int W = W1 < 1 ? 1 : W1;
+  static constexpr int LDS = W * P;         // elements of C2<T>
+};
+
+// tiles of each pass for one solve of line length L
+template <typename T, int L, int NT>
+__host__ __device__ constexpr int tiles_of(int pass) {
+  constexpr int N = L / 2, W = TC<T, L, NT>::W;
+  return pass == 0 ? N * (N / W)
+       : pass == 1 ? (N + 1) * (N / W)
+       : pass == 2 ? (N + 1) * (L / W)
+       : pass == 3 ? (N + 1) * (N / W)
+                   : N * (N / W);
+}
+
 // ------------------------------------------------------------ the passes ---
 // fwd_x: tile = W consecutive y at one z; real input, x < N.
-template <typename T, int L>
-__global__ void __launch_bounds__((Cfg<T, L>::NT))
-    k_fwd_x(const SolveBatch<T> desc, const C2<T>* __restrict__ tw) {
-  using K = Cfg<T, L>;
-  constexpr int N = K::N, W = K::W, P = K::P, NT = K::NT, TL = K::TL;
-  __shared__ C2<T> s[W * P];
-  const SolveDesc<T>& d = desc.d[blockIdx.y];
-  const int z = blockIdx.x / (N / W), y0 = (blockIdx.x % (N / W)) * W;
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T>* s,
+                                           const C2<T>* __restrict__ tw) {
+  using K = TC<T, L, NT>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
+  const int tid = threadIdx.x;
+  const int z = tile / (N / W), y0 = (tile % (N / W)) * W;
   const T* __restrict__ src = d.rho + ((size_t)z * N + y0) * N;
-  for (int i = threadIdx.x; i < W * N; i += NT) {
+  for (int i = tid; i < W * N; i += NT) {
     const int w = i / N, e = i - w * N;
     s[w * P + pad(e)] = C2<T>{src[i], (T)0};
   }
   __syncthreads();
-  fft_line<T, L, false, true, false>(s + (threadIdx.x / TL) * P, threadIdx.x % TL, tw);
+  const bool act = tid < W * TL;
+  fft_line<T, L, false, true, false>(s + (act ? tid / TL : 0) * P, tid % TL, tw, act);
   C2<T>* __restrict__ dst = d.X + (size_t)z * N + y0;
-  for (int i = threadIdx.x; i < W * (N + 1); i += NT) {
+  for (int i = tid; i < W * (N + 1); i += NT) {
     const int e = i / W, w = i - e * W;
     dst[(size_t)e * N * N + w] = s[w * P + pad(e)];
   }
 }
 
 // fwd_y: tile = W consecutive z at one kx; input y < N contiguous.
-template <typename T, int L>
-__global__ void __launch_bounds__((Cfg<T, L>::NT))
-    k_fwd_y(const SolveBatch<T> desc, const C2<T>* __restrict__ tw) {
-  using K = Cfg<T, L>;
-  constexpr int N = K::N, W = K::W, P = K::P, NT = K::NT, TL = K::TL;
-  __shared__ C2<T> s[W * P];
-  const SolveDesc<T>& d = desc.d[blockIdx.y];
-  const int kx = blockIdx.x / (N / W), z0 = (blockIdx.x % (N / W)) * W;
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T>* s,
+                                           const C2<T>* __restrict__ tw) {
+  using K = TC<T, L, NT>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
+  const int tid = threadIdx.x;
+  const int kx = tile / (N / W), z0 = (tile % (N / W)) * W;
   const C2<T>* __restrict__ src = d.X + ((size_t)kx * N + z0) * N;
-  for (int i = threadIdx.x; i < W * N; i += NT) {
+  for (int i = tid; i < W * N; i += NT) {
     const int w = i / N, e = i - w * N;
     s[w * P + pad(e)] = src[i];
   }
   __syncthreads();
-  fft_line<T, L, false, true, false>(s + (threadIdx.x / TL) * P, threadIdx.x % TL, tw);
+  const bool act = tid < W * TL;
+  fft_line<T, L, false, true, false>(s + (act ? tid / TL : 0) * P, tid % TL, tw, act);
   C2<T>* __restrict__ dst = d.C + (size_t)kx * L * N + z0;
-  for (int i = threadIdx.x; i < W * L; i += NT) {
+  for (int i = tid; i < W * L; i += NT) {
     const int e = i / W, w = i - e * W;
     dst[(size_t)e * N + w] = s[w * P + pad(e)];
   }
 }
 
 // zpass: tile = W consecutive ky at one kx; forward z, times Hhat, inverse z.
-template <typename T, int L>
-__global__ void __launch_bounds__((Cfg<T, L>::NT))
-    k_zpass(const SolveBatch<T> desc, const C2<T>* __restrict__ tw) {
-  using K = Cfg<T, L>;
-  constexpr int N = K::N, W = K::W, P = K::P, NT = K::NT, TL = K::TL;
-  __shared__ C2<T> s[W * P];
-  const SolveDesc<T>& d = desc.d[blockIdx.y];
-  const int kx = blockIdx.x / (L / W), ky0 = (blockIdx.x % (L / W)) * W;
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T>* s,
+                                           const C2<T>* __restrict__ tw) {
+  using K = TC<T, L, NT>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
+  const int tid = threadIdx.x;
+  const int kx = tile / (L / W), ky0 = (tile % (L / W)) * W;
   C2<T>* __restrict__ base = d.C + ((size_t)kx * L + ky0) * N;
-  for (int i = threadIdx.x; i < W * N; i += NT) {
+  for (int i = tid; i < W * N; i += NT) {
     const int w = i / N, e = i - w * N;
     s[w * P + pad(e)] = base[i];
   }
   __syncthreads();
-  C2<T>* line = s + (threadIdx.x / TL) * P;
-  fft_line<T, L, false, true, false>(line, threadIdx.x % TL, tw);
+  const bool act = tid < W * TL;
+  C2<T>* line = s + (act ? tid / TL : 0) * P;
+  fft_line<T, L, false, true, false>(line, tid % TL, tw, act);
   const T* __restrict__ H = d.H + (size_t)kx * (N + 1) * (N + 1);
-  for (int i = threadIdx.x; i < W * L; i += NT) {
+  for (int i = tid; i < W * L; i += NT) {
     const int w = i / L, e = i - w * L;
     const int ky = ky0 + w;
     const int fy = ky <= N ? ky : L - ky;
@@ -231,31 +253,31 @@ __global__ void __launch_bounds__((Cfg<T, L>::NT))
     c = cscale(c, h);
   }
   __syncthreads();
-  fft_line<T, L, true, false, true>(line, threadIdx.x % TL, tw);
-  for (int i = threadIdx.x; i < W * N; i += NT) {
+  fft_line<T, L, true, false, true>(line, tid % TL, tw, act);
+  for (int i = tid; i < W * N; i += NT) {
     const int w = i / N, e = i - w * N;
     base[i] = s[w * P + pad(e)];
   }
 }
 
 // inv_y: tile = W consecutive z at one kx; ky strided by N; keep y < N.
-template <typename T, int L>
-__global__ void __launch_bounds__((Cfg<T, L>::NT))
-    k_inv_y(const SolveBatch<T> desc, const C2<T>* __restrict__ tw) {
-  using K = Cfg<T, L>;
-  constexpr int N = K::N, W = K::W, P = K::P, NT = K::NT, TL = K::TL;
-  __shared__ C2<T> s[W * P];
-  const SolveDesc<T>& d = desc.d[blockIdx.y];
-  const int kx = blockIdx.x / (N / W), z0 = (blockIdx.x % (N / W)) * W;
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T>* s,
+                                           const C2<T>* __restrict__ tw) {
+  using K = TC<T, L, NT>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
+  const int tid = threadIdx.x;
+  const int kx = tile / (N / W), z0 = (tile % (N / W)) * W;
   const C2<T>* __restrict__ src = d.C + (size_t)kx * L * N + z0;
-  for (int i = threadIdx.x; i < W * L; i += NT) {
+  for (int i = tid; i < W * L; i += NT) {
     const int e = i / W, w = i - e * W;
     s[w * P + pad(e)] = src[(size_t)e * N + w];
   }
   __syncthreads();
-  fft_line<T, L, true, false, true>(s + (threadIdx.x / TL) * P, threadIdx.x % TL, tw);
+  const bool act = tid < W * TL;
+  fft_line<T, L, true, false, true>(s + (act ? tid / TL : 0) * P, tid % TL, tw, act);
   C2<T>* __restrict__ dst = d.X + ((size_t)kx * N + z0) * N;
-  for (int i = threadIdx.x; i < W * N; i += NT) {
+  for (int i = tid; i < W * N; i += NT) {
     const int w = i / N, e = i - w * N;
     dst[i] = s[w * P + pad(e)];
   }
@@ -263,78 +285,326 @@ __global__ void __launch_bounds__((Cfg<T, L>::NT))
 
 // inv_x: tile = W consecutive y at one z; kx <= N strided by N*N, the rest
 // of the line by Hermitian symmetry; real output x < N.
-template <typename T, int L>
-__global__ void __launch_bounds__((Cfg<T, L>::NT))
-    k_inv_x(const SolveBatch<T> desc, const C2<T>* __restrict__ tw) {
-  using K = Cfg<T, L>;
-  constexpr int N = K::N, W = K::W, P = K::P, NT = K::NT, TL = K::TL;
-  __shared__ C2<T> s[W * P];
-  const SolveDesc<T>& d = desc.d[blockIdx.y];
-  const int z = blockIdx.x / (N / W), y0 = (blockIdx.x % (N / W)) * W;
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T>* s,
+                                           const C2<T>* __restrict__ tw) {
+  using K = TC<T, L, NT>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
+  const int tid = threadIdx.x;
+  const int z = tile / (N / W), y0 = (tile % (N / W)) * W;
   const C2<T>* __restrict__ src = d.X + (size_t)z * N + y0;
-  for (int i = threadIdx.x; i < W * (N + 1); i += NT) {
+  for (int i = tid; i < W * (N + 1); i += NT) {
     const int e = i / W, w = i - e * W;
     const C2<T> v = src[(size_t)e * N * N + w];
     s[w * P + pad(e)] = v;
     if (e >= 1 && e < N) s[w * P + pad(L - e)] = conjc(v);
   }
   __syncthreads();
-  fft_line<T, L, true, false, true>(s + (threadIdx.x / TL) * P, threadIdx.x % TL, tw);
+  const bool act = tid < W * TL;
+  fft_line<T, L, true, false, true>(s + (act ? tid / TL : 0) * P, tid % TL, tw, act);
   T* __restrict__ dst = d.phi + ((size_t)z * N + y0) * N;
-  for (int i = threadIdx.x; i < W * N; i += NT) {
+  for (int i = tid; i < W * N; i += NT) {
     const int w = i / N, e = i - w * N;
     dst[i] = s[w * P + pad(e)].re;
   }
 }
 
-template <typename T, int L>
-static sbx_status launch_solve(int nsolves, const SolveBatch<T>& desc, hipStream_t st,
-                               Recorder* rec) {
-  using K = Cfg<T, L>;
-  constexpr int N = K::N, W = K::W;
-  const C2<T>* tw = twiddles<T>(L, st);
-  if (!tw) {
-    set_error("twiddle table allocation failed");
+template <typename T, int L, int NT, int PASS>
+__device__ __forceinline__ void run_tile(const SolveDesc<T>& d, int tile, C2<T>* s,
+                                         const C2<T>* __restrict__ tw) {
+  if constexpr (PASS == 0) tile_fwd_x<T, L, NT>(d, tile, s, tw);
+  else if constexpr (PASS == 1) tile_fwd_y<T, L, NT>(d, tile, s, tw);
+  else if constexpr (PASS == 2) tile_zpass<T, L, NT>(d, tile, s, tw);
+  else if constexpr (PASS == 3) tile_inv_y<T, L, NT>(d, tile, s, tw);
+  else tile_inv_x<T, L, NT>(d, tile, s, tw);
+}
+
+// Persistent pass over the solves of one grid size: work items are
+// (solve, tile) pairs; the first item of a block is its index, later ones
+// come from the counter until all are done.  With one block per item the
+// counter is never touched.
+template <typename T, int PASS, int NT, int L>
+__global__ void __launch_bounds__(NT)
+    k_pass(const SolveDesc<T>* __restrict__ solves, int tiles_per_solve, int total,
+           int* __restrict__ counter, const C2<T>* __restrict__ tw) {
+  __shared__ C2<T> s[TC<T, L, NT>::LDS];
+  __shared__ int item_sh;
+  int next = blockIdx.x;
+  for (;;) {
+    const int item = next;
+    if (item >= total) break;
+    const bool more = (int)gridDim.x < total;
+    if (more && threadIdx.x == 0) item_sh = (int)gridDim.x + atomicAdd(counter, 1);
+    const int sidx = item / tiles_per_solve;
+    run_tile<T, L, NT, PASS>(solves[sidx], item - sidx * tiles_per_solve, s, tw);
+    if (!more) break;
+    __syncthreads();  // LDS free for the next tile; item_sh written
+    next = __builtin_amdgcn_readfirstlane(item_sh);
+    __syncthreads();  // item_sh read by all before thread 0 rewrites it
+  }
+}
+
+template <typename T, int NT>
+static int tiles_for(int N, int pass) {
+  switch (N) {
+    case 8: return tiles_of<T, 16, NT>(pass);
+    case 16: return tiles_of<T, 32, NT>(pass);
+    case 32: return tiles_of<T, 64, NT>(pass);
+    case 64: return tiles_of<T, 128, NT>(pass);
+    case 128: return tiles_of<T, 256, NT>(pass);
+    default: return tiles_of<T, 512, NT>(pass);
+  }
+}
+
+template <typename T>
+static int tiles_nt(int nt, int N, int pass) {
+  return nt == 128 ? tiles_for<T, 128>(N, pass)
+       : nt == 256 ? tiles_for<T, 256>(N, pass)
+                   : tiles_for<T, 512>(N, pass);
+}
+
+template <typename T, int PASS, int NT>
+static void launch_nt(const SolveDesc<T>* solves, int N, int tps, int total, int grid, int* counter,
+                      const C2<T>* tw, hipStream_t st) {
+  const dim3 g(grid), b(NT);
+  switch (N) {
+    case 8: hipLaunchKernelGGL((k_pass<T, PASS, NT, 16>), g, b, 0, st, solves, tps, total, counter, tw); break;
+    case 16: hipLaunchKernelGGL((k_pass<T, PASS, NT, 32>), g, b, 0, st, solves, tps, total, counter, tw); break;
+    case 32: hipLaunchKernelGGL((k_pass<T, PASS, NT, 64>), g, b, 0, st, solves, tps, total, counter, tw); break;
+    case 64: hipLaunchKernelGGL((k_pass<T, PASS, NT, 128>), g, b, 0, st, solves, tps, total, counter, tw); break;
+    case 128: hipLaunchKernelGGL((k_pass<T, PASS, NT, 256>), g, b, 0, st, solves, tps, total, counter, tw); break;
+    default: hipLaunchKernelGGL((k_pass<T, PASS, NT, 512>), g, b, 0, st, solves, tps, total, counter, tw); break;
+  }
+}
+
+template <typename T, int PASS>
+static void launch_pass(const SolveDesc<T>* solves, int N, int nsolves, PassShape sh, int* counter,
+                        const C2<T>* tw, hipStream_t st) {
+  const int tps = tiles_nt<T>(sh.nt, N, PASS);
+  const int total = tps * nsolves;
+  const int grid = std::max(1, std::min(sh.grid <= 0 ? total : sh.grid, total));
+  if (sh.nt == 128) launch_nt<T, PASS, 128>(solves, N, tps, total, grid, counter, tw, st);
+  else if (sh.nt == 256) launch_nt<T, PASS, 256>(solves, N, tps, total, grid, counter, tw, st);
+  else launch_nt<T, PASS, 512>(solves, N, tps, total, grid, counter, tw, st);
+}
+
+template <typename T>
+static void launch_any(int pass, const SolveDesc<T>* solves, int N, int nsolves, PassShape sh,
+                       int* counter, const C2<T>* tw, hipStream_t st) {
+  switch (pass) {
+    case 0: launch_pass<T, 0>(solves, N, nsolves, sh, counter, tw, st); break;
+    case 1: launch_pass<T, 1>(solves, N, nsolves, sh, counter, tw, st); break;
+    case 2: launch_pass<T, 2>(solves, N, nsolves, sh, counter, tw, st); break;
+    case 3: launch_pass<T, 3>(solves, N, nsolves, sh, counter, tw, st); break;
+    default: launch_pass<T, 4>(solves, N, nsolves, sh, counter, tw, st); break;
+  }
+}
+
+__global__ void k_zero_int(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// ---------------------------------------------------------- the autotuner --
+// Candidate shapes per (precision, grid size, solve count, pass): block size
+// 128, 256 or 512 threads (512 only in FP32, where the longest lines still
+// fit 64 KB of LDS) and a persistent grid of 2, 4 or 8 blocks per compute
+// unit, or one block per tile.  Each candidate runs the pass on the plan's
+// own buffers (zeroed first); the fastest of 5 timed repetitions wins.
+// Results are cached for the life of the process.
+struct TuneKey {
+  int esz, N, count;
+  bool operator==(const TuneKey& o) const { return esz == o.esz && N == o.N && count == o.count; }
+};
+
+static std::mutex g_tune_mu;
+static std::vector<std::pair<TuneKey, std::array<PassShape, kPasses>>> g_tune;
+
+static bool tune_lookup(const TuneKey& k, std::array<PassShape, kPasses>& out) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (auto& e : g_tune)
+    if (e.first == k) {
+      out = e.second;
+      return true;
+    }
+  return false;
+}
+
+std::string tuning_report() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  std::string out;
+  static const char* names[kPasses] = {"fwd_x", "fwd_y", "zpass", "inv_y", "inv_x"};
+  for (auto& e : g_tune)
+    for (int p = 0; p < kPasses; ++p)
+      out += std::string(e.first.esz == 8 ? "fp64" : "fp32") + " N=" + std::to_string(e.first.N) +
+             " x" + std::to_string(e.first.count) + " " + names[p] + " nt=" +
+             std::to_string(e.second[p].nt) + " grid=" +
+             (e.second[p].grid <= 0 ? std::string("tiles") : std::to_string(e.second[p].grid)) + "\n";
+  return out;
+}
+
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+  return cus > 0 ? cus : 256;
+}
+
+bool tuning_cached(int esz, std::vector<int> mix) {
+  std::sort(mix.begin(), mix.end());
+  for (size_t i = 0; i < mix.size();) {
+    size_t j = i;
+    while (j < mix.size() && mix[j] == mix[i]) ++j;
+    std::array<PassShape, kPasses> a;
+    if (!tune_lookup(TuneKey{esz, mix[i], (int)(j - i)}, a)) return false;
+    i = j;
+  }
+  return true;
+}
+
+template <typename T>
+static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* host, int N, int count,
+                             int* counter, const C2<T>* tw, hipStream_t st,
+                             std::array<PassShape, kPasses>& out) {
+  const int cus = device_cus();
+  const int nts[3] = {128, 256, 512};
+  const int bpcs[4] = {2, 4, 8, 0};  // 0: one block per tile
+  for (int i = 0; i < count; ++i) {
+    SBX_HIP(hipMemsetAsync((void*)host[i].rho, 0, sizeof(T) * (size_t)N * N * N, st));
+    SBX_HIP(hipMemsetAsync(host[i].X, 0, sizeof(C2<T>) * x_elems(N), st));
+    SBX_HIP(hipMemsetAsync(host[i].C, 0, sizeof(C2<T>) * c_elems(N), st));
+  }
+  hipEvent_t e0, e1;
+  SBX_HIP(hipEventCreate(&e0));
+  SBX_HIP(hipEventCreate(&e1));
+  for (int pass = 0; pass < kPasses; ++pass) {
+    float best = 1e30f;
+    PassShape pick{256, 0};
+    for (int nt : nts) {
+      if (nt == 512 && sizeof(T) == 8) continue;
+      for (int bpc : bpcs) {
+        const PassShape sh{nt, bpc == 0 ? 0 : cus * bpc};
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 7; ++rep) {
+          hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, 1);
+          SBX_HIP(hipEventRecord(e0, st));
+          launch_any<T>(pass, d_solves, N, count, sh, counter, tw, st);
+          SBX_HIP(hipEventRecord(e1, st));
+          SBX_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          SBX_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (rep >= 2) ms_min = std::min(ms_min, ms);
+        }
+        if (ms_min < best) {
+          best = ms_min;
+          pick = sh;
+        }
+      }
+    }
+    out[pass] = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status plan_create(SolvePlan<T>& p, const SolveDesc<T>* descs, int n, hipStream_t st) {
+  plan_destroy(p);
+  if (n <= 0) return SBX_OK;
+  for (int i = 0; i < n; ++i) {
+    const int N = descs[i].N;
+    if (N < 8 || N > 256 || (N & (N - 1))) {
+      set_error("grid size must be a power of two in 8..256");
+      return SBX_EINVAL;
+    }
+  }
+  // solves grouped by grid size (stable), one launch per group and pass
+  p.host.assign(descs, descs + n);
+  std::stable_sort(p.host.begin(), p.host.end(),
+                   [](const SolveDesc<T>& a, const SolveDesc<T>& b) { return a.N < b.N; });
+  p.nsolves = n;
+  if (hipMalloc(&p.d_solves, sizeof(SolveDesc<T>) * n) != hipSuccess ||
+      hipMalloc(&p.d_counter, sizeof(int) * kPasses * kMaxGroups) != hipSuccess) {
+    (void)hipGetLastError();
+    plan_destroy(p);
+    set_error("out of device memory (solve plan)");
     return SBX_ENOMEM;
   }
-  const dim3 b(K::NT);
+  SBX_HIP(hipMemcpy(p.d_solves, p.host.data(), sizeof(SolveDesc<T>) * n, hipMemcpyHostToDevice));
+  p.ngroups = 0;
+  for (int i = 0; i < n;) {
+    int j = i;
+    while (j < n && p.host[j].N == p.host[i].N) ++j;
+    if (p.ngroups == kMaxGroups) {
+      set_error("too many distinct grid sizes in one plan");
+      return SBX_EINVAL;
+    }
+    SolveGroup& g = p.groups[p.ngroups++];
+    g.first = i;
+    g.count = j - i;
+    g.N = p.host[i].N;
+    i = j;
+  }
+  for (int gi = 0; gi < p.ngroups; ++gi) {
+    SolveGroup& g = p.groups[gi];
+    const C2<T>* tw = twiddles<T>(2 * g.N, st);
+    if (!tw) {
+      set_error("twiddle table allocation failed");
+      return SBX_ENOMEM;
+    }
+    g.tw = (const void*)tw;
+    std::array<PassShape, kPasses> a;
+    const TuneKey key{(int)sizeof(T), g.N, g.count};
+    if (!tune_lookup(key, a)) {
+      SBX_TRY(tune_group<T>(p.d_solves + g.first, p.host.data() + g.first, g.N, g.count,
+                            p.d_counter, tw, st, a));
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune.push_back({key, a});
+    }
+    for (int q = 0; q < kPasses; ++q) g.shape[q] = a[q];
+  }
+  SBX_HIP(hipStreamSynchronize(st));
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status plan_run_pass(const SolvePlan<T>& p, int q, int group, hipStream_t st) {
+  const SolveGroup& g = p.groups[group];
+  launch_any<T>(q, p.d_solves + g.first, g.N, g.count, g.shape[q],
+                p.d_counter + q * kMaxGroups + group, (const C2<T>*)g.tw, st);
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status plan_run(const SolvePlan<T>& p, hipStream_t st, Recorder* rec) {
+  if (p.nsolves == 0) return SBX_OK;
   Recorder none;
   Recorder& r = rec ? *rec : none;
-  hipLaunchKernelGGL((k_fwd_x<T, L>), dim3(N * (N / W), nsolves), b, 0, st, desc, tw);
-  r.mark(PH_FWD_X, st);
-  hipLaunchKernelGGL((k_fwd_y<T, L>), dim3((N + 1) * (N / W), nsolves), b, 0, st, desc, tw);
-  r.mark(PH_FWD_Y, st);
-  hipLaunchKernelGGL((k_zpass<T, L>), dim3((N + 1) * (L / W), nsolves), b, 0, st, desc, tw);
-  r.mark(PH_ZPASS, st);
-  hipLaunchKernelGGL((k_inv_y<T, L>), dim3((N + 1) * (N / W), nsolves), b, 0, st, desc, tw);
-  r.mark(PH_INV_Y, st);
-  hipLaunchKernelGGL((k_inv_x<T, L>), dim3(N * (N / W), nsolves), b, 0, st, desc, tw);
-  r.mark(PH_INV_X, st);
+  static const int marks[kPasses] = {PH_FWD_X, PH_FWD_Y, PH_ZPASS, PH_INV_Y, PH_INV_X};
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, p.d_counter, kPasses * kMaxGroups);
+  for (int q = 0; q < kPasses; ++q) {
+    for (int gi = 0; gi < p.ngroups; ++gi) SBX_TRY(plan_run_pass<T>(p, q, gi, st));
+    r.mark(marks[q], st);
+  }
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
 
 template <typename T>
-sbx_status solve_batch(int N, int nsolves, const SolveBatch<T>& desc, hipStream_t st,
-                       Recorder* rec) {
-  if (nsolves <= 0) return SBX_OK;
-  if (nsolves > kMaxBatch) {
-    set_error("too many solves in one batch");
-    return SBX_EINVAL;
-  }
-  switch (N) {
-    case 8: return launch_solve<T, 16>(nsolves, desc, st, rec);
-    case 16: return launch_solve<T, 32>(nsolves, desc, st, rec);
-    case 32: return launch_solve<T, 64>(nsolves, desc, st, rec);
-    case 64: return launch_solve<T, 128>(nsolves, desc, st, rec);
-    case 128: return launch_solve<T, 256>(nsolves, desc, st, rec);
-    case 256: return launch_solve<T, 512>(nsolves, desc, st, rec);
-    default: set_error("grid size must be a power of two in 8..256"); return SBX_EINVAL;
-  }
+void plan_destroy(SolvePlan<T>& p) {
+  if (p.d_solves) (void)hipFree(p.d_solves);
+  if (p.d_counter) (void)hipFree(p.d_counter);
+  p = SolvePlan<T>();
 }
 
-template sbx_status solve_batch<float>(int, int, const SolveBatch<float>&, hipStream_t, Recorder*);
-template sbx_status solve_batch<double>(int, int, const SolveBatch<double>&, hipStream_t, Recorder*);
+template sbx_status plan_create<float>(SolvePlan<float>&, const SolveDesc<float>*, int, hipStream_t);
+template sbx_status plan_create<double>(SolvePlan<double>&, const SolveDesc<double>*, int, hipStream_t);
+template sbx_status plan_run<float>(const SolvePlan<float>&, hipStream_t, Recorder*);
+template sbx_status plan_run<double>(const SolvePlan<double>&, hipStream_t, Recorder*);
+template sbx_status plan_run_pass<float>(const SolvePlan<float>&, int, int, hipStream_t);
+template sbx_status plan_run_pass<double>(const SolvePlan<double>&, int, int, hipStream_t);
+template void plan_destroy<float>(SolvePlan<float>&);
+template void plan_destroy<double>(SolvePlan<double>&);
 
 // ---------------------------------------------------- Green's table (FP64) --
 // H of Eq. 2 on the doubled grid, mirrored by Eq. 5: F[z][y][x] with lags
@@ -359,10 +629,10 @@ __global__ void k_green_fill(C2<double>* F, int N, double l, double lz, double h
 
 // In-place complex FFT of every line of F along one axis.
 template <int L, int AXIS>
-__global__ void __launch_bounds__((Cfg<double, L>::NT))
+__global__ void __launch_bounds__(256)
     k_c2c_axis(C2<double>* F, const C2<double>* __restrict__ tw) {
-  using K = Cfg<double, L>;
-  constexpr int W = K::W, P = K::P, NT = K::NT, TL = K::TL;
+  using K = TC<double, L, 256>;
+  constexpr int W = K::W, P = K::P, NT = 256, TL = K::TL;
   __shared__ C2<double> s[W * P];
   const int o = blockIdx.x / (L / W), i0 = (blockIdx.x % (L / W)) * W;
   if constexpr (AXIS == 0) {
@@ -372,7 +642,8 @@ __global__ void __launch_bounds__((Cfg<double, L>::NT))
       s[w * P + pad(e)] = base[i];
     }
     __syncthreads();
-    fft_line<double, L, false, false, false>(s + (threadIdx.x / TL) * P, threadIdx.x % TL, tw);
+    const bool act = (int)threadIdx.x < W * TL;
+    fft_line<double, L, false, false, false>(s + (act ? threadIdx.x / TL : 0) * P, threadIdx.x % TL, tw, act);
     for (int i = threadIdx.x; i < W * L; i += NT) {
       const int w = i / L, e = i - w * L;
       base[i] = s[w * P + pad(e)];
@@ -385,7 +656,8 @@ __global__ void __launch_bounds__((Cfg<double, L>::NT))
       s[w * P + pad(e)] = base[e * es + w];
     }
     __syncthreads();
-    fft_line<double, L, false, false, false>(s + (threadIdx.x / TL) * P, threadIdx.x % TL, tw);
+    const bool act = (int)threadIdx.x < W * TL;
+    fft_line<double, L, false, false, false>(s + (act ? threadIdx.x / TL : 0) * P, threadIdx.x % TL, tw, act);
     for (int i = threadIdx.x; i < W * L; i += NT) {
       const int e = i / W, w = i - e * W;
       base[e * es + w] = s[w * P + pad(e)];
@@ -421,13 +693,13 @@ __global__ void k_green_fold(const C2<double>* F, T* H, int N, double scale) {
 
 template <int L>
 static sbx_status green_fft(C2<double>* F, hipStream_t st) {
-  using K = Cfg<double, L>;
+  using K = TC<double, L, 256>;
   const C2<double>* tw = twiddles<double>(L, st);
   if (!tw) {
     set_error("twiddle table allocation failed");
     return SBX_ENOMEM;
   }
-  const dim3 g(L * (L / K::W)), b(K::NT);
+  const dim3 g(L * (L / K::W)), b(256);
   hipLaunchKernelGGL((k_c2c_axis<L, 0>), g, b, 0, st, F, tw);
   hipLaunchKernelGGL((k_c2c_axis<L, 1>), g, b, 0, st, F, tw);
   hipLaunchKernelGGL((k_c2c_axis<L, 2>), g, b, 0, st, F, tw);
