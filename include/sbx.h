@@ -103,6 +103,7 @@ typedef struct {
 
 typedef struct sbx_ctx sbx_ctx;
 typedef struct sbx_poisson sbx_poisson;
+typedef struct sbx_batch sbx_batch;
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* sbx_last_error(void);
@@ -184,6 +185,34 @@ sbx_status sbx_sync(sbx_ctx* ctx);
 
 /* Number of live particles (synchronises). */
 sbx_status sbx_count_live(sbx_ctx* ctx, int64_t* live);
+
+/* ---- batches: independent instances stepped together ---------------------- */
+
+/* Group n (1..32) contexts -- same device and precision, grids built,
+ * particles loaded, all fresh or all stepped together -- so that every phase
+ * of a step is one launch over all of them (the FFT passes: one launch per
+ * distinct grid size) and a step is one replay of a captured HIP graph (two
+ * graphs: with and without the cell sort).  Uneven sizes are fine: grids of
+ * 8..256 cells, any particle counts.  The contexts stay owned by the caller;
+ * while in the batch they are stepped only through it (sbx_step, forces,
+ * loading and rebuilding return SBX_ESTATE) and their getters need
+ * sbx_batch_sync after sbx_batch_step.  stream: hipStream_t or NULL.  The
+ * sort interval is taken from the first context. */
+sbx_status sbx_batch_create(sbx_ctx* const* ctxs, int32_t n, void* stream, sbx_batch** out);
+
+/* nsteps integration cycles of every instance; dt: one value per context in
+ * the order of creation (NULL keeps the previous values, initially each
+ * context's last dt).  Stream-ordered, does not synchronise.  No diagnostics
+ * records are taken in batch steps. */
+sbx_status sbx_batch_step(sbx_batch* b, const double* dt, int32_t nsteps);
+
+/* Wait for the batch's work and hand its state back to the contexts. */
+sbx_status sbx_batch_sync(sbx_batch* b);
+
+sbx_status sbx_batch_set_sort_interval(sbx_batch* b, int32_t every);
+
+/* Synchronise and release the contexts (they can be stepped alone again). */
+void sbx_batch_destroy(sbx_batch* b);
 
 /* ---- tracing: per-phase timing with HIP events ---------------------------- */
 

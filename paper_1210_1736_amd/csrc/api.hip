@@ -1,15 +1,7 @@
-// C ABI of the library: contexts (particles, grids, forces, steps) and
-// standalone Poisson plans.  Host code only orchestrates: every step of the
-// method runs in the kernels of fft.hip and particles.hip.
-#include <algorithm>
-#include <cmath>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "fft.h"
-#include "particles.h"
-#include "scan.h"
+// C ABI of the library: contexts (particles, grids, forces, steps).  Host
+// code only orchestrates: every step of the method runs in the kernels of
+// fft.hip and particles.hip.
+#include "ctx.h"
 
 namespace sbx {
 
@@ -20,7 +12,7 @@ static bool is_pow2_grid(int n) { return n >= 8 && n <= 256 && (n & (n - 1)) == 
 
 // Geometry of one level as the method reads it: the usable N-4 cells span
 // 2R, so l = 2R/(N-4); the z cell length of a flattened grid is q*l.
-static LevelDev make_level(const sbx_level& s) {
+LevelDev make_level(const sbx_level& s) {
   LevelDev L;
   L.N = s.n;
   L.half = (double)s.n / 2.0;
@@ -39,17 +31,17 @@ static LevelDev make_level(const sbx_level& s) {
   return L;
 }
 
-static double q_crit_of(int n, double Rc, double Ro, double Rs) {
+double q_crit_of(int n, double Rc, double Ro, double Rs) {
   const double a = Rc / Ro;
   const double b = 4.0 / (n - 4) * Rs / Ro;
   return a > b ? a : b;
 }
 
-static bool same_level(const sbx_level& a, const sbx_level& b) {
+bool same_level(const sbx_level& a, const sbx_level& b) {
   return a.n == b.n && a.R == b.R && a.q == b.q;
 }
 
-static sbx_status validate(int ng, const sbx_hierarchy* h) {
+sbx_status validate(int ng, const sbx_hierarchy* h) {
   if (!h || ng < 1 || ng > kMaxGal) {
     set_error("1 to 4 galaxies required");
     return SBX_EINVAL;
@@ -127,168 +119,6 @@ static sbx_status validate(int ng, const sbx_hierarchy* h) {
   return SBX_OK;
 }
 
-// ------------------------------------------------------------------ ctx ----
-struct Green {
-  sbx_level geo;
-  void* H;
-  double rel_imag;
-};
-
-}  // namespace sbx
-
-using namespace sbx;
-
-struct sbx_ctx {
-  sbx_config cfg;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  size_t esz = 4;  // bytes per real
-  // particles
-  int64_t n = 0;
-  void* x[3] = {};
-  void* v[3] = {};
-  void* m = nullptr;
-  int8_t* comp = nullptr;
-  int8_t* gal = nullptr;
-  uint8_t* lost = nullptr;
-  int32_t* id = nullptr;
-  // second set of particle arrays: target of the cell sort
-  void* x2[3] = {};
-  void* v2[3] = {};
-  void* m2 = nullptr;
-  int8_t* comp2 = nullptr;
-  int8_t* gal2 = nullptr;
-  uint8_t* lost2 = nullptr;
-  int32_t* id2 = nullptr;
-  uint32_t* key = nullptr;
-  uint32_t* count = nullptr;   // bins + 1
-  uint32_t* scan_tmp = nullptr;
-  size_t bins = 0;
-  int sort_every = 8;
-  double* com_partial = nullptr;  // kForceBlocksMax * kPreVals
-  bool com_fresh = false;         // com_partial holds the current positions' sums
-  // grids
-  bool built = false;
-  int ngal = 0;
-  int N = 0;
-  sbx_hierarchy hh[kMaxGal];
-  SysDev sys;
-  int nslots[kMaxGal] = {};
-  void* grid_block = nullptr;  // all grids back to back
-  void* grid[kMaxGal][kSlots] = {};
-  int slot_level[kMaxGal][kSlots] = {};
-  std::vector<Green> greens;
-  void* X = nullptr;
-  void* C = nullptr;
-  int nsolves = 0;
-  SolvePlan<float> plan32;
-  SolvePlan<double> plan64;
-  double* centres = nullptr;  // kMaxGal * 3
-  double* partial = nullptr;  // kForceBlocksMax * kNDiag + kNDiag
-  double* diag_one = nullptr; // kNDiag
-  double* diag_log = nullptr; // kDiagCap * kNDiag
-  int64_t diag_count = 0;
-  double* acc = nullptr;      // n * 3, lazily
-  double* pot = nullptr;      // n, lazily
-  int64_t acc_n = 0;
-  int64_t step_count = 0;
-  bool solved = false;        // centres computed by a solve
-  bool grids_fields = false;  // grids hold fields (not cell masses)
-  Recorder rec;
-};
-
-// Solve plans of a Poisson object are cached per (rho, phi, batch) so that a
-// loop over the same buffers reuses its device tables.
-struct PoissonPlan {
-  const void* rho;
-  void* phi;
-  int batch;
-  SolvePlan<float> p32;
-  SolvePlan<double> p64;
-};
-
-struct sbx_poisson {
-  int N = 0, prec = 0, device = 0;
-  sbx_level geo;
-  double G = 1.0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  void* H = nullptr;
-  void* X = nullptr;
-  void* C = nullptr;
-  int cap = 0;
-  double rel_imag = 0.0;
-  int64_t bytes = 0;
-  std::vector<PoissonPlan*> plans;
-};
-
-namespace {
-
-constexpr int kDiagCap = 4096;
-constexpr int kMaxSolves = 40;  // solves per Poisson plan launch
-
-template <typename T>
-PartDev<T> part_of(sbx_ctx* c) {
-  PartDev<T> p;
-  for (int k = 0; k < 3; ++k) {
-    p.x[k] = (T*)c->x[k];
-    p.v[k] = (T*)c->v[k];
-  }
-  p.m = (T*)c->m;
-  p.comp = c->comp;
-  p.gal = c->gal;
-  p.lost = c->lost;
-  p.id = c->id;
-  p.n = c->n;
-  return p;
-}
-
-template <typename T>
-PartDev<T> part2_of(sbx_ctx* c) {
-  PartDev<T> p;
-  for (int k = 0; k < 3; ++k) {
-    p.x[k] = (T*)c->x2[k];
-    p.v[k] = (T*)c->v2[k];
-  }
-  p.m = (T*)c->m2;
-  p.comp = c->comp2;
-  p.gal = c->gal2;
-  p.lost = c->lost2;
-  p.id = c->id2;
-  p.n = c->n;
-  return p;
-}
-
-void swap_particles(sbx_ctx* c) {
-  for (int k = 0; k < 3; ++k) {
-    std::swap(c->x[k], c->x2[k]);
-    std::swap(c->v[k], c->v2[k]);
-  }
-  std::swap(c->m, c->m2);
-  std::swap(c->comp, c->comp2);
-  std::swap(c->gal, c->gal2);
-  std::swap(c->lost, c->lost2);
-  std::swap(c->id, c->id2);
-}
-
-template <typename T>
-GridsDev<T> grids_of(sbx_ctx* c) {
-  GridsDev<T> G;
-  for (int g = 0; g < kMaxGal; ++g)
-    for (int k = 0; k < kSlots; ++k) G.g[g][k] = (T*)c->grid[g][k];
-  return G;
-}
-
-void free_ptr(void*& p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
-template <typename P>
-void free_typed(P*& p) {
-  if (p) (void)hipFree((void*)p);
-  p = nullptr;
-}
-
 sbx_status dev_alloc(void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (hipMalloc(p, bytes) != hipSuccess) {
@@ -300,29 +130,125 @@ sbx_status dev_alloc(void** p, size_t bytes) {
   return SBX_OK;
 }
 
-void free_particles(sbx_ctx* c) {
-  for (int k = 0; k < 3; ++k) {
-    free_ptr(c->x[k]);
-    free_ptr(c->v[k]);
-    free_ptr(c->x2[k]);
-    free_ptr(c->v2[k]);
+void free_ptr(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+sbx_status set_device(int dev) {
+  SBX_HIP(hipSetDevice(dev));
+  return SBX_OK;
+}
+
+void to_diag(const double* r, sbx_diag* d) {
+  std::memset(d, 0, sizeof(*d));
+  for (int c = 0; c < kNComp; ++c) {
+    d->ekin[c] = r[kDiagComp * c + 0];
+    d->epot[c] = r[kDiagComp * c + 1];
+    d->L[c][0] = r[kDiagComp * c + 2];
+    d->L[c][1] = r[kDiagComp * c + 3];
+    d->L[c][2] = r[kDiagComp * c + 4];
+    d->n_live[c] = (int64_t)llround(r[kDiagComp * c + 5]);
   }
-  free_ptr(c->m);
-  free_typed(c->comp);
-  free_typed(c->gal);
-  free_typed(c->lost);
-  free_typed(c->id);
-  free_ptr(c->m2);
-  free_typed(c->comp2);
-  free_typed(c->gal2);
-  free_typed(c->lost2);
-  free_typed(c->id2);
+  const double* q = r + kDiagDisc;
+  if (q[4] > 0) {
+    const double mR = q[0] / q[4], mz = q[2] / q[4];
+    d->disc_sigR = std::sqrt(std::fmax(q[1] / q[4] - mR * mR, 0.0));
+    d->disc_sigz = std::sqrt(std::fmax(q[3] / q[4] - mz * mz, 0.0));
+  }
+  d->n_lost = (int64_t)llround(r[kDiagLost]);
+}
+
+template <typename T>
+static PartDev<T> pset_dev(const PSet& s, int64_t n) {
+  PartDev<T> p;
+  for (int k = 0; k < 3; ++k) {
+    p.x[k] = (T*)s.x[k];
+    p.v[k] = (T*)s.v[k];
+  }
+  p.m = (T*)s.m;
+  p.comp = s.comp;
+  p.gal = s.gal;
+  p.lost = s.lost;
+  p.id = s.id;
+  p.n = n;
+  return p;
+}
+
+template <typename T>
+InstDev<T> inst_of(const sbx_ctx* c) {
+  InstDev<T> I;
+  std::memset(&I, 0, sizeof(I));
+  I.p[0] = pset_dev<T>(c->set[0], c->n);
+  I.p[1] = pset_dev<T>(c->set[1], c->n);
+  I.sys = c->sys;
+  for (int g = 0; g < kMaxGal; ++g)
+    for (int k = 0; k < kSlots; ++k) I.G.g[g][k] = (T*)c->grid[g][k];
+  I.centres = c->centres;
+  I.com_partial = c->com_partial;
+  I.pre_partial = c->pre_partial;
+  I.diag_partial = c->diag_partial;
+  I.diag_out = c->diag_one;
+  I.acc = c->acc;
+  I.pot = c->pot;
+  I.grid_block = (T*)c->grid_block;
+  I.grid_elems = c->grid_elems;
+  I.key = c->key;
+  I.count = c->count;
+  I.part_base = 0;
+  I.dt = c->dt_dev;
+  I.n = c->n;
+  return I;
+}
+
+template InstDev<float> inst_of<float>(const sbx_ctx*);
+template InstDev<double> inst_of<double>(const sbx_ctx*);
+
+sbx_status upload_inst(sbx_ctx* c) {
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  if (c->cfg.prec == SBX_FP64) {
+    const InstDev<double> I = inst_of<double>(c);
+    SBX_HIP(hipMemcpy(c->d_inst, &I, sizeof(I), hipMemcpyHostToDevice));
+  } else {
+    const InstDev<float> I = inst_of<float>(c);
+    SBX_HIP(hipMemcpy(c->d_inst, &I, sizeof(I), hipMemcpyHostToDevice));
+  }
+  SBX_HIP(hipMemcpy(c->d_cur, &c->cur, sizeof(int), hipMemcpyHostToDevice));
+  return SBX_OK;
+}
+
+}  // namespace sbx
+
+using namespace sbx;
+
+namespace {
+
+template <typename P>
+void free_typed(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+void free_particles(sbx_ctx* c) {
+  for (int s = 0; s < 2; ++s) {
+    PSet& q = c->set[s];
+    for (int k = 0; k < 3; ++k) {
+      free_ptr(q.x[k]);
+      free_ptr(q.v[k]);
+    }
+    free_ptr(q.m);
+    free_typed(q.comp);
+    free_typed(q.gal);
+    free_typed(q.lost);
+    free_typed(q.id);
+  }
   free_typed(c->key);
-  c->com_fresh = false;
   free_typed(c->acc);
   free_typed(c->pot);
   c->acc_n = 0;
   c->n = 0;
+  c->cur = 0;
+  c->com_fresh = false;
 }
 
 void free_grids(sbx_ctx* c) {
@@ -337,13 +263,9 @@ void free_grids(sbx_ctx* c) {
   free_ptr(c->X);
   free_ptr(c->C);
   std::memset(c->grid, 0, sizeof(c->grid));
+  c->grid_elems = 0;
   c->built = false;
   c->solved = false;
-}
-
-sbx_status set_device(int dev) {
-  SBX_HIP(hipSetDevice(dev));
-  return SBX_OK;
 }
 
 int slot_count(const sbx_hierarchy& h) { return h.n_levels == 3 ? kSlots : 1; }
@@ -360,7 +282,8 @@ sbx_status build_grids_t(sbx_ctx* c) {
   int total = 0;
   for (int g = 0; g < c->ngal; ++g) total += c->nslots[g];
   c->nsolves = total;
-  SBX_TRY(dev_alloc(&c->grid_block, cells * sizeof(T) * total));
+  c->grid_elems = cells * total;
+  SBX_TRY(dev_alloc(&c->grid_block, sizeof(T) * c->grid_elems));
   int s = 0;
   for (int g = 0; g < c->ngal; ++g)
     for (int k = 0; k < c->nslots[g]; ++k) c->grid[g][k] = (T*)c->grid_block + cells * (s++);
@@ -405,27 +328,21 @@ sbx_status build_grids_t(sbx_ctx* c) {
   return SBX_OK;
 }
 
-const void* green_for(sbx_ctx* c, const sbx_level& geo) {
-  for (auto& e : c->greens)
-    if (same_level(e.geo, geo)) return e.H;
-  return nullptr;
+template <typename T>
+const InstDev<T>* dinst(sbx_ctx* c) {
+  return (const InstDev<T>*)c->d_inst;
 }
 
 // Loss test, centres, mass assignment and all isolated solves of one step.
 template <typename T>
 sbx_status field_solve_t(sbx_ctx* c) {
-  const size_t cells = (size_t)c->N * c->N * c->N;
+  const std::vector<InstInfo> info{info_of(c)};
   c->rec.mark(PH_START, c->stream);
-  SBX_TRY(launch_zero<T>((T*)c->grid_block, cells * c->nsolves, c->stream));
+  SBX_TRY(launch_zero_grids<T>(dinst<T>(c), info, c->stream));
   c->rec.mark(PH_ZERO, c->stream);
-  const PartDev<T> p = part_of<T>(c);
-  if (c->com_fresh)
-    SBX_TRY(launch_centres(c->com_partial, force_blocks(c->n), c->sys,
-                           c->partial + (size_t)kRedBlocks * kPreVals, c->centres, c->stream));
-  else
-    SBX_TRY(launch_pre<T>(p, c->sys, c->partial, c->centres, c->stream));
+  SBX_TRY(launch_centres<T>(dinst<T>(c), c->d_cur, info, c->com_fresh, c->stream));
   c->rec.mark(PH_PRE, c->stream);
-  SBX_TRY(launch_deposit<T>(p, c->sys, c->centres, grids_of<T>(c), c->stream));
+  SBX_TRY(launch_deposit<T>(dinst<T>(c), c->d_cur, info, c->stream));
   c->rec.mark(PH_DEPOSIT, c->stream);
   if constexpr (sizeof(T) == 8) SBX_TRY(plan_run<T>(c->plan64, c->stream, &c->rec));
   else SBX_TRY(plan_run<T>(c->plan32, c->stream, &c->rec));
@@ -435,31 +352,33 @@ sbx_status field_solve_t(sbx_ctx* c) {
 }
 
 template <typename T>
-sbx_status force_t(sbx_ctx* c, double dt, int mode, double* diag_out) {
-  SBX_TRY(launch_force<T>(part_of<T>(c), c->sys, c->centres, grids_of<T>(c), dt, mode, c->acc,
-                          c->pot, c->partial, diag_out, c->com_partial, c->stream));
+sbx_status force_t(sbx_ctx* c, int mode) {
+  const std::vector<InstInfo> info{info_of(c)};
+  SBX_TRY(launch_force<T>(dinst<T>(c), c->d_cur, info, mode, c->stream));
   c->rec.mark(PH_FORCE, c->stream);
   if (mode & 1) c->com_fresh = true;
   return SBX_OK;
 }
 
 // Reorder the particles by the cell of their finest grid, at the centres of
-// the last solve (or the fixed centres).
+// the last solve (or the current centre of mass before the first one).
 template <typename T>
 sbx_status sort_t(sbx_ctx* c) {
+  const std::vector<InstInfo> info{info_of(c)};
   c->rec.mark(PH_START, c->stream);
-  if (!c->key) SBX_TRY(dev_alloc((void**)&c->key, sizeof(uint32_t) * c->n));
-  if (!c->solved) {
-    // centres are needed for the keys: take them from the current positions
-    SBX_TRY(launch_pre<T>(part_of<T>(c), c->sys, c->partial, c->centres, c->stream));
-  }
-  SBX_TRY(launch_sort<T>(part_of<T>(c), part2_of<T>(c), c->sys, c->centres, c->key, c->count,
-                         c->bins, c->scan_tmp, c->stream));
-  swap_particles(c);
+  if (!c->solved) SBX_TRY(launch_centres<T>(dinst<T>(c), c->d_cur, info, false, c->stream));
+  SBX_TRY(launch_sort<T>(dinst<T>(c), c->d_cur, info, c->count, c->bins + 1, c->scan_tmp, c->stream));
+  c->cur ^= 1;
   c->rec.mark(PH_SORT, c->stream);
   return SBX_OK;
 }
 
+sbx_status field_solve(sbx_ctx* c) {
+  return c->cfg.prec == SBX_FP64 ? field_solve_t<double>(c) : field_solve_t<float>(c);
+}
+sbx_status force(sbx_ctx* c, int mode) {
+  return c->cfg.prec == SBX_FP64 ? force_t<double>(c, mode) : force_t<float>(c, mode);
+}
 sbx_status sort_particles(sbx_ctx* c) {
   return c->cfg.prec == SBX_FP64 ? sort_t<double>(c) : sort_t<float>(c);
 }
@@ -471,24 +390,20 @@ void free_recorder(Recorder& r) {
   r = Recorder();
 }
 
-sbx_status field_solve(sbx_ctx* c) {
-  return c->cfg.prec == SBX_FP64 ? field_solve_t<double>(c) : field_solve_t<float>(c);
-}
-sbx_status force(sbx_ctx* c, double dt, int mode, double* diag_out) {
-  return c->cfg.prec == SBX_FP64 ? force_t<double>(c, dt, mode, diag_out)
-                                 : force_t<float>(c, dt, mode, diag_out);
-}
-
 sbx_status check_ready(sbx_ctx* c) {
   if (!c) {
     set_error("null context");
     return SBX_EINVAL;
   }
+  if (c->batch && c->batch->pending) {
+    set_error("the context's batch has queued work: call sbx_batch_sync first");
+    return SBX_ESTATE;
+  }
   if (!c->built) {
     set_error("build_grids has not been called");
     return SBX_ESTATE;
   }
-  if (c->n == 0 || !c->x[0]) {
+  if (c->n == 0 || !c->set[0].x[0]) {
     set_error("no particles loaded");
     return SBX_ESTATE;
   }
@@ -502,101 +417,13 @@ sbx_status ensure_acc(sbx_ctx* c) {
   SBX_TRY(dev_alloc((void**)&c->acc, sizeof(double) * 3 * c->n));
   SBX_TRY(dev_alloc((void**)&c->pot, sizeof(double) * c->n));
   c->acc_n = c->n;
-  return SBX_OK;
+  return upload_inst(c);
 }
 
-void to_diag(const double* r, sbx_diag* d) {
-  std::memset(d, 0, sizeof(*d));
-  for (int c = 0; c < kNComp; ++c) {
-    d->ekin[c] = r[kDiagComp * c + 0];
-    d->epot[c] = r[kDiagComp * c + 1];
-    d->L[c][0] = r[kDiagComp * c + 2];
-    d->L[c][1] = r[kDiagComp * c + 3];
-    d->L[c][2] = r[kDiagComp * c + 4];
-    d->n_live[c] = (int64_t)llround(r[kDiagComp * c + 5]);
-  }
-  const double* q = r + kDiagDisc;
-  if (q[4] > 0) {
-    const double mR = q[0] / q[4], mz = q[2] / q[4];
-    d->disc_sigR = std::sqrt(std::fmax(q[1] / q[4] - mR * mR, 0.0));
-    d->disc_sigz = std::sqrt(std::fmax(q[3] / q[4] - mz * mz, 0.0));
-  }
-  d->n_lost = (int64_t)llround(r[kDiagLost]);
-}
-
-template <typename T>
-SolvePlan<T>& plan_of(PoissonPlan* q) {
-  if constexpr (sizeof(T) == 8) return q->p64;
-  else return q->p32;
-}
-
-template <typename T>
-sbx_status poisson_solve_t(sbx_poisson* p, int batch, const void* rho, void* phi) {
-  const size_t cells = (size_t)p->N * p->N * p->N;
-  const int cap = std::min(batch, kMaxSolves);
-  if (cap > p->cap) {
-    SBX_HIP(hipStreamSynchronize(p->stream));
-    for (auto* q : p->plans) {
-      plan_destroy(q->p32);
-      plan_destroy(q->p64);
-      delete q;
-    }
-    p->plans.clear();
-    free_ptr(p->X);
-    free_ptr(p->C);
-    p->cap = 0;
-    SBX_TRY(dev_alloc(&p->X, x_elems(p->N) * sizeof(C2<T>) * cap));
-    SBX_TRY(dev_alloc(&p->C, c_elems(p->N) * sizeof(C2<T>) * cap));
-    p->cap = cap;
-    p->bytes = (int64_t)(h_elems(p->N) * sizeof(T) +
-                         (x_elems(p->N) + c_elems(p->N)) * sizeof(C2<T>) * cap);
-  }
-  for (int b0 = 0; b0 < batch; b0 += p->cap) {
-    const int nb = std::min(p->cap, batch - b0);
-    const void* r = (const T*)rho + cells * b0;
-    void* f = (T*)phi + cells * b0;
-    PoissonPlan* hit = nullptr;
-    for (auto* q : p->plans)
-      if (q->rho == r && q->phi == f && q->batch == nb) hit = q;
-    if (!hit) {
-      auto descs = [&](const T* rr, T* ff) {
-        std::vector<SolveDesc<T>> d(nb);
-        for (int i = 0; i < nb; ++i) {
-          d[i].rho = rr + cells * i;
-          d[i].phi = ff + cells * i;
-          d[i].X = (C2<T>*)p->X + x_elems(p->N) * i;
-          d[i].C = (C2<T>*)p->C + c_elems(p->N) * i;
-          d[i].H = (const T*)p->H;
-          d[i].N = p->N;
-        }
-        return d;
-      };
-      if (!tuning_cached((int)sizeof(T), std::vector<int>(nb, p->N))) {
-        // tune on scratch grids, never on the caller's buffers
-        T* scratch = nullptr;
-        SBX_TRY(dev_alloc((void**)&scratch, sizeof(T) * cells * nb));
-        SolvePlan<T> tmp;
-        auto d = descs(scratch, scratch);
-        const sbx_status rc = plan_create<T>(tmp, d.data(), nb, p->stream);
-        plan_destroy(tmp);
-        (void)hipFree(scratch);
-        SBX_TRY(rc);
-      }
-      if (p->plans.size() >= 8) {
-        SBX_HIP(hipStreamSynchronize(p->stream));
-        plan_destroy(p->plans.front()->p32);
-        plan_destroy(p->plans.front()->p64);
-        delete p->plans.front();
-        p->plans.erase(p->plans.begin());
-      }
-      hit = new PoissonPlan{r, f, nb, {}, {}};
-      p->plans.push_back(hit);
-      auto d = descs((const T*)r, (T*)f);
-      SBX_TRY(plan_create<T>(plan_of<T>(hit), d.data(), nb, p->stream));
-    }
-    SBX_TRY(plan_run<T>(plan_of<T>(hit), p->stream));
-  }
-  return SBX_OK;
+sbx_status set_dt(sbx_ctx* c, double dt) {
+  if (c->dt_dev == dt) return SBX_OK;
+  c->dt_dev = dt;
+  return upload_inst(c);
 }
 
 }  // namespace
@@ -660,12 +487,16 @@ sbx_status sbx_create(const sbx_config* cfg, sbx_ctx** out) {
     }
     c->own_stream = true;
   }
+  const size_t inst_bytes = cfg->prec == SBX_FP64 ? sizeof(InstDev<double>) : sizeof(InstDev<float>);
   sbx_status rc = SBX_OK;
   if ((rc = dev_alloc((void**)&c->centres, sizeof(double) * 3 * kMaxGal)) != SBX_OK ||
-      (rc = dev_alloc((void**)&c->partial, sizeof(double) * ((size_t)kForceBlocksMax * kNDiag + kNDiag))) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->pre_partial, sizeof(double) * ((size_t)kRedBlocks + 1) * kPreVals)) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->com_partial, sizeof(double) * (size_t)kForceBlocksMax * kPreVals)) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->diag_partial, sizeof(double) * (size_t)kForceBlocksMax * kNDiag)) != SBX_OK ||
       (rc = dev_alloc((void**)&c->diag_one, sizeof(double) * kNDiag)) != SBX_OK ||
       (rc = dev_alloc((void**)&c->diag_log, sizeof(double) * kNDiag * kDiagCap)) != SBX_OK ||
-      (rc = dev_alloc((void**)&c->com_partial, sizeof(double) * kForceBlocksMax * kPreVals)) != SBX_OK) {
+      (rc = dev_alloc(&c->d_inst, inst_bytes)) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->d_cur, sizeof(int))) != SBX_OK) {
     sbx_destroy(c);
     return rc;
   }
@@ -680,10 +511,13 @@ void sbx_destroy(sbx_ctx* c) {
   free_particles(c);
   free_grids(c);
   free_typed(c->centres);
-  free_typed(c->partial);
+  free_typed(c->pre_partial);
+  free_typed(c->com_partial);
+  free_typed(c->diag_partial);
   free_typed(c->diag_one);
   free_typed(c->diag_log);
-  free_typed(c->com_partial);
+  free_ptr(c->d_inst);
+  free_typed(c->d_cur);
   free_recorder(c->rec);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -744,6 +578,14 @@ sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const doub
     set_error("null argument or n <= 0");
     return SBX_EINVAL;
   }
+  if (n >= ((int64_t)1 << 31)) {
+    set_error("at most 2^31 - 1 particles per context");
+    return SBX_EINVAL;
+  }
+  if (c->batch) {
+    set_error("the context belongs to a batch");
+    return SBX_ESTATE;
+  }
   for (int64_t i = 0; i < n; ++i) {
     if (!std::isfinite(m[i]) || m[i] < 0.0) {
       set_error("masses must be finite and >= 0 (particle " + std::to_string(i) + ")");
@@ -767,58 +609,57 @@ sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const doub
   SBX_HIP(hipStreamSynchronize(c->stream));
   free_particles(c);
   const size_t es = c->esz;
-  for (int k = 0; k < 3; ++k) {
-    SBX_TRY(dev_alloc(&c->x[k], es * n));
-    SBX_TRY(dev_alloc(&c->v[k], es * n));
-    SBX_TRY(dev_alloc(&c->x2[k], es * n));
-    SBX_TRY(dev_alloc(&c->v2[k], es * n));
+  for (int s = 0; s < 2; ++s) {
+    PSet& q = c->set[s];
+    for (int k = 0; k < 3; ++k) {
+      SBX_TRY(dev_alloc(&q.x[k], es * n));
+      SBX_TRY(dev_alloc(&q.v[k], es * n));
+    }
+    SBX_TRY(dev_alloc(&q.m, es * n));
+    SBX_TRY(dev_alloc((void**)&q.comp, n));
+    SBX_TRY(dev_alloc((void**)&q.gal, n));
+    SBX_TRY(dev_alloc((void**)&q.lost, n));
+    SBX_TRY(dev_alloc((void**)&q.id, sizeof(int32_t) * n));
   }
-  SBX_TRY(dev_alloc(&c->m, es * n));
-  SBX_TRY(dev_alloc((void**)&c->comp, n));
-  SBX_TRY(dev_alloc((void**)&c->gal, n));
-  SBX_TRY(dev_alloc((void**)&c->lost, n));
-  SBX_TRY(dev_alloc((void**)&c->id, sizeof(int32_t) * n));
-  SBX_TRY(dev_alloc(&c->m2, es * n));
-  SBX_TRY(dev_alloc((void**)&c->comp2, n));
-  SBX_TRY(dev_alloc((void**)&c->gal2, n));
-  SBX_TRY(dev_alloc((void**)&c->lost2, n));
-  SBX_TRY(dev_alloc((void**)&c->id2, sizeof(int32_t) * n));
+  SBX_TRY(dev_alloc((void**)&c->key, sizeof(uint32_t) * n));
   c->n = n;
+  c->cur = 0;
   double* stage = nullptr;
   SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 3 * n));
-  sbx_status rc = SBX_OK;
+  PSet& q = c->set[0];
   auto run = [&]() -> sbx_status {
     SBX_HIP(hipMemcpy(stage, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
     if (c->cfg.prec == SBX_FP64)
-      SBX_TRY(launch_split3<double>(stage, (double*)c->x[0], (double*)c->x[1], (double*)c->x[2], n, c->stream));
+      SBX_TRY(launch_split3<double>(stage, (double*)q.x[0], (double*)q.x[1], (double*)q.x[2], n, c->stream));
     else
-      SBX_TRY(launch_split3<float>(stage, (float*)c->x[0], (float*)c->x[1], (float*)c->x[2], n, c->stream));
+      SBX_TRY(launch_split3<float>(stage, (float*)q.x[0], (float*)q.x[1], (float*)q.x[2], n, c->stream));
     SBX_HIP(hipStreamSynchronize(c->stream));
     SBX_HIP(hipMemcpy(stage, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
     if (c->cfg.prec == SBX_FP64)
-      SBX_TRY(launch_split3<double>(stage, (double*)c->v[0], (double*)c->v[1], (double*)c->v[2], n, c->stream));
+      SBX_TRY(launch_split3<double>(stage, (double*)q.v[0], (double*)q.v[1], (double*)q.v[2], n, c->stream));
     else
-      SBX_TRY(launch_split3<float>(stage, (float*)c->v[0], (float*)c->v[1], (float*)c->v[2], n, c->stream));
+      SBX_TRY(launch_split3<float>(stage, (float*)q.v[0], (float*)q.v[1], (float*)q.v[2], n, c->stream));
     SBX_HIP(hipStreamSynchronize(c->stream));
     SBX_HIP(hipMemcpy(stage, m, sizeof(double) * n, hipMemcpyHostToDevice));
     if (c->cfg.prec == SBX_FP64)
-      SBX_TRY(launch_convert_in<double>(stage, (double*)c->m, n, c->stream));
+      SBX_TRY(launch_convert_in<double>(stage, (double*)q.m, n, c->stream));
     else
-      SBX_TRY(launch_convert_in<float>(stage, (float*)c->m, n, c->stream));
+      SBX_TRY(launch_convert_in<float>(stage, (float*)q.m, n, c->stream));
     SBX_HIP(hipStreamSynchronize(c->stream));
-    SBX_HIP(hipMemcpy(c->comp, comp, n, hipMemcpyHostToDevice));
-    SBX_HIP(hipMemcpy(c->gal, gal, n, hipMemcpyHostToDevice));
-    SBX_HIP(hipMemset(c->lost, 0, n));
-    SBX_TRY(launch_iota(c->id, n, c->stream));
+    SBX_HIP(hipMemcpy(q.comp, comp, n, hipMemcpyHostToDevice));
+    SBX_HIP(hipMemcpy(q.gal, gal, n, hipMemcpyHostToDevice));
+    SBX_HIP(hipMemset(q.lost, 0, n));
+    SBX_TRY(launch_iota(q.id, n, c->stream));
     SBX_HIP(hipStreamSynchronize(c->stream));
     return SBX_OK;
   };
-  rc = run();
+  sbx_status rc = run();
   (void)hipFree(stage);
   c->solved = false;
   c->grids_fields = false;
   c->com_fresh = false;
   c->step_count = 0;
+  if (rc == SBX_OK) rc = upload_inst(c);
   return rc;
 }
 
@@ -826,6 +667,10 @@ sbx_status sbx_build_grids(sbx_ctx* c, int32_t n_galaxies, const sbx_hierarchy* 
   if (!c) {
     set_error("null context");
     return SBX_EINVAL;
+  }
+  if (c->batch) {
+    set_error("the context belongs to a batch");
+    return SBX_ESTATE;
   }
   SBX_TRY(validate(n_galaxies, h));
   SBX_TRY(set_device(c->cfg.device));
@@ -855,24 +700,29 @@ sbx_status sbx_build_grids(sbx_ctx* c, int32_t n_galaxies, const sbx_hierarchy* 
     return rc;
   }
   c->built = true;
-  return SBX_OK;
+  return upload_inst(c);
 }
 
 sbx_status sbx_compute_forces(sbx_ctx* c, double* acc, double* pot) {
   SBX_TRY(check_ready(c));
+  if (c->batch) {
+    set_error("the context belongs to a batch");
+    return SBX_ESTATE;
+  }
   SBX_TRY(ensure_acc(c));
   SBX_TRY(field_solve(c));
-  SBX_TRY(force(c, 0.0, 2, nullptr));
+  SBX_TRY(force(c, 2));
+  const int32_t* id = c->set[c->cur].id;
   double* stage = nullptr;
   SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 3 * c->n));
   auto run = [&]() -> sbx_status {
     if (acc) {
-      SBX_TRY(launch_unpermute<double>(c->acc, c->id, stage, c->n, 3, c->stream));
+      SBX_TRY(launch_unpermute<double>(c->acc, id, stage, c->n, 3, c->stream));
       SBX_HIP(hipMemcpyAsync(acc, stage, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
       SBX_HIP(hipStreamSynchronize(c->stream));
     }
     if (pot) {
-      SBX_TRY(launch_unpermute<double>(c->pot, c->id, stage, c->n, 1, c->stream));
+      SBX_TRY(launch_unpermute<double>(c->pot, id, stage, c->n, 1, c->stream));
       SBX_HIP(hipMemcpyAsync(pot, stage, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
     }
     SBX_HIP(hipStreamSynchronize(c->stream));
@@ -889,15 +739,22 @@ sbx_status sbx_step(sbx_ctx* c, double dt, int32_t nsteps, int32_t diag_every) {
     set_error("dt must be finite and nsteps >= 0");
     return SBX_EINVAL;
   }
+  if (c->batch) {
+    set_error("the context belongs to a batch: step it with sbx_batch_step");
+    return SBX_ESTATE;
+  }
+  SBX_TRY(set_dt(c, dt));
   for (int s = 0; s < nsteps; ++s) {
     if (c->sort_every > 0 && (c->step_count % c->sort_every) == 0) SBX_TRY(sort_particles(c));
     SBX_TRY(field_solve(c));
     const bool diag = diag_every > 0 && (c->step_count % diag_every) == 0;
     if (diag && c->diag_count < kDiagCap) {
-      SBX_TRY(force(c, dt, 1 | 4, c->diag_log + (size_t)kNDiag * c->diag_count));
+      SBX_TRY(force(c, 1 | 4));
+      SBX_HIP(hipMemcpyAsync(c->diag_log + (size_t)kNDiag * c->diag_count, c->diag_one,
+                             sizeof(double) * kNDiag, hipMemcpyDeviceToDevice, c->stream));
       ++c->diag_count;
     } else {
-      SBX_TRY(force(c, dt, 1, nullptr));
+      SBX_TRY(force(c, 1));
     }
     ++c->step_count;
   }
@@ -909,25 +766,30 @@ sbx_status sbx_get_particles(sbx_ctx* c, double* x, double* v, uint8_t* lost) {
     set_error("no particles loaded");
     return c ? SBX_ESTATE : SBX_EINVAL;
   }
+  if (c->batch && c->batch->pending) {
+    set_error("the context's batch has queued work: call sbx_batch_sync first");
+    return SBX_ESTATE;
+  }
   SBX_TRY(set_device(c->cfg.device));
+  const PSet& q = c->set[c->cur];
   double* stage = nullptr;
   SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 6 * c->n));
   double* stage2 = stage + 3 * c->n;
   auto run = [&]() -> sbx_status {
     for (int which = 0; which < 2; ++which) {
       double* out = which == 0 ? x : v;
-      void** src = which == 0 ? c->x : c->v;
+      void* const* src = which == 0 ? q.x : q.v;
       if (!out) continue;
       if (c->cfg.prec == SBX_FP64)
         SBX_TRY(launch_join3<double>((double*)src[0], (double*)src[1], (double*)src[2], stage, c->n, c->stream));
       else
         SBX_TRY(launch_join3<float>((float*)src[0], (float*)src[1], (float*)src[2], stage, c->n, c->stream));
-      SBX_TRY(launch_unpermute<double>(stage, c->id, stage2, c->n, 3, c->stream));
+      SBX_TRY(launch_unpermute<double>(stage, q.id, stage2, c->n, 3, c->stream));
       SBX_HIP(hipMemcpyAsync(out, stage2, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
       SBX_HIP(hipStreamSynchronize(c->stream));
     }
     if (lost) {
-      SBX_TRY(launch_unpermute<uint8_t>(c->lost, c->id, (uint8_t*)stage, c->n, 1, c->stream));
+      SBX_TRY(launch_unpermute<uint8_t>(q.lost, q.id, (uint8_t*)stage, c->n, 1, c->stream));
       SBX_HIP(hipMemcpyAsync(lost, stage, c->n, hipMemcpyDeviceToHost, c->stream));
     }
     SBX_HIP(hipStreamSynchronize(c->stream));
@@ -969,6 +831,7 @@ sbx_status sbx_get_indices(sbx_ctx* c, int32_t galaxy, int32_t level, int32_t* i
     SBX_HIP(hipStreamSynchronize(c->stream));
     SBX_HIP(hipMemcpy(c->centres, hc, sizeof(double) * 3 * c->ngal, hipMemcpyHostToDevice));
   }
+  const int32_t* id = c->set[c->cur].id;
   int32_t* di = nullptr;
   int8_t* dc = nullptr;
   SBX_TRY(dev_alloc((void**)&di, sizeof(int32_t) * 6 * c->n));
@@ -980,11 +843,11 @@ sbx_status sbx_get_indices(sbx_ctx* c, int32_t galaxy, int32_t level, int32_t* i
   int8_t* dc2 = dc + c->n;
   auto run = [&]() -> sbx_status {
     if (c->cfg.prec == SBX_FP64)
-      SBX_TRY(launch_indices<double>(part_of<double>(c), c->sys, c->centres, galaxy, level, di, dc, c->stream));
+      SBX_TRY(launch_indices<double>(dinst<double>(c), c->d_cur, c->n, galaxy, level, di, dc, c->stream));
     else
-      SBX_TRY(launch_indices<float>(part_of<float>(c), c->sys, c->centres, galaxy, level, di, dc, c->stream));
-    SBX_TRY(launch_unpermute<int32_t>(di, c->id, di2, c->n, 3, c->stream));
-    SBX_TRY(launch_unpermute<int8_t>(dc, c->id, dc2, c->n, 1, c->stream));
+      SBX_TRY(launch_indices<float>(dinst<float>(c), c->d_cur, c->n, galaxy, level, di, dc, c->stream));
+    SBX_TRY(launch_unpermute<int32_t>(di, id, di2, c->n, 3, c->stream));
+    SBX_TRY(launch_unpermute<int8_t>(dc, id, dc2, c->n, 1, c->stream));
     if (idx) SBX_HIP(hipMemcpyAsync(idx, di2, sizeof(int32_t) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
     if (cls) SBX_HIP(hipMemcpyAsync(cls, dc2, c->n, hipMemcpyDeviceToHost, c->stream));
     SBX_HIP(hipStreamSynchronize(c->stream));
@@ -1008,14 +871,15 @@ sbx_status sbx_get_grid(sbx_ctx* c, int32_t galaxy, int32_t which, int32_t kind,
     return SBX_ESTATE;
   }
   const size_t cells = (size_t)c->N * c->N * c->N;
+  const std::vector<InstInfo> info{info_of(c)};
   if (kind == 0) {
     // cell masses: re-run the assignment only (the solve overwrote them)
     if (c->cfg.prec == SBX_FP64) {
-      SBX_TRY(launch_zero<double>((double*)c->grid_block, cells * c->nsolves, c->stream));
-      SBX_TRY(launch_deposit<double>(part_of<double>(c), c->sys, c->centres, grids_of<double>(c), c->stream));
+      SBX_TRY(launch_zero_grids<double>(dinst<double>(c), info, c->stream));
+      SBX_TRY(launch_deposit<double>(dinst<double>(c), c->d_cur, info, c->stream));
     } else {
-      SBX_TRY(launch_zero<float>((float*)c->grid_block, cells * c->nsolves, c->stream));
-      SBX_TRY(launch_deposit<float>(part_of<float>(c), c->sys, c->centres, grids_of<float>(c), c->stream));
+      SBX_TRY(launch_zero_grids<float>(dinst<float>(c), info, c->stream));
+      SBX_TRY(launch_deposit<float>(dinst<float>(c), c->d_cur, info, c->stream));
     }
     c->grids_fields = false;
   }
@@ -1037,12 +901,17 @@ sbx_status sbx_get_grid(sbx_ctx* c, int32_t galaxy, int32_t which, int32_t kind,
 
 sbx_status sbx_diagnostics(sbx_ctx* c, double dt, sbx_diag* out) {
   SBX_TRY(check_ready(c));
+  if (c->batch) {
+    set_error("the context belongs to a batch");
+    return SBX_ESTATE;
+  }
   if (!out || !std::isfinite(dt)) {
     set_error("null output or non-finite dt");
     return SBX_EINVAL;
   }
+  SBX_TRY(set_dt(c, dt));
   SBX_TRY(field_solve(c));
-  SBX_TRY(force(c, dt, 4, c->diag_one));
+  SBX_TRY(force(c, 4));
   double r[kNDiag];
   SBX_HIP(hipMemcpyAsync(r, c->diag_one, sizeof(r), hipMemcpyDeviceToHost, c->stream));
   SBX_HIP(hipStreamSynchronize(c->stream));
@@ -1096,113 +965,12 @@ sbx_status sbx_count_live(sbx_ctx* c, int64_t* live) {
   }
   SBX_TRY(set_device(c->cfg.device));
   std::vector<uint8_t> l((size_t)c->n);
-  SBX_HIP(hipMemcpyAsync(l.data(), c->lost, c->n, hipMemcpyDeviceToHost, c->stream));
+  SBX_HIP(hipMemcpyAsync(l.data(), c->set[c->cur].lost, c->n, hipMemcpyDeviceToHost, c->stream));
   SBX_HIP(hipStreamSynchronize(c->stream));
   int64_t k = 0;
   for (uint8_t b : l) k += b ? 0 : 1;
   *live = k;
   return SBX_OK;
 }
-
-// ------------------------------------------------------- Poisson plans -----
-sbx_status sbx_poisson_create(int32_t n, double R, double q, double G, int32_t h0_mode, int32_t prec,
-                              int32_t device, void* stream, sbx_poisson** out) {
-  if (!out || !is_pow2_grid(n) || !(R > 0.0) || !(q > 0.0) || !(q <= 1.0) || !(G > 0.0) ||
-      (h0_mode != 0 && h0_mode != 2) || (prec != SBX_FP32 && prec != SBX_FP64)) {
-    set_error("bad Poisson plan arguments");
-    return SBX_EINVAL;
-  }
-  *out = nullptr;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
-    (void)hipGetLastError();
-    set_error("no HIP device available");
-    return SBX_EDEVICE;
-  }
-  SBX_TRY(set_device(device));
-  sbx_poisson* p = new (std::nothrow) sbx_poisson();
-  if (!p) return SBX_ENOMEM;
-  p->N = n;
-  p->prec = prec;
-  p->device = device;
-  p->geo = sbx_level{n, R, q};
-  p->G = G;
-  if (stream) {
-    p->stream = (hipStream_t)stream;
-  } else {
-    if (hipStreamCreate(&p->stream) != hipSuccess) {
-      delete p;
-      set_error("hipStreamCreate failed");
-      return SBX_EDEVICE;
-    }
-    p->own_stream = true;
-  }
-  const size_t es = prec == SBX_FP64 ? 8 : 4;
-  sbx_status rc = dev_alloc(&p->H, h_elems(n) * es);
-  if (rc == SBX_OK) {
-    const LevelDev L = make_level(p->geo);
-    rc = prec == SBX_FP64 ? build_green<double>(n, L.l, L.lz, G, h0_mode, (double*)p->H, &p->rel_imag, p->stream)
-                          : build_green<float>(n, L.l, L.lz, G, h0_mode, (float*)p->H, &p->rel_imag, p->stream);
-  }
-  if (rc != SBX_OK) {
-    sbx_poisson_destroy(p);
-    return rc;
-  }
-  p->bytes = (int64_t)(h_elems(n) * es);
-  *out = p;
-  return SBX_OK;
-}
-
-void sbx_poisson_destroy(sbx_poisson* p) {
-  if (!p) return;
-  (void)hipSetDevice(p->device);
-  if (p->stream) (void)hipStreamSynchronize(p->stream);
-  for (auto* q : p->plans) {
-    plan_destroy(q->p32);
-    plan_destroy(q->p64);
-    delete q;
-  }
-  p->plans.clear();
-  free_ptr(p->H);
-  free_ptr(p->X);
-  free_ptr(p->C);
-  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
-  delete p;
-}
-
-sbx_status sbx_poisson_solve(sbx_poisson* p, int32_t batch, const void* rho, void* phi) {
-  if (!p || !rho || !phi || batch <= 0 || batch > 64) {
-    set_error("bad Poisson solve arguments");
-    return SBX_EINVAL;
-  }
-  SBX_TRY(set_device(p->device));
-  return p->prec == SBX_FP64 ? poisson_solve_t<double>(p, batch, rho, phi)
-                             : poisson_solve_t<float>(p, batch, rho, phi);
-}
-
-sbx_status sbx_poisson_green(sbx_poisson* p, double* out, double* rel_imag) {
-  if (!p || !out) {
-    set_error("null argument");
-    return SBX_EINVAL;
-  }
-  SBX_TRY(set_device(p->device));
-  const size_t n = h_elems(p->N);
-  double* stage = nullptr;
-  SBX_TRY(dev_alloc((void**)&stage, n * sizeof(double)));
-  sbx_status rc = p->prec == SBX_FP64 ? launch_convert_out<double>((double*)p->H, stage, n, p->stream)
-                                      : launch_convert_out<float>((float*)p->H, stage, n, p->stream);
-  if (rc == SBX_OK) {
-    if (hipMemcpyAsync(out, stage, n * sizeof(double), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
-        hipStreamSynchronize(p->stream) != hipSuccess) {
-      set_error("copy of the Green's table failed");
-      rc = SBX_EDEVICE;
-    }
-  }
-  (void)hipFree(stage);
-  if (rel_imag) *rel_imag = p->rel_imag;
-  return rc;
-}
-
-int64_t sbx_poisson_bytes(sbx_poisson* p) { return p ? p->bytes : 0; }
 
 }  // extern "C"

@@ -1,13 +1,20 @@
 // Particle-side kernels of the nested-grid PM step (host interface).
+//
+// Every launch covers a set of independent instances (a context is one
+// instance; a batch of contexts is several) described by a device array of
+// InstDev records; instance i owns the blocks [span.start[i], span.start[i+1]).
 #pragma once
+
+#include <vector>
 
 #include "common.h"
 
 namespace sbx {
 
-constexpr int kMaxGal = 4;       // galaxies per context
+constexpr int kMaxGal = 4;       // galaxies per instance
 constexpr int kSlots = 5;        // grids per 3-level galaxy
 constexpr int kNComp = 8;        // particle component ids
+constexpr int kMaxInst = 32;     // instances per launch
 // diagnostics record: per component [ekin, epot, Lx, Ly, Lz, count],
 // disc [sum vR, sum vR^2, sum vz, sum vz^2, count], lost count
 constexpr int kDiagComp = 6;
@@ -15,8 +22,9 @@ constexpr int kDiagDisc = kNComp * kDiagComp;
 constexpr int kDiagLost = kDiagDisc + 5;
 constexpr int kNDiag = kDiagLost + 1;
 constexpr int kPreVals = kMaxGal * 4;  // per galaxy [m, m x, m y, m z]
-constexpr int kRedBlocks = 1024;       // grid of the loss-test / centre-of-mass pass
-constexpr int kForceBlocksMax = 4096;  // grid cap of the force pass (partial rows)
+constexpr int kRedBlocks = 1024;       // blocks per instance of the loss-test / COM pass
+constexpr int kForceBlocksMax = 4096;  // blocks per instance of the force pass
+constexpr int kDepChunk = 4096;        // particles per block of the mass assignment
 
 // One grid geometry as the kernels use it (all float64, computed on the host
 // exactly as the method's formulas read: l = 2R/(N-4), lz = q l, gamma = 1/l).
@@ -66,28 +74,76 @@ struct GridsDev {
 };
 
 template <typename T>
-sbx_status launch_zero(T* p, size_t n, hipStream_t s);
+struct InstDev {
+  PartDev<T> p[2];          // two particle sets; cur[i] selects the live one
+  SysDev sys;
+  GridsDev<T> G;
+  double* centres;          // 3 * kMaxGal
+  double* com_partial;      // force_blocks(n) rows of kPreVals
+  double* pre_partial;      // kRedBlocks rows of kPreVals, then kPreVals sums
+  double* diag_partial;     // force_blocks(n) rows of kNDiag
+  double* diag_out;         // kNDiag: where the next diagnostics record goes
+  double* acc;              // n * 3 (write mode)
+  double* pot;              // n (write mode, physical potential)
+  T* grid_block;            // all grids of the instance, back to back
+  size_t grid_elems;
+  uint32_t* key;            // n
+  uint32_t* count;          // bins + 1: this instance's slice of the shared counts
+  uint32_t part_base;       // sort position of the instance's first particle
+  double dt;
+  int64_t n;
+};
 
-// Loss test at the current positions plus centre-of-mass partial sums
-// (kRedBlocks rows of kPreVals into partial), then the centres.
-template <typename T>
-sbx_status launch_pre(const PartDev<T>& p, const SysDev& sys, double* partial, double* centres,
-                      hipStream_t s);
+// Host-side facts the launchers need to shape a multi-instance grid.
+struct InstInfo {
+  int64_t n;
+  size_t grid_elems;
+};
 
-// Centres from centre-of-mass partial sums (rows x kPreVals) written by the
-// previous moving force pass; `sums` receives the kPreVals column totals.
-sbx_status launch_centres(const double* partial, int rows, const SysDev& sys, double* sums,
-                          double* centres, hipStream_t s);
+struct Span {
+  int ninst;
+  int start[kMaxInst + 1];
+};
 
 int force_blocks(int64_t n);
 
-// Counting sort of the particles by the cell of their finest grid (relative
-// to their own galaxy): src -> dst.  key: n uint32; count: bins + 1 uint32
-// (bins = ngal * 3 * N^3); tmp: scan_tmp_elems(bins + 1).
 template <typename T>
-sbx_status launch_sort(const PartDev<T>& src, const PartDev<T>& dst, const SysDev& sys,
-                       const double* centres, uint32_t* key, uint32_t* count, size_t bins,
-                       uint32_t* tmp, hipStream_t s);
+sbx_status launch_zero(T* p, size_t n, hipStream_t s);
+
+// Zero every grid of every instance.
+template <typename T>
+sbx_status launch_zero_grids(const InstDev<T>* inst, const std::vector<InstInfo>& info, hipStream_t s);
+
+// Loss test at the current positions and centre-of-mass sums (pre_partial),
+// then the centres; with from_com the centres come from the sums the last
+// moving force pass left in com_partial instead (no particle pass).
+template <typename T>
+sbx_status launch_centres(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,
+                          bool from_com, hipStream_t s);
+
+template <typename T>
+sbx_status launch_deposit(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,
+                          hipStream_t s);
+
+// mode bits: 1 = move (kick + drift + loss test; centre-of-mass sums of the
+// new positions into com_partial), 2 = write acc/pot, 4 = diagnostics record
+// into diag_out.
+template <typename T>
+sbx_status launch_force(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,
+                        int mode, hipStream_t s);
+
+// Counting sort of every instance's particles by the cell of their finest
+// grid (relative to their own galaxy) from set cur to set cur^1, then flips
+// cur.  counts: the shared count buffer (sum of bins + 1 over instances),
+// tmp: scan_tmp_elems(total counts).
+template <typename T>
+sbx_status launch_sort(const InstDev<T>* inst, int* cur, const std::vector<InstInfo>& info,
+                       uint32_t* counts, size_t total_counts, uint32_t* tmp, hipStream_t s);
+
+// single-instance helpers
+template <typename T>
+sbx_status launch_indices(const InstDev<T>* inst, const int* cur, int64_t n, int galaxy, int level,
+                          int32_t* idx, int8_t* cls, hipStream_t s);
 
 sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s);
 
@@ -95,24 +151,6 @@ sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s);
 template <typename A>
 sbx_status launch_unpermute(const A* src, const int32_t* id, A* dst, int64_t n, int width,
                             hipStream_t s);
-
-template <typename T>
-sbx_status launch_deposit(const PartDev<T>& p, const SysDev& sys, const double* centres,
-                          const GridsDev<T>& grids, hipStream_t s);
-
-// mode bits: 1 = move (kick + drift + loss test; centre-of-mass partial sums
-// of the new positions into com_partial, force_blocks(n) rows of kPreVals),
-// 2 = write acc/pot (float64, acc n*3 row-major, pot = physical phi),
-// 4 = diagnostics record into diag_out (kNDiag doubles) via partial
-// (force_blocks(n) rows of kNDiag).
-template <typename T>
-sbx_status launch_force(const PartDev<T>& p, const SysDev& sys, const double* centres,
-                        const GridsDev<T>& fields, double dt, int mode, double* acc, double* pot,
-                        double* partial, double* diag_out, double* com_partial, hipStream_t s);
-
-template <typename T>
-sbx_status launch_indices(const PartDev<T>& p, const SysDev& sys, const double* centres, int galaxy,
-                          int level, int32_t* idx, int8_t* cls, hipStream_t s);
 
 template <typename T>
 sbx_status launch_convert_in(const double* src, T* dst, size_t n, hipStream_t s);

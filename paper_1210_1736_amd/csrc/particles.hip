@@ -1,7 +1,8 @@
 // Particle-side kernels: loss test and centre of mass, classification and
 // nearest-grid-point mass assignment, the Eq. 8 force with the grid-selection
-// rule fused with the leapfrog kick and drift (Eq. 6), and the FP64
-// diagnostic reductions.
+// rule fused with the leapfrog kick and drift (Eq. 6), the FP64 diagnostic
+// reductions and the cell sort.  Every kernel serves a set of instances
+// through a device table (see particles.h).
 //
 // Cell indices and classes are integers decided by float64 arithmetic with
 // every operation rounded separately (no fused multiply-add), so that any
@@ -113,73 +114,7 @@ __device__ __forceinline__ void block_sum_store(const double* vals, double* out,
     out[k] = k < nv ? ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k] : 0.0;
 }
 
-// out[k] = sum over rows of partial[row * nv + k]; block k, 256 threads, a
-// fixed summation order (strided per thread, then a fixed tree).
-__global__ void __launch_bounds__(256)
-    k_reduce_cols(const double* __restrict__ partial, int nrows, int nv, double* __restrict__ out) {
-  __shared__ double red[256];
-  const int k = blockIdx.x;
-  double s = 0.0;
-  for (int r = threadIdx.x; r < nrows; r += 256) s += partial[(size_t)r * nv + k];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[k] = red[0];
-}
 
-// ------------------------------------------------------ loss test and COM --
-template <typename T>
-__global__ void __launch_bounds__(256)
-    k_pre(PartDev<T> p, SysDev sys, double* __restrict__ partial) {
-  double acc[kPreVals];
-#pragma unroll
-  for (int k = 0; k < kPreVals; ++k) acc[k] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
-    if (p.lost[i]) continue;
-    const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
-    if (outside_global(sys, x, y, z)) {
-      p.lost[i] = 1;
-      continue;
-    }
-    const int g = p.gal[i];
-#pragma unroll
-    for (int gg = 0; gg < kMaxGal; ++gg) {
-      if (gg == g && sys.h[gg].centring == SBX_CENTRE_COM) {
-        const double m = (double)p.m[i];
-        acc[4 * gg + 0] += m;
-        acc[4 * gg + 1] += m * x;
-        acc[4 * gg + 2] += m * y;
-        acc[4 * gg + 3] += m * z;
-      }
-    }
-  }
-  block_sum_store<kPreVals>(acc, partial + (size_t)blockIdx.x * kPreVals, 4 * sys.ngal);
-}
-
-__global__ void k_centres(const double* __restrict__ sums, SysDev sys, double* __restrict__ centres) {
-  const int g = threadIdx.x;
-  if (g >= sys.ngal) return;
-  const HierDev& h = sys.h[g];
-  double c[3] = {h.centre[0], h.centre[1], h.centre[2]};
-  if (h.centring == SBX_CENTRE_COM && sums[4 * g] > 0.0) {
-    c[0] = sums[4 * g + 1] / sums[4 * g];
-    c[1] = sums[4 * g + 2] / sums[4 * g];
-    c[2] = sums[4 * g + 3] / sums[4 * g];
-  }
-  centres[3 * g + 0] = c[0];
-  centres[3 * g + 1] = c[1];
-  centres[3 * g + 2] = c[2];
-}
-
-// ---------------------------------------------------------- mass deposit --
-template <typename T>
-__device__ __forceinline__ T* cell_ptr(T* grid, const LevelDev& L, const int* i) {
-  return grid + ((size_t)i[2] * L.N + i[1]) * L.N + i[0];
-}
 
 // Segmented sum over runs of equal keys in consecutive lanes: returns, in the
 // last lane of each run (tail = true), the run's total.  All 64 lanes call it.
@@ -211,102 +146,6 @@ __device__ __forceinline__ uint32_t dep_key(int g, int slot, const LevelDev& L, 
          (uint32_t)(((i[2] * L.N) + i[1]) * L.N + i[0]);
 }
 
-// LDS-binned mass assignment.  Each block takes a contiguous chunk of the
-// (cell-sorted) particles; the three deposits of every particle are first
-// combined across lanes of a wavefront that hit the same cell (segmented
-// wave sum), then accumulated in an LDS hash table of the block's cells, and
-// finally flushed with one global atomic add per distinct cell.  Targets that
-// find no free LDS entry within a few probes go straight to global memory.
-//
-// Sources of the five grids (Sec. 2.1): core -> grid 1, grid 2, grid 4;
-// ring -> grid 3, grid 4; outer -> grid 5.  Grids 2+3 and 4+5 are assigned
-// as sums directly (their potentials are only used summed, and the solve is
-// linear).  Round 0 = the finest grid of the class, round 1 = middle (2+3)
-// or global (4+5), round 2 = global (4+5).
-constexpr int kDepChunk = 4096;     // particles per block
-constexpr int kDepTable = 4096;     // LDS hash entries (power of two)
-constexpr int kDepProbes = 8;
-
-template <typename T>
-__device__ __forceinline__ T* slot_ptr(const GridsDev<T>& G, const SysDev& sys, uint32_t key) {
-  const int gs = (int)(key >> 24);
-  const int g = gs / kSlots, slot = gs - g * kSlots;
-  return G.g[g][slot] + (key & 0xFFFFFFu);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256)
-    k_deposit(PartDev<T> p, SysDev sys_arg, const double* __restrict__ centres, GridsDev<T> G_arg) {
-  __shared__ uint32_t tkey[kDepTable];
-  __shared__ T tval[kDepTable];
-  // per-galaxy data staged in LDS: lanes index it by their own galaxy
-  __shared__ SysDev sys;
-  __shared__ GridsDev<T> G;
-  __shared__ double cen[3 * kMaxGal];
-  if (threadIdx.x == 0) {
-    sys = sys_arg;
-    G = G_arg;
-  }
-  if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = threadIdx.x < 3 * sys_arg.ngal ? centres[threadIdx.x] : 0.0;
-  for (int k = threadIdx.x; k < kDepTable; k += 256) {
-    tkey[k] = kNoKey;
-    tval[k] = (T)0;
-  }
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kDepChunk;
-  for (int j = 0; j < kDepChunk / 256; ++j) {
-    const int64_t i = base + j * 256 + threadIdx.x;
-    uint32_t k0 = kNoKey, k1 = kNoKey, k2 = kNoKey;
-    T m = (T)0;
-    if (i < p.n && !p.lost[i]) {
-      const int g = p.gal[i];
-      const HierDev& h = sys.h[g];
-      const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
-      Classified c;
-      classify(h, cen + 3 * g, x, y, z, c);
-      m = p.m[i];
-      if (h.n_levels == 1) {
-        if (c.cls == SBX_OUTER) k0 = dep_key(g, 0, h.lv[0], c.idx[0]);
-      } else if (c.cls == SBX_CORE) {
-        k0 = dep_key(g, 0, h.lv[0], c.idx[0]);   // grid 1
-        k1 = dep_key(g, 2, h.lv[1], c.idx[1]);   // grid 2 (in 2+3)
-        k2 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 4 (in 4+5)
-      } else if (c.cls == SBX_RING) {
-        k0 = dep_key(g, 1, h.lv[1], c.idx[1]);   // grid 3
-        k1 = dep_key(g, 2, h.lv[1], c.idx[1]);   // grid 3 (in 2+3)
-        k2 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 4 (in 4+5)
-      } else if (c.cls == SBX_OUTER) {
-        k0 = dep_key(g, 3, h.lv[2], c.idx[2]);   // grid 5
-        k1 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 5 (in 4+5)
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const uint32_t key = r == 0 ? k0 : (r == 1 ? k1 : k2);
-      bool tail;
-      const T s = wave_run_sum(key, m, tail);
-      if (tail && key != kNoKey) {
-        uint32_t hslot = (key * 2654435761u) >> (32 - 12);
-        bool done = false;
-        for (int q = 0; q < kDepProbes && !done; ++q) {
-          const uint32_t old = atomicCAS(tkey + hslot, kNoKey, key);
-          if (old == kNoKey || old == key) {
-            atomicAdd(tval + hslot, s);
-            done = true;
-          } else {
-            hslot = (hslot + 1) & (kDepTable - 1);
-          }
-        }
-        if (!done) unsafeAtomicAdd(slot_ptr(G, sys, key), s);
-      }
-    }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < kDepTable; k += 256) {
-    const uint32_t key = tkey[k];
-    if (key != kNoKey) unsafeAtomicAdd(slot_ptr(G, sys, key), tval[k]);
-  }
-}
 
 // ------------------------------------------------------------------ Eq. 8 --
 // Acceleration (+grad Phi) and Phi at the particle from one field on one
@@ -385,13 +224,249 @@ __device__ __forceinline__ void particle_field(const SysDev& sys, const double* 
   }
 }
 
+
+// Rows of the force pass partials (mirrors force_blocks on the host).
+__device__ __forceinline__ int force_blocks_dev(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > kForceBlocksMax ? kForceBlocksMax : b));
+}
+
+
+// ------------------------------------------------------------- instances --
+__device__ __forceinline__ int span_inst(const Span& sp, int b) {
+  int i = 0;
+  while (i + 1 < sp.ninst && sp.start[i + 1] <= b) ++i;
+  return i;
+}
+
+// Copy a trivially copyable record into LDS with the whole block.
+template <typename R>
+__device__ __forceinline__ void stage(R* dst, const R* src) {
+  static_assert(sizeof(R) % 4 == 0, "word copy");
+  const uint32_t* s = (const uint32_t*)src;
+  uint32_t* d = (uint32_t*)dst;
+  for (int k = threadIdx.x; k < (int)(sizeof(R) / 4); k += blockDim.x) d[k] = s[k];
+}
+
+static Span make_span(const std::vector<InstInfo>& info, int64_t (*blocks)(const InstInfo&)) {
+  Span sp;
+  sp.ninst = (int)info.size();
+  sp.start[0] = 0;
+  for (int i = 0; i < sp.ninst; ++i) sp.start[i + 1] = sp.start[i] + (int)blocks(info[i]);
+  return sp;
+}
+
+int force_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > kForceBlocksMax ? kForceBlocksMax : b));
+}
+
+static int64_t blocks_particles(const InstInfo& f) { return f.n > 0 ? (f.n + 255) / 256 : 1; }
+static int64_t blocks_force(const InstInfo& f) { return force_blocks(f.n); }
+static int64_t blocks_deposit(const InstInfo& f) { return f.n > 0 ? (f.n + kDepChunk - 1) / kDepChunk : 1; }
+static int64_t blocks_red(const InstInfo&) { return kRedBlocks; }
+static int64_t blocks_grid(const InstInfo& f) {
+  const int64_t b = (int64_t)((f.grid_elems + 1023) / 1024);
+  return b < 1 ? 1 : (b > 2048 ? 2048 : b);
+}
+
+// ------------------------------------------------------------ zero grids --
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_grids(const InstDev<T>* __restrict__ inst, Span sp) {
+  const int i = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[i], nb = sp.start[i + 1] - sp.start[i];
+  T* g = inst[i].grid_block;
+  const size_t n = inst[i].grid_elems;
+  for (size_t k = (size_t)lb * 256 + threadIdx.x; k < n; k += (size_t)nb * 256) g[k] = (T)0;
+}
+
+// ------------------------------------------------------ loss test and COM --
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_pre(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  const int ii = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
+  const InstDev<T>& I = inst[ii];
+  const PartDev<T> p = I.p[cur[ii]];
+  const SysDev& sys = I.sys;
+  double acc[kPreVals];
+#pragma unroll
+  for (int k = 0; k < kPreVals; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)nb * blockDim.x;
+  for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+    if (p.lost[i]) continue;
+    const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+    if (outside_global(sys, x, y, z)) {
+      p.lost[i] = 1;
+      continue;
+    }
+    const int g = p.gal[i];
+#pragma unroll
+    for (int gg = 0; gg < kMaxGal; ++gg) {
+      if (gg == g && sys.h[gg].centring == SBX_CENTRE_COM) {
+        const double m = (double)p.m[i];
+        acc[4 * gg + 0] += m;
+        acc[4 * gg + 1] += m * x;
+        acc[4 * gg + 2] += m * y;
+        acc[4 * gg + 3] += m * z;
+      }
+    }
+  }
+  block_sum_store<kPreVals>(acc, I.pre_partial + (size_t)lb * kPreVals, 4 * sys.ngal);
+}
+
+// One block per instance: column sums of the partial rows (fixed order:
+// strided per thread, then a fixed tree), then the centres.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_centres(const InstDev<T>* __restrict__ inst, int from_com) {
+  __shared__ double red[256];
+  __shared__ double sums[kPreVals];
+  const InstDev<T>& I = inst[blockIdx.x];
+  const double* part = from_com ? I.com_partial : I.pre_partial;
+  const int rows = from_com ? force_blocks_dev(I.n) : kRedBlocks;
+  const int nv = 4 * I.sys.ngal;
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    for (int r = threadIdx.x; r < rows; r += 256) s += part[(size_t)r * kPreVals + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[v] = red[0];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < I.sys.ngal) {
+    const int g = threadIdx.x;
+    const HierDev& h = I.sys.h[g];
+    double c[3] = {h.centre[0], h.centre[1], h.centre[2]};
+    if (h.centring == SBX_CENTRE_COM && sums[4 * g] > 0.0) {
+      c[0] = sums[4 * g + 1] / sums[4 * g];
+      c[1] = sums[4 * g + 2] / sums[4 * g];
+      c[2] = sums[4 * g + 3] / sums[4 * g];
+    }
+    I.centres[3 * g + 0] = c[0];
+    I.centres[3 * g + 1] = c[1];
+    I.centres[3 * g + 2] = c[2];
+  }
+}
+
+// ---------------------------------------------------------- mass deposit --
+// LDS-binned mass assignment.  Each block takes a contiguous chunk of the
+// (cell-sorted) particles; the three deposits of every particle are first
+// combined across lanes of a wavefront that hit the same cell (segmented
+// wave sum), then accumulated in an LDS hash table of the block's cells, and
+// finally flushed with one global atomic add per distinct cell.  Targets that
+// find no free LDS entry within a few probes go straight to global memory.
+//
+// Sources of the five grids (Sec. 2.1): core -> grid 1, grid 2, grid 4;
+// ring -> grid 3, grid 4; outer -> grid 5.  Grids 2+3 and 4+5 are assigned
+// as sums directly (their potentials are only used summed, and the solve is
+// linear).  Round 0 = the finest grid of the class, round 1 = middle (2+3)
+// or global (4+5), round 2 = global (4+5).
+constexpr int kDepTable = 4096;     // LDS hash entries (power of two)
+constexpr int kDepProbes = 8;
+
+template <typename T>
+__device__ __forceinline__ T* slot_ptr(const GridsDev<T>& G, uint32_t key) {
+  const int gs = (int)(key >> 24);
+  const int g = gs / kSlots, slot = gs - g * kSlots;
+  return G.g[g][slot] + (key & 0xFFFFFFu);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_deposit(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  __shared__ uint32_t tkey[kDepTable];
+  __shared__ T tval[kDepTable];
+  // per-galaxy data staged in LDS: lanes index it by their own galaxy
+  __shared__ SysDev sys;
+  __shared__ GridsDev<T> G;
+  __shared__ double cen[3 * kMaxGal];
+  const int ii = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[ii];
+  const InstDev<T>& I = inst[ii];
+  const PartDev<T> p = I.p[cur[ii]];
+  stage(&sys, &I.sys);
+  stage(&G, &I.G);
+  if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = I.centres[threadIdx.x];
+  for (int k = threadIdx.x; k < kDepTable; k += 256) {
+    tkey[k] = kNoKey;
+    tval[k] = (T)0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)lb * kDepChunk;
+  for (int j = 0; j < kDepChunk / 256; ++j) {
+    const int64_t i = base + j * 256 + threadIdx.x;
+    uint32_t k0 = kNoKey, k1 = kNoKey, k2 = kNoKey;
+    T m = (T)0;
+    if (i < p.n && !p.lost[i]) {
+      const int g = p.gal[i];
+      const HierDev& h = sys.h[g];
+      const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+      Classified c;
+      classify(h, cen + 3 * g, x, y, z, c);
+      m = p.m[i];
+      if (h.n_levels == 1) {
+        if (c.cls == SBX_OUTER) k0 = dep_key(g, 0, h.lv[0], c.idx[0]);
+      } else if (c.cls == SBX_CORE) {
+        k0 = dep_key(g, 0, h.lv[0], c.idx[0]);   // grid 1
+        k1 = dep_key(g, 2, h.lv[1], c.idx[1]);   // grid 2 (in 2+3)
+        k2 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 4 (in 4+5)
+      } else if (c.cls == SBX_RING) {
+        k0 = dep_key(g, 1, h.lv[1], c.idx[1]);   // grid 3
+        k1 = dep_key(g, 2, h.lv[1], c.idx[1]);   // grid 3 (in 2+3)
+        k2 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 4 (in 4+5)
+      } else if (c.cls == SBX_OUTER) {
+        k0 = dep_key(g, 3, h.lv[2], c.idx[2]);   // grid 5
+        k1 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 5 (in 4+5)
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const uint32_t key = r == 0 ? k0 : (r == 1 ? k1 : k2);
+      bool tail;
+      const T s = wave_run_sum(key, m, tail);
+      if (tail && key != kNoKey) {
+        uint32_t hslot = (key * 2654435761u) >> (32 - 12);
+        bool done = false;
+        for (int q = 0; q < kDepProbes && !done; ++q) {
+          const uint32_t old = atomicCAS(tkey + hslot, kNoKey, key);
+          if (old == kNoKey || old == key) {
+            atomicAdd(tval + hslot, s);
+            done = true;
+          } else {
+            hslot = (hslot + 1) & (kDepTable - 1);
+          }
+        }
+        if (!done) unsafeAtomicAdd(slot_ptr(G, key), s);
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kDepTable; k += 256) {
+    const uint32_t key = tkey[k];
+    if (key != kNoKey) unsafeAtomicAdd(slot_ptr(G, key), tval[k]);
+  }
+}
+
+// ----------------------------------------------------------- force + move --
 // MODE bits: 1 move, 2 write acc/pot, 4 diagnostics
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256)
-    k_force(PartDev<T> p, SysDev sys, const double* __restrict__ centres, GridsDev<T> F, T dt,
-            double dtd, double* __restrict__ acc_out, double* __restrict__ pot_out,
-            double* __restrict__ partial, double* __restrict__ com_partial) {
+    k_force(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
   constexpr bool MOVE = MODE & 1, OUT = MODE & 2, DIAG = MODE & 4;
+  const int ii = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
+  const InstDev<T>& I = inst[ii];
+  const PartDev<T> p = I.p[cur[ii]];
+  const SysDev& sys = I.sys;
+  const GridsDev<T>& F = I.G;
+  const double* __restrict__ centres = I.centres;
+  const T dt = (T)I.dt;
+  const double dtd = I.dt;
   double dg[DIAG ? kNDiag : 1];
   if constexpr (DIAG) {
     for (int k = 0; k < kNDiag; ++k) dg[k] = 0.0;
@@ -401,12 +476,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int k = 0; k < kPreVals; ++k) com[k] = 0.0;
   }
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+  const int64_t stride = (int64_t)nb * blockDim.x;
+  for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i < p.n; i += stride) {
     if (p.lost[i]) {
       if constexpr (OUT) {
-        acc_out[3 * i] = acc_out[3 * i + 1] = acc_out[3 * i + 2] = 0.0;
-        pot_out[i] = 0.0;
+        I.acc[3 * i] = I.acc[3 * i + 1] = I.acc[3 * i + 2] = 0.0;
+        I.pot[i] = 0.0;
       }
       if constexpr (DIAG) dg[kDiagLost] += 1.0;
       continue;
@@ -417,10 +492,10 @@ __global__ void __launch_bounds__(256)
     T phi = (T)0;
     particle_field(sys, centres, F, x, y, z, a, phi, OUT || DIAG);
     if constexpr (OUT) {
-      acc_out[3 * i] = (double)a[0];
-      acc_out[3 * i + 1] = (double)a[1];
-      acc_out[3 * i + 2] = (double)a[2];
-      pot_out[i] = -(double)phi;
+      I.acc[3 * i] = (double)a[0];
+      I.acc[3 * i + 1] = (double)a[1];
+      I.acc[3 * i + 2] = (double)a[2];
+      I.pot[i] = -(double)phi;
     }
     if constexpr (DIAG) {
       const double m = (double)p.m[i];
@@ -476,21 +551,129 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  if constexpr (DIAG) block_sum_store<kNDiag>(dg, partial + (size_t)blockIdx.x * kNDiag);
+  if constexpr (DIAG) block_sum_store<kNDiag>(dg, I.diag_partial + (size_t)lb * kNDiag);
   if constexpr (MOVE) {
     if constexpr (DIAG) __syncthreads();
-    block_sum_store<kPreVals>(com, com_partial + (size_t)blockIdx.x * kPreVals, 4 * sys.ngal);
+    block_sum_store<kPreVals>(com, I.com_partial + (size_t)lb * kPreVals, 4 * sys.ngal);
   }
+}
+
+// One block per (value, instance): column sum of the diagnostics partials.
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag_final(const InstDev<T>* __restrict__ inst) {
+  __shared__ double red[256];
+  const InstDev<T>& I = inst[blockIdx.y];
+  const int v = blockIdx.x;
+  const int rows = force_blocks_dev(I.n);
+  double s = 0.0;
+  for (int r = threadIdx.x; r < rows; r += 256) s += I.diag_partial[(size_t)r * kNDiag + v];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) I.diag_out[v] = red[0];
+}
+
+// ------------------------------------------------------------ cell sort ---
+// Key: cell of the particle's finest grid (relative to its own galaxy),
+// bins ordered by galaxy, then class level, then z, y, x; lost particles in
+// the last bin.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_sort_key(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  __shared__ SysDev sys;
+  __shared__ double cen[3 * kMaxGal];
+  const int ii = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[ii];
+  const InstDev<T>& I = inst[ii];
+  const PartDev<T> p = I.p[cur[ii]];
+  stage(&sys, &I.sys);
+  if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = I.centres[threadIdx.x];
+  __syncthreads();
+  const int N0 = sys.h[0].lv[0].N;
+  const uint32_t lost_bin = (uint32_t)((size_t)sys.ngal * 3 * N0 * N0 * N0);
+  const int64_t i = (int64_t)lb * 256 + threadIdx.x;
+  uint32_t k = kNoKey;  // lanes past the end keep a key of their own
+  if (i < p.n) {
+    k = lost_bin;
+    if (!p.lost[i]) {
+      const int g = p.gal[i];
+      const HierDev& h = sys.h[g];
+      Classified c;
+      classify(h, cen + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
+      if (c.cls != SBX_LOST) {
+        const int lev = h.n_levels == 1 ? 0 : c.cls;
+        const int N = h.lv[0].N;
+        const int* id = lev == 0 ? c.idx[0] : (lev == 1 ? c.idx[1] : c.idx[2]);
+        k = (uint32_t)((((size_t)(g * 3 + lev) * N + id[2]) * N + id[1]) * N + id[0]);
+      }
+    }
+    I.key[i] = k;
+  }
+  // every lane takes part in the wave sum (no divergent shuffles)
+  bool tail;
+  const uint32_t run = wave_run_sum<uint32_t>(k, 1u, tail);
+  if (tail && k != kNoKey) atomicAdd(I.count + k, run);
+}
+
+// Slots are reserved per run of equal keys in a wavefront: the run's last
+// lane reserves the whole run with one atomic add, the others take the
+// following slots in lane order.  Offsets are global (all instances' counts
+// scanned together); part_base turns them into the instance's own slots.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_sort_scatter(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  const int ii = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[ii];
+  const InstDev<T>& I = inst[ii];
+  const int c0 = cur[ii];
+  const PartDev<T> s = I.p[c0];
+  const PartDev<T> d = I.p[c0 ^ 1];
+  const int64_t i = (int64_t)lb * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint32_t k = i < s.n ? I.key[i] : kNoKey;
+  bool tail;
+  const uint32_t rank1 = wave_run_sum<uint32_t>(k, 1u, tail);  // 1-based rank in the run
+  uint32_t start = 0;
+  if (tail && k != kNoKey) start = atomicAdd(I.count + k, rank1);
+  // nearest tail at or after this lane: suffix minimum of tail lane ids
+  int tl = tail ? lane : 64;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t2 = __shfl_down(tl, o, 64);
+    if (lane + o < 64) tl = min(tl, t2);
+  }
+  const uint32_t run_start = __shfl(start, tl & 63, 64);
+  if (i >= s.n) return;
+  const uint32_t j = run_start + rank1 - 1 - I.part_base;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    d.x[q][j] = s.x[q][i];
+    d.v[q][j] = s.v[q][i];
+  }
+  d.m[j] = s.m[i];
+  d.comp[j] = s.comp[i];
+  d.gal[j] = s.gal[i];
+  d.lost[j] = s.lost[i];
+  d.id[j] = s.id[i];
+}
+
+__global__ void k_flip(int* cur, int n) {
+  if ((int)threadIdx.x < n) cur[threadIdx.x] ^= 1;
 }
 
 // ------------------------------------------------------------- readouts ---
 template <typename T>
-__global__ void k_indices(PartDev<T> p, SysDev sys, const double* __restrict__ centres, int g,
+__global__ void k_indices(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, int g,
                           int level, int32_t* __restrict__ idx, int8_t* __restrict__ cls) {
+  const InstDev<T>& I = inst[0];
+  const PartDev<T> p = I.p[cur[0]];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   Classified c;
-  classify(sys.h[g], centres + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
+  classify(I.sys.h[g], I.centres + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
   if (idx) {
     idx[3 * i] = c.idx[level][0];
     idx[3 * i + 1] = c.idx[level][1];
@@ -533,76 +716,6 @@ __global__ void k_join3(const T* x0, const T* x1, const T* x2, double* __restric
   }
 }
 
-// ------------------------------------------------------------ cell sort ---
-// Key: cell of the particle's finest grid (relative to its own galaxy),
-// bins ordered by galaxy, then class level, then z, y, x.
-template <typename T>
-__global__ void __launch_bounds__(256)
-    k_sort_key(PartDev<T> p, SysDev sys_arg, const double* __restrict__ centres,
-               uint32_t* __restrict__ key, uint32_t* __restrict__ count, uint32_t lost_bin) {
-  __shared__ SysDev sys;
-  if (threadIdx.x == 0) sys = sys_arg;
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t k = kNoKey;  // lanes past the end keep a key of their own
-  if (i < p.n) {
-    k = lost_bin;
-    if (!p.lost[i]) {
-      const int g = p.gal[i];
-      const HierDev& h = sys.h[g];
-      Classified c;
-      classify(h, centres + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
-      if (c.cls != SBX_LOST) {
-        const int lev = h.n_levels == 1 ? 0 : c.cls;
-        const int N = h.lv[0].N;
-        const int* id = lev == 0 ? c.idx[0] : (lev == 1 ? c.idx[1] : c.idx[2]);
-        k = (uint32_t)((((size_t)(g * 3 + lev) * N + id[2]) * N + id[1]) * N + id[0]);
-      }
-    }
-    key[i] = k;
-  }
-  // every lane takes part in the wave sum (no divergent shuffles)
-  bool tail;
-  const uint32_t run = wave_run_sum<uint32_t>(k, 1u, tail);
-  if (tail && k != kNoKey) atomicAdd(count + k, run);
-}
-
-// Slots are reserved per run of equal keys in a wavefront: the run's last
-// lane reserves the whole run with one atomic add, the others take the
-// following slots in lane order.
-template <typename T>
-__global__ void __launch_bounds__(256)
-    k_sort_scatter(PartDev<T> s, PartDev<T> d, const uint32_t* __restrict__ key,
-                   uint32_t* __restrict__ offs) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const uint32_t k = i < s.n ? key[i] : kNoKey;
-  bool tail;
-  const uint32_t rank1 = wave_run_sum<uint32_t>(k, 1u, tail);  // 1-based rank in the run
-  uint32_t start = 0;
-  if (tail && k != kNoKey) start = atomicAdd(offs + k, rank1);
-  // nearest tail at or after this lane: suffix minimum of tail lane ids
-  int tl = tail ? lane : 64;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t2 = __shfl_down(tl, o, 64);
-    if (lane + o < 64) tl = min(tl, t2);
-  }
-  const uint32_t run_start = __shfl(start, tl & 63, 64);
-  if (i >= s.n) return;
-  const uint32_t j = run_start + rank1 - 1;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    d.x[k][j] = s.x[k][i];
-    d.v[k][j] = s.v[k][i];
-  }
-  d.m[j] = s.m[i];
-  d.comp[j] = s.comp[i];
-  d.gal[j] = s.gal[i];
-  d.lost[j] = s.lost[i];
-  d.id[j] = s.id[i];
-}
-
 __global__ void k_iota(int32_t* id, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -620,11 +733,6 @@ __global__ void k_unpermute(const A* __restrict__ src, const int32_t* __restrict
 }
 
 // ------------------------------------------------------------- launchers --
-static inline unsigned blocks_for(int64_t n) {
-  int64_t b = (n + 255) / 256;
-  return (unsigned)(b < 1 ? 1 : b);
-}
-
 template <typename T>
 sbx_status launch_zero(T* p, size_t n, hipStream_t s) {
   hipLaunchKernelGGL((k_zero<T>), dim3(2048), dim3(256), 0, s, p, n);
@@ -632,38 +740,94 @@ sbx_status launch_zero(T* p, size_t n, hipStream_t s) {
   return SBX_OK;
 }
 
-int force_blocks(int64_t n) {
-  const int64_t b = (n + 255) / 256;
-  return (int)(b < 1 ? 1 : (b > kForceBlocksMax ? kForceBlocksMax : b));
+static sbx_status check_span(const std::vector<InstInfo>& info) {
+  if (info.empty() || (int)info.size() > kMaxInst) {
+    set_error("1 to 32 instances per launch");
+    return SBX_EINVAL;
+  }
+  return SBX_OK;
 }
 
-sbx_status launch_centres(const double* partial, int rows, const SysDev& sys, double* sums,
-                          double* centres, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_cols, dim3(kPreVals), dim3(256), 0, s, partial, rows, kPreVals, sums);
-  hipLaunchKernelGGL(k_centres, dim3(1), dim3(64), 0, s, sums, sys, centres);
+template <typename T>
+sbx_status launch_zero_grids(const InstDev<T>* inst, const std::vector<InstInfo>& info, hipStream_t s) {
+  SBX_TRY(check_span(info));
+  const Span sp = make_span(info, blocks_grid);
+  hipLaunchKernelGGL((k_zero_grids<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, sp);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
 
 template <typename T>
-sbx_status launch_pre(const PartDev<T>& p, const SysDev& sys, double* partial, double* centres,
-                      hipStream_t s) {
-  hipLaunchKernelGGL((k_pre<T>), dim3(kRedBlocks), dim3(256), 0, s, p, sys, partial);
+sbx_status launch_centres(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,
+                          bool from_com, hipStream_t s) {
+  SBX_TRY(check_span(info));
+  if (!from_com) {
+    const Span sp = make_span(info, blocks_red);
+    hipLaunchKernelGGL((k_pre<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
+  }
+  hipLaunchKernelGGL((k_centres<T>), dim3((unsigned)info.size()), dim3(256), 0, s, inst, from_com ? 1 : 0);
   SBX_HIP(hipGetLastError());
-  return launch_centres(partial, kRedBlocks, sys, partial + (size_t)kRedBlocks * kPreVals, centres, s);
+  return SBX_OK;
 }
 
 template <typename T>
-sbx_status launch_sort(const PartDev<T>& src, const PartDev<T>& dst, const SysDev& sys,
-                       const double* centres, uint32_t* key, uint32_t* count, size_t bins,
-                       uint32_t* tmp, hipStream_t s) {
-  if (src.n == 0) return SBX_OK;
-  SBX_TRY(launch_zero<uint32_t>(count, bins + 1, s));
-  hipLaunchKernelGGL((k_sort_key<T>), dim3(blocks_for(src.n)), dim3(256), 0, s, src, sys, centres, key,
-                     count, (uint32_t)bins);
+sbx_status launch_deposit(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,
+                          hipStream_t s) {
+  SBX_TRY(check_span(info));
+  const Span sp = make_span(info, blocks_deposit);
+  hipLaunchKernelGGL((k_deposit<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
   SBX_HIP(hipGetLastError());
-  SBX_TRY(exclusive_scan_u32(count, bins + 1, tmp, s));
-  hipLaunchKernelGGL((k_sort_scatter<T>), dim3(blocks_for(src.n)), dim3(256), 0, s, src, dst, key, count);
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_force(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,
+                        int mode, hipStream_t s) {
+  SBX_TRY(check_span(info));
+  const Span sp = make_span(info, blocks_force);
+  const dim3 g(sp.start[sp.ninst]), b(256);
+#define SBX_FORCE(M)                                                             \
+  case M:                                                                        \
+    hipLaunchKernelGGL((k_force<T, M>), g, b, 0, s, inst, cur, sp);             \
+    break;
+  switch (mode) {
+    SBX_FORCE(1)
+    SBX_FORCE(2)
+    SBX_FORCE(4)
+    SBX_FORCE(5)
+    SBX_FORCE(6)
+    default:
+      set_error("bad force mode");
+      return SBX_EINVAL;
+  }
+#undef SBX_FORCE
+  if (mode & 4)
+    hipLaunchKernelGGL((k_diag_final<T>), dim3(kNDiag, (unsigned)info.size()), dim3(256), 0, s, inst);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_sort(const InstDev<T>* inst, int* cur, const std::vector<InstInfo>& info,
+                       uint32_t* counts, size_t total_counts, uint32_t* tmp, hipStream_t s) {
+  SBX_TRY(check_span(info));
+  const Span sp = make_span(info, blocks_particles);
+  SBX_TRY(launch_zero<uint32_t>(counts, total_counts, s));
+  hipLaunchKernelGGL((k_sort_key<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
+  SBX_HIP(hipGetLastError());
+  SBX_TRY(exclusive_scan_u32(counts, total_counts, tmp, s));
+  hipLaunchKernelGGL((k_sort_scatter<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
+  hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, cur, (int)info.size());
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_indices(const InstDev<T>* inst, const int* cur, int64_t n, int galaxy, int level,
+                          int32_t* idx, int8_t* cls, hipStream_t s) {
+  if (n == 0) return SBX_OK;
+  hipLaunchKernelGGL((k_indices<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, inst, cur,
+                     galaxy, level, idx, cls);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
@@ -678,61 +842,6 @@ template <typename A>
 sbx_status launch_unpermute(const A* src, const int32_t* id, A* dst, int64_t n, int width,
                             hipStream_t s) {
   hipLaunchKernelGGL((k_unpermute<A>), dim3(2048), dim3(256), 0, s, src, id, dst, n, width);
-  SBX_HIP(hipGetLastError());
-  return SBX_OK;
-}
-
-template sbx_status launch_unpermute<double>(const double*, const int32_t*, double*, int64_t, int, hipStream_t);
-template sbx_status launch_unpermute<int32_t>(const int32_t*, const int32_t*, int32_t*, int64_t, int, hipStream_t);
-template sbx_status launch_unpermute<int8_t>(const int8_t*, const int32_t*, int8_t*, int64_t, int, hipStream_t);
-template sbx_status launch_unpermute<uint8_t>(const uint8_t*, const int32_t*, uint8_t*, int64_t, int, hipStream_t);
-
-template <typename T>
-sbx_status launch_deposit(const PartDev<T>& p, const SysDev& sys, const double* centres,
-                          const GridsDev<T>& grids, hipStream_t s) {
-  if (p.n == 0) return SBX_OK;
-  const unsigned nb = (unsigned)((p.n + kDepChunk - 1) / kDepChunk);
-  hipLaunchKernelGGL((k_deposit<T>), dim3(nb), dim3(256), 0, s, p, sys, centres, grids);
-  SBX_HIP(hipGetLastError());
-  return SBX_OK;
-}
-
-template <typename T>
-sbx_status launch_force(const PartDev<T>& p, const SysDev& sys, const double* centres,
-                        const GridsDev<T>& F, double dt, int mode, double* acc, double* pot,
-                        double* partial, double* diag_out, double* com_partial, hipStream_t s) {
-  const T dtt = (T)dt;
-  const dim3 b(256);
-  const int nb = force_blocks(p.n);
-  const dim3 g(nb);
-#define SBX_FORCE(M)                                                                          \
-  case M:                                                                                     \
-    hipLaunchKernelGGL((k_force<T, M>), g, b, 0, s, p, sys, centres, F, dtt, dt, acc, pot,   \
-                       partial, com_partial);                                                 \
-    break;
-  switch (mode) {
-    SBX_FORCE(1)
-    SBX_FORCE(2)
-    SBX_FORCE(4)
-    SBX_FORCE(5)
-    SBX_FORCE(6)
-    default:
-      set_error("bad force mode");
-      return SBX_EINVAL;
-  }
-#undef SBX_FORCE
-  if (mode & 4)
-    hipLaunchKernelGGL(k_reduce_cols, dim3(kNDiag), dim3(256), 0, s, partial, nb, kNDiag, diag_out);
-  SBX_HIP(hipGetLastError());
-  return SBX_OK;
-}
-
-template <typename T>
-sbx_status launch_indices(const PartDev<T>& p, const SysDev& sys, const double* centres, int galaxy,
-                          int level, int32_t* idx, int8_t* cls, hipStream_t s) {
-  if (p.n == 0) return SBX_OK;
-  hipLaunchKernelGGL((k_indices<T>), dim3(blocks_for(p.n)), dim3(256), 0, s, p, sys, centres, galaxy,
-                     level, idx, cls);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
@@ -768,25 +877,29 @@ sbx_status launch_join3(const T* x0, const T* x1, const T* x2, double* dst, int6
 
 #define SBX_INST(T)                                                                              \
   template sbx_status launch_zero<T>(T*, size_t, hipStream_t);                                   \
-  template sbx_status launch_pre<T>(const PartDev<T>&, const SysDev&, double*, double*,          \
-                                    hipStream_t);                                                \
-  template sbx_status launch_deposit<T>(const PartDev<T>&, const SysDev&, const double*,         \
-                                        const GridsDev<T>&, hipStream_t);                        \
-  template sbx_status launch_force<T>(const PartDev<T>&, const SysDev&, const double*,           \
-                                      const GridsDev<T>&, double, int, double*, double*,         \
-                                      double*, double*, double*, hipStream_t);                   \
-  template sbx_status launch_sort<T>(const PartDev<T>&, const PartDev<T>&, const SysDev&,        \
-                                     const double*, uint32_t*, uint32_t*, size_t, uint32_t*,     \
-                                     hipStream_t);                                               \
-  template sbx_status launch_indices<T>(const PartDev<T>&, const SysDev&, const double*, int,    \
-                                        int, int32_t*, int8_t*, hipStream_t);                    \
+  template sbx_status launch_zero_grids<T>(const InstDev<T>*, const std::vector<InstInfo>&,      \
+                                           hipStream_t);                                         \
+  template sbx_status launch_centres<T>(const InstDev<T>*, const int*,                           \
+                                        const std::vector<InstInfo>&, bool, hipStream_t);        \
+  template sbx_status launch_deposit<T>(const InstDev<T>*, const int*,                           \
+                                        const std::vector<InstInfo>&, hipStream_t);              \
+  template sbx_status launch_force<T>(const InstDev<T>*, const int*, const std::vector<InstInfo>&, \
+                                      int, hipStream_t);                                         \
+  template sbx_status launch_sort<T>(const InstDev<T>*, int*, const std::vector<InstInfo>&,      \
+                                     uint32_t*, size_t, uint32_t*, hipStream_t);                 \
+  template sbx_status launch_indices<T>(const InstDev<T>*, const int*, int64_t, int, int,        \
+                                        int32_t*, int8_t*, hipStream_t);                         \
   template sbx_status launch_convert_in<T>(const double*, T*, size_t, hipStream_t);              \
   template sbx_status launch_convert_out<T>(const T*, double*, size_t, hipStream_t);             \
   template sbx_status launch_split3<T>(const double*, T*, T*, T*, int64_t, hipStream_t);         \
   template sbx_status launch_join3<T>(const T*, const T*, const T*, double*, int64_t, hipStream_t);
 SBX_INST(float)
 SBX_INST(double)
-template sbx_status launch_zero<uint32_t>(uint32_t*, size_t, hipStream_t);
 #undef SBX_INST
+template sbx_status launch_zero<uint32_t>(uint32_t*, size_t, hipStream_t);
+template sbx_status launch_unpermute<double>(const double*, const int32_t*, double*, int64_t, int, hipStream_t);
+template sbx_status launch_unpermute<int32_t>(const int32_t*, const int32_t*, int32_t*, int64_t, int, hipStream_t);
+template sbx_status launch_unpermute<int8_t>(const int8_t*, const int32_t*, int8_t*, int64_t, int, hipStream_t);
+template sbx_status launch_unpermute<uint8_t>(const uint8_t*, const int32_t*, uint8_t*, int64_t, int, hipStream_t);
 
 }  // namespace sbx

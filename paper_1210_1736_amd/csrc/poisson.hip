@@ -1,0 +1,217 @@
+// C ABI of the standalone isolated Poisson solves (Eqs. 1-5).
+#include "ctx.h"
+
+using namespace sbx;
+
+// Solve plans of a Poisson object are cached per (rho, phi, batch) so that a
+// loop over the same buffers reuses its device tables.
+struct PoissonPlan {
+  const void* rho;
+  void* phi;
+  int batch;
+  SolvePlan<float> p32;
+  SolvePlan<double> p64;
+};
+
+struct sbx_poisson {
+  int N = 0, prec = 0, device = 0;
+  sbx_level geo;
+  double G = 1.0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* H = nullptr;
+  void* X = nullptr;
+  void* C = nullptr;
+  int cap = 0;
+  double rel_imag = 0.0;
+  int64_t bytes = 0;
+  std::vector<PoissonPlan*> plans;
+};
+
+
+namespace {
+
+constexpr int kMaxSolves = 40;
+
+bool is_pow2_grid(int n) { return n >= 8 && n <= 256 && (n & (n - 1)) == 0; }  // solves per Poisson plan launch
+
+template <typename T>
+SolvePlan<T>& plan_of(PoissonPlan* q) {
+  if constexpr (sizeof(T) == 8) return q->p64;
+  else return q->p32;
+}
+
+template <typename T>
+sbx_status poisson_solve_t(sbx_poisson* p, int batch, const void* rho, void* phi) {
+  const size_t cells = (size_t)p->N * p->N * p->N;
+  const int cap = std::min(batch, kMaxSolves);
+  if (cap > p->cap) {
+    SBX_HIP(hipStreamSynchronize(p->stream));
+    for (auto* q : p->plans) {
+      plan_destroy(q->p32);
+      plan_destroy(q->p64);
+      delete q;
+    }
+    p->plans.clear();
+    free_ptr(p->X);
+    free_ptr(p->C);
+    p->cap = 0;
+    SBX_TRY(dev_alloc(&p->X, x_elems(p->N) * sizeof(C2<T>) * cap));
+    SBX_TRY(dev_alloc(&p->C, c_elems(p->N) * sizeof(C2<T>) * cap));
+    p->cap = cap;
+    p->bytes = (int64_t)(h_elems(p->N) * sizeof(T) +
+                         (x_elems(p->N) + c_elems(p->N)) * sizeof(C2<T>) * cap);
+  }
+  for (int b0 = 0; b0 < batch; b0 += p->cap) {
+    const int nb = std::min(p->cap, batch - b0);
+    const void* r = (const T*)rho + cells * b0;
+    void* f = (T*)phi + cells * b0;
+    PoissonPlan* hit = nullptr;
+    for (auto* q : p->plans)
+      if (q->rho == r && q->phi == f && q->batch == nb) hit = q;
+    if (!hit) {
+      auto descs = [&](const T* rr, T* ff) {
+        std::vector<SolveDesc<T>> d(nb);
+        for (int i = 0; i < nb; ++i) {
+          d[i].rho = rr + cells * i;
+          d[i].phi = ff + cells * i;
+          d[i].X = (C2<T>*)p->X + x_elems(p->N) * i;
+          d[i].C = (C2<T>*)p->C + c_elems(p->N) * i;
+          d[i].H = (const T*)p->H;
+          d[i].N = p->N;
+        }
+        return d;
+      };
+      if (!tuning_cached((int)sizeof(T), std::vector<int>(nb, p->N))) {
+        // tune on scratch grids, never on the caller's buffers
+        T* scratch = nullptr;
+        SBX_TRY(dev_alloc((void**)&scratch, sizeof(T) * cells * nb));
+        SolvePlan<T> tmp;
+        auto d = descs(scratch, scratch);
+        const sbx_status rc = plan_create<T>(tmp, d.data(), nb, p->stream);
+        plan_destroy(tmp);
+        (void)hipFree(scratch);
+        SBX_TRY(rc);
+      }
+      if (p->plans.size() >= 8) {
+        SBX_HIP(hipStreamSynchronize(p->stream));
+        plan_destroy(p->plans.front()->p32);
+        plan_destroy(p->plans.front()->p64);
+        delete p->plans.front();
+        p->plans.erase(p->plans.begin());
+      }
+      hit = new PoissonPlan{r, f, nb, {}, {}};
+      p->plans.push_back(hit);
+      auto d = descs((const T*)r, (T*)f);
+      SBX_TRY(plan_create<T>(plan_of<T>(hit), d.data(), nb, p->stream));
+    }
+    SBX_TRY(plan_run<T>(plan_of<T>(hit), p->stream));
+  }
+  return SBX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sbx_status sbx_poisson_create(int32_t n, double R, double q, double G, int32_t h0_mode, int32_t prec,
+                              int32_t device, void* stream, sbx_poisson** out) {
+  if (!out || !is_pow2_grid(n) || !(R > 0.0) || !(q > 0.0) || !(q <= 1.0) || !(G > 0.0) ||
+      (h0_mode != 0 && h0_mode != 2) || (prec != SBX_FP32 && prec != SBX_FP64)) {
+    set_error("bad Poisson plan arguments");
+    return SBX_EINVAL;
+  }
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    set_error("no HIP device available");
+    return SBX_EDEVICE;
+  }
+  SBX_TRY(set_device(device));
+  sbx_poisson* p = new (std::nothrow) sbx_poisson();
+  if (!p) return SBX_ENOMEM;
+  p->N = n;
+  p->prec = prec;
+  p->device = device;
+  p->geo = sbx_level{n, R, q};
+  p->G = G;
+  if (stream) {
+    p->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreate(&p->stream) != hipSuccess) {
+      delete p;
+      set_error("hipStreamCreate failed");
+      return SBX_EDEVICE;
+    }
+    p->own_stream = true;
+  }
+  const size_t es = prec == SBX_FP64 ? 8 : 4;
+  sbx_status rc = dev_alloc(&p->H, h_elems(n) * es);
+  if (rc == SBX_OK) {
+    const LevelDev L = make_level(p->geo);
+    rc = prec == SBX_FP64 ? build_green<double>(n, L.l, L.lz, G, h0_mode, (double*)p->H, &p->rel_imag, p->stream)
+                          : build_green<float>(n, L.l, L.lz, G, h0_mode, (float*)p->H, &p->rel_imag, p->stream);
+  }
+  if (rc != SBX_OK) {
+    sbx_poisson_destroy(p);
+    return rc;
+  }
+  p->bytes = (int64_t)(h_elems(n) * es);
+  *out = p;
+  return SBX_OK;
+}
+
+void sbx_poisson_destroy(sbx_poisson* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (auto* q : p->plans) {
+    plan_destroy(q->p32);
+    plan_destroy(q->p64);
+    delete q;
+  }
+  p->plans.clear();
+  free_ptr(p->H);
+  free_ptr(p->X);
+  free_ptr(p->C);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+sbx_status sbx_poisson_solve(sbx_poisson* p, int32_t batch, const void* rho, void* phi) {
+  if (!p || !rho || !phi || batch <= 0 || batch > 64) {
+    set_error("bad Poisson solve arguments");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(p->device));
+  return p->prec == SBX_FP64 ? poisson_solve_t<double>(p, batch, rho, phi)
+                             : poisson_solve_t<float>(p, batch, rho, phi);
+}
+
+sbx_status sbx_poisson_green(sbx_poisson* p, double* out, double* rel_imag) {
+  if (!p || !out) {
+    set_error("null argument");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(p->device));
+  const size_t n = h_elems(p->N);
+  double* stage = nullptr;
+  SBX_TRY(dev_alloc((void**)&stage, n * sizeof(double)));
+  sbx_status rc = p->prec == SBX_FP64 ? launch_convert_out<double>((double*)p->H, stage, n, p->stream)
+                                      : launch_convert_out<float>((float*)p->H, stage, n, p->stream);
+  if (rc == SBX_OK) {
+    if (hipMemcpyAsync(out, stage, n * sizeof(double), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+        hipStreamSynchronize(p->stream) != hipSuccess) {
+      set_error("copy of the Green's table failed");
+      rc = SBX_EDEVICE;
+    }
+  }
+  (void)hipFree(stage);
+  if (rel_imag) *rel_imag = p->rel_imag;
+  return rc;
+}
+
+int64_t sbx_poisson_bytes(sbx_poisson* p) { return p ? p->bytes : 0; }
+
+}  // extern "C"

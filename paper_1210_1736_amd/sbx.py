@@ -93,6 +93,11 @@ def _load():
         "sbx_count_live": (S, [P, C.POINTER(I64)]),
         "sbx_profile_begin": (S, [P, I32]),
         "sbx_profile_end": (S, [P, I32, P, P]),
+        "sbx_batch_create": (S, [C.POINTER(P), I32, P, C.POINTER(P)]),
+        "sbx_batch_step": (S, [P, P, I32]),
+        "sbx_batch_sync": (S, [P]),
+        "sbx_batch_set_sort_interval": (S, [P, I32]),
+        "sbx_batch_destroy": (None, [P]),
         "sbx_poisson_create": (S, [I32, D, D, D, I32, I32, I32, P, C.POINTER(P)]),
         "sbx_poisson_destroy": (None, [P]),
         "sbx_poisson_solve": (S, [P, I32, P, P]),
@@ -260,6 +265,42 @@ class Context:
         k = C.c_int64()
         _check(_lib.sbx_count_live(self._h, C.byref(k)))
         return k.value
+
+
+class Batch:
+    """A batch of contexts stepped together (sbx_batch_*)."""
+
+    def __init__(self, contexts, stream=None):
+        arr = (C.c_void_p * len(contexts))(*[c._h.value for c in contexts])
+        h = C.c_void_p()
+        _check(_lib.sbx_batch_create(arr, len(contexts), stream, C.byref(h)))
+        self._h = h
+        self.contexts = list(contexts)
+
+    def close(self):
+        if self._h:
+            _lib.sbx_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sbx_batch_step(self, dt=None, nsteps=1):
+        if dt is None:
+            p = None
+        else:
+            dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (len(self.contexts),)))
+            p = _ptr(dt)
+        _check(_lib.sbx_batch_step(self._h, p, int(nsteps)))
+
+    def sbx_batch_sync(self):
+        _check(_lib.sbx_batch_sync(self._h))
+
+    def sbx_batch_set_sort_interval(self, every):
+        _check(_lib.sbx_batch_set_sort_interval(self._h, int(every)))
 
 
 class Poisson:

@@ -298,3 +298,51 @@ def random_cells(rng, N, n, lo=2, hi=None):
     """Integer cell indices inside [lo, hi] per axis (for field tests)."""
     hi = N - 3 if hi is None else hi
     return rng.integers(lo, hi + 1, size=(n, 3))
+
+
+def q_for(N):
+    """Smallest flattening in {1/4, 1/2, 1} admissible on 3 levels of half-extents
+    1, 4, 20 with N cells (the q_crit rule of Eq. 9 is applied by the library)."""
+    qc = max(1.0 / 4.0, 4.0 / (N - 4) * 20.0 / 4.0)
+    for q in (0.25, 0.5, 1.0):
+        if q >= qc:
+            return q
+    return 1.0
+
+
+def ensemble(n_inst=16, workload=4, steps=200, scale=1.0, sizes=(64, 128, 256), n_range=(1e5, 2e6)):
+    """Independent satellite-sinking instances of uneven size: per instance a
+    grid size from `sizes`, a particle count log-uniform in n_range (times
+    `scale`) split disc:bulge:halo as the disc galaxy, a satellite of mass
+    uniform in [0.02, 0.2] disc masses at equal particle mass, orbit
+    eccentricity uniform in [0, 0.8] and inclination uniform in [0, 180] deg."""
+    rng = rng_for(workload, 99)
+    out = []
+    for k in range(n_inst):
+        N = int(rng.choice(sizes))
+        n = int(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))) * scale)
+        msat = float(rng.uniform(0.02, 0.2))
+        e = float(rng.uniform(0.0, 0.8))
+        inc = float(rng.uniform(0.0, 180.0))
+        # the satellite's particles weigh as much as disc particles
+        n_gal = max(int(n / (1.0 + 2.0 * msat / 8.5)), 100)
+        gm = GalaxyModel(n_disc=int(n_gal * 2 / 8.5), n_bulge=int(n_gal * 0.5 / 8.5),
+                         n_halo=int(n_gal * 6 / 8.5))
+        x, v, m, comp, Menc = galaxy(1000 * workload + k, gm)
+        m_disc = gm.M_disc / max(gm.n_disc, 1)
+        ns = max(int(round(msat / m_disc)), 10)
+        srng = rng_for(1000 * workload + k, SAT)
+        ps, rs = plummer_positions(srng, ns, 0.6, 6.0)
+        vs = plummer_velocities(srng, rs, msat, 0.6)
+        X0, V0 = point_mass_orbit(float(Menc(10.0)), 10.0, e, inc)
+        x = np.concatenate([x, ps + X0]); v = np.concatenate([v, vs + V0])
+        m = np.concatenate([m, np.full(ns, msat / ns)])
+        comp = np.concatenate([comp, np.full(ns, SAT, np.int8)])
+        gal = np.concatenate([np.zeros(x.shape[0] - ns, np.int8), np.ones(ns, np.int8)])
+        q = q_for(N)
+        hg = HierSpec([LevelSpec(N, 1.0, q), LevelSpec(N, 4.0, q), LevelSpec(N, 20.0, 1.0)],
+                      centring="com")
+        hs = HierSpec([LevelSpec(N, 1.0, 1.0), LevelSpec(N, 6.0, 1.0), LevelSpec(N, 20.0, 1.0)],
+                      centring="com")
+        out.append(Workload(f"instance{k}_N{N}", x, v, m, comp, gal, [hg, hs], dt=0.01, steps=steps))
+    return out

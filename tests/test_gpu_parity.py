@@ -417,3 +417,35 @@ def test_fp32_steps_track_oracle(sbx):
     ev = np.linalg.norm(vg - v, axis=1) / vr
     assert np.percentile(ev, 99) < 1e-4
     assert np.max(np.abs(xg - x)) < 1e-4
+
+
+def test_batch_graph_replays_match_single_contexts(sbx):
+    """Instances of uneven size stepped as one batch (one launch per phase,
+    one graph replay per step, with cell sorts) equal the same instances
+    stepped one by one, after every replay."""
+    ws = synth.ensemble(n_inst=4, scale=0.004, sizes=(32, 64))
+    for w in ws:
+        for h in w.hier:
+            h.levels = [synth.LevelSpec(L.N, L.R, 1.0) for L in h.levels]
+    sizes = sorted({w.hier[0].levels[0].N for w in ws})
+    assert len(sizes) >= 2
+    ref = [T.make_ctx(w, sbx.SBX_FP64) for w in ws]
+    bat = [T.make_ctx(w, sbx.SBX_FP64) for w in ws]
+    for c in ref + bat:
+        c.sbx_set_sort_interval(3)
+    b = sbx.Batch(bat)
+    for step in range(7):
+        for c, w in zip(ref, ws):
+            c.sbx_step(w.dt, 1)
+        b.sbx_batch_step([w.dt for w in ws], 1)
+        b.sbx_batch_sync()
+        for c, d in zip(ref, bat):
+            xr, vr, lr = c.sbx_get_particles()
+            xb, vb, lb = d.sbx_get_particles()
+            assert np.array_equal(lr, lb)
+            assert np.max(np.abs(xr - xb)) < 1e-11, step
+            assert np.max(np.abs(vr - vb)) < 1e-9, step
+    with pytest.raises(sbx.SbxError):
+        bat[0].sbx_step(0.01, 1)
+    b.close()
+    bat[0].sbx_step(ws[0].dt, 1)  # released contexts step alone again
