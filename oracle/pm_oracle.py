@@ -549,3 +549,122 @@ class System:
             sz = float(np.sqrt(max(np.mean(vz * vz) - np.mean(vz) ** 2, 0.0)))
         return {"ekin": ekin, "epot": epot, "L": L, "disc_sigR": sR, "disc_sigz": sz,
                 "n_lost": int(lost.sum()), "centres": centres}
+
+
+# --------------------------------------------------------------------------
+# Adjoint of a leapfrog segment (reverse mode of Eqs. 1-8 and 6)
+# --------------------------------------------------------------------------
+def eq8_scatter_transpose(B, idx, delta, lengths, mu, taylor=True):
+    """B += A^T mu: the transpose of the Eq. 8 gather for per-particle vectors
+    mu (n,3).  A maps a field to the accelerations of the particles; its
+    transpose spreads mu over the 19 stencil points with the same weights."""
+    lx, ly, lz = lengths
+    i, j, k = idx[:, 0], idx[:, 1], idx[:, 2]
+    e = np.eye(3, dtype=np.int64)
+
+    def add(off, w):
+        np.add.at(B, (i + off[0], j + off[1], k + off[2]), w)
+    ln = np.array([lx, ly, lz])
+    for a in range(3):
+        add(e[a], mu[:, a] / (2.0 * ln[a]))
+        add(-e[a], -mu[:, a] / (2.0 * ln[a]))
+        if not taylor:
+            continue
+        w2 = mu[:, a] * delta[:, a] / (ln[a] * ln[a])
+        add(e[a], w2)
+        add(-e[a], w2)
+        add(np.zeros(3, np.int64), -2.0 * w2)
+        for b in range(3):
+            if b == a:
+                continue
+            w = mu[:, a] * delta[:, b] / (4.0 * ln[a] * ln[b])
+            add(e[a] + e[b], w)
+            add(-e[a] + e[b], -w)
+            add(-e[a] - e[b], w)
+            add(e[a] - e[b], -w)
+
+
+def eq8_jacobian(Phi, idx, lengths, taylor=True):
+    """d a / d x of Eq. 8 inside a cell: the matrix of second differences."""
+    _, _, DD = _derivs(Phi, idx, lengths)
+    if not taylor:
+        return np.zeros((idx.shape[0], 3, 3))
+    return np.transpose(DD, (2, 0, 1))
+
+
+def segment_loss_and_grads(sysm: System, x, v, m, comp, gal, dt, nsteps, sel_comp=0, sel_gal=0):
+    """Forward: nsteps integration cycles; loss L = sum over the selected
+    particles (component sel_comp of galaxy sel_gal) of 1/2 m v_z^2 with the
+    staggered v after the last kick.  Backward: exact reverse mode of the
+    discrete step (the nearest-grid-point cells are piecewise constant, so
+    only the in-cell offsets of Eq. 8 carry a position derivative).
+    Fixed centres only.  Returns (L, dL/dm, dL/dx0, dL/dv0).
+    parity unpinned beyond its finite-difference and transpose pins."""
+    for hh in sysm.h:
+        if hh.centring != "fixed":
+            raise ValueError("the segment adjoint needs fixed centres")
+    lost = np.zeros(x.shape[0], bool)
+    xs = [x.copy()]
+    xk, vk = x.copy(), v.copy()
+    for _ in range(nsteps):
+        xk, vk, lost, _ = sysm.step(xk, vk, m, gal, lost, dt)
+        xs.append(xk.copy())
+    sel = (comp == sel_comp) & (gal == sel_gal)
+    L = 0.5 * np.sum(m[sel] * vk[sel, 2] ** 2)
+    gm = np.zeros_like(m)
+    gm[sel] = 0.5 * vk[sel, 2] ** 2
+    lx = np.zeros_like(x)
+    lv = np.zeros_like(v)
+    lv[sel, 2] = m[sel] * vk[sel, 2]
+    live = ~lost
+    for k in range(nsteps - 1, -1, -1):
+        lv = lv + dt * lx
+        mu = np.where(live[:, None], dt * lv, 0.0)
+        xk = xs[k]
+        centres = sysm.centres(xk, m, gal, lost)
+        pots = sysm.potentials(xk, m, gal, lost, centres)
+        for g, hh in enumerate(sysm.h):
+            cls, idx = classify(xk, hh, centres[g])
+            Phi = pots[g]["Phi"]
+            nl = hh.n_levels
+            if nl == 1:
+                terms = [(cls == OUTER, 0, [0])]
+            else:
+                core, ring, outer = cls == CORE, cls == RING, cls == OUTER
+                # (particles, level, grids whose sum is the field)
+                terms = [(core, 0, [0]), (core, 1, [2]), (core, 2, [4]),
+                         (ring, 1, [1, 2]), (ring, 2, [4]), (outer, 2, [3, 4])]
+            Bs = [np.zeros_like(P) for P in Phi]
+            for mask, lev, grids in terms:
+                msk = mask & live
+                if not msk.any():
+                    continue
+                L_ = hh.levels[lev]
+                c = level_centre(hh, lev, centres[g])
+                ii = idx[lev][msk]
+                dl = cell_offset(xk[msk] - c, ii, L_)
+                F = sum(Phi[q] for q in grids)
+                J = eq8_jacobian(F, ii, L_.lengths, sysm.taylor)
+                lx[msk] += np.einsum("nab,nb->na", J, mu[msk])
+                Bt = np.zeros_like(F)
+                eq8_scatter_transpose(Bt, ii, dl, L_.lengths, mu[msk], sysm.taylor)
+                for q in grids:
+                    Bs[q] += Bt
+            # mass gradient: psi = K B on each grid, read at the source cells
+            own = (gal == g) & live
+            if nl == 1:
+                psi = sysm.solve(Bs[0], hh.levels[0])
+                ok = own & (cls == OUTER)
+                gm[ok] += psi[tuple(idx[0][ok].T)]
+                continue
+            L1, L2, L3 = hh.levels
+            psis = [sysm.solve(Bs[0], L1), sysm.solve(Bs[1], L2), sysm.solve(Bs[2], L2),
+                    sysm.solve(Bs[3], L3), sysm.solve(Bs[4], L3)]
+            core, ring, outer = own & (cls == CORE), own & (cls == RING), own & (cls == OUTER)
+            gm[core] += psis[0][tuple(idx[0][core].T)]     # grid 1
+            gm[core] += psis[1][tuple(idx[1][core].T)]     # grid 2
+            gm[ring] += psis[2][tuple(idx[1][ring].T)]     # grid 3
+            cr = core | ring
+            gm[cr] += psis[3][tuple(idx[2][cr].T)]         # grid 4
+            gm[outer] += psis[4][tuple(idx[2][outer].T)]   # grid 5
+    return L, gm, lx, lv
