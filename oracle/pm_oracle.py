@@ -594,8 +594,8 @@ def eq8_jacobian(Phi, idx, lengths, taylor=True):
 
 def segment_loss_and_grads(sysm: System, x, v, m, comp, gal, dt, nsteps, sel_comp=0, sel_gal=0):
     """Forward: nsteps integration cycles; loss L = sum over the selected
-    particles (component sel_comp of galaxy sel_gal) of 1/2 m v_z^2 with the
-    staggered v after the last kick.  Backward: exact reverse mode of the
+    particles (component sel_comp of galaxy sel_gal) still on the grids at the
+    end of 1/2 m v_z^2 with the staggered v after the last kick.  Backward: exact reverse mode of the
     discrete step (the nearest-grid-point cells are piecewise constant, so
     only the in-cell offsets of Eq. 8 carry a position derivative).
     Fixed centres only.  Returns (L, dL/dm, dL/dx0, dL/dv0).
@@ -609,7 +609,8 @@ def segment_loss_and_grads(sysm: System, x, v, m, comp, gal, dt, nsteps, sel_com
     for _ in range(nsteps):
         xk, vk, lost, _ = sysm.step(xk, vk, m, gal, lost, dt)
         xs.append(xk.copy())
-    sel = (comp == sel_comp) & (gal == sel_gal)
+    # particles lost by the end have left the system (Sec. 2.1): not counted
+    sel = (comp == sel_comp) & (gal == sel_gal) & ~lost
     L = 0.5 * np.sum(m[sel] * vk[sel, 2] ** 2)
     gm = np.zeros_like(m)
     gm[sel] = 0.5 * vk[sel, 2] ** 2

@@ -103,5 +103,5 @@ def _fwd(sysm, x, v, m, comp, gal, dt, K):
     lost = np.zeros(x.shape[0], bool)
     for _ in range(K):
         x, v, lost, _ = sysm.step(x, v, m, gal, lost, dt)
-    sel = (comp == 1) & (gal == 0)
+    sel = (comp == 1) & (gal == 0) & ~lost
     return 0.5 * np.sum(m[sel] * v[sel, 2] ** 2)
