@@ -174,6 +174,22 @@ sbx_status sbx_diagnostics(sbx_ctx* ctx, double dt, sbx_diag* out);
  * max entries (oldest first).  Synchronises. */
 sbx_status sbx_diag_log(sbx_ctx* ctx, int32_t max, sbx_diag* out, int32_t* count);
 
+/* Differentiable segment: nsteps integration cycles from the current state
+ * (no reordering inside), then the reverse mode of the discrete cycles, with
+ * (x, v) checkpoints every ckpt_every steps and the positions between
+ * checkpoints recomputed.  Loss L = sum over the live particles of component
+ * sel_comp of galaxy sel_gal of 1/2 m v_z^2, with v the staggered velocity
+ * after the last kick.  Outputs (host, caller's particle order, any may be
+ * NULL): loss (1), grad_m = dL/dm (n), grad_x = dL/dx (n*3) and
+ * grad_v = dL/dv (n*3) at the start of the segment.  Nearest-grid-point
+ * cells are piecewise constant, so dL/dx holds the in-cell (Eq. 8 offset)
+ * part only.  Particles lost by the end are frozen for the whole segment.
+ * Fixed centres only (SBX_EINVAL otherwise).  Leaves the context at the
+ * final state, as sbx_step would.  FP64 adjoint state in both precisions. */
+sbx_status sbx_adjoint_segment(sbx_ctx* ctx, double dt, int32_t nsteps, int32_t ckpt_every,
+                               int32_t sel_comp, int32_t sel_gal, double* loss, double* grad_m,
+                               double* grad_x, double* grad_v);
+
 /* Reorder the particles in device memory by the cell of their finest grid
  * every `every` steps (at the start of the step; 0 = never; default 8).  A
  * performance setting only: every output is returned in the caller's

@@ -254,6 +254,9 @@ void free_particles(sbx_ctx* c) {
 void free_grids(sbx_ctx* c) {
   plan_destroy(c->plan32);
   plan_destroy(c->plan64);
+  plan_destroy(c->adj32);
+  plan_destroy(c->adj64);
+  free_ptr(c->adj_block);
   free_ptr(c->grid_block);
   free_typed(c->count);
   free_typed(c->scan_tmp);
@@ -424,6 +427,138 @@ sbx_status set_dt(sbx_ctx* c, double dt) {
   if (c->dt_dev == dt) return SBX_OK;
   c->dt_dev = dt;
   return upload_inst(c);
+}
+
+
+// ------------------------------------------------------ segment adjoint ----
+template <typename T>
+GridsDev<T> adj_grids(sbx_ctx* c) {
+  GridsDev<T> G;
+  std::memset(&G, 0, sizeof(G));
+  for (int g = 0; g < c->ngal; ++g)
+    for (int k = 0; k < c->nslots[g]; ++k)
+      G.g[g][k] = (T*)c->adj_block + ((T*)c->grid[g][k] - (T*)c->grid_block);
+  return G;
+}
+
+template <typename T>
+sbx_status ensure_adjoint(sbx_ctx* c) {
+  if (c->adj_block) return SBX_OK;
+  SBX_TRY(dev_alloc(&c->adj_block, sizeof(T) * c->grid_elems));
+  SolvePlan<T>& fwd = sizeof(T) == 8 ? (SolvePlan<T>&)c->plan64 : (SolvePlan<T>&)c->plan32;
+  std::vector<SolveDesc<T>> d = fwd.host;
+  for (auto& e : d) {
+    T* a = (T*)c->adj_block + ((const T*)e.rho - (const T*)c->grid_block);
+    e.rho = a;
+    e.phi = a;
+  }
+  SolvePlan<T>& adj = sizeof(T) == 8 ? (SolvePlan<T>&)c->adj64 : (SolvePlan<T>&)c->adj32;
+  return plan_create<T>(adj, d.data(), (int)d.size(), c->stream);
+}
+
+template <typename T>
+sbx_status copy_set(sbx_ctx* c, const PSet& dst, const PSet& src, bool with_v, bool with_lost) {
+  const size_t b = sizeof(T) * c->n;
+  for (int k = 0; k < 3; ++k) {
+    SBX_HIP(hipMemcpyAsync(dst.x[k], src.x[k], b, hipMemcpyDeviceToDevice, c->stream));
+    if (with_v) SBX_HIP(hipMemcpyAsync(dst.v[k], src.v[k], b, hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (with_lost) SBX_HIP(hipMemcpyAsync(dst.lost, src.lost, c->n, hipMemcpyDeviceToDevice, c->stream));
+  return SBX_OK;
+}
+
+// Forward nsteps without sorting, checkpoints of (x, v, lost) every
+// ckpt_every steps, then the reverse cycles segment by segment: positions of
+// a segment are recomputed from its checkpoint, each reverse cycle re-solves
+// the fields at its positions, scatters the adjoint sources, solves them and
+// gathers the mass gradient.  Particles lost by the end are frozen.
+template <typename T>
+sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, int sel_gal,
+                     double* loss, double* grad_m, double* grad_x, double* grad_v) {
+  SBX_TRY(ensure_adjoint<T>(c));
+  SBX_TRY(set_dt(c, dt));
+  const int64_t n = c->n;
+  const int nck = (nsteps + ckpt - 1) / ckpt;
+  std::vector<void*> allocs;
+  auto alloc = [&](size_t bytes, void** p) -> sbx_status {
+    const sbx_status r = dev_alloc(p, bytes);
+    if (r == SBX_OK) allocs.push_back(*p);
+    return r;
+  };
+  auto make_set = [&](PSet& s, bool v, bool lost) -> sbx_status {
+    for (int k = 0; k < 3; ++k) {
+      SBX_TRY(alloc(sizeof(T) * n, &s.x[k]));
+      if (v) SBX_TRY(alloc(sizeof(T) * n, &s.v[k]));
+    }
+    if (lost) SBX_TRY(alloc(n, (void**)&s.lost));
+    return SBX_OK;
+  };
+  double *lx = nullptr, *lv = nullptr, *gm = nullptr, *dloss = nullptr, *stage = nullptr;
+  auto body = [&]() -> sbx_status {
+    std::vector<PSet> cks(nck + 1), xb(ckpt);
+    for (auto& s : cks) SBX_TRY(make_set(s, true, true));
+    for (auto& s : xb) SBX_TRY(make_set(s, false, false));
+    SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&lx));
+    SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&lv));
+    SBX_TRY(alloc(sizeof(double) * n, (void**)&gm));
+    SBX_TRY(alloc(sizeof(double) * 4, (void**)&dloss));
+    SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&stage));
+    PSet& live = c->set[c->cur];
+    // forward with checkpoints
+    for (int k = 0; k < nsteps; ++k) {
+      if (k % ckpt == 0) SBX_TRY(copy_set<T>(c, cks[k / ckpt], live, true, true));
+      SBX_TRY(field_solve(c));
+      SBX_TRY(force(c, 1));
+    }
+    SBX_TRY(copy_set<T>(c, cks[nck], live, true, true));  // final state
+    SBX_TRY(launch_adj_init<T>(dinst<T>(c), c->d_cur, n, sel_comp, sel_gal, lx, lv, gm, c->pre_partial,
+                               dloss, c->stream));
+    const uint8_t* frozen = cks[nck].lost;
+    const GridsDev<T> B = adj_grids<T>(c);
+    for (int seg = nck - 1; seg >= 0; --seg) {
+      const int k0 = seg * ckpt, k1 = std::min(k0 + ckpt, nsteps);
+      SBX_TRY(copy_set<T>(c, live, cks[seg], true, true));
+      c->com_fresh = false;
+      for (int k = k0; k < k1; ++k) {
+        SBX_TRY(copy_set<T>(c, xb[k - k0], live, false, false));
+        if (k + 1 < k1) {
+          SBX_TRY(field_solve(c));
+          SBX_TRY(force(c, 1));
+        }
+      }
+      SBX_HIP(hipMemcpyAsync(live.lost, frozen, n, hipMemcpyDeviceToDevice, c->stream));
+      for (int k = k1 - 1; k >= k0; --k) {
+        SBX_TRY(copy_set<T>(c, live, xb[k - k0], false, false));
+        c->com_fresh = false;
+        SBX_TRY(field_solve(c));
+        SBX_TRY(launch_zero<T>((T*)c->adj_block, c->grid_elems, c->stream));
+        SBX_TRY(launch_adj_step<T>(dinst<T>(c), c->d_cur, n, B, frozen, lx, lv, c->stream));
+        SolvePlan<T>& adj = sizeof(T) == 8 ? (SolvePlan<T>&)c->adj64 : (SolvePlan<T>&)c->adj32;
+        SBX_TRY(plan_run<T>(adj, c->stream));
+        SBX_TRY(launch_adj_gather<T>(dinst<T>(c), c->d_cur, n, B, frozen, gm, c->stream));
+      }
+    }
+    SBX_TRY(copy_set<T>(c, live, cks[nck], true, true));  // back to the final state
+    c->com_fresh = false;
+    c->grids_fields = false;
+    c->step_count += nsteps;
+    // outputs in the caller's order
+    const int32_t* id = live.id;
+    if (loss) SBX_HIP(hipMemcpyAsync(loss, dloss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    struct Out { double* host; double* dev; int w; } outs[3] = {{grad_m, gm, 1}, {grad_x, lx, 3}, {grad_v, lv, 3}};
+    for (auto& o : outs) {
+      if (!o.host) continue;
+      SBX_TRY(launch_unpermute<double>(o.dev, id, stage, n, o.w, c->stream));
+      SBX_HIP(hipMemcpyAsync(o.host, stage, sizeof(double) * o.w * n, hipMemcpyDeviceToHost, c->stream));
+      SBX_HIP(hipStreamSynchronize(c->stream));
+    }
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    return SBX_OK;
+  };
+  const sbx_status rc = body();
+  (void)hipStreamSynchronize(c->stream);
+  for (void* p : allocs) (void)hipFree(p);
+  return rc;
 }
 
 }  // namespace
@@ -933,6 +1068,29 @@ sbx_status sbx_diag_log(sbx_ctx* c, int32_t max, sbx_diag* out, int32_t* count) 
   SBX_HIP(hipStreamSynchronize(c->stream));
   for (int64_t i = 0; i < k; ++i) to_diag(r.data() + i * kNDiag, out + i);
   return SBX_OK;
+}
+
+sbx_status sbx_adjoint_segment(sbx_ctx* c, double dt, int32_t nsteps, int32_t ckpt_every,
+                               int32_t sel_comp, int32_t sel_gal, double* loss, double* grad_m,
+                               double* grad_x, double* grad_v) {
+  SBX_TRY(check_ready(c));
+  if (c->batch) {
+    set_error("the context belongs to a batch");
+    return SBX_ESTATE;
+  }
+  if (!std::isfinite(dt) || nsteps < 1 || ckpt_every < 1 || sel_comp < 0 || sel_comp >= kNComp ||
+      sel_gal < 0 || sel_gal >= c->ngal) {
+    set_error("bad segment arguments");
+    return SBX_EINVAL;
+  }
+  for (int g = 0; g < c->ngal; ++g)
+    if (c->hh[g].centring != SBX_CENTRE_FIXED) {
+      set_error("the segment adjoint needs fixed centres");
+      return SBX_EINVAL;
+    }
+  return c->cfg.prec == SBX_FP64
+             ? adjoint_t<double>(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x, grad_v)
+             : adjoint_t<float>(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x, grad_v);
 }
 
 sbx_status sbx_set_sort_interval(sbx_ctx* c, int32_t every) {

@@ -72,6 +72,10 @@ struct sbx_ctx {
   int nsolves = 0;
   sbx::SolvePlan<float> plan32;
   sbx::SolvePlan<double> plan64;
+  // adjoint grids (same layout as the grids) and their solve plan
+  void* adj_block = nullptr;
+  sbx::SolvePlan<float> adj32;
+  sbx::SolvePlan<double> adj64;
   // cell sort
   uint32_t* key = nullptr;
   uint32_t* count = nullptr;     // bins + 1

@@ -145,6 +145,22 @@ template <typename T>
 sbx_status launch_indices(const InstDev<T>* inst, const int* cur, int64_t n, int galaxy, int level,
                           int32_t* idx, int8_t* cls, hipStream_t s);
 
+// Reverse mode of a leapfrog segment (single instance, fixed centres).
+// init: loss (one double) and seeds of the adjoints; step: one reverse cycle
+// at the positions in the live set with the forward fields in the grids,
+// adjoint sources scattered into B; gather: mass gradient from the adjoint
+// potentials P.  `frozen` marks particles treated as lost for the segment.
+template <typename T>
+sbx_status launch_adj_init(const InstDev<T>* inst, const int* cur, int64_t n, int sel_comp,
+                           int sel_gal, double* lx, double* lv, double* gm, double* partial,
+                           double* loss, hipStream_t s);
+template <typename T>
+sbx_status launch_adj_step(const InstDev<T>* inst, const int* cur, int64_t n, const GridsDev<T>& B,
+                           const uint8_t* frozen, double* lx, double* lv, hipStream_t s);
+template <typename T>
+sbx_status launch_adj_gather(const InstDev<T>* inst, const int* cur, int64_t n, const GridsDev<T>& P,
+                             const uint8_t* frozen, double* gm, hipStream_t s);
+
 sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s);
 
 // dst[id[i] * width + w] = src[i * width + w]

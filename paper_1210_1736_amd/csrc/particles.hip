@@ -315,6 +315,21 @@ __global__ void __launch_bounds__(256)
   block_sum_store<kPreVals>(acc, I.pre_partial + (size_t)lb * kPreVals, 4 * sys.ngal);
 }
 
+// Sum of rows values (fixed order) into out[0]; one block of 256 threads.
+__global__ void __launch_bounds__(256) k_reduce_one(const double* __restrict__ part, int rows,
+                                                    double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int r = threadIdx.x; r < rows; r += 256) s += part[r];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // One block per instance: column sums of the partial rows (fixed order:
 // strided per thread, then a fixed tree), then the centres.
 template <typename T>
@@ -664,6 +679,178 @@ __global__ void k_flip(int* cur, int n) {
   if ((int)threadIdx.x < n) cur[threadIdx.x] ^= 1;
 }
 
+
+// ---------------------------------------------------------------- adjoint --
+// Reverse mode of one integration cycle (see the oracle's derivation):
+// lv += dt lx; mu = dt lv; lx += J mu with J the Eq. 8 second differences at
+// the particle; every field the particle reads gets A^T mu on its grid (the
+// Eq. 8 stencil weights transposed).  Adjoint state is kept in float64.
+template <typename T>
+__device__ __forceinline__ void eq8_adjoint(const T* __restrict__ F, T* __restrict__ B,
+                                            const LevelDev& L, const int* id, double dx, double dy,
+                                            double dz, int taylor, const double* mu, double* lx) {
+  const ptrdiff_t sy = L.N, sz = (ptrdiff_t)L.N * L.N;
+  const ptrdiff_t o = (ptrdiff_t)id[2] * sz + (ptrdiff_t)id[1] * sy + id[0];
+  const T* P = F + o;
+  T* Q = B + o;
+  const double Dx = dx - ((double)id[0] - L.half) * L.l;
+  const double Dy = dy - ((double)id[1] - L.half) * L.l;
+  const double Dz = dz - ((double)id[2] - L.half) * L.lz;
+  const double mx = mu[0], my = mu[1], mz = mu[2];
+  if (!taylor) {
+    unsafeAtomicAdd(Q + 1, (T)(mx * L.c_2l));
+    unsafeAtomicAdd(Q - 1, (T)(-mx * L.c_2l));
+    unsafeAtomicAdd(Q + sy, (T)(my * L.c_2l));
+    unsafeAtomicAdd(Q - sy, (T)(-my * L.c_2l));
+    unsafeAtomicAdd(Q + sz, (T)(mz * L.c_2lz));
+    unsafeAtomicAdd(Q - sz, (T)(-mz * L.c_2lz));
+    return;
+  }
+  // J mu from the field's second differences (symmetric)
+  const double p0 = (double)P[0];
+  const double hxx = ((double)P[1] + (double)P[-1] - 2.0 * p0) * L.c_l2;
+  const double hyy = ((double)P[sy] + (double)P[-sy] - 2.0 * p0) * L.c_l2;
+  const double hzz = ((double)P[sz] + (double)P[-sz] - 2.0 * p0) * L.c_lz2;
+  const double hxy = ((double)P[1 + sy] - (double)P[-1 + sy] + (double)P[-1 - sy] - (double)P[1 - sy]) * L.c_4ll;
+  const double hxz = ((double)P[1 + sz] - (double)P[-1 + sz] + (double)P[-1 - sz] - (double)P[1 - sz]) * L.c_4llz;
+  const double hyz = ((double)P[sy + sz] - (double)P[-sy + sz] + (double)P[-sy - sz] - (double)P[sy - sz]) * L.c_4llz;
+  lx[0] += hxx * mx + hxy * my + hxz * mz;
+  lx[1] += hxy * mx + hyy * my + hyz * mz;
+  lx[2] += hxz * mx + hyz * my + hzz * mz;
+  // A^T mu: faces, centre, edges
+  const double wx = mx * Dx * L.c_l2, wy = my * Dy * L.c_l2, wz = mz * Dz * L.c_lz2;
+  unsafeAtomicAdd(Q + 1, (T)(mx * L.c_2l + wx));
+  unsafeAtomicAdd(Q - 1, (T)(-mx * L.c_2l + wx));
+  unsafeAtomicAdd(Q + sy, (T)(my * L.c_2l + wy));
+  unsafeAtomicAdd(Q - sy, (T)(-my * L.c_2l + wy));
+  unsafeAtomicAdd(Q + sz, (T)(mz * L.c_2lz + wz));
+  unsafeAtomicAdd(Q - sz, (T)(-mz * L.c_2lz + wz));
+  unsafeAtomicAdd(Q, (T)(-2.0 * (wx + wy + wz)));
+  const double exy = (mx * Dy + my * Dx) * L.c_4ll;
+  const double exz = (mx * Dz + mz * Dx) * L.c_4llz;
+  const double eyz = (my * Dz + mz * Dy) * L.c_4llz;
+  unsafeAtomicAdd(Q + 1 + sy, (T)exy);
+  unsafeAtomicAdd(Q - 1 + sy, (T)(-exy));
+  unsafeAtomicAdd(Q - 1 - sy, (T)exy);
+  unsafeAtomicAdd(Q + 1 - sy, (T)(-exy));
+  unsafeAtomicAdd(Q + 1 + sz, (T)exz);
+  unsafeAtomicAdd(Q - 1 + sz, (T)(-exz));
+  unsafeAtomicAdd(Q - 1 - sz, (T)exz);
+  unsafeAtomicAdd(Q + 1 - sz, (T)(-exz));
+  unsafeAtomicAdd(Q + sy + sz, (T)eyz);
+  unsafeAtomicAdd(Q - sy + sz, (T)(-eyz));
+  unsafeAtomicAdd(Q - sy - sz, (T)eyz);
+  unsafeAtomicAdd(Q + sy - sz, (T)(-eyz));
+}
+
+// Seed: L = sum over the selected particles of 1/2 m vz^2; dL/dvz = m vz,
+// dL/dm = 1/2 vz^2 (explicit part); loss partial sums per block (fixed order).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_adj_init(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, int sel_comp,
+               int sel_gal, double* __restrict__ lx, double* __restrict__ lv,
+               double* __restrict__ gm, double* __restrict__ partial) {
+  const InstDev<T>& I = inst[0];
+  const PartDev<T> p = I.p[cur[0]];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    lx[3 * i] = lx[3 * i + 1] = lx[3 * i + 2] = 0.0;
+    lv[3 * i] = lv[3 * i + 1] = 0.0;
+    const bool sel = p.comp[i] == sel_comp && p.gal[i] == sel_gal && !p.lost[i];
+    const double m = (double)p.m[i], vz = (double)p.v[2][i];
+    lv[3 * i + 2] = sel ? m * vz : 0.0;
+    gm[i] = sel ? 0.5 * vz * vz : 0.0;
+    if (sel) acc += 0.5 * m * vz * vz;
+  }
+  double v[1] = {acc};
+  block_sum_store<1>(v, partial + blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_adj_step(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, GridsDev<T> Bg,
+               const uint8_t* __restrict__ frozen, double* __restrict__ lx, double* __restrict__ lv) {
+  const InstDev<T>& I = inst[0];
+  const PartDev<T> p = I.p[cur[0]];
+  const SysDev& sys = I.sys;
+  const double dt = I.dt;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n || frozen[i]) return;
+  double l[3] = {lx[3 * i], lx[3 * i + 1], lx[3 * i + 2]};
+  double w[3] = {lv[3 * i] + dt * l[0], lv[3 * i + 1] + dt * l[1], lv[3 * i + 2] + dt * l[2]};
+  lv[3 * i] = w[0];
+  lv[3 * i + 1] = w[1];
+  lv[3 * i + 2] = w[2];
+  const double mu[3] = {dt * w[0], dt * w[1], dt * w[2]};
+  const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+  for (int g = 0; g < sys.ngal; ++g) {
+    const HierDev& h = sys.h[g];
+    const double* c = I.centres + 3 * g;
+    Classified cl;
+    classify(h, c, x, y, z, cl);
+    const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+    const GridsDev<T>& F = I.G;
+    if (h.n_levels == 1) {
+      if (cl.cls == SBX_OUTER) eq8_adjoint(F.g[g][0], Bg.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, sys.taylor, mu, l);
+      continue;
+    }
+    const double ox = x - h.outer_c[0], oy = y - h.outer_c[1], oz = z - h.outer_c[2];
+    switch (cl.cls) {
+      case SBX_CORE:
+        eq8_adjoint(F.g[g][0], Bg.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, sys.taylor, mu, l);
+        eq8_adjoint(F.g[g][1], Bg.g[g][1], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, mu, l);
+        eq8_adjoint(F.g[g][3], Bg.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, mu, l);
+        break;
+      case SBX_RING:
+        eq8_adjoint(F.g[g][2], Bg.g[g][2], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, mu, l);
+        eq8_adjoint(F.g[g][3], Bg.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, mu, l);
+        break;
+      case SBX_OUTER:
+        eq8_adjoint(F.g[g][4], Bg.g[g][4], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, mu, l);
+        break;
+      default:
+        break;
+    }
+  }
+  lx[3 * i] = l[0];
+  lx[3 * i + 1] = l[1];
+  lx[3 * i + 2] = l[2];
+}
+
+template <typename T>
+__device__ __forceinline__ const T* cell_ptr(const T* grid, const LevelDev& L, const int* i) {
+  return grid + ((size_t)i[2] * L.N + i[1]) * L.N + i[0];
+}
+
+// Mass gradient: the adjoint potential psi of every grid a particle feeds,
+// read at its source cell (the transpose of the nearest-grid-point deposit).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_adj_gather(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, GridsDev<T> Pg,
+                 const uint8_t* __restrict__ frozen, double* __restrict__ gm) {
+  const InstDev<T>& I = inst[0];
+  const PartDev<T> p = I.p[cur[0]];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n || frozen[i]) return;
+  const int g = p.gal[i];
+  const HierDev& h = I.sys.h[g];
+  Classified c;
+  classify(h, I.centres + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
+  double s = 0.0;
+  auto at = [&](int slot, int lev) { return (double)*cell_ptr(Pg.g[g][slot], h.lv[lev], c.idx[lev]); };
+  if (h.n_levels == 1) {
+    if (c.cls == SBX_OUTER) s = at(0, 0);
+  } else if (c.cls == SBX_CORE) {
+    s = at(0, 0) + at(2, 1) + at(4, 2);
+  } else if (c.cls == SBX_RING) {
+    s = at(1, 1) + at(2, 1) + at(4, 2);
+  } else if (c.cls == SBX_OUTER) {
+    s = at(3, 2) + at(4, 2);
+  }
+  gm[i] += s;
+}
+
 // ------------------------------------------------------------- readouts ---
 template <typename T>
 __global__ void k_indices(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, int g,
@@ -832,6 +1019,38 @@ sbx_status launch_indices(const InstDev<T>* inst, const int* cur, int64_t n, int
   return SBX_OK;
 }
 
+
+template <typename T>
+sbx_status launch_adj_init(const InstDev<T>* inst, const int* cur, int64_t n, int sel_comp,
+                           int sel_gal, double* lx, double* lv, double* gm, double* partial,
+                           double* loss, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_init<T>), dim3(kRedBlocks), dim3(256), 0, s, inst, cur, sel_comp, sel_gal,
+                     lx, lv, gm, partial);
+  hipLaunchKernelGGL(k_reduce_one, dim3(1), dim3(256), 0, s, partial, kRedBlocks, loss);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_adj_step(const InstDev<T>* inst, const int* cur, int64_t n, const GridsDev<T>& B,
+                           const uint8_t* frozen, double* lx, double* lv, hipStream_t s) {
+  if (n == 0) return SBX_OK;
+  hipLaunchKernelGGL((k_adj_step<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, inst, cur, B,
+                     frozen, lx, lv);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status launch_adj_gather(const InstDev<T>* inst, const int* cur, int64_t n, const GridsDev<T>& P,
+                             const uint8_t* frozen, double* gm, hipStream_t s) {
+  if (n == 0) return SBX_OK;
+  hipLaunchKernelGGL((k_adj_gather<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, inst, cur, P,
+                     frozen, gm);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
 sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_iota, dim3(2048), dim3(256), 0, s, id, n);
   SBX_HIP(hipGetLastError());
@@ -889,6 +1108,15 @@ sbx_status launch_join3(const T* x0, const T* x1, const T* x2, double* dst, int6
                                      uint32_t*, size_t, uint32_t*, hipStream_t);                 \
   template sbx_status launch_indices<T>(const InstDev<T>*, const int*, int64_t, int, int,        \
                                         int32_t*, int8_t*, hipStream_t);                         \
+  template sbx_status launch_adj_init<T>(const InstDev<T>*, const int*, int64_t, int, int,       \
+                                         double*, double*, double*, double*, double*,            \
+                                         hipStream_t);                                           \
+  template sbx_status launch_adj_step<T>(const InstDev<T>*, const int*, int64_t,                 \
+                                         const GridsDev<T>&, const uint8_t*, double*, double*,   \
+                                         hipStream_t);                                           \
+  template sbx_status launch_adj_gather<T>(const InstDev<T>*, const int*, int64_t,               \
+                                           const GridsDev<T>&, const uint8_t*, double*,          \
+                                           hipStream_t);                                         \
   template sbx_status launch_convert_in<T>(const double*, T*, size_t, hipStream_t);              \
   template sbx_status launch_convert_out<T>(const T*, double*, size_t, hipStream_t);             \
   template sbx_status launch_split3<T>(const double*, T*, T*, T*, int64_t, hipStream_t);         \

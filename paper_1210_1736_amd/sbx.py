@@ -90,6 +90,7 @@ def _load():
         "sbx_diag_log": (S, [P, I32, C.POINTER(sbx_diag), C.POINTER(I32)]),
         "sbx_sync": (S, [P]),
         "sbx_set_sort_interval": (S, [P, I32]),
+        "sbx_adjoint_segment": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
         "sbx_count_live": (S, [P, C.POINTER(I64)]),
         "sbx_profile_begin": (S, [P, I32]),
         "sbx_profile_end": (S, [P, I32, P, P]),
@@ -214,6 +215,16 @@ class Context:
 
     def sbx_sync(self):
         _check(_lib.sbx_sync(self._h))
+
+    def sbx_adjoint_segment(self, dt, nsteps, ckpt_every=2, sel_comp=0, sel_gal=0, grads=True):
+        """Loss and gradients of a differentiable segment (see sbx.h)."""
+        loss = np.zeros(1)
+        gm = np.empty(self.n) if grads else None
+        gx = np.empty((self.n, 3)) if grads else None
+        gv = np.empty((self.n, 3)) if grads else None
+        _check(_lib.sbx_adjoint_segment(self._h, float(dt), int(nsteps), int(ckpt_every), int(sel_comp),
+                                        int(sel_gal), _ptr(loss), _ptr(gm), _ptr(gx), _ptr(gv)))
+        return float(loss[0]), gm, gx, gv
 
     def sbx_set_sort_interval(self, every):
         _check(_lib.sbx_set_sort_interval(self._h, int(every)))

@@ -1,0 +1,175 @@
+"""GPU parity of the differentiable segment: the library's reverse mode
+(sbx_adjoint_segment) against the oracle's reverse mode and against central
+finite differences of the library's own forward.
+
+Bars: FP64 loss within 1e-12 relative; gradients within 1e-9 of their
+largest magnitude (the forward trajectories agree to ~1e-13; deposit and
+adjoint scatter use FP64 atomics, so sums differ in rounding order only).
+FP32 form (FP32 particles and fields, FP64 adjoint state): loss within 1e-6
+relative; dL/dm and dL/dv within 1e-5, dL/dx within 1e-4 of their largest
+magnitude (dL/dx carries second differences of the FP32 field).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pm_oracle as O
+from tests import common as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sbx():
+    from paper_1210_1736_amd import sbx as m
+    return m
+
+
+def _rng(k):
+    return np.random.default_rng(np.random.SeedSequence([1210, 1736, 960, k]))
+
+
+def _workload(kind, n=3000, seed=1):
+    """A flattened cloud on one fixed grid or three nested fixed grids."""
+    rng = _rng(seed)
+    x = rng.normal(size=(n, 3)) * np.array([0.6, 0.6, 0.15])
+    v = rng.normal(size=(n, 3)) * 0.3
+    m = rng.uniform(0.5, 1.5, n) / n
+    comp = (rng.uniform(size=n) < 0.5).astype(np.int8)
+    gal = np.zeros(n, np.int8)
+    if kind == "single":
+        hs = synth.HierSpec([synth.LevelSpec(32, 2.5, 1.0)])
+    else:
+        hs = synth.HierSpec([synth.LevelSpec(32, 0.5, 0.5), synth.LevelSpec(32, 1.5, 0.5),
+                             synth.LevelSpec(32, 4.0, 1.0)], centring="fixed")
+    return synth.Workload("adjoint-" + kind, x, v, m, comp, gal, [hs], 0.02, 5)
+
+
+def _maxrel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("kind", ["single", "nested"])
+@pytest.mark.parametrize("ckpt", [1, 2, 5])
+def test_adjoint_matches_oracle_fp64(sbx, kind, ckpt):
+    w = _workload(kind)
+    ctx = T.make_ctx(w, sbx.SBX_FP64)
+    L, gm, gx, gv = ctx.sbx_adjoint_segment(w.dt, w.steps, ckpt, 1, 0)
+    Lr, gmr, gxr, gvr = O.segment_loss_and_grads(T.oracle_system(w), w.x, w.v, w.m, w.comp, w.gal,
+                                                  w.dt, w.steps, 1, 0)
+    assert L == pytest.approx(Lr, rel=1e-12)
+    for a, b in ((gm, gmr), (gx, gxr), (gv, gvr)):
+        assert _maxrel(a, b) < 1e-9
+    # the context is left at the end of the segment, as sbx_step would leave it
+    ref = T.make_ctx(w, sbx.SBX_FP64)
+    ref.sbx_step(w.dt, w.steps)
+    xa, va, la = ctx.sbx_get_particles()
+    xb, vb, lb = ref.sbx_get_particles()
+    assert np.array_equal(la, lb)
+    assert np.abs(xa - xb).max() < 1e-13 and np.abs(va - vb).max() < 1e-12
+
+
+def test_adjoint_two_galaxies_fp64(sbx):
+    """Galaxy with a satellite (its own single grid on the shared global
+    level); selected component in the second galaxy."""
+    w = _workload("nested", n=2000, seed=2)
+    rng = _rng(3)
+    ns = 500
+    xs = rng.normal(size=(ns, 3)) * 0.2 + np.array([1.5, 0.3, 0.0])
+    vs = rng.normal(size=(ns, 3)) * 0.1 + np.array([0.0, 0.5, 0.0])
+    w.x = np.vstack([w.x, xs]); w.v = np.vstack([w.v, vs])
+    w.m = np.concatenate([w.m, np.full(ns, 0.3 / ns)])
+    w.comp = np.concatenate([w.comp, np.full(ns, 2, np.int8)])
+    w.gal = np.concatenate([w.gal, np.ones(ns, np.int8)])
+    sat = synth.HierSpec([synth.LevelSpec(32, 0.6, 1.0), synth.LevelSpec(32, 1.5, 1.0),
+                          synth.LevelSpec(32, 4.0, 1.0)], centring="fixed", centre=(1.5, 0.3, 0.0))
+    w.hier = [w.hier[0], sat]
+    ctx = T.make_ctx(w, sbx.SBX_FP64)
+    L, gm, gx, gv = ctx.sbx_adjoint_segment(w.dt, 4, 2, 2, 1)
+    Lr, gmr, gxr, gvr = O.segment_loss_and_grads(T.oracle_system(w), w.x, w.v, w.m, w.comp, w.gal,
+                                                  w.dt, 4, 2, 1)
+    assert L == pytest.approx(Lr, rel=1e-12)
+    for a, b in ((gm, gmr), (gx, gxr), (gv, gvr)):
+        assert _maxrel(a, b) < 1e-9
+
+
+def test_adjoint_matches_finite_differences_on_gpu(sbx):
+    """Central differences of the library's own forward loss, for 32 seeded
+    particles (mass, one velocity and one position component each)."""
+    w = _workload("nested", seed=4)
+    ctx = T.make_ctx(w, sbx.SBX_FP64)
+    _, gm, gx, gv = ctx.sbx_adjoint_segment(w.dt, w.steps, 2, 1, 0)
+    sel = (w.comp == 1) & (w.gal == 0)
+    fwd = T.make_ctx(w, sbx.SBX_FP64)
+
+    def loss(x, v, m):
+        fwd.sbx_load_particles(x, v, m, w.comp, w.gal)
+        fwd.sbx_step(w.dt, w.steps)
+        _, vg, lg = fwd.sbx_get_particles()
+        s = sel & ~lg
+        return 0.5 * np.sum(m[s] * vg[s, 2] ** 2)
+
+    rng = _rng(5)
+    for q in rng.choice(w.n, 32, replace=False):
+        eps = 1e-4 * w.m[q]
+        mp = w.m.copy(); mp[q] += eps
+        mm = w.m.copy(); mm[q] -= eps
+        fd = (loss(w.x, w.v, mp) - loss(w.x, w.v, mm)) / (2 * eps)
+        assert fd == pytest.approx(gm[q], rel=2e-5, abs=1e-9 * np.abs(gm).max())
+        a = int(rng.integers(0, 3))
+        h = 1e-7
+        vp = w.v.copy(); vp[q, a] += h
+        vm = w.v.copy(); vm[q, a] -= h
+        fd = (loss(w.x, vp, w.m) - loss(w.x, vm, w.m)) / (2 * h)
+        assert fd == pytest.approx(gv[q, a], rel=1e-4, abs=1e-6 * np.abs(gv).max())
+        xp = w.x.copy(); xp[q, a] += h
+        xm = w.x.copy(); xm[q, a] -= h
+        fd = (loss(xp, w.v, w.m) - loss(xm, w.v, w.m)) / (2 * h)
+        assert fd == pytest.approx(gx[q, a], rel=1e-4, abs=1e-6 * np.abs(gx).max())
+
+
+def test_adjoint_fp32_form(sbx):
+    w = _workload("nested", seed=6)
+    ctx = T.make_ctx(w, sbx.SBX_FP32)
+    L, gm, gx, gv = ctx.sbx_adjoint_segment(w.dt, w.steps, 2, 1, 0)
+    x, v, m = T.oracle_inputs(w, sbx.SBX_FP32)
+    Lr, gmr, gxr, gvr = O.segment_loss_and_grads(T.oracle_system(w), x, v, m, w.comp, w.gal,
+                                                  w.dt, w.steps, 1, 0)
+    errs = [_maxrel(a, b) for a, b in ((gm, gmr), (gx, gxr), (gv, gvr))]
+    print(f"FP32 adjoint: loss {abs(L / Lr - 1):.2e}, grad m/x/v {errs[0]:.2e} {errs[1]:.2e} {errs[2]:.2e}")
+    assert L == pytest.approx(Lr, rel=1e-6)
+    assert errs[0] < 1e-5 and errs[1] < 1e-4 and errs[2] < 1e-5
+
+
+def test_adjoint_autograd_function(sbx):
+    import torch
+    from paper_1210_1736_amd.autograd import segment_loss
+    w = _workload("single", n=1000, seed=7)
+    ctx = T.make_ctx(w, sbx.SBX_FP64)
+    x = torch.tensor(w.x, requires_grad=True)
+    v = torch.tensor(w.v, requires_grad=True)
+    m = torch.tensor(w.m, requires_grad=True)
+    L = segment_loss(ctx, x, v, m, w.comp, w.gal, w.dt, 3, 1, 1, 0)
+    (2.0 * L).backward()
+    Lr, gmr, gxr, gvr = O.segment_loss_and_grads(T.oracle_system(w), w.x, w.v, w.m, w.comp, w.gal,
+                                                  w.dt, 3, 1, 0)
+    assert float(L.detach()) == pytest.approx(Lr, rel=1e-12)
+    assert _maxrel(m.grad.numpy(), 2 * gmr) < 1e-9
+    assert _maxrel(x.grad.numpy(), 2 * gxr) < 1e-9
+    assert _maxrel(v.grad.numpy(), 2 * gvr) < 1e-9
+
+
+def test_adjoint_rejects_bad_arguments(sbx):
+    w = _workload("single", n=200, seed=8)
+    ctx = T.make_ctx(w, sbx.SBX_FP64)
+    for args in ((w.dt, 0, 1), (w.dt, 2, 0), (float("nan"), 2, 1)):
+        with pytest.raises(sbx.SbxError):
+            ctx.sbx_adjoint_segment(*args)
+    with pytest.raises(sbx.SbxError):
+        ctx.sbx_adjoint_segment(w.dt, 2, 1, sel_comp=9)
+    with pytest.raises(sbx.SbxError):
+        ctx.sbx_adjoint_segment(w.dt, 2, 1, sel_gal=1)
+    g = T.small_galaxy(scale=0.001, N=32, centring="com", q=1.0)
+    c2 = T.make_ctx(g, sbx.SBX_FP64)
+    with pytest.raises(sbx.SbxError):
+        c2.sbx_adjoint_segment(g.dt, 2, 1)
