@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FFT_PASSES = ("fwd_x", "fwd_y", "zpass", "inv_y", "inv_x")
 
 
 def _log(msg):
@@ -62,6 +63,35 @@ def phase_bytes(phase, N, nsolves, n_live, esz):
     if phase == "force":    # x, v, gal, lost read; x, v written; fields read once
         return n_live * (12 * esz + 2) + grids
     return 0
+
+
+KERNEL_SOURCES = ["paper_1210_1736_amd/csrc/particles.hip", "paper_1210_1736_amd/csrc/particles.h",
+                  "paper_1210_1736_amd/csrc/common.h", "paper_1210_1736_amd/csrc/fft.hip",
+                  "paper_1210_1736_amd/csrc/fft.h"]
+PROFILE = "profiles/step_kernels_disc_galaxy_3x128_fp32.md"
+PHASE_KERNEL = {"deposit": "k_deposit<float>", "force": "k_force<float, 1>", "pre": "k_pre<float>"}
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch of the phase's kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    try:
+        for f in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        text = open(os.path.join(ROOT, PROFILE)).read()
+    except OSError:
+        return None
+    if f"Kernel-source hash: {h.hexdigest()[:16]}" not in text or phase not in PHASE_KERNEL:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip("|").split("|")]
+        if len(cells) == 5 and cells[0] == PHASE_KERNEL[phase]:
+            return float(cells[4]) * 1e6
+    return None
 
 
 def time_solves(sbx, torch, N, R, q, prec, batch, iters):
@@ -119,6 +149,99 @@ def timed_steps(sbx, torch, w, prec, steps, warmup, diag_every, profile=True, so
     return t1 - t0, 0.5 * (live0 + live1), phases
 
 
+def precision_errors(sbx, w):
+    """Force and potential error of the FP32 form at the initial state of the
+    workload, against the FP64 form (which the parity tests hold within 1e-9
+    of the FP64 oracle): per-particle |a32 - a64| over rms|a64|, and
+    max|phi32 - phi64| over max|phi64|."""
+    import dataclasses
+    out = {}
+    res = {}
+    # both forms start from the same (FP32-representable) inputs, so that
+    # cells and classes agree and only the arithmetic differs
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    w = dataclasses.replace(w, x=f32(w.x), v=f32(w.v), m=f32(w.m))
+    for name, prec in (("fp64", sbx.SBX_FP64), ("fp32", sbx.SBX_FP32)):
+        ctx = make_ctx(sbx, w, prec)
+        res[name] = ctx.sbx_compute_forces()
+        ctx.close()
+    a64, p64 = res["fp64"]
+    a32, p32 = res["fp32"]
+    rms = float(np.sqrt(np.mean(np.sum(a64 * a64, axis=1))))
+    e = np.linalg.norm(a32 - a64, axis=1) / rms
+    out["reference"] = "FP64 GPU form on the same FP32-rounded inputs"
+    out["force_rel_p99"] = float(np.percentile(e, 99))
+    out["force_rel_max"] = float(e.max())
+    out["pot_rel_max"] = float(np.abs(p32 - p64).max() / np.abs(p64).max())
+    return out
+
+
+def galaxy_satellite_rate(sbx, torch, steps, warmup):
+    """Galaxy plus satellite: two 3-level hierarchies, 10 solves per step."""
+    import synth
+    w = synth.galaxy_satellite()
+    t, live, _ = timed_steps(sbx, torch, w, sbx.SBX_FP32, steps, warmup, 10, profile=False)
+    return {"workload": "disc galaxy + Plummer satellite (200k, M 0.1), two 3-level 128^3 "
+                        "hierarchies, FP32, diagnostics every 10 steps",
+            "particles_live": live, "solves_per_step": 10, "steps": steps,
+            "particle_steps_per_s": live * steps / t, "ms_per_step": 1e3 * t / steps}
+
+
+def ensemble_rate(sbx, torch, steps, warmup):
+    """16 independent galaxy + satellite instances of uneven size stepped as
+    one batch (one graph replay per step)."""
+    import synth
+    ws = synth.ensemble()
+    ctxs = [make_ctx(sbx, w, sbx.SBX_FP32) for w in ws]
+    b = sbx.Batch(ctxs)
+    b.sbx_batch_step(0.01, warmup)
+    b.sbx_batch_sync()
+    live0 = sum(c.sbx_count_live() for c in ctxs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.sbx_batch_step(0.01, steps)
+    b.sbx_batch_sync()
+    t1 = time.perf_counter()
+    live1 = sum(c.sbx_count_live() for c in ctxs)
+    sizes = [w.hier[0].levels[0].N for w in ws]
+    b.close()
+    for c in ctxs:
+        c.close()
+    live = 0.5 * (live0 + live1)
+    return {"workload": "16 galaxy + satellite instances, grids " +
+                        ", ".join(f"{sizes.count(N)} x {N}^3" for N in sorted(set(sizes))) +
+                        f", {sum(w.n for w in ws)} particles, FP32",
+            "instances": len(ws), "solves_per_step": 10 * len(ws), "steps": steps,
+            "particles_live": live, "particle_steps_per_s": live * steps / (t1 - t0),
+            "ms_per_step": 1e3 * (t1 - t0) / steps}
+
+
+def adjoint_rate(sbx, torch):
+    """Differentiable segment: 10 steps forward and the reverse mode with
+    checkpoints every 2 steps, gradients for every particle."""
+    import synth
+    w = synth.adjoint_segment()
+    ctx = make_ctx(sbx, w, sbx.SBX_FP32)
+    ctx.sbx_step(w.dt, 1)
+    ctx.sbx_sync()
+    t0 = time.perf_counter()
+    ctx.sbx_step(w.dt, w.steps)
+    ctx.sbx_sync()
+    t1 = time.perf_counter()
+    ctx.sbx_adjoint_segment(w.dt, w.steps, 2, synth.DISC, 0)   # allocations, first use
+    t2 = time.perf_counter()
+    loss, gm, gx, gv = ctx.sbx_adjoint_segment(w.dt, w.steps, 2, synth.DISC, 0)
+    t3 = time.perf_counter()
+    ctx.close()
+    return {"workload": "one 256^3 grid, 1M disc + 1M halo + 50k satellite, FP32, 10 steps, "
+                        "checkpoints every 2 steps, loss = disc vertical kinetic energy",
+            "particles": w.n, "forward_s": t1 - t0, "segment_s": t3 - t2,
+            "segment_over_forward": (t3 - t2) / (t1 - t0),
+            "includes": "forward with checkpoints, recomputation, reverse cycles, gradient "
+                        "copies to the host",
+            "loss": loss, "grad_finite": bool(np.isfinite(gm).all() and np.isfinite(gx).all())}
+
+
 def cpu_baseline(w, frac):
     """The FP64 oracle, as it stands, on a bounded sample: one step of the
     same galaxy with a random `frac` of its particles (same grids)."""
@@ -157,6 +280,13 @@ def main():
     ap.add_argument("--step-only", action="store_true",
                     help="only the FP32 step loop (for profiler runs)")
     ap.add_argument("--sort-every", type=int, default=None)
+    ap.add_argument("--extra-steps", type=int, default=20,
+                    help="timed steps of the galaxy + satellite and ensemble workloads")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy a buffer of this many MiB three times (a plain copy "
+                         "kernel of known size, to scale hardware byte counters)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the precision, satellite, ensemble and adjoint measurements")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -166,6 +296,14 @@ def main():
     import torch
     import synth
     from paper_1210_1736_amd import sbx
+
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     _log("generating the 3 x 128^3 disc-galaxy workload (8.5M particles)")
     w = synth.disc_galaxy(scale=1.0)
@@ -181,6 +319,7 @@ def main():
     if args.step_only:
         args.no_fp64 = True
         args.no_cpu_baseline = True
+        args.no_extra = True
     fp64 = None
     if not args.no_fp64:
         _log(f"FP64: {args.fp64_steps} timed steps")
@@ -198,6 +337,17 @@ def main():
             solves[f"{name}_batch{batch}"] = {"solves_per_s": rate, "ms_per_batch": ms}
     torch.cuda.synchronize()
 
+    extra = {}
+    if not args.no_extra:
+        _log("FP32 force and potential error against the FP64 form")
+        extra["precision"] = precision_errors(sbx, w)
+        _log("galaxy + satellite")
+        extra["galaxy_satellite"] = galaxy_satellite_rate(sbx, torch, args.extra_steps, 2)
+        _log("ensemble of 16 instances")
+        extra["ensemble"] = ensemble_rate(sbx, torch, args.extra_steps, 2)
+        _log("differentiable segment")
+        extra["adjoint"] = adjoint_rate(sbx, torch)
+
     # roofline of the dominant kernel of the FP32 step
     steps = args.steps
     per_step = {k: v[0] / steps for k, v in ph32.items() if v[1]}
@@ -207,7 +357,7 @@ def main():
     by = phase_bytes(dom, N, nsolves, live32, 4)
     achieved = by / (avg_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
             "bytes_per_launch": by, "avg_launch_ms": avg_ms}
     step_bytes = sum(phase_bytes(k, N, nsolves, live32, 4) for k in per_step)
     step_roof = step_bytes / (t32 / steps) / 1e9
@@ -237,6 +387,8 @@ def main():
         "fp64": fp64,
         "solves": solves,
         "phases_ms_per_step": per_step,
+        "solves_in_step_per_s": nsolves / (1e-3 * sum(per_step.get(k, 0.0) for k in FFT_PASSES)),
+        **extra,
         "step_effective_GBs": step_roof,
         "roofline": roof,
         "cpu_baseline": cpu,

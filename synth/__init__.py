@@ -346,3 +346,26 @@ def ensemble(n_inst=16, workload=4, steps=200, scale=1.0, sizes=(64, 128, 256), 
                       centring="com")
         out.append(Workload(f"instance{k}_N{N}", x, v, m, comp, gal, [hg, hs], dt=0.01, steps=steps))
     return out
+
+
+def adjoint_segment(scale=1.0, N=256, workload=5, steps=10):
+    """Differentiable segment: one fixed 256^3 grid of half-extent 12 holding
+    1M disc and 1M halo particles (disc-galaxy shapes; the halo cut at 11.5 so
+    that every particle starts on the grid) and a 50k-particle Plummer
+    satellite (M = 0.1, a = 0.6, cut at 3 so that it fits on the grid) at
+    radius 8 in the disc plane on a circular orbit; all in one galaxy, the
+    satellite as its own component."""
+    gm = GalaxyModel(n_disc=int(1_000_000 * scale), n_bulge=0, n_halo=int(1_000_000 * scale),
+                     rc_halo=11.5)
+    x, v, m, comp, Menc = galaxy(workload, gm)
+    ns = int(50_000 * scale)
+    rng = rng_for(workload, SAT)
+    ps, rs = plummer_positions(rng, ns, 0.6, 3.0)
+    vs = plummer_velocities(rng, rs, 0.1, 0.6)
+    X0, V0 = point_mass_orbit(float(Menc(8.0)), 8.0, 0.0, 0.0)
+    x = np.concatenate([x, ps + X0]); v = np.concatenate([v, vs + V0])
+    m = np.concatenate([m, np.full(ns, 0.1 / ns)])
+    comp = np.concatenate([comp, np.full(ns, SAT, np.int8)])
+    h = HierSpec([LevelSpec(N, 12.0, 1.0)])
+    return Workload("adjoint_segment_256", x, v, m, comp, np.zeros(x.shape[0], np.int8), [h],
+                    dt=0.01, steps=steps)
