@@ -11,6 +11,7 @@
 #include <array>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "fft.h"
 
@@ -19,74 +20,163 @@ namespace sbx {
 __device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
 
 // ------------------------------------------------------------- Stockham ---
-// One pass of radix R with stride NS over a line in LDS (in place).
-// Threads without a line (act = false) only take part in the barriers.
-template <typename T, int L, int R, int NS, bool INV, bool PIN, bool POUT>
-__device__ __forceinline__ void st_pass(C2<T>* line, int t, const C2<T>* __restrict__ tw, bool act) {
-  constexpr int TL = L / 16, NB = L / R, BPT = NB / TL;
-  C2<T> v[BPT][R];
-  if (act) {
-#pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-      const int j = t + b * TL;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (PIN && r >= R / 2) v[b][r] = C2<T>{(T)0, (T)0};
-        else v[b][r] = line[pad(j + r * NB)];
-      }
-    }
-  }
-  __syncthreads();
-  if (act) {
-#pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int j = t + b * TL;
-    const int k = j & (NS - 1);
-    if constexpr (NS > 1) {
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        C2<T> w = tw[(r - 1) * NS + k];
-        if (INV) w.im = -w.im;
-        v[b][r] = cmul(v[b][r], w);
-      }
-    }
-    dftR<R, INV>(v[b]);
-    const int base = (j / NS) * NS * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (POUT && r >= R / 2) continue;
-      line[pad(base + r * NS)] = v[b][r];
-    }
-  }
-  }
-  __syncthreads();
+// A line of length L is transformed by TL = L/16 threads of one wavefront
+// (64/TL lines per wave), so the exchanges between radix passes go through
+// LDS with wave-level ordering only.  Passes: radix 16 (stride 1), then
+// radix L/16 (L <= 256) or 16 (L = 512) with stride 16, then for L = 512 a
+// radix-2 pass with stride 256.  Every thread holds 16 values per pass
+// (16/R butterflies of radix R).
+//
+// Forward pass p (decimation in time, Stockham autosort): butterfly j reads
+// positions j + r*L/R, multiplies by twiddles, takes the R-point DFT and
+// writes positions (j - k) R + k + r NS, k = j mod NS.  The inverse
+// transform runs the conjugate transposes of the same passes in reverse
+// order (gather from the output positions, inverse DFT, conjugate twiddles,
+// scatter to the input positions).  The last forward pass reads and writes
+// the same positions, which is what lets the z pass apply the Green's
+// function and the first inverse pass in registers.
+template <int L>
+struct Line {
+  static constexpr int TL = L / 16;
+  static constexpr int NP = L == 16 ? 1 : (L <= 256 ? 2 : 3);
+  template <int p>
+  static constexpr int R = p == 0 ? 16 : (p == 1 ? (L <= 256 ? L / 16 : 16) : 2);
+  template <int p>
+  static constexpr int NS = p == 0 ? 1 : (p == 1 ? 16 : 256);
+  template <int p>
+  static constexpr int TW = p == 2 ? 240 : 0;  // offset of the pass in the twiddle table
+};
+
+// Order the LDS accesses of one wavefront (they execute in issue order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Full length-L transform of one line by the TL threads t = 0..TL-1.
-// PIN: input is zero in [L/2, L); POUT: only [0, L/2) of the output is kept.
-template <typename T, int L, bool INV, bool PIN, bool POUT>
-__device__ __forceinline__ void fft_line(C2<T>* line, int t, const C2<T>* __restrict__ tw,
-                                         bool act) {
-  if constexpr (L == 16) {
-    st_pass<T, L, 16, 1, INV, PIN, POUT>(line, t, tw, act);
-  } else if constexpr (L == 32) {
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
-    st_pass<T, L, 2, 16, INV, false, POUT>(line, t, tw, act);
-  } else if constexpr (L == 64) {
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
-    st_pass<T, L, 4, 16, INV, false, POUT>(line, t, tw, act);
-  } else if constexpr (L == 128) {
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
-    st_pass<T, L, 8, 16, INV, false, POUT>(line, t, tw, act);
-  } else if constexpr (L == 256) {
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
-    st_pass<T, L, 16, 16, INV, false, POUT>(line, t, tw, act);
-  } else {
-    static_assert(L == 512, "L in 16..512");
-    st_pass<T, L, 16, 1, INV, PIN, false>(line, t, tw, act);
-    st_pass<T, L, 16, 16, INV, false, false>(line, t, tw, act);
-    st_pass<T, L, 2, 256, INV, false, POUT>(line, t, tw + 240, act);
+template <int L, int p>
+__device__ __forceinline__ int pos_in(int j, int r) {
+  return j + r * (L / Line<L>::template R<p>);
+}
+template <int L, int p>
+__device__ __forceinline__ int pos_out(int j, int r) {
+  constexpr int NS = Line<L>::template NS<p>, R = Line<L>::template R<p>;
+  const int k = j & (NS - 1);
+  return (j - k) * R + k + r * NS;
+}
+
+template <typename T, int L, int p>
+__device__ __forceinline__ void fwd_bfly(C2<T>* v, int t, const C2<T>* __restrict__ tw) {
+  using F = Line<L>;
+  constexpr int R = F::template R<p>, NS = F::template NS<p>, BPT = 16 / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    if constexpr (NS > 1) {
+      const int k = (t + b * F::TL) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r)
+        v[b * R + r] = cmul(v[b * R + r], tw[F::template TW<p> + (r - 1) * NS + k]);
+    }
+    dftR<R, false>(v + b * R);
   }
+}
+
+template <typename T, int L, int p>
+__device__ __forceinline__ void inv_bfly(C2<T>* v, int t, const C2<T>* __restrict__ tw) {
+  using F = Line<L>;
+  constexpr int R = F::template R<p>, NS = F::template NS<p>, BPT = 16 / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    dftR<R, true>(v + b * R);
+    if constexpr (NS > 1) {
+      const int k = (t + b * F::TL) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r)
+        v[b * R + r] = cmul(v[b * R + r], conjc(tw[F::template TW<p> + (r - 1) * NS + k]));
+    }
+  }
+}
+
+// LDS gathers and scatters of one line (padded by one element per 16).
+// ZHI: the upper half of the line's input is zero (padded input).
+template <typename T, int L, int p, bool ZHI>
+__device__ __forceinline__ void gather_in(const C2<T>* s, int t, C2<T>* v) {
+  constexpr int R = Line<L>::template R<p>, BPT = 16 / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      v[b * R + r] = (ZHI && r >= R / 2) ? C2<T>{(T)0, (T)0}
+                                         : s[pad(pos_in<L, p>(t + b * Line<L>::TL, r))];
+}
+// HALF: only positions below L/2 are kept (cropped output).
+template <typename T, int L, int p, bool HALF>
+__device__ __forceinline__ void scatter_in(C2<T>* s, int t, const C2<T>* v) {
+  constexpr int R = Line<L>::template R<p>, BPT = 16 / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (!HALF || r < R / 2) s[pad(pos_in<L, p>(t + b * Line<L>::TL, r))] = v[b * R + r];
+}
+template <typename T, int L, int p>
+__device__ __forceinline__ void gather_out(const C2<T>* s, int t, C2<T>* v) {
+  constexpr int R = Line<L>::template R<p>, BPT = 16 / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b * R + r] = s[pad(pos_out<L, p>(t + b * Line<L>::TL, r))];
+}
+template <typename T, int L, int p>
+__device__ __forceinline__ void scatter_out(C2<T>* s, int t, const C2<T>* v) {
+  constexpr int R = Line<L>::template R<p>, BPT = 16 / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[pad(pos_out<L, p>(t + b * Line<L>::TL, r))] = v[b * R + r];
+}
+
+// Forward passes PS..NP-1 on an LDS line, in place; v holds the inputs of
+// pass PS on entry (already gathered) and the last pass's outputs (natural
+// order, positions j + r L/R) on exit, also written to LDS when STORE.
+template <typename T, int L, int PS, bool STORE>
+__device__ __forceinline__ void fwd_from(C2<T>* s, int t, C2<T>* v, const C2<T>* __restrict__ tw) {
+  constexpr int NP = Line<L>::NP;
+  fwd_bfly<T, L, PS>(v, t, tw);
+  if constexpr (PS + 1 < NP) {
+    scatter_out<T, L, PS>(s, t, v);
+    wave_sync();
+    gather_in<T, L, PS + 1, false>(s, t, v);
+    wave_sync();
+    fwd_from<T, L, PS + 1, STORE>(s, t, v, tw);
+  } else if constexpr (STORE) {
+    scatter_out<T, L, PS>(s, t, v);
+  }
+}
+
+// Inverse passes PE..0 (conjugate transposes, reverse order); v holds the
+// inputs of pass PE (gathered at its output positions) on entry and the
+// natural-order results of pass 0 (positions t + r TL) on exit.
+template <typename T, int L, int PE>
+__device__ __forceinline__ void inv_down(C2<T>* s, int t, C2<T>* v, const C2<T>* __restrict__ tw) {
+  inv_bfly<T, L, PE>(v, t, tw);
+  if constexpr (PE > 0) {
+    scatter_in<T, L, PE, false>(s, t, v);
+    wave_sync();
+    gather_out<T, L, PE - 1>(s, t, v);
+    wave_sync();
+    inv_down<T, L, PE - 1>(s, t, v, tw);
+  }
+}
+
+// Full forward transform of a line held in LDS in natural order (in place).
+template <typename T, int L>
+__device__ __forceinline__ void line_fwd_lds(C2<T>* s, int t, const C2<T>* __restrict__ tw) {
+  C2<T> v[16];
+  gather_in<T, L, 0, false>(s, t, v);
+  wave_sync();
+  fwd_from<T, L, 0, true>(s, t, v, tw);
+  wave_sync();
 }
 
 // Twiddle table for length L: for every pass after the first, entries
@@ -152,49 +242,67 @@ template const C2<float>* twiddles<float>(int, hipStream_t);
 template const C2<double>* twiddles<double>(int, hipStream_t);
 
 // ------------------------------------------------------------ tile shape ---
-// A block of NT threads transforms W lines of length L; TL = L/16 threads
-// per line.  W is capped by the tile dimension (N) and by 64 KB of LDS;
-// threads beyond W * TL only help with loads, stores and barriers.
-template <typename T, int L, int NT>
+// A block of NT threads covers WT = NT/TL lines at a time.  The z pass takes
+// W = WT lines per tile (each wave its own lines, no block barrier).  The x
+// and y passes, whose other side is strided across lines, take at least
+// 128 bytes of lines per tile (the block loops over them in rounds) within
+// the LDS budget; a tile's lines are staged in LDS for the strided side.
+constexpr int kLdsCap = 81920;  // two blocks per compute unit
+
+template <typename T, int L, int NT, int PASS>
 struct TC {
   static constexpr int N = L / 2;
   static constexpr int TL = L / 16;
   static constexpr int P = L + L / 16 + 1;  // LDS pitch of one line
-  static constexpr int W0 = NT / TL < N ? NT / TL : N;
-  static constexpr int WLDS = 65536 / (P * (int)sizeof(C2<T>));
-  static constexpr int W1 = W0 <= WLDS ? W0 : (WLDS >= 16 ? 16 : (WLDS >= 8 ? 8 : (WLDS >= 4 ? 4 : 2)));
-  static constexpr int W = W1 < 1 ? 1 : W1;
-  static constexpr int LDS = W * P;         // elements of C2<T>
+  static constexpr int LB = P * (int)sizeof(C2<T>);
+  static constexpr int WT = NT / TL;
+  static constexpr int WC = 128 / (int)sizeof(C2<T>);
+  static constexpr int fitw(int w) { return (w > 1 && w * LB > kLdsCap) ? fitw(w / 2) : w; }
+  static constexpr int Wx0 = (WT > WC ? WT : WC) < N ? (WT > WC ? WT : WC) : N;
+  static constexpr int W = PASS == 2 ? (WT < L ? WT : L) : fitw(Wx0);
+  static constexpr bool fits = W * LB <= kLdsCap;
+  static constexpr int LDS = fits ? W * P : 1;  // elements of C2<T>
+  static constexpr int ROUNDS = (W + WT - 1) / WT;
 };
 
 // tiles of each pass for one solve of line length L
 template <typename T, int L, int NT>
 __host__ __device__ constexpr int tiles_of(int pass) {
-  constexpr int N = L / 2, W = TC<T, L, NT>::W;
-  return pass == 0 ? N * (N / W)
-       : pass == 1 ? (N + 1) * (N / W)
-       : pass == 2 ? (N + 1) * (L / W)
-       : pass == 3 ? (N + 1) * (N / W)
-                   : N * (N / W);
+  constexpr int N = L / 2;
+  return pass == 0 ? N * (N / TC<T, L, NT, 0>::W)
+       : pass == 1 ? (N + 1) * (N / TC<T, L, NT, 1>::W)
+       : pass == 2 ? (N + 1) * (L / TC<T, L, NT, 2>::W)
+       : pass == 3 ? (N + 1) * (N / TC<T, L, NT, 3>::W)
+                   : N * (N / TC<T, L, NT, 4>::W);
+}
+
+template <typename T, int L, int NT, int PASS>
+__host__ __device__ constexpr bool shape_fits() {
+  return TC<T, L, NT, PASS>::fits;
 }
 
 // ------------------------------------------------------------ the passes ---
-// fwd_x: tile = W consecutive y at one z; real input, x < N.
+// fwd_x: tile = W consecutive y at one z; real input x < N read straight into
+// registers; output X[kx][z][y] (kx <= N) staged in LDS, stored across lines.
 template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT>;
+  using K = TC<T, L, NT, 0>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, t = tid % TL;
   const int z = tile / (N / W), y0 = (tile % (N / W)) * W;
-  const T* __restrict__ src = d.rho + ((size_t)z * N + y0) * N;
-  for (int i = tid; i < W * N; i += NT) {
-    const int w = i / N, e = i - w * N;
-    s[w * P + pad(e)] = C2<T>{src[i], (T)0};
+#pragma unroll 1
+  for (int u = 0; u < K::ROUNDS; ++u) {
+    const int w = u * K::WT + tid / TL;
+    if (w < W) {
+      const T* __restrict__ src = d.rho + ((size_t)z * N + y0 + w) * N;
+      C2<T> v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = r < 8 ? C2<T>{src[t + r * TL], (T)0} : C2<T>{(T)0, (T)0};
+      fwd_from<T, L, 0, true>(s + w * P, t, v, tw);
+    }
   }
   __syncthreads();
-  const bool act = tid < W * TL;
-  fft_line<T, L, false, true, false>(s + (act ? tid / TL : 0) * P, tid % TL, tw, act);
   C2<T>* __restrict__ dst = d.X + (size_t)z * N + y0;
   for (int i = tid; i < W * (N + 1); i += NT) {
     const int e = i / W, w = i - e * W;
@@ -202,22 +310,27 @@ __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T
   }
 }
 
-// fwd_y: tile = W consecutive z at one kx; input y < N contiguous.
+// fwd_y: tile = W consecutive z at one kx; each line (y < N, contiguous) read
+// straight into registers; output C[kx][ky][z] stored across lines.
 template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT>;
+  using K = TC<T, L, NT, 1>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, t = tid % TL;
   const int kx = tile / (N / W), z0 = (tile % (N / W)) * W;
-  const C2<T>* __restrict__ src = d.X + ((size_t)kx * N + z0) * N;
-  for (int i = tid; i < W * N; i += NT) {
-    const int w = i / N, e = i - w * N;
-    s[w * P + pad(e)] = src[i];
+#pragma unroll 1
+  for (int u = 0; u < K::ROUNDS; ++u) {
+    const int w = u * K::WT + tid / TL;
+    if (w < W) {
+      const C2<T>* __restrict__ src = d.X + ((size_t)kx * N + z0 + w) * N;
+      C2<T> v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = r < 8 ? src[t + r * TL] : C2<T>{(T)0, (T)0};
+      fwd_from<T, L, 0, true>(s + w * P, t, v, tw);
+    }
   }
   __syncthreads();
-  const bool act = tid < W * TL;
-  fft_line<T, L, false, true, false>(s + (act ? tid / TL : 0) * P, tid % TL, tw, act);
   C2<T>* __restrict__ dst = d.C + (size_t)kx * L * N + z0;
   for (int i = tid; i < W * L; i += NT) {
     const int e = i / W, w = i - e * W;
@@ -225,48 +338,61 @@ __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T
   }
 }
 
-// zpass: tile = W consecutive ky at one kx; forward z, times Hhat, inverse z.
+// zpass: tile = W consecutive ky at one kx, one line per TL threads; forward
+// z (input z < N) from global, times Hhat in registers, inverse z, keep
+// z < N, back to global.  No block barrier.
 template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT>;
-  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
-  const int tid = threadIdx.x;
-  const int kx = tile / (L / W), ky0 = (tile % (L / W)) * W;
-  C2<T>* __restrict__ base = d.C + ((size_t)kx * L + ky0) * N;
-  for (int i = tid; i < W * N; i += NT) {
-    const int w = i / N, e = i - w * N;
-    s[w * P + pad(e)] = base[i];
+  using K = TC<T, L, NT, 2>;
+  using F = Line<L>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
+  constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
+  const int tid = threadIdx.x, t = tid % TL, w = tid / TL;
+  if (w >= W) return;
+  const int kx = tile / (L / W), ky = (tile % (L / W)) * W + w;
+  C2<T>* __restrict__ g = d.C + ((size_t)kx * L + ky) * N;
+  C2<T>* sl = s + w * P;
+  C2<T> v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = r < 8 ? g[t + r * TL] : C2<T>{(T)0, (T)0};
+  if constexpr (NP > 1) {
+    fwd_bfly<T, L, 0>(v, t, tw);
+    scatter_out<T, L, 0>(sl, t, v);
+    wave_sync();
+    gather_in<T, L, 1, false>(sl, t, v);
+    wave_sync();
+    if constexpr (NP > 2) {
+      fwd_bfly<T, L, 1>(v, t, tw);
+      scatter_out<T, L, 1>(sl, t, v);
+      wave_sync();
+      gather_in<T, L, 2, false>(sl, t, v);
+      wave_sync();
+    }
   }
-  __syncthreads();
-  const bool act = tid < W * TL;
-  C2<T>* line = s + (act ? tid / TL : 0) * P;
-  fft_line<T, L, false, true, false>(line, tid % TL, tw, act);
-  const T* __restrict__ H = d.H + (size_t)kx * (N + 1) * (N + 1);
-  for (int i = tid; i < W * L; i += NT) {
-    const int w = i / L, e = i - w * L;
-    const int ky = ky0 + w;
-    const int fy = ky <= N ? ky : L - ky;
-    const int fz = e <= N ? e : L - e;
-    const T h = H[fy * (N + 1) + fz];
-    C2<T>& c = s[w * P + pad(e)];
-    c = cscale(c, h);
-  }
-  __syncthreads();
-  fft_line<T, L, true, false, true>(line, tid % TL, tw, act);
-  for (int i = tid; i < W * N; i += NT) {
-    const int w = i / N, e = i - w * N;
-    base[i] = s[w * P + pad(e)];
-  }
+  fwd_bfly<T, L, NP - 1>(v, t, tw);
+  // Hhat at frequencies (kx, ky, e), e = j + r L/R of the last pass
+  const T* __restrict__ H = d.H + ((size_t)kx * (N + 1) + (ky <= N ? ky : L - ky)) * (N + 1);
+#pragma unroll
+  for (int b = 0; b < 16 / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int e = t + b * TL + r * NBL;
+      v[b * RL + r] = cscale(v[b * RL + r], H[e <= N ? e : L - e]);
+    }
+  inv_down<T, L, NP - 1>(sl, t, v, tw);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) g[t + r * TL] = v[r];
 }
 
-// inv_y: tile = W consecutive z at one kx; ky strided by N; keep y < N.
+// inv_y: tile = W consecutive z at one kx; ky strided by N, staged in LDS;
+// output lines X[kx][z][y < N] written straight from registers.
 template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT>;
-  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
-  const int tid = threadIdx.x;
+  using K = TC<T, L, NT, 3>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = Line<L>::NP;
+  const int tid = threadIdx.x, t = tid % TL;
   const int kx = tile / (N / W), z0 = (tile % (N / W)) * W;
   const C2<T>* __restrict__ src = d.C + (size_t)kx * L * N + z0;
   for (int i = tid; i < W * L; i += NT) {
@@ -274,23 +400,31 @@ __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T
     s[w * P + pad(e)] = src[(size_t)e * N + w];
   }
   __syncthreads();
-  const bool act = tid < W * TL;
-  fft_line<T, L, true, false, true>(s + (act ? tid / TL : 0) * P, tid % TL, tw, act);
-  C2<T>* __restrict__ dst = d.X + ((size_t)kx * N + z0) * N;
-  for (int i = tid; i < W * N; i += NT) {
-    const int w = i / N, e = i - w * N;
-    dst[i] = s[w * P + pad(e)];
+#pragma unroll 1
+  for (int u = 0; u < K::ROUNDS; ++u) {
+    const int w = u * K::WT + tid / TL;
+    if (w < W) {
+      C2<T>* sl = s + w * P;
+      C2<T> v[16];
+      gather_out<T, L, NP - 1>(sl, t, v);
+      wave_sync();
+      inv_down<T, L, NP - 1>(sl, t, v, tw);
+      C2<T>* __restrict__ dst = d.X + ((size_t)kx * N + z0 + w) * N;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) dst[t + r * TL] = v[r];
+    }
   }
 }
 
-// inv_x: tile = W consecutive y at one z; kx <= N strided by N*N, the rest
-// of the line by Hermitian symmetry; real output x < N.
+// inv_x: tile = W consecutive y at one z; kx <= N strided by N*N, the rest of
+// the line by Hermitian symmetry, staged in LDS; real output rows x < N
+// written straight from registers.
 template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT>;
-  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
-  const int tid = threadIdx.x;
+  using K = TC<T, L, NT, 4>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = Line<L>::NP;
+  const int tid = threadIdx.x, t = tid % TL;
   const int z = tile / (N / W), y0 = (tile % (N / W)) * W;
   const C2<T>* __restrict__ src = d.X + (size_t)z * N + y0;
   for (int i = tid; i < W * (N + 1); i += NT) {
@@ -300,12 +434,19 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
     if (e >= 1 && e < N) s[w * P + pad(L - e)] = conjc(v);
   }
   __syncthreads();
-  const bool act = tid < W * TL;
-  fft_line<T, L, true, false, true>(s + (act ? tid / TL : 0) * P, tid % TL, tw, act);
-  T* __restrict__ dst = d.phi + ((size_t)z * N + y0) * N;
-  for (int i = tid; i < W * N; i += NT) {
-    const int w = i / N, e = i - w * N;
-    dst[i] = s[w * P + pad(e)].re;
+#pragma unroll 1
+  for (int u = 0; u < K::ROUNDS; ++u) {
+    const int w = u * K::WT + tid / TL;
+    if (w < W) {
+      C2<T>* sl = s + w * P;
+      C2<T> v[16];
+      gather_out<T, L, NP - 1>(sl, t, v);
+      wave_sync();
+      inv_down<T, L, NP - 1>(sl, t, v, tw);
+      T* __restrict__ dst = d.phi + ((size_t)z * N + y0 + w) * N;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) dst[t + r * TL] = v[r].re;
+    }
   }
 }
 
@@ -327,7 +468,7 @@ template <typename T, int PASS, int NT, int L>
 __global__ void __launch_bounds__(NT)
     k_pass(const SolveDesc<T>* __restrict__ solves, int tiles_per_solve, int total,
            int* __restrict__ counter, const C2<T>* __restrict__ tw) {
-  __shared__ C2<T> s[TC<T, L, NT>::LDS];
+  __shared__ C2<T> s[TC<T, L, NT, PASS>::LDS];
   __shared__ int item_sh;
   int next = blockIdx.x;
   for (;;) {
@@ -363,6 +504,37 @@ static int tiles_nt(int nt, int N, int pass) {
                    : tiles_for<T, 512>(N, pass);
 }
 
+template <typename T, int NT, int PASS>
+static bool fits_nt(int N) {
+  switch (N) {
+    case 8: return shape_fits<T, 16, NT, PASS>();
+    case 16: return shape_fits<T, 32, NT, PASS>();
+    case 32: return shape_fits<T, 64, NT, PASS>();
+    case 64: return shape_fits<T, 128, NT, PASS>();
+    case 128: return shape_fits<T, 256, NT, PASS>();
+    default: return shape_fits<T, 512, NT, PASS>();
+  }
+}
+
+// Whether a block size fits the LDS budget for a pass and grid size.
+template <typename T>
+static bool shape_ok(int nt, int N, int pass) {
+  auto f = [&](auto ntc) {
+    constexpr int NT = decltype(ntc)::value;
+    switch (pass) {
+      case 0: return fits_nt<T, NT, 0>(N);
+      case 1: return fits_nt<T, NT, 1>(N);
+      case 2: return fits_nt<T, NT, 2>(N);
+      case 3: return fits_nt<T, NT, 3>(N);
+      default: return fits_nt<T, NT, 4>(N);
+    }
+  };
+  return nt == 128 ? f(std::integral_constant<int, 128>())
+       : nt == 256 ? f(std::integral_constant<int, 256>())
+       : nt == 512 ? f(std::integral_constant<int, 512>())
+                   : false;
+}
+
 template <typename T, int PASS, int NT>
 static void launch_nt(const SolveDesc<T>* solves, int N, int tps, int total, int grid, int* counter,
                       const C2<T>* tw, hipStream_t st) {
@@ -380,6 +552,7 @@ static void launch_nt(const SolveDesc<T>* solves, int N, int tps, int total, int
 template <typename T, int PASS>
 static void launch_pass(const SolveDesc<T>* solves, int N, int nsolves, PassShape sh, int* counter,
                         const C2<T>* tw, hipStream_t st) {
+  if (!shape_ok<T>(sh.nt, N, PASS)) sh.nt = 256;
   const int tps = tiles_nt<T>(sh.nt, N, PASS);
   const int total = tps * nsolves;
   const int grid = std::max(1, std::min(sh.grid <= 0 ? total : sh.grid, total));
@@ -480,7 +653,7 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
     float best = 1e30f;
     PassShape pick{256, 0};
     for (int nt : nts) {
-      if (nt == 512 && sizeof(T) == 8) continue;
+      if (!shape_ok<T>(nt, N, pass)) continue;
       for (int bpc : bpcs) {
         const PassShape sh{nt, bpc == 0 ? 0 : cus * bpc};
         float ms_min = 1e30f;
@@ -627,41 +800,36 @@ __global__ void k_green_fill(C2<double>* F, int N, double l, double lz, double h
   }
 }
 
-// In-place complex FFT of every line of F along one axis.
+// In-place complex FFT of every line of F along one axis: W lines per block
+// staged in LDS, each transformed by TL threads of one wave.
+template <int L>
+struct GreenTile {
+  static constexpr int TL = L / 16, P = L + L / 16 + 1, NT = 256;
+  static constexpr int W = NT / TL < L ? NT / TL : L;
+};
+
 template <int L, int AXIS>
 __global__ void __launch_bounds__(256)
     k_c2c_axis(C2<double>* F, const C2<double>* __restrict__ tw) {
-  using K = TC<double, L, 256>;
-  constexpr int W = K::W, P = K::P, NT = 256, TL = K::TL;
+  using K = GreenTile<L>;
+  constexpr int W = K::W, P = K::P, NT = K::NT, TL = K::TL;
   __shared__ C2<double> s[W * P];
   const int o = blockIdx.x / (L / W), i0 = (blockIdx.x % (L / W)) * W;
-  if constexpr (AXIS == 0) {
-    C2<double>* base = F + ((size_t)o * L + i0) * L;
-    for (int i = threadIdx.x; i < W * L; i += NT) {
-      const int w = i / L, e = i - w * L;
-      s[w * P + pad(e)] = base[i];
-    }
-    __syncthreads();
-    const bool act = (int)threadIdx.x < W * TL;
-    fft_line<double, L, false, false, false>(s + (act ? threadIdx.x / TL : 0) * P, threadIdx.x % TL, tw, act);
-    for (int i = threadIdx.x; i < W * L; i += NT) {
-      const int w = i / L, e = i - w * L;
-      base[i] = s[w * P + pad(e)];
-    }
-  } else {
-    const size_t es = AXIS == 1 ? (size_t)L : (size_t)L * L;
-    C2<double>* base = F + (AXIS == 1 ? (size_t)o * L * L : (size_t)o * L) + i0;
-    for (int i = threadIdx.x; i < W * L; i += NT) {
-      const int e = i / W, w = i - e * W;
-      s[w * P + pad(e)] = base[e * es + w];
-    }
-    __syncthreads();
-    const bool act = (int)threadIdx.x < W * TL;
-    fft_line<double, L, false, false, false>(s + (act ? threadIdx.x / TL : 0) * P, threadIdx.x % TL, tw, act);
-    for (int i = threadIdx.x; i < W * L; i += NT) {
-      const int e = i / W, w = i - e * W;
-      base[e * es + w] = s[w * P + pad(e)];
-    }
+  const size_t es = AXIS == 0 ? 1 : (AXIS == 1 ? (size_t)L : (size_t)L * L);
+  const size_t ws = AXIS == 0 ? (size_t)L : 1;
+  C2<double>* base = F + (AXIS == 0 ? (size_t)o * L * L + (size_t)i0 * L
+                                    : (AXIS == 1 ? (size_t)o * L * L : (size_t)o * L) + i0);
+  for (int i = threadIdx.x; i < W * L; i += NT) {
+    const int e = AXIS == 0 ? i % L : i / W, w = AXIS == 0 ? i / L : i % W;
+    s[w * P + pad(e)] = base[e * es + w * ws];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < W * TL)
+    line_fwd_lds<double, L>(s + (threadIdx.x / TL) * P, threadIdx.x % TL, tw);
+  __syncthreads();
+  for (int i = threadIdx.x; i < W * L; i += NT) {
+    const int e = AXIS == 0 ? i % L : i / W, w = AXIS == 0 ? i / L : i % W;
+    base[e * es + w * ws] = s[w * P + pad(e)];
   }
 }
 
@@ -693,7 +861,7 @@ __global__ void k_green_fold(const C2<double>* F, T* H, int N, double scale) {
 
 template <int L>
 static sbx_status green_fft(C2<double>* F, hipStream_t st) {
-  using K = TC<double, L, 256>;
+  using K = GreenTile<L>;
   const C2<double>* tw = twiddles<double>(L, st);
   if (!tw) {
     set_error("twiddle table allocation failed");
