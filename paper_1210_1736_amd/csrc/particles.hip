@@ -12,6 +12,21 @@
 
 namespace sbx {
 
+// Global-memory views of pointers held in device records: accesses through
+// them compile to global_* instructions instead of flat_* ones (which also
+// count against the LDS/scalar wait counter).
+template <typename T>
+using gp = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gp<T> glb(T* p) {
+  return (gp<T>)p;
+}
+
+template <typename T>
+__device__ __forceinline__ void atomic_add_g(gp<T> p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------------ cell index --
 // Eq. 7: a = [gamma (x - c) + N/2], nearest integer = floor(u + 0.5).
 __device__ __forceinline__ int ngp_cell(double x, double c, double gamma, double half) {
@@ -151,18 +166,38 @@ __device__ __forceinline__ uint32_t dep_key(int g, int slot, const LevelDev& L, 
 // Acceleration (+grad Phi) and Phi at the particle from one field on one
 // level: central differences plus the second-order Taylor terms, the offset
 // Delta = (x - c) - (i - N/2) * l measured from the cell centre.
+// Three consecutive values of a grid row (x-1, x, x+1): one 12-byte load in
+// FP32, a 16-byte and an 8-byte load in FP64.
+template <typename T>
+struct Row3 {
+  T m, c, p;
+};
+typedef float f32x3 __attribute__((ext_vector_type(3), aligned(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2), aligned(8)));
+__device__ __forceinline__ Row3<float> row3(gp<const float> q) {
+  const f32x3 v = *(gp<const f32x3>)(q - 1);
+  return {v.x, v.y, v.z};
+}
+__device__ __forceinline__ Row3<double> row3(gp<const double> q) {
+  const f64x2 v = *(gp<const f64x2>)(q - 1);
+  return {v.x, v.y, q[1]};
+}
+
 template <typename T>
 __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, const int* id,
                                     double dx, double dy, double dz, int taylor, T* a, T& phi,
                                     bool want_phi) {
   const ptrdiff_t sy = L.N, sz = (ptrdiff_t)L.N * L.N;
-  const T* P = F + (ptrdiff_t)id[2] * sz + (ptrdiff_t)id[1] * sy + id[0];
+  const gp<const T> P = glb(F) + ((ptrdiff_t)id[2] * sz + (ptrdiff_t)id[1] * sy + id[0]);
   const T Dx = (T)(dx - ((double)id[0] - L.half) * L.l);
   const T Dy = (T)(dy - ((double)id[1] - L.half) * L.l);
   const T Dz = (T)(dz - ((double)id[2] - L.half) * L.lz);
   const T i2l = (T)L.c_2l, i2lz = (T)L.c_2lz;
-  const T p0 = P[0];
-  const T xp = P[1], xm = P[-1], yp = P[sy], ym = P[-sy], zp = P[sz], zm = P[-sz];
+  // the 19-point stencil as 5 rows of three along x and 4 single values
+  const Row3<T> r00 = row3(P), rp0 = row3(P + sy), rm0 = row3(P - sy);
+  const Row3<T> r0p = row3(P + sz), r0m = row3(P - sz);
+  const T p0 = r00.c, xp = r00.p, xm = r00.m;
+  const T yp = rp0.c, ym = rm0.c, zp = r0p.c, zm = r0m.c;
   const T gx = (xp - xm) * i2l, gy = (yp - ym) * i2l, gz = (zp - zm) * i2lz;
   if (!taylor) {
     a[0] += gx;
@@ -176,8 +211,8 @@ __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, 
   const T hxx = (xp + xm - (T)2 * p0) * il2;
   const T hyy = (yp + ym - (T)2 * p0) * il2;
   const T hzz = (zp + zm - (T)2 * p0) * ilz2;
-  const T hxy = (P[1 + sy] - P[-1 + sy] + P[-1 - sy] - P[1 - sy]) * i4xy;
-  const T hxz = (P[1 + sz] - P[-1 + sz] + P[-1 - sz] - P[1 - sz]) * i4xz;
+  const T hxy = (rp0.p - rp0.m + rm0.m - rm0.p) * i4xy;
+  const T hxz = (r0p.p - r0p.m + r0m.m - r0m.p) * i4xz;
   const T hyz = (P[sy + sz] - P[-sy + sz] + P[-sy - sz] - P[sy - sz]) * i4xz;
   a[0] += gx + hxx * Dx + hxy * Dy + hxz * Dz;
   a[1] += gy + hyy * Dy + hxy * Dx + hyz * Dz;
@@ -369,18 +404,22 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------- mass deposit --
-// LDS-binned mass assignment.  Each block takes a contiguous chunk of the
-// (cell-sorted) particles; the three deposits of every particle are first
-// combined across lanes of a wavefront that hit the same cell (segmented
-// wave sum), then accumulated in an LDS hash table of the block's cells, and
-// finally flushed with one global atomic add per distinct cell.  Targets that
-// find no free LDS entry within a few probes go straight to global memory.
+// Mass assignment on cell-sorted particles.  Each block takes a contiguous
+// chunk of particles.  The deposits on a particle's finest level (the level
+// the sort orders by) are combined across lanes of a wavefront that hit the
+// same cell (segmented wave sum) and added to global memory straight from the
+// run tails: consecutive runs hit neighbouring cells, so these atomics are
+// close to coalesced.  Deposits on coarser levels repeat across many
+// particles of a chunk; they are summed in the wavefront, accumulated in an
+// LDS hash table of the block's coarse cells and flushed with one global
+// atomic per distinct cell (targets that find no free entry within a few
+// probes go straight to global memory).
 //
 // Sources of the five grids (Sec. 2.1): core -> grid 1, grid 2, grid 4;
 // ring -> grid 3, grid 4; outer -> grid 5.  Grids 2+3 and 4+5 are assigned
 // as sums directly (their potentials are only used summed, and the solve is
-// linear).  Round 0 = the finest grid of the class, round 1 = middle (2+3)
-// or global (4+5), round 2 = global (4+5).
+// linear), so a ring particle adds to slots 1 and 2 of its middle cell and
+// an outer particle to slots 3 and 4 of its global cell.
 constexpr int kDepTable = 4096;     // LDS hash entries (power of two)
 constexpr int kDepProbes = 8;
 
@@ -404,6 +443,10 @@ __global__ void __launch_bounds__(256)
   const int lb = blockIdx.x - sp.start[ii];
   const InstDev<T>& I = inst[ii];
   const PartDev<T> p = I.p[cur[ii]];
+  const gp<const T> X0 = glb((const T*)p.x[0]), X1 = glb((const T*)p.x[1]), X2 = glb((const T*)p.x[2]);
+  const gp<const T> Mv = glb((const T*)p.m);
+  const gp<const uint8_t> LOST = glb((const uint8_t*)p.lost);
+  const gp<const int8_t> GAL = glb((const int8_t*)p.gal);
   stage(&sys, &I.sys);
   stage(&G, &I.G);
   if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = I.centres[threadIdx.x];
@@ -415,33 +458,43 @@ __global__ void __launch_bounds__(256)
   const int64_t base = (int64_t)lb * kDepChunk;
   for (int j = 0; j < kDepChunk / 256; ++j) {
     const int64_t i = base + j * 256 + threadIdx.x;
-    uint32_t k0 = kNoKey, k1 = kNoKey, k2 = kNoKey;
+    // fine: key on the finest level, fine2: the same cell in the summed slot
+    // (ring and outer), or kNoKey; coarse keys c1, c2 go through the table
+    uint32_t fine = kNoKey, fine2 = kNoKey, c1 = kNoKey, c2 = kNoKey;
     T m = (T)0;
-    if (i < p.n && !p.lost[i]) {
-      const int g = p.gal[i];
+    if (i < p.n && !LOST[i]) {
+      const int g = GAL[i];
       const HierDev& h = sys.h[g];
-      const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+      const double x = (double)X0[i], y = (double)X1[i], z = (double)X2[i];
       Classified c;
       classify(h, cen + 3 * g, x, y, z, c);
-      m = p.m[i];
+      m = Mv[i];
       if (h.n_levels == 1) {
-        if (c.cls == SBX_OUTER) k0 = dep_key(g, 0, h.lv[0], c.idx[0]);
+        if (c.cls == SBX_OUTER) fine = dep_key(g, 0, h.lv[0], c.idx[0]);
       } else if (c.cls == SBX_CORE) {
-        k0 = dep_key(g, 0, h.lv[0], c.idx[0]);   // grid 1
-        k1 = dep_key(g, 2, h.lv[1], c.idx[1]);   // grid 2 (in 2+3)
-        k2 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 4 (in 4+5)
+        fine = dep_key(g, 0, h.lv[0], c.idx[0]);  // grid 1
+        c1 = dep_key(g, 2, h.lv[1], c.idx[1]);    // grid 2 (in 2+3)
+        c2 = dep_key(g, 4, h.lv[2], c.idx[2]);    // grid 4 (in 4+5)
       } else if (c.cls == SBX_RING) {
-        k0 = dep_key(g, 1, h.lv[1], c.idx[1]);   // grid 3
-        k1 = dep_key(g, 2, h.lv[1], c.idx[1]);   // grid 3 (in 2+3)
-        k2 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 4 (in 4+5)
+        fine = dep_key(g, 1, h.lv[1], c.idx[1]);  // grid 3
+        fine2 = dep_key(g, 2, h.lv[1], c.idx[1]); // grid 3 (in 2+3)
+        c2 = dep_key(g, 4, h.lv[2], c.idx[2]);    // grid 4 (in 4+5)
       } else if (c.cls == SBX_OUTER) {
-        k0 = dep_key(g, 3, h.lv[2], c.idx[2]);   // grid 5
-        k1 = dep_key(g, 4, h.lv[2], c.idx[2]);   // grid 5 (in 4+5)
+        fine = dep_key(g, 3, h.lv[2], c.idx[2]);  // grid 5
+        fine2 = dep_key(g, 4, h.lv[2], c.idx[2]); // grid 5 (in 4+5)
+      }
+    }
+    {
+      bool tail;
+      const T s = wave_run_sum(fine, m, tail);
+      if (tail && fine != kNoKey) {
+        atomic_add_g(glb(slot_ptr(G, fine)), s);
+        if (fine2 != kNoKey) atomic_add_g(glb(slot_ptr(G, fine2)), s);
       }
     }
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const uint32_t key = r == 0 ? k0 : (r == 1 ? k1 : k2);
+    for (int r = 0; r < 2; ++r) {
+      const uint32_t key = r == 0 ? c1 : c2;
       bool tail;
       const T s = wave_run_sum(key, m, tail);
       if (tail && key != kNoKey) {
@@ -456,19 +509,21 @@ __global__ void __launch_bounds__(256)
             hslot = (hslot + 1) & (kDepTable - 1);
           }
         }
-        if (!done) unsafeAtomicAdd(slot_ptr(G, key), s);
+        if (!done) atomic_add_g(glb(slot_ptr(G, key)), s);
       }
     }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < kDepTable; k += 256) {
     const uint32_t key = tkey[k];
-    if (key != kNoKey) unsafeAtomicAdd(slot_ptr(G, key), tval[k]);
+    if (key != kNoKey) atomic_add_g(glb(slot_ptr(G, key)), tval[k]);
   }
 }
 
 // ----------------------------------------------------------- force + move --
-// MODE bits: 1 move, 2 write acc/pot, 4 diagnostics
+// MODE bits: 1 move, 2 write acc/pot, 4 diagnostics.  The block walks the
+// instance's particles in block-uniform strides so that every lane of a
+// wavefront takes part in the per-component diagnostic sums.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256)
     k_force(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
@@ -477,14 +532,26 @@ __global__ void __launch_bounds__(256)
   const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
   const InstDev<T>& I = inst[ii];
   const PartDev<T> p = I.p[cur[ii]];
+  const gp<T> X0 = glb(p.x[0]), X1 = glb(p.x[1]), X2 = glb(p.x[2]);
+  const gp<T> V0 = glb(p.v[0]), V1 = glb(p.v[1]), V2 = glb(p.v[2]);
+  const gp<const T> Mv = glb((const T*)p.m);
+  const gp<uint8_t> LOST = glb(p.lost);
+  const gp<const int8_t> GAL = glb((const int8_t*)p.gal), COMP = glb((const int8_t*)p.comp);
   const SysDev& sys = I.sys;
   const GridsDev<T>& F = I.G;
   const double* __restrict__ centres = I.centres;
   const T dt = (T)I.dt;
   const double dtd = I.dt;
-  double dg[DIAG ? kNDiag : 1];
+  // diagnostics: per-component sums per wavefront in LDS (one writer per
+  // row, fixed order), disc and lost counts in registers
+  __shared__ double wacc[DIAG ? 4 : 1][DIAG ? kDiagDisc : 1];
+  double dd[DIAG ? 6 : 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if constexpr (DIAG) {
-    for (int k = 0; k < kNDiag; ++k) dg[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dd[k] = 0.0;
+    for (int k = threadIdx.x; k < 4 * kDiagDisc; k += 256) (&wacc[0][0])[k] = 0.0;
+    __syncthreads();
   }
   double com[MOVE ? kPreVals : 1];
   if constexpr (MOVE) {
@@ -492,81 +559,106 @@ __global__ void __launch_bounds__(256)
     for (int k = 0; k < kPreVals; ++k) com[k] = 0.0;
   }
   const int64_t stride = (int64_t)nb * blockDim.x;
-  for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i < p.n; i += stride) {
-    if (p.lost[i]) {
+  for (int64_t i0 = (int64_t)lb * blockDim.x; i0 < p.n; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool valid = i < p.n;
+    const bool live = valid && !LOST[i];
+    int dc = -1;                        // component for the diagnostic sums
+    double dv[DIAG ? kDiagComp : 1];    // this lane's contribution
+    if (valid && !live) {
       if constexpr (OUT) {
         I.acc[3 * i] = I.acc[3 * i + 1] = I.acc[3 * i + 2] = 0.0;
         I.pot[i] = 0.0;
       }
-      if constexpr (DIAG) dg[kDiagLost] += 1.0;
-      continue;
+      if constexpr (DIAG) dd[5] += 1.0;
     }
-    const T xs = p.x[0][i], ys = p.x[1][i], zs = p.x[2][i];
-    const double x = (double)xs, y = (double)ys, z = (double)zs;
-    T a[3] = {(T)0, (T)0, (T)0};
-    T phi = (T)0;
-    particle_field(sys, centres, F, x, y, z, a, phi, OUT || DIAG);
-    if constexpr (OUT) {
-      I.acc[3 * i] = (double)a[0];
-      I.acc[3 * i + 1] = (double)a[1];
-      I.acc[3 * i + 2] = (double)a[2];
-      I.pot[i] = -(double)phi;
-    }
-    if constexpr (DIAG) {
-      const double m = (double)p.m[i];
-      const double vx = (double)p.v[0][i] + 0.5 * dtd * (double)a[0];
-      const double vy = (double)p.v[1][i] + 0.5 * dtd * (double)a[1];
-      const double vz = (double)p.v[2][i] + 0.5 * dtd * (double)a[2];
-      const int c = p.comp[i] & (kNComp - 1);
-      double* d = dg + kDiagComp * c;
-      d[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
-      d[1] += 0.5 * m * (-(double)phi);
-      d[2] += m * (y * vz - z * vy);
-      d[3] += m * (z * vx - x * vz);
-      d[4] += m * (x * vy - y * vx);
-      d[5] += 1.0;
-      if (c == 0 && p.gal[i] == 0) {
-        const double rx = x - centres[0], ry = y - centres[1];
-        const double R = sqrt(rx * rx + ry * ry);
-        const double vR = R > 0.0 ? (rx * vx + ry * vy) / R : 0.0;
-        dg[kDiagDisc + 0] += vR;
-        dg[kDiagDisc + 1] += vR * vR;
-        dg[kDiagDisc + 2] += vz;
-        dg[kDiagDisc + 3] += vz * vz;
-        dg[kDiagDisc + 4] += 1.0;
+    if (live) {
+      const T xs = X0[i], ys = X1[i], zs = X2[i];
+      const double x = (double)xs, y = (double)ys, z = (double)zs;
+      T a[3] = {(T)0, (T)0, (T)0};
+      T phi = (T)0;
+      particle_field(sys, centres, F, x, y, z, a, phi, OUT || DIAG);
+      if constexpr (OUT) {
+        I.acc[3 * i] = (double)a[0];
+        I.acc[3 * i + 1] = (double)a[1];
+        I.acc[3 * i + 2] = (double)a[2];
+        I.pot[i] = -(double)phi;
       }
-    }
-    if constexpr (MOVE) {
-      const T vx = p.v[0][i] + dt * a[0];
-      const T vy = p.v[1][i] + dt * a[1];
-      const T vz = p.v[2][i] + dt * a[2];
-      const T nx = xs + dt * vx, ny = ys + dt * vy, nz = zs + dt * vz;
-      p.v[0][i] = vx;
-      p.v[1][i] = vy;
-      p.v[2][i] = vz;
-      p.x[0][i] = nx;
-      p.x[1][i] = ny;
-      p.x[2][i] = nz;
-      const double ex = (double)nx, ey = (double)ny, ez = (double)nz;
-      if (outside_global(sys, ex, ey, ez)) {
-        p.lost[i] = 1;
-      } else {
-        // centre-of-mass sums of the new positions for the next step
-        const int g = p.gal[i];
-        const double m = (double)p.m[i];
+      if constexpr (DIAG) {
+        const double m = (double)Mv[i];
+        const double vx = (double)V0[i] + 0.5 * dtd * (double)a[0];
+        const double vy = (double)V1[i] + 0.5 * dtd * (double)a[1];
+        const double vz = (double)V2[i] + 0.5 * dtd * (double)a[2];
+        dc = COMP[i] & (kNComp - 1);
+        dv[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz);
+        dv[1] = 0.5 * m * (-(double)phi);
+        dv[2] = m * (y * vz - z * vy);
+        dv[3] = m * (z * vx - x * vz);
+        dv[4] = m * (x * vy - y * vx);
+        dv[5] = 1.0;
+        if (dc == 0 && GAL[i] == 0) {
+          const double rx = x - centres[0], ry = y - centres[1];
+          const double R = sqrt(rx * rx + ry * ry);
+          const double vR = R > 0.0 ? (rx * vx + ry * vy) / R : 0.0;
+          dd[0] += vR;
+          dd[1] += vR * vR;
+          dd[2] += vz;
+          dd[3] += vz * vz;
+          dd[4] += 1.0;
+        }
+      }
+      if constexpr (MOVE) {
+        const T vx = V0[i] + dt * a[0];
+        const T vy = V1[i] + dt * a[1];
+        const T vz = V2[i] + dt * a[2];
+        const T nx = xs + dt * vx, ny = ys + dt * vy, nz = zs + dt * vz;
+        V0[i] = vx;
+        V1[i] = vy;
+        V2[i] = vz;
+        X0[i] = nx;
+        X1[i] = ny;
+        X2[i] = nz;
+        const double ex = (double)nx, ey = (double)ny, ez = (double)nz;
+        if (outside_global(sys, ex, ey, ez)) {
+          LOST[i] = 1;
+        } else {
+          // centre-of-mass sums of the new positions for the next step
+          const int g = GAL[i];
+          const double m = (double)Mv[i];
 #pragma unroll
-        for (int gg = 0; gg < kMaxGal; ++gg) {
-          if (gg == g && sys.h[gg].centring == SBX_CENTRE_COM) {
-            com[4 * gg + 0] += m;
-            com[4 * gg + 1] += m * ex;
-            com[4 * gg + 2] += m * ey;
-            com[4 * gg + 3] += m * ez;
+          for (int gg = 0; gg < kMaxGal; ++gg) {
+            if (gg == g && sys.h[gg].centring == SBX_CENTRE_COM) {
+              com[4 * gg + 0] += m;
+              com[4 * gg + 1] += m * ex;
+              com[4 * gg + 2] += m * ey;
+              com[4 * gg + 3] += m * ez;
+            }
           }
         }
       }
     }
+    if constexpr (DIAG) {
+      // one pass per component present in the wavefront (uniform loop)
+      for (;;) {
+        const unsigned long long act = __ballot(dc >= 0);
+        if (act == 0ull) break;
+        const int c0 = __shfl(dc, __ffsll((long long)act) - 1, 64);
+        const bool mine = dc == c0;
+#pragma unroll
+        for (int k = 0; k < kDiagComp; ++k) {
+          const double sum = wave_sum(mine ? dv[k] : 0.0);
+          if (lane == 0) wacc[wave][kDiagComp * c0 + k] += sum;
+        }
+        if (mine) dc = -1;
+      }
+    }
   }
-  if constexpr (DIAG) block_sum_store<kNDiag>(dg, I.diag_partial + (size_t)lb * kNDiag);
+  if constexpr (DIAG) {
+    double* out = I.diag_partial + (size_t)lb * kNDiag;
+    block_sum_store<6>(dd, out + kDiagDisc);  // disc sums and lost count (synchronises)
+    for (int k = threadIdx.x; k < kDiagDisc; k += 256)
+      out[k] = ((wacc[0][k] + wacc[1][k]) + wacc[2][k]) + wacc[3][k];
+  }
   if constexpr (MOVE) {
     if constexpr (DIAG) __syncthreads();
     block_sum_store<kPreVals>(com, I.com_partial + (size_t)lb * kPreVals, 4 * sys.ngal);
