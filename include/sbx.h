@@ -191,7 +191,7 @@ sbx_status sbx_adjoint_segment(sbx_ctx* ctx, double dt, int32_t nsteps, int32_t 
                                double* grad_x, double* grad_v);
 
 /* Reorder the particles in device memory by the cell of their finest grid
- * every `every` steps (at the start of the step; 0 = never; default 8).  A
+ * every `every` steps (at the start of the step; 0 = never; default 4).  A
  * performance setting only: every output is returned in the caller's
  * particle order. */
 sbx_status sbx_set_sort_interval(sbx_ctx* ctx, int32_t every);
@@ -225,6 +225,7 @@ sbx_status sbx_batch_step(sbx_batch* b, const double* dt, int32_t nsteps);
 /* Wait for the batch's work and hand its state back to the contexts. */
 sbx_status sbx_batch_sync(sbx_batch* b);
 
+/* Sort interval of the batch (as sbx_set_sort_interval; default 4). */
 sbx_status sbx_batch_set_sort_interval(sbx_batch* b, int32_t every);
 
 /* Synchronise and release the contexts (they can be stepped alone again). */

@@ -324,8 +324,8 @@ sbx_status build_grids_t(sbx_ctx* c) {
     }
   if constexpr (sizeof(T) == 8) SBX_TRY(plan_create<T>(c->plan64, descs.data(), (int)descs.size(), c->stream));
   else SBX_TRY(plan_create<T>(c->plan32, descs.data(), (int)descs.size(), c->stream));
-  // counting-sort bins: one per cell of every level of every galaxy
-  c->bins = (size_t)c->ngal * 3 * N * N * N;
+  // counting-sort bins (cells, or pairs of cells per axis, of every level)
+  c->bins = sort_bins(c->sys);
   SBX_TRY(dev_alloc((void**)&c->count, sizeof(uint32_t) * (c->bins + 1)));
   SBX_TRY(dev_alloc((void**)&c->scan_tmp, sizeof(uint32_t) * scan_tmp_elems(c->bins + 1)));
   return SBX_OK;

@@ -81,7 +81,7 @@ struct sbx_ctx {
   uint32_t* count = nullptr;     // bins + 1
   uint32_t* scan_tmp = nullptr;
   size_t bins = 0;
-  int sort_every = 8;
+  int sort_every = 4;
   // reductions and outputs
   double* centres = nullptr;       // kMaxGal * 3
   double* pre_partial = nullptr;   // (kRedBlocks + 1) * kPreVals
@@ -123,7 +123,7 @@ struct sbx_batch {
   sbx::SolvePlan<double> p64;
   hipGraph_t graph[2] = {nullptr, nullptr};      // [0] plain step, [1] step with sort
   hipGraphExec_t exec[2] = {nullptr, nullptr};
-  int sort_every = 8;
+  int sort_every = 4;
   int64_t step_count = 0;
   bool fresh = false;              // every instance's centre-of-mass sums are current
   bool pending = false;            // work queued since the last sbx_batch_sync

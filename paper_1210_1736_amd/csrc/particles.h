@@ -94,6 +94,27 @@ struct InstDev {
   int64_t n;
 };
 
+// Counting-sort bins.  A particle's bin is the cell of its finest grid
+// relative to its own galaxy, coarsened by sort_group cells per axis; bins
+// are ordered by galaxy, level, z, y, x, and the last bin holds the lost
+// particles.  (Coarser bins make runs of equal keys longer but cost the
+// deposit more than they save in the sort, so every level uses single
+// cells.)
+__host__ __device__ inline int sort_group(const HierDev&, int) { return 1; }
+__host__ __device__ inline size_t level_bins(const HierDev& h, int lev) {
+  const size_t n = (size_t)(h.lv[lev].N / sort_group(h, lev));
+  return n * n * n;
+}
+__host__ __device__ inline size_t bins_before(const SysDev& s, int g, int lev) {
+  size_t b = 0;
+  for (int gg = 0; gg < g; ++gg)
+    for (int l = 0; l < s.h[gg].n_levels; ++l) b += level_bins(s.h[gg], l);
+  for (int l = 0; l < lev; ++l) b += level_bins(s.h[g], l);
+  return b;
+}
+// number of bins before the lost bin
+__host__ __device__ inline size_t sort_bins(const SysDev& s) { return bins_before(s, s.ngal, 0); }
+
 // Host-side facts the launchers need to shape a multi-instance grid.
 struct InstInfo {
   int64_t n;

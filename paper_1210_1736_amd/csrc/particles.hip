@@ -131,24 +131,57 @@ __device__ __forceinline__ void block_sum_store(const double* vals, double* out,
 
 
 
+// Cross-lane moves by DPP (data-parallel primitives of the VALU, no LDS
+// round trip).  Lanes whose source is outside the pattern, or whose row is
+// masked off, receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_t(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp_u32<CTRL, ROWS>(__builtin_bit_cast(uint32_t, v)));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = dpp_u32<CTRL, ROWS>((uint32_t)u);
+    const uint32_t hi = dpp_u32<CTRL, ROWS>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+constexpr int kDppRowShr = 0x110;    // + n: from lane - n of the same row of 16
+constexpr int kDppBcast15 = 0x142;   // lane 15 of each row to the next row
+constexpr int kDppBcast31 = 0x143;   // lane 31 to rows 2 and 3
+constexpr int kDppWaveShr1 = 0x138;  // from lane - 1
+constexpr int kDppWaveShl1 = 0x130;  // from lane + 1
+
+// One step of a segmented inclusive scan: add the partial from the source
+// lane unless a segment starts at or before this lane within the span.
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ void seg_step(T& s, uint32_t& f) {
+  const T su = dpp_t<CTRL, ROWS>(s);
+  const uint32_t fu = dpp_u32<CTRL, ROWS>(f);
+  if (!f) s += su;
+  f |= fu;
+}
+
 // Segmented sum over runs of equal keys in consecutive lanes: returns, in the
 // last lane of each run (tail = true), the run's total.  All 64 lanes call it.
+// Scan within rows of 16 lanes (shifts 1, 2, 4, 8), then across rows by the
+// row broadcasts of lanes 15 and 31.
 template <typename T>
 __device__ __forceinline__ T wave_run_sum(uint32_t key, T val, bool& tail) {
   const int lane = threadIdx.x & 63;
-  const uint32_t kprev = __shfl_up(key, 1, 64);
-  const uint32_t knext = __shfl_down(key, 1, 64);
-  int f = (lane == 0) || (kprev != key);
+  const uint32_t kprev = dpp_u32<kDppWaveShr1, 0xf>(key);
+  const uint32_t knext = dpp_u32<kDppWaveShl1, 0xf>(key);
+  uint32_t f = (lane == 0) || (kprev != key);
   T s = val;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const T su = __shfl_up(s, o, 64);
-    const int fu = __shfl_up(f, o, 64);
-    if (lane >= o) {
-      if (!f) s += su;
-      f |= fu;
-    }
-  }
+  seg_step<kDppRowShr + 1, 0xf>(s, f);
+  seg_step<kDppRowShr + 2, 0xf>(s, f);
+  seg_step<kDppRowShr + 4, 0xf>(s, f);
+  seg_step<kDppRowShr + 8, 0xf>(s, f);
+  seg_step<kDppBcast15, 0xa>(s, f);
+  seg_step<kDppBcast31, 0xc>(s, f);
   tail = (lane == 63) || (knext != key);
   return s;
 }
@@ -300,6 +333,10 @@ static int64_t blocks_particles(const InstInfo& f) { return f.n > 0 ? (f.n + 255
 static int64_t blocks_force(const InstInfo& f) { return force_blocks(f.n); }
 static int64_t blocks_deposit(const InstInfo& f) { return f.n > 0 ? (f.n + kDepChunk - 1) / kDepChunk : 1; }
 static int64_t blocks_red(const InstInfo&) { return kRedBlocks; }
+constexpr int kSortPPT = 1;  // particles per thread of the sort scatter
+static int64_t blocks_sort(const InstInfo& f) {
+  return f.n > 0 ? (f.n + 256 * kSortPPT - 1) / (256 * kSortPPT) : 1;
+}
 static int64_t blocks_grid(const InstInfo& f) {
   const int64_t b = (int64_t)((f.grid_elems + 1023) / 1024);
   return b < 1 ? 1 : (b > 2048 ? 2048 : b);
@@ -323,6 +360,7 @@ __global__ void __launch_bounds__(256)
   const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
   const InstDev<T>& I = inst[ii];
   const PartDev<T> p = I.p[cur[ii]];
+  const gp<const T> X0 = glb((const T*)p.x[0]), X1 = glb((const T*)p.x[1]), X2 = glb((const T*)p.x[2]);
   const SysDev& sys = I.sys;
   double acc[kPreVals];
 #pragma unroll
@@ -330,7 +368,7 @@ __global__ void __launch_bounds__(256)
   const int64_t stride = (int64_t)nb * blockDim.x;
   for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i < p.n; i += stride) {
     if (p.lost[i]) continue;
-    const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+    const double x = (double)X0[i], y = (double)X1[i], z = (double)X2[i];
     if (outside_global(sys, x, y, z)) {
       p.lost[i] = 1;
       continue;
@@ -684,9 +722,7 @@ __global__ void __launch_bounds__(256) k_diag_final(const InstDev<T>* __restrict
 }
 
 // ------------------------------------------------------------ cell sort ---
-// Key: cell of the particle's finest grid (relative to its own galaxy),
-// bins ordered by galaxy, then class level, then z, y, x; lost particles in
-// the last bin.
+// Key: the sort bin of the particle (see sort_group in particles.h).
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_sort_key(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
@@ -696,11 +732,11 @@ __global__ void __launch_bounds__(256)
   const int lb = blockIdx.x - sp.start[ii];
   const InstDev<T>& I = inst[ii];
   const PartDev<T> p = I.p[cur[ii]];
+  const gp<const T> X0 = glb((const T*)p.x[0]), X1 = glb((const T*)p.x[1]), X2 = glb((const T*)p.x[2]);
   stage(&sys, &I.sys);
   if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = I.centres[threadIdx.x];
   __syncthreads();
-  const int N0 = sys.h[0].lv[0].N;
-  const uint32_t lost_bin = (uint32_t)((size_t)sys.ngal * 3 * N0 * N0 * N0);
+  const uint32_t lost_bin = (uint32_t)sort_bins(sys);
   const int64_t i = (int64_t)lb * 256 + threadIdx.x;
   uint32_t k = kNoKey;  // lanes past the end keep a key of their own
   if (i < p.n) {
@@ -709,12 +745,14 @@ __global__ void __launch_bounds__(256)
       const int g = p.gal[i];
       const HierDev& h = sys.h[g];
       Classified c;
-      classify(h, cen + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
+      classify(h, cen + 3 * g, (double)X0[i], (double)X1[i], (double)X2[i], c);
       if (c.cls != SBX_LOST) {
         const int lev = h.n_levels == 1 ? 0 : c.cls;
-        const int N = h.lv[0].N;
+        const int gr = sort_group(h, lev);
+        const int n = h.lv[lev].N / gr;
         const int* id = lev == 0 ? c.idx[0] : (lev == 1 ? c.idx[1] : c.idx[2]);
-        k = (uint32_t)((((size_t)(g * 3 + lev) * N + id[2]) * N + id[1]) * N + id[0]);
+        k = (uint32_t)(bins_before(sys, g, lev) +
+                       (((size_t)(id[2] / gr) * n + id[1] / gr) * n + id[0] / gr));
       }
     }
     I.key[i] = k;
@@ -729,6 +767,9 @@ __global__ void __launch_bounds__(256)
 // lane reserves the whole run with one atomic add, the others take the
 // following slots in lane order.  Offsets are global (all instances' counts
 // scanned together); part_base turns them into the instance's own slots.
+// Each thread moves kSortPPT particles so that several reservations are in
+// flight before their results are needed.
+
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_sort_scatter(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
@@ -738,33 +779,57 @@ __global__ void __launch_bounds__(256)
   const int c0 = cur[ii];
   const PartDev<T> s = I.p[c0];
   const PartDev<T> d = I.p[c0 ^ 1];
-  const int64_t i = (int64_t)lb * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  const uint32_t k = i < s.n ? I.key[i] : kNoKey;
-  bool tail;
-  const uint32_t rank1 = wave_run_sum<uint32_t>(k, 1u, tail);  // 1-based rank in the run
-  uint32_t start = 0;
-  if (tail && k != kNoKey) start = atomicAdd(I.count + k, rank1);
-  // nearest tail at or after this lane: suffix minimum of tail lane ids
-  int tl = tail ? lane : 64;
+  const gp<uint32_t> count = glb(I.count);
+  const gp<const uint32_t> key = glb((const uint32_t*)I.key);
+  int64_t i[kSortPPT];
+  uint32_t k[kSortPPT], rank1[kSortPPT], start[kSortPPT];
+  bool tail[kSortPPT];
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t2 = __shfl_down(tl, o, 64);
-    if (lane + o < 64) tl = min(tl, t2);
+  for (int u = 0; u < kSortPPT; ++u) {
+    i[u] = ((int64_t)lb * kSortPPT + u) * 256 + threadIdx.x;
+    k[u] = i[u] < s.n ? key[i[u]] : kNoKey;
   }
-  const uint32_t run_start = __shfl(start, tl & 63, 64);
-  if (i >= s.n) return;
-  const uint32_t j = run_start + rank1 - 1 - I.part_base;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    d.x[q][j] = s.x[q][i];
-    d.v[q][j] = s.v[q][i];
+  for (int u = 0; u < kSortPPT; ++u) rank1[u] = wave_run_sum<uint32_t>(k[u], 1u, tail[u]);
+#pragma unroll
+  for (int u = 0; u < kSortPPT; ++u)
+    start[u] = (tail[u] && k[u] != kNoKey)
+                   ? __hip_atomic_fetch_add(count + k[u], rank1[u], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                   : 0u;
+  const gp<T> dx0 = glb((T*)d.x[0]), dx1 = glb((T*)d.x[1]), dx2 = glb((T*)d.x[2]);
+  const gp<T> dv0 = glb((T*)d.v[0]), dv1 = glb((T*)d.v[1]), dv2 = glb((T*)d.v[2]);
+  const gp<T> dm = glb((T*)d.m);
+  const gp<int8_t> dcomp = glb(d.comp), dgal = glb(d.gal);
+  const gp<uint8_t> dlost = glb(d.lost);
+  const gp<int32_t> did = glb(d.id);
+#pragma unroll
+  for (int u = 0; u < kSortPPT; ++u) {
+    // nearest tail at or after this lane: suffix minimum of tail lane ids
+    int tl = tail[u] ? lane : 64;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t2 = __shfl_down(tl, o, 64);
+      if (lane + o < 64) tl = min(tl, t2);
+    }
+    const uint32_t run_start = __shfl(start[u], tl & 63, 64);
+    const int64_t q = i[u];
+    if (q < s.n) {
+      const uint32_t j = run_start + rank1[u] - 1 - I.part_base;
+      dx0[j] = glb((const T*)s.x[0])[q];
+      dx1[j] = glb((const T*)s.x[1])[q];
+      dx2[j] = glb((const T*)s.x[2])[q];
+      dv0[j] = glb((const T*)s.v[0])[q];
+      dv1[j] = glb((const T*)s.v[1])[q];
+      dv2[j] = glb((const T*)s.v[2])[q];
+      dm[j] = glb((const T*)s.m)[q];
+      dcomp[j] = glb((const int8_t*)s.comp)[q];
+      dgal[j] = glb((const int8_t*)s.gal)[q];
+      dlost[j] = glb((const uint8_t*)s.lost)[q];
+      did[j] = glb((const int32_t*)s.id)[q];
+    }
   }
-  d.m[j] = s.m[i];
-  d.comp[j] = s.comp[i];
-  d.gal[j] = s.gal[i];
-  d.lost[j] = s.lost[i];
-  d.id[j] = s.id[i];
 }
 
 __global__ void k_flip(int* cur, int n) {
@@ -1095,7 +1160,8 @@ sbx_status launch_sort(const InstDev<T>* inst, int* cur, const std::vector<InstI
   hipLaunchKernelGGL((k_sort_key<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
   SBX_HIP(hipGetLastError());
   SBX_TRY(exclusive_scan_u32(counts, total_counts, tmp, s));
-  hipLaunchKernelGGL((k_sort_scatter<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
+  const Span sq = make_span(info, blocks_sort);
+  hipLaunchKernelGGL((k_sort_scatter<T>), dim3(sq.start[sq.ninst]), dim3(256), 0, s, inst, cur, sq);
   hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, cur, (int)info.size());
   SBX_HIP(hipGetLastError());
   return SBX_OK;

@@ -173,3 +173,72 @@ def test_adjoint_rejects_bad_arguments(sbx):
     c2 = T.make_ctx(g, sbx.SBX_FP64)
     with pytest.raises(sbx.SbxError):
         c2.sbx_adjoint_segment(g.dt, 2, 1)
+
+
+def test_adjoint_segment_full_size_fd(sbx):
+    """The differentiable-segment workload at full size (one 256^3 grid,
+    2.05M particles, 10 steps, checkpoints every 2 steps), FP64: dL/dm against
+    central differences of the library's own forward on 32 seeded masses and
+    dL/dx, dL/dv on 8 of them."""
+    w = synth.adjoint_segment()
+    ctx = T.make_ctx(w, sbx.SBX_FP64)
+    L, gm, gx, gv = ctx.sbx_adjoint_segment(w.dt, w.steps, 2, synth.DISC, 0)
+    ctx.close()
+    sel = (w.comp == synth.DISC) & (w.gal == 0)
+    fwd = T.make_ctx(w, sbx.SBX_FP64)
+
+    def loss(x, v, m):
+        fwd.sbx_load_particles(x, v, m, w.comp, w.gal)
+        fwd.sbx_step(w.dt, w.steps)
+        _, vg, lg = fwd.sbx_get_particles()
+        s = sel & ~lg
+        return 0.5 * np.sum(m[s] * vg[s, 2] ** 2)
+
+    assert loss(w.x, w.v, w.m) == pytest.approx(L, rel=1e-12)
+    # the FP64 deposit sums in any order (atomics), so two forward runs differ
+    # by a few units in the last place of L: allow 64 of them in each
+    # difference quotient
+    def noise(h):
+        return 64 * np.spacing(L) / (2 * h)
+
+    rng = _rng(9)
+    picks = rng.choice(w.n, 32, replace=False)
+    for n_, q in enumerate(picks):
+        eps = 1e-2 * w.m[q]
+        mp = w.m.copy(); mp[q] += eps
+        mm = w.m.copy(); mm[q] -= eps
+        fd = (loss(w.x, w.v, mp) - loss(w.x, w.v, mm)) / (2 * eps)
+        assert fd == pytest.approx(gm[q], rel=1e-4, abs=max(1e-6 * np.abs(gm).max(), noise(eps)))
+        if n_ >= 8:
+            continue
+        a = int(rng.integers(0, 3))
+        h = 1e-6
+        vp = w.v.copy(); vp[q, a] += h
+        vm = w.v.copy(); vm[q, a] -= h
+        fd = (loss(w.x, vp, w.m) - loss(w.x, vm, w.m)) / (2 * h)
+        assert fd == pytest.approx(gv[q, a], rel=1e-4, abs=max(1e-6 * np.abs(gv).max(), noise(h)))
+        xp = w.x.copy(); xp[q, a] += h
+        xm = w.x.copy(); xm[q, a] -= h
+        fd = (loss(xp, w.v, w.m) - loss(xm, w.v, w.m)) / (2 * h)
+        assert fd == pytest.approx(gx[q, a], rel=1e-4, abs=max(1e-6 * np.abs(gx).max(), noise(h)))
+
+
+def test_adjoint_segment_full_size_fp32(sbx):
+    """FP32 form of the full-size segment against the FP64 form on the same
+    (FP32-rounded) inputs."""
+    import dataclasses
+    w = synth.adjoint_segment()
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    w = dataclasses.replace(w, x=f32(w.x), v=f32(w.v), m=f32(w.m))
+    out = {}
+    for prec in (sbx.SBX_FP64, sbx.SBX_FP32):
+        ctx = T.make_ctx(w, prec)
+        out[prec] = ctx.sbx_adjoint_segment(w.dt, w.steps, 2, synth.DISC, 0)
+        ctx.close()
+    L64, gm64, gx64, gv64 = out[sbx.SBX_FP64]
+    L32, gm32, gx32, gv32 = out[sbx.SBX_FP32]
+    errs = [_maxrel(a, b) for a, b in ((gm32, gm64), (gx32, gx64), (gv32, gv64))]
+    print(f"full-size FP32 adjoint: loss {abs(L32 / L64 - 1):.2e}, grad m/x/v "
+          f"{errs[0]:.2e} {errs[1]:.2e} {errs[2]:.2e}")
+    assert L32 == pytest.approx(L64, rel=1e-5)
+    assert errs[0] < 2e-4 and errs[1] < 5e-3 and errs[2] < 5e-4
