@@ -24,7 +24,7 @@ constexpr int kNDiag = kDiagLost + 1;
 constexpr int kPreVals = kMaxGal * 4;  // per galaxy [m, m x, m y, m z]
 constexpr int kRedBlocks = 1024;       // blocks per instance of the loss-test / COM pass
 constexpr int kForceBlocksMax = 4096;  // blocks per instance of the force pass
-constexpr int kDepChunk = 4096;        // particles per block of the mass assignment
+constexpr int kDepChunk = 2048;        // particles per block of the mass assignment
 
 // One grid geometry as the kernels use it (all float64, computed on the host
 // exactly as the method's formulas read: l = 2R/(N-4), lz = q l, gamma = 1/l).

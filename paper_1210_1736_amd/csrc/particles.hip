@@ -186,6 +186,18 @@ __device__ __forceinline__ T wave_run_sum(uint32_t key, T val, bool& tail) {
   return s;
 }
 
+// Sum over the 64 lanes by a DPP scan; the total is valid in lane 63 only.
+template <typename T>
+__device__ __forceinline__ T wave_total63(T v) {
+  v += dpp_t<kDppRowShr + 1, 0xf>(v);
+  v += dpp_t<kDppRowShr + 2, 0xf>(v);
+  v += dpp_t<kDppRowShr + 4, 0xf>(v);
+  v += dpp_t<kDppRowShr + 8, 0xf>(v);
+  v += dpp_t<kDppBcast15, 0xa>(v);
+  v += dpp_t<kDppBcast31, 0xc>(v);
+  return v;
+}
+
 // Key of a deposit target: grid slot (galaxy * 5 + slot) in the top bits,
 // cell index in the low 24 bits (N <= 256).
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
@@ -458,7 +470,8 @@ __global__ void __launch_bounds__(256)
 // as sums directly (their potentials are only used summed, and the solve is
 // linear), so a ring particle adds to slots 1 and 2 of its middle cell and
 // an outer particle to slots 3 and 4 of its global cell.
-constexpr int kDepTable = 4096;     // LDS hash entries (power of two)
+constexpr int kDepTableBits = 11;
+constexpr int kDepTable = 1 << kDepTableBits;  // LDS hash entries
 constexpr int kDepProbes = 8;
 
 template <typename T>
@@ -536,7 +549,7 @@ __global__ void __launch_bounds__(256)
       bool tail;
       const T s = wave_run_sum(key, m, tail);
       if (tail && key != kNoKey) {
-        uint32_t hslot = (key * 2654435761u) >> (32 - 12);
+        uint32_t hslot = (key * 2654435761u) >> (32 - kDepTableBits);
         bool done = false;
         for (int q = 0; q < kDepProbes && !done; ++q) {
           const uint32_t old = atomicCAS(tkey + hslot, kNoKey, key);
@@ -591,10 +604,12 @@ __global__ void __launch_bounds__(256)
     for (int k = threadIdx.x; k < 4 * kDiagDisc; k += 256) (&wacc[0][0])[k] = 0.0;
     __syncthreads();
   }
-  double com[MOVE ? kPreVals : 1];
+  // centre-of-mass sums of the moved particles, per wavefront in LDS (one
+  // writer per row, fixed order)
+  __shared__ double wcom[MOVE ? 4 : 1][MOVE ? kPreVals : 1];
   if constexpr (MOVE) {
-#pragma unroll
-    for (int k = 0; k < kPreVals; ++k) com[k] = 0.0;
+    for (int k = threadIdx.x; k < 4 * kPreVals; k += 256) (&wcom[0][0])[k] = 0.0;
+    __syncthreads();
   }
   const int64_t stride = (int64_t)nb * blockDim.x;
   for (int64_t i0 = (int64_t)lb * blockDim.x; i0 < p.n; i0 += stride) {
@@ -603,6 +618,8 @@ __global__ void __launch_bounds__(256)
     const bool live = valid && !LOST[i];
     int dc = -1;                        // component for the diagnostic sums
     double dv[DIAG ? kDiagComp : 1];    // this lane's contribution
+    int cg = -1;                        // galaxy for the centre-of-mass sums
+    double cm = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
     if (valid && !live) {
       if constexpr (OUT) {
         I.acc[3 * i] = I.acc[3 * i + 1] = I.acc[3 * i + 2] = 0.0;
@@ -661,17 +678,25 @@ __global__ void __launch_bounds__(256)
           LOST[i] = 1;
         } else {
           // centre-of-mass sums of the new positions for the next step
-          const int g = GAL[i];
-          const double m = (double)Mv[i];
-#pragma unroll
-          for (int gg = 0; gg < kMaxGal; ++gg) {
-            if (gg == g && sys.h[gg].centring == SBX_CENTRE_COM) {
-              com[4 * gg + 0] += m;
-              com[4 * gg + 1] += m * ex;
-              com[4 * gg + 2] += m * ey;
-              com[4 * gg + 3] += m * ez;
-            }
-          }
+          cg = GAL[i];
+          cm = (double)Mv[i];
+          cx = cm * ex;
+          cy = cm * ey;
+          cz = cm * ez;
+        }
+      }
+    }
+    if constexpr (MOVE) {
+      for (int g = 0; g < sys.ngal; ++g) {
+        if (sys.h[g].centring != SBX_CENTRE_COM) continue;
+        const bool mine = cg == g;
+        const double s0 = wave_total63(mine ? cm : 0.0), s1 = wave_total63(mine ? cx : 0.0);
+        const double s2 = wave_total63(mine ? cy : 0.0), s3 = wave_total63(mine ? cz : 0.0);
+        if (lane == 63) {
+          wcom[wave][4 * g + 0] += s0;
+          wcom[wave][4 * g + 1] += s1;
+          wcom[wave][4 * g + 2] += s2;
+          wcom[wave][4 * g + 3] += s3;
         }
       }
     }
@@ -698,8 +723,10 @@ __global__ void __launch_bounds__(256)
       out[k] = ((wacc[0][k] + wacc[1][k]) + wacc[2][k]) + wacc[3][k];
   }
   if constexpr (MOVE) {
-    if constexpr (DIAG) __syncthreads();
-    block_sum_store<kPreVals>(com, I.com_partial + (size_t)lb * kPreVals, 4 * sys.ngal);
+    __syncthreads();
+    double* out = I.com_partial + (size_t)lb * kPreVals;
+    for (int k = threadIdx.x; k < kPreVals; k += 256)
+      out[k] = k < 4 * sys.ngal ? ((wcom[0][k] + wcom[1][k]) + wcom[2][k]) + wcom[3][k] : 0.0;
   }
 }
 
