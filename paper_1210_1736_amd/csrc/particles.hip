@@ -345,10 +345,7 @@ static int64_t blocks_particles(const InstInfo& f) { return f.n > 0 ? (f.n + 255
 static int64_t blocks_force(const InstInfo& f) { return force_blocks(f.n); }
 static int64_t blocks_deposit(const InstInfo& f) { return f.n > 0 ? (f.n + kDepChunk - 1) / kDepChunk : 1; }
 static int64_t blocks_red(const InstInfo&) { return kRedBlocks; }
-constexpr int kSortPPT = 1;  // particles per thread of the sort scatter
-static int64_t blocks_sort(const InstInfo& f) {
-  return f.n > 0 ? (f.n + 256 * kSortPPT - 1) / (256 * kSortPPT) : 1;
-}
+static int64_t blocks_sort(const InstInfo& f) { return f.n > 0 ? (f.n + 255) / 256 : 1; }
 static int64_t blocks_grid(const InstInfo& f) {
   const int64_t b = (int64_t)((f.grid_elems + 1023) / 1024);
   return b < 1 ? 1 : (b > 2048 ? 2048 : b);
@@ -794,8 +791,6 @@ __global__ void __launch_bounds__(256)
 // lane reserves the whole run with one atomic add, the others take the
 // following slots in lane order.  Offsets are global (all instances' counts
 // scanned together); part_base turns them into the instance's own slots.
-// Each thread moves kSortPPT particles so that several reservations are in
-// flight before their results are needed.
 
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -807,56 +802,55 @@ __global__ void __launch_bounds__(256)
   const PartDev<T> s = I.p[c0];
   const PartDev<T> d = I.p[c0 ^ 1];
   const int lane = threadIdx.x & 63;
-  const gp<uint32_t> count = glb(I.count);
-  const gp<const uint32_t> key = glb((const uint32_t*)I.key);
-  int64_t i[kSortPPT];
-  uint32_t k[kSortPPT], rank1[kSortPPT], start[kSortPPT];
-  bool tail[kSortPPT];
-#pragma unroll
-  for (int u = 0; u < kSortPPT; ++u) {
-    i[u] = ((int64_t)lb * kSortPPT + u) * 256 + threadIdx.x;
-    k[u] = i[u] < s.n ? key[i[u]] : kNoKey;
+  const int64_t q = (int64_t)lb * 256 + threadIdx.x;
+  const bool in = q < s.n;
+  // the particle's fields are read before the slot reservation so that both
+  // latencies overlap
+  T x0 = 0, x1 = 0, x2 = 0, v0 = 0, v1 = 0, v2 = 0, m = 0;
+  int8_t comp = 0, gal = 0;
+  uint8_t lost = 0;
+  int32_t id = 0;
+  uint32_t k = kNoKey;
+  if (in) {
+    k = glb((const uint32_t*)I.key)[q];
+    x0 = glb((const T*)s.x[0])[q];
+    x1 = glb((const T*)s.x[1])[q];
+    x2 = glb((const T*)s.x[2])[q];
+    v0 = glb((const T*)s.v[0])[q];
+    v1 = glb((const T*)s.v[1])[q];
+    v2 = glb((const T*)s.v[2])[q];
+    m = glb((const T*)s.m)[q];
+    comp = glb((const int8_t*)s.comp)[q];
+    gal = glb((const int8_t*)s.gal)[q];
+    lost = glb((const uint8_t*)s.lost)[q];
+    id = glb((const int32_t*)s.id)[q];
   }
+  bool tail;
+  const uint32_t rank1 = wave_run_sum<uint32_t>(k, 1u, tail);  // 1-based rank in the run
+  uint32_t start = 0;
+  if (tail && k != kNoKey)
+    start = __hip_atomic_fetch_add(glb(I.count) + k, rank1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // nearest tail at or after this lane: suffix minimum of tail lane ids
+  int tl = tail ? lane : 64;
 #pragma unroll
-  for (int u = 0; u < kSortPPT; ++u) rank1[u] = wave_run_sum<uint32_t>(k[u], 1u, tail[u]);
-#pragma unroll
-  for (int u = 0; u < kSortPPT; ++u)
-    start[u] = (tail[u] && k[u] != kNoKey)
-                   ? __hip_atomic_fetch_add(count + k[u], rank1[u], __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT)
-                   : 0u;
-  const gp<T> dx0 = glb((T*)d.x[0]), dx1 = glb((T*)d.x[1]), dx2 = glb((T*)d.x[2]);
-  const gp<T> dv0 = glb((T*)d.v[0]), dv1 = glb((T*)d.v[1]), dv2 = glb((T*)d.v[2]);
-  const gp<T> dm = glb((T*)d.m);
-  const gp<int8_t> dcomp = glb(d.comp), dgal = glb(d.gal);
-  const gp<uint8_t> dlost = glb(d.lost);
-  const gp<int32_t> did = glb(d.id);
-#pragma unroll
-  for (int u = 0; u < kSortPPT; ++u) {
-    // nearest tail at or after this lane: suffix minimum of tail lane ids
-    int tl = tail[u] ? lane : 64;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t2 = __shfl_down(tl, o, 64);
-      if (lane + o < 64) tl = min(tl, t2);
-    }
-    const uint32_t run_start = __shfl(start[u], tl & 63, 64);
-    const int64_t q = i[u];
-    if (q < s.n) {
-      const uint32_t j = run_start + rank1[u] - 1 - I.part_base;
-      dx0[j] = glb((const T*)s.x[0])[q];
-      dx1[j] = glb((const T*)s.x[1])[q];
-      dx2[j] = glb((const T*)s.x[2])[q];
-      dv0[j] = glb((const T*)s.v[0])[q];
-      dv1[j] = glb((const T*)s.v[1])[q];
-      dv2[j] = glb((const T*)s.v[2])[q];
-      dm[j] = glb((const T*)s.m)[q];
-      dcomp[j] = glb((const int8_t*)s.comp)[q];
-      dgal[j] = glb((const int8_t*)s.gal)[q];
-      dlost[j] = glb((const uint8_t*)s.lost)[q];
-      did[j] = glb((const int32_t*)s.id)[q];
-    }
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t2 = __shfl_down(tl, o, 64);
+    if (lane + o < 64) tl = min(tl, t2);
   }
+  const uint32_t run_start = __shfl(start, tl & 63, 64);
+  if (!in) return;
+  const uint32_t j = run_start + rank1 - 1 - I.part_base;
+  glb((T*)d.x[0])[j] = x0;
+  glb((T*)d.x[1])[j] = x1;
+  glb((T*)d.x[2])[j] = x2;
+  glb((T*)d.v[0])[j] = v0;
+  glb((T*)d.v[1])[j] = v1;
+  glb((T*)d.v[2])[j] = v2;
+  glb((T*)d.m)[j] = m;
+  glb(d.comp)[j] = comp;
+  glb(d.gal)[j] = gal;
+  glb(d.lost)[j] = lost;
+  glb(d.id)[j] = id;
 }
 
 __global__ void k_flip(int* cur, int n) {
