@@ -305,7 +305,7 @@ sbx_status build_grids_t(sbx_ctx* c) {
                              &c->greens.back().rel_imag, c->stream));
     }
   SBX_TRY(dev_alloc(&c->X, x_elems(N) * sizeof(C2<T>) * total));
-  SBX_TRY(dev_alloc(&c->C, c_elems(N) * sizeof(C2<T>) * total));
+  SBX_TRY(dev_alloc(&c->C, cd_elems(N) * sizeof(C2<T>) * total));
   // one persistent plan for all solves of a step
   std::vector<SolveDesc<T>> descs;
   int s2 = 0;
@@ -315,7 +315,8 @@ sbx_status build_grids_t(sbx_ctx* c) {
       d.rho = (const T*)c->grid[g][k];
       d.phi = (T*)c->grid[g][k];
       d.X = (C2<T>*)c->X + x_elems(N) * s2;
-      d.C = (C2<T>*)c->C + c_elems(N) * s2;
+      d.C = (C2<T>*)c->C + cd_elems(N) * s2;
+      d.D = d.C + c_elems(N);
       d.H = nullptr;
       d.N = N;
       for (auto& e : c->greens)

@@ -5,9 +5,12 @@
 // Five passes, each a batch of 1D FFTs of length L = 2N held in LDS:
 //   fwd_x : rho[z][y][x]   (x < N)      -> X[kx][z][y]  (kx <= N, real-to-complex)
 //   fwd_y : X[kx][z][y]    (y < N)      -> C[kx][ky][z] (ky < 2N)
-//   zpass : C[kx][ky][z]   (z < N)      -> forward z, times Hhat, inverse z, keep z < N
-//   inv_y : C[kx][ky][z]                -> X[kx][z][y]  (keep y < N)
-//   inv_x : X[kx][z][y]    (kx <= N)    -> phi[z][y][x] (complex-to-real, keep x < N)
+//   zpass : C[kx][ky][z]   (z < N)      -> forward z, times Hhat, inverse z, keep z < N,
+//                                          stored as D[kx][z][ky]
+//   inv_y : D[kx][z][ky]                -> E[z][y][kx]  (keep y < N; E reuses X)
+//   inv_x : E[z][y][kx]    (kx <= N)    -> phi[z][y][x] (complex-to-real, keep x < N)
+// Every pass reads whole lines (contiguous); the transposes are done on the
+// write side, through LDS, in runs of at least 128 bytes.
 // Zero halves of the padded inputs are never read, unused halves of the
 // outputs never written.  Hhat (real, even per axis) is stored on (N+1)^3.
 //
@@ -27,8 +30,9 @@ template <typename T>
 struct SolveDesc {
   const T* rho;   // N^3 cell masses
   T* phi;         // N^3 output (may alias rho)
-  C2<T>* X;       // (N+1) * N * N
+  C2<T>* X;       // (N+1) * N * N, also E: N * N rows of N + kEPad
   C2<T>* C;       // (N+1) * 2N * N
+  C2<T>* D;       // (N+1) * N * 2N
   const T* H;     // (N+1)^3 transformed Green's function, scaled by G/(2N)^3
   int N;
 };
@@ -61,8 +65,13 @@ struct SolvePlan {
 };
 
 // Workspace sizes in elements of C2<T>.
-inline size_t x_elems(int N) { return (size_t)(N + 1) * N * N; }
+// E rows (kx = 0..N) are padded to N + 16 entries so that every row starts
+// on a 128-byte boundary; X (the forward layout) fits in the same space.
+constexpr int kEPad = 16;
+inline size_t x_elems(int N) { return (size_t)N * N * (N + kEPad); }
 inline size_t c_elems(int N) { return (size_t)(N + 1) * 2 * N * N; }
+// C and D of one solve, back to back (D = C + c_elems(N))
+inline size_t cd_elems(int N) { return 2 * c_elems(N); }
 inline size_t h_elems(int N) { return (size_t)(N + 1) * (N + 1) * (N + 1); }
 
 // Prepare a plan for the given solves (device tables, twiddles, launch

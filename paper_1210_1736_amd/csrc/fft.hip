@@ -259,20 +259,24 @@ struct TC {
   static constexpr int WC = 128 / (int)sizeof(C2<T>);
   static constexpr int fitw(int w) { return (w > 1 && w * LB > kLdsCap) ? fitw(w / 2) : w; }
   static constexpr int Wx0 = (WT > WC ? WT : WC) < N ? (WT > WC ? WT : WC) : N;
-  static constexpr int W = PASS == 2 ? (WT < L ? WT : L) : fitw(Wx0);
+  // lines per tile: z pass and inverse x (no staging of a strided side
+  // beyond their own lines) take one round of the block; the others at
+  // least WC lines for their transposed side
+  static constexpr int W = PASS == 2 ? (WT < L ? WT : L) : PASS == 4 ? (WT < N ? WT : N) : fitw(Wx0);
   static constexpr bool fits = W * LB <= kLdsCap;
   static constexpr int LDS = fits ? W * P : 1;  // elements of C2<T>
   static constexpr int ROUNDS = (W + WT - 1) / WT;
 };
 
-// tiles of each pass for one solve of line length L
+// tiles of each pass for one solve of line length L (the inverse y pass
+// tiles kx = 0..N, the last tile partly)
 template <typename T, int L, int NT>
 __host__ __device__ constexpr int tiles_of(int pass) {
   constexpr int N = L / 2;
   return pass == 0 ? N * (N / TC<T, L, NT, 0>::W)
        : pass == 1 ? (N + 1) * (N / TC<T, L, NT, 1>::W)
        : pass == 2 ? (N + 1) * (L / TC<T, L, NT, 2>::W)
-       : pass == 3 ? (N + 1) * (N / TC<T, L, NT, 3>::W)
+       : pass == 3 ? N * ((N + TC<T, L, NT, 3>::W) / TC<T, L, NT, 3>::W)
                    : N * (N / TC<T, L, NT, 4>::W);
 }
 
@@ -340,7 +344,7 @@ __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T
 
 // zpass: tile = W consecutive ky at one kx, one line per TL threads; forward
 // z (input z < N) from global, times Hhat in registers, inverse z, keep
-// z < N, back to global.  No block barrier.
+// z < N; stored transposed as D[kx][z][ky] through LDS.
 template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
@@ -349,105 +353,118 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
   constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
   const int tid = threadIdx.x, t = tid % TL, w = tid / TL;
-  if (w >= W) return;
-  const int kx = tile / (L / W), ky = (tile % (L / W)) * W + w;
-  C2<T>* __restrict__ g = d.C + ((size_t)kx * L + ky) * N;
-  C2<T>* sl = s + w * P;
-  C2<T> v[16];
+  const int kx = tile / (L / W), ky0 = (tile % (L / W)) * W;
+  if (w < W) {
+    const int ky = ky0 + w;
+    const C2<T>* __restrict__ g = d.C + ((size_t)kx * L + ky) * N;
+    C2<T>* sl = s + w * P;
+    C2<T> v[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = r < 8 ? g[t + r * TL] : C2<T>{(T)0, (T)0};
-  if constexpr (NP > 1) {
-    fwd_bfly<T, L, 0>(v, t, tw);
-    scatter_out<T, L, 0>(sl, t, v);
-    wave_sync();
-    gather_in<T, L, 1, false>(sl, t, v);
-    wave_sync();
-    if constexpr (NP > 2) {
-      fwd_bfly<T, L, 1>(v, t, tw);
-      scatter_out<T, L, 1>(sl, t, v);
+    for (int r = 0; r < 16; ++r) v[r] = r < 8 ? g[t + r * TL] : C2<T>{(T)0, (T)0};
+    if constexpr (NP > 1) {
+      fwd_bfly<T, L, 0>(v, t, tw);
+      scatter_out<T, L, 0>(sl, t, v);
       wave_sync();
-      gather_in<T, L, 2, false>(sl, t, v);
+      gather_in<T, L, 1, false>(sl, t, v);
       wave_sync();
+      if constexpr (NP > 2) {
+        fwd_bfly<T, L, 1>(v, t, tw);
+        scatter_out<T, L, 1>(sl, t, v);
+        wave_sync();
+        gather_in<T, L, 2, false>(sl, t, v);
+        wave_sync();
+      }
+    }
+    fwd_bfly<T, L, NP - 1>(v, t, tw);
+    // Hhat at frequencies (kx, ky, e), e = j + r L/R of the last pass
+    const T* __restrict__ H = d.H + ((size_t)kx * (N + 1) + (ky <= N ? ky : L - ky)) * (N + 1);
+#pragma unroll
+    for (int b = 0; b < 16 / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int e = t + b * TL + r * NBL;
+        v[b * RL + r] = cscale(v[b * RL + r], H[e <= N ? e : L - e]);
+      }
+    inv_down<T, L, NP - 1>(sl, t, v, tw);
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) sl[pad(t + r * TL)] = v[r];
+  }
+  __syncthreads();
+  C2<T>* __restrict__ dst = d.D + (size_t)kx * N * L + ky0;
+  for (int i = tid; i < W * N; i += NT) {
+    const int z = i / W, ww = i - z * W;
+    dst[(size_t)z * L + ww] = s[ww * P + pad(z)];
+  }
+}
+
+// inv_y: tile = W consecutive kx (<= N) at one z; lines D[kx][z][0..2N)
+// read straight into registers; output y < N stored transposed as
+// E[z][y][kx] (in the X buffer, rows padded to N + kEPad) through LDS.
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T>* s,
+                                           const C2<T>* __restrict__ tw) {
+  using K = TC<T, L, NT, 3>;
+  using F = Line<L>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
+  constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
+  constexpr int NKT = (N + W) / W;  // kx tiles
+  const int tid = threadIdx.x, t = tid % TL;
+  const int z = tile / NKT, kx0 = (tile % NKT) * W;
+#pragma unroll 1
+  for (int u = 0; u < K::ROUNDS; ++u) {
+    const int w = u * K::WT + tid / TL;
+    if (w < W && kx0 + w <= N) {
+      const C2<T>* __restrict__ src = d.D + ((size_t)(kx0 + w) * N + z) * L;
+      C2<T>* sl = s + w * P;
+      C2<T> v[16];
+      // inputs of the first inverse pass: natural positions of the last pass
+#pragma unroll
+      for (int b = 0; b < 16 / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) v[b * RL + r] = src[t + b * TL + r * NBL];
+      inv_down<T, L, NP - 1>(sl, t, v, tw);
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) sl[pad(t + r * TL)] = v[r];
     }
   }
-  fwd_bfly<T, L, NP - 1>(v, t, tw);
-  // Hhat at frequencies (kx, ky, e), e = j + r L/R of the last pass
-  const T* __restrict__ H = d.H + ((size_t)kx * (N + 1) + (ky <= N ? ky : L - ky)) * (N + 1);
+  __syncthreads();
+  C2<T>* __restrict__ dst = d.X + (size_t)z * N * (N + kEPad) + kx0;
+  for (int i = tid; i < W * N; i += NT) {
+    const int y = i / W, w = i - y * W;
+    if (kx0 + w <= N) dst[(size_t)y * (N + kEPad) + w] = s[w * P + pad(y)];
+  }
+}
+
+// inv_x: tile = W consecutive y at one z; lines E[z][y][0..N] read straight
+// into registers (rows of N + kEPad), the rest of each line by Hermitian
+// symmetry; real output
+// rows x < N written straight from registers.  No block barrier.
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T>* s,
+                                           const C2<T>* __restrict__ tw) {
+  using K = TC<T, L, NT, 4>;
+  using F = Line<L>;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
+  constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
+  const int tid = threadIdx.x, t = tid % TL, w = tid / TL;
+  const int z = tile / (N / W), y0 = (tile % (N / W)) * W;
+  if (w >= W) return;
+  const C2<T>* __restrict__ src = d.X + ((size_t)z * N + y0 + w) * (N + kEPad);
+  C2<T>* sl = s + w * P;
+  C2<T> v[16];
 #pragma unroll
   for (int b = 0; b < 16 / RL; ++b)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const int e = t + b * TL + r * NBL;
-      v[b * RL + r] = cscale(v[b * RL + r], H[e <= N ? e : L - e]);
+      v[b * RL + r] = e <= N ? src[e] : conjc(src[L - e]);
     }
   inv_down<T, L, NP - 1>(sl, t, v, tw);
+  T* __restrict__ dst = d.phi + ((size_t)z * N + y0 + w) * N;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) g[t + r * TL] = v[r];
-}
-
-// inv_y: tile = W consecutive z at one kx; ky strided by N, staged in LDS;
-// output lines X[kx][z][y < N] written straight from registers.
-template <typename T, int L, int NT>
-__device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T>* s,
-                                           const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT, 3>;
-  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = Line<L>::NP;
-  const int tid = threadIdx.x, t = tid % TL;
-  const int kx = tile / (N / W), z0 = (tile % (N / W)) * W;
-  const C2<T>* __restrict__ src = d.C + (size_t)kx * L * N + z0;
-  for (int i = tid; i < W * L; i += NT) {
-    const int e = i / W, w = i - e * W;
-    s[w * P + pad(e)] = src[(size_t)e * N + w];
-  }
-  __syncthreads();
-#pragma unroll 1
-  for (int u = 0; u < K::ROUNDS; ++u) {
-    const int w = u * K::WT + tid / TL;
-    if (w < W) {
-      C2<T>* sl = s + w * P;
-      C2<T> v[16];
-      gather_out<T, L, NP - 1>(sl, t, v);
-      wave_sync();
-      inv_down<T, L, NP - 1>(sl, t, v, tw);
-      C2<T>* __restrict__ dst = d.X + ((size_t)kx * N + z0 + w) * N;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) dst[t + r * TL] = v[r];
-    }
-  }
-}
-
-// inv_x: tile = W consecutive y at one z; kx <= N strided by N*N, the rest of
-// the line by Hermitian symmetry, staged in LDS; real output rows x < N
-// written straight from registers.
-template <typename T, int L, int NT>
-__device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T>* s,
-                                           const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT, 4>;
-  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = Line<L>::NP;
-  const int tid = threadIdx.x, t = tid % TL;
-  const int z = tile / (N / W), y0 = (tile % (N / W)) * W;
-  const C2<T>* __restrict__ src = d.X + (size_t)z * N + y0;
-  for (int i = tid; i < W * (N + 1); i += NT) {
-    const int e = i / W, w = i - e * W;
-    const C2<T> v = src[(size_t)e * N * N + w];
-    s[w * P + pad(e)] = v;
-    if (e >= 1 && e < N) s[w * P + pad(L - e)] = conjc(v);
-  }
-  __syncthreads();
-#pragma unroll 1
-  for (int u = 0; u < K::ROUNDS; ++u) {
-    const int w = u * K::WT + tid / TL;
-    if (w < W) {
-      C2<T>* sl = s + w * P;
-      C2<T> v[16];
-      gather_out<T, L, NP - 1>(sl, t, v);
-      wave_sync();
-      inv_down<T, L, NP - 1>(sl, t, v, tw);
-      T* __restrict__ dst = d.phi + ((size_t)z * N + y0 + w) * N;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) dst[t + r * TL] = v[r].re;
-    }
-  }
+  for (int r = 0; r < 8; ++r) dst[t + r * TL] = v[r].re;
 }
 
 template <typename T, int L, int NT, int PASS>
@@ -645,6 +662,7 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
     SBX_HIP(hipMemsetAsync((void*)host[i].rho, 0, sizeof(T) * (size_t)N * N * N, st));
     SBX_HIP(hipMemsetAsync(host[i].X, 0, sizeof(C2<T>) * x_elems(N), st));
     SBX_HIP(hipMemsetAsync(host[i].C, 0, sizeof(C2<T>) * c_elems(N), st));
+    SBX_HIP(hipMemsetAsync(host[i].D, 0, sizeof(C2<T>) * c_elems(N), st));
   }
   hipEvent_t e0, e1;
   SBX_HIP(hipEventCreate(&e0));

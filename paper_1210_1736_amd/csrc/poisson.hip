@@ -57,10 +57,10 @@ sbx_status poisson_solve_t(sbx_poisson* p, int batch, const void* rho, void* phi
     free_ptr(p->C);
     p->cap = 0;
     SBX_TRY(dev_alloc(&p->X, x_elems(p->N) * sizeof(C2<T>) * cap));
-    SBX_TRY(dev_alloc(&p->C, c_elems(p->N) * sizeof(C2<T>) * cap));
+    SBX_TRY(dev_alloc(&p->C, cd_elems(p->N) * sizeof(C2<T>) * cap));
     p->cap = cap;
     p->bytes = (int64_t)(h_elems(p->N) * sizeof(T) +
-                         (x_elems(p->N) + c_elems(p->N)) * sizeof(C2<T>) * cap);
+                         (x_elems(p->N) + cd_elems(p->N)) * sizeof(C2<T>) * cap);
   }
   for (int b0 = 0; b0 < batch; b0 += p->cap) {
     const int nb = std::min(p->cap, batch - b0);
@@ -76,7 +76,8 @@ sbx_status poisson_solve_t(sbx_poisson* p, int batch, const void* rho, void* phi
           d[i].rho = rr + cells * i;
           d[i].phi = ff + cells * i;
           d[i].X = (C2<T>*)p->X + x_elems(p->N) * i;
-          d[i].C = (C2<T>*)p->C + c_elems(p->N) * i;
+          d[i].C = (C2<T>*)p->C + cd_elems(p->N) * i;
+          d[i].D = d[i].C + c_elems(p->N);
           d[i].H = (const T*)p->H;
           d[i].N = p->N;
         }
