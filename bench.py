@@ -274,7 +274,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=20)
     ap.add_argument("--solve-iters", type=int, default=20)
     ap.add_argument("--diag-every", type=int, default=10)
-    ap.add_argument("--cpu-frac", type=float, default=0.3)
+    ap.add_argument("--cpu-frac", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--step-only", action="store_true",
