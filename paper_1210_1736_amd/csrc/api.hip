@@ -504,6 +504,9 @@ sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, 
     SBX_TRY(alloc(sizeof(double) * n, (void**)&gm));
     SBX_TRY(alloc(sizeof(double) * 4, (void**)&dloss));
     SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&stage));
+    // reorder by cell once for the segment (locality of the gathers and of
+    // the adjoint scatter); nothing is reordered inside the segment
+    if (c->sort_every > 0) SBX_TRY(sort_particles(c));
     PSet& live = c->set[c->cur];
     // forward with checkpoints
     for (int k = 0; k < nsteps; ++k) {

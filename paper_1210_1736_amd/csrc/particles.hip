@@ -863,25 +863,52 @@ __global__ void k_flip(int* cur, int n) {
 // lv += dt lx; mu = dt lv; lx += J mu with J the Eq. 8 second differences at
 // the particle; every field the particle reads gets A^T mu on its grid (the
 // Eq. 8 stencil weights transposed).  Adjoint state is kept in float64.
+//
+// The A^T mu contributions of a block's particles (19 cells per field) are
+// summed in an LDS hash table keyed like the deposit (grid slot, cell) and
+// flushed with one global atomic per distinct cell; cell-sorted particles
+// share most of their stencil cells.
+constexpr int kAdjTableBits = 12;
+constexpr int kAdjTable = 1 << kAdjTableBits;
+
 template <typename T>
-__device__ __forceinline__ void eq8_adjoint(const T* __restrict__ F, T* __restrict__ B,
-                                            const LevelDev& L, const int* id, double dx, double dy,
-                                            double dz, int taylor, const double* mu, double* lx) {
-  const ptrdiff_t sy = L.N, sz = (ptrdiff_t)L.N * L.N;
+struct AdjSink {
+  uint32_t* tkey;
+  T* tval;
+  const GridsDev<T>* B;
+  __device__ __forceinline__ void add(uint32_t key, double v) const {
+    uint32_t h = (key * 2654435761u) >> (32 - kAdjTableBits);
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t old = atomicCAS(tkey + h, kNoKey, key);
+      if (old == kNoKey || old == key) {
+        atomicAdd(tval + h, (T)v);
+        return;
+      }
+      h = (h + 1) & (kAdjTable - 1);
+    }
+    atomic_add_g(glb(slot_ptr(*B, key)), (T)v);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void eq8_adjoint(const T* __restrict__ F, const AdjSink<T>& sink,
+                                            uint32_t key, const LevelDev& L, const int* id,
+                                            double dx, double dy, double dz, int taylor,
+                                            const double* mu, double* lx) {
+  const int sy = L.N, sz = L.N * L.N;
   const ptrdiff_t o = (ptrdiff_t)id[2] * sz + (ptrdiff_t)id[1] * sy + id[0];
-  const T* P = F + o;
-  T* Q = B + o;
+  const gp<const T> P = glb(F) + o;
   const double Dx = dx - ((double)id[0] - L.half) * L.l;
   const double Dy = dy - ((double)id[1] - L.half) * L.l;
   const double Dz = dz - ((double)id[2] - L.half) * L.lz;
   const double mx = mu[0], my = mu[1], mz = mu[2];
   if (!taylor) {
-    unsafeAtomicAdd(Q + 1, (T)(mx * L.c_2l));
-    unsafeAtomicAdd(Q - 1, (T)(-mx * L.c_2l));
-    unsafeAtomicAdd(Q + sy, (T)(my * L.c_2l));
-    unsafeAtomicAdd(Q - sy, (T)(-my * L.c_2l));
-    unsafeAtomicAdd(Q + sz, (T)(mz * L.c_2lz));
-    unsafeAtomicAdd(Q - sz, (T)(-mz * L.c_2lz));
+    sink.add(key + 1, mx * L.c_2l);
+    sink.add(key - 1, -mx * L.c_2l);
+    sink.add(key + sy, my * L.c_2l);
+    sink.add(key - sy, -my * L.c_2l);
+    sink.add(key + sz, mz * L.c_2lz);
+    sink.add(key - sz, -mz * L.c_2lz);
     return;
   }
   // J mu from the field's second differences (symmetric)
@@ -897,28 +924,28 @@ __device__ __forceinline__ void eq8_adjoint(const T* __restrict__ F, T* __restri
   lx[2] += hxz * mx + hyz * my + hzz * mz;
   // A^T mu: faces, centre, edges
   const double wx = mx * Dx * L.c_l2, wy = my * Dy * L.c_l2, wz = mz * Dz * L.c_lz2;
-  unsafeAtomicAdd(Q + 1, (T)(mx * L.c_2l + wx));
-  unsafeAtomicAdd(Q - 1, (T)(-mx * L.c_2l + wx));
-  unsafeAtomicAdd(Q + sy, (T)(my * L.c_2l + wy));
-  unsafeAtomicAdd(Q - sy, (T)(-my * L.c_2l + wy));
-  unsafeAtomicAdd(Q + sz, (T)(mz * L.c_2lz + wz));
-  unsafeAtomicAdd(Q - sz, (T)(-mz * L.c_2lz + wz));
-  unsafeAtomicAdd(Q, (T)(-2.0 * (wx + wy + wz)));
+  sink.add(key + 1, mx * L.c_2l + wx);
+  sink.add(key - 1, -mx * L.c_2l + wx);
+  sink.add(key + sy, my * L.c_2l + wy);
+  sink.add(key - sy, -my * L.c_2l + wy);
+  sink.add(key + sz, mz * L.c_2lz + wz);
+  sink.add(key - sz, -mz * L.c_2lz + wz);
+  sink.add(key, -2.0 * (wx + wy + wz));
   const double exy = (mx * Dy + my * Dx) * L.c_4ll;
   const double exz = (mx * Dz + mz * Dx) * L.c_4llz;
   const double eyz = (my * Dz + mz * Dy) * L.c_4llz;
-  unsafeAtomicAdd(Q + 1 + sy, (T)exy);
-  unsafeAtomicAdd(Q - 1 + sy, (T)(-exy));
-  unsafeAtomicAdd(Q - 1 - sy, (T)exy);
-  unsafeAtomicAdd(Q + 1 - sy, (T)(-exy));
-  unsafeAtomicAdd(Q + 1 + sz, (T)exz);
-  unsafeAtomicAdd(Q - 1 + sz, (T)(-exz));
-  unsafeAtomicAdd(Q - 1 - sz, (T)exz);
-  unsafeAtomicAdd(Q + 1 - sz, (T)(-exz));
-  unsafeAtomicAdd(Q + sy + sz, (T)eyz);
-  unsafeAtomicAdd(Q - sy + sz, (T)(-eyz));
-  unsafeAtomicAdd(Q - sy - sz, (T)eyz);
-  unsafeAtomicAdd(Q + sy - sz, (T)(-eyz));
+  sink.add(key + 1 + sy, exy);
+  sink.add(key - 1 + sy, -exy);
+  sink.add(key - 1 - sy, exy);
+  sink.add(key + 1 - sy, -exy);
+  sink.add(key + 1 + sz, exz);
+  sink.add(key - 1 + sz, -exz);
+  sink.add(key - 1 - sz, exz);
+  sink.add(key + 1 - sz, -exz);
+  sink.add(key + sy + sz, eyz);
+  sink.add(key - sy + sz, -eyz);
+  sink.add(key - sy - sz, eyz);
+  sink.add(key + sy - sz, -eyz);
 }
 
 // Seed: L = sum over the selected particles of 1/2 m vz^2; dL/dvz = m vz,
@@ -949,51 +976,73 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_adj_step(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, GridsDev<T> Bg,
                const uint8_t* __restrict__ frozen, double* __restrict__ lx, double* __restrict__ lv) {
+  __shared__ uint32_t tkey[kAdjTable];
+  __shared__ T tval[kAdjTable];
+  for (int k = threadIdx.x; k < kAdjTable; k += 256) {
+    tkey[k] = kNoKey;
+    tval[k] = (T)0;
+  }
+  __syncthreads();
+  const AdjSink<T> sink{tkey, tval, &Bg};
   const InstDev<T>& I = inst[0];
   const PartDev<T> p = I.p[cur[0]];
   const SysDev& sys = I.sys;
   const double dt = I.dt;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n || frozen[i]) return;
-  double l[3] = {lx[3 * i], lx[3 * i + 1], lx[3 * i + 2]};
-  double w[3] = {lv[3 * i] + dt * l[0], lv[3 * i + 1] + dt * l[1], lv[3 * i + 2] + dt * l[2]};
-  lv[3 * i] = w[0];
-  lv[3 * i + 1] = w[1];
-  lv[3 * i + 2] = w[2];
-  const double mu[3] = {dt * w[0], dt * w[1], dt * w[2]};
-  const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
-  for (int g = 0; g < sys.ngal; ++g) {
-    const HierDev& h = sys.h[g];
-    const double* c = I.centres + 3 * g;
-    Classified cl;
-    classify(h, c, x, y, z, cl);
-    const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+  if (i < p.n && !frozen[i]) {
+    double l[3] = {lx[3 * i], lx[3 * i + 1], lx[3 * i + 2]};
+    double w[3] = {lv[3 * i] + dt * l[0], lv[3 * i + 1] + dt * l[1], lv[3 * i + 2] + dt * l[2]};
+    lv[3 * i] = w[0];
+    lv[3 * i + 1] = w[1];
+    lv[3 * i + 2] = w[2];
+    const double mu[3] = {dt * w[0], dt * w[1], dt * w[2]};
+    const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
     const GridsDev<T>& F = I.G;
-    if (h.n_levels == 1) {
-      if (cl.cls == SBX_OUTER) eq8_adjoint(F.g[g][0], Bg.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, sys.taylor, mu, l);
-      continue;
+    for (int g = 0; g < sys.ngal; ++g) {
+      const HierDev& h = sys.h[g];
+      const double* c = I.centres + 3 * g;
+      Classified cl;
+      classify(h, c, x, y, z, cl);
+      const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+      if (h.n_levels == 1) {
+        if (cl.cls == SBX_OUTER)
+          eq8_adjoint(F.g[g][0], sink, dep_key(g, 0, h.lv[0], cl.idx[0]), h.lv[0], cl.idx[0], dx, dy,
+                      dz, sys.taylor, mu, l);
+        continue;
+      }
+      const double ox = x - h.outer_c[0], oy = y - h.outer_c[1], oz = z - h.outer_c[2];
+      switch (cl.cls) {
+        case SBX_CORE:
+          eq8_adjoint(F.g[g][0], sink, dep_key(g, 0, h.lv[0], cl.idx[0]), h.lv[0], cl.idx[0], dx, dy,
+                      dz, sys.taylor, mu, l);
+          eq8_adjoint(F.g[g][1], sink, dep_key(g, 1, h.lv[1], cl.idx[1]), h.lv[1], cl.idx[1], dx, dy,
+                      dz, sys.taylor, mu, l);
+          eq8_adjoint(F.g[g][3], sink, dep_key(g, 3, h.lv[2], cl.idx[2]), h.lv[2], cl.idx[2], ox, oy,
+                      oz, sys.taylor, mu, l);
+          break;
+        case SBX_RING:
+          eq8_adjoint(F.g[g][2], sink, dep_key(g, 2, h.lv[1], cl.idx[1]), h.lv[1], cl.idx[1], dx, dy,
+                      dz, sys.taylor, mu, l);
+          eq8_adjoint(F.g[g][3], sink, dep_key(g, 3, h.lv[2], cl.idx[2]), h.lv[2], cl.idx[2], ox, oy,
+                      oz, sys.taylor, mu, l);
+          break;
+        case SBX_OUTER:
+          eq8_adjoint(F.g[g][4], sink, dep_key(g, 4, h.lv[2], cl.idx[2]), h.lv[2], cl.idx[2], ox, oy,
+                      oz, sys.taylor, mu, l);
+          break;
+        default:
+          break;
+      }
     }
-    const double ox = x - h.outer_c[0], oy = y - h.outer_c[1], oz = z - h.outer_c[2];
-    switch (cl.cls) {
-      case SBX_CORE:
-        eq8_adjoint(F.g[g][0], Bg.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, sys.taylor, mu, l);
-        eq8_adjoint(F.g[g][1], Bg.g[g][1], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, mu, l);
-        eq8_adjoint(F.g[g][3], Bg.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, mu, l);
-        break;
-      case SBX_RING:
-        eq8_adjoint(F.g[g][2], Bg.g[g][2], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, mu, l);
-        eq8_adjoint(F.g[g][3], Bg.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, mu, l);
-        break;
-      case SBX_OUTER:
-        eq8_adjoint(F.g[g][4], Bg.g[g][4], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, mu, l);
-        break;
-      default:
-        break;
-    }
+    lx[3 * i] = l[0];
+    lx[3 * i + 1] = l[1];
+    lx[3 * i + 2] = l[2];
   }
-  lx[3 * i] = l[0];
-  lx[3 * i + 1] = l[1];
-  lx[3 * i + 2] = l[2];
+  __syncthreads();
+  for (int k = threadIdx.x; k < kAdjTable; k += 256) {
+    const uint32_t key = tkey[k];
+    if (key != kNoKey) atomic_add_g(glb(slot_ptr(Bg, key)), tval[k]);
+  }
 }
 
 template <typename T>
