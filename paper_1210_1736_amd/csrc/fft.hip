@@ -258,14 +258,21 @@ struct TC {
   static constexpr int WT = NT / TL;
   static constexpr int WC = 128 / (int)sizeof(C2<T>);
   static constexpr int fitw(int w) { return (w > 1 && w * LB > kLdsCap) ? fitw(w / 2) : w; }
-  static constexpr int Wx0 = (WT > WC ? WT : WC) < N ? (WT > WC ? WT : WC) : N;
-  // lines per tile: z pass and inverse x (no staging of a strided side
-  // beyond their own lines) take one round of the block; the others at
-  // least WC lines for their transposed side
-  static constexpr int W = PASS == 2 ? (WT < L ? WT : L) : PASS == 4 ? (WT < N ? WT : N) : fitw(Wx0);
-  static constexpr bool fits = W * LB <= kLdsCap;
-  static constexpr int LDS = fits ? W * P : 1;  // elements of C2<T>
-  static constexpr int ROUNDS = (W + WT - 1) / WT;
+  static constexpr int fitw2(int w) { return (w > 2 && (w / 2) * LB > kLdsCap) ? fitw2(w / 2) : w; }
+  static constexpr int mx(int a, int b) { return a > b ? a : b; }
+  static constexpr int mn(int a, int b) { return a < b ? a : b; }
+  // W: grid rows per tile.  fwd_x packs two real rows into one complex line
+  // (W/2 lines, at least 128 bytes per stored run); the z pass takes one
+  // round of lines; inv_x takes one round of complex lines, each two real
+  // rows (2 W rows per tile); fwd_y and inv_y at least 128 bytes per run.
+  static constexpr int W = PASS == 0   ? fitw2(mn(N, mx(2 * WT, WC)))
+                         : PASS == 2 ? mn(WT, L)
+                         : PASS == 4 ? mn(WT, N / 2)
+                                     : fitw(mn(N, mx(WT, WC)));
+  static constexpr int LINES = PASS == 0 ? W / 2 : W;  // lines held in LDS
+  static constexpr bool fits = LINES * LB <= kLdsCap;
+  static constexpr int LDS = fits ? LINES * P : 1;     // elements of C2<T>
+  static constexpr int ROUNDS = (LINES + WT - 1) / WT;
 };
 
 // tiles of each pass for one solve of line length L (the inverse y pass
@@ -277,7 +284,7 @@ __host__ __device__ constexpr int tiles_of(int pass) {
        : pass == 1 ? (N + 1) * (N / TC<T, L, NT, 1>::W)
        : pass == 2 ? (N + 1) * (L / TC<T, L, NT, 2>::W)
        : pass == 3 ? N * ((N + TC<T, L, NT, 3>::W) / TC<T, L, NT, 3>::W)
-                   : N * (N / TC<T, L, NT, 4>::W);
+                   : N * (N / (2 * TC<T, L, NT, 4>::W));
 }
 
 template <typename T, int L, int NT, int PASS>
@@ -286,31 +293,40 @@ __host__ __device__ constexpr bool shape_fits() {
 }
 
 // ------------------------------------------------------------ the passes ---
-// fwd_x: tile = W consecutive y at one z; real input x < N read straight into
-// registers; output X[kx][z][y] (kx <= N) staged in LDS, stored across lines.
+// fwd_x: tile = W consecutive y at one z; real rows x < N taken two at a
+// time as the real and imaginary parts of one complex line (straight into
+// registers); after the transform the two spectra are separated by
+// Hermitian symmetry, X_a = (Z + conj Z(-k)) / 2, X_b = -i (Z - conj Z(-k)) / 2,
+// and stored as X[kx][z][y] (kx <= N) across rows.
 template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
   using K = TC<T, L, NT, 0>;
-  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
+  constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, WL = K::LINES;
   const int tid = threadIdx.x, t = tid % TL;
   const int z = tile / (N / W), y0 = (tile % (N / W)) * W;
 #pragma unroll 1
   for (int u = 0; u < K::ROUNDS; ++u) {
-    const int w = u * K::WT + tid / TL;
-    if (w < W) {
-      const T* __restrict__ src = d.rho + ((size_t)z * N + y0 + w) * N;
+    const int j = u * K::WT + tid / TL;
+    if (j < WL) {
+      const T* __restrict__ a = d.rho + ((size_t)z * N + y0 + 2 * j) * N;
+      const T* __restrict__ b = a + N;
       C2<T> v[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = r < 8 ? C2<T>{src[t + r * TL], (T)0} : C2<T>{(T)0, (T)0};
-      fwd_from<T, L, 0, true>(s + w * P, t, v, tw);
+      for (int r = 0; r < 16; ++r)
+        v[r] = r < 8 ? C2<T>{a[t + r * TL], b[t + r * TL]} : C2<T>{(T)0, (T)0};
+      fwd_from<T, L, 0, true>(s + j * P, t, v, tw);
     }
   }
   __syncthreads();
   C2<T>* __restrict__ dst = d.X + (size_t)z * N + y0;
+  const T h = (T)0.5;
   for (int i = tid; i < W * (N + 1); i += NT) {
     const int e = i / W, w = i - e * W;
-    dst[(size_t)e * N * N + w] = s[w * P + pad(e)];
+    const C2<T>* sl = s + (w >> 1) * P;
+    const C2<T> Z = sl[pad(e)], R = sl[pad(e == 0 ? 0 : L - e)];
+    dst[(size_t)e * N * N + w] = (w & 1) ? C2<T>{(Z.im + R.im) * h, (R.re - Z.re) * h}
+                                         : C2<T>{(Z.re + R.re) * h, (Z.im - R.im) * h};
   }
 }
 
@@ -437,10 +453,11 @@ __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T
   }
 }
 
-// inv_x: tile = W consecutive y at one z; lines E[z][y][0..N] read straight
-// into registers (rows of N + kEPad), the rest of each line by Hermitian
-// symmetry; real output
-// rows x < N written straight from registers.  No block barrier.
+// inv_x: tile = 2W consecutive y at one z; the lines E[z][y][0..N] of two
+// rows (each extended to 2N by Hermitian symmetry) are combined as A + iB
+// into one complex line, read straight into registers; the inverse
+// transform's real and imaginary parts are the two real output rows x < N.
+// No block barrier.
 template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
@@ -448,23 +465,34 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
   using F = Line<L>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
   constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
-  const int tid = threadIdx.x, t = tid % TL, w = tid / TL;
-  const int z = tile / (N / W), y0 = (tile % (N / W)) * W;
-  if (w >= W) return;
-  const C2<T>* __restrict__ src = d.X + ((size_t)z * N + y0 + w) * (N + kEPad);
-  C2<T>* sl = s + w * P;
+  const int tid = threadIdx.x, t = tid % TL, j = tid / TL;
+  const int z = tile / (N / (2 * W)), y0 = (tile % (N / (2 * W))) * 2 * W;
+  if (j >= W) return;
+  const C2<T>* __restrict__ A = d.X + ((size_t)z * N + y0 + 2 * j) * (N + kEPad);
+  const C2<T>* __restrict__ B = A + (N + kEPad);
+  C2<T>* sl = s + j * P;
   C2<T> v[16];
 #pragma unroll
   for (int b = 0; b < 16 / RL; ++b)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const int e = t + b * TL + r * NBL;
-      v[b * RL + r] = e <= N ? src[e] : conjc(src[L - e]);
+      if (e <= N) {
+        const C2<T> a = A[e], q = B[e];
+        v[b * RL + r] = C2<T>{a.re - q.im, a.im + q.re};
+      } else {
+        const C2<T> a = A[L - e], q = B[L - e];
+        v[b * RL + r] = C2<T>{a.re + q.im, q.re - a.im};
+      }
     }
   inv_down<T, L, NP - 1>(sl, t, v, tw);
-  T* __restrict__ dst = d.phi + ((size_t)z * N + y0 + w) * N;
+  T* __restrict__ da = d.phi + ((size_t)z * N + y0 + 2 * j) * N;
+  T* __restrict__ db = da + N;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) dst[t + r * TL] = v[r].re;
+  for (int r = 0; r < 8; ++r) {
+    da[t + r * TL] = v[r].re;
+    db[t + r * TL] = v[r].im;
+  }
 }
 
 template <typename T, int L, int NT, int PASS>
