@@ -609,10 +609,27 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
   }
   const int64_t stride = (int64_t)nb * blockDim.x;
+  // the next particle's flag and position are loaded one iteration ahead
+  int64_t inext = (int64_t)lb * blockDim.x + threadIdx.x;
+  uint8_t lnext = inext < p.n ? LOST[inext] : (uint8_t)1;
+  T xn = (T)0, yn = (T)0, zn = (T)0;
+  if (inext < p.n) {
+    xn = X0[inext];
+    yn = X1[inext];
+    zn = X2[inext];
+  }
   for (int64_t i0 = (int64_t)lb * blockDim.x; i0 < p.n; i0 += stride) {
     const int64_t i = i0 + threadIdx.x;
     const bool valid = i < p.n;
-    const bool live = valid && !LOST[i];
+    const bool live = valid && !lnext;
+    const T xs = xn, ys = yn, zs = zn;
+    inext = i + stride;
+    if (inext < p.n) {
+      lnext = LOST[inext];
+      xn = X0[inext];
+      yn = X1[inext];
+      zn = X2[inext];
+    }
     int dc = -1;                        // component for the diagnostic sums
     double dv[DIAG ? kDiagComp : 1];    // this lane's contribution
     int cg = -1;                        // galaxy for the centre-of-mass sums
@@ -625,7 +642,6 @@ __global__ void __launch_bounds__(256)
       if constexpr (DIAG) dd[5] += 1.0;
     }
     if (live) {
-      const T xs = X0[i], ys = X1[i], zs = X2[i];
       const double x = (double)xs, y = (double)ys, z = (double)zs;
       T a[3] = {(T)0, (T)0, (T)0};
       T phi = (T)0;
