@@ -504,19 +504,36 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   const int64_t base = (int64_t)lb * kDepChunk;
+  // the next particle is loaded one iteration ahead
+  auto fetch = [&](int64_t q, bool& ok, int& g, T& x, T& y, T& z, T& mm) {
+    ok = q < p.n && !LOST[q];
+    if (ok) {
+      g = GAL[q];
+      x = X0[q];
+      y = X1[q];
+      z = X2[q];
+      mm = Mv[q];
+    }
+  };
+  bool okn = false;
+  int gn = 0;
+  T xn = (T)0, yn = (T)0, zn = (T)0, mn = (T)0;
+  fetch(base + threadIdx.x, okn, gn, xn, yn, zn, mn);
   for (int j = 0; j < kDepChunk / 256; ++j) {
-    const int64_t i = base + j * 256 + threadIdx.x;
+    const bool ok = okn;
+    const int g = gn;
+    const T xs = xn, ys = yn, zs = zn, ms = mn;
+    if (j + 1 < kDepChunk / 256) fetch(base + (j + 1) * 256 + threadIdx.x, okn, gn, xn, yn, zn, mn);
     // fine: key on the finest level, fine2: the same cell in the summed slot
     // (ring and outer), or kNoKey; coarse keys c1, c2 go through the table
     uint32_t fine = kNoKey, fine2 = kNoKey, c1 = kNoKey, c2 = kNoKey;
     T m = (T)0;
-    if (i < p.n && !LOST[i]) {
-      const int g = GAL[i];
+    if (ok) {
       const HierDev& h = sys.h[g];
-      const double x = (double)X0[i], y = (double)X1[i], z = (double)X2[i];
+      const double x = (double)xs, y = (double)ys, z = (double)zs;
       Classified c;
       classify(h, cen + 3 * g, x, y, z, c);
-      m = Mv[i];
+      m = ms;
       if (h.n_levels == 1) {
         if (c.cls == SBX_OUTER) fine = dep_key(g, 0, h.lv[0], c.idx[0]);
       } else if (c.cls == SBX_CORE) {
