@@ -129,6 +129,16 @@ void sbx_destroy(sbx_ctx* ctx);
 sbx_status sbx_load_particles(sbx_ctx* ctx, int64_t n, const double* x, const double* v,
                               const double* m, const int8_t* comp, const int8_t* gal);
 
+/* As sbx_load_particles, from device memory of the context's device (same
+ * layouts; e.g. the storage of torch tensors).  The arrays are read on the
+ * context stream: work that produced them must be ordered before the call
+ * (same stream, or synchronised).  They are validated on the device (first
+ * bad particle reported, SBX_EINVAL); pointers that are not device memory of
+ * the context's device are rejected with SBX_EINVAL.  Borrowed for the call
+ * only. */
+sbx_status sbx_load_particles_device(sbx_ctx* ctx, int64_t n, const double* x, const double* v,
+                                     const double* m, const int8_t* comp, const int8_t* gal);
+
 /* Validate the hierarchies and build the Green's tables (Sec. 2.1: the
  * transformed H is computed once): H of Eq. 2 on lags 0..N, mirrored to
  * (2N)^3 by Eq. 5, transformed by an FP64 FFT, scaled by G/(2N)^3 and stored
@@ -149,6 +159,10 @@ sbx_status sbx_step(sbx_ctx* ctx, double dt, int32_t nsteps, int32_t diag_every)
 /* Read back positions, velocities (v(t - dt/2)) and lost flags (any may be
  * NULL).  Synchronises the context stream. */
 sbx_status sbx_get_particles(sbx_ctx* ctx, double* x, double* v, uint8_t* lost);
+
+/* As sbx_get_particles, into device memory of the context's device (written
+ * on the context stream; the call returns when the writes are done). */
+sbx_status sbx_get_particles_device(sbx_ctx* ctx, double* x, double* v, uint8_t* lost);
 
 /* Centres used by the last solve: n_galaxies * 3 doubles. */
 sbx_status sbx_get_centres(sbx_ctx* ctx, double* centres);
@@ -189,6 +203,12 @@ sbx_status sbx_diag_log(sbx_ctx* ctx, int32_t max, sbx_diag* out, int32_t* count
 sbx_status sbx_adjoint_segment(sbx_ctx* ctx, double dt, int32_t nsteps, int32_t ckpt_every,
                                int32_t sel_comp, int32_t sel_gal, double* loss, double* grad_m,
                                double* grad_x, double* grad_v);
+
+/* As sbx_adjoint_segment with grad_m, grad_x, grad_v in device memory of the
+ * context's device (loss stays a host pointer). */
+sbx_status sbx_adjoint_segment_device(sbx_ctx* ctx, double dt, int32_t nsteps, int32_t ckpt_every,
+                                      int32_t sel_comp, int32_t sel_gal, double* loss,
+                                      double* grad_m, double* grad_x, double* grad_v);
 
 /* Reorder the particles in device memory by the cell of their finest grid
  * every `every` steps (at the start of the step; 0 = never; default 4).  A

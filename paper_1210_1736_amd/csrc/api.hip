@@ -475,7 +475,7 @@ sbx_status copy_set(sbx_ctx* c, const PSet& dst, const PSet& src, bool with_v, b
 // gathers the mass gradient.  Particles lost by the end are frozen.
 template <typename T>
 sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, int sel_gal,
-                     double* loss, double* grad_m, double* grad_x, double* grad_v) {
+                     double* loss, double* grad_m, double* grad_x, double* grad_v, bool dev_out) {
   SBX_TRY(ensure_adjoint<T>(c));
   SBX_TRY(set_dt(c, dt));
   const int64_t n = c->n;
@@ -552,8 +552,9 @@ sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, 
     struct Out { double* host; double* dev; int w; } outs[3] = {{grad_m, gm, 1}, {grad_x, lx, 3}, {grad_v, lv, 3}};
     for (auto& o : outs) {
       if (!o.host) continue;
-      SBX_TRY(launch_unpermute<double>(o.dev, id, stage, n, o.w, c->stream));
-      SBX_HIP(hipMemcpyAsync(o.host, stage, sizeof(double) * o.w * n, hipMemcpyDeviceToHost, c->stream));
+      SBX_TRY(launch_unpermute<double>(o.dev, id, dev_out ? o.host : stage, n, o.w, c->stream));
+      if (!dev_out)
+        SBX_HIP(hipMemcpyAsync(o.host, stage, sizeof(double) * o.w * n, hipMemcpyDeviceToHost, c->stream));
       SBX_HIP(hipStreamSynchronize(c->stream));
     }
     SBX_HIP(hipStreamSynchronize(c->stream));
@@ -711,8 +712,22 @@ sbx_status sbx_profile_end(sbx_ctx* c, int32_t n_phases, double* out_ms, int64_t
   return SBX_OK;
 }
 
-sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const double* v,
-                              const double* m, const int8_t* comp, const int8_t* gal) {
+}  // extern "C"
+
+namespace {
+
+// Whether p is device memory of the given device (device or managed).
+bool on_device(const void* p, int device) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged) && at.device == device;
+}
+
+sbx_status load_impl(sbx_ctx* c, int64_t n, const double* x, const double* v, const double* m,
+                     const int8_t* comp, const int8_t* gal, bool dev) {
   if (!c || n <= 0 || !x || !v || !m || !comp || !gal) {
     set_error("null argument or n <= 0");
     return SBX_EINVAL;
@@ -725,26 +740,54 @@ sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const doub
     set_error("the context belongs to a batch");
     return SBX_ESTATE;
   }
-  for (int64_t i = 0; i < n; ++i) {
-    if (!std::isfinite(m[i]) || m[i] < 0.0) {
-      set_error("masses must be finite and >= 0 (particle " + std::to_string(i) + ")");
-      return SBX_EINVAL;
-    }
-    for (int k = 0; k < 3; ++k)
-      if (!std::isfinite(x[3 * i + k]) || !std::isfinite(v[3 * i + k])) {
-        set_error("positions and velocities must be finite (particle " + std::to_string(i) + ")");
+  SBX_TRY(set_device(c->cfg.device));
+  const int ngal_limit = c->built ? c->ngal : kMaxGal;
+  if (dev) {
+    for (const void* p : {(const void*)x, (const void*)v, (const void*)m, (const void*)comp, (const void*)gal})
+      if (!on_device(p, c->cfg.device)) {
+        set_error("inputs must be device memory of the context's device");
         return SBX_EINVAL;
       }
-    if (comp[i] < 0 || comp[i] >= kNComp || gal[i] < 0 || gal[i] >= kMaxGal) {
-      set_error("component id in 0..7 and galaxy id in 0..3 required");
+    unsigned long long* bad = nullptr;
+    SBX_TRY(dev_alloc((void**)&bad, sizeof(unsigned long long)));
+    unsigned long long first = ~0ull;
+    sbx_status rc = SBX_OK;
+    if (hipMemcpyAsync(bad, &first, sizeof(first), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        launch_validate_particles(x, v, m, comp, gal, n, ngal_limit, bad, c->stream) != SBX_OK ||
+        hipMemcpyAsync(&first, bad, sizeof(first), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      set_error(std::string("particle validation: ") + hipGetErrorString(hipGetLastError()));
+      rc = SBX_EDEVICE;
+    }
+    (void)hipFree(bad);
+    SBX_TRY(rc);
+    if (first != ~0ull) {
+      set_error("particle " + std::to_string(first) +
+                ": masses must be finite and >= 0, positions and velocities finite, component id "
+                "in 0..7 and galaxy id within the hierarchies");
       return SBX_EINVAL;
     }
-    if (c->built && gal[i] >= c->ngal) {
-      set_error("galaxy id beyond the built hierarchies");
-      return SBX_EINVAL;
+  } else {
+    for (int64_t i = 0; i < n; ++i) {
+      if (!std::isfinite(m[i]) || m[i] < 0.0) {
+        set_error("masses must be finite and >= 0 (particle " + std::to_string(i) + ")");
+        return SBX_EINVAL;
+      }
+      for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(x[3 * i + k]) || !std::isfinite(v[3 * i + k])) {
+          set_error("positions and velocities must be finite (particle " + std::to_string(i) + ")");
+          return SBX_EINVAL;
+        }
+      if (comp[i] < 0 || comp[i] >= kNComp || gal[i] < 0 || gal[i] >= kMaxGal) {
+        set_error("component id in 0..7 and galaxy id in 0..3 required");
+        return SBX_EINVAL;
+      }
+      if (c->built && gal[i] >= c->ngal) {
+        set_error("galaxy id beyond the built hierarchies");
+        return SBX_EINVAL;
+      }
     }
   }
-  SBX_TRY(set_device(c->cfg.device));
   SBX_HIP(hipStreamSynchronize(c->stream));
   free_particles(c);
   const size_t es = c->esz;
@@ -764,42 +807,112 @@ sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const doub
   c->n = n;
   c->cur = 0;
   double* stage = nullptr;
-  SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 3 * n));
+  if (!dev) SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 3 * n));
   PSet& q = c->set[0];
+  // device inputs are read in place; host inputs go through one staging array
+  auto in = [&](const double* src, size_t count) -> const double* {
+    if (dev) return src;
+    if (hipMemcpy(stage, src, sizeof(double) * count, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    return stage;
+  };
+  const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   auto run = [&]() -> sbx_status {
-    SBX_HIP(hipMemcpy(stage, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    for (int which = 0; which < 2; ++which) {
+      const double* src = in(which == 0 ? x : v, 3 * (size_t)n);
+      if (!src) {
+        set_error(std::string("particle upload: ") + hipGetErrorString(hipGetLastError()));
+        return SBX_EDEVICE;
+      }
+      void* const* d = which == 0 ? q.x : q.v;
+      if (c->cfg.prec == SBX_FP64)
+        SBX_TRY(launch_split3<double>(src, (double*)d[0], (double*)d[1], (double*)d[2], n, c->stream));
+      else
+        SBX_TRY(launch_split3<float>(src, (float*)d[0], (float*)d[1], (float*)d[2], n, c->stream));
+      SBX_HIP(hipStreamSynchronize(c->stream));
+    }
+    const double* ms = in(m, n);
+    if (!ms) {
+      set_error(std::string("particle upload: ") + hipGetErrorString(hipGetLastError()));
+      return SBX_EDEVICE;
+    }
     if (c->cfg.prec == SBX_FP64)
-      SBX_TRY(launch_split3<double>(stage, (double*)q.x[0], (double*)q.x[1], (double*)q.x[2], n, c->stream));
+      SBX_TRY(launch_convert_in<double>(ms, (double*)q.m, n, c->stream));
     else
-      SBX_TRY(launch_split3<float>(stage, (float*)q.x[0], (float*)q.x[1], (float*)q.x[2], n, c->stream));
-    SBX_HIP(hipStreamSynchronize(c->stream));
-    SBX_HIP(hipMemcpy(stage, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
-    if (c->cfg.prec == SBX_FP64)
-      SBX_TRY(launch_split3<double>(stage, (double*)q.v[0], (double*)q.v[1], (double*)q.v[2], n, c->stream));
-    else
-      SBX_TRY(launch_split3<float>(stage, (float*)q.v[0], (float*)q.v[1], (float*)q.v[2], n, c->stream));
-    SBX_HIP(hipStreamSynchronize(c->stream));
-    SBX_HIP(hipMemcpy(stage, m, sizeof(double) * n, hipMemcpyHostToDevice));
-    if (c->cfg.prec == SBX_FP64)
-      SBX_TRY(launch_convert_in<double>(stage, (double*)q.m, n, c->stream));
-    else
-      SBX_TRY(launch_convert_in<float>(stage, (float*)q.m, n, c->stream));
-    SBX_HIP(hipStreamSynchronize(c->stream));
-    SBX_HIP(hipMemcpy(q.comp, comp, n, hipMemcpyHostToDevice));
-    SBX_HIP(hipMemcpy(q.gal, gal, n, hipMemcpyHostToDevice));
-    SBX_HIP(hipMemset(q.lost, 0, n));
+      SBX_TRY(launch_convert_in<float>(ms, (float*)q.m, n, c->stream));
+    SBX_HIP(hipMemcpyAsync(q.comp, comp, n, kind, c->stream));
+    SBX_HIP(hipMemcpyAsync(q.gal, gal, n, kind, c->stream));
+    SBX_TRY(launch_zero<uint8_t>(q.lost, n, c->stream));
     SBX_TRY(launch_iota(q.id, n, c->stream));
     SBX_HIP(hipStreamSynchronize(c->stream));
     return SBX_OK;
   };
   sbx_status rc = run();
-  (void)hipFree(stage);
+  if (stage) (void)hipFree(stage);
   c->solved = false;
   c->grids_fields = false;
   c->com_fresh = false;
   c->step_count = 0;
   if (rc == SBX_OK) rc = upload_inst(c);
   return rc;
+}
+
+sbx_status get_impl(sbx_ctx* c, double* x, double* v, uint8_t* lost, bool dev) {
+  if (!c || c->n == 0) {
+    set_error("no particles loaded");
+    return c ? SBX_ESTATE : SBX_EINVAL;
+  }
+  if (c->batch && c->batch->pending) {
+    set_error("the context's batch has queued work: call sbx_batch_sync first");
+    return SBX_ESTATE;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  if (dev)
+    for (const void* p : {(const void*)x, (const void*)v, (const void*)lost})
+      if (p && !on_device(p, c->cfg.device)) {
+        set_error("outputs must be device memory of the context's device");
+        return SBX_EINVAL;
+      }
+  const PSet& q = c->set[c->cur];
+  double* stage = nullptr;
+  SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 6 * c->n));
+  double* stage2 = stage + 3 * c->n;
+  auto run = [&]() -> sbx_status {
+    for (int which = 0; which < 2; ++which) {
+      double* out = which == 0 ? x : v;
+      void* const* src = which == 0 ? q.x : q.v;
+      if (!out) continue;
+      if (c->cfg.prec == SBX_FP64)
+        SBX_TRY(launch_join3<double>((double*)src[0], (double*)src[1], (double*)src[2], stage, c->n, c->stream));
+      else
+        SBX_TRY(launch_join3<float>((float*)src[0], (float*)src[1], (float*)src[2], stage, c->n, c->stream));
+      SBX_TRY(launch_unpermute<double>(stage, q.id, dev ? out : stage2, c->n, 3, c->stream));
+      if (!dev) SBX_HIP(hipMemcpyAsync(out, stage2, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
+      SBX_HIP(hipStreamSynchronize(c->stream));
+    }
+    if (lost) {
+      SBX_TRY(launch_unpermute<uint8_t>(q.lost, q.id, dev ? lost : (uint8_t*)stage, c->n, 1, c->stream));
+      if (!dev) SBX_HIP(hipMemcpyAsync(lost, stage, c->n, hipMemcpyDeviceToHost, c->stream));
+    }
+    SBX_HIP(hipStreamSynchronize(c->stream));
+    return SBX_OK;
+  };
+  const sbx_status rc = run();
+  (void)hipFree(stage);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const double* v,
+                              const double* m, const int8_t* comp, const int8_t* gal) {
+  return load_impl(c, n, x, v, m, comp, gal, false);
+}
+
+sbx_status sbx_load_particles_device(sbx_ctx* c, int64_t n, const double* x, const double* v,
+                                     const double* m, const int8_t* comp, const int8_t* gal) {
+  return load_impl(c, n, x, v, m, comp, gal, true);
 }
 
 sbx_status sbx_build_grids(sbx_ctx* c, int32_t n_galaxies, const sbx_hierarchy* h) {
@@ -901,42 +1014,11 @@ sbx_status sbx_step(sbx_ctx* c, double dt, int32_t nsteps, int32_t diag_every) {
 }
 
 sbx_status sbx_get_particles(sbx_ctx* c, double* x, double* v, uint8_t* lost) {
-  if (!c || c->n == 0) {
-    set_error("no particles loaded");
-    return c ? SBX_ESTATE : SBX_EINVAL;
-  }
-  if (c->batch && c->batch->pending) {
-    set_error("the context's batch has queued work: call sbx_batch_sync first");
-    return SBX_ESTATE;
-  }
-  SBX_TRY(set_device(c->cfg.device));
-  const PSet& q = c->set[c->cur];
-  double* stage = nullptr;
-  SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * 6 * c->n));
-  double* stage2 = stage + 3 * c->n;
-  auto run = [&]() -> sbx_status {
-    for (int which = 0; which < 2; ++which) {
-      double* out = which == 0 ? x : v;
-      void* const* src = which == 0 ? q.x : q.v;
-      if (!out) continue;
-      if (c->cfg.prec == SBX_FP64)
-        SBX_TRY(launch_join3<double>((double*)src[0], (double*)src[1], (double*)src[2], stage, c->n, c->stream));
-      else
-        SBX_TRY(launch_join3<float>((float*)src[0], (float*)src[1], (float*)src[2], stage, c->n, c->stream));
-      SBX_TRY(launch_unpermute<double>(stage, q.id, stage2, c->n, 3, c->stream));
-      SBX_HIP(hipMemcpyAsync(out, stage2, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
-      SBX_HIP(hipStreamSynchronize(c->stream));
-    }
-    if (lost) {
-      SBX_TRY(launch_unpermute<uint8_t>(q.lost, q.id, (uint8_t*)stage, c->n, 1, c->stream));
-      SBX_HIP(hipMemcpyAsync(lost, stage, c->n, hipMemcpyDeviceToHost, c->stream));
-    }
-    SBX_HIP(hipStreamSynchronize(c->stream));
-    return SBX_OK;
-  };
-  const sbx_status rc = run();
-  (void)hipFree(stage);
-  return rc;
+  return get_impl(c, x, v, lost, false);
+}
+
+sbx_status sbx_get_particles_device(sbx_ctx* c, double* x, double* v, uint8_t* lost) {
+  return get_impl(c, x, v, lost, true);
 }
 
 sbx_status sbx_get_centres(sbx_ctx* c, double* centres) {
@@ -1074,10 +1156,20 @@ sbx_status sbx_diag_log(sbx_ctx* c, int32_t max, sbx_diag* out, int32_t* count) 
   return SBX_OK;
 }
 
-sbx_status sbx_adjoint_segment(sbx_ctx* c, double dt, int32_t nsteps, int32_t ckpt_every,
-                               int32_t sel_comp, int32_t sel_gal, double* loss, double* grad_m,
-                               double* grad_x, double* grad_v) {
+}  // extern "C"
+
+namespace {
+
+sbx_status adjoint_impl(sbx_ctx* c, double dt, int32_t nsteps, int32_t ckpt_every, int32_t sel_comp,
+                        int32_t sel_gal, double* loss, double* grad_m, double* grad_x,
+                        double* grad_v, bool dev_out) {
   SBX_TRY(check_ready(c));
+  if (dev_out)
+    for (const void* p : {(const void*)grad_m, (const void*)grad_x, (const void*)grad_v})
+      if (p && !on_device(p, c->cfg.device)) {
+        set_error("gradient outputs must be device memory of the context's device");
+        return SBX_EINVAL;
+      }
   if (c->batch) {
     set_error("the context belongs to a batch");
     return SBX_ESTATE;
@@ -1093,8 +1185,26 @@ sbx_status sbx_adjoint_segment(sbx_ctx* c, double dt, int32_t nsteps, int32_t ck
       return SBX_EINVAL;
     }
   return c->cfg.prec == SBX_FP64
-             ? adjoint_t<double>(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x, grad_v)
-             : adjoint_t<float>(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x, grad_v);
+             ? adjoint_t<double>(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x,
+                                 grad_v, dev_out)
+             : adjoint_t<float>(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x,
+                                grad_v, dev_out);
+}
+
+}  // namespace
+
+extern "C" {
+
+sbx_status sbx_adjoint_segment(sbx_ctx* c, double dt, int32_t nsteps, int32_t ckpt_every,
+                               int32_t sel_comp, int32_t sel_gal, double* loss, double* grad_m,
+                               double* grad_x, double* grad_v) {
+  return adjoint_impl(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x, grad_v, false);
+}
+
+sbx_status sbx_adjoint_segment_device(sbx_ctx* c, double dt, int32_t nsteps, int32_t ckpt_every,
+                                      int32_t sel_comp, int32_t sel_gal, double* loss,
+                                      double* grad_m, double* grad_x, double* grad_v) {
+  return adjoint_impl(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x, grad_v, true);
 }
 
 sbx_status sbx_set_sort_interval(sbx_ctx* c, int32_t every) {

@@ -184,6 +184,12 @@ sbx_status launch_adj_gather(const InstDev<T>* inst, const int* cur, int64_t n, 
 
 sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s);
 
+// Device-side check of particle inputs (device arrays, host layout): the
+// lowest bad index goes to *bad (device, preset to all ones by the caller).
+sbx_status launch_validate_particles(const double* x, const double* v, const double* m,
+                                     const int8_t* comp, const int8_t* gal, int64_t n, int ngal,
+                                     unsigned long long* bad, hipStream_t s);
+
 // dst[id[i] * width + w] = src[i * width + w]
 template <typename A>
 sbx_status launch_unpermute(const A* src, const int32_t* id, A* dst, int64_t n, int width,

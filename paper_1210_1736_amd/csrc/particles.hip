@@ -1312,6 +1312,32 @@ sbx_status launch_adj_gather(const InstDev<T>* inst, const int* cur, int64_t n, 
   return SBX_OK;
 }
 
+// First particle (lowest index) whose inputs are not acceptable: non-finite
+// or negative mass, non-finite position or velocity, component outside
+// 0..kNComp-1, galaxy outside 0..ngal-1.  *bad stays at its initial value
+// (all ones) when every particle is acceptable.
+__global__ void k_validate_particles(const double* __restrict__ x, const double* __restrict__ v,
+                                     const double* __restrict__ m, const int8_t* __restrict__ comp,
+                                     const int8_t* __restrict__ gal, int64_t n, int ngal,
+                                     unsigned long long* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    bool ok = isfinite(m[i]) && m[i] >= 0.0 && comp[i] >= 0 && comp[i] < kNComp && gal[i] >= 0 &&
+              gal[i] < ngal;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ok = ok && isfinite(x[3 * i + k]) && isfinite(v[3 * i + k]);
+    if (!ok) atomicMin(bad, (unsigned long long)i);
+  }
+}
+
+sbx_status launch_validate_particles(const double* x, const double* v, const double* m,
+                                     const int8_t* comp, const int8_t* gal, int64_t n, int ngal,
+                                     unsigned long long* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate_particles, dim3(2048), dim3(256), 0, s, x, v, m, comp, gal, n, ngal, bad);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
 sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_iota, dim3(2048), dim3(256), 0, s, id, n);
   SBX_HIP(hipGetLastError());
@@ -1386,6 +1412,7 @@ SBX_INST(float)
 SBX_INST(double)
 #undef SBX_INST
 template sbx_status launch_zero<uint32_t>(uint32_t*, size_t, hipStream_t);
+template sbx_status launch_zero<uint8_t>(uint8_t*, size_t, hipStream_t);
 template sbx_status launch_unpermute<double>(const double*, const int32_t*, double*, int64_t, int, hipStream_t);
 template sbx_status launch_unpermute<int32_t>(const int32_t*, const int32_t*, int32_t*, int64_t, int, hipStream_t);
 template sbx_status launch_unpermute<int8_t>(const int8_t*, const int32_t*, int8_t*, int64_t, int, hipStream_t);

@@ -91,6 +91,9 @@ def _load():
         "sbx_sync": (S, [P]),
         "sbx_set_sort_interval": (S, [P, I32]),
         "sbx_adjoint_segment": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
+        "sbx_adjoint_segment_device": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
+        "sbx_load_particles_device": (S, [P, I64, P, P, P, P, P]),
+        "sbx_get_particles_device": (S, [P, P, P, P]),
         "sbx_count_live": (S, [P, C.POINTER(I64)]),
         "sbx_profile_begin": (S, [P, I32]),
         "sbx_profile_end": (S, [P, I32, P, P]),
@@ -196,6 +199,28 @@ class Context:
             raise ValueError("shapes: x, v (n,3); m, comp, gal (n,)")
         _check(_lib.sbx_load_particles(self._h, n, _ptr(x), _ptr(v), _ptr(m), _ptr(comp), _ptr(gal)))
         self.n = n
+
+    def sbx_load_particles_device(self, n, x, v, m, comp, gal):
+        """Device pointers (ints, e.g. tensor.data_ptr()): x, v float64 (n,3),
+        m float64 (n,), comp, gal int8 (n,), on the context's device."""
+        _check(_lib.sbx_load_particles_device(self._h, int(n), C.c_void_p(x), C.c_void_p(v),
+                                              C.c_void_p(m), C.c_void_p(comp), C.c_void_p(gal)))
+        self.n = int(n)
+
+    def sbx_get_particles_device(self, x=None, v=None, lost=None):
+        """Device pointers (ints) for x, v float64 (n,3) and lost uint8 (n,)."""
+        vp = lambda a: C.c_void_p(a) if a else None
+        _check(_lib.sbx_get_particles_device(self._h, vp(x), vp(v), vp(lost)))
+
+    def sbx_adjoint_segment_device(self, dt, nsteps, ckpt_every, sel_comp, sel_gal, grad_m, grad_x,
+                                   grad_v):
+        """Gradients into device pointers (ints or None); returns the loss."""
+        loss = np.zeros(1)
+        vp = lambda a: C.c_void_p(a) if a else None
+        _check(_lib.sbx_adjoint_segment_device(self._h, float(dt), int(nsteps), int(ckpt_every),
+                                               int(sel_comp), int(sel_gal), _ptr(loss), vp(grad_m),
+                                               vp(grad_x), vp(grad_v)))
+        return float(loss[0])
 
     def sbx_build_grids(self, hierarchies):
         arr = hierarchy_array(hierarchies)

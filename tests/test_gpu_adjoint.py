@@ -242,3 +242,24 @@ def test_adjoint_segment_full_size_fp32(sbx):
           f"{errs[0]:.2e} {errs[1]:.2e} {errs[2]:.2e}")
     assert L32 == pytest.approx(L64, rel=1e-5)
     assert errs[0] < 2e-4 and errs[1] < 5e-3 and errs[2] < 5e-4
+
+
+def test_adjoint_autograd_on_gpu_tensors(sbx):
+    """The autograd form with CUDA tensors: device entry points, gradients
+    returned as device tensors, equal to the oracle's."""
+    import torch
+    from paper_1210_1736_amd.autograd import segment_loss
+    w = _workload("nested", n=1500, seed=10)
+    ctx = T.make_ctx(w, sbx.SBX_FP64)
+    x = torch.tensor(w.x, device="cuda", requires_grad=True)
+    v = torch.tensor(w.v, device="cuda", requires_grad=True)
+    m = torch.tensor(w.m, device="cuda", requires_grad=True)
+    L = segment_loss(ctx, x, v, m, w.comp, w.gal, w.dt, 4, 2, 1, 0)
+    L.backward()
+    assert m.grad.is_cuda and x.grad.is_cuda
+    Lr, gmr, gxr, gvr = O.segment_loss_and_grads(T.oracle_system(w), w.x, w.v, w.m, w.comp, w.gal,
+                                                  w.dt, 4, 1, 0)
+    assert float(L.detach()) == pytest.approx(Lr, rel=1e-12)
+    assert _maxrel(m.grad.cpu().numpy(), gmr) < 1e-9
+    assert _maxrel(x.grad.cpu().numpy(), gxr) < 1e-9
+    assert _maxrel(v.grad.cpu().numpy(), gvr) < 1e-9

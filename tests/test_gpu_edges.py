@@ -104,3 +104,64 @@ def test_empty_input_rejected(sbx):
         ctx.sbx_load_particles(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0),
                                np.zeros(0, np.int8), np.zeros(0, np.int8))
     assert e.value.status == sbx.SBX_EINVAL
+
+
+def test_device_entry_points_match_host(sbx):
+    """Particles loaded from device memory and read back into device memory
+    equal the host path, before and after steps."""
+    import torch
+    w = _nested(5000, 13)
+    a = T.make_ctx(w, sbx.SBX_FP32)
+    b = sbx.Context(prec=sbx.SBX_FP32, G=w.G)
+    b.sbx_build_grids([T.sbx_hier(h) for h in w.hier])
+    xd = torch.tensor(w.x, device="cuda")
+    vd = torch.tensor(w.v, device="cuda")
+    md = torch.tensor(w.m, device="cuda")
+    cd = torch.tensor(w.comp, device="cuda")
+    gd = torch.tensor(w.gal, device="cuda")
+    torch.cuda.synchronize()
+    b.sbx_load_particles_device(w.n, xd.data_ptr(), vd.data_ptr(), md.data_ptr(), cd.data_ptr(),
+                                gd.data_ptr())
+    for steps in (0, 5):
+        a.sbx_step(w.dt, steps)
+        b.sbx_step(w.dt, steps)
+        xa, va, la = a.sbx_get_particles()
+        xo = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
+        vo = torch.empty_like(xo)
+        lo = torch.empty(w.n, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        b.sbx_get_particles_device(xo.data_ptr(), vo.data_ptr(), lo.data_ptr())
+        assert np.array_equal(lo.cpu().numpy().astype(bool), la)
+        assert np.abs(xo.cpu().numpy() - xa).max() < 1e-6
+        assert np.abs(vo.cpu().numpy() - va).max() < 1e-5
+
+
+def test_device_entry_points_validate(sbx):
+    import torch
+    w = _nested(300, 14)
+    ctx = sbx.Context(prec=sbx.SBX_FP64)
+    ctx.sbx_build_grids([T.sbx_hier(h) for h in w.hier])
+    xd = torch.tensor(w.x, device="cuda")
+    vd = torch.tensor(w.v, device="cuda")
+    md = torch.tensor(w.m, device="cuda")
+    cd = torch.tensor(w.comp, device="cuda")
+    gd = torch.tensor(w.gal, device="cuda")
+    # host memory where device memory is required
+    with pytest.raises(sbx.SbxError) as e:
+        ctx.sbx_load_particles_device(w.n, w.x.ctypes.data, vd.data_ptr(), md.data_ptr(),
+                                      cd.data_ptr(), gd.data_ptr())
+    assert e.value.status == sbx.SBX_EINVAL
+    # a non-finite position, a negative mass, a galaxy id beyond the hierarchies
+    for which, k in (("x", 17), ("m", 41), ("gal", 99)):
+        x2, m2, g2 = xd.clone(), md.clone(), gd.clone()
+        if which == "x":
+            x2[k, 1] = float("nan")
+        elif which == "m":
+            m2[k] = -1.0
+        else:
+            g2[k] = 2
+        torch.cuda.synchronize()
+        with pytest.raises(sbx.SbxError) as e:
+            ctx.sbx_load_particles_device(w.n, x2.data_ptr(), vd.data_ptr(), m2.data_ptr(),
+                                          cd.data_ptr(), g2.data_ptr())
+        assert e.value.status == sbx.SBX_EINVAL and f"particle {k}" in str(e.value)
