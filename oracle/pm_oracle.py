@@ -669,3 +669,75 @@ def segment_loss_and_grads(sysm: System, x, v, m, comp, gal, dt, nsteps, sel_com
             gm[cr] += psis[3][tuple(idx[2][cr].T)]         # grid 4
             gm[outer] += psis[4][tuple(idx[2][outer].T)]   # grid 5
     return L, gm, lx, lv
+
+
+# --------------------------------------------------------------------------
+# Disc diagnostics of the paper's analysis (Sec. 5: heat, thickness,
+# vertical profile, velocity dispersions near the solar radius)
+# --------------------------------------------------------------------------
+def disc_analysis(x, v, m, comp, gal, lost, centre, n_bins, annulus, n_z, z_max,
+                  disc_comp=0, disc_gal=0):
+    """Diagnostics of the disc (live particles of component disc_comp of
+    galaxy disc_gal), with positions relative to `centre` and velocities
+    relative to the disc's mass-weighted mean velocity.
+
+    * Radial bins of equal particle numbers (Sec. 5.2 and 6.3): particles
+      ordered by cylindrical R (ties by particle index), bin k holding
+      n // n_bins particles plus one for k < n % n_bins.  Per bin: mean R,
+      mean circular velocity (mean v_phi) and RMS z (sqrt of mean z^2).
+    * Heat (Sec. 6.3): E = sum 1/2 m |v - vbar_c(R)|^2, with vbar_c the bin
+      values linearly interpolated in R between the bins' mean radii (held
+      constant beyond the first and last) and directed along phi.
+    * In the annulus R_lo <= R < R_hi: sigma_R, sigma_phi, sigma_z (about the
+      annulus means), sigma_tot^2, and the vertical density profile: mass in
+      n_z equal bins of z over [-z_max, z_max) divided by the annulus area
+      times the bin width (Sec. 5.2).
+    Unweighted means over particles (the disc particles have equal masses in
+    the paper's models).  parity unpinned beyond its closed-form pins.
+    """
+    sel = (comp == disc_comp) & (gal == disc_gal) & ~lost
+    idx = np.nonzero(sel)[0]
+    d = x[idx] - np.asarray(centre, dtype=np.float64)
+    ms = m[idx]
+    vb = np.sum(ms[:, None] * v[idx], axis=0) / np.sum(ms)
+    u = v[idx] - vb
+    dx, dy, z = d[:, 0], d[:, 1], d[:, 2]
+    R = np.sqrt(dx * dx + dy * dy)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        vR = np.where(R > 0, (dx * u[:, 0] + dy * u[:, 1]) / R, 0.0)
+        vphi = np.where(R > 0, (dx * u[:, 1] - dy * u[:, 0]) / R, 0.0)
+    vz = u[:, 2]
+    n = R.shape[0]
+    order = np.argsort(R, kind="stable")
+    base, extra = divmod(n, n_bins)
+    sizes = np.array([base + (1 if k < extra else 0) for k in range(n_bins)])
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    bin_r = np.zeros(n_bins); bin_vc = np.zeros(n_bins); bin_rms_z = np.zeros(n_bins)
+    for k in range(n_bins):
+        o = order[starts[k]:starts[k + 1]]
+        if o.size == 0:
+            continue
+        bin_r[k] = np.mean(R[o])
+        bin_vc[k] = np.mean(vphi[o])
+        bin_rms_z[k] = np.sqrt(np.mean(z[o] ** 2))
+    vc_at = np.interp(R, bin_r, bin_vc)
+    heat = 0.5 * np.sum(ms * ((vR * vR + (vphi - vc_at) ** 2) + vz * vz))
+    lo, hi = annulus
+    a = (R >= lo) & (R < hi)
+    na = int(a.sum())
+
+    def sd(q):
+        return float(np.sqrt(max(np.mean(q * q) - np.mean(q) ** 2, 0.0))) if na else 0.0
+    sR, sphi, sz = sd(vR[a]), sd(vphi[a]), sd(vz[a])
+    dz = 2.0 * z_max / n_z
+    area = np.pi * (hi * hi - lo * lo)
+    hz = np.zeros(n_z)
+    za = z[a]
+    inz = (za >= -z_max) & (za < z_max)
+    k = np.floor((za[inz] + z_max) / dz).astype(int)
+    k = np.minimum(k, n_z - 1)
+    np.add.at(hz, k, ms[a][inz])
+    rho_z = hz / (area * dz)
+    return {"n_disc": n, "bulk_v": vb, "bin_r": bin_r, "bin_vc": bin_vc, "bin_rms_z": bin_rms_z,
+            "bin_sizes": sizes, "e_heat": heat, "sig_R": sR, "sig_phi": sphi, "sig_z": sz,
+            "sig_tot2": sR * sR + sphi * sphi + sz * sz, "n_annulus": na, "rho_z": rho_z}
