@@ -251,6 +251,24 @@ def adjoint_rate(sbx, torch):
             "loss": loss, "grad_finite": bool(torch.isfinite(gm).all() and torch.isfinite(gx).all())}
 
 
+def disc_analysis_rate(sbx, torch, w):
+    """The paper's disc diagnostics on the benchmark galaxy (2M disc
+    particles): 100 equal-number radial bins, heat, dispersions and the
+    vertical profile near R = 3.2."""
+    ctx = make_ctx(sbx, w, sbx.SBX_FP32)
+    ctx.sbx_step(w.dt, 1)
+    ctx.sbx_disc_analysis(100, (3.0, 3.4), 40, 1.0)
+    ctx.sbx_sync()
+    t0 = time.perf_counter()
+    out = ctx.sbx_disc_analysis(100, (3.0, 3.4), 40, 1.0)
+    t1 = time.perf_counter()
+    ctx.close()
+    return {"ms": 1e3 * (t1 - t0), "n_disc": out["n_disc"], "e_heat": out["e_heat"],
+            "sig_z_over_sig_R": out["sig_z"] / out["sig_R"] if out["sig_R"] > 0 else None,
+            "includes": "selection, stable radix sort of the radii, bins, heat, annulus, "
+                        "allocations and host copies"}
+
+
 def cpu_baseline(w, frac):
     """The FP64 oracle, as it stands, on a bounded sample: one step of the
     same galaxy with a random `frac` of its particles (same grids)."""
@@ -356,6 +374,8 @@ def main():
         extra["ensemble"] = ensemble_rate(sbx, torch, args.extra_steps, 2)
         _log("differentiable segment")
         extra["adjoint"] = adjoint_rate(sbx, torch)
+        _log("disc diagnostics")
+        extra["disc_analysis"] = disc_analysis_rate(sbx, torch, w)
 
     # roofline of the dominant kernel of the FP32 step
     steps = args.steps

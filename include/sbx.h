@@ -210,6 +210,44 @@ sbx_status sbx_adjoint_segment_device(sbx_ctx* ctx, double dt, int32_t nsteps, i
                                       int32_t sel_comp, int32_t sel_gal, double* loss,
                                       double* grad_m, double* grad_x, double* grad_v);
 
+/* Disc diagnostics of the paper's analysis (Sec. 5.2, 6.3, 6.4).
+ * The disc is the live particles of component `comp` of galaxy `galaxy`;
+ * positions are taken relative to that galaxy's centre at the last solve
+ * (its given centre before any solve) and velocities (the stored staggered
+ * v) relative to the disc's mass-weighted mean velocity.
+ *   - Radial bins of equal particle numbers: particles ordered by cylindrical
+ *     R (ties in the caller's particle order), bin k holding n / n_bins
+ *     particles plus one for k < n % n_bins.  Per bin (unweighted means):
+ *     mean R, mean circular velocity (mean v_phi), RMS z.
+ *   - Heat: sum of 1/2 m |v - vbar_c(R) phi|^2 over the disc, vbar_c linearly
+ *     interpolated between the bins' mean radii, constant beyond the ends.
+ *   - In the annulus R_lo <= R < R_hi: sigma_R, sigma_phi, sigma_z about the
+ *     annulus means, sigma_tot^2, and the vertical density profile: mass in
+ *     n_z equal bins of z over [-z_max, z_max) over (annulus area x bin
+ *     width).
+ * Every sum is reduced in a fixed order except the profile bins.  Outputs on
+ * the host: bin_r, bin_vc, bin_rms_z (n_bins each) and rho_z (n_z), any may
+ * be NULL.  SBX_EINVAL for a bad query (1 <= n_bins <= 2048,
+ * 1 <= n_z <= 1024, z_max > 0, 0 <= R_lo < R_hi), SBX_ESTATE without disc
+ * particles. */
+typedef struct {
+  int32_t n_bins;
+  double annulus[2];
+  int32_t n_z;
+  double z_max;
+  int32_t comp, galaxy;
+} sbx_disc_query;
+
+typedef struct {
+  double e_heat;
+  double sig_R, sig_phi, sig_z, sig_tot2;
+  double bulk_v[3];
+  int64_t n_disc, n_annulus;
+} sbx_disc_result;
+
+sbx_status sbx_disc_analysis(sbx_ctx* ctx, const sbx_disc_query* q, sbx_disc_result* out,
+                             double* bin_r, double* bin_vc, double* bin_rms_z, double* rho_z);
+
 /* Reorder the particles in device memory by the cell of their finest grid
  * every `every` steps (at the start of the step; 0 = never; default 4).  A
  * performance setting only: every output is returned in the caller's

@@ -59,6 +59,17 @@ class sbx_diag(C.Structure):
                 "n_live": np.array(self.n_live[:])}
 
 
+class sbx_disc_query(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("annulus", C.c_double * 2), ("n_z", C.c_int32),
+                ("z_max", C.c_double), ("comp", C.c_int32), ("galaxy", C.c_int32)]
+
+
+class sbx_disc_result(C.Structure):
+    _fields_ = [("e_heat", C.c_double), ("sig_R", C.c_double), ("sig_phi", C.c_double),
+                ("sig_z", C.c_double), ("sig_tot2", C.c_double), ("bulk_v", C.c_double * 3),
+                ("n_disc", C.c_int64), ("n_annulus", C.c_int64)]
+
+
 def _load():
     # PyTorch wheels carry their own copy of the HIP runtime under the same
     # soname; loading torch first makes the library bind to that one copy, so
@@ -93,6 +104,7 @@ def _load():
         "sbx_adjoint_segment": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
         "sbx_adjoint_segment_device": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
         "sbx_load_particles_device": (S, [P, I64, P, P, P, P, P]),
+        "sbx_disc_analysis": (S, [P, P, P, P, P, P, P]),
         "sbx_get_particles_device": (S, [P, P, P, P]),
         "sbx_count_live": (S, [P, C.POINTER(I64)]),
         "sbx_profile_begin": (S, [P, I32]),
@@ -221,6 +233,18 @@ class Context:
                                                int(sel_comp), int(sel_gal), _ptr(loss), vp(grad_m),
                                                vp(grad_x), vp(grad_v)))
         return float(loss[0])
+
+    def sbx_disc_analysis(self, n_bins, annulus, n_z, z_max, comp=0, galaxy=0):
+        """Disc diagnostics (see sbx.h) as a dict."""
+        q = sbx_disc_query(int(n_bins), (C.c_double * 2)(*annulus), int(n_z), float(z_max), int(comp),
+                           int(galaxy))
+        r = sbx_disc_result()
+        br, bv, bz, rz = np.empty(n_bins), np.empty(n_bins), np.empty(n_bins), np.empty(n_z)
+        _check(_lib.sbx_disc_analysis(self._h, C.byref(q), C.byref(r), _ptr(br), _ptr(bv), _ptr(bz),
+                                      _ptr(rz)))
+        return {"e_heat": r.e_heat, "sig_R": r.sig_R, "sig_phi": r.sig_phi, "sig_z": r.sig_z,
+                "sig_tot2": r.sig_tot2, "bulk_v": np.array(r.bulk_v[:]), "n_disc": r.n_disc,
+                "n_annulus": r.n_annulus, "bin_r": br, "bin_vc": bv, "bin_rms_z": bz, "rho_z": rz}
 
     def sbx_build_grids(self, hierarchies):
         arr = hierarchy_array(hierarchies)
