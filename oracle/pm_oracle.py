@@ -741,3 +741,24 @@ def disc_analysis(x, v, m, comp, gal, lost, centre, n_bins, annulus, n_z, z_max,
     return {"n_disc": n, "bulk_v": vb, "bin_r": bin_r, "bin_vc": bin_vc, "bin_rms_z": bin_rms_z,
             "bin_sizes": sizes, "e_heat": heat, "sig_R": sR, "sig_phi": sphi, "sig_z": sz,
             "sig_tot2": sR * sR + sphi * sphi + sz * sz, "n_annulus": na, "rho_z": rho_z}
+
+
+def disc_modes(x, m, comp, gal, lost, centre, n_rbins, r_max, m_max, disc_comp=0, disc_gal=0):
+    """Fourier coefficients of the disc's surface density (Sec. 6.6): in
+    annular bins [k dR, (k+1) dR), A_m = (1/S_k) sum M exp(-i m phi) over the
+    bin's particles, phi the polar angle about `centre`, S_k the bin area.
+    Returns an (n_rbins, m_max + 1) complex array.  parity unpinned beyond
+    its closed-form pins."""
+    sel = (comp == disc_comp) & (gal == disc_gal) & ~lost
+    d = x[sel] - np.asarray(centre, dtype=np.float64)
+    ms = m[sel]
+    R = np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1])
+    ph = np.arctan2(d[:, 1], d[:, 0])
+    dR = r_max / n_rbins
+    out = np.zeros((n_rbins, m_max + 1), complex)
+    for k in range(n_rbins):
+        b = (R >= k * dR) & (R < (k + 1) * dR)
+        S = np.pi * dR * dR * ((k + 1) ** 2 - k ** 2)
+        for q in range(m_max + 1):
+            out[k, q] = np.sum(ms[b] * np.exp(-1j * q * ph[b])) / S
+    return out

@@ -96,3 +96,25 @@ def test_bulk_motion_is_not_heat():
     b = O.disc_analysis(x, v + np.array([0.3, -1.1, 0.2]), m, *args)
     assert b["e_heat"] == pytest.approx(a["e_heat"], rel=1e-10)
     assert b["sig_R"] == pytest.approx(a["sig_R"], rel=1e-10)
+
+
+def test_modes_of_uniform_ring_and_two_arm_pattern():
+    """A ring of equal masses at equally spaced angles has A_0 = mass / area
+    and no other modes below the ring's count; masses modulated by
+    1 + e cos(2 phi) add A_2 = e A_0 / 2 and nothing at m = 1."""
+    K = 360
+    ph = 2 * np.pi * (np.arange(K) + 0.25) / K
+    R = 2.5
+    x = np.stack([R * np.cos(ph), R * np.sin(ph), 0 * ph], axis=1)
+    m = np.full(K, 1.0 / K)
+    z = np.zeros(K, np.int8)
+    A = O.disc_modes(x, m, z, z, np.zeros(K, bool), (0, 0, 0), 5, 5.0, 4)
+    S = np.pi * (3 ** 2 - 2 ** 2)
+    assert A[2, 0].real == pytest.approx(1.0 / S, rel=1e-12)
+    assert np.abs(A[2, 1:]).max() < 1e-14
+    assert np.abs(A[[0, 1, 3, 4]]).max() == 0.0
+    e = 0.3
+    m2 = m * (1 + e * np.cos(2 * ph))
+    A2 = O.disc_modes(x, m2, z, z, np.zeros(K, bool), (0, 0, 0), 5, 5.0, 4)
+    assert abs(A2[2, 2]) == pytest.approx(0.5 * e / S, rel=1e-12)
+    assert abs(A2[2, 1]) < 1e-14 and abs(A2[2, 3]) < 1e-14
