@@ -289,98 +289,125 @@ PartDev<T> live_set(sbx_ctx* c) {
   return p;
 }
 
-template <typename T>
-sbx_status disc_t(sbx_ctx* c, const sbx_disc_query* qy, sbx_disc_result* res, double* bin_r,
-                  double* bin_vc, double* bin_rms_z, double* rho_z) {
-  const int64_t n = c->n;
-  hipStream_t s = c->stream;
+// Device buffers of a prepared disc: compact arrays in caller order and the
+// radial order.  Freed together.
+struct Disc {
   std::vector<void*> allocs;
-  auto alloc = [&](void** p, size_t bytes) -> sbx_status {
+  int64_t n = 0;
+  double *d3 = nullptr, *v3 = nullptr, *m1 = nullptr, *bulk = nullptr;
+  double *R = nullptr, *vR = nullptr, *vphi = nullptr, *vz = nullptr;
+  uint64_t* key = nullptr;    // sorted radius keys (FP64 bits)
+  uint32_t* order = nullptr;  // compact index of the sorted positions
+  sbx_status alloc(void** p, size_t bytes) {
     const sbx_status r = dev_alloc(p, bytes ? bytes : 8);
     if (r == SBX_OK) allocs.push_back(*p);
     return r;
-  };
+  }
+  ~Disc() {
+    for (void* q : allocs) (void)hipFree(q);
+  }
+};
+
+// Select the disc (caller order), centre it on the galaxy, take velocities
+// relative to its mean, compute cylindrical quantities, sort by radius.
+template <typename T>
+sbx_status disc_prepare(sbx_ctx* c, int comp, int galaxy, Disc& D) {
+  const int64_t n = c->n;
+  hipStream_t s = c->stream;
+  const PartDev<T> p = live_set<T>(c);
+  uint32_t *flag = nullptr, *tmp = nullptr;
+  SBX_TRY(D.alloc((void**)&flag, sizeof(uint32_t) * (n + 1)));
+  SBX_TRY(D.alloc((void**)&tmp, sizeof(uint32_t) * scan_tmp_elems(n + 1)));
+  SBX_TRY(launch_zero<uint32_t>(flag, n + 1, s));
+  hipLaunchKernelGGL((k_disc_flags<T>), dim3(1024), dim3(256), 0, s, p, comp, galaxy, flag);
+  SBX_TRY(exclusive_scan_u32(flag, n + 1, tmp, s));
+  uint32_t nd32 = 0;
+  SBX_HIP(hipMemcpyAsync(&nd32, flag + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  SBX_HIP(hipStreamSynchronize(s));
+  const int64_t nd = nd32;
+  D.n = nd;
+  if (nd == 0) {
+    set_error("no live particles of the requested disc component");
+    return SBX_ESTATE;
+  }
+  // centre of the galaxy's grids at the last solve (else its given centre)
+  double cen[3];
+  for (int k = 0; k < 3; ++k) cen[k] = c->hh[galaxy].centre[k];
+  if (c->solved) SBX_HIP(hipMemcpy(cen, c->centres + 3 * galaxy, sizeof(cen), hipMemcpyDeviceToHost));
+  double *dcen = nullptr, *part = nullptr;
+  SBX_TRY(D.alloc((void**)&dcen, sizeof(cen)));
+  SBX_HIP(hipMemcpyAsync(dcen, cen, sizeof(cen), hipMemcpyHostToDevice, s));
+  SBX_TRY(D.alloc((void**)&D.d3, sizeof(double) * 3 * nd));
+  SBX_TRY(D.alloc((void**)&D.v3, sizeof(double) * 3 * nd));
+  SBX_TRY(D.alloc((void**)&D.m1, sizeof(double) * nd));
+  hipLaunchKernelGGL((k_disc_compact<T>), dim3(1024), dim3(256), 0, s, p, comp, galaxy, flag, dcen, D.d3,
+                     D.v3, D.m1);
+  SBX_TRY(D.alloc((void**)&part, sizeof(double) * 1024 * 4));
+  SBX_TRY(D.alloc((void**)&D.bulk, sizeof(double) * 4));
+  hipLaunchKernelGGL(k_disc_bulk, dim3(1024), dim3(256), 0, s, D.v3, D.m1, nd, part);
+  hipLaunchKernelGGL(k_columns, dim3(4), dim3(256), 0, s, part, 1024, 4, D.bulk);
+  uint64_t* kb = nullptr;
+  uint32_t *vb = nullptr, *cnt = nullptr, *ctmp = nullptr;
+  SBX_TRY(D.alloc((void**)&D.R, sizeof(double) * nd));
+  SBX_TRY(D.alloc((void**)&D.vR, sizeof(double) * nd));
+  SBX_TRY(D.alloc((void**)&D.vphi, sizeof(double) * nd));
+  SBX_TRY(D.alloc((void**)&D.vz, sizeof(double) * nd));
+  SBX_TRY(D.alloc((void**)&D.key, sizeof(uint64_t) * nd));
+  SBX_TRY(D.alloc((void**)&kb, sizeof(uint64_t) * nd));
+  SBX_TRY(D.alloc((void**)&D.order, sizeof(uint32_t) * nd));
+  SBX_TRY(D.alloc((void**)&vb, sizeof(uint32_t) * nd));
+  hipLaunchKernelGGL(k_disc_cyl, dim3(1024), dim3(256), 0, s, D.d3, D.v3, D.bulk, nd, D.R, D.vR, D.vphi,
+                     D.vz, D.key, D.order);
+  const int nb = (int)((nd + kRsTile - 1) / kRsTile);
+  const size_t ncnt = (size_t)256 * nb;
+  SBX_TRY(D.alloc((void**)&cnt, sizeof(uint32_t) * ncnt));
+  SBX_TRY(D.alloc((void**)&ctmp, sizeof(uint32_t) * scan_tmp_elems(ncnt)));
+  uint64_t* ka = D.key;
+  uint32_t* va = D.order;
+  for (int shift = 0; shift < 64; shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(64), 0, s, ka, nd, shift, nb, cnt);
+    SBX_TRY(exclusive_scan_u32(cnt, ncnt, ctmp, s));
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(64), 0, s, ka, va, nd, shift, nb, cnt, kb, vb);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  D.key = ka;  // eight passes: the sorted data is back in the first buffers
+  D.order = va;
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status disc_t(sbx_ctx* c, const sbx_disc_query* qy, sbx_disc_result* res, double* bin_r,
+                  double* bin_vc, double* bin_rms_z, double* rho_z) {
+  hipStream_t s = c->stream;
+  Disc D;
   auto body = [&]() -> sbx_status {
-    const PartDev<T> p = live_set<T>(c);
-    uint32_t *flag = nullptr, *tmp = nullptr;
-    SBX_TRY(alloc((void**)&flag, sizeof(uint32_t) * (n + 1)));
-    SBX_TRY(alloc((void**)&tmp, sizeof(uint32_t) * scan_tmp_elems(n + 1)));
-    SBX_TRY(launch_zero<uint32_t>(flag, n + 1, s));
-    hipLaunchKernelGGL((k_disc_flags<T>), dim3(1024), dim3(256), 0, s, p, qy->comp, qy->galaxy, flag);
-    SBX_TRY(exclusive_scan_u32(flag, n + 1, tmp, s));
-    uint32_t nd32 = 0;
-    SBX_HIP(hipMemcpyAsync(&nd32, flag + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    SBX_HIP(hipStreamSynchronize(s));
-    const int64_t nd = nd32;
+    SBX_TRY(disc_prepare<T>(c, qy->comp, qy->galaxy, D));
+    const int64_t nd = D.n;
     res->n_disc = nd;
-    if (nd == 0) {
-      set_error("no live particles of the requested disc component");
-      return SBX_ESTATE;
-    }
-    // centre of the galaxy's grids at the last solve (else its given centre)
-    double cen[3];
-    const double* hc = c->hh[qy->galaxy].centre;
-    for (int k = 0; k < 3; ++k) cen[k] = hc[k];
-    if (c->solved) {
-      SBX_HIP(hipMemcpy(cen, c->centres + 3 * qy->galaxy, sizeof(cen), hipMemcpyDeviceToHost));
-    }
-    double *dcen = nullptr, *d3 = nullptr, *v3 = nullptr, *m1 = nullptr, *part = nullptr, *bulk = nullptr;
-    SBX_TRY(alloc((void**)&dcen, sizeof(cen)));
-    SBX_HIP(hipMemcpyAsync(dcen, cen, sizeof(cen), hipMemcpyHostToDevice, s));
-    SBX_TRY(alloc((void**)&d3, sizeof(double) * 3 * nd));
-    SBX_TRY(alloc((void**)&v3, sizeof(double) * 3 * nd));
-    SBX_TRY(alloc((void**)&m1, sizeof(double) * nd));
-    hipLaunchKernelGGL((k_disc_compact<T>), dim3(1024), dim3(256), 0, s, p, qy->comp, qy->galaxy, flag,
-                       dcen, d3, v3, m1);
-    SBX_TRY(alloc((void**)&part, sizeof(double) * 1024 * 4));
-    SBX_TRY(alloc((void**)&bulk, sizeof(double) * 4));
-    hipLaunchKernelGGL(k_disc_bulk, dim3(1024), dim3(256), 0, s, v3, m1, nd, part);
-    hipLaunchKernelGGL(k_columns, dim3(4), dim3(256), 0, s, part, 1024, 4, bulk);
-    double *R = nullptr, *vR = nullptr, *vphi = nullptr, *vz = nullptr;
-    uint64_t *ka = nullptr, *kb = nullptr;
-    uint32_t *va = nullptr, *vb = nullptr, *cnt = nullptr, *ctmp = nullptr;
-    SBX_TRY(alloc((void**)&R, sizeof(double) * nd));
-    SBX_TRY(alloc((void**)&vR, sizeof(double) * nd));
-    SBX_TRY(alloc((void**)&vphi, sizeof(double) * nd));
-    SBX_TRY(alloc((void**)&vz, sizeof(double) * nd));
-    SBX_TRY(alloc((void**)&ka, sizeof(uint64_t) * nd));
-    SBX_TRY(alloc((void**)&kb, sizeof(uint64_t) * nd));
-    SBX_TRY(alloc((void**)&va, sizeof(uint32_t) * nd));
-    SBX_TRY(alloc((void**)&vb, sizeof(uint32_t) * nd));
-    hipLaunchKernelGGL(k_disc_cyl, dim3(1024), dim3(256), 0, s, d3, v3, bulk, nd, R, vR, vphi, vz, ka, va);
-    const int nb = (int)((nd + kRsTile - 1) / kRsTile);
-    const size_t ncnt = (size_t)256 * nb;
-    SBX_TRY(alloc((void**)&cnt, sizeof(uint32_t) * ncnt));
-    SBX_TRY(alloc((void**)&ctmp, sizeof(uint32_t) * scan_tmp_elems(ncnt)));
-    for (int shift = 0; shift < 64; shift += 8) {
-      hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(64), 0, s, ka, nd, shift, nb, cnt);
-      SBX_TRY(exclusive_scan_u32(cnt, ncnt, ctmp, s));
-      hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(64), 0, s, ka, va, nd, shift, nb, cnt, kb, vb);
-      std::swap(ka, kb);
-      std::swap(va, vb);
-    }
-    SBX_HIP(hipGetLastError());
     const int nbins = qy->n_bins;
     double *br = nullptr, *bv = nullptr, *bz = nullptr, *apart = nullptr, *zpart = nullptr,
            *asum = nullptr, *zsum = nullptr;
-    SBX_TRY(alloc((void**)&br, sizeof(double) * nbins));
-    SBX_TRY(alloc((void**)&bv, sizeof(double) * nbins));
-    SBX_TRY(alloc((void**)&bz, sizeof(double) * nbins));
-    hipLaunchKernelGGL(k_disc_bins, dim3(nbins), dim3(256), 0, s, va, nd, nbins, R, vphi, d3, br, bv, bz);
-    SBX_TRY(alloc((void**)&apart, sizeof(double) * kAnBlocks * kAnVals));
-    SBX_TRY(alloc((void**)&zpart, sizeof(double) * kAnBlocks * qy->n_z));
-    SBX_TRY(alloc((void**)&asum, sizeof(double) * kAnVals));
-    SBX_TRY(alloc((void**)&zsum, sizeof(double) * qy->n_z));
+    SBX_TRY(D.alloc((void**)&br, sizeof(double) * nbins));
+    SBX_TRY(D.alloc((void**)&bv, sizeof(double) * nbins));
+    SBX_TRY(D.alloc((void**)&bz, sizeof(double) * nbins));
+    hipLaunchKernelGGL(k_disc_bins, dim3(nbins), dim3(256), 0, s, D.order, nd, nbins, D.R, D.vphi, D.d3, br,
+                       bv, bz);
+    SBX_TRY(D.alloc((void**)&apart, sizeof(double) * kAnBlocks * kAnVals));
+    SBX_TRY(D.alloc((void**)&zpart, sizeof(double) * kAnBlocks * qy->n_z));
+    SBX_TRY(D.alloc((void**)&asum, sizeof(double) * kAnVals));
+    SBX_TRY(D.alloc((void**)&zsum, sizeof(double) * qy->n_z));
     const size_t shb = sizeof(double) * (2 * (size_t)nbins + qy->n_z);
-    hipLaunchKernelGGL(k_disc_heat, dim3(kAnBlocks), dim3(256), shb, s, nd, nbins, br, bv, R, vR, vphi, vz,
-                       d3, m1, qy->annulus[0], qy->annulus[1], qy->n_z, qy->z_max, apart, zpart);
+    hipLaunchKernelGGL(k_disc_heat, dim3(kAnBlocks), dim3(256), shb, s, nd, nbins, br, bv, D.R, D.vR, D.vphi,
+                       D.vz, D.d3, D.m1, qy->annulus[0], qy->annulus[1], qy->n_z, qy->z_max, apart, zpart);
     hipLaunchKernelGGL(k_columns, dim3(kAnVals), dim3(256), 0, s, apart, kAnBlocks, kAnVals, asum);
     hipLaunchKernelGGL(k_columns, dim3(qy->n_z), dim3(256), 0, s, zpart, kAnBlocks, qy->n_z, zsum);
     SBX_HIP(hipGetLastError());
     double a[kAnVals], b4[4];
     std::vector<double> z(qy->n_z);
     SBX_HIP(hipMemcpyAsync(a, asum, sizeof(a), hipMemcpyDeviceToHost, s));
-    SBX_HIP(hipMemcpyAsync(b4, bulk, sizeof(b4), hipMemcpyDeviceToHost, s));
+    SBX_HIP(hipMemcpyAsync(b4, D.bulk, sizeof(b4), hipMemcpyDeviceToHost, s));
     SBX_HIP(hipMemcpyAsync(z.data(), zsum, sizeof(double) * qy->n_z, hipMemcpyDeviceToHost, s));
     if (bin_r) SBX_HIP(hipMemcpyAsync(bin_r, br, sizeof(double) * nbins, hipMemcpyDeviceToHost, s));
     if (bin_vc) SBX_HIP(hipMemcpyAsync(bin_vc, bv, sizeof(double) * nbins, hipMemcpyDeviceToHost, s));
@@ -406,7 +433,71 @@ sbx_status disc_t(sbx_ctx* c, const sbx_disc_query* qy, sbx_disc_result* res, do
   };
   const sbx_status rc = body();
   (void)hipStreamSynchronize(s);
-  for (void* q : allocs) (void)hipFree(q);
+  return rc;
+}
+
+// ------------------------------------------------------------ disc modes --
+// first sorted position with R >= r (sorted radius keys)
+__device__ __forceinline__ int64_t lower_bound_r(const uint64_t* key, int64_t n, double r) {
+  const uint64_t kr = (uint64_t)__double_as_longlong(r);
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (key[mid] < kr) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One block per annular bin [k dR, (k+1) dR): sum over its particles of
+// M cos(m phi) and -M sin(m phi), m = 0..mmax, in a fixed order; divided by
+// the bin area.  out[(k * (mmax + 1) + m) * 2 + {0, 1}] = re, im.
+__global__ void __launch_bounds__(256)
+    k_disc_modes(const uint64_t* __restrict__ key, const uint32_t* __restrict__ order, int64_t n,
+                 const double* __restrict__ d3, const double* __restrict__ m1, double dR, int mmax,
+                 double* __restrict__ out) {
+  constexpr int kMaxM = 16;
+  const int k = blockIdx.x;
+  const int64_t s0 = lower_bound_r(key, n, k * dR), s1 = lower_bound_r(key, n, (k + 1) * dR);
+  double a[2 * (kMaxM + 1)] = {};
+  for (int64_t j = s0 + threadIdx.x; j < s1; j += 256) {
+    const uint32_t i = order[j];
+    const double ph = atan2(d3[3 * (size_t)i + 1], d3[3 * (size_t)i]);
+    const double m = m1[i];
+#pragma unroll
+    for (int q = 0; q <= kMaxM; ++q) {
+      if (q > mmax) break;
+      double sn, cs;
+      sincos((double)q * ph, &sn, &cs);
+      a[2 * q] += m * cs;
+      a[2 * q + 1] -= m * sn;
+    }
+  }
+  __shared__ double res[2 * (kMaxM + 1)];
+  block_rows<2 * (kMaxM + 1)>(a, res);
+  __syncthreads();
+  const double S = M_PI * dR * dR * ((double)(k + 1) * (k + 1) - (double)k * k);
+  for (int q = threadIdx.x; q < 2 * (mmax + 1); q += 256) out[(size_t)k * 2 * (mmax + 1) + q] = res[q] / S;
+}
+
+template <typename T>
+sbx_status modes_t(sbx_ctx* c, int comp, int galaxy, int nr, double rmax, int mmax, double* coeff) {
+  hipStream_t s = c->stream;
+  Disc D;
+  auto body = [&]() -> sbx_status {
+    SBX_TRY(disc_prepare<T>(c, comp, galaxy, D));
+    double* out = nullptr;
+    const size_t cnt = (size_t)nr * (mmax + 1) * 2;
+    SBX_TRY(D.alloc((void**)&out, sizeof(double) * cnt));
+    hipLaunchKernelGGL(k_disc_modes, dim3(nr), dim3(256), 0, s, D.key, D.order, D.n, D.d3, D.m1, rmax / nr,
+                       mmax, out);
+    SBX_HIP(hipGetLastError());
+    SBX_HIP(hipMemcpyAsync(coeff, out, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+    SBX_HIP(hipStreamSynchronize(s));
+    return SBX_OK;
+  };
+  const sbx_status rc = body();
+  (void)hipStreamSynchronize(s);
   return rc;
 }
 
@@ -439,6 +530,30 @@ sbx_status sbx_disc_analysis(sbx_ctx* c, const sbx_disc_query* q, sbx_disc_resul
   std::memset(res, 0, sizeof(*res));
   return c->cfg.prec == SBX_FP64 ? disc_t<double>(c, q, res, bin_r, bin_vc, bin_rms_z, rho_z)
                                  : disc_t<float>(c, q, res, bin_r, bin_vc, bin_rms_z, rho_z);
+}
+
+sbx_status sbx_disc_modes(sbx_ctx* c, int32_t comp, int32_t galaxy, int32_t n_rbins, double r_max,
+                          int32_t m_max, double* coeff) {
+  if (!c || !coeff) {
+    set_error("null argument");
+    return SBX_EINVAL;
+  }
+  if (c->batch && c->batch->pending) {
+    set_error("the context's batch has queued work: call sbx_batch_sync first");
+    return SBX_ESTATE;
+  }
+  if (!c->built || c->n == 0) {
+    set_error("build_grids and load_particles first");
+    return SBX_ESTATE;
+  }
+  if (n_rbins < 1 || n_rbins > 65536 || !(r_max > 0.0) || m_max < 0 || m_max > 16 || comp < 0 ||
+      comp >= kNComp || galaxy < 0 || galaxy >= c->ngal) {
+    set_error("bad mode query (1 <= n_rbins <= 65536, r_max > 0, 0 <= m_max <= 16)");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  return c->cfg.prec == SBX_FP64 ? modes_t<double>(c, comp, galaxy, n_rbins, r_max, m_max, coeff)
+                                 : modes_t<float>(c, comp, galaxy, n_rbins, r_max, m_max, coeff);
 }
 
 }  // extern "C"

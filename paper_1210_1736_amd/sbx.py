@@ -105,6 +105,7 @@ def _load():
         "sbx_adjoint_segment_device": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
         "sbx_load_particles_device": (S, [P, I64, P, P, P, P, P]),
         "sbx_disc_analysis": (S, [P, P, P, P, P, P, P]),
+        "sbx_disc_modes": (S, [P, I32, I32, I32, D, I32, P]),
         "sbx_get_particles_device": (S, [P, P, P, P]),
         "sbx_count_live": (S, [P, C.POINTER(I64)]),
         "sbx_profile_begin": (S, [P, I32]),
@@ -245,6 +246,13 @@ class Context:
         return {"e_heat": r.e_heat, "sig_R": r.sig_R, "sig_phi": r.sig_phi, "sig_z": r.sig_z,
                 "sig_tot2": r.sig_tot2, "bulk_v": np.array(r.bulk_v[:]), "n_disc": r.n_disc,
                 "n_annulus": r.n_annulus, "bin_r": br, "bin_vc": bv, "bin_rms_z": bz, "rho_z": rz}
+
+    def sbx_disc_modes(self, n_rbins, r_max, m_max, comp=0, galaxy=0):
+        """(n_rbins, m_max + 1) complex Fourier coefficients (see sbx.h)."""
+        out = np.empty(n_rbins * (m_max + 1) * 2)
+        _check(_lib.sbx_disc_modes(self._h, int(comp), int(galaxy), int(n_rbins), float(r_max),
+                                   int(m_max), _ptr(out)))
+        return out.view(np.complex128).reshape(n_rbins, m_max + 1)
 
     def sbx_build_grids(self, hierarchies):
         arr = hierarchy_array(hierarchies)

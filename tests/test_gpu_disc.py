@@ -77,3 +77,16 @@ def test_disc_analysis_errors(sbx):
     with pytest.raises(sbx.SbxError) as e:
         ctx.sbx_disc_analysis(4, (1, 2), 4, 1.0, comp=7)
     assert e.value.status == sbx.SBX_ESTATE
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_disc_modes_match_oracle(sbx, prec):
+    w = _galaxy(0.02)
+    ctx = T.make_ctx(w, prec)
+    ctx.sbx_step(w.dt, 2)
+    xg, _, lg = ctx.sbx_get_particles()
+    got = ctx.sbx_disc_modes(30, 6.0, 4)
+    ref = O.disc_modes(xg, w.m if prec == 1 else T.rounded(w.m, prec), w.comp, w.gal, lg,
+                       w.hier[0].centre, 30, 6.0, 4)
+    scale = np.abs(ref[:, 0]).max()
+    assert np.abs(got - ref).max() <= 1e-10 * scale
