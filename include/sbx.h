@@ -248,6 +248,17 @@ typedef struct {
 sbx_status sbx_disc_analysis(sbx_ctx* ctx, const sbx_disc_query* q, sbx_disc_result* out,
                              double* bin_r, double* bin_vc, double* bin_rms_z, double* rho_z);
 
+/* Fourier coefficients of the disc's surface density in annular bins
+ * (Sec. 6.6): for bin k = [k dR, (k+1) dR), dR = r_max / n_rbins, and
+ * m = 0..m_max, A_m = (1/S_k) sum over the bin's particles of M exp(-i m phi)
+ * with phi the polar angle about the galaxy centre and S_k the bin area.
+ * Same disc selection and centre as sbx_disc_analysis.  coeff (host):
+ * n_rbins * (m_max + 1) * 2 doubles, (re, im) at (k * (m_max + 1) + m) * 2.
+ * Sums in a fixed order.  SBX_EINVAL unless 1 <= n_rbins <= 65536,
+ * r_max > 0, 0 <= m_max <= 16. */
+sbx_status sbx_disc_modes(sbx_ctx* ctx, int32_t comp, int32_t galaxy, int32_t n_rbins, double r_max,
+                          int32_t m_max, double* coeff);
+
 /* Reorder the particles in device memory by the cell of their finest grid
  * every `every` steps (at the start of the step; 0 = never; default 4).  A
  * performance setting only: every output is returned in the caller's
