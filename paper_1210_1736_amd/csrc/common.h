@@ -172,12 +172,62 @@ __device__ __forceinline__ void dft16(C2<T>* v) {
   }
 }
 
+// cos and sin of 2 pi m / 32, m = 0..15
+__device__ constexpr double kCos32[16] = {
+    1.0, 0.98078528040323043, 0.92387953251128674, 0.83146961230254524,
+    0.70710678118654752, 0.55557023301960218, 0.38268343236508977, 0.19509032201612826,
+    0.0, -0.19509032201612826, -0.38268343236508977, -0.55557023301960218,
+    -0.70710678118654752, -0.83146961230254524, -0.92387953251128674, -0.98078528040323043};
+__device__ constexpr double kSin32[16] = {
+    0.0, 0.19509032201612826, 0.38268343236508977, 0.55557023301960218,
+    0.70710678118654752, 0.83146961230254524, 0.92387953251128674, 0.98078528040323043,
+    1.0, 0.98078528040323043, 0.92387953251128674, 0.83146961230254524,
+    0.70710678118654752, 0.55557023301960218, 0.38268343236508977, 0.19509032201612826};
+
+// a * exp(-+ 2 pi i m / 32), m = 0..15 a compile-time constant
+template <int M, bool INV, typename T>
+__device__ __forceinline__ C2<T> tw32(C2<T> a) {
+  if constexpr ((M & 1) == 0) {
+    return tw16<M / 2, INV>(a);
+  } else {
+    const T c = (T)kCos32[M];
+    const T s = INV ? (T)kSin32[M] : -(T)kSin32[M];
+    return C2<T>{a.re * c - a.im * s, a.re * s + a.im * c};
+  }
+}
+
+template <int M, bool INV, typename T>
+__device__ __forceinline__ void tw32_all(C2<T>* b) {
+  b[M] = tw32<M, INV>(b[M]);
+  if constexpr (M + 1 < 16) tw32_all<M + 1, INV>(b);
+}
+
+// 32 = 16 x 2: n = 2 n1 + n2, k = k1 + 16 k2
+template <bool INV, typename T>
+__device__ __forceinline__ void dft32(C2<T>* v) {
+  C2<T> a[16], b[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    a[n1] = v[2 * n1];
+    b[n1] = v[2 * n1 + 1];
+  }
+  dft16<INV>(a);
+  dft16<INV>(b);
+  tw32_all<1, INV>(b);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) {
+    v[k1] = a[k1] + b[k1];
+    v[k1 + 16] = a[k1] - b[k1];
+  }
+}
+
 template <int R, bool INV, typename T>
 __device__ __forceinline__ void dftR(C2<T>* v) {
   if constexpr (R == 2) dft2<INV>(v);
   else if constexpr (R == 4) dft4<INV>(v);
   else if constexpr (R == 8) dft8<INV>(v);
-  else dft16<INV>(v);
+  else if constexpr (R == 16) dft16<INV>(v);
+  else dft32<INV>(v);
 }
 
 }  // namespace sbx

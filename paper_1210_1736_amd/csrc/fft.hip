@@ -2,9 +2,9 @@
 // function (Eqs. 3-5 of the method) and the FP64 Green's-table build.
 //
 // Each block holds W lines of length L = 2N in LDS and runs a Stockham
-// autosort FFT on them: a radix-16 pass (one 16-point DFT in registers per
-// thread), then the remaining radix (2, 4, 8 or 16) with twiddles from a
-// table.  Global loads and stores are arranged so that consecutive threads
+// autosort FFT on them: a first pass of radix 16 (radix 32 for L = 512) with
+// one DFT in registers per thread, then the remaining radix (2, 4, 8 or 16)
+// with twiddles from a table.  Global loads and stores are arranged so that consecutive threads
 // touch consecutive addresses: along the line when the line is contiguous,
 // across the W lines of a tile when it is strided.
 #include <algorithm>
@@ -20,12 +20,13 @@ namespace sbx {
 __device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
 
 // ------------------------------------------------------------- Stockham ---
-// A line of length L is transformed by TL = L/16 threads of one wavefront
-// (64/TL lines per wave), so the exchanges between radix passes go through
-// LDS with wave-level ordering only.  Passes: radix 16 (stride 1), then
-// radix L/16 (L <= 256) or 16 (L = 512) with stride 16, then for L = 512 a
-// radix-2 pass with stride 256.  Every thread holds 16 values per pass
-// (16/R butterflies of radix R).
+// A line of length L is transformed by TL = L/VPT threads of one wavefront
+// (64/TL lines per wave), each holding VPT values (16, or 32 for L = 512 in
+// FP32), so the exchanges between the passes go through LDS with wave-level
+// ordering only.  Passes: radix VPT (stride 1), then radix L/VPT with stride
+// VPT (VPT/R butterflies of radix R per thread); in FP64 at L = 512 the
+// second pass is radix 16 and a radix-2 pass with stride 256 follows (32
+// complex doubles per thread would not leave room for the rest).
 //
 // Forward pass p (decimation in time, Stockham autosort): butterfly j reads
 // positions j + r*L/R, multiplies by twiddles, takes the R-point DFT and
@@ -35,16 +36,17 @@ __device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
 // scatter to the input positions).  The last forward pass reads and writes
 // the same positions, which is what lets the z pass apply the Green's
 // function and the first inverse pass in registers.
-template <int L>
+template <typename T, int L>
 struct Line {
-  static constexpr int TL = L / 16;
-  static constexpr int NP = L == 16 ? 1 : (L <= 256 ? 2 : 3);
+  static constexpr int VPT = (L == 512 && sizeof(T) == 4) ? 32 : 16;
+  static constexpr int TL = L / VPT;
+  static constexpr int NP = L == 16 ? 1 : (L / VPT <= 16 ? 2 : 3);
   template <int p>
-  static constexpr int R = p == 0 ? 16 : (p == 1 ? (L <= 256 ? L / 16 : 16) : 2);
+  static constexpr int R = p == 0 ? VPT : (p == 1 ? (L / VPT <= 16 ? L / VPT : 16) : 2);
   template <int p>
-  static constexpr int NS = p == 0 ? 1 : (p == 1 ? 16 : 256);
+  static constexpr int NS = p == 0 ? 1 : (p == 1 ? VPT : 16 * VPT);
   template <int p>
-  static constexpr int TW = p == 2 ? 240 : 0;  // offset of the pass in the twiddle table
+  static constexpr int TW = p == 2 ? 15 * VPT : 0;  // offset of the pass in the twiddle table
 };
 
 // Order the LDS accesses of one wavefront (they execute in issue order).
@@ -54,21 +56,21 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int L, int p>
+template <typename T, int L, int p>
 __device__ __forceinline__ int pos_in(int j, int r) {
-  return j + r * (L / Line<L>::template R<p>);
+  return j + r * (L / Line<T, L>::template R<p>);
 }
-template <int L, int p>
+template <typename T, int L, int p>
 __device__ __forceinline__ int pos_out(int j, int r) {
-  constexpr int NS = Line<L>::template NS<p>, R = Line<L>::template R<p>;
+  constexpr int NS = Line<T, L>::template NS<p>, R = Line<T, L>::template R<p>;
   const int k = j & (NS - 1);
   return (j - k) * R + k + r * NS;
 }
 
 template <typename T, int L, int p>
 __device__ __forceinline__ void fwd_bfly(C2<T>* v, int t, const C2<T>* __restrict__ tw) {
-  using F = Line<L>;
-  constexpr int R = F::template R<p>, NS = F::template NS<p>, BPT = 16 / R;
+  using F = Line<T, L>;
+  constexpr int R = F::template R<p>, NS = F::template NS<p>, BPT = F::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     if constexpr (NS > 1) {
@@ -83,8 +85,8 @@ __device__ __forceinline__ void fwd_bfly(C2<T>* v, int t, const C2<T>* __restric
 
 template <typename T, int L, int p>
 __device__ __forceinline__ void inv_bfly(C2<T>* v, int t, const C2<T>* __restrict__ tw) {
-  using F = Line<L>;
-  constexpr int R = F::template R<p>, NS = F::template NS<p>, BPT = 16 / R;
+  using F = Line<T, L>;
+  constexpr int R = F::template R<p>, NS = F::template NS<p>, BPT = F::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     dftR<R, true>(v + b * R);
@@ -101,39 +103,39 @@ __device__ __forceinline__ void inv_bfly(C2<T>* v, int t, const C2<T>* __restric
 // ZHI: the upper half of the line's input is zero (padded input).
 template <typename T, int L, int p, bool ZHI>
 __device__ __forceinline__ void gather_in(const C2<T>* s, int t, C2<T>* v) {
-  constexpr int R = Line<L>::template R<p>, BPT = 16 / R;
+  constexpr int R = Line<T, L>::template R<p>, BPT = Line<T, L>::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b)
 #pragma unroll
     for (int r = 0; r < R; ++r)
       v[b * R + r] = (ZHI && r >= R / 2) ? C2<T>{(T)0, (T)0}
-                                         : s[pad(pos_in<L, p>(t + b * Line<L>::TL, r))];
+                                         : s[pad(pos_in<T, L, p>(t + b * Line<T, L>::TL, r))];
 }
 // HALF: only positions below L/2 are kept (cropped output).
 template <typename T, int L, int p, bool HALF>
 __device__ __forceinline__ void scatter_in(C2<T>* s, int t, const C2<T>* v) {
-  constexpr int R = Line<L>::template R<p>, BPT = 16 / R;
+  constexpr int R = Line<T, L>::template R<p>, BPT = Line<T, L>::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b)
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (!HALF || r < R / 2) s[pad(pos_in<L, p>(t + b * Line<L>::TL, r))] = v[b * R + r];
+      if (!HALF || r < R / 2) s[pad(pos_in<T, L, p>(t + b * Line<T, L>::TL, r))] = v[b * R + r];
 }
 template <typename T, int L, int p>
 __device__ __forceinline__ void gather_out(const C2<T>* s, int t, C2<T>* v) {
-  constexpr int R = Line<L>::template R<p>, BPT = 16 / R;
+  constexpr int R = Line<T, L>::template R<p>, BPT = Line<T, L>::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b)
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[b * R + r] = s[pad(pos_out<L, p>(t + b * Line<L>::TL, r))];
+    for (int r = 0; r < R; ++r) v[b * R + r] = s[pad(pos_out<T, L, p>(t + b * Line<T, L>::TL, r))];
 }
 template <typename T, int L, int p>
 __device__ __forceinline__ void scatter_out(C2<T>* s, int t, const C2<T>* v) {
-  constexpr int R = Line<L>::template R<p>, BPT = 16 / R;
+  constexpr int R = Line<T, L>::template R<p>, BPT = Line<T, L>::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b)
 #pragma unroll
-    for (int r = 0; r < R; ++r) s[pad(pos_out<L, p>(t + b * Line<L>::TL, r))] = v[b * R + r];
+    for (int r = 0; r < R; ++r) s[pad(pos_out<T, L, p>(t + b * Line<T, L>::TL, r))] = v[b * R + r];
 }
 
 // Forward passes PS..NP-1 on an LDS line, in place; v holds the inputs of
@@ -141,7 +143,7 @@ __device__ __forceinline__ void scatter_out(C2<T>* s, int t, const C2<T>* v) {
 // order, positions j + r L/R) on exit, also written to LDS when STORE.
 template <typename T, int L, int PS, bool STORE>
 __device__ __forceinline__ void fwd_from(C2<T>* s, int t, C2<T>* v, const C2<T>* __restrict__ tw) {
-  constexpr int NP = Line<L>::NP;
+  constexpr int NP = Line<T, L>::NP;
   fwd_bfly<T, L, PS>(v, t, tw);
   if constexpr (PS + 1 < NP) {
     scatter_out<T, L, PS>(s, t, v);
@@ -172,24 +174,11 @@ __device__ __forceinline__ void inv_down(C2<T>* s, int t, C2<T>* v, const C2<T>*
 // Full forward transform of a line held in LDS in natural order (in place).
 template <typename T, int L>
 __device__ __forceinline__ void line_fwd_lds(C2<T>* s, int t, const C2<T>* __restrict__ tw) {
-  C2<T> v[16];
+  C2<T> v[Line<T, L>::VPT];
   gather_in<T, L, 0, false>(s, t, v);
   wave_sync();
   fwd_from<T, L, 0, true>(s, t, v, tw);
   wave_sync();
-}
-
-// Twiddle table for length L: for every pass after the first, entries
-// (r-1)*NS + k = exp(-2 pi i k r / (NS R)), r = 1..R-1, k = 0..NS-1.
-static int tw_len(int L) {
-  switch (L) {
-    case 16: return 1;
-    case 32: return 16;
-    case 64: return 48;
-    case 128: return 112;
-    case 256: return 240;
-    default: return 496;
-  }
 }
 
 template <typename T>
@@ -200,6 +189,34 @@ __global__ void k_twiddle(C2<T>* tw, int R, int NS) {
   double s, c;
   sincospi(2.0 * (double)(k * r) / (double)(NS * R), &s, &c);
   tw[i] = C2<T>{(T)c, (T)(-s)};
+}
+
+// Twiddle table for length L: for every pass after the first, at the
+// pass's offset, entries (r-1)*NS + k = exp(-2 pi i k r / (NS R)),
+// r = 1..R-1, k = 0..NS-1.
+template <typename T, int L, int p>
+static int tw_fill(C2<T>* tw, hipStream_t st) {
+  using F = Line<T, L>;
+  if constexpr (p >= F::NP) {
+    return F::template TW<p - 1> + (F::template R<p - 1> - 1) * F::template NS<p - 1>;
+  } else {
+    constexpr int R = F::template R<p>, NS = F::template NS<p>, n = (R - 1) * NS;
+    if (tw) hipLaunchKernelGGL(k_twiddle<T>, dim3((n + 255) / 256), dim3(256), 0, st,
+                               tw + F::template TW<p>, R, NS);
+    return tw_fill<T, L, p + 1>(tw, st);
+  }
+}
+
+template <typename T>
+static int tw_make(int L, C2<T>* tw, hipStream_t st) {
+  switch (L) {
+    case 16: return 1;
+    case 32: return tw_fill<T, 32, 1>(tw, st);
+    case 64: return tw_fill<T, 64, 1>(tw, st);
+    case 128: return tw_fill<T, 128, 1>(tw, st);
+    case 256: return tw_fill<T, 256, 1>(tw, st);
+    default: return tw_fill<T, 512, 1>(tw, st);
+  }
 }
 
 template <typename T>
@@ -213,23 +230,8 @@ const C2<T>* twiddles(int L, hipStream_t st) {
   std::lock_guard<std::mutex> g(mu);
   if (cache[dev][lg]) return cache[dev][lg];
   C2<T>* p = nullptr;
-  if (hipMalloc(&p, sizeof(C2<T>) * tw_len(L)) != hipSuccess) return nullptr;
-  struct PassRN { int R, NS, off; };
-  PassRN ps[2] = {{0, 0, 0}, {0, 0, 0}};
-  int np = 0;
-  switch (L) {
-    case 32: ps[0] = {2, 16, 0}; np = 1; break;
-    case 64: ps[0] = {4, 16, 0}; np = 1; break;
-    case 128: ps[0] = {8, 16, 0}; np = 1; break;
-    case 256: ps[0] = {16, 16, 0}; np = 1; break;
-    case 512: ps[0] = {16, 16, 0}; ps[1] = {2, 256, 240}; np = 2; break;
-    default: break;
-  }
-  for (int i = 0; i < np; ++i) {
-    const int n = (ps[i].R - 1) * ps[i].NS;
-    hipLaunchKernelGGL(k_twiddle<T>, dim3((n + 255) / 256), dim3(256), 0, st, p + ps[i].off,
-                       ps[i].R, ps[i].NS);
-  }
+  if (hipMalloc(&p, sizeof(C2<T>) * tw_make<T>(L, nullptr, st)) != hipSuccess) return nullptr;
+  tw_make<T>(L, p, st);
   if (hipStreamSynchronize(st) != hipSuccess) {
     (void)hipFree(p);
     return nullptr;
@@ -252,7 +254,7 @@ constexpr int kLdsCap = 81920;  // two blocks per compute unit
 template <typename T, int L, int NT, int PASS>
 struct TC {
   static constexpr int N = L / 2;
-  static constexpr int TL = L / 16;
+  static constexpr int TL = Line<T, L>::TL;
   static constexpr int P = L + L / 16 + 1;  // LDS pitch of one line
   static constexpr int LB = P * (int)sizeof(C2<T>);
   static constexpr int WT = NT / TL;
@@ -311,10 +313,11 @@ __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T
     if (j < WL) {
       const T* __restrict__ a = d.rho + ((size_t)z * N + y0 + 2 * j) * N;
       const T* __restrict__ b = a + N;
-      C2<T> v[16];
+      constexpr int VPT = Line<T, L>::VPT;
+      C2<T> v[VPT];
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        v[r] = r < 8 ? C2<T>{a[t + r * TL], b[t + r * TL]} : C2<T>{(T)0, (T)0};
+      for (int r = 0; r < VPT; ++r)
+        v[r] = r < VPT / 2 ? C2<T>{a[t + r * TL], b[t + r * TL]} : C2<T>{(T)0, (T)0};
       fwd_from<T, L, 0, true>(s + j * P, t, v, tw);
     }
   }
@@ -344,9 +347,10 @@ __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T
     const int w = u * K::WT + tid / TL;
     if (w < W) {
       const C2<T>* __restrict__ src = d.X + ((size_t)kx * N + z0 + w) * N;
-      C2<T> v[16];
+      constexpr int VPT = Line<T, L>::VPT;
+      C2<T> v[VPT];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = r < 8 ? src[t + r * TL] : C2<T>{(T)0, (T)0};
+      for (int r = 0; r < VPT; ++r) v[r] = r < VPT / 2 ? src[t + r * TL] : C2<T>{(T)0, (T)0};
       fwd_from<T, L, 0, true>(s + w * P, t, v, tw);
     }
   }
@@ -365,7 +369,7 @@ template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
   using K = TC<T, L, NT, 2>;
-  using F = Line<L>;
+  using F = Line<T, L>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
   constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
   const int tid = threadIdx.x, t = tid % TL, w = tid / TL;
@@ -374,9 +378,9 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
     const int ky = ky0 + w;
     const C2<T>* __restrict__ g = d.C + ((size_t)kx * L + ky) * N;
     C2<T>* sl = s + w * P;
-    C2<T> v[16];
+    C2<T> v[F::VPT];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = r < 8 ? g[t + r * TL] : C2<T>{(T)0, (T)0};
+    for (int r = 0; r < F::VPT; ++r) v[r] = r < F::VPT / 2 ? g[t + r * TL] : C2<T>{(T)0, (T)0};
     if constexpr (NP > 1) {
       fwd_bfly<T, L, 0>(v, t, tw);
       scatter_out<T, L, 0>(sl, t, v);
@@ -395,7 +399,7 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
     // Hhat at frequencies (kx, ky, e), e = j + r L/R of the last pass
     const T* __restrict__ H = d.H + ((size_t)kx * (N + 1) + (ky <= N ? ky : L - ky)) * (N + 1);
 #pragma unroll
-    for (int b = 0; b < 16 / RL; ++b)
+    for (int b = 0; b < F::VPT / RL; ++b)
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int e = t + b * TL + r * NBL;
@@ -404,7 +408,7 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
     inv_down<T, L, NP - 1>(sl, t, v, tw);
     wave_sync();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) sl[pad(t + r * TL)] = v[r];
+    for (int r = 0; r < F::VPT / 2; ++r) sl[pad(t + r * TL)] = v[r];
   }
   __syncthreads();
   C2<T>* __restrict__ dst = d.D + (size_t)kx * N * L + ky0;
@@ -421,7 +425,7 @@ template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
   using K = TC<T, L, NT, 3>;
-  using F = Line<L>;
+  using F = Line<T, L>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
   constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
   constexpr int NKT = (N + W) / W;  // kx tiles
@@ -433,16 +437,16 @@ __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T
     if (w < W && kx0 + w <= N) {
       const C2<T>* __restrict__ src = d.D + ((size_t)(kx0 + w) * N + z) * L;
       C2<T>* sl = s + w * P;
-      C2<T> v[16];
+      C2<T> v[F::VPT];
       // inputs of the first inverse pass: natural positions of the last pass
 #pragma unroll
-      for (int b = 0; b < 16 / RL; ++b)
+      for (int b = 0; b < F::VPT / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) v[b * RL + r] = src[t + b * TL + r * NBL];
       inv_down<T, L, NP - 1>(sl, t, v, tw);
       wave_sync();
 #pragma unroll
-      for (int r = 0; r < 8; ++r) sl[pad(t + r * TL)] = v[r];
+      for (int r = 0; r < F::VPT / 2; ++r) sl[pad(t + r * TL)] = v[r];
     }
   }
   __syncthreads();
@@ -462,7 +466,7 @@ template <typename T, int L, int NT>
 __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
   using K = TC<T, L, NT, 4>;
-  using F = Line<L>;
+  using F = Line<T, L>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
   constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
   const int tid = threadIdx.x, t = tid % TL, j = tid / TL;
@@ -471,9 +475,9 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
   const C2<T>* __restrict__ A = d.X + ((size_t)z * N + y0 + 2 * j) * (N + kEPad);
   const C2<T>* __restrict__ B = A + (N + kEPad);
   C2<T>* sl = s + j * P;
-  C2<T> v[16];
+  C2<T> v[F::VPT];
 #pragma unroll
-  for (int b = 0; b < 16 / RL; ++b)
+  for (int b = 0; b < F::VPT / RL; ++b)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const int e = t + b * TL + r * NBL;
@@ -489,7 +493,7 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
   T* __restrict__ da = d.phi + ((size_t)z * N + y0 + 2 * j) * N;
   T* __restrict__ db = da + N;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
+  for (int r = 0; r < F::VPT / 2; ++r) {
     da[t + r * TL] = v[r].re;
     db[t + r * TL] = v[r].im;
   }
@@ -850,8 +854,11 @@ __global__ void k_green_fill(C2<double>* F, int N, double l, double lz, double h
 // staged in LDS, each transformed by TL threads of one wave.
 template <int L>
 struct GreenTile {
-  static constexpr int TL = L / 16, P = L + L / 16 + 1, NT = 256;
-  static constexpr int W = NT / TL < L ? NT / TL : L;
+  static constexpr int TL = Line<double, L>::TL, P = L + L / 16 + 1, NT = 256;
+  static constexpr int fit(int w) {
+    return (w > 1 && w * P * (int)sizeof(C2<double>) > kLdsCap) ? fit(w / 2) : w;
+  }
+  static constexpr int W = fit(NT / TL < L ? NT / TL : L);
 };
 
 template <int L, int AXIS>
