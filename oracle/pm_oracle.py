@@ -94,17 +94,18 @@ class Hierarchy:
 
     Three levels: inner (grid 1), middle (grids 2 and 3 share it) and outer
     (grids 4 and 5, the fixed global grid).  One level: a single isolated grid
-    holding every particle.  `centring` is 'fixed' or 'com' (centre of mass,
-    the alternative the paper names to the density maximum); it moves the
-    inner and middle levels only.  The outer level keeps its own fixed centre.
+    holding every particle.  `centring` is 'fixed', 'com' (centre of mass,
+    the alternative the paper names) or 'density' (the density maximum, see
+    density_max_centre); it moves the inner and middle levels only.  The
+    outer level keeps its own fixed centre.
     """
 
     def __init__(self, levels, centring="fixed", centre=(0.0, 0.0, 0.0)):
         self.levels = list(levels)
         if len(self.levels) not in (1, 3):
             raise ValueError("a hierarchy has 1 or 3 levels")
-        if centring not in ("fixed", "com"):
-            raise ValueError("centring is 'fixed' or 'com'")
+        if centring not in ("fixed", "com", "density"):
+            raise ValueError("centring is 'fixed', 'com' or 'density'")
         if len(self.levels) == 1 and centring != "fixed":
             raise ValueError("a single grid is the fixed global grid")
         self.centring = centring
@@ -208,6 +209,54 @@ def centre_of_mass(x, m, mask):
     """
     mm = m[mask]
     return (x[mask] * mm[:, None]).sum(axis=0) / mm.sum()
+
+
+def density_mass_shift(m):
+    """Binary scale of the exact integer cell masses of density_max_centre.
+
+    s = 62 - e - b, where m_max < 2^e (e from frexp of the largest particle
+    mass of the whole set, lost and other galaxies included) and b is the
+    bit length of the particle count n, so n * m_max * 2^s < 2^62: every cell
+    total of the integers floor(m * 2^s) fits in 62 bits.
+    """
+    n = int(m.shape[0])
+    e = int(np.frexp(np.max(m))[1]) if n > 0 else 0
+    return 62 - e - n.bit_length()
+
+
+def density_max_centre(x, m, mask, L: Level, prev_centre, shift):
+    """Density maximum of one galaxy (Sec. 2.1: the inner and middle grids
+    follow the galaxy's density maximum).  Parity unpinned beyond the pins of
+    the test suite: the paper does not say how the maximum is located.
+
+    Reading: the selected particles' masses are binned on the cells of Eq. 7
+    of the galaxy's inner grid placed at the previous centre (all N^3 cells,
+    not only the usable ones).  Each mass enters as the integer
+    floor(m * 2^shift), so the cell totals are exact and independent of the
+    summation order.  The densest cell is the one with the largest total;
+    ties go to the lowest (z, y, x) index.  The centre is the FP64 centre of
+    mass of the selected particles in the 3x3x3 block of cells around it.
+    With no selected particle on the grid the previous centre is kept.
+    """
+    prev = np.asarray(prev_centre, dtype=np.float64)
+    N = L.N
+    xs, ms = x[mask], m[mask]
+    idx, _ = ngp_cell(xs, prev, L)
+    on = np.all((idx >= 0) & (idx < N), axis=1)
+    if not on.any():
+        return prev.copy()
+    q = np.floor(np.ldexp(ms[on], shift)).astype(np.int64)
+    io = idx[on]
+    lin = (io[:, 2] * N + io[:, 1]) * N + io[:, 0]
+    hist = np.zeros(N ** 3, dtype=np.int64)
+    np.add.at(hist, lin, q)
+    if hist.max() <= 0:
+        return prev.copy()
+    best = int(np.argmax(hist))            # first maximum: lowest (z, y, x)
+    b = np.array([best % N, (best // N) % N, best // (N * N)])
+    win = np.all(np.abs(idx - b) <= 1, axis=1) & on
+    mw = ms[win]
+    return (xs[win] * mw[:, None]).sum(axis=0) / mw.sum()
 
 
 # --------------------------------------------------------------------------
@@ -401,11 +450,20 @@ class System:
         return solve_fft(M, self.hhat[(L.N, L.R, L.q)], self.G)
 
     # -- per galaxy --------------------------------------------------------
-    def centres(self, x, m, gal, lost):
+    def centres(self, x, m, gal, lost, prev=None):
+        """Centres of the inner and middle grids of every galaxy.
+
+        `prev` (per galaxy) is the centre of the previous solve, used by
+        density centring; the hierarchy's own centre when None.
+        """
         c = []
         for g, hh in enumerate(self.h):
             if hh.centring == "com":
                 c.append(centre_of_mass(x, m, (gal == g) & ~lost))
+            elif hh.centring == "density":
+                p = hh.centre if prev is None else prev[g]
+                c.append(density_max_centre(x, m, (gal == g) & ~lost, hh.levels[0], p,
+                                            density_mass_shift(m)))
             else:
                 c.append(hh.centre.copy())
         return c
@@ -496,18 +554,21 @@ class System:
         idx, _ = ngp_cell(x, c, L)
         return ~in_usable(idx, L.N)
 
-    def step(self, x, v, m, gal, lost, dt):
+    def step(self, x, v, m, gal, lost, dt, prev_centres=None):
         """One integration cycle (Sec. 2.1): fields, Eq. 8, leapfrog of Eq. 6.
 
         Loss: particles outside the global grid at the start of the step (only
         possible for the initial positions) and after the drift are flagged
         lost and never move, deposit or feel a force again.  The centres are
-        taken after the start-of-step loss test.
+        taken after the start-of-step loss test (density centring starts from
+        prev_centres, the centres of the previous step); they are kept in
+        self.last_centres.
         Returns new (x, v, lost) and the accelerations used.
         """
         x = x.copy(); v = v.copy(); lost = lost.copy()
         lost |= self.lost_now(x)
-        centres = self.centres(x, m, gal, lost)
+        centres = self.centres(x, m, gal, lost, prev_centres)
+        self.last_centres = centres
         acc = self.accel(x, m, gal, lost, centres)
         live = ~lost
         x[live], v[live] = leapfrog_kd(x[live], v[live], acc[live], dt)
@@ -515,7 +576,7 @@ class System:
         return x, v, lost, acc
 
     # -- diagnostics -----------------------------------------------------------
-    def diagnostics(self, x, v, m, comp, gal, lost, dt, n_comp=8):
+    def diagnostics(self, x, v, m, comp, gal, lost, dt, n_comp=8, prev_centres=None):
         """FP64 energy and angular momentum per component, disc dispersions.
 
         v is the staggered v(t - dt/2); the synchronised velocity is
@@ -525,7 +586,7 @@ class System:
         galaxy 0's centre.
         parity unpinned beyond the pins of the energy it sums.
         """
-        centres = self.centres(x, m, gal, lost)
+        centres = self.centres(x, m, gal, lost, prev_centres)
         acc, Pp = self.accel(x, m, gal, lost, centres, want_pot=True)
         live = ~lost
         vs = v + 0.5 * dt * acc
