@@ -118,7 +118,7 @@ def time_solves(sbx, torch, N, R, q, prec, batch, iters):
 
 def make_ctx(sbx, w, prec):
     from paper_1210_1736_amd import sbx as S
-    cent = {"com": S.SBX_CENTRE_COM, "fixed": S.SBX_CENTRE_FIXED}
+    cent = {"com": S.SBX_CENTRE_COM, "fixed": S.SBX_CENTRE_FIXED, "density": S.SBX_CENTRE_DENSITY}
     hs = [S.make_hierarchy([(L.N, L.R, L.q) for L in h.levels], cent[h.centring], h.centre,
                            h.outer_centre) for h in w.hier]
     ctx = S.Context(prec=prec, G=w.G)

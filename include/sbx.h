@@ -52,7 +52,7 @@ typedef enum {
 } sbx_status;
 
 typedef enum { SBX_FP32 = 0, SBX_FP64 = 1 } sbx_prec;
-typedef enum { SBX_CENTRE_FIXED = 0, SBX_CENTRE_COM = 1 } sbx_centring;
+typedef enum { SBX_CENTRE_FIXED = 0, SBX_CENTRE_COM = 1, SBX_CENTRE_DENSITY = 2 } sbx_centring;
 
 /* Particle classes relative to one galaxy's grids (Sec. 2.1 list of grids). */
 typedef enum { SBX_CORE = 0, SBX_RING = 1, SBX_OUTER = 2, SBX_LOST = 3 } sbx_class;
@@ -70,7 +70,17 @@ typedef struct {
  *   outer = the fixed global grid (grids 4 and 5), centred at outer_centre.
  *   The inner and middle levels follow the galaxy centre: `centre` when
  *   centring = SBX_CENTRE_FIXED, the centre of mass of the galaxy's live
- *   particles (recomputed every step) when SBX_CENTRE_COM.
+ *   particles (recomputed every step) when SBX_CENTRE_COM, the galaxy's
+ *   density maximum when SBX_CENTRE_DENSITY (recomputed at every solve,
+ *   starting from the centre of the previous solve, `centre` for the first
+ *   one): the galaxy's live particle masses are binned on the N^3 cells
+ *   (Eq. 7) of the inner grid placed at that centre as exact integers
+ *   floor(m 2^s), s = 62 - e - b with m_max < 2^e over all particles and b
+ *   the bit length of the particle count; the densest cell (ties: lowest
+ *   (z, y, x) index) and the FP64 mass centre of the galaxy's live particles
+ *   in its 3x3x3 block of cells give the new centre (the previous one is
+ *   kept when no particle is on the grid).  Costs an N^3 array of 64-bit
+ *   integers per galaxy.
  * n_levels = 1: one isolated grid lv[0], fixed at `centre`, holding every
  *   particle (centring must be SBX_CENTRE_FIXED). */
 typedef struct {

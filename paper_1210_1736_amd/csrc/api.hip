@@ -53,7 +53,8 @@ sbx_status validate(int ng, const sbx_hierarchy* h) {
       set_error("a hierarchy has 1 or 3 levels");
       return SBX_EINVAL;
     }
-    if (hh.centring != SBX_CENTRE_FIXED && hh.centring != SBX_CENTRE_COM) {
+    if (hh.centring != SBX_CENTRE_FIXED && hh.centring != SBX_CENTRE_COM &&
+        hh.centring != SBX_CENTRE_DENSITY) {
       set_error("unknown centring");
       return SBX_EINVAL;
     }
@@ -196,6 +197,10 @@ InstDev<T> inst_of(const sbx_ctx* c) {
   I.key = c->key;
   I.count = c->count;
   I.part_base = 0;
+  I.dm_hist = c->dm_hist;
+  I.dm_elems = c->dm_elems;
+  I.dm_aux = c->dm_aux;
+  I.dm_partial = c->dm_partial;
   I.dt = c->dt_dev;
   I.n = c->n;
   return I;
@@ -206,6 +211,14 @@ template InstDev<double> inst_of<double>(const sbx_ctx*);
 
 sbx_status upload_inst(sbx_ctx* c) {
   SBX_HIP(hipStreamSynchronize(c->stream));
+  if (c->built && !c->solved) {
+    // the centres a solve starts from (density-maximum centring) until the
+    // first solve has computed them
+    double hc[3 * kMaxGal];
+    for (int g = 0; g < c->ngal; ++g)
+      for (int k = 0; k < 3; ++k) hc[3 * g + k] = c->hh[g].centre[k];
+    SBX_HIP(hipMemcpy(c->centres, hc, sizeof(double) * 3 * c->ngal, hipMemcpyHostToDevice));
+  }
   if (c->cfg.prec == SBX_FP64) {
     const InstDev<double> I = inst_of<double>(c);
     SBX_HIP(hipMemcpy(c->d_inst, &I, sizeof(I), hipMemcpyHostToDevice));
@@ -260,6 +273,10 @@ void free_grids(sbx_ctx* c) {
   free_ptr(c->grid_block);
   free_typed(c->count);
   free_typed(c->scan_tmp);
+  free_typed(c->dm_hist);
+  free_typed(c->dm_aux);
+  free_typed(c->dm_partial);
+  c->dm_elems = 0;
   c->bins = 0;
   for (auto& g : c->greens) free_ptr(g.H);
   c->greens.clear();
@@ -329,6 +346,15 @@ sbx_status build_grids_t(sbx_ctx* c) {
   c->bins = sort_bins(c->sys);
   SBX_TRY(dev_alloc((void**)&c->count, sizeof(uint32_t) * (c->bins + 1)));
   SBX_TRY(dev_alloc((void**)&c->scan_tmp, sizeof(uint32_t) * scan_tmp_elems(c->bins + 1)));
+  // density-maximum centring: one N^3 integer histogram per galaxy
+  bool dm = false;
+  for (int g = 0; g < c->ngal; ++g) dm = dm || c->hh[g].centring == SBX_CENTRE_DENSITY;
+  if (dm) {
+    c->dm_elems = cells * c->ngal;
+    SBX_TRY(dev_alloc((void**)&c->dm_hist, sizeof(unsigned long long) * c->dm_elems));
+    SBX_TRY(dev_alloc((void**)&c->dm_aux, sizeof(unsigned long long) * kDmAux));
+    SBX_TRY(dev_alloc((void**)&c->dm_partial, sizeof(double) * (size_t)kRedBlocks * kPreVals));
+  }
   return SBX_OK;
 }
 
@@ -370,7 +396,7 @@ template <typename T>
 sbx_status sort_t(sbx_ctx* c) {
   const std::vector<InstInfo> info{info_of(c)};
   c->rec.mark(PH_START, c->stream);
-  if (!c->solved) SBX_TRY(launch_centres<T>(dinst<T>(c), c->d_cur, info, false, c->stream));
+  if (!c->solved) SBX_TRY(launch_centres<T>(dinst<T>(c), c->d_cur, info, false, c->stream, false));
   SBX_TRY(launch_sort<T>(dinst<T>(c), c->d_cur, info, c->count, c->bins + 1, c->scan_tmp, c->stream));
   c->cur ^= 1;
   c->rec.mark(PH_SORT, c->stream);

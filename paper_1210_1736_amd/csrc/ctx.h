@@ -76,6 +76,11 @@ struct sbx_ctx {
   void* adj_block = nullptr;
   sbx::SolvePlan<float> adj32;
   sbx::SolvePlan<double> adj64;
+  // density-maximum centring: integer cell masses, search scratch, block sums
+  unsigned long long* dm_hist = nullptr;
+  size_t dm_elems = 0;
+  unsigned long long* dm_aux = nullptr;
+  double* dm_partial = nullptr;
   // cell sort
   uint32_t* key = nullptr;
   uint32_t* count = nullptr;     // bins + 1
@@ -139,6 +144,6 @@ InstDev<T> inst_of(const sbx_ctx* c);
 // Upload the context's instance record (synchronises the context stream).
 sbx_status upload_inst(sbx_ctx* c);
 
-inline InstInfo info_of(const sbx_ctx* c) { return InstInfo{c->n, c->grid_elems}; }
+inline InstInfo info_of(const sbx_ctx* c) { return InstInfo{c->n, c->grid_elems, c->dm_elems}; }
 
 }  // namespace sbx

@@ -25,6 +25,7 @@ constexpr int kPreVals = kMaxGal * 4;  // per galaxy [m, m x, m y, m z]
 constexpr int kRedBlocks = 1024;       // blocks per instance of the loss-test / COM pass
 constexpr int kForceBlocksMax = 4096;  // blocks per instance of the force pass
 constexpr int kDepChunk = 2048;        // particles per block of the mass assignment
+constexpr int kArgParts = 256;         // blocks per galaxy of the densest-cell search
 
 // One grid geometry as the kernels use it (all float64, computed on the host
 // exactly as the method's formulas read: l = 2R/(N-4), lz = q l, gamma = 1/l).
@@ -41,7 +42,7 @@ struct LevelDev {
 
 struct HierDev {
   int n_levels;
-  int centring;  // 0 fixed, 1 centre of mass
+  int centring;  // 0 fixed, 1 centre of mass, 2 density maximum
   LevelDev lv[3];
   double centre[3];   // fixed centre (inner/middle levels, or the single grid)
   double outer_c[3];  // centre of the global grid (3 levels)
@@ -90,9 +91,17 @@ struct InstDev {
   uint32_t* key;            // n
   uint32_t* count;          // bins + 1: this instance's slice of the shared counts
   uint32_t part_base;       // sort position of the instance's first particle
+  // density-maximum centring (null / 0 when no galaxy uses it)
+  unsigned long long* dm_hist;  // ngal * N^3 integer cell masses of the inner grids
+  size_t dm_elems;
+  unsigned long long* dm_aux;   // [0] bits of the largest mass, [1 + g] densest cell
+                                // of galaxy g (all ones: none), then kMaxGal *
+                                // kArgParts (value, index) partials
+  double* dm_partial;           // kRedBlocks rows of kPreVals: block mass sums
   double dt;
   int64_t n;
 };
+constexpr int kDmAux = 1 + kMaxGal + 2 * kMaxGal * kArgParts;
 
 // Counting-sort bins.  A particle's bin is the cell of its finest grid
 // relative to its own galaxy, coarsened by sort_group cells per axis; bins
@@ -119,6 +128,7 @@ __host__ __device__ inline size_t sort_bins(const SysDev& s) { return bins_befor
 struct InstInfo {
   int64_t n;
   size_t grid_elems;
+  size_t dm_elems;  // density-maximum histogram (0: no galaxy uses it)
 };
 
 struct Span {
@@ -138,9 +148,11 @@ sbx_status launch_zero_grids(const InstDev<T>* inst, const std::vector<InstInfo>
 // Loss test at the current positions and centre-of-mass sums (pre_partial),
 // then the centres; with from_com the centres come from the sums the last
 // moving force pass left in com_partial instead (no particle pass).
+// Galaxies centred on their density maximum move from their current centre
+// (the centres array) when density is set, and keep it otherwise.
 template <typename T>
 sbx_status launch_centres(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,
-                          bool from_com, hipStream_t s);
+                          bool from_com, hipStream_t s, bool density = true);
 
 template <typename T>
 sbx_status launch_deposit(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,

@@ -345,6 +345,10 @@ static int64_t blocks_particles(const InstInfo& f) { return f.n > 0 ? (f.n + 255
 static int64_t blocks_force(const InstInfo& f) { return force_blocks(f.n); }
 static int64_t blocks_deposit(const InstInfo& f) { return f.n > 0 ? (f.n + kDepChunk - 1) / kDepChunk : 1; }
 static int64_t blocks_red(const InstInfo&) { return kRedBlocks; }
+static int64_t blocks_dm(const InstInfo& f) {
+  const int64_t b = (int64_t)((f.dm_elems + 1023) / 1024);
+  return b < 1 ? 1 : (b > 2048 ? 2048 : b);
+}
 static int64_t blocks_sort(const InstInfo& f) { return f.n > 0 ? (f.n + 255) / 256 : 1; }
 static int64_t blocks_grid(const InstInfo& f) {
   const int64_t b = (int64_t)((f.grid_elems + 1023) / 1024);
@@ -413,17 +417,21 @@ __global__ void __launch_bounds__(256) k_reduce_one(const double* __restrict__ p
 }
 
 // One block per instance: column sums of the partial rows (fixed order:
-// strided per thread, then a fixed tree), then the centres.
+// strided per thread, then a fixed tree), then the centres.  Galaxies centred
+// on their density maximum take their sums from dm_partial when `density`
+// is set and keep their current centre otherwise.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_centres(const InstDev<T>* __restrict__ inst, int from_com) {
+    k_centres(const InstDev<T>* __restrict__ inst, int from_com, int density) {
   __shared__ double red[256];
   __shared__ double sums[kPreVals];
   const InstDev<T>& I = inst[blockIdx.x];
-  const double* part = from_com ? I.com_partial : I.pre_partial;
-  const int rows = from_com ? force_blocks_dev(I.n) : kRedBlocks;
   const int nv = 4 * I.sys.ngal;
   for (int v = 0; v < nv; ++v) {
+    const bool dm = I.sys.h[v / 4].centring == SBX_CENTRE_DENSITY;
+    if (dm && !(density && I.dm_partial)) continue;
+    const double* part = dm ? I.dm_partial : (from_com ? I.com_partial : I.pre_partial);
+    const int rows = (from_com && !dm) ? force_blocks_dev(I.n) : kRedBlocks;
     double s = 0.0;
     for (int r = threadIdx.x; r < rows; r += 256) s += part[(size_t)r * kPreVals + v];
     red[threadIdx.x] = s;
@@ -439,7 +447,13 @@ __global__ void __launch_bounds__(256)
     const int g = threadIdx.x;
     const HierDev& h = I.sys.h[g];
     double c[3] = {h.centre[0], h.centre[1], h.centre[2]};
-    if (h.centring == SBX_CENTRE_COM && sums[4 * g] > 0.0) {
+    const bool dm = h.centring == SBX_CENTRE_DENSITY;
+    if (dm) {
+      c[0] = I.centres[3 * g + 0];
+      c[1] = I.centres[3 * g + 1];
+      c[2] = I.centres[3 * g + 2];
+    }
+    if ((h.centring == SBX_CENTRE_COM || (dm && density && I.dm_partial)) && sums[4 * g] > 0.0) {
       c[0] = sums[4 * g + 1] / sums[4 * g];
       c[1] = sums[4 * g + 2] / sums[4 * g];
       c[2] = sums[4 * g + 3] / sums[4 * g];
@@ -448,6 +462,200 @@ __global__ void __launch_bounds__(256)
     I.centres[3 * g + 1] = c[1];
     I.centres[3 * g + 2] = c[2];
   }
+}
+
+// ------------------------------------------------ density-maximum centring --
+// Reading of Sec. 2.1 (the inner and middle grids follow the density maximum
+// of their galaxy): the galaxy's live particle masses are binned on the N^3
+// cells (Eq. 7) of its inner grid placed at the current centre, each as the
+// integer floor(m 2^s), s = 62 - e - b (the largest mass of the instance is
+// below 2^e, b is the bit length of n), so every cell total fits in 62 bits
+// and does not depend on the order of the atomic adds.  The densest cell
+// (ties: lowest (z, y, x) index) and the FP64 mass centre of the live
+// particles in its 3x3x3 block give the new centre.
+
+__device__ __forceinline__ int dm_shift(unsigned long long mmax_bits, int64_t n) {
+  int e = 0;
+  (void)frexp(__longlong_as_double((long long)mmax_bits), &e);
+  const int b = n > 0 ? 64 - __clzll((long long)n) : 0;
+  return 62 - e - b;
+}
+
+// Zero the histogram and the largest-mass word.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dm_zero(const InstDev<T>* __restrict__ inst, Span sp) {
+  const int i = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[i], nb = sp.start[i + 1] - sp.start[i];
+  const InstDev<T>& I = inst[i];
+  if (!I.dm_hist) return;
+  if (lb == 0 && threadIdx.x == 0) I.dm_aux[0] = 0ull;
+  for (size_t k = (size_t)lb * 256 + threadIdx.x; k < I.dm_elems; k += (size_t)nb * 256) I.dm_hist[k] = 0ull;
+}
+
+// Largest particle mass of the instance (all particles): the bit patterns of
+// non-negative doubles order like the values.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_dm_mmax(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  const int ii = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
+  const InstDev<T>& I = inst[ii];
+  if (!I.dm_hist) return;
+  const PartDev<T> p = I.p[cur[ii]];
+  unsigned long long mx = 0ull;
+  for (int64_t i = (int64_t)lb * 256 + threadIdx.x; i < p.n; i += (int64_t)nb * 256)
+    mx = max(mx, (unsigned long long)__double_as_longlong((double)p.m[i]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (unsigned long long)__shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0 && mx) atomicMax(I.dm_aux, mx);
+}
+
+// Integer cell masses of every density-centred galaxy's live particles.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_dm_hist(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  const int ii = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
+  const InstDev<T>& I = inst[ii];
+  if (!I.dm_hist) return;
+  const PartDev<T> p = I.p[cur[ii]];
+  const SysDev& sys = I.sys;
+  const int shift = dm_shift(I.dm_aux[0], I.n);
+  const int N = sys.h[0].lv[0].N;
+  const uint32_t N3 = (uint32_t)N * N * N;
+  // every lane of a wave runs the same number of rounds (wave_run_sum)
+  for (int64_t base = (int64_t)lb * 256; base < p.n; base += (int64_t)nb * 256) {
+    const int64_t i = base + threadIdx.x;
+    uint32_t key = kNoKey;
+    unsigned long long q = 0ull;
+    if (i < p.n && !p.lost[i]) {
+      const int g = p.gal[i];
+      const HierDev& h = sys.h[g];
+      if (h.centring == SBX_CENTRE_DENSITY) {
+        int c[3];
+        cell3(h.lv[0], I.centres + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
+        if (c[0] >= 0 && c[0] < N && c[1] >= 0 && c[1] < N && c[2] >= 0 && c[2] < N) {
+          key = (uint32_t)g * N3 + ((uint32_t)c[2] * N + c[1]) * N + c[0];
+          q = (unsigned long long)floor(ldexp((double)p.m[i], shift));
+        }
+      }
+    }
+    bool tail;
+    const unsigned long long s = wave_run_sum<unsigned long long>(key, q, tail);
+    if (tail && key != kNoKey) atomic_add_g(glb(I.dm_hist + key), s);
+  }
+}
+
+// Larger total wins; equal totals go to the lower index.
+__device__ __forceinline__ void dm_better(unsigned long long& v, unsigned long long& k,
+                                          unsigned long long v2, unsigned long long k2) {
+  if (v2 > v || (v2 == v && k2 < k)) {
+    v = v2;
+    k = k2;
+  }
+}
+
+__device__ __forceinline__ void dm_block_best(unsigned long long& v, unsigned long long& k) {
+  __shared__ unsigned long long sv[256], sk[256];
+  sv[threadIdx.x] = v;
+  sk[threadIdx.x] = k;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      unsigned long long a = sv[threadIdx.x], b = sk[threadIdx.x];
+      dm_better(a, b, sv[threadIdx.x + w], sk[threadIdx.x + w]);
+      sv[threadIdx.x] = a;
+      sk[threadIdx.x] = b;
+    }
+    __syncthreads();
+  }
+  v = sv[0];
+  k = sk[0];
+}
+
+// Densest cell, first stage: grid (kArgParts, kMaxGal, instances).
+template <typename T>
+__global__ void __launch_bounds__(256) k_dm_arg1(const InstDev<T>* __restrict__ inst) {
+  const InstDev<T>& I = inst[blockIdx.z];
+  const int g = blockIdx.y;
+  if (!I.dm_hist || g >= I.sys.ngal || I.sys.h[g].centring != SBX_CENTRE_DENSITY) return;
+  const int N = I.sys.h[0].lv[0].N;
+  const size_t N3 = (size_t)N * N * N;
+  const unsigned long long* hg = I.dm_hist + (size_t)g * N3;
+  unsigned long long v = 0ull, k = ~0ull;
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < N3; c += (size_t)kArgParts * 256)
+    dm_better(v, k, hg[c], c);
+  dm_block_best(v, k);
+  if (threadIdx.x == 0) {
+    unsigned long long* part = I.dm_aux + 1 + kMaxGal + 2 * ((size_t)g * kArgParts + blockIdx.x);
+    part[0] = v;
+    part[1] = k;
+  }
+}
+
+// Second stage: grid (kMaxGal, instances); the cell, or all ones when the
+// galaxy has no mass on its inner grid.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dm_arg2(const InstDev<T>* __restrict__ inst) {
+  const InstDev<T>& I = inst[blockIdx.y];
+  const int g = blockIdx.x;
+  if (!I.dm_hist || g >= I.sys.ngal || I.sys.h[g].centring != SBX_CENTRE_DENSITY) return;
+  const unsigned long long* part = I.dm_aux + 1 + kMaxGal + 2 * (size_t)g * kArgParts;
+  unsigned long long v = 0ull, k = ~0ull;
+  for (int r = threadIdx.x; r < kArgParts; r += 256) dm_better(v, k, part[2 * r], part[2 * r + 1]);
+  dm_block_best(v, k);
+  if (threadIdx.x == 0) I.dm_aux[1 + g] = v > 0ull ? k : ~0ull;
+}
+
+// Mass sums of each density-centred galaxy's live particles in the 3x3x3
+// block around its densest cell (rows of dm_partial).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_dm_window(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  const int ii = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
+  const InstDev<T>& I = inst[ii];
+  if (!I.dm_hist) return;
+  const PartDev<T> p = I.p[cur[ii]];
+  const SysDev& sys = I.sys;
+  const int N = sys.h[0].lv[0].N;
+  int best[kMaxGal][3];
+#pragma unroll
+  for (int g = 0; g < kMaxGal; ++g) {
+    const unsigned long long k = g < sys.ngal && sys.h[g].centring == SBX_CENTRE_DENSITY
+                                     ? I.dm_aux[1 + g] : ~0ull;
+    if (k == ~0ull) {
+      best[g][0] = best[g][1] = best[g][2] = -1000;  // never within one cell
+    } else {
+      best[g][0] = (int)(k % N);
+      best[g][1] = (int)((k / N) % N);
+      best[g][2] = (int)(k / ((unsigned long long)N * N));
+    }
+  }
+  double acc[kPreVals];
+#pragma unroll
+  for (int k = 0; k < kPreVals; ++k) acc[k] = 0.0;
+  for (int64_t i = (int64_t)lb * 256 + threadIdx.x; i < p.n; i += (int64_t)nb * 256) {
+    if (p.lost[i]) continue;
+    const int g = p.gal[i];
+    const HierDev& h = sys.h[g];
+    if (h.centring != SBX_CENTRE_DENSITY) continue;
+    const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+    int c[3];
+    cell3(h.lv[0], I.centres + 3 * g, x, y, z, c);
+#pragma unroll
+    for (int gg = 0; gg < kMaxGal; ++gg) {
+      if (gg == g && abs(c[0] - best[gg][0]) <= 1 && abs(c[1] - best[gg][1]) <= 1 &&
+          abs(c[2] - best[gg][2]) <= 1) {
+        const double m = (double)p.m[i];
+        acc[4 * gg + 0] += m;
+        acc[4 * gg + 1] += m * x;
+        acc[4 * gg + 2] += m * y;
+        acc[4 * gg + 3] += m * z;
+      }
+    }
+  }
+  block_sum_store<kPreVals>(acc, I.dm_partial + (size_t)lb * kPreVals, 4 * sys.ngal);
 }
 
 // ---------------------------------------------------------- mass deposit --
@@ -1206,13 +1414,27 @@ sbx_status launch_zero_grids(const InstDev<T>* inst, const std::vector<InstInfo>
 
 template <typename T>
 sbx_status launch_centres(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,
-                          bool from_com, hipStream_t s) {
+                          bool from_com, hipStream_t s, bool density) {
   SBX_TRY(check_span(info));
   if (!from_com) {
     const Span sp = make_span(info, blocks_red);
     hipLaunchKernelGGL((k_pre<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
   }
-  hipLaunchKernelGGL((k_centres<T>), dim3((unsigned)info.size()), dim3(256), 0, s, inst, from_com ? 1 : 0);
+  bool any_dm = false;
+  for (const InstInfo& f : info) any_dm = any_dm || f.dm_elems > 0;
+  if (density && any_dm) {
+    const unsigned ni = (unsigned)info.size();
+    const Span sz = make_span(info, blocks_dm);
+    const Span sr = make_span(info, blocks_red);
+    hipLaunchKernelGGL((k_dm_zero<T>), dim3(sz.start[sz.ninst]), dim3(256), 0, s, inst, sz);
+    hipLaunchKernelGGL((k_dm_mmax<T>), dim3(sr.start[sr.ninst]), dim3(256), 0, s, inst, cur, sr);
+    hipLaunchKernelGGL((k_dm_hist<T>), dim3(sr.start[sr.ninst]), dim3(256), 0, s, inst, cur, sr);
+    hipLaunchKernelGGL((k_dm_arg1<T>), dim3(kArgParts, kMaxGal, ni), dim3(256), 0, s, inst);
+    hipLaunchKernelGGL((k_dm_arg2<T>), dim3(kMaxGal, ni), dim3(256), 0, s, inst);
+    hipLaunchKernelGGL((k_dm_window<T>), dim3(sr.start[sr.ninst]), dim3(256), 0, s, inst, cur, sr);
+  }
+  hipLaunchKernelGGL((k_centres<T>), dim3((unsigned)info.size()), dim3(256), 0, s, inst, from_com ? 1 : 0,
+                     density ? 1 : 0);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
@@ -1386,7 +1608,7 @@ sbx_status launch_join3(const T* x0, const T* x1, const T* x2, double* dst, int6
   template sbx_status launch_zero_grids<T>(const InstDev<T>*, const std::vector<InstInfo>&,      \
                                            hipStream_t);                                         \
   template sbx_status launch_centres<T>(const InstDev<T>*, const int*,                           \
-                                        const std::vector<InstInfo>&, bool, hipStream_t);        \
+                                        const std::vector<InstInfo>&, bool, hipStream_t, bool);  \
   template sbx_status launch_deposit<T>(const InstDev<T>*, const int*,                           \
                                         const std::vector<InstInfo>&, hipStream_t);              \
   template sbx_status launch_force<T>(const InstDev<T>*, const int*, const std::vector<InstInfo>&, \

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libsbx.so")
 
 SBX_OK, SBX_EINVAL, SBX_ENOMEM, SBX_EDEVICE, SBX_EQCRIT, SBX_ESTATE = 0, -1, -2, -3, -4, -5
 SBX_FP32, SBX_FP64 = 0, 1
-SBX_CENTRE_FIXED, SBX_CENTRE_COM = 0, 1
+SBX_CENTRE_FIXED, SBX_CENTRE_COM, SBX_CENTRE_DENSITY = 0, 1, 2
 CORE, RING, OUTER, LOST = 0, 1, 2, 3
 
 N_PHASES = 11

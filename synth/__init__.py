@@ -39,7 +39,7 @@ class LevelSpec:
 @dataclasses.dataclass
 class HierSpec:
     levels: list
-    centring: str = "fixed"          # 'fixed' or 'com'
+    centring: str = "fixed"          # 'fixed', 'com' or 'density'
     centre: tuple = (0.0, 0.0, 0.0)  # fixed centre (inner/middle if fixed; single grid)
     outer_centre: tuple = (0.0, 0.0, 0.0)
 

@@ -18,7 +18,8 @@ def oracle_hier(hs: synth.HierSpec) -> O.Hierarchy:
 
 def sbx_hier(hs: synth.HierSpec):
     from paper_1210_1736_amd import sbx
-    cent = sbx.SBX_CENTRE_COM if hs.centring == "com" else sbx.SBX_CENTRE_FIXED
+    cent = {"com": sbx.SBX_CENTRE_COM, "density": sbx.SBX_CENTRE_DENSITY}.get(hs.centring,
+                                                                              sbx.SBX_CENTRE_FIXED)
     return sbx.make_hierarchy([(L.N, L.R, L.q) for L in hs.levels], cent, hs.centre, hs.outer_centre)
 
 
