@@ -187,6 +187,19 @@ def galaxy_satellite_rate(sbx, torch, steps, warmup):
             "particle_steps_per_s": live * steps / t, "ms_per_step": 1e3 * t / steps}
 
 
+def density_centring_rate(sbx, torch, w, steps, warmup, diag_every):
+    """The main workload with the inner and middle grids on the galaxy's
+    density maximum instead of its centre of mass."""
+    import copy
+    wd = copy.deepcopy(w)
+    wd.hier[0].centring = "density"
+    t, live, ph = timed_steps(sbx, torch, wd, sbx.SBX_FP32, steps, warmup, diag_every)
+    return {"workload": "the FP32 disc-galaxy step with density-maximum centring",
+            "steps": steps, "particles_live": live, "ms_per_step": 1e3 * t / steps,
+            "particle_steps_per_s": live * steps / t,
+            "centring_ms_per_step": ph["pre"][0] / steps if "pre" in ph else None}
+
+
 def ensemble_rate(sbx, torch, steps, warmup):
     """16 independent galaxy + satellite instances of uneven size stepped as
     one batch (one graph replay per step)."""
@@ -368,6 +381,9 @@ def main():
     if not args.no_extra:
         _log("FP32 force and potential error against the FP64 form")
         extra["precision"] = precision_errors(sbx, w)
+        _log("density-maximum centring")
+        extra["density_centring"] = density_centring_rate(sbx, torch, w, args.extra_steps, 2,
+                                                          args.diag_every)
         _log("galaxy + satellite")
         extra["galaxy_satellite"] = galaxy_satellite_rate(sbx, torch, args.extra_steps, 2)
         _log("ensemble of 16 instances")
