@@ -200,6 +200,30 @@ def density_centring_rate(sbx, torch, w, steps, warmup, diag_every):
             "centring_ms_per_step": ph["pre"][0] / steps if "pre" in ph else None}
 
 
+def heating_experiment(sbx, torch, w, steps=400, every=100):
+    """The reduced isolated-disc heating sweep (N in {64, 128}, q in {1,
+    0.5, 0.25}) on the benchmark galaxy, FP32, diagnostics every `every`
+    steps."""
+    from paper_1210_1736_amd import heating
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = heating.sweep(w.x, w.v, w.m, w.comp, w.gal, steps=steps, every=every, dt=w.dt, G=w.G)
+    t1 = time.perf_counter()
+    rows = []
+    for r in runs:
+        if "skipped" in r:
+            rows.append({"N": r["N"], "q": r["q"], "skipped": r["skipped"]})
+            continue
+        rows.append({"N": r["N"], "q": r["q"], "ms_per_step": 1e3 * r["steps_s"] / r["steps"],
+                     "e_heat": [r["e_heat"][0], r["e_heat"][-1]],
+                     "heating_rate_rel": r["heating_rate_rel"],
+                     "sig_z": [r["sig_z"][0], r["sig_z"][-1]],
+                     "rms_z": [r["rms_z"][0], r["rms_z"][-1]]})
+    return {"workload": f"disc galaxy in isolation, {steps} steps of dt {w.dt} per configuration, "
+                        "grids (N, 1, q), (N, 4, q), (N, 20, 1)",
+            "configs": rows, "wall_s": t1 - t0}
+
+
 def ensemble_rate(sbx, torch, steps, warmup):
     """16 independent galaxy + satellite instances of uneven size stepped as
     one batch (one graph replay per step)."""
@@ -392,6 +416,8 @@ def main():
         extra["adjoint"] = adjoint_rate(sbx, torch)
         _log("disc diagnostics")
         extra["disc_analysis"] = disc_analysis_rate(sbx, torch, w)
+        _log("heating sweep")
+        extra["heating"] = heating_experiment(sbx, torch, w)
 
     # roofline of the dominant kernel of the FP32 step
     steps = args.steps
