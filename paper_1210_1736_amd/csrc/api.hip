@@ -201,6 +201,7 @@ InstDev<T> inst_of(const sbx_ctx* c) {
   I.dm_elems = c->dm_elems;
   I.dm_aux = c->dm_aux;
   I.dm_partial = c->dm_partial;
+  I.dm_mmax = c->dm_mmax;
   I.dt = c->dt_dev;
   I.n = c->n;
   return I;
@@ -662,7 +663,8 @@ sbx_status sbx_create(const sbx_config* cfg, sbx_ctx** out) {
       (rc = dev_alloc((void**)&c->diag_one, sizeof(double) * kNDiag)) != SBX_OK ||
       (rc = dev_alloc((void**)&c->diag_log, sizeof(double) * kNDiag * kDiagCap)) != SBX_OK ||
       (rc = dev_alloc(&c->d_inst, inst_bytes)) != SBX_OK ||
-      (rc = dev_alloc((void**)&c->d_cur, sizeof(int))) != SBX_OK) {
+      (rc = dev_alloc((void**)&c->d_cur, sizeof(int))) != SBX_OK ||
+      (rc = dev_alloc((void**)&c->dm_mmax, sizeof(unsigned long long))) != SBX_OK) {
     sbx_destroy(c);
     return rc;
   }
@@ -682,6 +684,7 @@ void sbx_destroy(sbx_ctx* c) {
   free_typed(c->diag_partial);
   free_typed(c->diag_one);
   free_typed(c->diag_log);
+  free_typed(c->dm_mmax);
   free_ptr(c->d_inst);
   free_typed(c->d_cur);
   free_recorder(c->rec);
@@ -861,10 +864,13 @@ sbx_status load_impl(sbx_ctx* c, int64_t n, const double* x, const double* v, co
       set_error(std::string("particle upload: ") + hipGetErrorString(hipGetLastError()));
       return SBX_EDEVICE;
     }
-    if (c->cfg.prec == SBX_FP64)
+    if (c->cfg.prec == SBX_FP64) {
       SBX_TRY(launch_convert_in<double>(ms, (double*)q.m, n, c->stream));
-    else
+      SBX_TRY(launch_mass_max<double>((const double*)q.m, n, c->dm_mmax, c->stream));
+    } else {
       SBX_TRY(launch_convert_in<float>(ms, (float*)q.m, n, c->stream));
+      SBX_TRY(launch_mass_max<float>((const float*)q.m, n, c->dm_mmax, c->stream));
+    }
     SBX_HIP(hipMemcpyAsync(q.comp, comp, n, kind, c->stream));
     SBX_HIP(hipMemcpyAsync(q.gal, gal, n, kind, c->stream));
     SBX_TRY(launch_zero<uint8_t>(q.lost, n, c->stream));

@@ -81,6 +81,7 @@ struct sbx_ctx {
   size_t dm_elems = 0;
   unsigned long long* dm_aux = nullptr;
   double* dm_partial = nullptr;
+  unsigned long long* dm_mmax = nullptr;  // largest particle mass (bits), taken at load
   // cell sort
   uint32_t* key = nullptr;
   uint32_t* count = nullptr;     // bins + 1

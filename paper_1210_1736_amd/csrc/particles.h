@@ -94,14 +94,14 @@ struct InstDev {
   // density-maximum centring (null / 0 when no galaxy uses it)
   unsigned long long* dm_hist;  // ngal * N^3 integer cell masses of the inner grids
   size_t dm_elems;
-  unsigned long long* dm_aux;   // [0] bits of the largest mass, [1 + g] densest cell
-                                // of galaxy g (all ones: none), then kMaxGal *
-                                // kArgParts (value, index) partials
+  unsigned long long* dm_aux;   // [g] densest cell of galaxy g (all ones: none), then
+                                // kMaxGal * kArgParts (value, index) partials
   double* dm_partial;           // kRedBlocks rows of kPreVals: block mass sums
+  const unsigned long long* dm_mmax;  // bits of the largest particle mass (set at load)
   double dt;
   int64_t n;
 };
-constexpr int kDmAux = 1 + kMaxGal + 2 * kMaxGal * kArgParts;
+constexpr int kDmAux = kMaxGal + 2 * kMaxGal * kArgParts;
 
 // Counting-sort bins.  A particle's bin is the cell of its finest grid
 // relative to its own galaxy, coarsened by sort_group cells per axis; bins
@@ -195,6 +195,10 @@ sbx_status launch_adj_gather(const InstDev<T>* inst, const int* cur, int64_t n, 
                              const uint8_t* frozen, double* gm, hipStream_t s);
 
 sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s);
+
+// Bits of the largest of n non-negative masses into *out (device).
+template <typename T>
+sbx_status launch_mass_max(const T* m, int64_t n, unsigned long long* out, hipStream_t s);
 
 // Device-side check of particle inputs (device arrays, host layout): the
 // lowest bad index goes to *bad (device, preset to all ones by the caller).

@@ -481,69 +481,68 @@ __device__ __forceinline__ int dm_shift(unsigned long long mmax_bits, int64_t n)
   return 62 - e - b;
 }
 
-// Zero the histogram and the largest-mass word.
+// Zero the histogram.
 template <typename T>
 __global__ void __launch_bounds__(256) k_dm_zero(const InstDev<T>* __restrict__ inst, Span sp) {
   const int i = span_inst(sp, blockIdx.x);
   const int lb = blockIdx.x - sp.start[i], nb = sp.start[i + 1] - sp.start[i];
   const InstDev<T>& I = inst[i];
   if (!I.dm_hist) return;
-  if (lb == 0 && threadIdx.x == 0) I.dm_aux[0] = 0ull;
   for (size_t k = (size_t)lb * 256 + threadIdx.x; k < I.dm_elems; k += (size_t)nb * 256) I.dm_hist[k] = 0ull;
 }
 
-// Largest particle mass of the instance (all particles): the bit patterns of
-// non-negative doubles order like the values.
+// Largest particle mass (taken when the particles are loaded; the masses do
+// not change afterwards): the bit patterns of non-negative doubles order like
+// the values.  *out must be zero on entry.
 template <typename T>
-__global__ void __launch_bounds__(256)
-    k_dm_mmax(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
-  const int ii = span_inst(sp, blockIdx.x);
-  const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
-  const InstDev<T>& I = inst[ii];
-  if (!I.dm_hist) return;
-  const PartDev<T> p = I.p[cur[ii]];
+__global__ void __launch_bounds__(256) k_mass_max(const T* __restrict__ m, int64_t n,
+                                                  unsigned long long* __restrict__ out) {
+  const gp<const T> M = glb(m);
   unsigned long long mx = 0ull;
-  for (int64_t i = (int64_t)lb * 256 + threadIdx.x; i < p.n; i += (int64_t)nb * 256)
-    mx = max(mx, (unsigned long long)__double_as_longlong((double)p.m[i]));
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    mx = max(mx, (unsigned long long)__double_as_longlong((double)M[i]));
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mx = max(mx, (unsigned long long)__shfl_xor(mx, o, 64));
-  if ((threadIdx.x & 63) == 0 && mx) atomicMax(I.dm_aux, mx);
+  if ((threadIdx.x & 63) == 0 && mx) atomicMax(out, mx);
 }
 
-// Integer cell masses of every density-centred galaxy's live particles.
+// Integer cell masses of every density-centred galaxy's live particles (one
+// particle per thread).
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_dm_hist(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  __shared__ SysDev sys;
+  __shared__ double cen[3 * kMaxGal];
   const int ii = span_inst(sp, blockIdx.x);
-  const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
+  const int lb = blockIdx.x - sp.start[ii];
   const InstDev<T>& I = inst[ii];
   if (!I.dm_hist) return;
   const PartDev<T> p = I.p[cur[ii]];
-  const SysDev& sys = I.sys;
-  const int shift = dm_shift(I.dm_aux[0], I.n);
+  stage(&sys, &I.sys);
+  if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = I.centres[threadIdx.x];
+  __syncthreads();
+  const int shift = dm_shift(*I.dm_mmax, I.n);
   const int N = sys.h[0].lv[0].N;
   const uint32_t N3 = (uint32_t)N * N * N;
-  // every lane of a wave runs the same number of rounds (wave_run_sum)
-  for (int64_t base = (int64_t)lb * 256; base < p.n; base += (int64_t)nb * 256) {
-    const int64_t i = base + threadIdx.x;
-    uint32_t key = kNoKey;
-    unsigned long long q = 0ull;
-    if (i < p.n && !p.lost[i]) {
-      const int g = p.gal[i];
-      const HierDev& h = sys.h[g];
-      if (h.centring == SBX_CENTRE_DENSITY) {
-        int c[3];
-        cell3(h.lv[0], I.centres + 3 * g, (double)p.x[0][i], (double)p.x[1][i], (double)p.x[2][i], c);
-        if (c[0] >= 0 && c[0] < N && c[1] >= 0 && c[1] < N && c[2] >= 0 && c[2] < N) {
-          key = (uint32_t)g * N3 + ((uint32_t)c[2] * N + c[1]) * N + c[0];
-          q = (unsigned long long)floor(ldexp((double)p.m[i], shift));
-        }
+  const int64_t i = (int64_t)lb * 256 + threadIdx.x;
+  uint32_t key = kNoKey;  // lanes past the end take part in the wave sum
+  unsigned long long q = 0ull;
+  if (i < p.n && !glb((const uint8_t*)p.lost)[i]) {
+    const int g = glb((const int8_t*)p.gal)[i];
+    const HierDev& h = sys.h[g];
+    if (h.centring == SBX_CENTRE_DENSITY) {
+      int c[3];
+      cell3(h.lv[0], cen + 3 * g, (double)glb((const T*)p.x[0])[i], (double)glb((const T*)p.x[1])[i],
+            (double)glb((const T*)p.x[2])[i], c);
+      if (c[0] >= 0 && c[0] < N && c[1] >= 0 && c[1] < N && c[2] >= 0 && c[2] < N) {
+        key = (uint32_t)g * N3 + ((uint32_t)c[2] * N + c[1]) * N + c[0];
+        q = (unsigned long long)floor(ldexp((double)glb((const T*)p.m)[i], shift));
       }
     }
-    bool tail;
-    const unsigned long long s = wave_run_sum<unsigned long long>(key, q, tail);
-    if (tail && key != kNoKey) atomic_add_g(glb(I.dm_hist + key), s);
   }
+  bool tail;
+  const unsigned long long s = wave_run_sum<unsigned long long>(key, q, tail);
+  if (tail && key != kNoKey) atomic_add_g(glb(I.dm_hist + key), s);
 }
 
 // Larger total wins; equal totals go to the lower index.
@@ -587,7 +586,7 @@ __global__ void __launch_bounds__(256) k_dm_arg1(const InstDev<T>* __restrict__ 
     dm_better(v, k, hg[c], c);
   dm_block_best(v, k);
   if (threadIdx.x == 0) {
-    unsigned long long* part = I.dm_aux + 1 + kMaxGal + 2 * ((size_t)g * kArgParts + blockIdx.x);
+    unsigned long long* part = I.dm_aux + kMaxGal + 2 * ((size_t)g * kArgParts + blockIdx.x);
     part[0] = v;
     part[1] = k;
   }
@@ -600,11 +599,11 @@ __global__ void __launch_bounds__(256) k_dm_arg2(const InstDev<T>* __restrict__ 
   const InstDev<T>& I = inst[blockIdx.y];
   const int g = blockIdx.x;
   if (!I.dm_hist || g >= I.sys.ngal || I.sys.h[g].centring != SBX_CENTRE_DENSITY) return;
-  const unsigned long long* part = I.dm_aux + 1 + kMaxGal + 2 * (size_t)g * kArgParts;
+  const unsigned long long* part = I.dm_aux + kMaxGal + 2 * (size_t)g * kArgParts;
   unsigned long long v = 0ull, k = ~0ull;
   for (int r = threadIdx.x; r < kArgParts; r += 256) dm_better(v, k, part[2 * r], part[2 * r + 1]);
   dm_block_best(v, k);
-  if (threadIdx.x == 0) I.dm_aux[1 + g] = v > 0ull ? k : ~0ull;
+  if (threadIdx.x == 0) I.dm_aux[g] = v > 0ull ? k : ~0ull;
 }
 
 // Mass sums of each density-centred galaxy's live particles in the 3x3x3
@@ -612,18 +611,26 @@ __global__ void __launch_bounds__(256) k_dm_arg2(const InstDev<T>* __restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_dm_window(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  __shared__ SysDev sys;
+  __shared__ double cen[3 * kMaxGal];
   const int ii = span_inst(sp, blockIdx.x);
   const int lb = blockIdx.x - sp.start[ii], nb = sp.start[ii + 1] - sp.start[ii];
   const InstDev<T>& I = inst[ii];
   if (!I.dm_hist) return;
   const PartDev<T> p = I.p[cur[ii]];
-  const SysDev& sys = I.sys;
+  stage(&sys, &I.sys);
+  if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = I.centres[threadIdx.x];
+  __syncthreads();
+  const gp<const T> X0 = glb((const T*)p.x[0]), X1 = glb((const T*)p.x[1]), X2 = glb((const T*)p.x[2]);
+  const gp<const T> M = glb((const T*)p.m);
+  const gp<const uint8_t> LOST = glb((const uint8_t*)p.lost);
+  const gp<const int8_t> GAL = glb((const int8_t*)p.gal);
   const int N = sys.h[0].lv[0].N;
   int best[kMaxGal][3];
 #pragma unroll
   for (int g = 0; g < kMaxGal; ++g) {
     const unsigned long long k = g < sys.ngal && sys.h[g].centring == SBX_CENTRE_DENSITY
-                                     ? I.dm_aux[1 + g] : ~0ull;
+                                     ? I.dm_aux[g] : ~0ull;
     if (k == ~0ull) {
       best[g][0] = best[g][1] = best[g][2] = -1000;  // never within one cell
     } else {
@@ -636,18 +643,18 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int k = 0; k < kPreVals; ++k) acc[k] = 0.0;
   for (int64_t i = (int64_t)lb * 256 + threadIdx.x; i < p.n; i += (int64_t)nb * 256) {
-    if (p.lost[i]) continue;
-    const int g = p.gal[i];
+    if (LOST[i]) continue;
+    const int g = GAL[i];
     const HierDev& h = sys.h[g];
     if (h.centring != SBX_CENTRE_DENSITY) continue;
-    const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
+    const double x = (double)X0[i], y = (double)X1[i], z = (double)X2[i];
     int c[3];
-    cell3(h.lv[0], I.centres + 3 * g, x, y, z, c);
+    cell3(h.lv[0], cen + 3 * g, x, y, z, c);
 #pragma unroll
     for (int gg = 0; gg < kMaxGal; ++gg) {
       if (gg == g && abs(c[0] - best[gg][0]) <= 1 && abs(c[1] - best[gg][1]) <= 1 &&
           abs(c[2] - best[gg][2]) <= 1) {
-        const double m = (double)p.m[i];
+        const double m = (double)M[i];
         acc[4 * gg + 0] += m;
         acc[4 * gg + 1] += m * x;
         acc[4 * gg + 2] += m * y;
@@ -1426,9 +1433,9 @@ sbx_status launch_centres(const InstDev<T>* inst, const int* cur, const std::vec
     const unsigned ni = (unsigned)info.size();
     const Span sz = make_span(info, blocks_dm);
     const Span sr = make_span(info, blocks_red);
+    const Span sq = make_span(info, blocks_particles);
     hipLaunchKernelGGL((k_dm_zero<T>), dim3(sz.start[sz.ninst]), dim3(256), 0, s, inst, sz);
-    hipLaunchKernelGGL((k_dm_mmax<T>), dim3(sr.start[sr.ninst]), dim3(256), 0, s, inst, cur, sr);
-    hipLaunchKernelGGL((k_dm_hist<T>), dim3(sr.start[sr.ninst]), dim3(256), 0, s, inst, cur, sr);
+    hipLaunchKernelGGL((k_dm_hist<T>), dim3(sq.start[sq.ninst]), dim3(256), 0, s, inst, cur, sq);
     hipLaunchKernelGGL((k_dm_arg1<T>), dim3(kArgParts, kMaxGal, ni), dim3(256), 0, s, inst);
     hipLaunchKernelGGL((k_dm_arg2<T>), dim3(kMaxGal, ni), dim3(256), 0, s, inst);
     hipLaunchKernelGGL((k_dm_window<T>), dim3(sr.start[sr.ninst]), dim3(256), 0, s, inst, cur, sr);
@@ -1559,6 +1566,16 @@ sbx_status launch_validate_particles(const double* x, const double* v, const dou
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
+
+template <typename T>
+sbx_status launch_mass_max(const T* m, int64_t n, unsigned long long* out, hipStream_t s) {
+  SBX_HIP(hipMemsetAsync(out, 0, sizeof(unsigned long long), s));
+  hipLaunchKernelGGL((k_mass_max<T>), dim3(1024), dim3(256), 0, s, m, n, out);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+template sbx_status launch_mass_max<float>(const float*, int64_t, unsigned long long*, hipStream_t);
+template sbx_status launch_mass_max<double>(const double*, int64_t, unsigned long long*, hipStream_t);
 
 sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_iota, dim3(2048), dim3(256), 0, s, id, n);
