@@ -116,19 +116,22 @@ def time_solves(sbx, torch, N, R, q, prec, batch, iters):
     return batch / (ms * 1e-3), ms
 
 
-def make_ctx(sbx, w, prec):
+def make_ctx(sbx, w, prec, merge=False):
     from paper_1210_1736_amd import sbx as S
     cent = {"com": S.SBX_CENTRE_COM, "fixed": S.SBX_CENTRE_FIXED, "density": S.SBX_CENTRE_DENSITY}
     hs = [S.make_hierarchy([(L.N, L.R, L.q) for L in h.levels], cent[h.centring], h.centre,
                            h.outer_centre) for h in w.hier]
     ctx = S.Context(prec=prec, G=w.G)
+    if merge:
+        ctx.sbx_set_outer_merge(1)
     ctx.sbx_build_grids(hs)
     ctx.sbx_load_particles(w.x, w.v, w.m, w.comp, w.gal)
     return ctx
 
 
-def timed_steps(sbx, torch, w, prec, steps, warmup, diag_every, profile=True, sort_every=None):
-    ctx = make_ctx(sbx, w, prec)
+def timed_steps(sbx, torch, w, prec, steps, warmup, diag_every, profile=True, sort_every=None,
+                merge=False):
+    ctx = make_ctx(sbx, w, prec, merge)
     if sort_every is not None:
         ctx.sbx_set_sort_interval(sort_every)
     ctx.sbx_step(w.dt, warmup, diag_every)
@@ -177,14 +180,19 @@ def precision_errors(sbx, w):
 
 
 def galaxy_satellite_rate(sbx, torch, steps, warmup):
-    """Galaxy plus satellite: two 3-level hierarchies, 10 solves per step."""
+    """Galaxy plus satellite: two 3-level hierarchies, 10 solves per step, and
+    9 with the two grids 5 merged into one solve."""
     import synth
     w = synth.galaxy_satellite()
     t, live, _ = timed_steps(sbx, torch, w, sbx.SBX_FP32, steps, warmup, 10, profile=False)
+    tm, livem, _ = timed_steps(sbx, torch, w, sbx.SBX_FP32, steps, warmup, 10, profile=False,
+                               merge=True)
     return {"workload": "disc galaxy + Plummer satellite (200k, M 0.1), two 3-level 128^3 "
                         "hierarchies, FP32, diagnostics every 10 steps",
             "particles_live": live, "solves_per_step": 10, "steps": steps,
-            "particle_steps_per_s": live * steps / t, "ms_per_step": 1e3 * t / steps}
+            "particle_steps_per_s": live * steps / t, "ms_per_step": 1e3 * t / steps,
+            "merged_grid5": {"solves_per_step": 9, "ms_per_step": 1e3 * tm / steps,
+                             "particle_steps_per_s": livem * steps / tm}}
 
 
 def density_centring_rate(sbx, torch, w, steps, warmup, diag_every):

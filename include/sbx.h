@@ -269,6 +269,18 @@ sbx_status sbx_disc_analysis(sbx_ctx* ctx, const sbx_disc_query* q, sbx_disc_res
 sbx_status sbx_disc_modes(sbx_ctx* ctx, int32_t comp, int32_t galaxy, int32_t n_rbins, double r_max,
                           int32_t m_max, double* coeff);
 
+/* Merge grid 5 of all galaxies into one solve (1) or solve it per galaxy (0,
+ * the default); applied at the next sbx_build_grids.  Each class's sum of
+ * Sec. 2.1 contains grid 5 (core: grids 1 + 3 + 5, ring: 2 + 3 + 5, outer:
+ * 4 + 5), so by linearity of Eq. 1 the sum over galaxies of their grid-5
+ * potentials is the potential of the summed grid-5 masses, read once per
+ * particle: n_galaxies * 4 + 1 solves per step instead of n_galaxies * 5.
+ * The build then fails with SBX_EINVAL unless there are at least two
+ * galaxies, all with three levels.  In sbx_get_grid, which 3 of galaxy 0 is
+ * the summed grid 5 (which 3 of the others stays zero) and which 4 is grid 4
+ * alone.  sbx_adjoint_segment rejects a merged context (SBX_EINVAL). */
+sbx_status sbx_set_outer_merge(sbx_ctx* ctx, int32_t merge);
+
 /* Reorder the particles in device memory by the cell of their finest grid
  * every `every` steps (at the start of the step; 0 = never; default 4).  A
  * performance setting only: every output is returned in the caller's

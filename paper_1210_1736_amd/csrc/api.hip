@@ -329,6 +329,7 @@ sbx_status build_grids_t(sbx_ctx* c) {
   int s2 = 0;
   for (int g = 0; g < c->ngal; ++g)
     for (int k = 0; k < c->nslots[g]; ++k, ++s2) {
+      if (c->sys.merge5 && g > 0 && k == 3) continue;  // summed into galaxy 0's grid 5
       SolveDesc<T> d;
       d.rho = (const T*)c->grid[g][k];
       d.phi = (T*)c->grid[g][k];
@@ -341,6 +342,7 @@ sbx_status build_grids_t(sbx_ctx* c) {
         if (same_level(e.geo, c->hh[g].lv[c->slot_level[g][k]])) d.H = (const T*)e.H;
       descs.push_back(d);
     }
+  c->nsolves = (int)descs.size();
   if constexpr (sizeof(T) == 8) SBX_TRY(plan_create<T>(c->plan64, descs.data(), (int)descs.size(), c->stream));
   else SBX_TRY(plan_create<T>(c->plan32, descs.data(), (int)descs.size(), c->stream));
   // counting-sort bins (cells, or pairs of cells per axis, of every level)
@@ -965,6 +967,15 @@ sbx_status sbx_build_grids(sbx_ctx* c, int32_t n_galaxies, const sbx_hierarchy* 
   std::memset(&c->sys, 0, sizeof(c->sys));
   c->sys.ngal = n_galaxies;
   c->sys.taylor = c->cfg.taylor ? 1 : 0;
+  if (c->merge5) {
+    bool ok = n_galaxies >= 2;
+    for (int g = 0; g < n_galaxies; ++g) ok = ok && h[g].n_levels == 3;
+    if (!ok) {
+      set_error("merging the outer grids needs at least two galaxies with three levels");
+      return SBX_EINVAL;
+    }
+    c->sys.merge5 = 1;
+  }
   for (int g = 0; g < n_galaxies; ++g) {
     c->hh[g] = h[g];
     HierDev& d = c->sys.h[g];
@@ -1216,6 +1227,10 @@ sbx_status adjoint_impl(sbx_ctx* c, double dt, int32_t nsteps, int32_t ckpt_ever
       set_error("the segment adjoint needs fixed centres");
       return SBX_EINVAL;
     }
+  if (c->sys.merge5) {
+    set_error("the segment adjoint needs separate outer grids (no sbx_set_outer_merge)");
+    return SBX_EINVAL;
+  }
   return c->cfg.prec == SBX_FP64
              ? adjoint_t<double>(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x,
                                  grad_v, dev_out)
@@ -1237,6 +1252,15 @@ sbx_status sbx_adjoint_segment_device(sbx_ctx* c, double dt, int32_t nsteps, int
                                       int32_t sel_comp, int32_t sel_gal, double* loss,
                                       double* grad_m, double* grad_x, double* grad_v) {
   return adjoint_impl(c, dt, nsteps, ckpt_every, sel_comp, sel_gal, loss, grad_m, grad_x, grad_v, true);
+}
+
+sbx_status sbx_set_outer_merge(sbx_ctx* c, int32_t merge) {
+  if (!c || (merge != 0 && merge != 1)) {
+    set_error("bad argument");
+    return SBX_EINVAL;
+  }
+  c->merge5 = merge;
+  return SBX_OK;
 }
 
 sbx_status sbx_set_sort_interval(sbx_ctx* c, int32_t every) {

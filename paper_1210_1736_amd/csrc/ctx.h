@@ -88,6 +88,7 @@ struct sbx_ctx {
   uint32_t* scan_tmp = nullptr;
   size_t bins = 0;
   int sort_every = 4;
+  int merge5 = 0;  // requested by sbx_set_outer_merge, applied at the next build
   // reductions and outputs
   double* centres = nullptr;       // kMaxGal * 3
   double* pre_partial = nullptr;   // (kRedBlocks + 1) * kPreVals

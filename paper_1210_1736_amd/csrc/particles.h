@@ -51,6 +51,7 @@ struct HierDev {
 struct SysDev {
   int ngal;
   int taylor;
+  int merge5;  // grid 5 of every galaxy summed into galaxy 0's slot 3 (one solve)
   HierDev h[kMaxGal];
 };
 
@@ -69,6 +70,8 @@ struct PartDev {
 // Grid slots of one galaxy: 3 levels -> 0: grid 1 (inner, core),
 // 1: grid 3 (middle, ring), 2: grids 2+3 (middle, core+ring), 3: grid 5
 // (global, outer), 4: grids 4+5 (global, all).  1 level -> slot 0 only.
+// With merge5: slot 3 of galaxy 0 holds grid 5 of all galaxies summed, slot 3
+// of the others is unused, and slot 4 holds grid 4 alone.
 template <typename T>
 struct GridsDev {
   T* g[kMaxGal][kSlots];

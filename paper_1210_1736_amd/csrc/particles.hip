@@ -270,10 +270,15 @@ __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, 
 
 // Sum over galaxies of the fields the grid-selection rule gives each class:
 // core -> grid 1 + grid 3 + grid 5, ring -> (2 + 3) + grid 5, outer -> (4 + 5).
+// With merge5 every class's grid 5 term is the shared summed grid 5, read
+// once per particle (Sec. 2.1: each class's sum contains grid 5).
 template <typename T>
 __device__ __forceinline__ void particle_field(const SysDev& sys, const double* centres,
                                                const GridsDev<T>& F, double x, double y,
                                                double z, T* a, T& phi, bool want_phi) {
+  const bool m5 = sys.merge5 != 0;
+  bool live5 = false;
+  int i5[3] = {0, 0, 0};
   for (int g = 0; g < sys.ngal; ++g) {
     const HierDev& h = sys.h[g];
     const double* c = centres + 3 * g;
@@ -289,11 +294,11 @@ __device__ __forceinline__ void particle_field(const SysDev& sys, const double* 
       case SBX_CORE:
         eq8(F.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, sys.taylor, a, phi, want_phi);
         eq8(F.g[g][1], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, a, phi, want_phi);
-        eq8(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
+        if (!m5) eq8(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
         break;
       case SBX_RING:
         eq8(F.g[g][2], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, a, phi, want_phi);
-        eq8(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
+        if (!m5) eq8(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
         break;
       case SBX_OUTER:
         eq8(F.g[g][4], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
@@ -301,6 +306,17 @@ __device__ __forceinline__ void particle_field(const SysDev& sys, const double* 
       default:
         break;
     }
+    if (m5 && g == 0 && cl.cls != SBX_LOST) {
+      live5 = true;
+      i5[0] = cl.idx[2][0];
+      i5[1] = cl.idx[2][1];
+      i5[2] = cl.idx[2][2];
+    }
+  }
+  if (live5) {
+    const HierDev& h = sys.h[0];
+    eq8(F.g[0][3], h.lv[2], i5, x - h.outer_c[0], y - h.outer_c[1], z - h.outer_c[2], sys.taylor, a,
+        phi, want_phi);
   }
 }
 
@@ -681,7 +697,8 @@ __global__ void __launch_bounds__(256)
 // ring -> grid 3, grid 4; outer -> grid 5.  Grids 2+3 and 4+5 are assigned
 // as sums directly (their potentials are only used summed, and the solve is
 // linear), so a ring particle adds to slots 1 and 2 of its middle cell and
-// an outer particle to slots 3 and 4 of its global cell.
+// an outer particle to slots 3 and 4 of its global cell (with merge5: to
+// galaxy 0's slot 3 only, the summed grid 5 of all galaxies).
 constexpr int kDepTableBits = 11;
 constexpr int kDepTable = 1 << kDepTableBits;  // LDS hash entries
 constexpr int kDepProbes = 8;
@@ -760,8 +777,12 @@ __global__ void __launch_bounds__(256)
         fine2 = dep_key(g, 2, h.lv[1], c.idx[1]); // grid 3 (in 2+3)
         c2 = dep_key(g, 4, h.lv[2], c.idx[2]);    // grid 4 (in 4+5)
       } else if (c.cls == SBX_OUTER) {
-        fine = dep_key(g, 3, h.lv[2], c.idx[2]);  // grid 5
-        fine2 = dep_key(g, 4, h.lv[2], c.idx[2]); // grid 5 (in 4+5)
+        if (sys.merge5) {
+          fine = dep_key(0, 3, h.lv[2], c.idx[2]);  // summed grid 5 of all galaxies
+        } else {
+          fine = dep_key(g, 3, h.lv[2], c.idx[2]);  // grid 5
+          fine2 = dep_key(g, 4, h.lv[2], c.idx[2]); // grid 5 (in 4+5)
+        }
       }
     }
     {

@@ -101,6 +101,7 @@ def _load():
         "sbx_diag_log": (S, [P, I32, C.POINTER(sbx_diag), C.POINTER(I32)]),
         "sbx_sync": (S, [P]),
         "sbx_set_sort_interval": (S, [P, I32]),
+        "sbx_set_outer_merge": (S, [P, I32]),
         "sbx_adjoint_segment": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
         "sbx_adjoint_segment_device": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
         "sbx_load_particles_device": (S, [P, I64, P, P, P, P, P]),
@@ -282,6 +283,9 @@ class Context:
         _check(_lib.sbx_adjoint_segment(self._h, float(dt), int(nsteps), int(ckpt_every), int(sel_comp),
                                         int(sel_gal), _ptr(loss), _ptr(gm), _ptr(gx), _ptr(gv)))
         return float(loss[0]), gm, gx, gv
+
+    def sbx_set_outer_merge(self, merge):
+        _check(_lib.sbx_set_outer_merge(self._h, int(merge)))
 
     def sbx_set_sort_interval(self, every):
         _check(_lib.sbx_set_sort_interval(self._h, int(every)))
