@@ -24,10 +24,24 @@ __global__ void __launch_bounds__(kScanThreads)
   __shared__ uint32_t wtot[kScanThreads / 64];
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
+  // whole 16-item runs of an aligned array load as four 16-byte vectors
+  const bool vec = ((uintptr_t)d & 15u) == 0 && base + kScanItems <= n;
+  if (vec) {
+#pragma unroll
+    for (int k = 0; k < kScanItems / 4; ++k) {
+      const uint4 q = *(const uint4*)(d + base + 4 * k);
+      v[4 * k] = q.x;
+      v[4 * k + 1] = q.y;
+      v[4 * k + 2] = q.z;
+      v[4 * k + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = base + k < n ? d[base + k] : 0u;
+  }
   uint32_t t = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? d[base + k] : 0u;
     const uint32_t c = v[k];
     v[k] = t;
     t += c;
@@ -39,9 +53,16 @@ __global__ void __launch_bounds__(kScanThreads)
   uint32_t woff = 0;
   for (int w = 0; w < wave; ++w) woff += wtot[w];
   const uint32_t off = woff + incl - t;
+  if (vec) {
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) d[base + k] = v[k] + off;
+    for (int k = 0; k < kScanItems / 4; ++k)
+      *(uint4*)(d + base + 4 * k) =
+          make_uint4(v[4 * k] + off, v[4 * k + 1] + off, v[4 * k + 2] + off, v[4 * k + 3] + off);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+      if (base + k < n) d[base + k] = v[k] + off;
+  }
   if (threadIdx.x == kScanThreads - 1) {
     uint32_t tot = 0;
     for (int w = 0; w < kScanThreads / 64; ++w) tot += wtot[w];
