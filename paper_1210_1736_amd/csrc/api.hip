@@ -289,10 +289,12 @@ void free_grids(sbx_ctx* c) {
   c->solved = false;
 }
 
+// grids allocated per galaxy (fields and mass-only), and the solved ones
 int slot_count(const sbx_hierarchy& h) { return h.n_levels == 3 ? kSlots : 1; }
+int field_slot_count(const sbx_hierarchy& h) { return h.n_levels == 3 ? kFieldSlots : 1; }
 int slot_level_of(const sbx_hierarchy& h, int slot) {
   if (h.n_levels == 1) return 0;
-  static const int lv[kSlots] = {0, 1, 1, 2, 2};
+  static const int lv[kSlots] = {0, 1, 1, 2, 2, 1, 2};
   return lv[slot];
 }
 
@@ -328,10 +330,18 @@ sbx_status build_grids_t(sbx_ctx* c) {
   std::vector<SolveDesc<T>> descs;
   int s2 = 0;
   for (int g = 0; g < c->ngal; ++g)
-    for (int k = 0; k < c->nslots[g]; ++k, ++s2) {
+    for (int k = 0; k < field_slot_count(c->hh[g]); ++k, ++s2) {
       if (c->sys.merge5 && g > 0 && k == 3) continue;  // summed into galaxy 0's grid 5
       SolveDesc<T> d;
       d.rho = (const T*)c->grid[g][k];
+      d.rho2 = nullptr;
+      if (c->hh[g].n_levels == 3 && k == 2) {         // grids 2 + 3
+        d.rho = (const T*)c->grid[g][kSlotG2];
+        d.rho2 = (const T*)c->grid[g][1];
+      } else if (c->hh[g].n_levels == 3 && k == 4) {  // grids 4 + 5 (4 alone if merged)
+        d.rho = (const T*)c->grid[g][kSlotG4];
+        d.rho2 = c->sys.merge5 ? nullptr : (const T*)c->grid[g][3];
+      }
       d.phi = (T*)c->grid[g][k];
       d.X = (C2<T>*)c->X + x_elems(N) * s2;
       d.C = (C2<T>*)c->C + cd_elems(N) * s2;
@@ -478,8 +488,10 @@ sbx_status ensure_adjoint(sbx_ctx* c) {
   SolvePlan<T>& fwd = sizeof(T) == 8 ? (SolvePlan<T>&)c->plan64 : (SolvePlan<T>&)c->plan32;
   std::vector<SolveDesc<T>> d = fwd.host;
   for (auto& e : d) {
-    T* a = (T*)c->adj_block + ((const T*)e.rho - (const T*)c->grid_block);
+    // the adjoint sources are scattered into the slots the fields are read from
+    T* a = (T*)c->adj_block + ((const T*)e.phi - (const T*)c->grid_block);
     e.rho = a;
+    e.rho2 = nullptr;
     e.phi = a;
   }
   SolvePlan<T>& adj = sizeof(T) == 8 ? (SolvePlan<T>&)c->adj64 : (SolvePlan<T>&)c->adj32;
@@ -1125,7 +1137,7 @@ sbx_status sbx_get_indices(sbx_ctx* c, int32_t galaxy, int32_t level, int32_t* i
 
 sbx_status sbx_get_grid(sbx_ctx* c, int32_t galaxy, int32_t which, int32_t kind, double* out) {
   SBX_TRY(check_ready(c));
-  if (galaxy < 0 || galaxy >= c->ngal || which < 0 || which >= c->nslots[galaxy] || !out ||
+  if (galaxy < 0 || galaxy >= c->ngal || which < 0 || which >= field_slot_count(c->hh[galaxy]) || !out ||
       (kind != 0 && kind != 1)) {
     set_error("galaxy, grid or kind out of range");
     return SBX_EINVAL;
@@ -1147,15 +1159,33 @@ sbx_status sbx_get_grid(sbx_ctx* c, int32_t galaxy, int32_t which, int32_t kind,
     }
     c->grids_fields = false;
   }
+  // masses of the summed grids: their two sources, added here
+  const bool sum2 = kind == 0 && c->hh[galaxy].n_levels == 3 && (which == 2 || which == 4);
+  const void* src = c->grid[galaxy][which];
+  const void* src2 = nullptr;
+  if (sum2) {
+    src = c->grid[galaxy][which == 2 ? kSlotG2 : kSlotG4];
+    if (which == 2 || !c->sys.merge5) src2 = c->grid[galaxy][which == 2 ? 1 : 3];
+  }
   double* stage = nullptr;
   SBX_TRY(dev_alloc((void**)&stage, sizeof(double) * cells));
-  auto run = [&]() -> sbx_status {
+  std::vector<double> add;
+  auto fetch = [&](const void* g, double* host) -> sbx_status {
     if (c->cfg.prec == SBX_FP64)
-      SBX_TRY(launch_convert_out<double>((double*)c->grid[galaxy][which], stage, cells, c->stream));
+      SBX_TRY(launch_convert_out<double>((const double*)g, stage, cells, c->stream));
     else
-      SBX_TRY(launch_convert_out<float>((float*)c->grid[galaxy][which], stage, cells, c->stream));
-    SBX_HIP(hipMemcpyAsync(out, stage, sizeof(double) * cells, hipMemcpyDeviceToHost, c->stream));
+      SBX_TRY(launch_convert_out<float>((const float*)g, stage, cells, c->stream));
+    SBX_HIP(hipMemcpyAsync(host, stage, sizeof(double) * cells, hipMemcpyDeviceToHost, c->stream));
     SBX_HIP(hipStreamSynchronize(c->stream));
+    return SBX_OK;
+  };
+  auto run = [&]() -> sbx_status {
+    SBX_TRY(fetch(src, out));
+    if (src2) {
+      add.resize(cells);
+      SBX_TRY(fetch(src2, add.data()));
+      for (size_t i = 0; i < cells; ++i) out[i] += add[i];
+    }
     return SBX_OK;
   };
   const sbx_status rc = run();

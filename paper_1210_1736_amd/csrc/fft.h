@@ -29,6 +29,7 @@ namespace sbx {
 template <typename T>
 struct SolveDesc {
   const T* rho;   // N^3 cell masses
+  const T* rho2;  // null, or N^3 cell masses added to rho (the summed grids)
   T* phi;         // N^3 output (may alias rho)
   C2<T>* X;       // (N+1) * N * N, also E: N * N rows of N + kEPad
   C2<T>* C;       // (N+1) * 2N * N

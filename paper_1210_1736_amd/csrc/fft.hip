@@ -311,13 +311,23 @@ __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T
   for (int u = 0; u < K::ROUNDS; ++u) {
     const int j = u * K::WT + tid / TL;
     if (j < WL) {
-      const T* __restrict__ a = d.rho + ((size_t)z * N + y0 + 2 * j) * N;
+      const size_t row = ((size_t)z * N + y0 + 2 * j) * N;
+      const T* __restrict__ a = d.rho + row;
       const T* __restrict__ b = a + N;
       constexpr int VPT = Line<T, L>::VPT;
       C2<T> v[VPT];
 #pragma unroll
       for (int r = 0; r < VPT; ++r)
         v[r] = r < VPT / 2 ? C2<T>{a[t + r * TL], b[t + r * TL]} : C2<T>{(T)0, (T)0};
+      if (d.rho2) {  // summed grids: the second source is added on the way in
+        const T* __restrict__ a2 = d.rho2 + row;
+        const T* __restrict__ b2 = a2 + N;
+#pragma unroll
+        for (int r = 0; r < VPT / 2; ++r) {
+          v[r].re += a2[t + r * TL];
+          v[r].im += b2[t + r * TL];
+        }
+      }
       fwd_from<T, L, 0, true>(s + j * P, t, v, tw);
     }
   }
@@ -692,6 +702,8 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
   const int bpcs[4] = {2, 4, 8, 0};  // 0: one block per tile
   for (int i = 0; i < count; ++i) {
     SBX_HIP(hipMemsetAsync((void*)host[i].rho, 0, sizeof(T) * (size_t)N * N * N, st));
+    if (host[i].rho2)
+      SBX_HIP(hipMemsetAsync((void*)host[i].rho2, 0, sizeof(T) * (size_t)N * N * N, st));
     SBX_HIP(hipMemsetAsync(host[i].X, 0, sizeof(C2<T>) * x_elems(N), st));
     SBX_HIP(hipMemsetAsync(host[i].C, 0, sizeof(C2<T>) * c_elems(N), st));
     SBX_HIP(hipMemsetAsync(host[i].D, 0, sizeof(C2<T>) * c_elems(N), st));

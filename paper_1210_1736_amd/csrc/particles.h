@@ -12,7 +12,10 @@
 namespace sbx {
 
 constexpr int kMaxGal = 4;       // galaxies per instance
-constexpr int kSlots = 5;        // grids per 3-level galaxy
+constexpr int kSlots = 7;        // grids per 3-level galaxy (5 fields + 2 mass-only)
+constexpr int kFieldSlots = 5;   // solved grids per 3-level galaxy
+constexpr int kSlotG2 = 5;       // grid 2 masses (core, middle level)
+constexpr int kSlotG4 = 6;       // grid 4 masses (core and ring, global level)
 constexpr int kNComp = 8;        // particle component ids
 constexpr int kMaxInst = 32;     // instances per launch
 // diagnostics record: per component [ekin, epot, Lx, Ly, Lz, count],
@@ -69,9 +72,12 @@ struct PartDev {
 
 // Grid slots of one galaxy: 3 levels -> 0: grid 1 (inner, core),
 // 1: grid 3 (middle, ring), 2: grids 2+3 (middle, core+ring), 3: grid 5
-// (global, outer), 4: grids 4+5 (global, all).  1 level -> slot 0 only.
-// With merge5: slot 3 of galaxy 0 holds grid 5 of all galaxies summed, slot 3
-// of the others is unused, and slot 4 holds grid 4 alone.
+// (global, outer), 4: grids 4+5 (global, all), 5: grid 2 masses, 6: grid 4
+// masses.  Particles deposit into 0, 1, 3, 5 and 6 (each mass once); the
+// solves of slots 2 and 4 read 5 + 1 and 6 + 3 and write their fields into
+// slots 2 and 4.  1 level -> slot 0 only.  With merge5: slot 3 of galaxy 0
+// holds grid 5 of all galaxies summed, slot 3 of the others is unused, and
+// slot 4 is the field of grid 4 alone.
 template <typename T>
 struct GridsDev {
   T* g[kMaxGal][kSlots];

@@ -694,11 +694,11 @@ __global__ void __launch_bounds__(256)
 // probes go straight to global memory).
 //
 // Sources of the five grids (Sec. 2.1): core -> grid 1, grid 2, grid 4;
-// ring -> grid 3, grid 4; outer -> grid 5.  Grids 2+3 and 4+5 are assigned
-// as sums directly (their potentials are only used summed, and the solve is
-// linear), so a ring particle adds to slots 1 and 2 of its middle cell and
-// an outer particle to slots 3 and 4 of its global cell (with merge5: to
-// galaxy 0's slot 3 only, the summed grid 5 of all galaxies).
+// ring -> grid 3, grid 4; outer -> grid 5.  The potentials of grids 2 and 4
+// are only used summed with those of grids 3 and 5, and the solve is linear,
+// so only the sums 2+3 and 4+5 are solved; every mass is assigned once, to
+// its own grid, and the solves of the summed grids add their two sources as
+// they read them (see the slot layout in particles.h).
 constexpr int kDepTableBits = 11;
 constexpr int kDepTable = 1 << kDepTableBits;  // LDS hash entries
 constexpr int kDepProbes = 8;
@@ -756,9 +756,9 @@ __global__ void __launch_bounds__(256)
     const int g = gn;
     const T xs = xn, ys = yn, zs = zn, ms = mn;
     if (j + 1 < kDepChunk / 256) fetch(base + (j + 1) * 256 + threadIdx.x, okn, gn, xn, yn, zn, mn);
-    // fine: key on the finest level, fine2: the same cell in the summed slot
-    // (ring and outer), or kNoKey; coarse keys c1, c2 go through the table
-    uint32_t fine = kNoKey, fine2 = kNoKey, c1 = kNoKey, c2 = kNoKey;
+    // fine: key on the finest level, or kNoKey; coarse keys c1, c2 go
+    // through the table
+    uint32_t fine = kNoKey, c1 = kNoKey, c2 = kNoKey;
     T m = (T)0;
     if (ok) {
       const HierDev& h = sys.h[g];
@@ -769,29 +769,20 @@ __global__ void __launch_bounds__(256)
       if (h.n_levels == 1) {
         if (c.cls == SBX_OUTER) fine = dep_key(g, 0, h.lv[0], c.idx[0]);
       } else if (c.cls == SBX_CORE) {
-        fine = dep_key(g, 0, h.lv[0], c.idx[0]);  // grid 1
-        c1 = dep_key(g, 2, h.lv[1], c.idx[1]);    // grid 2 (in 2+3)
-        c2 = dep_key(g, 4, h.lv[2], c.idx[2]);    // grid 4 (in 4+5)
+        fine = dep_key(g, 0, h.lv[0], c.idx[0]);        // grid 1
+        c1 = dep_key(g, kSlotG2, h.lv[1], c.idx[1]);    // grid 2
+        c2 = dep_key(g, kSlotG4, h.lv[2], c.idx[2]);    // grid 4
       } else if (c.cls == SBX_RING) {
-        fine = dep_key(g, 1, h.lv[1], c.idx[1]);  // grid 3
-        fine2 = dep_key(g, 2, h.lv[1], c.idx[1]); // grid 3 (in 2+3)
-        c2 = dep_key(g, 4, h.lv[2], c.idx[2]);    // grid 4 (in 4+5)
+        fine = dep_key(g, 1, h.lv[1], c.idx[1]);        // grid 3
+        c2 = dep_key(g, kSlotG4, h.lv[2], c.idx[2]);    // grid 4
       } else if (c.cls == SBX_OUTER) {
-        if (sys.merge5) {
-          fine = dep_key(0, 3, h.lv[2], c.idx[2]);  // summed grid 5 of all galaxies
-        } else {
-          fine = dep_key(g, 3, h.lv[2], c.idx[2]);  // grid 5
-          fine2 = dep_key(g, 4, h.lv[2], c.idx[2]); // grid 5 (in 4+5)
-        }
+        fine = dep_key(sys.merge5 ? 0 : g, 3, h.lv[2], c.idx[2]);  // grid 5 (summed if merged)
       }
     }
     {
       bool tail;
       const T s = wave_run_sum(fine, m, tail);
-      if (tail && fine != kNoKey) {
-        atomic_add_g(glb(slot_ptr(G, fine)), s);
-        if (fine2 != kNoKey) atomic_add_g(glb(slot_ptr(G, fine2)), s);
-      }
+      if (tail && fine != kNoKey) atomic_add_g(glb(slot_ptr(G, fine)), s);
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {

@@ -74,6 +74,7 @@ sbx_status poisson_solve_t(sbx_poisson* p, int batch, const void* rho, void* phi
         std::vector<SolveDesc<T>> d(nb);
         for (int i = 0; i < nb; ++i) {
           d[i].rho = rr + cells * i;
+          d[i].rho2 = nullptr;
           d[i].phi = ff + cells * i;
           d[i].X = (C2<T>*)p->X + x_elems(p->N) * i;
           d[i].C = (C2<T>*)p->C + cd_elems(p->N) * i;
