@@ -1,0 +1,87 @@
+"""GPU parity at the full sizes of the benchmark workloads beyond the disc
+galaxy: the galaxy plus satellite (two 3-level 128^3 hierarchies, 8.7M
+particles) and the ensemble of 16 uneven instances stepped as one batch.
+
+Bars as in test_gpu_parity (FP32 form against the FP64 oracle on the same
+FP32-rounded inputs): forces 99th percentile within 1e-4 and max within 1e-3
+of the rms force; classes and cells bit-exact; after one step velocities
+within 1e-4 of the rms velocity (99th percentile), positions within 1e-4,
+loss flags exact.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pm_oracle as O
+from tests import common as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sbx():
+    from paper_1210_1736_amd import sbx as m
+    return m
+
+
+def _rng(k):
+    return np.random.default_rng(np.random.SeedSequence([1210, 1736, 900, k]))
+
+
+@pytest.mark.parametrize("merge", [0, 1])
+def test_galaxy_satellite_full_size_sampled(sbx, merge):
+    w = synth.galaxy_satellite(scale=1.0)
+    sysm = T.oracle_system(w)
+    x, v, m = T.oracle_inputs(w, sbx.SBX_FP32)
+    lost = sysm.lost_now(x)
+    centres = sysm.centres(x, m, w.gal, lost)
+    pots = sysm.potentials(x, m, w.gal, lost, centres)
+    ctx = sbx.Context(prec=sbx.SBX_FP32, G=w.G)
+    ctx.sbx_set_outer_merge(merge)
+    ctx.sbx_build_grids([T.sbx_hier(h) for h in w.hier])
+    ctx.sbx_load_particles(w.x, w.v, w.m, w.comp, w.gal)
+    acc, _ = ctx.sbx_compute_forces()
+    rng = _rng(merge)
+    live = ~lost
+    s = np.concatenate([rng.choice(np.flatnonzero(live & (w.gal == g)), 10000, replace=False)
+                        for g in range(2)])
+    a_ref, _ = sysm.field_at(x[s], centres, pots)
+    e = T.rel_err_vec(acc[s], a_ref)
+    print(f"FP32 galaxy+satellite (merge {merge}) force error: p99 {np.percentile(e, 99):.2e} "
+          f"max {e.max():.2e} of rms")
+    assert np.percentile(e, 99) < 1e-4 and e.max() < 1e-3
+    cg = ctx.sbx_get_centres()
+    for g in range(2):
+        assert np.allclose(cg[g], centres[g], rtol=0, atol=1e-12 * (1 + np.abs(centres[g]).max()))
+        cls_ref, idx_ref = O.classify(x[s], sysm.h[g], centres[g])
+        for level in range(3):
+            idx, cls = ctx.sbx_get_indices(g, level)
+            assert np.array_equal(cls[s], cls_ref), (g, level)
+            assert np.array_equal(idx[s].astype(np.int64), idx_ref[level]), (g, level)
+
+
+def test_ensemble_full_size_batch_step(sbx):
+    """All 16 instances in one batch, one step (cell sort included); the two
+    smallest-grid instances are checked against the oracle's step."""
+    ws = synth.ensemble()
+    ctxs = [T.make_ctx(w, sbx.SBX_FP32) for w in ws]
+    b = sbx.Batch(ctxs)
+    b.sbx_batch_step(0.01, 1)
+    b.sbx_batch_sync()
+    b.close()
+    order = sorted(range(len(ws)), key=lambda i: (ws[i].hier[0].levels[0].N, ws[i].n))
+    for i in order[:2]:
+        w = ws[i]
+        sysm = T.oracle_system(w)
+        x, v, m = T.oracle_inputs(w, sbx.SBX_FP32)
+        lost = np.zeros(w.n, bool)
+        x, v, lost, _ = sysm.step(x, v, m, w.gal, lost, 0.01)
+        xg, vg, lg = ctxs[i].sbx_get_particles()
+        assert np.array_equal(lg, lost), w.name
+        vr = np.sqrt(np.mean(np.sum(v * v, axis=1)))
+        ev = np.linalg.norm(vg - v, axis=1) / vr
+        print(f"{w.name}: n {w.n}, velocity error p99 {np.percentile(ev, 99):.2e} max {ev.max():.2e}")
+        assert np.percentile(ev, 99) < 1e-4, w.name
+        assert np.max(np.abs(xg - x)) < 1e-4, w.name
+    for c in ctxs:
+        c.close()
