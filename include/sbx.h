@@ -154,6 +154,8 @@ sbx_status sbx_load_particles_device(sbx_ctx* ctx, int64_t n, const double* x, c
  * (2N)^3 by Eq. 5, transformed by an FP64 FFT, scaled by G/(2N)^3 and stored
  * on (N+1)^3 (it is real and even per axis).  Allocates the grids. */
 sbx_status sbx_build_grids(sbx_ctx* ctx, int32_t n_galaxies, const sbx_hierarchy* h);
+/* (1 <= n_galaxies <= 8; every galaxy's grids are solved and summed into the
+ * forces of all particles, Sec. 2.1: the number of galaxies is not fixed.) */
 
 /* One field solve at the current positions, no motion: loss test, centres,
  * mass assignment, the isolated solves, Eq. 8 with the grid-selection rule.

@@ -43,7 +43,7 @@ bool same_level(const sbx_level& a, const sbx_level& b) {
 
 sbx_status validate(int ng, const sbx_hierarchy* h) {
   if (!h || ng < 1 || ng > kMaxGal) {
-    set_error("1 to 4 galaxies required");
+    set_error("1 to 8 galaxies required");
     return SBX_EINVAL;
   }
   const int N0 = h[0].lv[0].n;
@@ -822,7 +822,7 @@ sbx_status load_impl(sbx_ctx* c, int64_t n, const double* x, const double* v, co
           return SBX_EINVAL;
         }
       if (comp[i] < 0 || comp[i] >= kNComp || gal[i] < 0 || gal[i] >= kMaxGal) {
-        set_error("component id in 0..7 and galaxy id in 0..3 required");
+        set_error("component id in 0..7 and galaxy id in 0..7 required");
         return SBX_EINVAL;
       }
       if (c->built && gal[i] >= c->ngal) {

@@ -11,7 +11,7 @@
 
 namespace sbx {
 
-constexpr int kMaxGal = 4;       // galaxies per instance
+constexpr int kMaxGal = 8;       // galaxies per instance
 constexpr int kSlots = 7;        // grids per 3-level galaxy (5 fields + 2 mass-only)
 constexpr int kFieldSlots = 5;   // solved grids per 3-level galaxy
 constexpr int kSlotG2 = 5;       // grid 2 masses (core, middle level)
