@@ -355,7 +355,7 @@ sbx_status build_grids_t(sbx_ctx* c) {
   c->nsolves = (int)descs.size();
   if constexpr (sizeof(T) == 8) SBX_TRY(plan_create<T>(c->plan64, descs.data(), (int)descs.size(), c->stream));
   else SBX_TRY(plan_create<T>(c->plan32, descs.data(), (int)descs.size(), c->stream));
-  // counting-sort bins (cells, or pairs of cells per axis, of every level)
+  // counting-sort bins (the cells of every level of every galaxy)
   c->bins = sort_bins(c->sys);
   SBX_TRY(dev_alloc((void**)&c->count, sizeof(uint32_t) * (c->bins + 1)));
   SBX_TRY(dev_alloc((void**)&c->scan_tmp, sizeof(uint32_t) * scan_tmp_elems(c->bins + 1)));

@@ -113,14 +113,12 @@ struct InstDev {
 constexpr int kDmAux = kMaxGal + 2 * kMaxGal * kArgParts;
 
 // Counting-sort bins.  A particle's bin is the cell of its finest grid
-// relative to its own galaxy, coarsened by sort_group cells per axis; bins
-// are ordered by galaxy, level, z, y, x, and the last bin holds the lost
-// particles.  (Coarser bins make runs of equal keys longer but cost the
-// deposit more than they save in the sort, so every level uses single
-// cells.)
-__host__ __device__ inline int sort_group(const HierDev&, int) { return 1; }
+// relative to its own galaxy; bins are ordered by galaxy, level, z, y, x,
+// and the last bin holds the lost particles.  (Coarser bins shorten the sort
+// but change the order the deposit sees, which costs it more than the sort
+// saves.)
 __host__ __device__ inline size_t level_bins(const HierDev& h, int lev) {
-  const size_t n = (size_t)(h.lv[lev].N / sort_group(h, lev));
+  const size_t n = (size_t)h.lv[lev].N;
   return n * n * n;
 }
 __host__ __device__ inline size_t bins_before(const SysDev& s, int g, int lev) {

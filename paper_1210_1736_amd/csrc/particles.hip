@@ -1006,7 +1006,7 @@ __global__ void __launch_bounds__(256) k_diag_final(const InstDev<T>* __restrict
 }
 
 // ------------------------------------------------------------ cell sort ---
-// Key: the sort bin of the particle (see sort_group in particles.h).
+// Key: the sort bin of the particle (see level_bins in particles.h).
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_sort_key(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
@@ -1032,11 +1032,9 @@ __global__ void __launch_bounds__(256)
       classify(h, cen + 3 * g, (double)X0[i], (double)X1[i], (double)X2[i], c);
       if (c.cls != SBX_LOST) {
         const int lev = h.n_levels == 1 ? 0 : c.cls;
-        const int gr = sort_group(h, lev);
-        const int n = h.lv[lev].N / gr;
+        const size_t n = (size_t)h.lv[lev].N;
         const int* id = lev == 0 ? c.idx[0] : (lev == 1 ? c.idx[1] : c.idx[2]);
-        k = (uint32_t)(bins_before(sys, g, lev) +
-                       (((size_t)(id[2] / gr) * n + id[1] / gr) * n + id[0] / gr));
+        k = (uint32_t)(bins_before(sys, g, lev) + ((id[2] * n + id[1]) * n + id[0]));
       }
     }
     I.key[i] = k;
