@@ -193,7 +193,7 @@ InstDev<T> inst_of(const sbx_ctx* c) {
   I.acc = c->acc;
   I.pot = c->pot;
   I.grid_block = (T*)c->grid_block;
-  I.grid_elems = c->grid_elems;
+  I.grid_elems = c->mass_elems;
   I.key = c->key;
   I.count = c->count;
   I.part_base = 0;
@@ -285,6 +285,7 @@ void free_grids(sbx_ctx* c) {
   free_ptr(c->C);
   std::memset(c->grid, 0, sizeof(c->grid));
   c->grid_elems = 0;
+  c->mass_elems = 0;
   c->built = false;
   c->solved = false;
 }
@@ -307,9 +308,16 @@ sbx_status build_grids_t(sbx_ctx* c) {
   c->nsolves = total;
   c->grid_elems = cells * total;
   SBX_TRY(dev_alloc(&c->grid_block, sizeof(T) * c->grid_elems));
+  // the slots that receive masses first (they are cleared every step), then
+  // the two that only ever hold fields of summed grids (2 and 4)
   int s = 0;
   for (int g = 0; g < c->ngal; ++g)
-    for (int k = 0; k < c->nslots[g]; ++k) c->grid[g][k] = (T*)c->grid_block + cells * (s++);
+    for (int k = 0; k < c->nslots[g]; ++k)
+      if (c->nslots[g] == 1 || (k != 2 && k != 4)) c->grid[g][k] = (T*)c->grid_block + cells * (s++);
+  c->mass_elems = cells * s;
+  for (int g = 0; g < c->ngal; ++g)
+    if (c->nslots[g] > 1)
+      for (int k : {2, 4}) c->grid[g][k] = (T*)c->grid_block + cells * (s++);
   // Green's tables, one per distinct level geometry
   for (int g = 0; g < c->ngal; ++g)
     for (int lv = 0; lv < c->hh[g].n_levels; ++lv) {

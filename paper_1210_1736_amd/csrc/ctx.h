@@ -65,6 +65,7 @@ struct sbx_ctx {
   int slot_level[sbx::kMaxGal][sbx::kSlots] = {};
   void* grid_block = nullptr;  // all grids back to back
   size_t grid_elems = 0;
+  size_t mass_elems = 0;       // the leading part of the block that takes masses
   void* grid[sbx::kMaxGal][sbx::kSlots] = {};
   std::vector<sbx::Green> greens;
   void* X = nullptr;
@@ -146,6 +147,6 @@ InstDev<T> inst_of(const sbx_ctx* c);
 // Upload the context's instance record (synchronises the context stream).
 sbx_status upload_inst(sbx_ctx* c);
 
-inline InstInfo info_of(const sbx_ctx* c) { return InstInfo{c->n, c->grid_elems, c->dm_elems}; }
+inline InstInfo info_of(const sbx_ctx* c) { return InstInfo{c->n, c->mass_elems, c->dm_elems}; }
 
 }  // namespace sbx

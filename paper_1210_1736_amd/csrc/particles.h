@@ -89,14 +89,14 @@ struct InstDev {
   SysDev sys;
   GridsDev<T> G;
   double* centres;          // 3 * kMaxGal
-  double* com_partial;      // force_blocks(n) rows of kPreVals
-  double* pre_partial;      // kRedBlocks rows of kPreVals, then kPreVals sums
+  double* com_partial;      // kPreVals columns of kForceBlocksMax block rows (column-major)
+  double* pre_partial;      // kPreVals columns of kRedBlocks block rows (column-major)
   double* diag_partial;     // force_blocks(n) rows of kNDiag
   double* diag_out;         // kNDiag: where the next diagnostics record goes
   double* acc;              // n * 3 (write mode)
   double* pot;              // n (write mode, physical potential)
   T* grid_block;            // all grids of the instance, back to back
-  size_t grid_elems;
+  size_t grid_elems;        // the leading grids that take masses (cleared per step)
   uint32_t* key;            // n
   uint32_t* count;          // bins + 1: this instance's slice of the shared counts
   uint32_t part_base;       // sort position of the instance's first particle
@@ -105,7 +105,7 @@ struct InstDev {
   size_t dm_elems;
   unsigned long long* dm_aux;   // [g] densest cell of galaxy g (all ones: none), then
                                 // kMaxGal * kArgParts (value, index) partials
-  double* dm_partial;           // kRedBlocks rows of kPreVals: block mass sums
+  double* dm_partial;           // as pre_partial: block sums around the densest cell
   const unsigned long long* dm_mmax;  // bits of the largest particle mass (set at load)
   double dt;
   int64_t n;
@@ -134,7 +134,7 @@ __host__ __device__ inline size_t sort_bins(const SysDev& s) { return bins_befor
 // Host-side facts the launchers need to shape a multi-instance grid.
 struct InstInfo {
   int64_t n;
-  size_t grid_elems;
+  size_t grid_elems;  // grid elements cleared per step
   size_t dm_elems;  // density-maximum histogram (0: no galaxy uses it)
 };
 

@@ -111,10 +111,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum vals[0..nv) over the block (256 threads) in a fixed order; thread k
-// writes total k to out[k].
+// writes total k to out[k * stride].
 // Only the first nv (<= NV) values are reduced; the rest are written as 0.
 template <int NV>
-__device__ __forceinline__ void block_sum_store(const double* vals, double* out, int nv = NV) {
+__device__ __forceinline__ void block_sum_store(const double* vals, double* out, int nv = NV,
+                                                int stride = 1) {
   __shared__ double red[4][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -126,7 +127,7 @@ __device__ __forceinline__ void block_sum_store(const double* vals, double* out,
   }
   __syncthreads();
   for (int k = threadIdx.x; k < NV; k += blockDim.x)
-    out[k] = k < nv ? ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k] : 0.0;
+    out[(size_t)k * stride] = k < nv ? ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k] : 0.0;
 }
 
 
@@ -414,7 +415,7 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  block_sum_store<kPreVals>(acc, I.pre_partial + (size_t)lb * kPreVals, 4 * sys.ngal);
+  block_sum_store<kPreVals>(acc, I.pre_partial + lb, 4 * sys.ngal, kRedBlocks);
 }
 
 // Sum of rows values (fixed order) into out[0]; one block of 256 threads.
@@ -432,33 +433,58 @@ __global__ void __launch_bounds__(256) k_reduce_one(const double* __restrict__ p
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
-// One block per instance: column sums of the partial rows (fixed order:
-// strided per thread, then a fixed tree), then the centres.  Galaxies centred
-// on their density maximum take their sums from dm_partial when `density`
-// is set and keep their current centre otherwise.
+// One block per instance: column sums of the partial rows, then the
+// centres.  The partials are stored column by column (value v of block row
+// r at v * rows_max + r), so each column is one contiguous run: per galaxy
+// the threads load eight rows of its four columns per round (32 loads in
+// flight; one block is all the kernel has, so it is bound by these round
+// trips), then the block reduces each column in a fixed order (wavefront
+// butterfly, then the four waves in order).  Galaxies
+// centred on their density maximum take their sums from dm_partial when
+// `density` is set and keep their current centre otherwise.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_centres(const InstDev<T>* __restrict__ inst, int from_com, int density) {
-  __shared__ double red[256];
+  __shared__ double red[4][kPreVals];
   __shared__ double sums[kPreVals];
   const InstDev<T>& I = inst[blockIdx.x];
-  const int nv = 4 * I.sys.ngal;
-  for (int v = 0; v < nv; ++v) {
-    const bool dm = I.sys.h[v / 4].centring == SBX_CENTRE_DENSITY;
-    if (dm && !(density && I.dm_partial)) continue;
-    const double* part = dm ? I.dm_partial : (from_com ? I.com_partial : I.pre_partial);
-    const int rows = (from_com && !dm) ? force_blocks_dev(I.n) : kRedBlocks;
-    double s = 0.0;
-    for (int r = threadIdx.x; r < rows; r += 256) s += part[(size_t)r * kPreVals + v];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool dm_on = density && I.dm_partial;
+  for (int g = 0; g < I.sys.ngal; ++g) {
+    const bool dm = I.sys.h[g].centring == SBX_CENTRE_DENSITY;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!dm || dm_on) {
+      const bool com = from_com && !dm;
+      const size_t cs = com ? kForceBlocksMax : kRedBlocks;  // column stride
+      const double* col = (dm ? I.dm_partial : (com ? I.com_partial : I.pre_partial)) + 4 * g * cs;
+      const int rows = com ? force_blocks_dev(I.n) : kRedBlocks;
+      // the galaxy's four columns, eight rows each per round, loads together
+      for (int r0 = threadIdx.x; r0 < rows; r0 += 8 * 256) {
+        double x[4][8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int r = r0 + u * 256;
+            x[k][u] = r < rows ? col[k * cs + r] : 0.0;
+          }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          a[k] += ((x[k][0] + x[k][1]) + (x[k][2] + x[k][3])) + ((x[k][4] + x[k][5]) + (x[k][6] + x[k][7]));
+      }
     }
-    if (threadIdx.x == 0) sums[v] = red[0];
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double w = wave_sum(a[k]);
+      if (lane == 0) red[wave][4 * g + k] = w;
+    }
   }
+  __syncthreads();
+  if ((int)threadIdx.x < 4 * I.sys.ngal) {
+    const int v = threadIdx.x;
+    sums[v] = ((red[0][v] + red[1][v]) + red[2][v]) + red[3][v];
+  }
+  __syncthreads();
   if ((int)threadIdx.x < I.sys.ngal) {
     const int g = threadIdx.x;
     const HierDev& h = I.sys.h[g];
@@ -469,7 +495,7 @@ __global__ void __launch_bounds__(256)
       c[1] = I.centres[3 * g + 1];
       c[2] = I.centres[3 * g + 2];
     }
-    if ((h.centring == SBX_CENTRE_COM || (dm && density && I.dm_partial)) && sums[4 * g] > 0.0) {
+    if ((h.centring == SBX_CENTRE_COM || (dm && dm_on)) && sums[4 * g] > 0.0) {
       c[0] = sums[4 * g + 1] / sums[4 * g];
       c[1] = sums[4 * g + 2] / sums[4 * g];
       c[2] = sums[4 * g + 3] / sums[4 * g];
@@ -678,7 +704,7 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  block_sum_store<kPreVals>(acc, I.dm_partial + (size_t)lb * kPreVals, 4 * sys.ngal);
+  block_sum_store<kPreVals>(acc, I.dm_partial + lb, 4 * sys.ngal, kRedBlocks);
 }
 
 // ---------------------------------------------------------- mass deposit --
@@ -981,9 +1007,9 @@ __global__ void __launch_bounds__(256)
   }
   if constexpr (MOVE) {
     __syncthreads();
-    double* out = I.com_partial + (size_t)lb * kPreVals;
-    for (int k = threadIdx.x; k < kPreVals; k += 256)
-      out[k] = k < 4 * sys.ngal ? ((wcom[0][k] + wcom[1][k]) + wcom[2][k]) + wcom[3][k] : 0.0;
+    double* out = I.com_partial + lb;
+    for (int k = threadIdx.x; k < 4 * sys.ngal; k += 256)
+      out[(size_t)k * kForceBlocksMax] = ((wcom[0][k] + wcom[1][k]) + wcom[2][k]) + wcom[3][k];
   }
 }
 
@@ -995,7 +1021,16 @@ __global__ void __launch_bounds__(256) k_diag_final(const InstDev<T>* __restrict
   const int v = blockIdx.x;
   const int rows = force_blocks_dev(I.n);
   double s = 0.0;
-  for (int r = threadIdx.x; r < rows; r += 256) s += I.diag_partial[(size_t)r * kNDiag + v];
+  // four rows per round with their loads issued together
+  for (int r0 = threadIdx.x; r0 < rows; r0 += 4 * 256) {
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * 256;
+      x[u] = r < rows ? I.diag_partial[(size_t)r * kNDiag + v] : 0.0;
+    }
+    s += ((x[0] + x[1]) + x[2]) + x[3];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
