@@ -137,8 +137,6 @@ def timed_steps(sbx, torch, w, prec, steps, warmup, diag_every, profile=True, so
     ctx.sbx_step(w.dt, warmup, diag_every)
     ctx.sbx_sync()
     live0 = ctx.sbx_count_live()
-    if profile:
-        ctx.sbx_profile_begin(64 * (steps + 2))
     torch.cuda.synchronize()
     ctx.sbx_sync()
     t0 = time.perf_counter()
@@ -146,8 +144,15 @@ def timed_steps(sbx, torch, w, prec, steps, warmup, diag_every, profile=True, so
     ctx.sbx_sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    phases = ctx.sbx_profile_end() if profile else {}
     live1 = ctx.sbx_count_live()
+    phases = {}
+    if profile:
+        # phase times from a second pass of the same length with an event
+        # after every phase (the events themselves cost time, so the timed
+        # pass above runs without them)
+        ctx.sbx_profile_begin(64 * (steps + 2))
+        ctx.sbx_step(w.dt, steps, diag_every)
+        phases = ctx.sbx_profile_end()
     ctx.close()
     return t1 - t0, 0.5 * (live0 + live1), phases
 
@@ -477,6 +482,8 @@ def main():
         "fp64": fp64,
         "solves": solves,
         "phases_ms_per_step": per_step,
+        "phases_note": "HIP events after every phase, from a second pass of the same steps "
+                       "(the timed pass runs without events)",
         "solves_in_step_per_s": nsolves / (1e-3 * sum(per_step.get(k, 0.0) for k in FFT_PASSES)),
         **extra,
         "step_effective_GBs": step_roof,

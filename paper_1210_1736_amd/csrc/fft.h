@@ -81,13 +81,15 @@ inline size_t h_elems(int N) { return (size_t)(N + 1) * (N + 1) * (N + 1); }
 template <typename T>
 sbx_status plan_create(SolvePlan<T>& plan, const SolveDesc<T>* descs, int n, hipStream_t s);
 
-// Run all solves of the plan (zeroes the work counters, five launches).
+// Run all solves of the plan (five launches; each pass clears the work
+// counter of the pass before it, so the counters are zero between runs).
 template <typename T>
 sbx_status plan_run(const SolvePlan<T>& plan, hipStream_t s, Recorder* rec = nullptr);
 
 // One pass (0..4) of one size group, for callers that schedule the groups
-// themselves (e.g. as concurrent branches of a graph).  The work counters are
-// zeroed by plan_run; callers of plan_run_pass zero p.d_counter themselves.
+// themselves (e.g. as concurrent branches of a graph).  Clears the work
+// counter of the previous pass of the group: run the passes of a group in
+// order 0..4, each after the one before it has finished.
 template <typename T>
 sbx_status plan_run_pass(const SolvePlan<T>& plan, int pass, int group, hipStream_t s);
 

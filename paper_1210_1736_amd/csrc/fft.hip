@@ -522,13 +522,16 @@ __device__ __forceinline__ void run_tile(const SolveDesc<T>& d, int tile, C2<T>*
 // Persistent pass over the solves of one grid size: work items are
 // (solve, tile) pairs; the first item of a block is its index, later ones
 // come from the counter until all are done.  With one block per item the
-// counter is never touched.
+// counter is never touched.  `reset` (may be null) is the counter of the
+// pass that ran before this one; it is cleared here for its next use, which
+// saves a launch per solve set.
 template <typename T, int PASS, int NT, int L>
 __global__ void __launch_bounds__(NT)
     k_pass(const SolveDesc<T>* __restrict__ solves, int tiles_per_solve, int total,
-           int* __restrict__ counter, const C2<T>* __restrict__ tw) {
+           int* __restrict__ counter, int* __restrict__ reset, const C2<T>* __restrict__ tw) {
   __shared__ C2<T> s[TC<T, L, NT, PASS>::LDS];
   __shared__ int item_sh;
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) *reset = 0;
   int next = blockIdx.x;
   for (;;) {
     const int item = next;
@@ -596,39 +599,39 @@ static bool shape_ok(int nt, int N, int pass) {
 
 template <typename T, int PASS, int NT>
 static void launch_nt(const SolveDesc<T>* solves, int N, int tps, int total, int grid, int* counter,
-                      const C2<T>* tw, hipStream_t st) {
+                      int* reset, const C2<T>* tw, hipStream_t st) {
   const dim3 g(grid), b(NT);
   switch (N) {
-    case 8: hipLaunchKernelGGL((k_pass<T, PASS, NT, 16>), g, b, 0, st, solves, tps, total, counter, tw); break;
-    case 16: hipLaunchKernelGGL((k_pass<T, PASS, NT, 32>), g, b, 0, st, solves, tps, total, counter, tw); break;
-    case 32: hipLaunchKernelGGL((k_pass<T, PASS, NT, 64>), g, b, 0, st, solves, tps, total, counter, tw); break;
-    case 64: hipLaunchKernelGGL((k_pass<T, PASS, NT, 128>), g, b, 0, st, solves, tps, total, counter, tw); break;
-    case 128: hipLaunchKernelGGL((k_pass<T, PASS, NT, 256>), g, b, 0, st, solves, tps, total, counter, tw); break;
-    default: hipLaunchKernelGGL((k_pass<T, PASS, NT, 512>), g, b, 0, st, solves, tps, total, counter, tw); break;
+    case 8: hipLaunchKernelGGL((k_pass<T, PASS, NT, 16>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
+    case 16: hipLaunchKernelGGL((k_pass<T, PASS, NT, 32>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
+    case 32: hipLaunchKernelGGL((k_pass<T, PASS, NT, 64>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
+    case 64: hipLaunchKernelGGL((k_pass<T, PASS, NT, 128>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
+    case 128: hipLaunchKernelGGL((k_pass<T, PASS, NT, 256>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
+    default: hipLaunchKernelGGL((k_pass<T, PASS, NT, 512>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
   }
 }
 
 template <typename T, int PASS>
 static void launch_pass(const SolveDesc<T>* solves, int N, int nsolves, PassShape sh, int* counter,
-                        const C2<T>* tw, hipStream_t st) {
+                        int* reset, const C2<T>* tw, hipStream_t st) {
   if (!shape_ok<T>(sh.nt, N, PASS)) sh.nt = 256;
   const int tps = tiles_nt<T>(sh.nt, N, PASS);
   const int total = tps * nsolves;
   const int grid = std::max(1, std::min(sh.grid <= 0 ? total : sh.grid, total));
-  if (sh.nt == 128) launch_nt<T, PASS, 128>(solves, N, tps, total, grid, counter, tw, st);
-  else if (sh.nt == 256) launch_nt<T, PASS, 256>(solves, N, tps, total, grid, counter, tw, st);
-  else launch_nt<T, PASS, 512>(solves, N, tps, total, grid, counter, tw, st);
+  if (sh.nt == 128) launch_nt<T, PASS, 128>(solves, N, tps, total, grid, counter, reset, tw, st);
+  else if (sh.nt == 256) launch_nt<T, PASS, 256>(solves, N, tps, total, grid, counter, reset, tw, st);
+  else launch_nt<T, PASS, 512>(solves, N, tps, total, grid, counter, reset, tw, st);
 }
 
 template <typename T>
 static void launch_any(int pass, const SolveDesc<T>* solves, int N, int nsolves, PassShape sh,
-                       int* counter, const C2<T>* tw, hipStream_t st) {
+                       int* counter, int* reset, const C2<T>* tw, hipStream_t st) {
   switch (pass) {
-    case 0: launch_pass<T, 0>(solves, N, nsolves, sh, counter, tw, st); break;
-    case 1: launch_pass<T, 1>(solves, N, nsolves, sh, counter, tw, st); break;
-    case 2: launch_pass<T, 2>(solves, N, nsolves, sh, counter, tw, st); break;
-    case 3: launch_pass<T, 3>(solves, N, nsolves, sh, counter, tw, st); break;
-    default: launch_pass<T, 4>(solves, N, nsolves, sh, counter, tw, st); break;
+    case 0: launch_pass<T, 0>(solves, N, nsolves, sh, counter, reset, tw, st); break;
+    case 1: launch_pass<T, 1>(solves, N, nsolves, sh, counter, reset, tw, st); break;
+    case 2: launch_pass<T, 2>(solves, N, nsolves, sh, counter, reset, tw, st); break;
+    case 3: launch_pass<T, 3>(solves, N, nsolves, sh, counter, reset, tw, st); break;
+    default: launch_pass<T, 4>(solves, N, nsolves, sh, counter, reset, tw, st); break;
   }
 }
 
@@ -722,7 +725,7 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
         for (int rep = 0; rep < 7; ++rep) {
           hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, 1);
           SBX_HIP(hipEventRecord(e0, st));
-          launch_any<T>(pass, d_solves, N, count, sh, counter, tw, st);
+          launch_any<T>(pass, d_solves, N, count, sh, counter, nullptr, tw, st);
           SBX_HIP(hipEventRecord(e1, st));
           SBX_HIP(hipEventSynchronize(e1));
           float ms = 0.f;
@@ -798,6 +801,8 @@ sbx_status plan_create(SolvePlan<T>& p, const SolveDesc<T>* descs, int n, hipStr
     }
     for (int q = 0; q < kPasses; ++q) g.shape[q] = a[q];
   }
+  // work counters start at zero; every pass then clears its predecessor's
+  SBX_HIP(hipMemsetAsync(p.d_counter, 0, sizeof(int) * kPasses * kMaxGroups, st));
   SBX_HIP(hipStreamSynchronize(st));
   return SBX_OK;
 }
@@ -806,7 +811,8 @@ template <typename T>
 sbx_status plan_run_pass(const SolvePlan<T>& p, int q, int group, hipStream_t st) {
   const SolveGroup& g = p.groups[group];
   launch_any<T>(q, p.d_solves + g.first, g.N, g.count, g.shape[q],
-                p.d_counter + q * kMaxGroups + group, (const C2<T>*)g.tw, st);
+                p.d_counter + q * kMaxGroups + group,
+                p.d_counter + ((q + kPasses - 1) % kPasses) * kMaxGroups + group, (const C2<T>*)g.tw, st);
   return SBX_OK;
 }
 
@@ -816,7 +822,6 @@ sbx_status plan_run(const SolvePlan<T>& p, hipStream_t st, Recorder* rec) {
   Recorder none;
   Recorder& r = rec ? *rec : none;
   static const int marks[kPasses] = {PH_FWD_X, PH_FWD_Y, PH_ZPASS, PH_INV_Y, PH_INV_X};
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, p.d_counter, kPasses * kMaxGroups);
   for (int q = 0; q < kPasses; ++q) {
     for (int gi = 0; gi < p.ngroups; ++gi) SBX_TRY(plan_run_pass<T>(p, q, gi, st));
     r.mark(marks[q], st);
