@@ -389,9 +389,13 @@ template <typename T>
 sbx_status field_solve_t(sbx_ctx* c) {
   const std::vector<InstInfo> info{info_of(c)};
   c->rec.mark(PH_START, c->stream);
-  SBX_TRY(launch_zero_grids<T>(dinst<T>(c), info, c->stream));
-  c->rec.mark(PH_ZERO, c->stream);
-  SBX_TRY(launch_centres<T>(dinst<T>(c), c->d_cur, info, c->com_fresh, c->stream));
+  if (c->com_fresh && c->dm_elems == 0) {
+    SBX_TRY(launch_zero_and_centres<T>(dinst<T>(c), info, c->stream));
+  } else {
+    SBX_TRY(launch_zero_grids<T>(dinst<T>(c), info, c->stream));
+    c->rec.mark(PH_ZERO, c->stream);
+    SBX_TRY(launch_centres<T>(dinst<T>(c), c->d_cur, info, c->com_fresh, c->stream));
+  }
   c->rec.mark(PH_PRE, c->stream);
   SBX_TRY(launch_deposit<T>(dinst<T>(c), c->d_cur, info, c->stream));
   c->rec.mark(PH_DEPOSIT, c->stream);

@@ -46,8 +46,14 @@ sbx_status record_step(sbx_batch* b, bool from_com, bool with_sort) {
   const InstDev<T>* inst = (const InstDev<T>*)b->d_inst;
   if (with_sort)
     SBX_TRY(launch_sort<T>(inst, b->d_cur, b->info, b->counts, b->total_counts, b->scan_tmp, b->stream));
-  SBX_TRY(launch_zero_grids<T>(inst, b->info, b->stream));
-  SBX_TRY(launch_centres<T>(inst, b->d_cur, b->info, from_com, b->stream));
+  bool any_dm = false;
+  for (const InstInfo& f : b->info) any_dm = any_dm || f.dm_elems > 0;
+  if (from_com && !any_dm) {
+    SBX_TRY(launch_zero_and_centres<T>(inst, b->info, b->stream));
+  } else {
+    SBX_TRY(launch_zero_grids<T>(inst, b->info, b->stream));
+    SBX_TRY(launch_centres<T>(inst, b->d_cur, b->info, from_com, b->stream));
+  }
   SBX_TRY(launch_deposit<T>(inst, b->d_cur, b->info, b->stream));
   SBX_TRY(plan_run<T>(bplan<T>(b), b->stream));
   SBX_TRY(launch_force<T>(inst, b->d_cur, b->info, 1, b->stream));

@@ -152,6 +152,13 @@ sbx_status launch_zero(T* p, size_t n, hipStream_t s);
 template <typename T>
 sbx_status launch_zero_grids(const InstDev<T>* inst, const std::vector<InstInfo>& info, hipStream_t s);
 
+// Zero the grids and compute the centres from the sums the last moving force
+// pass left in com_partial, in one launch (valid when no instance uses
+// density centring and the sums are current).
+template <typename T>
+sbx_status launch_zero_and_centres(const InstDev<T>* inst, const std::vector<InstInfo>& info,
+                                   hipStream_t s);
+
 // Loss test at the current positions and centre-of-mass sums (pre_partial),
 // then the centres; with from_com the centres come from the sums the last
 // moving force pass left in com_partial instead (no particle pass).

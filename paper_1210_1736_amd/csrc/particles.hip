@@ -443,11 +443,9 @@ __global__ void __launch_bounds__(256) k_reduce_one(const double* __restrict__ p
 // centred on their density maximum take their sums from dm_partial when
 // `density` is set and keep their current centre otherwise.
 template <typename T>
-__global__ void __launch_bounds__(256)
-    k_centres(const InstDev<T>* __restrict__ inst, int from_com, int density) {
+__device__ __forceinline__ void centres_of(const InstDev<T>& I, int from_com, int density) {
   __shared__ double red[4][kPreVals];
   __shared__ double sums[kPreVals];
-  const InstDev<T>& I = inst[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool dm_on = density && I.dm_partial;
   for (int g = 0; g < I.sys.ngal; ++g) {
@@ -504,6 +502,26 @@ __global__ void __launch_bounds__(256)
     I.centres[3 * g + 1] = c[1];
     I.centres[3 * g + 2] = c[2];
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_centres(const InstDev<T>* __restrict__ inst, int from_com, int density) {
+  centres_of(inst[blockIdx.x], from_com, density);
+}
+
+// The grid clearing of the next deposit and, in each instance's first
+// block, the centres from the sums the last moving force pass left (one
+// launch instead of two when no density centring needs the particles).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_zero_centres(const InstDev<T>* __restrict__ inst, Span sp) {
+  const int i = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[i], nb = sp.start[i + 1] - sp.start[i];
+  if (lb == 0) centres_of(inst[i], 1, 0);
+  T* g = inst[i].grid_block;
+  const size_t n = inst[i].grid_elems;
+  for (size_t k = (size_t)lb * 256 + threadIdx.x; k < n; k += (size_t)nb * 256) g[k] = (T)0;
 }
 
 // ------------------------------------------------ density-maximum centring --
@@ -1465,6 +1483,16 @@ sbx_status launch_zero_grids(const InstDev<T>* inst, const std::vector<InstInfo>
 }
 
 template <typename T>
+sbx_status launch_zero_and_centres(const InstDev<T>* inst, const std::vector<InstInfo>& info,
+                                   hipStream_t s) {
+  SBX_TRY(check_span(info));
+  const Span sp = make_span(info, blocks_grid);
+  hipLaunchKernelGGL((k_zero_centres<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, sp);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template <typename T>
 sbx_status launch_centres(const InstDev<T>* inst, const int* cur, const std::vector<InstInfo>& info,
                           bool from_com, hipStream_t s, bool density) {
   SBX_TRY(check_span(info));
@@ -1669,6 +1697,8 @@ sbx_status launch_join3(const T* x0, const T* x1, const T* x2, double* dst, int6
   template sbx_status launch_zero<T>(T*, size_t, hipStream_t);                                   \
   template sbx_status launch_zero_grids<T>(const InstDev<T>*, const std::vector<InstInfo>&,      \
                                            hipStream_t);                                         \
+  template sbx_status launch_zero_and_centres<T>(const InstDev<T>*, const std::vector<InstInfo>&, \
+                                                 hipStream_t);                                   \
   template sbx_status launch_centres<T>(const InstDev<T>*, const int*,                           \
                                         const std::vector<InstInfo>&, bool, hipStream_t, bool);  \
   template sbx_status launch_deposit<T>(const InstDev<T>*, const int*,                           \
