@@ -229,10 +229,9 @@ __device__ __forceinline__ Row3<double> row3(gp<const double> q) {
   return {v.x, v.y, q[1]};
 }
 
-template <typename T>
+template <bool TAYLOR, typename T>
 __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, const int* id,
-                                    double dx, double dy, double dz, int taylor, T* a, T& phi,
-                                    bool want_phi) {
+                                    double dx, double dy, double dz, T* a, T& phi, bool want_phi) {
   const ptrdiff_t sy = L.N, sz = (ptrdiff_t)L.N * L.N;
   const gp<const T> P = glb(F) + ((ptrdiff_t)id[2] * sz + (ptrdiff_t)id[1] * sy + id[0]);
   const T Dx = (T)(dx - ((double)id[0] - L.half) * L.l);
@@ -242,10 +241,13 @@ __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, 
   // the 19-point stencil as 5 rows of three along x and 4 single values
   const Row3<T> r00 = row3(P), rp0 = row3(P + sy), rm0 = row3(P - sy);
   const Row3<T> r0p = row3(P + sz), r0m = row3(P - sz);
+  // the yz diagonals are loaded with the rows (one round trip per field;
+  // every stencil point lies inside the grid for any usable cell)
+  const T dpp = P[sy + sz], dmp = P[-sy + sz], dmm = P[-sy - sz], dpm = P[sy - sz];
   const T p0 = r00.c, xp = r00.p, xm = r00.m;
   const T yp = rp0.c, ym = rm0.c, zp = r0p.c, zm = r0m.c;
   const T gx = (xp - xm) * i2l, gy = (yp - ym) * i2l, gz = (zp - zm) * i2lz;
-  if (!taylor) {
+  if constexpr (!TAYLOR) {
     a[0] += gx;
     a[1] += gy;
     a[2] += gz;
@@ -259,7 +261,7 @@ __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, 
   const T hzz = (zp + zm - (T)2 * p0) * ilz2;
   const T hxy = (rp0.p - rp0.m + rm0.m - rm0.p) * i4xy;
   const T hxz = (r0p.p - r0p.m + r0m.m - r0m.p) * i4xz;
-  const T hyz = (P[sy + sz] - P[-sy + sz] + P[-sy - sz] - P[sy - sz]) * i4xz;
+  const T hyz = (dpp - dmp + dmm - dpm) * i4xz;
   a[0] += gx + hxx * Dx + hxy * Dy + hxz * Dz;
   a[1] += gy + hyy * Dy + hxy * Dx + hyz * Dz;
   a[2] += gz + hzz * Dz + hxz * Dx + hyz * Dy;
@@ -267,13 +269,16 @@ __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, 
     phi += p0 + gx * Dx + gy * Dy + gz * Dz +
            (T)0.5 * (hxx * Dx * Dx + hyy * Dy * Dy + hzz * Dz * Dz) + hxy * Dx * Dy +
            hxz * Dx * Dz + hyz * Dy * Dz;
+  // one field's stencil in registers at a time: gathering the next field's
+  // ahead of this arithmetic costs more in occupancy than it hides
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // Sum over galaxies of the fields the grid-selection rule gives each class:
 // core -> grid 1 + grid 3 + grid 5, ring -> (2 + 3) + grid 5, outer -> (4 + 5).
 // With merge5 every class's grid 5 term is the shared summed grid 5, read
 // once per particle (Sec. 2.1: each class's sum contains grid 5).
-template <typename T>
+template <bool TAYLOR, typename T>
 __device__ __forceinline__ void particle_field(const SysDev& sys, const double* centres,
                                                const GridsDev<T>& F, double x, double y,
                                                double z, T* a, T& phi, bool want_phi) {
@@ -287,22 +292,22 @@ __device__ __forceinline__ void particle_field(const SysDev& sys, const double* 
     classify(h, c, x, y, z, cl);
     const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
     if (h.n_levels == 1) {
-      if (cl.cls == SBX_OUTER) eq8(F.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, sys.taylor, a, phi, want_phi);
+      if (cl.cls == SBX_OUTER) eq8<TAYLOR>(F.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, a, phi, want_phi);
       continue;
     }
     const double ox = x - h.outer_c[0], oy = y - h.outer_c[1], oz = z - h.outer_c[2];
     switch (cl.cls) {
       case SBX_CORE:
-        eq8(F.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, sys.taylor, a, phi, want_phi);
-        eq8(F.g[g][1], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, a, phi, want_phi);
-        if (!m5) eq8(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
+        eq8<TAYLOR>(F.g[g][0], h.lv[0], cl.idx[0], dx, dy, dz, a, phi, want_phi);
+        eq8<TAYLOR>(F.g[g][1], h.lv[1], cl.idx[1], dx, dy, dz, a, phi, want_phi);
+        if (!m5) eq8<TAYLOR>(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, a, phi, want_phi);
         break;
       case SBX_RING:
-        eq8(F.g[g][2], h.lv[1], cl.idx[1], dx, dy, dz, sys.taylor, a, phi, want_phi);
-        if (!m5) eq8(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
+        eq8<TAYLOR>(F.g[g][2], h.lv[1], cl.idx[1], dx, dy, dz, a, phi, want_phi);
+        if (!m5) eq8<TAYLOR>(F.g[g][3], h.lv[2], cl.idx[2], ox, oy, oz, a, phi, want_phi);
         break;
       case SBX_OUTER:
-        eq8(F.g[g][4], h.lv[2], cl.idx[2], ox, oy, oz, sys.taylor, a, phi, want_phi);
+        eq8<TAYLOR>(F.g[g][4], h.lv[2], cl.idx[2], ox, oy, oz, a, phi, want_phi);
         break;
       default:
         break;
@@ -316,8 +321,8 @@ __device__ __forceinline__ void particle_field(const SysDev& sys, const double* 
   }
   if (live5) {
     const HierDev& h = sys.h[0];
-    eq8(F.g[0][3], h.lv[2], i5, x - h.outer_c[0], y - h.outer_c[1], z - h.outer_c[2], sys.taylor, a,
-        phi, want_phi);
+    eq8<TAYLOR>(F.g[0][3], h.lv[2], i5, x - h.outer_c[0], y - h.outer_c[1], z - h.outer_c[2], a, phi,
+               want_phi);
   }
 }
 
@@ -875,7 +880,11 @@ __global__ void __launch_bounds__(256)
   const gp<const int8_t> GAL = glb((const int8_t*)p.gal), COMP = glb((const int8_t*)p.comp);
   const SysDev& sys = I.sys;
   const GridsDev<T>& F = I.G;
-  const double* __restrict__ centres = I.centres;
+  // the centres are read from LDS: a global load of them inside the loop
+  // would wait for every load in flight, the next particle's included
+  __shared__ double centres[3 * kMaxGal];
+  if (threadIdx.x < 3 * kMaxGal) centres[threadIdx.x] = I.centres[threadIdx.x];
+  __syncthreads();
   const T dt = (T)I.dt;
   const double dtd = I.dt;
   // diagnostics: per-component sums per wavefront in LDS (one writer per
@@ -933,7 +942,10 @@ __global__ void __launch_bounds__(256)
       const double x = (double)xs, y = (double)ys, z = (double)zs;
       T a[3] = {(T)0, (T)0, (T)0};
       T phi = (T)0;
-      particle_field(sys, centres, F, x, y, z, a, phi, OUT || DIAG);
+      if (sys.taylor)
+        particle_field<true>(sys, centres, F, x, y, z, a, phi, OUT || DIAG);
+      else
+        particle_field<false>(sys, centres, F, x, y, z, a, phi, OUT || DIAG);
       if constexpr (OUT) {
         I.acc[3 * i] = (double)a[0];
         I.acc[3 * i + 1] = (double)a[1];
@@ -964,6 +976,9 @@ __global__ void __launch_bounds__(256)
         }
       }
       if constexpr (MOVE) {
+        // galaxy and mass for the centre-of-mass sums load with the velocity
+        const int gi = GAL[i];
+        const T mi = Mv[i];
         const T vx = V0[i] + dt * a[0];
         const T vy = V1[i] + dt * a[1];
         const T vz = V2[i] + dt * a[2];
@@ -979,8 +994,8 @@ __global__ void __launch_bounds__(256)
           LOST[i] = 1;
         } else {
           // centre-of-mass sums of the new positions for the next step
-          cg = GAL[i];
-          cm = (double)Mv[i];
+          cg = gi;
+          cm = (double)mi;
           cx = cm * ex;
           cy = cm * ey;
           cz = cm * ez;
