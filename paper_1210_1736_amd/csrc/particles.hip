@@ -785,10 +785,13 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   const int64_t base = (int64_t)lb * kDepChunk;
-  // the next particle is loaded one iteration ahead
-  auto fetch = [&](int64_t q, bool& ok, int& g, T& x, T& y, T& z, T& mm) {
-    ok = q < p.n && !LOST[q];
-    if (ok) {
+  // The next particle is loaded one iteration ahead, every field whatever
+  // its flag, so that the loads go out together and the flag is waited for
+  // only where it is used (l = 1 marks no particle).
+  auto fetch = [&](int64_t q, uint8_t& l, int& g, T& x, T& y, T& z, T& mm) {
+    l = 1;
+    if (q < p.n) {
+      l = LOST[q];
       g = GAL[q];
       x = X0[q];
       y = X1[q];
@@ -796,15 +799,15 @@ __global__ void __launch_bounds__(256)
       mm = Mv[q];
     }
   };
-  bool okn = false;
+  uint8_t lnx = 1;
   int gn = 0;
   T xn = (T)0, yn = (T)0, zn = (T)0, mn = (T)0;
-  fetch(base + threadIdx.x, okn, gn, xn, yn, zn, mn);
+  fetch(base + threadIdx.x, lnx, gn, xn, yn, zn, mn);
   for (int j = 0; j < kDepChunk / 256; ++j) {
-    const bool ok = okn;
+    const bool ok = lnx == 0;
     const int g = gn;
     const T xs = xn, ys = yn, zs = zn, ms = mn;
-    if (j + 1 < kDepChunk / 256) fetch(base + (j + 1) * 256 + threadIdx.x, okn, gn, xn, yn, zn, mn);
+    if (j + 1 < kDepChunk / 256) fetch(base + (j + 1) * 256 + threadIdx.x, lnx, gn, xn, yn, zn, mn);
     // fine: key on the finest level, or kNoKey; coarse keys c1, c2 go
     // through the table
     uint32_t fine = kNoKey, c1 = kNoKey, c2 = kNoKey;
@@ -940,6 +943,17 @@ __global__ void __launch_bounds__(256)
     }
     if (live) {
       const double x = (double)xs, y = (double)ys, z = (double)zs;
+      // velocity, galaxy and mass are loaded before the field gathers, so
+      // their memory latency overlaps the gathers'
+      T v0 = (T)0, v1 = (T)0, v2 = (T)0, mi = (T)0;
+      int gi = 0;
+      if constexpr (MOVE) {
+        v0 = V0[i];
+        v1 = V1[i];
+        v2 = V2[i];
+        gi = GAL[i];
+        mi = Mv[i];
+      }
       T a[3] = {(T)0, (T)0, (T)0};
       T phi = (T)0;
       if (sys.taylor)
@@ -976,12 +990,9 @@ __global__ void __launch_bounds__(256)
         }
       }
       if constexpr (MOVE) {
-        // galaxy and mass for the centre-of-mass sums load with the velocity
-        const int gi = GAL[i];
-        const T mi = Mv[i];
-        const T vx = V0[i] + dt * a[0];
-        const T vy = V1[i] + dt * a[1];
-        const T vz = V2[i] + dt * a[2];
+        const T vx = v0 + dt * a[0];
+        const T vy = v1 + dt * a[1];
+        const T vz = v2 + dt * a[2];
         const T nx = xs + dt * vx, ny = ys + dt * vy, nz = zs + dt * vz;
         V0[i] = vx;
         V1[i] = vy;
