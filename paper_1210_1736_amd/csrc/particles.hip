@@ -1103,18 +1103,20 @@ __global__ void __launch_bounds__(256)
   const int64_t i = (int64_t)lb * 256 + threadIdx.x;
   uint32_t k = kNoKey;  // lanes past the end keep a key of their own
   if (i < p.n) {
+    // flag, galaxy and position are loaded together (one round trip); a
+    // lost particle's classification is computed and discarded
+    const uint8_t lost = glb((const uint8_t*)p.lost)[i];
+    const int g = glb((const int8_t*)p.gal)[i];
+    const double x = (double)X0[i], y = (double)X1[i], z = (double)X2[i];
+    const HierDev& h = sys.h[g];
+    Classified c;
+    classify(h, cen + 3 * g, x, y, z, c);
     k = lost_bin;
-    if (!p.lost[i]) {
-      const int g = p.gal[i];
-      const HierDev& h = sys.h[g];
-      Classified c;
-      classify(h, cen + 3 * g, (double)X0[i], (double)X1[i], (double)X2[i], c);
-      if (c.cls != SBX_LOST) {
-        const int lev = h.n_levels == 1 ? 0 : c.cls;
-        const size_t n = (size_t)h.lv[lev].N;
-        const int* id = lev == 0 ? c.idx[0] : (lev == 1 ? c.idx[1] : c.idx[2]);
-        k = (uint32_t)(bins_before(sys, g, lev) + ((id[2] * n + id[1]) * n + id[0]));
-      }
+    if (!lost && c.cls != SBX_LOST) {
+      const int lev = h.n_levels == 1 ? 0 : c.cls;
+      const size_t n = (size_t)h.lv[lev].N;
+      const int* id = lev == 0 ? c.idx[0] : (lev == 1 ? c.idx[1] : c.idx[2]);
+      k = (uint32_t)(bins_before(sys, g, lev) + ((id[2] * n + id[1]) * n + id[0]));
     }
     I.key[i] = k;
   }
