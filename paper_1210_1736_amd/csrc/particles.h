@@ -27,7 +27,7 @@ constexpr int kNDiag = kDiagLost + 1;
 constexpr int kPreVals = kMaxGal * 4;  // per galaxy [m, m x, m y, m z]
 constexpr int kRedBlocks = 1024;       // blocks per instance of the loss-test / COM pass
 constexpr int kForceBlocksMax = 2048;  // blocks per instance of the force pass
-constexpr int kDepChunk = 2048;        // particles per block of the mass assignment
+constexpr int kDepChunk = 8192;        // particles per block of the mass assignment
 constexpr int kArgParts = 256;         // blocks per galaxy of the densest-cell search
 
 // One grid geometry as the kernels use it (all float64, computed on the host
