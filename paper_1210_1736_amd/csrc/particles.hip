@@ -269,8 +269,9 @@ __device__ __forceinline__ void eq8(const T* __restrict__ F, const LevelDev& L, 
     phi += p0 + gx * Dx + gy * Dy + gz * Dz +
            (T)0.5 * (hxx * Dx * Dx + hyy * Dy * Dy + hzz * Dz * Dz) + hxy * Dx * Dy +
            hxz * Dx * Dz + hyz * Dy * Dz;
-  // one field's stencil in registers at a time: gathering the next field's
-  // ahead of this arithmetic costs more in occupancy than it hides
+  // one field's stencil in registers at a time: letting the scheduler
+  // gather the next field's ahead of this arithmetic took more registers
+  // and measured slower
   __builtin_amdgcn_sched_barrier(0);
 }
 
