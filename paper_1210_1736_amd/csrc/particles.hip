@@ -944,17 +944,18 @@ __global__ void __launch_bounds__(256)
     }
     if (live) {
       const double x = (double)xs, y = (double)ys, z = (double)zs;
-      // velocity, galaxy and mass are loaded before the field gathers, so
-      // their memory latency overlaps the gathers'
+      // velocity, galaxy, mass (and component) are loaded before the field
+      // gathers, so their memory latency overlaps the gathers'
       T v0 = (T)0, v1 = (T)0, v2 = (T)0, mi = (T)0;
-      int gi = 0;
-      if constexpr (MOVE) {
+      int gi = 0, ci = 0;
+      if constexpr (MOVE || DIAG) {
         v0 = V0[i];
         v1 = V1[i];
         v2 = V2[i];
         gi = GAL[i];
         mi = Mv[i];
       }
+      if constexpr (DIAG) ci = COMP[i];
       T a[3] = {(T)0, (T)0, (T)0};
       T phi = (T)0;
       if (sys.taylor)
@@ -968,18 +969,18 @@ __global__ void __launch_bounds__(256)
         I.pot[i] = -(double)phi;
       }
       if constexpr (DIAG) {
-        const double m = (double)Mv[i];
-        const double vx = (double)V0[i] + 0.5 * dtd * (double)a[0];
-        const double vy = (double)V1[i] + 0.5 * dtd * (double)a[1];
-        const double vz = (double)V2[i] + 0.5 * dtd * (double)a[2];
-        dc = COMP[i] & (kNComp - 1);
+        const double m = (double)mi;
+        const double vx = (double)v0 + 0.5 * dtd * (double)a[0];
+        const double vy = (double)v1 + 0.5 * dtd * (double)a[1];
+        const double vz = (double)v2 + 0.5 * dtd * (double)a[2];
+        dc = ci & (kNComp - 1);
         dv[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz);
         dv[1] = 0.5 * m * (-(double)phi);
         dv[2] = m * (y * vz - z * vy);
         dv[3] = m * (z * vx - x * vz);
         dv[4] = m * (x * vy - y * vx);
         dv[5] = 1.0;
-        if (dc == 0 && GAL[i] == 0) {
+        if (dc == 0 && gi == 0) {
           const double rx = x - centres[0], ry = y - centres[1];
           const double R = sqrt(rx * rx + ry * ry);
           const double vR = R > 0.0 ? (rx * vx + ry * vy) / R : 0.0;
@@ -1318,13 +1319,15 @@ __global__ void __launch_bounds__(256)
                const uint8_t* __restrict__ frozen, double* __restrict__ lx, double* __restrict__ lv) {
   __shared__ uint32_t tkey[kAdjTable];
   __shared__ T tval[kAdjTable];
+  __shared__ double cen[3 * kMaxGal];  // read from LDS inside the galaxy loop
+  const InstDev<T>& I = inst[0];
   for (int k = threadIdx.x; k < kAdjTable; k += 256) {
     tkey[k] = kNoKey;
     tval[k] = (T)0;
   }
+  if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = I.centres[threadIdx.x];
   __syncthreads();
   const AdjSink<T> sink{tkey, tval, &Bg};
-  const InstDev<T>& I = inst[0];
   const PartDev<T> p = I.p[cur[0]];
   const SysDev& sys = I.sys;
   const double dt = I.dt;
@@ -1340,7 +1343,7 @@ __global__ void __launch_bounds__(256)
     const GridsDev<T>& F = I.G;
     for (int g = 0; g < sys.ngal; ++g) {
       const HierDev& h = sys.h[g];
-      const double* c = I.centres + 3 * g;
+      const double* c = cen + 3 * g;
       Classified cl;
       classify(h, c, x, y, z, cl);
       const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
