@@ -195,6 +195,7 @@ InstDev<T> inst_of(const sbx_ctx* c) {
   I.grid_block = (T*)c->grid_block;
   I.grid_elems = c->mass_elems;
   I.key = c->key;
+  I.rank = c->rank;
   I.count = c->count;
   I.part_base = 0;
   I.dm_hist = c->dm_hist;
@@ -257,6 +258,7 @@ void free_particles(sbx_ctx* c) {
     free_typed(q.id);
   }
   free_typed(c->key);
+  free_typed(c->rank);
   free_typed(c->acc);
   free_typed(c->pot);
   c->acc_n = 0;
@@ -859,6 +861,7 @@ sbx_status load_impl(sbx_ctx* c, int64_t n, const double* x, const double* v, co
     SBX_TRY(dev_alloc((void**)&q.id, sizeof(int32_t) * n));
   }
   SBX_TRY(dev_alloc((void**)&c->key, sizeof(uint32_t) * n));
+  SBX_TRY(dev_alloc((void**)&c->rank, sizeof(uint32_t) * n));
   c->n = n;
   c->cur = 0;
   double* stage = nullptr;

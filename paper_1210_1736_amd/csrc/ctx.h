@@ -85,6 +85,7 @@ struct sbx_ctx {
   unsigned long long* dm_mmax = nullptr;  // largest particle mass (bits), taken at load
   // cell sort
   uint32_t* key = nullptr;
+  uint32_t* rank = nullptr;
   uint32_t* count = nullptr;     // bins + 1
   uint32_t* scan_tmp = nullptr;
   size_t bins = 0;

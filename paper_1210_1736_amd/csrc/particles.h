@@ -98,6 +98,7 @@ struct InstDev {
   T* grid_block;            // all grids of the instance, back to back
   size_t grid_elems;        // the leading grids that take masses (cleared per step)
   uint32_t* key;            // n
+  uint32_t* rank;           // n: place of the particle within its sort bin
   uint32_t* count;          // bins + 1: this instance's slice of the shared counts
   uint32_t part_base;       // sort position of the instance's first particle
   // density-maximum centring (null / 0 when no galaxy uses it)

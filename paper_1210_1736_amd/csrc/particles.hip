@@ -1122,16 +1122,30 @@ __global__ void __launch_bounds__(256)
     }
     I.key[i] = k;
   }
-  // every lane takes part in the wave sum (no divergent shuffles)
+  // Each run of equal keys in the wavefront reserves its places in the bin
+  // with one atomic from its last lane; every lane keeps its own place, so
+  // the scatter needs no atomic (every lane takes part in the wave sum and
+  // the shuffles: no divergent shuffles).
+  const int lane = threadIdx.x & 63;
   bool tail;
-  const uint32_t run = wave_run_sum<uint32_t>(k, 1u, tail);
-  if (tail && k != kNoKey) atomicAdd(I.count + k, run);
+  const uint32_t rank1 = wave_run_sum<uint32_t>(k, 1u, tail);  // 1-based place in the run
+  uint32_t base = 0;
+  if (tail && k != kNoKey)
+    base = __hip_atomic_fetch_add(glb(I.count) + k, rank1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // nearest tail at or after this lane: suffix minimum of tail lane ids
+  int tl = tail ? lane : 64;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t2 = __shfl_down(tl, o, 64);
+    if (lane + o < 64) tl = min(tl, t2);
+  }
+  const uint32_t run_base = __shfl(base, tl & 63, 64);
+  if (i < p.n) I.rank[i] = run_base + rank1 - 1;
 }
 
-// Slots are reserved per run of equal keys in a wavefront: the run's last
-// lane reserves the whole run with one atomic add, the others take the
-// following slots in lane order.  Offsets are global (all instances' counts
-// scanned together); part_base turns them into the instance's own slots.
+// A particle's slot is the start of its bin (the counts scanned, global over
+// all instances) plus its place in the bin from the key pass; part_base
+// turns it into the instance's own slot.
 
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -1142,45 +1156,19 @@ __global__ void __launch_bounds__(256)
   const int c0 = cur[ii];
   const PartDev<T> s = I.p[c0];
   const PartDev<T> d = I.p[c0 ^ 1];
-  const int lane = threadIdx.x & 63;
   const int64_t q = (int64_t)lb * 256 + threadIdx.x;
-  const bool in = q < s.n;
-  // the particle's fields are read before the slot reservation so that both
-  // latencies overlap
-  T x0 = 0, x1 = 0, x2 = 0, v0 = 0, v1 = 0, v2 = 0, m = 0;
-  int8_t comp = 0, gal = 0;
-  uint8_t lost = 0;
-  int32_t id = 0;
-  uint32_t k = kNoKey;
-  if (in) {
-    k = glb((const uint32_t*)I.key)[q];
-    x0 = glb((const T*)s.x[0])[q];
-    x1 = glb((const T*)s.x[1])[q];
-    x2 = glb((const T*)s.x[2])[q];
-    v0 = glb((const T*)s.v[0])[q];
-    v1 = glb((const T*)s.v[1])[q];
-    v2 = glb((const T*)s.v[2])[q];
-    m = glb((const T*)s.m)[q];
-    comp = glb((const int8_t*)s.comp)[q];
-    gal = glb((const int8_t*)s.gal)[q];
-    lost = glb((const uint8_t*)s.lost)[q];
-    id = glb((const int32_t*)s.id)[q];
-  }
-  bool tail;
-  const uint32_t rank1 = wave_run_sum<uint32_t>(k, 1u, tail);  // 1-based rank in the run
-  uint32_t start = 0;
-  if (tail && k != kNoKey)
-    start = __hip_atomic_fetch_add(glb(I.count) + k, rank1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // nearest tail at or after this lane: suffix minimum of tail lane ids
-  int tl = tail ? lane : 64;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t2 = __shfl_down(tl, o, 64);
-    if (lane + o < 64) tl = min(tl, t2);
-  }
-  const uint32_t run_start = __shfl(start, tl & 63, 64);
-  if (!in) return;
-  const uint32_t j = run_start + rank1 - 1 - I.part_base;
+  if (q >= s.n) return;
+  // the particle, its key and its place load together, then the start of
+  // its bin
+  const uint32_t k = glb((const uint32_t*)I.key)[q];
+  const uint32_t r = glb((const uint32_t*)I.rank)[q];
+  const T x0 = glb((const T*)s.x[0])[q], x1 = glb((const T*)s.x[1])[q], x2 = glb((const T*)s.x[2])[q];
+  const T v0 = glb((const T*)s.v[0])[q], v1 = glb((const T*)s.v[1])[q], v2 = glb((const T*)s.v[2])[q];
+  const T m = glb((const T*)s.m)[q];
+  const int8_t comp = glb((const int8_t*)s.comp)[q], gal = glb((const int8_t*)s.gal)[q];
+  const uint8_t lost = glb((const uint8_t*)s.lost)[q];
+  const int32_t id = glb((const int32_t*)s.id)[q];
+  const uint32_t j = glb((const uint32_t*)I.count)[k] + r - I.part_base;
   glb((T*)d.x[0])[j] = x0;
   glb((T*)d.x[1])[j] = x1;
   glb((T*)d.x[2])[j] = x2;
