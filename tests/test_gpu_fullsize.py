@@ -87,27 +87,34 @@ def test_ensemble_full_size_batch_step(sbx):
         c.close()
 
 
-def test_disc_galaxy_full_size_steps(sbx):
+@pytest.mark.parametrize("prec", [0, 1])  # SBX_FP32, SBX_FP64
+def test_disc_galaxy_full_size_steps(sbx, prec):
     """The timed launch configuration on the full 3 x 128^3 disc galaxy
-    (8.5M particles, FP32): two steps, the first with the reorder (the
-    default interval) and the diagnostics (every 10 steps), so both moving
-    force passes run, against two oracle steps (Eq. 6) from the same
-    FP32-rounded inputs.
-    A particle may leave the global grid in one precision and not the other
-    only within rounding of its boundary, so the loss flags may differ for a
-    handful; motion is compared on the rest."""
+    (8.5M particles): two steps, the first with the reorder (the default
+    interval) and the diagnostics (every 10 steps), so both moving force
+    passes run, against two oracle steps (Eq. 6) from the same inputs
+    (FP32-rounded for the FP32 form).  FP64 bars as in test_gpu_parity
+    (positions within 1e-10, velocities within 1e-8, loss flags exact).  In
+    FP32 a particle may leave the global grid in one precision and not the
+    other only within rounding of its boundary, so the flags may differ for
+    a handful; motion is compared on the rest."""
     w = synth.disc_galaxy(scale=1.0)
     sysm = T.oracle_system(w)
-    x, v, m = T.oracle_inputs(w, sbx.SBX_FP32)
+    x, v, m = T.oracle_inputs(w, prec)
     lost = np.zeros(w.n, bool)
     for _ in range(2):
         x, v, lost, _ = sysm.step(x, v, m, w.gal, lost, w.dt)
-    ctx = T.make_ctx(w, sbx.SBX_FP32)
+    ctx = T.make_ctx(w, prec)
     ctx.sbx_step(w.dt, 2, 10)
     xg, vg, lg = ctx.sbx_get_particles()
     ctx.close()
     differ = np.flatnonzero(lg != lost)
     print(f"full disc galaxy, 2 steps: {lost.sum()} lost in the oracle, {differ.size} flags differ")
+    if prec == sbx.SBX_FP64:
+        assert differ.size == 0
+        assert np.max(np.abs(xg - x)) < 1e-10
+        assert np.max(np.abs(vg - v)) < 1e-8
+        return
     assert differ.size <= 10
     both = ~(lg | lost)
     vr = np.sqrt(np.mean(np.sum(v[both] * v[both], axis=1)))
