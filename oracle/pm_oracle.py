@@ -653,23 +653,35 @@ def eq8_jacobian(Phi, idx, lengths, taylor=True):
     return np.transpose(DD, (2, 0, 1))
 
 
-def segment_loss_and_grads(sysm: System, x, v, m, comp, gal, dt, nsteps, sel_comp=0, sel_gal=0):
-    """Forward: nsteps integration cycles; loss L = sum over the selected
-    particles (component sel_comp of galaxy sel_gal) still on the grids at the
-    end of 1/2 m v_z^2 with the staggered v after the last kick.  Backward: exact reverse mode of the
-    discrete step (the nearest-grid-point cells are piecewise constant, so
-    only the in-cell offsets of Eq. 8 carry a position derivative).
-    Fixed centres only.  Returns (L, dL/dm, dL/dx0, dL/dv0).
+def segment_loss_and_grads(sysm: System, x, v, m, comp, gal, dt, nsteps, sel_comp=0, sel_gal=0,
+                           lost0=None):
+    """Forward: nsteps integration cycles (Eq. 6 with the fields of Sec. 2.1)
+    from the state (x, v, lost0); loss L = sum over the selected particles
+    (component sel_comp of galaxy sel_gal) still on the grids at the end of
+    1/2 m v_z^2, with the staggered v after the last kick.  Backward: reverse
+    mode of the discrete cycles.
+
+    Particle loss (Sec. 2.1) is part of the forward: the particles that take
+    part in cycle k are those live after that cycle's start-of-step loss
+    test.  The reverse of cycle k re-solves the fields from exactly those
+    particles, so a particle that leaves during the segment still receives
+    dL/dm from the cycles in which its mass shaped the fields; a particle that
+    sits out a cycle passes its adjoints through it unchanged.  The
+    nearest-grid-point cells and the loss test are piecewise constant, so
+    only the in-cell offsets of Eq. 8 carry a position derivative (almost
+    everywhere).  Fixed centres only.  Returns (L, dL/dm, dL/dx0, dL/dv0).
     parity unpinned beyond its finite-difference and transpose pins."""
     for hh in sysm.h:
         if hh.centring != "fixed":
             raise ValueError("the segment adjoint needs fixed centres")
-    lost = np.zeros(x.shape[0], bool)
-    xs = [x.copy()]
+    lost = np.zeros(x.shape[0], bool) if lost0 is None else np.asarray(lost0, bool).copy()
+    xs, lives = [], []
     xk, vk = x.copy(), v.copy()
     for _ in range(nsteps):
-        xk, vk, lost, _ = sysm.step(xk, vk, m, gal, lost, dt)
+        # participants of this cycle: live after its start-of-step loss test
+        lives.append(~(lost | sysm.lost_now(xk)))
         xs.append(xk.copy())
+        xk, vk, lost, _ = sysm.step(xk, vk, m, gal, lost, dt)
     # particles lost by the end have left the system (Sec. 2.1): not counted
     sel = (comp == sel_comp) & (gal == sel_gal) & ~lost
     L = 0.5 * np.sum(m[sel] * vk[sel, 2] ** 2)
@@ -678,13 +690,15 @@ def segment_loss_and_grads(sysm: System, x, v, m, comp, gal, dt, nsteps, sel_com
     lx = np.zeros_like(x)
     lv = np.zeros_like(v)
     lv[sel, 2] = m[sel] * vk[sel, 2]
-    live = ~lost
     for k in range(nsteps - 1, -1, -1):
-        lv = lv + dt * lx
+        live = lives[k]
+        out_k = ~live
+        # reverse drift (x' = x + dt v'), then reverse kick (v' = v + dt a(x))
+        lv = np.where(live[:, None], lv + dt * lx, lv)
         mu = np.where(live[:, None], dt * lv, 0.0)
         xk = xs[k]
-        centres = sysm.centres(xk, m, gal, lost)
-        pots = sysm.potentials(xk, m, gal, lost, centres)
+        centres = sysm.centres(xk, m, gal, out_k)
+        pots = sysm.potentials(xk, m, gal, out_k, centres)
         for g, hh in enumerate(sysm.h):
             cls, idx = classify(xk, hh, centres[g])
             Phi = pots[g]["Phi"]
@@ -713,6 +727,7 @@ def segment_loss_and_grads(sysm: System, x, v, m, comp, gal, dt, nsteps, sel_com
                 for q in grids:
                     Bs[q] += Bt
             # mass gradient: psi = K B on each grid, read at the source cells
+            # of the particles that deposited in this cycle
             own = (gal == g) & live
             if nl == 1:
                 psi = sysm.solve(Bs[0], hh.levels[0])

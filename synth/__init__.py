@@ -369,3 +369,30 @@ def adjoint_segment(scale=1.0, N=256, workload=5, steps=10):
     h = HierSpec([LevelSpec(N, 12.0, 1.0)])
     return Workload("adjoint_segment_256", x, v, m, comp, np.zeros(x.shape[0], np.int8), [h],
                     dt=0.01, steps=steps)
+
+
+def escape_segment(kind="single", n=3000, workload=6, steps=4, dt=0.02):
+    """A flattened cloud on fixed grids plus four heavy particles that leave
+    the outermost grid during a short segment: they start inside its usable
+    cells, moving outward fast enough to cross its boundary in the drift of
+    the second cycle (they take part in cycles 0 and 1 and are lost from
+    cycle 2 on).  kind 'single': one 32^3 grid of half-extent 2.5; 'nested':
+    three fixed 32^3 levels of half-extents 0.5, 1.5 (both q = 1/2) and 4.
+    The escapers are component 1, the component the segment tests select."""
+    rng = rng_for(workload, 0 if kind == "single" else 1)
+    x = rng.normal(size=(n, 3)) * np.array([0.6, 0.6, 0.15])
+    v = rng.normal(size=(n, 3)) * 0.3
+    m = rng.uniform(0.5, 1.5, n) / n
+    comp = (rng.uniform(size=n) < 0.5).astype(np.int8)
+    if kind == "single":
+        hs = HierSpec([LevelSpec(32, 2.5, 1.0)])
+        hi, lo, speed = 2.33, -2.51, 2.5     # usable edges at +2.411 and -2.589
+    else:
+        hs = HierSpec([LevelSpec(32, 0.5, 0.5), LevelSpec(32, 1.5, 0.5), LevelSpec(32, 4.0, 1.0)])
+        hi, lo, speed = 3.72, -4.0, 4.0      # usable edges at +3.857 and -4.143
+    ex = np.array([[hi, 0.1, 0.3], [lo, -0.2, -0.25], [0.15, hi, 0.2], [-0.1, 0.2, hi]])
+    ev = np.array([[speed, 0.0, 0.0], [-speed, 0.0, 0.0], [0.0, speed, 0.0], [0.0, 0.0, speed]])
+    x = np.vstack([x, ex]); v = np.vstack([v, ev])
+    m = np.concatenate([m, np.full(4, 0.02)])
+    comp = np.concatenate([comp, np.ones(4, np.int8)])
+    return Workload("escape-" + kind, x, v, m, comp, np.zeros(n + 4, np.int8), [hs], dt, steps)

@@ -105,3 +105,52 @@ def _fwd(sysm, x, v, m, comp, gal, dt, K):
         x, v, lost, _ = sysm.step(x, v, m, gal, lost, dt)
     sel = (comp == 1) & (gal == 0) & ~lost
     return 0.5 * np.sum(m[sel] * v[sel, 2] ** 2)
+
+
+@pytest.mark.parametrize("kind", ["single", "nested"])
+def test_segment_gradients_with_particles_lost_mid_segment(kind):
+    """Four heavy particles take part in cycles 0 and 1 of a 4-cycle segment
+    and leave the outermost grid in the drift of cycle 1 (Sec. 2.1 particle
+    loss).  Their masses shaped the fields of cycles 0 and 1, so dL/dm of each
+    is nonzero and equals the central difference of the forward loss; they
+    are not in the loss and their cells are piecewise constant, so dL/dx and
+    dL/dv vanish.  Cloud particles are checked as in the plain segment."""
+    import synth
+    w = synth.escape_segment(kind)
+    from tests import common as T
+    sysm = T.oracle_system(w)
+    esc = np.arange(w.n - 4, w.n)
+    # the set-up: escapers live in cycles 0 and 1, lost from cycle 2 on
+    x, v, lost = w.x.copy(), w.v.copy(), np.zeros(w.n, bool)
+    for k in range(w.steps):
+        live = ~(lost | sysm.lost_now(x))
+        assert bool(live[esc].all()) == (k < 2) and bool(live[esc].any()) == (k < 2)
+        x, v, lost, _ = sysm.step(x, v, w.m, w.gal, lost, w.dt)
+    assert lost[esc].all() and lost.sum() == 4
+    L, gm, gx, gv = O.segment_loss_and_grads(sysm, w.x, w.v, w.m, w.comp, w.gal, w.dt, w.steps, 1, 0)
+    assert L == pytest.approx(_fwd(sysm, w.x, w.v, w.m, w.comp, w.gal, w.dt, w.steps), rel=1e-14)
+
+    def loss(x_, v_, m_):
+        return _fwd(sysm, x_, v_, m_, w.comp, w.gal, w.dt, w.steps)
+
+    for q in esc:
+        eps = 1e-4 * w.m[q]
+        mp = w.m.copy(); mp[q] += eps
+        mm = w.m.copy(); mm[q] -= eps
+        fd = (loss(w.x, w.v, mp) - loss(w.x, w.v, mm)) / (2 * eps)
+        assert abs(gm[q]) > 1e-6 * abs(gm).max()
+        assert fd == pytest.approx(gm[q], rel=2e-5)
+        assert not gx[q].any() and not gv[q].any()
+    rng = _rng(6)
+    for q in rng.choice(w.n - 4, 4, replace=False):
+        eps = 1e-4 * w.m[q]
+        mp = w.m.copy(); mp[q] += eps
+        mm = w.m.copy(); mm[q] -= eps
+        fd = (loss(w.x, w.v, mp) - loss(w.x, w.v, mm)) / (2 * eps)
+        assert fd == pytest.approx(gm[q], rel=2e-5, abs=1e-9 * abs(gm).max())
+        a = int(rng.integers(0, 3))
+        h = 1e-7
+        vp = w.v.copy(); vp[q, a] += h
+        vm = w.v.copy(); vm[q, a] -= h
+        fd = (loss(w.x, vp, w.m) - loss(w.x, vm, w.m)) / (2 * h)
+        assert fd == pytest.approx(gv[q, a], rel=1e-4, abs=1e-6 * abs(gv).max())
