@@ -209,7 +209,10 @@ sbx_status sbx_diag_log(sbx_ctx* ctx, int32_t max, sbx_diag* out, int32_t* count
  * NULL): loss (1), grad_m = dL/dm (n), grad_x = dL/dx (n*3) and
  * grad_v = dL/dv (n*3) at the start of the segment.  Nearest-grid-point
  * cells are piecewise constant, so dL/dx holds the in-cell (Eq. 8 offset)
- * part only.  Particles lost by the end are frozen for the whole segment.
+ * part only.  Each reverse cycle re-solves the fields from the particles that
+ * took part in that cycle (live after its start-of-step loss test, Sec. 2.1):
+ * a particle lost during the segment is not in the loss, but its dL/dm
+ * collects the fields of the cycles before its loss.
  * Fixed centres only (SBX_EINVAL otherwise).  Leaves the context at the
  * final state, as sbx_step would.  FP64 adjoint state in both precisions. */
 sbx_status sbx_adjoint_segment(sbx_ctx* ctx, double dt, int32_t nsteps, int32_t ckpt_every,

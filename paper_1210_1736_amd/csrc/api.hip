@@ -524,10 +524,13 @@ sbx_status copy_set(sbx_ctx* c, const PSet& dst, const PSet& src, bool with_v, b
 }
 
 // Forward nsteps without sorting, checkpoints of (x, v, lost) every
-// ckpt_every steps, then the reverse cycles segment by segment: positions of
-// a segment are recomputed from its checkpoint, each reverse cycle re-solves
-// the fields at its positions, scatters the adjoint sources, solves them and
-// gathers the mass gradient.  Particles lost by the end are frozen.
+// ckpt_every steps, then the reverse cycles segment by segment: positions
+// and lost flags of a segment's cycles are recomputed from its checkpoint,
+// each reverse cycle re-solves the fields from the particles that took part
+// in that cycle (live after its start-of-step loss test), scatters the
+// adjoint sources, solves them and gathers the mass gradient.  A particle
+// lost during the segment thus collects dL/dm from the cycles before its
+// loss, and passes its adjoints unchanged through the cycles it sat out.
 template <typename T>
 sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, int sel_gal,
                      double* loss, double* grad_m, double* grad_x, double* grad_v, bool dev_out) {
@@ -553,7 +556,7 @@ sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, 
   auto body = [&]() -> sbx_status {
     std::vector<PSet> cks(nck + 1), xb(ckpt);
     for (auto& s : cks) SBX_TRY(make_set(s, true, true));
-    for (auto& s : xb) SBX_TRY(make_set(s, false, false));
+    for (auto& s : xb) SBX_TRY(make_set(s, false, true));
     SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&lx));
     SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&lv));
     SBX_TRY(alloc(sizeof(double) * n, (void**)&gm));
@@ -572,29 +575,30 @@ sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, 
     SBX_TRY(copy_set<T>(c, cks[nck], live, true, true));  // final state
     SBX_TRY(launch_adj_init<T>(dinst<T>(c), c->d_cur, n, sel_comp, sel_gal, lx, lv, gm, c->pre_partial,
                                dloss, c->stream));
-    const uint8_t* frozen = cks[nck].lost;
     const GridsDev<T> B = adj_grids<T>(c);
     for (int seg = nck - 1; seg >= 0; --seg) {
       const int k0 = seg * ckpt, k1 = std::min(k0 + ckpt, nsteps);
       SBX_TRY(copy_set<T>(c, live, cks[seg], true, true));
       c->com_fresh = false;
       for (int k = k0; k < k1; ++k) {
-        SBX_TRY(copy_set<T>(c, xb[k - k0], live, false, false));
+        // positions and lost flags at the start of cycle k
+        SBX_TRY(copy_set<T>(c, xb[k - k0], live, false, true));
         if (k + 1 < k1) {
           SBX_TRY(field_solve(c));
           SBX_TRY(force(c, 1));
         }
       }
-      SBX_HIP(hipMemcpyAsync(live.lost, frozen, n, hipMemcpyDeviceToDevice, c->stream));
       for (int k = k1 - 1; k >= k0; --k) {
-        SBX_TRY(copy_set<T>(c, live, xb[k - k0], false, false));
+        SBX_TRY(copy_set<T>(c, live, xb[k - k0], false, true));
+        // the solve's loss test leaves in live.lost exactly the particles
+        // that sat out cycle k
         c->com_fresh = false;
         SBX_TRY(field_solve(c));
         SBX_TRY(launch_zero<T>((T*)c->adj_block, c->grid_elems, c->stream));
-        SBX_TRY(launch_adj_step<T>(dinst<T>(c), c->d_cur, n, B, frozen, lx, lv, c->stream));
+        SBX_TRY(launch_adj_step<T>(dinst<T>(c), c->d_cur, n, B, live.lost, lx, lv, c->stream));
         SolvePlan<T>& adj = sizeof(T) == 8 ? (SolvePlan<T>&)c->adj64 : (SolvePlan<T>&)c->adj32;
         SBX_TRY(plan_run<T>(adj, c->stream));
-        SBX_TRY(launch_adj_gather<T>(dinst<T>(c), c->d_cur, n, B, frozen, gm, c->stream));
+        SBX_TRY(launch_adj_gather<T>(dinst<T>(c), c->d_cur, n, B, live.lost, gm, c->stream));
       }
     }
     SBX_TRY(copy_set<T>(c, live, cks[nck], true, true));  // back to the final state

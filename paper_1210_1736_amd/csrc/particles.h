@@ -197,17 +197,18 @@ sbx_status launch_indices(const InstDev<T>* inst, const int* cur, int64_t n, int
 // init: loss (one double) and seeds of the adjoints; step: one reverse cycle
 // at the positions in the live set with the forward fields in the grids,
 // adjoint sources scattered into B; gather: mass gradient from the adjoint
-// potentials P.  `frozen` marks particles treated as lost for the segment.
+// potentials P.  `out` marks the particles that sat out the cycle (lost at
+// its start): their adjoints pass through unchanged and they gather nothing.
 template <typename T>
 sbx_status launch_adj_init(const InstDev<T>* inst, const int* cur, int64_t n, int sel_comp,
                            int sel_gal, double* lx, double* lv, double* gm, double* partial,
                            double* loss, hipStream_t s);
 template <typename T>
 sbx_status launch_adj_step(const InstDev<T>* inst, const int* cur, int64_t n, const GridsDev<T>& B,
-                           const uint8_t* frozen, double* lx, double* lv, hipStream_t s);
+                           const uint8_t* out, double* lx, double* lv, hipStream_t s);
 template <typename T>
 sbx_status launch_adj_gather(const InstDev<T>* inst, const int* cur, int64_t n, const GridsDev<T>& P,
-                             const uint8_t* frozen, double* gm, hipStream_t s);
+                             const uint8_t* out, double* gm, hipStream_t s);
 
 sbx_status launch_iota(int32_t* id, int64_t n, hipStream_t s);
 

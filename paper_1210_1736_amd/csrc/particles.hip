@@ -1304,7 +1304,7 @@ __global__ void __launch_bounds__(256)
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_adj_step(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, GridsDev<T> Bg,
-               const uint8_t* __restrict__ frozen, double* __restrict__ lx, double* __restrict__ lv) {
+               const uint8_t* __restrict__ out, double* __restrict__ lx, double* __restrict__ lv) {
   __shared__ uint32_t tkey[kAdjTable];
   __shared__ T tval[kAdjTable];
   __shared__ double cen[3 * kMaxGal];  // read from LDS inside the galaxy loop
@@ -1320,7 +1320,7 @@ __global__ void __launch_bounds__(256)
   const SysDev& sys = I.sys;
   const double dt = I.dt;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < p.n && !frozen[i]) {
+  if (i < p.n && !out[i]) {
     double l[3] = {lx[3 * i], lx[3 * i + 1], lx[3 * i + 2]};
     double w[3] = {lv[3 * i] + dt * l[0], lv[3 * i + 1] + dt * l[1], lv[3 * i + 2] + dt * l[2]};
     lv[3 * i] = w[0];
@@ -1386,11 +1386,11 @@ __device__ __forceinline__ const T* cell_ptr(const T* grid, const LevelDev& L, c
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_adj_gather(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, GridsDev<T> Pg,
-                 const uint8_t* __restrict__ frozen, double* __restrict__ gm) {
+                 const uint8_t* __restrict__ out, double* __restrict__ gm) {
   const InstDev<T>& I = inst[0];
   const PartDev<T> p = I.p[cur[0]];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n || frozen[i]) return;
+  if (i >= p.n || out[i]) return;
   const int g = p.gal[i];
   const HierDev& h = I.sys.h[g];
   Classified c;
@@ -1616,20 +1616,20 @@ sbx_status launch_adj_init(const InstDev<T>* inst, const int* cur, int64_t n, in
 
 template <typename T>
 sbx_status launch_adj_step(const InstDev<T>* inst, const int* cur, int64_t n, const GridsDev<T>& B,
-                           const uint8_t* frozen, double* lx, double* lv, hipStream_t s) {
+                           const uint8_t* out, double* lx, double* lv, hipStream_t s) {
   if (n == 0) return SBX_OK;
   hipLaunchKernelGGL((k_adj_step<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, inst, cur, B,
-                     frozen, lx, lv);
+                     out, lx, lv);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
 
 template <typename T>
 sbx_status launch_adj_gather(const InstDev<T>* inst, const int* cur, int64_t n, const GridsDev<T>& P,
-                             const uint8_t* frozen, double* gm, hipStream_t s) {
+                             const uint8_t* out, double* gm, hipStream_t s) {
   if (n == 0) return SBX_OK;
   hipLaunchKernelGGL((k_adj_gather<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, inst, cur, P,
-                     frozen, gm);
+                     out, gm);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }

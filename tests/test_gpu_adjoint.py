@@ -263,3 +263,50 @@ def test_adjoint_autograd_on_gpu_tensors(sbx):
     assert _maxrel(m.grad.cpu().numpy(), gmr) < 1e-9
     assert _maxrel(x.grad.cpu().numpy(), gxr) < 1e-9
     assert _maxrel(v.grad.cpu().numpy(), gvr) < 1e-9
+
+
+@pytest.mark.parametrize("kind", ["single", "nested"])
+@pytest.mark.parametrize("ckpt", [1, 2, 3])
+def test_adjoint_particles_lost_mid_segment_fp64(sbx, kind, ckpt):
+    """Four heavy particles take part in cycles 0 and 1 of a 4-cycle segment
+    and leave the outermost grid in the drift of cycle 1 (Sec. 2.1 loss):
+    the library's reverse mode against the oracle's, whose mass gradients of
+    such particles are pinned by central differences.  Every checkpoint
+    interval puts the loss at a different place relative to the checkpoints
+    (inside a recomputed interval, at a checkpoint, in the first interval).
+    The escapers' dL/dm are also compared one by one."""
+    w = synth.escape_segment(kind)
+    esc = np.arange(w.n - 4, w.n)
+    ctx = T.make_ctx(w, sbx.SBX_FP64)
+    L, gm, gx, gv = ctx.sbx_adjoint_segment(w.dt, w.steps, ckpt, 1, 0)
+    _, _, lost = ctx.sbx_get_particles()
+    Lr, gmr, gxr, gvr = O.segment_loss_and_grads(T.oracle_system(w), w.x, w.v, w.m, w.comp, w.gal,
+                                                  w.dt, w.steps, 1, 0)
+    assert lost[esc].all() and int(lost.sum()) == 4
+    assert L == pytest.approx(Lr, rel=1e-12)
+    for a, b in ((gm, gmr), (gx, gxr), (gv, gvr)):
+        assert _maxrel(a, b) < 1e-9
+    assert np.all(np.abs(gm[esc] - gmr[esc]) <= 1e-7 * np.abs(gmr[esc]))
+    assert np.all(gmr[esc] != 0.0) and not gx[esc].any() and not gv[esc].any()
+
+
+@pytest.mark.parametrize("kind", ["single", "nested"])
+def test_adjoint_particles_lost_mid_segment_fp32(sbx, kind):
+    """The same segment in the FP32 form against the oracle on the
+    FP32-rounded inputs, at the FP32 bars of the plain segment; the escapers'
+    dL/dm within 1e-3 of their own size (their values are 1e-5 of the largest
+    gradient, so the whole-vector bar alone would not see them)."""
+    w = synth.escape_segment(kind)
+    esc = np.arange(w.n - 4, w.n)
+    ctx = T.make_ctx(w, sbx.SBX_FP32)
+    L, gm, gx, gv = ctx.sbx_adjoint_segment(w.dt, w.steps, 2, 1, 0)
+    x, v, m = T.oracle_inputs(w, sbx.SBX_FP32)
+    Lr, gmr, gxr, gvr = O.segment_loss_and_grads(T.oracle_system(w), x, v, m, w.comp, w.gal,
+                                                  w.dt, w.steps, 1, 0)
+    errs = [_maxrel(a, b) for a, b in ((gm, gmr), (gx, gxr), (gv, gvr))]
+    e_esc = np.abs(gm[esc] - gmr[esc]) / np.abs(gmr[esc])
+    print(f"FP32 escape segment ({kind}): loss {abs(L / Lr - 1):.2e}, grad m/x/v "
+          f"{errs[0]:.2e} {errs[1]:.2e} {errs[2]:.2e}, escapers dL/dm {e_esc.max():.2e}")
+    assert L == pytest.approx(Lr, rel=1e-6)
+    assert errs[0] < 1e-5 and errs[1] < 1e-4 and errs[2] < 1e-5
+    assert e_esc.max() < 1e-3
