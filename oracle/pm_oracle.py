@@ -203,9 +203,8 @@ def level_centre(h: Hierarchy, k: int, gal_centre):
 
 
 def centre_of_mass(x, m, mask):
-    """Centre of mass of the selected particles (Sec. 2.1 alternative centring).
-
-    Plain float64 sums in index order.
+    """Centre of mass of the selected particles (Sec. 2.1 alternative centring):
+    sum m x / sum m in float64 (numpy's summation order).
     """
     mm = m[mask]
     return (x[mask] * mm[:, None]).sum(axis=0) / mm.sum()
@@ -397,9 +396,9 @@ def eq8_accel(Phi, idx, delta, lengths, taylor=True):
 def taylor_potential(Phi, idx, delta, lengths, taylor=True):
     """Phi_paper at the particle: the quadratic whose gradient is Eq. 8.
 
-    P0 + sum_a D_a Delta_a + 1/2 sum_ab DD_ab Delta_a Delta_b.
-    parity unpinned beyond its gradient being Eq. 8 (the paper does not say how
-    the potential at a particle is read off the grid).
+    P0 + sum_a D_a Delta_a + 1/2 sum_ab DD_ab Delta_a Delta_b (the paper does
+    not say how the potential at a particle is read off the grid; this form is
+    exact, like Eq. 8, on a field that is quadratic in position).
     """
     P0, D, DD = _derivs(Phi, idx, lengths)
     if not taylor:
@@ -579,13 +578,15 @@ class System:
     def diagnostics(self, x, v, m, comp, gal, lost, dt, n_comp=8, prev_centres=None):
         """FP64 energy and angular momentum per component, disc dispersions.
 
-        v is the staggered v(t - dt/2); the synchronised velocity is
-        v + dt/2 * a(t).  W_c = 1/2 sum m phi with phi = -Phi_paper at the
-        particle; L_c = sum m x cross v_sync about the origin.  Disc (component 0
-        of galaxy 0) sigma_R and sigma_z about their means, R measured from
+        Taken at the start of a step: particles outside the global grid are
+        lost first (the step's start-of-step loss test, Sec. 2.1).  v is the
+        staggered v(t - dt/2); the synchronised velocity is v + dt/2 * a(t).
+        W_c = 1/2 sum m phi with phi = -Phi_paper at the particle; L_c = sum
+        m x cross v_sync about the origin.  Disc (component 0 of galaxy 0)
+        sigma_R and sigma_z about their means (unweighted), R measured from
         galaxy 0's centre.
-        parity unpinned beyond the pins of the energy it sums.
         """
+        lost = lost | self.lost_now(x)
         centres = self.centres(x, m, gal, lost, prev_centres)
         acc, Pp = self.accel(x, m, gal, lost, centres, want_pot=True)
         live = ~lost

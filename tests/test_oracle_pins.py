@@ -376,3 +376,110 @@ def test_energy_of_two_bodies():
     assert d["ekin"][0] == pytest.approx(0.5 * 0.7 * 0.09, rel=1e-12)
     Lz = 0.7 * x[0, 0] * 0.3 + 0.4 * x[1, 0] * (-0.2)
     assert d["L"][:, 2].sum() == pytest.approx(Lz, rel=1e-12)
+
+
+# ------------------------------------------------- Eq. 8 Taylor form --------
+def test_taylor_form_exact_on_quadratic_field():
+    """Central differences of a quadratic are exact, so on a grid holding
+    Phi(r) = c0 + g.r + 1/2 r.A.r at the cell centres Eq. 8 gives grad Phi
+    exactly and the quadratic Taylor form (the potential at a particle) gives
+    Phi exactly, anywhere in a cell.  Anisotropic cells (q = 1/2), a shifted
+    grid centre and a full symmetric A with distinct entries catch a swapped
+    offset, a dropped 1/2, a sign or an l/lz mix-up."""
+    N = 16
+    c = np.array([0.3, -0.2, 0.1])
+    L = O.Level(N, 2.0, 0.5, centre=c)
+    c0, g = 0.7, np.array([0.11, -0.23, 0.37])
+    A = np.array([[1.3, 0.4, -0.7], [0.4, -0.9, 0.25], [-0.7, 0.25, 2.1]])
+    i = np.arange(N)
+    R = np.stack(np.meshgrid(i, i, i, indexing="ij"), axis=-1).astype(float)
+    R = (R - N / 2.0) * L.lengths
+    Phi = c0 + R @ g + 0.5 * np.einsum("...a,ab,...b->...", R, A, R)
+    rng = _rng(40)
+    cells = rng.integers(3, N - 3, size=(200, 3))
+    x = c + (cells - N / 2.0 + rng.uniform(-0.49, 0.49, size=(200, 3))) * L.lengths
+    sysm = O.System([O.Hierarchy([L], "fixed", c)])
+    acc, pot = sysm.field_at(x, [c], [{"Phi": [Phi]}])
+    r = x - c
+    assert np.allclose(acc, g + r @ A, rtol=1e-12, atol=1e-12)
+    assert np.allclose(pot, c0 + r @ g + 0.5 * np.einsum("na,ab,nb->n", r, A, r), rtol=1e-12,
+                       atol=1e-12)
+    # the offsets really span the cells (not only their centres)
+    idx, d = O.ngp_cell(x, c, L)
+    assert np.array_equal(idx, cells)
+    assert np.abs(O.cell_offset(d, idx, L) / L.lengths).max() > 0.45
+
+
+# ------------------------------------------------------- diagnostics --------
+def test_diagnostics_half_kick_at_nonzero_dt():
+    """E_kin and L use v_sync = v(t - dt/2) + dt/2 a(t), which is the mean of
+    the staggered velocities before and after the step's kick (Eq. 6; the
+    kick is pinned by the parabola test).  A dropped or doubled half kick
+    gives the old or the new staggered velocity instead.  A particle outside
+    the global grid is lost before the sums."""
+    L = O.Level(32, 2.5)
+    sysm = O.System([O.Hierarchy([L])])
+    rng = _rng(41)
+    n = 300
+    x = rng.normal(size=(n, 3)) * 0.5
+    x[0] = [3.0, 0.0, 0.0]                        # off the grid: lost
+    v = rng.normal(size=(n, 3)) * 0.3
+    m = rng.uniform(0.5, 1.5, n) / n
+    comp = (rng.uniform(size=n) < 0.4).astype(np.int8)
+    gal = np.zeros(n, np.int8)
+    lost = np.zeros(n, bool)
+    dt = 0.05
+    d = sysm.diagnostics(x, v, m, comp, gal, lost, dt)
+    x1, v1, lost1, acc = sysm.step(x, v, m, gal, lost, dt)
+    assert lost1[0] and not lost1[1:].any()
+    vs = 0.5 * (v + v1)
+    for c in (0, 1):
+        s = (comp == c) & ~lost1
+        assert d["ekin"][c] == pytest.approx(0.5 * np.sum(m[s] * np.sum(vs[s] ** 2, axis=1)), rel=1e-13)
+        Lc = np.sum(m[s, None] * np.cross(x[s], vs[s]), axis=0)
+        assert np.allclose(d["L"][c], Lc, rtol=1e-12, atol=1e-15)
+    # the half kick is a visible part of E_kin here
+    s = (comp == 0) & ~lost1
+    e_old = 0.5 * np.sum(m[s] * np.sum(v[s] ** 2, axis=1))
+    assert abs(d["ekin"][0] / e_old - 1.0) > 1e-4
+    assert d["n_lost"] == 1
+
+
+def test_disc_dispersions_hand_placed():
+    """sigma_R and sigma_z of the disc (live component 0 of galaxy 0) about
+    galaxy 0's centre, unweighted, on four particles whose radial and vertical
+    velocities are (1, 3, -1, 5) and (0.2, -0.4, 0.6, 0): sigma_R = sqrt(5),
+    sigma_z = sqrt(0.13).  A bulge particle and a lost disc particle with
+    large velocities must not enter."""
+    c = np.array([0.5, -0.25, 0.0])
+    L = O.Level(32, 2.5, centre=c)
+    sysm = O.System([O.Hierarchy([L], "fixed", c)])
+    d = np.array([[1.0, 0.0, 0.1], [0.0, 1.0, -0.1], [-1.0, 0.0, 0.0], [0.0, -1.0, 0.05],
+                  [0.3, 0.3, 0.0], [0.2, -0.1, 0.0]])
+    v = np.array([[1.0, 0.7, 0.2], [0.3, 3.0, -0.4], [1.0, -0.5, 0.6], [0.1, -5.0, 0.0],
+                  [9.0, 9.0, 9.0], [-7.0, 8.0, -6.0]])
+    x = c + d
+    m = np.array([1.0, 2.0, 0.5, 1.5, 3.0, 1.0]) * 1e-3
+    comp = np.array([0, 0, 0, 0, 1, 0], np.int8)
+    lost = np.array([False] * 5 + [True])
+    out = sysm.diagnostics(x, v, m, comp, np.zeros(6, np.int8), lost, 0.0)
+    assert out["disc_sigR"] == pytest.approx(np.sqrt(5.0), rel=1e-14)
+    assert out["disc_sigz"] == pytest.approx(np.sqrt(0.13), rel=1e-13)
+
+
+# ------------------------------------------------------- centre of mass -----
+def test_centre_of_mass_hand_placed():
+    """Centre-of-mass centring (Sec. 2.1) of two galaxies: each galaxy's live
+    particles only.  Galaxy 0: masses 1, 2, 3 at (0,0,0), (1,0,0), (0,1,0.5)
+    -> (1/3, 1/2, 1/4); galaxy 1: masses 2, 2 at (3,0,0), (5,2,0) -> (4,1,0).
+    A heavy lost particle in each galaxy is left out."""
+    lv = lambda: [O.Level(32, 1.0), O.Level(32, 4.0), O.Level(32, 20.0)]
+    sysm = O.System([O.Hierarchy(lv(), "com"), O.Hierarchy(lv(), "com")])
+    x = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0.5], [5, 5, 5], [3, 0, 0], [5, 2, 0], [-3, -3, 0]],
+                 float)
+    m = np.array([1.0, 2.0, 3.0, 10.0, 2.0, 2.0, 7.0])
+    gal = np.array([0, 0, 0, 0, 1, 1, 1], np.int8)
+    lost = np.array([False, False, False, True, False, False, True])
+    c = sysm.centres(x, m, gal, lost)
+    assert np.allclose(c[0], [1.0 / 3.0, 0.5, 0.25], rtol=1e-15, atol=0)
+    assert np.allclose(c[1], [4.0, 1.0, 0.0], rtol=1e-15, atol=0)
