@@ -14,7 +14,7 @@ isolated direct sum of Eq. 1 with the Green's function of Eq. 2) the oracle
 computes that definition; everything around it (nearest-grid-point cells,
 Eq. 8 differencing, the five grids and their selection rule, leapfrog) is an
 approximation scheme and is followed step by step in the paper's order.  The
-FFT route of Eqs. 3-5 uses numpy's FFT as a library step.
+FFT route of Eqs. 3-5 uses a library FFT (scipy.fft) as a step.
 
 Readings of points the paper leaves open (each one is also used by the GPU
 library, and listed in the design notes):
@@ -40,7 +40,21 @@ their docstring.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft as _fft
+
+# Threads of the library FFT used as a step of Eqs. 3-5 (pocketfft through
+# scipy.fft; the transform is the same whatever the count).
+_FFT_WORKERS = os.cpu_count() or 1
+
+
+def set_fft_workers(n: int) -> int:
+    """Set the number of threads of the oracle's FFT steps; returns the old one."""
+    global _FFT_WORKERS
+    old, _FFT_WORKERS = _FFT_WORKERS, max(1, int(n))
+    return old
 
 CORE, RING, OUTER, LOST = 0, 1, 2, 3
 
@@ -305,7 +319,7 @@ def green_hat(L: Level, h0_mode: int = 0):
 
     Returns (Hhat real (2N)^3, max|Im| / max|Re|).
     """
-    F = np.fft.fftn(green_extended(L, h0_mode))
+    F = _fft.fftn(green_extended(L, h0_mode), workers=_FFT_WORKERS)
     rel_imag = float(np.abs(F.imag).max() / np.abs(F.real).max())
     return F.real.copy(), rel_imag
 
@@ -319,9 +333,9 @@ def solve_fft(M, Hhat, G=1.0):
     N = M.shape[0]
     P = np.zeros((2 * N,) * 3)
     P[:N, :N, :N] = M
-    rho_hat = np.fft.rfftn(P)
+    rho_hat = _fft.rfftn(P, workers=_FFT_WORKERS)
     prod = rho_hat * Hhat[:, :, : N + 1]
-    return G * np.fft.irfftn(prod, s=P.shape, axes=(0, 1, 2))[:N, :N, :N]
+    return G * _fft.irfftn(prod, s=P.shape, axes=(0, 1, 2), workers=_FFT_WORKERS)[:N, :N, :N]
 
 
 def solve_direct(M, L: Level, G=1.0, h0_mode: int = 0):

@@ -53,38 +53,58 @@ def test_galaxy_satellite_full_size_sampled(sbx, merge):
     cg = ctx.sbx_get_centres()
     for g in range(2):
         assert np.allclose(cg[g], centres[g], rtol=0, atol=1e-12 * (1 + np.abs(centres[g]).max()))
-        cls_ref, idx_ref = O.classify(x[s], sysm.h[g], centres[g])
+        cls_ref, idx_ref = O.classify(x[s], sysm.h[g], cg[g])
         for level in range(3):
             idx, cls = ctx.sbx_get_indices(g, level)
             assert np.array_equal(cls[s], cls_ref), (g, level)
             assert np.array_equal(idx[s].astype(np.int64), idx_ref[level]), (g, level)
 
 
-def test_ensemble_full_size_batch_step(sbx):
-    """All 16 instances in one batch, one step (cell sort included); the two
-    smallest-grid instances are checked against the oracle's step."""
+@pytest.fixture(scope="module")
+def ensemble_stepped(sbx):
+    """All 16 instances in one batch (one graph replay per step), one step
+    with the cell sort; returns the workloads and each instance's state."""
     ws = synth.ensemble()
     ctxs = [T.make_ctx(w, sbx.SBX_FP32) for w in ws]
     b = sbx.Batch(ctxs)
     b.sbx_batch_step(0.01, 1)
     b.sbx_batch_sync()
     b.close()
-    order = sorted(range(len(ws)), key=lambda i: (ws[i].hier[0].levels[0].N, ws[i].n))
-    for i in order[:2]:
-        w = ws[i]
-        sysm = T.oracle_system(w)
-        x, v, m = T.oracle_inputs(w, sbx.SBX_FP32)
-        lost = np.zeros(w.n, bool)
-        x, v, lost, _ = sysm.step(x, v, m, w.gal, lost, 0.01)
-        xg, vg, lg = ctxs[i].sbx_get_particles()
-        assert np.array_equal(lg, lost), w.name
-        vr = np.sqrt(np.mean(np.sum(v * v, axis=1)))
-        ev = np.linalg.norm(vg - v, axis=1) / vr
-        print(f"{w.name}: n {w.n}, velocity error p99 {np.percentile(ev, 99):.2e} max {ev.max():.2e}")
-        assert np.percentile(ev, 99) < 1e-4, w.name
-        assert np.max(np.abs(xg - x)) < 1e-4, w.name
+    states = [c.sbx_get_particles() for c in ctxs]
     for c in ctxs:
         c.close()
+    return ws, states
+
+
+def _check_instance(sbx, w, state):
+    sysm = T.oracle_system(w)
+    x, v, m = T.oracle_inputs(w, sbx.SBX_FP32)
+    lost = np.zeros(w.n, bool)
+    x, v, lost, _ = sysm.step(x, v, m, w.gal, lost, 0.01)
+    xg, vg, lg = state
+    assert np.array_equal(lg, lost), w.name
+    vr = np.sqrt(np.mean(np.sum(v * v, axis=1)))
+    ev = np.linalg.norm(vg - v, axis=1) / vr
+    print(f"{w.name}: n {w.n}, velocity error p99 {np.percentile(ev, 99):.2e} max {ev.max():.2e}")
+    assert np.percentile(ev, 99) < 1e-4, w.name
+    assert np.max(np.abs(xg - x)) < 1e-4, w.name
+
+
+def _ensemble_pick(ws, N, k):
+    """Index of the k-th smallest instance (by particle count) of grid size N."""
+    ids = sorted((i for i in range(len(ws)) if ws[i].hier[0].levels[0].N == N), key=lambda i: ws[i].n)
+    return ids[k]
+
+
+@pytest.mark.parametrize("N,k", [(64, 0), (64, 1), (128, 0), (256, 0)])
+def test_ensemble_full_size_batch_step(sbx, ensemble_stepped, N, k):
+    """One batch step of the 16-instance ensemble against the oracle's step of
+    single instances: the two smallest 64^3 instances and the smallest 128^3
+    and 256^3 ones (each size group has its own launch shapes, work counters
+    and graph nodes in the batch)."""
+    ws, states = ensemble_stepped
+    i = _ensemble_pick(ws, N, k)
+    _check_instance(sbx, ws[i], states[i])
 
 
 @pytest.mark.parametrize("prec", [0, 1])  # SBX_FP32, SBX_FP64
@@ -122,3 +142,31 @@ def test_disc_galaxy_full_size_steps(sbx, prec):
     print(f"velocity error p99 {np.percentile(ev, 99):.2e} max {ev.max():.2e} of rms")
     assert np.percentile(ev, 99) < 1e-4 and ev.max() < 1e-3
     assert np.max(np.abs(xg[both] - x[both])) < 1e-4
+
+
+def test_disc_galaxy_fp32_diagnostics_records(sbx):
+    """The precision form's FP64 diagnostics (FP32 fields and particles, FP64
+    reductions in the moving force pass) on the full 3 x 128^3 disc galaxy,
+    8.5M particles: the in-step records of two steps (diag_every = 1)
+    against the oracle's diagnostics of the same states -- the initial one,
+    and the library's state after the first step -- at the FP32 bars of
+    test_gpu_parity."""
+    from tests.test_gpu_parity import assert_diag_close
+    w = synth.disc_galaxy(scale=1.0)
+    sysm = T.oracle_system(w)
+    ctx = T.make_ctx(w, sbx.SBX_FP32)
+    states = []
+    for _ in range(2):
+        states.append(ctx.sbx_get_particles())
+        ctx.sbx_step(w.dt, 1, 1)
+    log = ctx.sbx_diag_log()
+    ctx.close()
+    assert len(log) == 2
+    m = T.rounded(w.m, sbx.SBX_FP32)
+    for k, (xg, vg, lg) in enumerate(states):
+        ref = sysm.diagnostics(xg, vg, m, w.comp, w.gal, lg.astype(bool), w.dt)
+        e = [float(np.abs(log[k]["ekin"][:3] / ref["ekin"][:3] - 1).max()),
+             float(np.abs(log[k]["epot"][:3] / ref["epot"][:3] - 1).max())]
+        print(f"record {k}: E_kin rel {e[0]:.2e}, W rel {e[1]:.2e}, sigma_R "
+              f"{abs(log[k]['disc_sigR'] / ref['disc_sigR'] - 1):.2e}")
+        assert_diag_close(log[k], ref, sbx.SBX_FP32, m, xg, vg)

@@ -61,7 +61,7 @@ def test_six_galaxies_forces_and_classes(sbx, prec):
     cg = ctx.sbx_get_centres()
     for g in range(6):
         assert np.allclose(cg[g], centres[g], rtol=0, atol=1e-13 * (1 + np.abs(centres[g]).max()))
-        cls_ref, idx_ref = O.classify(x, sysm.h[g], centres[g])
+        cls_ref, idx_ref = O.classify(x, sysm.h[g], cg[g])
         idx, cls = ctx.sbx_get_indices(g, 0)
         assert np.array_equal(cls, cls_ref), g
         assert np.array_equal(idx.astype(np.int64), idx_ref[0]), g
