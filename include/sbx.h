@@ -30,8 +30,9 @@
  *     (usable cells [2, N-3] per axis, Table 3); z cell length q*l; cell of
  *     Eq. 7 = floor(((x - c) * gamma + N/2) + 0.5) in float64 with each
  *     operation rounded; membership by the spheroidal radius
- *     (dx^2 + dy^2) + (dz/q)^2 < R^2; H(0,0,0) = H(1,0,0) unless h0_mode = 2
- *     (zero); velocities are staggered, v = v(t - dt/2).
+ *     (dx^2 + dy^2) + (dz/q)^2 < R^2; H(0,0,0) = H(1,0,0) unless h0_mode
+ *     is 1 (cell mean of 1/r) or 2 (zero); velocities are staggered,
+ *     v = v(t - dt/2).
  */
 #ifndef SBX_H
 #define SBX_H
@@ -48,7 +49,10 @@ typedef enum {
   SBX_ENOMEM = -2,   /* device or host allocation failed                     */
   SBX_EDEVICE = -3,  /* HIP runtime error (no device, launch failure, ...)   */
   SBX_EQCRIT = -4,   /* flattening below q_crit of Eq. 9                     */
-  SBX_ESTATE = -5    /* call out of order (e.g. step before build_grids)     */
+  SBX_ESTATE = -5,   /* call out of order (e.g. step before build_grids)     */
+  SBX_EPARITY = -6   /* a self-check of the method failed: the FP64 transform
+                        of the mirrored Green's function (Eq. 5) is not real
+                        to rounding (max|Im| / max|Re| above 1e-10)          */
 } sbx_status;
 
 typedef enum { SBX_FP32 = 0, SBX_FP64 = 1 } sbx_prec;
@@ -94,7 +98,10 @@ typedef struct {
 typedef struct {
   int32_t prec;     /* sbx_prec: arithmetic of grids, FFT, forces, particles */
   double G;         /* gravitational constant                                 */
-  int32_t h0_mode;  /* H(0,0,0): 0 = H(1,0,0) = 1/l (default), 2 = 0          */
+  int32_t h0_mode;  /* H(0,0,0), singular in Eq. 2: 0 = H(1,0,0) = 1/l
+                       (default), 1 = mean of 1/r over the cell (closed form
+                       of a uniform prism; 2.3800774/l in a cubic cell),
+                       2 = 0                                                  */
   int32_t taylor;   /* 1 = full Eq. 8, 0 = central differences only           */
   int32_t device;   /* HIP device ordinal                                     */
   void* stream;     /* hipStream_t to run on, or NULL for a private stream    */
@@ -152,7 +159,9 @@ sbx_status sbx_load_particles_device(sbx_ctx* ctx, int64_t n, const double* x, c
 /* Validate the hierarchies and build the Green's tables (Sec. 2.1: the
  * transformed H is computed once): H of Eq. 2 on lags 0..N, mirrored to
  * (2N)^3 by Eq. 5, transformed by an FP64 FFT, scaled by G/(2N)^3 and stored
- * on (N+1)^3 (it is real and even per axis).  Allocates the grids. */
+ * on (N+1)^3 (it is real and even per axis).  Allocates the grids.
+ * SBX_EQCRIT below q_crit, SBX_EPARITY if a transformed table is not real to
+ * rounding (max|Im| / max|Re| > 1e-10), SBX_ENOMEM, SBX_EINVAL. */
 sbx_status sbx_build_grids(sbx_ctx* ctx, int32_t n_galaxies, const sbx_hierarchy* h);
 /* (1 <= n_galaxies <= 8; every galaxy's grids are solved and summed into the
  * forces of all particles, Sec. 2.1: the number of galaxies is not fixed.) */
@@ -347,7 +356,8 @@ sbx_status sbx_profile_end(sbx_ctx* ctx, int32_t n_phases, double* out_ms, int64
 /* ---- standalone isolated Poisson solves (Eqs. 1-5) ------------------------ */
 
 /* Plan for isolated solves on one geometry (n, R, q) in precision prec.
- * Builds the Green's table as sbx_build_grids does. */
+ * Builds the Green's table as sbx_build_grids does (h0_mode as in
+ * sbx_config; SBX_EPARITY as in sbx_build_grids). */
 sbx_status sbx_poisson_create(int32_t n, double R, double q, double G, int32_t h0_mode,
                               int32_t prec, int32_t device, void* stream, sbx_poisson** out);
 void sbx_poisson_destroy(sbx_poisson* p);

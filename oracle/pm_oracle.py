@@ -23,7 +23,7 @@ library, and listed in the design notes):
   * grids hold cell MASS; H uses physical distances, so Eq. 1 reads
     Phi[a] = G * sum M[xi] / |(xi-a) * (lx, ly, lz)|;
   * H(0,0,0) (singular in Eq. 2) is H(1,0,0) = 1/lx by default (h0_mode 0),
-    or 0 (h0_mode 2);
+    the mean of 1/r over the cell (h0_mode 1) or 0 (h0_mode 2);
   * Phi_paper = +G sum M H is positive and the acceleration is +grad Phi_paper
     (Eq. 8); the physical potential reported is phi = -Phi_paper;
   * nearest integer of Eq. 7: u = (x - c) * gamma + N/2 as separate float64
@@ -284,12 +284,35 @@ def deposit(idx, m, N):
 # --------------------------------------------------------------------------
 # Green's function and the isolated solve (Eqs. 1-5)
 # --------------------------------------------------------------------------
+def cell_mean_inverse_distance(lx, ly, lz):
+    """Mean of 1/r over a cell of sides (lx, ly, lz) about its centre.
+
+    The integral of 1/r over the box [0,a] x [0,b] x [0,c] with r measured
+    from a corner is the textbook potential of a uniform rectangular prism,
+      F = bc asinh(a / sqrt(b^2 + c^2)) + ac asinh(b / sqrt(a^2 + c^2))
+        + ab asinh(c / sqrt(a^2 + b^2)) - a^2/2 atan(bc / (a r))
+        - b^2/2 atan(ac / (b r)) - c^2/2 atan(ab / (c r)),  r = |(a, b, c)|;
+    the cell is eight such octants of half-sides.
+    """
+    a, b, c = 0.5 * lx, 0.5 * ly, 0.5 * lz
+    r = np.sqrt(a * a + b * b + c * c)
+    F = (b * c * np.arcsinh(a / np.hypot(b, c)) + a * c * np.arcsinh(b / np.hypot(a, c))
+         + a * b * np.arcsinh(c / np.hypot(a, b)) - 0.5 * a * a * np.arctan(b * c / (a * r))
+         - 0.5 * b * b * np.arctan(a * c / (b * r)) - 0.5 * c * c * np.arctan(a * b / (c * r)))
+    return float(8.0 * F / (lx * ly * lz))
+
+
 def h0_value(L: Level, h0_mode: int) -> float:
+    """H(0,0,0), which Eq. 2 leaves singular: H(1,0,0) = 1/l (h0_mode 0), the
+    mean of 1/r over the cell (h0_mode 1, the cell's own mass spread
+    uniformly), or 0 (h0_mode 2)."""
     if h0_mode == 0:
         return 1.0 / L.l
+    if h0_mode == 1:
+        return cell_mean_inverse_distance(L.l, L.l, L.lz)
     if h0_mode == 2:
         return 0.0
-    raise ValueError("h0_mode must be 0 (H(1,0,0)) or 2 (zero)")
+    raise ValueError("h0_mode must be 0 (H(1,0,0)), 1 (cell mean) or 2 (zero)")
 
 
 def green_table(L: Level, h0_mode: int = 0):

@@ -650,8 +650,8 @@ sbx_status sbx_create(const sbx_config* cfg, sbx_ctx** out) {
     set_error("prec must be SBX_FP32 or SBX_FP64");
     return SBX_EINVAL;
   }
-  if (cfg->h0_mode != 0 && cfg->h0_mode != 2) {
-    set_error("h0_mode must be 0 or 2");
+  if (cfg->h0_mode < 0 || cfg->h0_mode > 2) {
+    set_error("h0_mode must be 0, 1 or 2");
     return SBX_EINVAL;
   }
   if (!std::isfinite(cfg->G) || !(cfg->G > 0.0)) {

@@ -945,6 +945,22 @@ static sbx_status green_fft(C2<double>* F, hipStream_t st) {
   return SBX_OK;
 }
 
+// Mean of 1/r over a cell of sides (lx, ly, lz) about its centre: eight
+// octants of the integral of 1/r over a box [0,a]x[0,b]x[0,c] taken from a
+// corner (the potential of a uniform rectangular prism at its corner).
+static double cell_mean_inv_r(double lx, double ly, double lz) {
+  const double a = 0.5 * lx, b = 0.5 * ly, c = 0.5 * lz;
+  const double r = std::sqrt(a * a + b * b + c * c);
+  const double f = b * c * std::asinh(a / std::hypot(b, c)) + a * c * std::asinh(b / std::hypot(a, c)) +
+                   a * b * std::asinh(c / std::hypot(a, b)) - 0.5 * a * a * std::atan(b * c / (a * r)) -
+                   0.5 * b * b * std::atan(a * c / (b * r)) - 0.5 * c * c * std::atan(a * b / (c * r));
+  return 8.0 * f / (lx * ly * lz);
+}
+
+// Largest admissible max|Im| / max|Re| of the FP64 transform of the mirrored
+// Green's function: Eq. 5 makes it real, so only rounding may remain.
+constexpr double kGreenImagTol = 1e-10;
+
 template <typename T>
 sbx_status build_green(int N, double l, double lz, double G, int h0_mode, T* H, double* rel_imag,
                        hipStream_t st) {
@@ -961,7 +977,7 @@ sbx_status build_green(int N, double l, double lz, double G, int h0_mode, T* H, 
     set_error("out of device memory");
     return SBX_ENOMEM;
   }
-  const double h0 = h0_mode == 2 ? 0.0 : 1.0 / l;
+  const double h0 = h0_mode == 2 ? 0.0 : (h0_mode == 1 ? cell_mean_inv_r(l, l, lz) : 1.0 / l);
   sbx_status rc = SBX_OK;
   hipLaunchKernelGGL(k_green_fill, dim3(2048), dim3(256), 0, st, F, N, l, lz, h0);
   switch (N) {
@@ -983,11 +999,17 @@ sbx_status build_green(int N, double l, double lz, double G, int h0_mode, T* H, 
         hipStreamSynchronize(st) != hipSuccess) {
       set_error(std::string("Green's table build: ") + hipGetErrorString(hipGetLastError()));
       rc = SBX_EDEVICE;
-    } else if (rel_imag) {
+    } else {
       double re, im;
       memcpy(&re, &host[0], 8);
       memcpy(&im, &host[1], 8);
-      *rel_imag = re > 0 ? im / re : 0.0;
+      const double ri = re > 0 ? im / re : 1.0;
+      if (rel_imag) *rel_imag = ri;
+      if (!(ri <= kGreenImagTol)) {
+        set_error("transformed Green's function not real to rounding (max|Im|/max|Re| = " +
+                  std::to_string(ri) + "): the mirror symmetry of Eq. 5 is broken");
+        rc = SBX_EPARITY;
+      }
     }
   }
   (void)hipFree(mx);

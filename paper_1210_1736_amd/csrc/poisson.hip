@@ -119,7 +119,7 @@ extern "C" {
 sbx_status sbx_poisson_create(int32_t n, double R, double q, double G, int32_t h0_mode, int32_t prec,
                               int32_t device, void* stream, sbx_poisson** out) {
   if (!out || !is_pow2_grid(n) || !(R > 0.0) || !(q > 0.0) || !(q <= 1.0) || !(G > 0.0) ||
-      (h0_mode != 0 && h0_mode != 2) || (prec != SBX_FP32 && prec != SBX_FP64)) {
+      h0_mode < 0 || h0_mode > 2 || (prec != SBX_FP32 && prec != SBX_FP64)) {
     set_error("bad Poisson plan arguments");
     return SBX_EINVAL;
   }

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsbx.so")
 
-SBX_OK, SBX_EINVAL, SBX_ENOMEM, SBX_EDEVICE, SBX_EQCRIT, SBX_ESTATE = 0, -1, -2, -3, -4, -5
+SBX_OK, SBX_EINVAL, SBX_ENOMEM, SBX_EDEVICE, SBX_EQCRIT, SBX_ESTATE, SBX_EPARITY = 0, -1, -2, -3, -4, -5, -6
 SBX_FP32, SBX_FP64 = 0, 1
 SBX_CENTRE_FIXED, SBX_CENTRE_COM, SBX_CENTRE_DENSITY = 0, 1, 2
 CORE, RING, OUTER, LOST = 0, 1, 2, 3
@@ -24,7 +24,7 @@ PHASES = ["start", "zero", "pre", "deposit", "fwd_x", "fwd_y", "zpass", "inv_y",
           "sort"]
 
 _NAMES = {0: "SBX_OK", -1: "SBX_EINVAL", -2: "SBX_ENOMEM", -3: "SBX_EDEVICE", -4: "SBX_EQCRIT",
-          -5: "SBX_ESTATE"}
+          -5: "SBX_ESTATE", -6: "SBX_EPARITY"}
 
 
 class SbxError(RuntimeError):

@@ -52,6 +52,41 @@ def test_green_table_matches_oracle(sbx, N, q, prec):
     assert np.max(np.abs(Hs - ref)) <= tol * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("h0", [0, 1, 2])
+@pytest.mark.parametrize("N,q", [(16, 1.0), (64, 0.25)])
+@pytest.mark.parametrize("prec", PRECS)
+def test_green_table_h0_readings(sbx, N, q, h0, prec):
+    """The three readings of the singular H(0,0,0) (h0_mode 0: H(1,0,0),
+    1: mean of 1/r over the cell, 2: zero) against the oracle's tables."""
+    R = 2.0
+    p = sbx.Poisson(N, R, q, G=1.0, h0_mode=h0, prec=prec)
+    Hs, rel_imag = p.sbx_poisson_green()
+    assert rel_imag < 1e-13
+    Hh, _ = O.green_hat(O.Level(N, R, q), h0)
+    ref = Hh[: N + 1, : N + 1, : N + 1] / (2 * N) ** 3
+    tol = 1e-12 if prec == sbx.SBX_FP64 else 2e-7
+    assert np.max(np.abs(Hs - ref)) <= tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("h0", [1, 2])
+def test_forces_h0_readings_fp64(sbx, h0):
+    """Fields and forces of the nested galaxy with the other readings of
+    H(0,0,0), through sbx_create's h0_mode, against the oracle."""
+    w = T.small_galaxy(scale=0.003, N=32, q=0.5)
+    sysm = T.oracle_system(w, h0_mode=h0)
+    lost = sysm.lost_now(w.x)
+    centres = sysm.centres(w.x, w.m, w.gal, lost)
+    pots = sysm.potentials(w.x, w.m, w.gal, lost, centres)
+    ctx = T.make_ctx(w, sbx.SBX_FP64, h0_mode=h0)
+    acc, pot = ctx.sbx_compute_forces()
+    for k, ref in enumerate(_slots(pots[0]["Phi"])):
+        g = ctx.sbx_get_grid(0, k, 1).transpose(2, 1, 0)
+        assert np.max(np.abs(g - ref)) <= 1e-11 * np.max(np.abs(ref)), k
+    a_ref, P_ref = sysm.accel(w.x, w.m, w.gal, lost, centres, pots, want_pot=True)
+    assert T.rel_err_vec(acc, a_ref).max() < 1e-9
+    assert np.abs(pot + P_ref).max() < 1e-11 * np.abs(P_ref).max()
+
+
 # ----------------------------------------------------------- Poisson solve --
 def _solve_gpu(sbx, torch, N, R, q, Ms, prec, G=1.0):
     dt = torch.float64 if prec == sbx.SBX_FP64 else torch.float32

@@ -483,3 +483,36 @@ def test_centre_of_mass_hand_placed():
     c = sysm.centres(x, m, gal, lost)
     assert np.allclose(c[0], [1.0 / 3.0, 0.5, 0.25], rtol=1e-15, atol=0)
     assert np.allclose(c[1], [4.0, 1.0, 0.0], rtol=1e-15, atol=0)
+
+
+# ------------------------------------------------- H(0,0,0) readings -------
+@pytest.mark.parametrize("sides", [(1.0, 1.0, 1.0), (1.0, 1.0, 0.25), (0.3, 0.3, 0.15)])
+def test_cell_mean_h0_against_quadrature(sides):
+    """h0_mode 1: the mean of 1/r over the cell, from the closed form of the
+    potential of a uniform prism, against adaptive cubature of 1/r over one
+    octant (unit cube: 2.3800773640)."""
+    from scipy import integrate
+    lx, ly, lz = sides
+    f = lambda z, y, x: 1.0 / np.sqrt(x * x + y * y + z * z)
+    v, _ = integrate.tplquad(f, 0, lx / 2, 0, ly / 2, 0, lz / 2, epsabs=1e-13, epsrel=1e-12)
+    ref = 8.0 * v / (lx * ly * lz)
+    assert O.cell_mean_inverse_distance(lx, ly, lz) == pytest.approx(ref, rel=1e-11)
+    L = O.Level(16, 1.0, lz / lx)
+    assert O.h0_value(L, 1) == pytest.approx(O.cell_mean_inverse_distance(L.l, L.l, L.lz), rel=1e-15)
+    if sides == (1.0, 1.0, 1.0):
+        assert ref == pytest.approx(2.3800773640, abs=1e-10)
+
+
+def test_h0_mode_changes_only_the_own_cell_term():
+    """The three readings of H(0,0,0) differ only in the zero-lag term: the
+    fields of a point mass differ by G m (h0 - h0') in its own cell alone."""
+    N = 16
+    L = O.Level(N, 2.0, 0.5)
+    M = np.zeros((N, N, N)); M[5, 7, 9] = 0.8
+    f = {k: O.solve_fft(M, O.green_hat(L, k)[0]) for k in (0, 1, 2)}
+    for a, b in ((0, 1), (1, 2), (0, 2)):
+        d = f[a] - f[b]
+        want = 0.8 * (O.h0_value(L, a) - O.h0_value(L, b))
+        assert d[5, 7, 9] == pytest.approx(want, rel=1e-11)
+        d[5, 7, 9] = 0.0
+        assert np.abs(d).max() < 1e-12 * np.abs(f[a]).max()
