@@ -234,7 +234,7 @@ sbx_status sbx_adjoint_segment_device(sbx_ctx* ctx, double dt, int32_t nsteps, i
                                       int32_t sel_comp, int32_t sel_gal, double* loss,
                                       double* grad_m, double* grad_x, double* grad_v);
 
-/* Disc diagnostics of the paper's analysis (Sec. 5.2, 6.3, 6.4).
+/* Disc diagnostics of the paper's analysis (Sec. 4.2, 5.2-5.4).
  * The disc is the live particles of component `comp` of galaxy `galaxy`;
  * positions are taken relative to that galaxy's centre at the last solve
  * (its given centre before any solve) and velocities (the stored staggered
@@ -273,7 +273,7 @@ sbx_status sbx_disc_analysis(sbx_ctx* ctx, const sbx_disc_query* q, sbx_disc_res
                              double* bin_r, double* bin_vc, double* bin_rms_z, double* rho_z);
 
 /* Fourier coefficients of the disc's surface density in annular bins
- * (Sec. 6.6): for bin k = [k dR, (k+1) dR), dR = r_max / n_rbins, and
+ * (Sec. 5.6): for bin k = [k dR, (k+1) dR), dR = r_max / n_rbins, and
  * m = 0..m_max, A_m = (1/S_k) sum over the bin's particles of M exp(-i m phi)
  * with phi the polar angle about the galaxy centre and S_k the bin area.
  * Same disc selection and centre as sbx_disc_analysis.  coeff (host):

@@ -786,7 +786,7 @@ def segment_loss_and_grads(sysm: System, x, v, m, comp, gal, dt, nsteps, sel_com
 
 
 # --------------------------------------------------------------------------
-# Disc diagnostics of the paper's analysis (Sec. 5: heat, thickness,
+# Disc diagnostics of the paper's analysis (Sec. 4.2 and 5.2-5.4: heat, thickness,
 # vertical profile, velocity dispersions near the solar radius)
 # --------------------------------------------------------------------------
 def disc_analysis(x, v, m, comp, gal, lost, centre, n_bins, annulus, n_z, z_max,
@@ -795,17 +795,17 @@ def disc_analysis(x, v, m, comp, gal, lost, centre, n_bins, annulus, n_z, z_max,
     galaxy disc_gal), with positions relative to `centre` and velocities
     relative to the disc's mass-weighted mean velocity.
 
-    * Radial bins of equal particle numbers (Sec. 5.2 and 6.3): particles
+    * Radial bins of equal particle numbers (Sec. 4.2 and 5.3): particles
       ordered by cylindrical R (ties by particle index), bin k holding
       n // n_bins particles plus one for k < n % n_bins.  Per bin: mean R,
       mean circular velocity (mean v_phi) and RMS z (sqrt of mean z^2).
-    * Heat (Sec. 6.3): E = sum 1/2 m |v - vbar_c(R)|^2, with vbar_c the bin
+    * Heat (Sec. 5.3, Eq. 14): E = sum 1/2 m |v - vbar_c(R)|^2, with vbar_c the bin
       values linearly interpolated in R between the bins' mean radii (held
       constant beyond the first and last) and directed along phi.
     * In the annulus R_lo <= R < R_hi: sigma_R, sigma_phi, sigma_z (about the
       annulus means), sigma_tot^2, and the vertical density profile: mass in
       n_z equal bins of z over [-z_max, z_max) divided by the annulus area
-      times the bin width (Sec. 5.2).
+      times the bin width (Sec. 4.2 and 5.2).
     Unweighted means over particles (the disc particles have equal masses in
     the paper's models).  parity unpinned beyond its closed-form pins.
     """
@@ -858,7 +858,7 @@ def disc_analysis(x, v, m, comp, gal, lost, centre, n_bins, annulus, n_z, z_max,
 
 
 def disc_modes(x, m, comp, gal, lost, centre, n_rbins, r_max, m_max, disc_comp=0, disc_gal=0):
-    """Fourier coefficients of the disc's surface density (Sec. 6.6): in
+    """Fourier coefficients of the disc's surface density (Sec. 5.6): in
     annular bins [k dR, (k+1) dR), A_m = (1/S_k) sum M exp(-i m phi) over the
     bin's particles, phi the polar angle about `centre`, S_k the bin area.
     Returns an (n_rbins, m_max + 1) complex array.  parity unpinned beyond

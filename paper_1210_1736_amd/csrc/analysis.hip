@@ -1,4 +1,4 @@
-// Disc diagnostics of the paper's analysis (Sec. 5.2 and 6.3-6.4): heat of
+// Disc diagnostics of the paper's analysis (Sec. 4.2 and 5.2-5.4): heat of
 // the disc with the mean circular velocity from radial bins of equal
 // particle numbers, RMS thickness per bin, vertical density profile and
 // velocity dispersions in an annulus.  The radial order comes from a stable

@@ -1,5 +1,5 @@
-"""Reduced isolated-disc heating experiment (Sec. 5.2; diagnostics of
-Sec. 6.3-6.4): one disc galaxy evolved in isolation on three nested grids of
+"""Reduced isolated-disc heating experiment (Sec. 4, Table 3; diagnostics of
+Sec. 4.2 and 5.2-5.4): one disc galaxy evolved in isolation on three nested grids of
 N^3 cells whose inner two levels are flattened to q, with the disc's heat,
 velocity dispersions and thickness recorded along the way.  The paper runs
 this sweep over N and q on its relaxed model for a gigayear; here it runs on

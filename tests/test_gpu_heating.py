@@ -1,4 +1,4 @@
-"""The reduced heating experiment (Sec. 5.2) on the GPU: its diagnostics
+"""The reduced heating experiment (Sec. 4, Table 3) on the GPU: its diagnostics
 series against the oracle stepping the same galaxy (FP64, a few steps), and
 the sweep's handling of configurations below q_crit (Eq. 9)."""
 import numpy as np
