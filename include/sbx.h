@@ -156,6 +156,24 @@ sbx_status sbx_load_particles(sbx_ctx* ctx, int64_t n, const double* x, const do
 sbx_status sbx_load_particles_device(sbx_ctx* ctx, int64_t n, const double* x, const double* v,
                                      const double* m, const int8_t* comp, const int8_t* gal);
 
+/* Borrow the particle storage of the caller (e.g. torch tensors) instead
+ * of copying it in.  All arrays are device memory of the context's device;
+ * x, v, m are in the context precision (float for SBX_FP32, double for
+ * SBX_FP64) and laid out as structures of arrays: x[k * n + i] is coordinate
+ * k of particle i (a 3 x n row-major array), v likewise (v(t - dt/2)), m[n];
+ * comp, gal: n int8 as in sbx_load_particles; lost: n uint8 (0 = live), read
+ * and written by the library.  Steps move x and v and set lost in place on
+ * the context stream; getters copy from them.  The storage is borrowed until
+ * sbx_destroy or the next sbx_load_particles*, sbx_bind_device_particles or
+ * sbx_load: the caller keeps it alive and orders its own work on it with the
+ * context stream.  Bound particles are never reordered (the cell sort, a
+ * performance setting only, is skipped), and a context holding them cannot
+ * join a batch.  Validated on the device as sbx_load_particles_device
+ * (SBX_EINVAL); x, v and lost must not overlap any other array (SBX_EINVAL).
+ * Lost flags are taken as given. */
+sbx_status sbx_bind_device_particles(sbx_ctx* ctx, int64_t n, void* x, void* v, void* m,
+                                     int8_t* comp, int8_t* gal, uint8_t* lost);
+
 /* Validate the hierarchies and build the Green's tables (Sec. 2.1: the
  * transformed H is computed once): H of Eq. 2 on lags 0..N, mirrored to
  * (2N)^3 by Eq. 5, transformed by an FP64 FFT, scaled by G/(2N)^3 and stored
@@ -301,8 +319,31 @@ sbx_status sbx_set_outer_merge(sbx_ctx* ctx, int32_t merge);
  * particle order. */
 sbx_status sbx_set_sort_interval(sbx_ctx* ctx, int32_t every);
 
+/* Checkpoint files (Sec. 3.1 and 4.1: models are evolved in isolation, kept
+ * and reused).  sbx_save writes the whole state of a context: precision, G,
+ * h0_mode, taylor, the hierarchies, the outer-merge and sort settings, the
+ * step count and last dt, the centres of the last solve (the state density-
+ * maximum centring continues from), and the particles in the caller's order
+ * (x, staggered v, m, comp, gal, lost).  The diagnostics log is not saved.
+ * Synchronises.  SBX_ESTATE without grids or particles, SBX_EINVAL when the
+ * file cannot be written.
+ * sbx_load restores such a file into a context created with the same
+ * precision, G, h0_mode and taylor setting (SBX_EINVAL otherwise, and for a
+ * file that is not a version-1 checkpoint, truncated or corrupt): it rebuilds
+ * the grids and Green's tables, loads the particles (owned copies) with
+ * their lost flags, and restores the step count, dt, centres and settings.
+ * Stepping on from a loaded state gives what stepping the saved context
+ * would have given, up to the summation order of the mass assignment (bit
+ * for bit when every cell total is exact, e.g. dyadic masses, with fixed
+ * centres). */
+sbx_status sbx_save(sbx_ctx* ctx, const char* path);
+sbx_status sbx_load(sbx_ctx* ctx, const char* path);
+
 /* Block until all work queued on the context stream has finished. */
 sbx_status sbx_sync(sbx_ctx* ctx);
+
+/* Particles held (live and lost) and galaxies built; either may be NULL. */
+sbx_status sbx_get_counts(sbx_ctx* ctx, int64_t* n, int32_t* n_galaxies);
 
 /* Number of live particles (synchronises). */
 sbx_status sbx_count_live(sbx_ctx* ctx, int64_t* live);

@@ -245,6 +245,12 @@ void free_typed(P*& p) {
 }
 
 void free_particles(sbx_ctx* c) {
+  if (c->bound) {
+    // borrowed storage stays with the caller; only the id array is ours
+    free_typed(c->set[0].id);
+    c->set[0] = PSet();
+    c->bound = false;
+  }
   for (int s = 0; s < 2; ++s) {
     PSet& q = c->set[s];
     for (int k = 0; k < 3; ++k) {
@@ -564,7 +570,7 @@ sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, 
     SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&stage));
     // reorder by cell once for the segment (locality of the gathers and of
     // the adjoint scatter); nothing is reordered inside the segment
-    if (c->sort_every > 0) SBX_TRY(sort_particles(c));
+    if (c->sort_every > 0 && !c->bound) SBX_TRY(sort_particles(c));
     PSet& live = c->set[c->cur];
     // forward with checkpoints
     for (int k = 0; k < nsteps; ++k) {
@@ -775,7 +781,7 @@ sbx_status sbx_profile_end(sbx_ctx* c, int32_t n_phases, double* out_ms, int64_t
 
 }  // extern "C"
 
-namespace {
+namespace sbx {
 
 // Whether p is device memory of the given device (device or managed).
 bool on_device(const void* p, int device) {
@@ -966,7 +972,100 @@ sbx_status get_impl(sbx_ctx* c, double* x, double* v, uint8_t* lost, bool dev) {
   return rc;
 }
 
-}  // namespace
+// Borrowed particle storage: the caller's structure-of-arrays in the context
+// precision becomes the live particle set (never reordered).
+template <typename T>
+sbx_status bind_t(sbx_ctx* c, int64_t n, void* x, void* v, void* m, int8_t* comp, int8_t* gal,
+                  uint8_t* lost) {
+  const int ngal_limit = c->built ? c->ngal : kMaxGal;
+  unsigned long long* bad = nullptr;
+  SBX_TRY(dev_alloc((void**)&bad, sizeof(unsigned long long)));
+  unsigned long long first = ~0ull;
+  sbx_status rc = SBX_OK;
+  if (hipMemcpyAsync(bad, &first, sizeof(first), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      launch_validate_soa<T>((const T*)x, (const T*)v, (const T*)m, comp, gal, n, ngal_limit, bad,
+                             c->stream) != SBX_OK ||
+      hipMemcpyAsync(&first, bad, sizeof(first), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    set_error(std::string("particle validation: ") + hipGetErrorString(hipGetLastError()));
+    rc = SBX_EDEVICE;
+  }
+  (void)hipFree(bad);
+  SBX_TRY(rc);
+  if (first != ~0ull) {
+    set_error("particle " + std::to_string(first) +
+              ": masses must be finite and >= 0, positions and velocities finite, component id "
+              "in 0..7 and galaxy id within the hierarchies");
+    return SBX_EINVAL;
+  }
+  free_particles(c);
+  PSet& q = c->set[0];
+  for (int k = 0; k < 3; ++k) {
+    q.x[k] = (T*)x + (size_t)k * n;
+    q.v[k] = (T*)v + (size_t)k * n;
+  }
+  q.m = m;
+  q.comp = comp;
+  q.gal = gal;
+  q.lost = lost;
+  c->bound = true;
+  c->n = n;
+  c->cur = 0;
+  if (dev_alloc((void**)&q.id, sizeof(int32_t) * n) != SBX_OK) {
+    const std::string msg = sbx_last_error();
+    free_particles(c);
+    set_error(msg);
+    return SBX_ENOMEM;
+  }
+  SBX_TRY(launch_iota(q.id, n, c->stream));
+  SBX_TRY(launch_mass_max<T>((const T*)m, n, c->dm_mmax, c->stream));
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  c->solved = false;
+  c->grids_fields = false;
+  c->com_fresh = false;
+  c->step_count = 0;
+  return upload_inst(c);
+}
+
+sbx_status bind_impl(sbx_ctx* c, int64_t n, void* x, void* v, void* m, int8_t* comp, int8_t* gal,
+                     uint8_t* lost) {
+  if (!c || n <= 0 || !x || !v || !m || !comp || !gal || !lost) {
+    set_error("null argument or n <= 0");
+    return SBX_EINVAL;
+  }
+  if (n >= ((int64_t)1 << 31)) {
+    set_error("at most 2^31 - 1 particles per context");
+    return SBX_EINVAL;
+  }
+  if (c->batch) {
+    set_error("the context belongs to a batch");
+    return SBX_ESTATE;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  for (const void* p : {(const void*)x, (const void*)v, (const void*)m, (const void*)comp,
+                        (const void*)gal, (const void*)lost})
+    if (!on_device(p, c->cfg.device)) {
+      set_error("bound arrays must be device memory of the context's device");
+      return SBX_EINVAL;
+    }
+  // the moving arrays must not overlap each other or the read-only ones
+  const size_t es = c->esz;
+  struct Range { uintptr_t a, b; } r[6] = {
+      {(uintptr_t)x, (uintptr_t)x + 3 * es * n}, {(uintptr_t)v, (uintptr_t)v + 3 * es * n},
+      {(uintptr_t)m, (uintptr_t)m + es * n},     {(uintptr_t)comp, (uintptr_t)comp + n},
+      {(uintptr_t)gal, (uintptr_t)gal + n},      {(uintptr_t)lost, (uintptr_t)lost + n}};
+  for (int i = 0; i < 6; ++i)
+    for (int j = i + 1; j < 6; ++j)
+      if ((i < 2 || i == 5 || j < 2 || j == 5) && r[i].a < r[j].b && r[j].a < r[i].b) {
+        set_error("the bound positions, velocities and lost flags must not overlap other arrays");
+        return SBX_EINVAL;
+      }
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  return c->cfg.prec == SBX_FP64 ? bind_t<double>(c, n, x, v, m, comp, gal, lost)
+                                 : bind_t<float>(c, n, x, v, m, comp, gal, lost);
+}
+
+}  // namespace sbx
 
 extern "C" {
 
@@ -978,6 +1077,11 @@ sbx_status sbx_load_particles(sbx_ctx* c, int64_t n, const double* x, const doub
 sbx_status sbx_load_particles_device(sbx_ctx* c, int64_t n, const double* x, const double* v,
                                      const double* m, const int8_t* comp, const int8_t* gal) {
   return load_impl(c, n, x, v, m, comp, gal, true);
+}
+
+sbx_status sbx_bind_device_particles(sbx_ctx* c, int64_t n, void* x, void* v, void* m, int8_t* comp,
+                                     int8_t* gal, uint8_t* lost) {
+  return bind_impl(c, n, x, v, m, comp, gal, lost);
 }
 
 sbx_status sbx_build_grids(sbx_ctx* c, int32_t n_galaxies, const sbx_hierarchy* h) {
@@ -1071,7 +1175,8 @@ sbx_status sbx_step(sbx_ctx* c, double dt, int32_t nsteps, int32_t diag_every) {
   }
   SBX_TRY(set_dt(c, dt));
   for (int s = 0; s < nsteps; ++s) {
-    if (c->sort_every > 0 && (c->step_count % c->sort_every) == 0) SBX_TRY(sort_particles(c));
+    if (c->sort_every > 0 && !c->bound && (c->step_count % c->sort_every) == 0)
+      SBX_TRY(sort_particles(c));
     SBX_TRY(field_solve(c));
     const bool diag = diag_every > 0 && (c->step_count % diag_every) == 0;
     if (diag && c->diag_count < kDiagCap) {
@@ -1328,6 +1433,16 @@ sbx_status sbx_sync(sbx_ctx* c) {
   }
   SBX_TRY(set_device(c->cfg.device));
   SBX_HIP(hipStreamSynchronize(c->stream));
+  return SBX_OK;
+}
+
+sbx_status sbx_get_counts(sbx_ctx* c, int64_t* n, int32_t* n_galaxies) {
+  if (!c) {
+    set_error("null context");
+    return SBX_EINVAL;
+  }
+  if (n) *n = c->n;
+  if (n_galaxies) *n_galaxies = c->built ? c->ngal : 0;
   return SBX_OK;
 }
 

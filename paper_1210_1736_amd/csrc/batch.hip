@@ -172,6 +172,11 @@ sbx_status sbx_batch_create(sbx_ctx* const* ctxs, int32_t n, void* stream, sbx_b
       set_error("a context already belongs to a batch");
       return SBX_ESTATE;
     }
+    if (c->bound) {
+      set_error("a context with bound (borrowed) particles cannot join a batch: the batch "
+                "reorders particles");
+      return SBX_ESTATE;
+    }
     if (c->cfg.prec != ctxs[0]->cfg.prec || c->cfg.device != ctxs[0]->cfg.device) {
       set_error("contexts of a batch share device and precision");
       return SBX_EINVAL;

@@ -54,6 +54,7 @@ struct sbx_ctx {
   int64_t n = 0;
   sbx::PSet set[2];
   int cur = 0;
+  bool bound = false;  // set[0] is the caller's storage (sbx_bind_device_particles)
   int* d_cur = nullptr;
   // grids
   bool built = false;
@@ -147,6 +148,16 @@ InstDev<T> inst_of(const sbx_ctx* c);
 
 // Upload the context's instance record (synchronises the context stream).
 sbx_status upload_inst(sbx_ctx* c);
+
+// Whether p is device memory of the given device.
+bool on_device(const void* p, int device);
+// Particle load (host or device arrays, host layout), read-back (caller's
+// order) and borrowed-storage bind behind the ABI entry points.
+sbx_status load_impl(sbx_ctx* c, int64_t n, const double* x, const double* v, const double* m,
+                     const int8_t* comp, const int8_t* gal, bool dev);
+sbx_status get_impl(sbx_ctx* c, double* x, double* v, uint8_t* lost, bool dev);
+sbx_status bind_impl(sbx_ctx* c, int64_t n, void* x, void* v, void* m, int8_t* comp, int8_t* gal,
+                     uint8_t* lost);
 
 inline InstInfo info_of(const sbx_ctx* c) { return InstInfo{c->n, c->mass_elems, c->dm_elems}; }
 

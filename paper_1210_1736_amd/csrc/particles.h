@@ -222,6 +222,13 @@ sbx_status launch_validate_particles(const double* x, const double* v, const dou
                                      const int8_t* comp, const int8_t* gal, int64_t n, int ngal,
                                      unsigned long long* bad, hipStream_t s);
 
+// As launch_validate_particles for structure-of-arrays inputs in precision
+// T (x[k * n + i], v likewise).
+template <typename T>
+sbx_status launch_validate_soa(const T* x, const T* v, const T* m, const int8_t* comp,
+                               const int8_t* gal, int64_t n, int ngal, unsigned long long* bad,
+                               hipStream_t s);
+
 // dst[id[i] * width + w] = src[i * width + w]
 template <typename A>
 sbx_status launch_unpermute(const A* src, const int32_t* id, A* dst, int64_t n, int width,

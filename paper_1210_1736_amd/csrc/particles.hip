@@ -1661,6 +1661,37 @@ sbx_status launch_validate_particles(const double* x, const double* v, const dou
 }
 
 template <typename T>
+__global__ void k_validate_soa(const T* __restrict__ x, const T* __restrict__ v,
+                               const T* __restrict__ m, const int8_t* __restrict__ comp,
+                               const int8_t* __restrict__ gal, int64_t n, int ngal,
+                               unsigned long long* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    bool ok = isfinite((double)m[i]) && m[i] >= (T)0 && comp[i] >= 0 && comp[i] < kNComp &&
+              gal[i] >= 0 && gal[i] < ngal;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      ok = ok && isfinite((double)x[k * n + i]) && isfinite((double)v[k * n + i]);
+    if (!ok) atomicMin(bad, (unsigned long long)i);
+  }
+}
+
+template <typename T>
+sbx_status launch_validate_soa(const T* x, const T* v, const T* m, const int8_t* comp,
+                               const int8_t* gal, int64_t n, int ngal, unsigned long long* bad,
+                               hipStream_t s) {
+  hipLaunchKernelGGL((k_validate_soa<T>), dim3(2048), dim3(256), 0, s, x, v, m, comp, gal, n, ngal, bad);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+template sbx_status launch_validate_soa<float>(const float*, const float*, const float*, const int8_t*,
+                                               const int8_t*, int64_t, int, unsigned long long*,
+                                               hipStream_t);
+template sbx_status launch_validate_soa<double>(const double*, const double*, const double*,
+                                                const int8_t*, const int8_t*, int64_t, int,
+                                                unsigned long long*, hipStream_t);
+
+template <typename T>
 sbx_status launch_mass_max(const T* m, int64_t n, unsigned long long* out, hipStream_t s) {
   SBX_HIP(hipMemsetAsync(out, 0, sizeof(unsigned long long), s));
   hipLaunchKernelGGL((k_mass_max<T>), dim3(1024), dim3(256), 0, s, m, n, out);

@@ -108,6 +108,10 @@ def _load():
         "sbx_disc_analysis": (S, [P, P, P, P, P, P, P]),
         "sbx_disc_modes": (S, [P, I32, I32, I32, D, I32, P]),
         "sbx_get_particles_device": (S, [P, P, P, P]),
+        "sbx_bind_device_particles": (S, [P, I64, P, P, P, P, P, P]),
+        "sbx_save": (S, [P, C.c_char_p]),
+        "sbx_get_counts": (S, [P, C.POINTER(I64), C.POINTER(I32)]),
+        "sbx_load": (S, [P, C.c_char_p]),
         "sbx_count_live": (S, [P, C.POINTER(I64)]),
         "sbx_profile_begin": (S, [P, I32]),
         "sbx_profile_end": (S, [P, I32, P, P]),
@@ -189,11 +193,13 @@ class Context:
         self.prec = prec
         self.n = 0
         self.ngal = 0
+        self.bound_state = None  # storage borrowed by sbx_bind_device_particles, kept alive here
 
     def close(self):
         if self._h:
             _lib.sbx_destroy(self._h)
             self._h = None
+        self.bound_state = None
 
     def __del__(self):
         try:
@@ -220,6 +226,24 @@ class Context:
         _check(_lib.sbx_load_particles_device(self._h, int(n), C.c_void_p(x), C.c_void_p(v),
                                               C.c_void_p(m), C.c_void_p(comp), C.c_void_p(gal)))
         self.n = int(n)
+
+    def sbx_bind_device_particles(self, n, x, v, m, comp, gal, lost):
+        """Borrow device storage (ints, e.g. tensor.data_ptr()): x, v as 3 x n
+        arrays and m (n,) in the context precision, comp, gal int8 (n,), lost
+        uint8 (n,).  The caller keeps the storage alive while bound."""
+        vp = C.c_void_p
+        _check(_lib.sbx_bind_device_particles(self._h, int(n), vp(x), vp(v), vp(m), vp(comp),
+                                              vp(gal), vp(lost)))
+        self.n = int(n)
+
+    def sbx_save(self, path):
+        _check(_lib.sbx_save(self._h, os.fsencode(path)))
+
+    def sbx_load(self, path):
+        _check(_lib.sbx_load(self._h, os.fsencode(path)))
+        n, ng = C.c_int64(), C.c_int32()
+        _check(_lib.sbx_get_counts(self._h, C.byref(n), C.byref(ng)))
+        self.n, self.ngal = n.value, ng.value
 
     def sbx_get_particles_device(self, x=None, v=None, lost=None):
         """Device pointers (ints) for x, v float64 (n,3) and lost uint8 (n,)."""

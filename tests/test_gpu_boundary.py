@@ -1,0 +1,204 @@
+"""GPU tests of the boundary calls around the method: borrowed particle
+storage (sbx_bind_device_particles) and checkpoint files (sbx_save /
+sbx_load), against contexts that copy their particles and against
+uninterrupted stepping."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests import common as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sbx():
+    from paper_1210_1736_amd import sbx as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a ROCm device"
+    return t
+
+
+def _rng(k):
+    return np.random.default_rng(np.random.SeedSequence([1210, 1736, 980, k]))
+
+
+def _galaxy(centring="com", n_out=40):
+    """The small nested galaxy plus particles placed off the global grid (lost
+    at the first step)."""
+    w = T.small_galaxy(scale=0.003, N=32, centring=centring, q=0.5)
+    rng = _rng(1)
+    xo = rng.normal(size=(n_out, 3))
+    xo = 30.0 * xo / np.linalg.norm(xo, axis=1)[:, None]
+    w.x = np.vstack([w.x, xo]); w.v = np.vstack([w.v, np.zeros((n_out, 3))])
+    w.m = np.concatenate([w.m, np.full(n_out, w.m[0])])
+    w.comp = np.concatenate([w.comp, np.zeros(n_out, np.int8)])
+    w.gal = np.concatenate([w.gal, np.zeros(n_out, np.int8)])
+    return w
+
+
+# ------------------------------------------------------------------ bind ---
+def _bind(sbx, torch, ctx, w):
+    pt = torch.float64 if ctx.prec == sbx.SBX_FP64 else torch.float32
+    st = {"x": torch.tensor(w.x.T.copy(), dtype=pt, device="cuda"),
+          "v": torch.tensor(w.v.T.copy(), dtype=pt, device="cuda"),
+          "m": torch.tensor(w.m, dtype=pt, device="cuda"),
+          "comp": torch.tensor(w.comp, dtype=torch.int8, device="cuda"),
+          "gal": torch.tensor(w.gal, dtype=torch.int8, device="cuda"),
+          "lost": torch.zeros(w.n, dtype=torch.uint8, device="cuda")}
+    torch.cuda.synchronize()
+    ctx.sbx_bind_device_particles(w.n, *(st[k].data_ptr() for k in ("x", "v", "m", "comp", "gal", "lost")))
+    ctx.bound_state = st
+    return st
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bound_particles_step_in_place(sbx, torch, prec):
+    """Steps on borrowed storage move the caller's arrays in place and match a
+    context that copied the same particles in (FP64 within 1e-12; FP32 within
+    FP32 rounding of the summation order)."""
+    w = _galaxy()
+    hs = [T.sbx_hier(h) for h in w.hier]
+    a = sbx.Context(prec=prec, G=w.G)
+    a.sbx_build_grids(hs)
+    st = _bind(sbx, torch, a, w)
+    b = T.make_ctx(w, prec)
+    for c in (a, b):
+        c.sbx_step(w.dt, 5, 2)
+    xa, va, la = a.sbx_get_particles()
+    xb, vb, lb = b.sbx_get_particles()
+    assert np.array_equal(la, lb) and la.sum() >= 40
+    tol = 1e-12 if prec == sbx.SBX_FP64 else 1e-5
+    assert np.abs(xa - xb).max() < tol and np.abs(va - vb).max() < tol * 10
+    # the caller's storage holds the state (no copy out)
+    torch.cuda.synchronize()
+    assert np.array_equal(st["x"].double().cpu().numpy().T, xa)
+    assert np.array_equal(st["v"].double().cpu().numpy().T, va)
+    assert np.array_equal(st["lost"].cpu().numpy(), la)
+    da, db = a.sbx_diag_log(), b.sbx_diag_log()
+    assert len(da) == len(db) == 3
+    assert np.allclose(da[-1]["ekin"], db[-1]["ekin"], rtol=1e-9 if prec else 1e-6)
+    a.close(); b.close()
+
+
+def test_bind_rejects_bad_storage(sbx, torch):
+    w = _galaxy(n_out=0)
+    ctx = sbx.Context(prec=sbx.SBX_FP32, G=w.G)
+    ctx.sbx_build_grids([T.sbx_hier(h) for h in w.hier])
+    st = _bind(sbx, torch, ctx, w)
+    p = {k: st[k].data_ptr() for k in st}
+    # overlapping positions and velocities
+    with pytest.raises(sbx.SbxError) as e:
+        ctx.sbx_bind_device_particles(w.n, p["x"], p["x"], p["m"], p["comp"], p["gal"], p["lost"])
+    assert e.value.status == sbx.SBX_EINVAL
+    # host memory
+    xh = np.zeros((3, w.n), np.float32)
+    with pytest.raises(sbx.SbxError) as e:
+        ctx.sbx_bind_device_particles(w.n, xh.ctypes.data, p["v"], p["m"], p["comp"], p["gal"], p["lost"])
+    assert e.value.status == sbx.SBX_EINVAL
+    # a negative mass is found on the device
+    bad = st["m"].clone(); bad[7] = -1.0
+    torch.cuda.synchronize()
+    with pytest.raises(sbx.SbxError) as e:
+        ctx.sbx_bind_device_particles(w.n, p["x"], p["v"], bad.data_ptr(), p["comp"], p["gal"], p["lost"])
+    assert e.value.status == sbx.SBX_EINVAL and "particle 7" in str(e.value)
+    # a context with bound particles cannot join a batch
+    ctx2 = sbx.Context(prec=sbx.SBX_FP32, G=w.G)
+    ctx2.sbx_build_grids([T.sbx_hier(h) for h in w.hier])
+    _bind(sbx, torch, ctx2, w)
+    with pytest.raises(sbx.SbxError) as e:
+        sbx.Batch([ctx2])
+    assert e.value.status == sbx.SBX_ESTATE
+    ctx.close(); ctx2.close()
+
+
+# ----------------------------------------------------------- checkpoints ---
+def test_checkpoint_resume_is_bitwise_fp64(sbx, tmp_path):
+    """Save after 3 steps, load into a fresh context, step 3 more: the result
+    equals 6 uninterrupted steps bit for bit.  Masses are dyadic and the
+    centres fixed, so every cell total and every other operation is exact or
+    independent of the order of the particles (which the cell sort changes)."""
+    w = T.small_galaxy(scale=0.003, N=32, centring="fixed", q=0.5)
+    w.m = np.ldexp(np.round(np.ldexp(w.m, 30)), -30)
+    assert np.all(w.m > 0)
+    a = T.make_ctx(w, sbx.SBX_FP64)
+    a.sbx_step(w.dt, 3)
+    path = str(tmp_path / "state.sbx")
+    a.sbx_save(path)
+    a.sbx_step(w.dt, 3)
+    b = sbx.Context(prec=sbx.SBX_FP64, G=w.G)
+    b.sbx_load(path)
+    assert b.n == w.n and b.ngal == 1
+    b.sbx_step(w.dt, 3)
+    xa, va, la = a.sbx_get_particles()
+    xb, vb, lb = b.sbx_get_particles()
+    assert np.array_equal(la, lb) and np.array_equal(xa, xb) and np.array_equal(va, vb)
+    a.close(); b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("centring", ["com", "density"])
+def test_checkpoint_restores_state(sbx, tmp_path, prec, centring):
+    """A saved state reads back whole: particles (bitwise, lost flags
+    included), centres of the last solve, step count (same sort and
+    diagnostics schedule), and stepping on agrees with the saved context up
+    to the summation order of the mass assignment."""
+    w = _galaxy(centring)
+    a = T.make_ctx(w, prec)
+    a.sbx_step(w.dt, 3)
+    path = str(tmp_path / f"s{prec}{centring}.sbx")
+    a.sbx_save(path)
+    b = sbx.Context(prec=prec, G=w.G)
+    b.sbx_load(path)
+    for ga, gb in zip(a.sbx_get_particles(), b.sbx_get_particles()):
+        assert np.array_equal(ga, gb)
+    assert np.array_equal(a.sbx_get_centres(), b.sbx_get_centres())
+    assert a.sbx_count_live() == b.sbx_count_live() == w.n - 40
+    for c in (a, b):
+        c.sbx_step(w.dt, 3, 2)
+    xa, va, la = a.sbx_get_particles()
+    xb, vb, lb = b.sbx_get_particles()
+    assert np.array_equal(la, lb)
+    tol = 1e-11 if prec == sbx.SBX_FP64 else 1e-5
+    assert np.abs(xa - xb).max() < tol
+    assert np.allclose(a.sbx_get_centres(), b.sbx_get_centres(), rtol=0, atol=tol)
+    # step 4 of 6 is the one diagnostics step on both sides (same step count)
+    assert len(a.sbx_diag_log()) == len(b.sbx_diag_log()) == 1
+    a.close(); b.close()
+
+
+def test_checkpoint_rejects_bad_files(sbx, tmp_path):
+    w = T.small_galaxy(scale=0.002, N=32, centring="com", q=0.5)
+    a = T.make_ctx(w, sbx.SBX_FP64)
+    a.sbx_step(w.dt, 1)
+    path = str(tmp_path / "s.sbx")
+    a.sbx_save(path)
+    # another precision
+    b = sbx.Context(prec=sbx.SBX_FP32, G=w.G)
+    with pytest.raises(sbx.SbxError) as e:
+        b.sbx_load(path)
+    assert e.value.status == sbx.SBX_EINVAL
+    # truncated, corrupt, missing
+    data = open(path, "rb").read()
+    c = sbx.Context(prec=sbx.SBX_FP64, G=w.G)
+    for name, blob in (("trunc", data[:-9]), ("junk", b"not a checkpoint" * 10),
+                       ("tail", data[:-8] + b"XXXXXXXX")):
+        p = str(tmp_path / name)
+        open(p, "wb").write(blob)
+        with pytest.raises(sbx.SbxError) as e:
+            c.sbx_load(p)
+        assert e.value.status == sbx.SBX_EINVAL, name
+    with pytest.raises(sbx.SbxError):
+        c.sbx_load(str(tmp_path / "missing.sbx"))
+    # nothing to save
+    with pytest.raises(sbx.SbxError) as e:
+        sbx.Context(prec=sbx.SBX_FP64).sbx_save(str(tmp_path / "empty.sbx"))
+    assert e.value.status == sbx.SBX_ESTATE
+    a.close(); b.close(); c.close()
