@@ -177,7 +177,9 @@ def precision_errors(sbx, w):
     a32, p32 = res["fp32"]
     rms = float(np.sqrt(np.mean(np.sum(a64 * a64, axis=1))))
     e = np.linalg.norm(a32 - a64, axis=1) / rms
-    out["reference"] = "FP64 GPU form on the same FP32-rounded inputs"
+    out["reference"] = ("FP64 GPU form on the same FP32-rounded inputs (transitive: the parity "
+                        "tests hold the FP64 form within 1e-9 of the FP64 oracle's forces, and the "
+                        "FP32 form against the oracle directly at the FP32 bars)")
     out["force_rel_p99"] = float(np.percentile(e, 99))
     out["force_rel_max"] = float(e.max())
     out["pot_rel_max"] = float(np.abs(p32 - p64).max() / np.abs(p64).max())
@@ -319,26 +321,89 @@ def disc_analysis_rate(sbx, torch, w):
                         "allocations and host copies"}
 
 
-def cpu_baseline(w, frac):
-    """The FP64 oracle, as it stands, on a bounded sample: one step of the
-    same galaxy with a random `frac` of its particles (same grids)."""
+def cpu_threads():
+    """Threads the CPU baseline may use: the process's thread budget
+    (OMP_NUM_THREADS) when set, else the usable cores, at most 16 (the CPU
+    share of one GPU on the GPU machines)."""
+    env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return env or min(aff, 16)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+_CPU_STATE = {}   # inherited by the forked workers of the CPU baseline
+
+
+def _eq8_chunk(bounds):
+    a, b = bounds
+    st = _CPU_STATE
+    return st["sysm"].field_at(st["x"][a:b], st["centres"], st["pots"])[0]
+
+
+def oracle_parallel_step(sysm, x, v, m, gal, lost, dt, cores):
+    """One integration cycle of the oracle, as System.step computes it and in
+    its order (loss test, centres, the five solves per galaxy with the FFT on
+    `cores` threads, Eq. 8 with the selection rule, leapfrog, loss test), the
+    per-particle Eq. 8 phase split over `cores` forked processes (each
+    particle's force depends only on its position and the fields).  Returns
+    new (x, v, lost, acc)."""
+    import multiprocessing as mp
     from oracle import pm_oracle as O
+    x = x.copy(); v = v.copy(); lost = lost.copy()
+    lost |= sysm.lost_now(x)
+    centres = sysm.centres(x, m, gal, lost)
+    pots = sysm.potentials(x, m, gal, lost, centres)
+    live = np.flatnonzero(~lost)
+    _CPU_STATE.update(sysm=sysm, x=x[live], centres=centres, pots=pots)
+    cuts = np.linspace(0, live.size, 4 * cores + 1).astype(int)
+    with mp.get_context("fork").Pool(cores) as pool:
+        parts = pool.map(_eq8_chunk, list(zip(cuts[:-1], cuts[1:])))
+    _CPU_STATE.clear()
+    acc = np.zeros_like(x)
+    acc[live] = np.concatenate(parts) if parts else np.zeros((0, 3))
+    x[live], v[live] = O.leapfrog_kd(x[live], v[live], acc[live], dt)
+    was_live = ~lost
+    lost |= was_live & sysm.lost_now(x)
+    return x, v, lost, acc
+
+
+def cpu_baseline_worker(npz, frac):
+    """The CPU-baseline leg proper, in a process that never touches the GPU:
+    the oracle, as it stands, on a bounded sample of the benchmark workload
+    (one step of the same galaxy and grids with a random `frac` of its
+    particles), on the host's cores; then standalone 128^3 solves."""
+    from oracle import pm_oracle as O
+    import synth
+    cores = cpu_threads()
+    O.set_fft_workers(cores)
+    d = np.load(npz)
+    w = synth.disc_galaxy(scale=1e-4)            # the grid set-up; particles from the file
     rng = np.random.default_rng(1736)
-    n = int(w.n * frac)
-    s = rng.choice(w.n, n, replace=False)
+    n_all = d["x"].shape[0]
+    n = int(n_all * frac)
+    s = np.sort(rng.choice(n_all, n, replace=False))
     hs = []
     for h in w.hier:
         lv = [O.Level(L.N, L.R, L.q) for L in h.levels[:2]]
         lv.append(O.Level(h.levels[2].N, h.levels[2].R, h.levels[2].q, centre=h.outer_centre))
         hs.append(O.Hierarchy(lv, h.centring, h.centre))
     sysm = O.System(hs, G=w.G)
-    x, v, m = w.x[s], w.v[s], w.m[s]
-    gal = w.gal[s]
+    x, v, m, gal = d["x"][s], d["v"][s], d["m"][s], d["gal"][s]
     lost = np.zeros(n, bool)
     t0 = time.perf_counter()
-    sysm.step(x, v, m, gal, lost, w.dt)
+    oracle_parallel_step(sysm, x, v, m, gal, lost, w.dt, cores)
     dt = time.perf_counter() - t0
-    # standalone 128^3 isolated solves (the solves/s half of the metric)
     L = hs[0].levels[1]
     rho = np.random.default_rng(1737).random((L.N, L.N, L.N))
     ts = []
@@ -347,11 +412,34 @@ def cpu_baseline(w, frac):
         sysm.solve(rho, L)
         ts.append(time.perf_counter() - t1)
     ts.sort()
-    return {"value": n / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "solves_per_s": 1.0 / ts[1],
-            "sample": f"1 step of the same galaxy and grids with {n} of its {w.n} particles "
-                      f"(random {frac:.0%}), numpy float64 single thread, {dt:.1f} s; "
-                      f"solves/s: median of 3 standalone {L.N}^3 solves"}
+    return {"value": n / dt, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "solves_per_s": 1.0 / ts[1],
+            "step_s": dt,
+            "sample": f"1 step of the same galaxy and grids with {n} of its {n_all} particles "
+                      f"(random {frac:.0%}): the FP64 numpy oracle's step with its FFTs on "
+                      f"{cores} threads and its per-particle Eq. 8 phase over {cores} processes, "
+                      f"{dt:.1f} s; solves/s: median of 3 standalone {L.N}^3 solves on "
+                      f"{cores} threads"}
+
+
+def cpu_baseline(w, frac):
+    """Run the CPU-baseline leg in a child process (it forks workers, which a
+    process holding the GPU should not do) on the workload's particles."""
+    import subprocess
+    import tempfile
+    tmp = tempfile.mkdtemp(prefix="sbx_cpu_")
+    npz = os.path.join(tmp, "w.npz")
+    try:
+        np.savez(npz, x=w.x, v=w.v, m=w.m, gal=w.gal)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", npz,
+                            "--cpu-frac", str(frac)], capture_output=True, text=True)
+        if r.returncode != 0:
+            _log(f"CPU baseline failed: {r.stderr[-2000:]}")
+            return None
+        return json.loads(r.stdout.strip().splitlines()[-1])
+    finally:
+        import shutil
+        shutil.rmtree(tmp, ignore_errors=True)
 
 
 def main():
@@ -375,7 +463,11 @@ def main():
                          "kernel of known size, to scale hardware byte counters)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the precision, satellite, ensemble and adjoint measurements")
+    ap.add_argument("--cpu-baseline-worker", metavar="NPZ", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline_worker:
+        print(json.dumps(cpu_baseline_worker(args.cpu_baseline_worker, args.cpu_frac)), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -422,7 +514,11 @@ def main():
     for name, prec in (() if args.step_only else (("fp32", sbx.SBX_FP32), ("fp64", sbx.SBX_FP64))):
         for batch in (5, 20):
             rate, ms = time_solves(sbx, torch, 128, 4.0, 0.25, prec, batch, args.solve_iters)
-            solves[f"{name}_batch{batch}"] = {"solves_per_s": rate, "ms_per_batch": ms}
+            esz = 8 if prec == sbx.SBX_FP64 else 4
+            model = sum(phase_bytes(ph, 128, 1, 0, esz) for ph in FFT_PASSES)
+            solves[f"{name}_batch{batch}"] = {"solves_per_s": rate, "ms_per_batch": ms,
+                                             "model_bytes_per_solve": model,
+                                             "frac_of_hbm_peak": rate * model / 1e9 / HBM_PEAK_GBS}
     torch.cuda.synchronize()
 
     extra = {}
@@ -487,6 +583,9 @@ def main():
         "solves_in_step_per_s": nsolves / (1e-3 * sum(per_step.get(k, 0.0) for k in FFT_PASSES)),
         **extra,
         "step_effective_GBs": step_roof,
+        "step_frac_of_hbm_peak": step_roof / HBM_PEAK_GBS,
+        "solves_in_step_frac_of_hbm_peak": sum(phase_bytes(k, N, nsolves, live32, 4) for k in FFT_PASSES)
+        / (1e-3 * sum(per_step.get(k, 0.0) for k in FFT_PASSES)) / 1e9 / HBM_PEAK_GBS,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

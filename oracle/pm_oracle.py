@@ -46,8 +46,10 @@ import numpy as np
 import scipy.fft as _fft
 
 # Threads of the library FFT used as a step of Eqs. 3-5 (pocketfft through
-# scipy.fft; the transform is the same whatever the count).
-_FFT_WORKERS = os.cpu_count() or 1
+# scipy.fft; the transform is the same whatever the count): the process's
+# thread budget (OMP_NUM_THREADS) when set, else the usable cores, at most 16.
+_FFT_WORKERS = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(
+    len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1), 16)
 
 
 def set_fft_workers(n: int) -> int:

@@ -6,6 +6,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -75,3 +76,26 @@ def test_measured_traffic_missing_files(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "KERNEL_SOURCES", ["absent.hip"])
     assert bench.measured_traffic("force") is None
+
+
+def test_cpu_baseline_step_equals_oracle_step():
+    """The CPU baseline's step (System.step's phases with the per-particle
+    Eq. 8 phase over forked workers) gives the oracle's System.step exactly."""
+    import bench
+    import synth
+    from tests import common as T
+    w = T.small_galaxy(scale=0.002, N=32, q=1.0)
+    sysm = T.oracle_system(w)
+    lost = np.zeros(w.n, bool)
+    a = sysm.step(w.x, w.v, w.m, w.gal, lost, w.dt)
+    b = bench.oracle_parallel_step(sysm, w.x, w.v, w.m, w.gal, lost, w.dt, 2)
+    for p, q in zip(a, b):
+        assert np.array_equal(p, q)
+
+
+def test_cpu_threads_respects_budget(monkeypatch):
+    import bench
+    monkeypatch.setenv("OMP_NUM_THREADS", "3")
+    assert bench.cpu_threads() == 3
+    monkeypatch.delenv("OMP_NUM_THREADS")
+    assert 1 <= bench.cpu_threads() <= 16
