@@ -33,7 +33,7 @@ def _rng(k):
 def _galaxy(centring="com", n_out=40):
     """The small nested galaxy plus particles placed off the global grid (lost
     at the first step)."""
-    w = T.small_galaxy(scale=0.003, N=32, centring=centring, q=0.5)
+    w = T.small_galaxy(scale=0.003, N=32, centring=centring, q=1.0)
     rng = _rng(1)
     xo = rng.normal(size=(n_out, 3))
     xo = 30.0 * xo / np.linalg.norm(xo, axis=1)[:, None]
@@ -125,7 +125,7 @@ def test_checkpoint_resume_is_bitwise_fp64(sbx, tmp_path):
     equals 6 uninterrupted steps bit for bit.  Masses are dyadic and the
     centres fixed, so every cell total and every other operation is exact or
     independent of the order of the particles (which the cell sort changes)."""
-    w = T.small_galaxy(scale=0.003, N=32, centring="fixed", q=0.5)
+    w = T.small_galaxy(scale=0.003, N=32, centring="fixed", q=1.0)
     w.m = np.ldexp(np.round(np.ldexp(w.m, 30)), -30)
     assert np.all(w.m > 0)
     a = T.make_ctx(w, sbx.SBX_FP64)
@@ -175,7 +175,7 @@ def test_checkpoint_restores_state(sbx, tmp_path, prec, centring):
 
 
 def test_checkpoint_rejects_bad_files(sbx, tmp_path):
-    w = T.small_galaxy(scale=0.002, N=32, centring="com", q=0.5)
+    w = T.small_galaxy(scale=0.002, N=32, centring="com", q=1.0)
     a = T.make_ctx(w, sbx.SBX_FP64)
     a.sbx_step(w.dt, 1)
     path = str(tmp_path / "s.sbx")

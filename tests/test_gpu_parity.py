@@ -72,7 +72,7 @@ def test_green_table_h0_readings(sbx, N, q, h0, prec):
 def test_forces_h0_readings_fp64(sbx, h0):
     """Fields and forces of the nested galaxy with the other readings of
     H(0,0,0), through sbx_create's h0_mode, against the oracle."""
-    w = T.small_galaxy(scale=0.003, N=32, q=0.5)
+    w = T.small_galaxy(scale=0.003, N=64, q=0.5)
     sysm = T.oracle_system(w, h0_mode=h0)
     lost = sysm.lost_now(w.x)
     centres = sysm.centres(w.x, w.m, w.gal, lost)
