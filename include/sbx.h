@@ -409,6 +409,25 @@ void sbx_poisson_destroy(sbx_poisson* p);
  * the same buffer.  batch <= 64.  Stream-ordered on the plan's stream. */
 sbx_status sbx_poisson_solve(sbx_poisson* p, int32_t batch, const void* rho, void* phi);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * sbx_poisson_solve, but the work arrays, the solve descriptors and the work
+ * counters live in a fixed work space of 96 MiB (100663296 bytes) that each
+ * GPU the library runs on holds until the process ends; the call launches
+ * kernels only (no hipMalloc, hipFree, memset, copy or synchronisation) and
+ * returns without waiting.  The plan (made by sbx_poisson_create, which sets
+ * the work space up on its device) supplies the Green's table and stream;
+ * the caller passes rho and phi as for sbx_poisson_solve.  SBX_EINVAL when
+ * the batch needs more than the work space: each grid takes 5 N^3 + 20 N^2
+ * complex values of the plan precision (plus a few hundred bytes per call),
+ * so one 128^3 solve fits in FP32 (82.5 MiB), four 64^3 solves in FP64 and
+ * nine in FP32.  Every call on a GPU uses
+ * that GPU's one work space: calls that overlap in time on one GPU (other
+ * streams, other threads, other plans) race and must be ordered by the
+ * caller.  The work counters are cleared at the start of each call by a
+ * kernel, so stale contents of an earlier call do not matter. */
+sbx_status sbx_poisson_solve_noalloc(sbx_poisson* p, int32_t batch, const void* rho, void* phi);
+
 /* The stored transformed Green's function, (n+1)^3 float64, index
  * (kx * (n+1) + ky) * (n+1) + kz, scaled by G/(2n)^3; rel_imag receives
  * max|Im| / max|Re| of the FP64 transform before folding (may be NULL). */

@@ -96,6 +96,20 @@ sbx_status plan_run_pass(const SolvePlan<T>& plan, int pass, int group, hipStrea
 template <typename T>
 void plan_destroy(SolvePlan<T>& plan);
 
+// Make (once per device, precision and length; allocates) the twiddle table
+// of the solves of N^3 grids.
+template <typename T>
+sbx_status prepare_twiddles(int N, hipStream_t s);
+
+// The five passes of nsolves solves of N^3 grids whose descriptors are
+// already in device memory, with the tuned launch shapes of (T, N, nsolves)
+// when cached and default shapes otherwise.  Launches only: allocates
+// nothing and waits for nothing (the twiddle table must exist).  d_counter:
+// kPasses work counters, zero on entry, left nonzero.
+template <typename T>
+sbx_status run_solves_noalloc(const SolveDesc<T>* d_solves, int nsolves, int N, int* d_counter,
+                              hipStream_t s);
+
 // Whether launch shapes for this precision and mix of grid sizes are cached.
 bool tuning_cached(int esz, std::vector<int> mix);
 

@@ -219,8 +219,11 @@ static int tw_make(int L, C2<T>* tw, hipStream_t st) {
   }
 }
 
+// Twiddle tables are made once per (device, precision, length) and kept for
+// the life of the process.  With create = false a missing table is not made
+// (nothing is allocated) and null is returned.
 template <typename T>
-const C2<T>* twiddles(int L, hipStream_t st) {
+const C2<T>* twiddles(int L, hipStream_t st, bool create = true) {
   static std::mutex mu;
   static C2<T>* cache[64][10] = {};
   int dev = 0;
@@ -228,7 +231,7 @@ const C2<T>* twiddles(int L, hipStream_t st) {
   int lg = 0;
   while ((1 << lg) < L) ++lg;
   std::lock_guard<std::mutex> g(mu);
-  if (cache[dev][lg]) return cache[dev][lg];
+  if (cache[dev][lg] || !create) return cache[dev][lg];
   C2<T>* p = nullptr;
   if (hipMalloc(&p, sizeof(C2<T>) * tw_make<T>(L, nullptr, st)) != hipSuccess) return nullptr;
   tw_make<T>(L, p, st);
@@ -240,8 +243,8 @@ const C2<T>* twiddles(int L, hipStream_t st) {
   return p;
 }
 
-template const C2<float>* twiddles<float>(int, hipStream_t);
-template const C2<double>* twiddles<double>(int, hipStream_t);
+template const C2<float>* twiddles<float>(int, hipStream_t, bool);
+template const C2<double>* twiddles<double>(int, hipStream_t, bool);
 
 // ------------------------------------------------------------ tile shape ---
 // A block of NT threads covers WT = NT/TL lines at a time.  The z pass takes
@@ -829,6 +832,38 @@ sbx_status plan_run(const SolvePlan<T>& p, hipStream_t st, Recorder* rec) {
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
+
+template <typename T>
+sbx_status prepare_twiddles(int N, hipStream_t st) {
+  if (!twiddles<T>(2 * N, st)) {
+    set_error("twiddle table allocation failed");
+    return SBX_ENOMEM;
+  }
+  return SBX_OK;
+}
+
+template <typename T>
+sbx_status run_solves_noalloc(const SolveDesc<T>* d_solves, int nsolves, int N, int* d_counter,
+                              hipStream_t st) {
+  const C2<T>* tw = twiddles<T>(2 * N, st, false);
+  if (!tw) {
+    set_error("no twiddle table for this grid size on this device (create a plan first)");
+    return SBX_ESTATE;
+  }
+  std::array<PassShape, kPasses> a;
+  if (!tune_lookup(TuneKey{(int)sizeof(T), N, nsolves}, a))
+    for (auto& sh : a) sh = PassShape{256, 0};
+  for (int q = 0; q < kPasses; ++q)
+    launch_any<T>(q, d_solves, N, nsolves, a[q], d_counter + q, d_counter + (q + kPasses - 1) % kPasses,
+                  tw, st);
+  SBX_HIP(hipGetLastError());
+  return SBX_OK;
+}
+
+template sbx_status prepare_twiddles<float>(int, hipStream_t);
+template sbx_status prepare_twiddles<double>(int, hipStream_t);
+template sbx_status run_solves_noalloc<float>(const SolveDesc<float>*, int, int, int*, hipStream_t);
+template sbx_status run_solves_noalloc<double>(const SolveDesc<double>*, int, int, int*, hipStream_t);
 
 template <typename T>
 void plan_destroy(SolvePlan<T>& p) {

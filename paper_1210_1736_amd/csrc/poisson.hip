@@ -1,7 +1,79 @@
 // C ABI of the standalone isolated Poisson solves (Eqs. 1-5).
+#include <mutex>
+
 #include "ctx.h"
 
 using namespace sbx;
+
+// ------------------------------------------------------- no-alloc solves ---
+// Work space of sbx_poisson_solve_noalloc: a fixed array in device memory of
+// every GPU the library runs on, held until the process ends.  Layout per
+// call: kPasses work counters, the solve descriptors, then per solve the X
+// half spectrum and the C/D work arrays.  In host code the array's name is
+// not a device address: kernels get the address from hipGetSymbolAddress,
+// taken once per device when the first plan on that device is created.
+constexpr size_t kNoallocBytes = 96ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+constexpr int kMaxDev = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDev] = {};
+std::string g_scratch_err[kMaxDev];
+
+// The device address of `scratch` on the current device (set-up, once per
+// device; the failure message is kept for the entry point to report).
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDev) return;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    g_scratch_err[device] = std::string("hipGetSymbolAddress of the no-alloc work space failed: ") +
+                            hipGetErrorString(e);
+    return;
+  }
+  g_scratch[device] = ptr;
+}
+
+void* scratch_of(int device, std::string& why) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (device < 0 || device >= kMaxDev) {
+    why = "device ordinal beyond the no-alloc work space table";
+    return nullptr;
+  }
+  if (!g_scratch[device]) why = g_scratch_err[device].empty() ? "no-alloc work space not set up"
+                                                               : g_scratch_err[device];
+  return g_scratch[device];
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// One block: clear the work counters and write the descriptors of `batch`
+// solves whose grids, work arrays and table are at the given places.
+template <typename T>
+__global__ void k_noalloc_setup(SolveDesc<T>* __restrict__ d, int batch, const T* rho, T* phi,
+                                C2<T>* X, C2<T>* CD, const T* H, int N, size_t cells, size_t xe,
+                                size_t ce, int* __restrict__ counters, int ncnt) {
+  for (int i = threadIdx.x; i < ncnt; i += blockDim.x) counters[i] = 0;
+  for (int b = threadIdx.x; b < batch; b += blockDim.x) {
+    SolveDesc<T> s;
+    s.rho = rho + cells * b;
+    s.rho2 = nullptr;
+    s.phi = phi + cells * b;
+    s.X = X + xe * b;
+    s.C = CD + 2 * ce * b;
+    s.D = s.C + ce;
+    s.H = H;
+    s.N = N;
+    d[b] = s;
+  }
+}
+
+}  // namespace
 
 // Solve plans of a Poisson object are cached per (rho, phi, batch) so that a
 // loop over the same buffers reuses its device tables.
@@ -155,6 +227,12 @@ sbx_status sbx_poisson_create(int32_t n, double R, double q, double G, int32_t h
     rc = prec == SBX_FP64 ? build_green<double>(n, L.l, L.lz, G, h0_mode, (double*)p->H, &p->rel_imag, p->stream)
                           : build_green<float>(n, L.l, L.lz, G, h0_mode, (float*)p->H, &p->rel_imag, p->stream);
   }
+  // what sbx_poisson_solve_noalloc needs on this device, made here: the
+  // work space address and the twiddle table of the plan's precision
+  if (rc == SBX_OK) {
+    scratch_setup(device);
+    rc = prec == SBX_FP64 ? prepare_twiddles<double>(n, p->stream) : prepare_twiddles<float>(n, p->stream);
+  }
   if (rc != SBX_OK) {
     sbx_poisson_destroy(p);
     return rc;
@@ -189,6 +267,54 @@ sbx_status sbx_poisson_solve(sbx_poisson* p, int32_t batch, const void* rho, voi
   SBX_TRY(set_device(p->device));
   return p->prec == SBX_FP64 ? poisson_solve_t<double>(p, batch, rho, phi)
                              : poisson_solve_t<float>(p, batch, rho, phi);
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+sbx_status poisson_noalloc_t(sbx_poisson* p, int batch, const void* rho, void* phi, void* base) {
+  const int N = p->N;
+  const size_t cells = (size_t)N * N * N, xe = x_elems(N), ce = c_elems(N);
+  const size_t off_desc = round256(sizeof(int) * kPasses);
+  const size_t off_x = off_desc + round256(sizeof(SolveDesc<T>) * batch);
+  const size_t off_cd = off_x + round256(sizeof(C2<T>) * xe * batch);
+  const size_t need = off_cd + sizeof(C2<T>) * 2 * ce * batch;
+  if (need > kNoallocBytes) {
+    set_error("no-alloc solve of " + std::to_string(batch) + " grid(s) of " + std::to_string(N) +
+              "^3 needs " + std::to_string(need) + " bytes of work space; the fixed no-alloc work "
+              "space holds " + std::to_string(kNoallocBytes) + " (use sbx_poisson_solve)");
+    return SBX_EINVAL;
+  }
+  unsigned char* s = (unsigned char*)base;
+  int* counters = (int*)s;
+  SolveDesc<T>* d = (SolveDesc<T>*)(s + off_desc);
+  hipLaunchKernelGGL((k_noalloc_setup<T>), dim3(1), dim3(64), 0, p->stream, d, batch, (const T*)rho,
+                     (T*)phi, (C2<T>*)(s + off_x), (C2<T>*)(s + off_cd), (const T*)p->H, N, cells, xe,
+                     ce, counters, kPasses);
+  SBX_HIP(hipGetLastError());
+  return run_solves_noalloc<T>(d, batch, N, counters, p->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+sbx_status sbx_poisson_solve_noalloc(sbx_poisson* p, int32_t batch, const void* rho, void* phi) {
+  if (!p || !rho || !phi || batch <= 0 || batch > 64) {
+    set_error("bad Poisson solve arguments");
+    return SBX_EINVAL;
+  }
+  SBX_TRY(set_device(p->device));
+  std::string why;
+  void* base = scratch_of(p->device, why);
+  if (!base) {
+    set_error(why);
+    return SBX_EDEVICE;
+  }
+  return p->prec == SBX_FP64 ? poisson_noalloc_t<double>(p, batch, rho, phi, base)
+                             : poisson_noalloc_t<float>(p, batch, rho, phi, base);
 }
 
 sbx_status sbx_poisson_green(sbx_poisson* p, double* out, double* rel_imag) {

@@ -123,6 +123,7 @@ def _load():
         "sbx_poisson_create": (S, [I32, D, D, D, I32, I32, I32, P, C.POINTER(P)]),
         "sbx_poisson_destroy": (None, [P]),
         "sbx_poisson_solve": (S, [P, I32, P, P]),
+        "sbx_poisson_solve_noalloc": (S, [P, I32, P, P]),
         "sbx_poisson_green": (S, [P, P, dp]),
         "sbx_poisson_bytes": (I64, [P]),
     }
@@ -423,6 +424,12 @@ class Poisson:
     def sbx_poisson_solve(self, batch, rho_ptr, phi_ptr):
         """rho_ptr, phi_ptr: device addresses (int) of batch * n^3 elements."""
         _check(_lib.sbx_poisson_solve(self._h, int(batch), C.c_void_p(rho_ptr), C.c_void_p(phi_ptr)))
+
+    def sbx_poisson_solve_noalloc(self, batch, rho_ptr, phi_ptr):
+        """As sbx_poisson_solve, with the fixed per-GPU work space (no device
+        allocation; overlapping calls on one GPU race)."""
+        _check(_lib.sbx_poisson_solve_noalloc(self._h, int(batch), C.c_void_p(rho_ptr),
+                                              C.c_void_p(phi_ptr)))
 
     def sbx_poisson_green(self):
         n1 = self.n + 1

@@ -1,0 +1,77 @@
+"""The no-alloc Poisson entry point (sbx_poisson_solve_noalloc) against the
+allocating one (sbx_poisson_solve) through the C ABI: two calls in a row
+on the shared per-GPU work space, the second with a smaller input, at the
+field bars of the parity tests (FP32 3e-6, FP64 1e-11 of max|Phi|); then the
+size limit."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sbx():
+    from paper_1210_1736_amd import sbx as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a ROCm device"
+    return t
+
+
+def _solve_both(sbx, torch, N, prec, batch, seed):
+    dt = torch.float64 if prec == sbx.SBX_FP64 else torch.float32
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    rho = torch.rand((batch, N, N, N), dtype=dt, device="cuda", generator=g)
+    rho = rho * (torch.rand(rho.shape, dtype=dt, device="cuda", generator=g) < 0.05)
+    ref = torch.empty_like(rho)
+    out = torch.full_like(rho, float("nan"))
+    st = torch.cuda.current_stream()
+    p = sbx.Poisson(N, 2.0, 0.5, G=1.0, prec=prec, stream=st.cuda_stream)
+    p.sbx_poisson_solve(batch, rho.data_ptr(), ref.data_ptr())
+    p.sbx_poisson_solve_noalloc(batch, rho.data_ptr(), out.data_ptr())
+    torch.cuda.synchronize()
+    p.close()
+    return ref.double().cpu().numpy(), out.double().cpu().numpy()
+
+
+def test_noalloc_matches_allocating_solve(sbx, torch):
+    print("no-alloc: call 1, FP32 128^3 x 1", flush=True)
+    ref, out = _solve_both(sbx, torch, 128, sbx.SBX_FP32, 1, 1)
+    assert np.isfinite(out).all()
+    assert np.abs(out - ref).max() <= 3e-6 * np.abs(ref).max()
+    print("no-alloc: call 2, FP32 64^3 x 2 (smaller input)", flush=True)
+    ref, out = _solve_both(sbx, torch, 64, sbx.SBX_FP32, 2, 2)
+    assert np.isfinite(out).all()
+    assert np.abs(out - ref).max() <= 3e-6 * np.abs(ref).max()
+    print("no-alloc: call 3, FP64 32^3 x 3", flush=True)
+    ref, out = _solve_both(sbx, torch, 32, sbx.SBX_FP64, 3, 3)
+    assert np.isfinite(out).all()
+    assert np.abs(out - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_noalloc_rejects_batches_beyond_the_work_space(sbx, torch):
+    st = torch.cuda.current_stream()
+    for N, prec, batch in ((128, sbx.SBX_FP32, 2), (128, sbx.SBX_FP64, 1), (64, sbx.SBX_FP64, 5)):
+        dt = torch.float64 if prec == sbx.SBX_FP64 else torch.float32
+        rho = torch.zeros((batch, N, N, N), dtype=dt, device="cuda")
+        p = sbx.Poisson(N, 2.0, 1.0, prec=prec, stream=st.cuda_stream)
+        with pytest.raises(sbx.SbxError) as e:
+            p.sbx_poisson_solve_noalloc(batch, rho.data_ptr(), rho.data_ptr())
+        assert e.value.status == sbx.SBX_EINVAL and "work space" in str(e.value)
+        p.close()
+    # the largest batch that fits still runs
+    N, batch = 64, 4
+    rho = torch.rand((batch, N, N, N), dtype=torch.float64, device="cuda")
+    phi = torch.empty_like(rho)
+    ref = torch.empty_like(rho)
+    p = sbx.Poisson(N, 2.0, 1.0, prec=sbx.SBX_FP64, stream=st.cuda_stream)
+    p.sbx_poisson_solve_noalloc(batch, rho.data_ptr(), phi.data_ptr())
+    p.sbx_poisson_solve(batch, rho.data_ptr(), ref.data_ptr())
+    torch.cuda.synchronize()
+    p.close()
+    r, o = ref.cpu().numpy(), phi.cpu().numpy()
+    assert np.abs(o - r).max() <= 1e-11 * np.abs(r).max()
