@@ -267,6 +267,8 @@ void free_particles(sbx_ctx* c) {
   free_typed(c->rank);
   free_typed(c->acc);
   free_typed(c->pot);
+  free_ptr(c->adj_work);
+  c->adj_work_bytes = 0;
   c->acc_n = 0;
   c->n = 0;
   c->cur = 0;
@@ -279,6 +281,8 @@ void free_grids(sbx_ctx* c) {
   plan_destroy(c->adj32);
   plan_destroy(c->adj64);
   free_ptr(c->adj_block);
+  free_ptr(c->adj_work);
+  c->adj_work_bytes = 0;
   free_ptr(c->grid_block);
   free_typed(c->count);
   free_typed(c->scan_tmp);
@@ -530,13 +534,16 @@ sbx_status copy_set(sbx_ctx* c, const PSet& dst, const PSet& src, bool with_v, b
 }
 
 // Forward nsteps without sorting, checkpoints of (x, v, lost) every
-// ckpt_every steps, then the reverse cycles segment by segment: positions
-// and lost flags of a segment's cycles are recomputed from its checkpoint,
-// each reverse cycle re-solves the fields from the particles that took part
-// in that cycle (live after its start-of-step loss test), scatters the
-// adjoint sources, solves them and gathers the mass gradient.  A particle
-// lost during the segment thus collects dL/dm from the cycles before its
-// loss, and passes its adjoints unchanged through the cycles it sat out.
+// ckpt_every steps, then the reverse cycles interval by interval.  The
+// positions, lost flags and fields of an interval's cycles are recomputed
+// from its checkpoint (the last interval keeps them from the forward pass):
+// each cycle's solve runs from the particles that take part in it (live
+// after its start-of-step loss test), and its lost flags and fields are kept
+// for the reverse cycle, which scatters the adjoint sources, solves them and
+// gathers the mass gradient.  A particle lost during the segment thus
+// collects dL/dm from the cycles before its loss, and passes its adjoints
+// unchanged through the cycles it sat out.  Work arrays live in one device
+// buffer of the context, kept between calls.
 template <typename T>
 sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, int sel_gal,
                      double* loss, double* grad_m, double* grad_x, double* grad_v, bool dev_out) {
@@ -544,91 +551,109 @@ sbx_status adjoint_t(sbx_ctx* c, double dt, int nsteps, int ckpt, int sel_comp, 
   SBX_TRY(set_dt(c, dt));
   const int64_t n = c->n;
   const int nck = (nsteps + ckpt - 1) / ckpt;
-  std::vector<void*> allocs;
-  auto alloc = [&](size_t bytes, void** p) -> sbx_status {
-    const sbx_status r = dev_alloc(p, bytes);
-    if (r == SBX_OK) allocs.push_back(*p);
-    return r;
-  };
-  auto make_set = [&](PSet& s, bool v, bool lost) -> sbx_status {
-    for (int k = 0; k < 3; ++k) {
-      SBX_TRY(alloc(sizeof(T) * n, &s.x[k]));
-      if (v) SBX_TRY(alloc(sizeof(T) * n, &s.v[k]));
+  // carve the work buffer: checkpoints (x, v, lost), per-cycle (x, lost) and
+  // fields of one interval, adjoint state, loss, staging
+  size_t need = 0;
+  auto take = [&](size_t bytes) { const size_t at = need; need += (bytes + 255) & ~(size_t)255; return at; };
+  std::vector<size_t> ck_off(nck + 1), xb_off(ckpt), fb_off(ckpt);
+  const size_t set_x = 3 * sizeof(T) * n;
+  for (auto& o : ck_off) o = take(2 * set_x + n);
+  for (auto& o : xb_off) o = take(set_x + n);
+  for (auto& o : fb_off) o = take(sizeof(T) * c->grid_elems);
+  const size_t lx_off = take(sizeof(double) * 3 * n), lv_off = take(sizeof(double) * 3 * n);
+  const size_t gm_off = take(sizeof(double) * n), dl_off = take(sizeof(double) * 4);
+  const size_t st_off = take(sizeof(double) * 3 * n);
+  if (c->adj_work_bytes < need) {
+    free_ptr(c->adj_work);
+    c->adj_work_bytes = 0;
+    SBX_TRY(dev_alloc(&c->adj_work, need));
+    c->adj_work_bytes = need;
+  }
+  char* base = (char*)c->adj_work;
+  auto set_at = [&](size_t off, bool with_v, PSet& s) {
+    char* q = base + off;
+    for (int k = 0; k < 3; ++k) s.x[k] = q + sizeof(T) * n * k;
+    q += set_x;
+    if (with_v) {
+      for (int k = 0; k < 3; ++k) s.v[k] = q + sizeof(T) * n * k;
+      q += set_x;
     }
-    if (lost) SBX_TRY(alloc(n, (void**)&s.lost));
+    s.lost = (uint8_t*)q;
+  };
+  std::vector<PSet> cks(nck + 1), xb(ckpt);
+  for (int i = 0; i <= nck; ++i) set_at(ck_off[i], true, cks[i]);
+  for (int i = 0; i < ckpt; ++i) set_at(xb_off[i], false, xb[i]);
+  double* lx = (double*)(base + lx_off);
+  double* lv = (double*)(base + lv_off);
+  double* gm = (double*)(base + gm_off);
+  double* dloss = (double*)(base + dl_off);
+  double* stage = (double*)(base + st_off);
+  const size_t gbytes = sizeof(T) * c->grid_elems;
+  // reorder by cell once for the segment (locality of the gathers and of
+  // the adjoint scatter); nothing is reordered inside the segment
+  if (c->sort_every > 0 && !c->bound) SBX_TRY(sort_particles(c));
+  PSet& live = c->set[c->cur];
+  // one cycle with its record for the reverse: positions before the solve,
+  // lost flags after its loss test, fields after the solve
+  auto cycle = [&](int slot, bool move) -> sbx_status {
+    SBX_TRY(copy_set<T>(c, xb[slot], live, false, false));
+    SBX_TRY(field_solve(c));
+    SBX_HIP(hipMemcpyAsync(xb[slot].lost, live.lost, n, hipMemcpyDeviceToDevice, c->stream));
+    SBX_HIP(hipMemcpyAsync(base + fb_off[slot], c->grid_block, gbytes, hipMemcpyDeviceToDevice, c->stream));
+    if (move) SBX_TRY(force(c, 1));
     return SBX_OK;
   };
-  double *lx = nullptr, *lv = nullptr, *gm = nullptr, *dloss = nullptr, *stage = nullptr;
-  auto body = [&]() -> sbx_status {
-    std::vector<PSet> cks(nck + 1), xb(ckpt);
-    for (auto& s : cks) SBX_TRY(make_set(s, true, true));
-    for (auto& s : xb) SBX_TRY(make_set(s, false, true));
-    SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&lx));
-    SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&lv));
-    SBX_TRY(alloc(sizeof(double) * n, (void**)&gm));
-    SBX_TRY(alloc(sizeof(double) * 4, (void**)&dloss));
-    SBX_TRY(alloc(sizeof(double) * 3 * n, (void**)&stage));
-    // reorder by cell once for the segment (locality of the gathers and of
-    // the adjoint scatter); nothing is reordered inside the segment
-    if (c->sort_every > 0 && !c->bound) SBX_TRY(sort_particles(c));
-    PSet& live = c->set[c->cur];
-    // forward with checkpoints
-    for (int k = 0; k < nsteps; ++k) {
-      if (k % ckpt == 0) SBX_TRY(copy_set<T>(c, cks[k / ckpt], live, true, true));
+  // forward with checkpoints; the last interval keeps its records
+  const int k0_last = (nck - 1) * ckpt;
+  for (int k = 0; k < nsteps; ++k) {
+    if (k % ckpt == 0) SBX_TRY(copy_set<T>(c, cks[k / ckpt], live, true, true));
+    if (k >= k0_last) {
+      SBX_TRY(cycle(k - k0_last, true));
+    } else {
       SBX_TRY(field_solve(c));
       SBX_TRY(force(c, 1));
     }
-    SBX_TRY(copy_set<T>(c, cks[nck], live, true, true));  // final state
-    SBX_TRY(launch_adj_init<T>(dinst<T>(c), c->d_cur, n, sel_comp, sel_gal, lx, lv, gm, c->pre_partial,
-                               dloss, c->stream));
-    const GridsDev<T> B = adj_grids<T>(c);
-    for (int seg = nck - 1; seg >= 0; --seg) {
-      const int k0 = seg * ckpt, k1 = std::min(k0 + ckpt, nsteps);
+  }
+  SBX_TRY(copy_set<T>(c, cks[nck], live, true, true));  // final state
+  SBX_TRY(launch_adj_init<T>(dinst<T>(c), c->d_cur, n, sel_comp, sel_gal, lx, lv, gm, c->pre_partial,
+                             dloss, c->stream));
+  const GridsDev<T> B = adj_grids<T>(c);
+  SolvePlan<T>& adj = sizeof(T) == 8 ? (SolvePlan<T>&)c->adj64 : (SolvePlan<T>&)c->adj32;
+  for (int seg = nck - 1; seg >= 0; --seg) {
+    const int k0 = seg * ckpt, k1 = std::min(k0 + ckpt, nsteps);
+    if (seg < nck - 1) {
       SBX_TRY(copy_set<T>(c, live, cks[seg], true, true));
-      c->com_fresh = false;
-      for (int k = k0; k < k1; ++k) {
-        // positions and lost flags at the start of cycle k
-        SBX_TRY(copy_set<T>(c, xb[k - k0], live, false, true));
-        if (k + 1 < k1) {
-          SBX_TRY(field_solve(c));
-          SBX_TRY(force(c, 1));
-        }
-      }
-      for (int k = k1 - 1; k >= k0; --k) {
-        SBX_TRY(copy_set<T>(c, live, xb[k - k0], false, true));
-        // the solve's loss test leaves in live.lost exactly the particles
-        // that sat out cycle k
-        c->com_fresh = false;
-        SBX_TRY(field_solve(c));
-        SBX_TRY(launch_zero<T>((T*)c->adj_block, c->grid_elems, c->stream));
-        SBX_TRY(launch_adj_step<T>(dinst<T>(c), c->d_cur, n, B, live.lost, lx, lv, c->stream));
-        SolvePlan<T>& adj = sizeof(T) == 8 ? (SolvePlan<T>&)c->adj64 : (SolvePlan<T>&)c->adj32;
-        SBX_TRY(plan_run<T>(adj, c->stream));
-        SBX_TRY(launch_adj_gather<T>(dinst<T>(c), c->d_cur, n, B, live.lost, gm, c->stream));
-      }
+      c->com_fresh = false;  // the first solve runs the start-of-step loss test
+      for (int k = k0; k < k1; ++k) SBX_TRY(cycle(k - k0, k + 1 < k1));
     }
-    SBX_TRY(copy_set<T>(c, live, cks[nck], true, true));  // back to the final state
-    c->com_fresh = false;
-    c->grids_fields = false;
-    c->step_count += nsteps;
-    // outputs in the caller's order
-    const int32_t* id = live.id;
-    if (loss) SBX_HIP(hipMemcpyAsync(loss, dloss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    struct Out { double* host; double* dev; int w; } outs[3] = {{grad_m, gm, 1}, {grad_x, lx, 3}, {grad_v, lv, 3}};
-    for (auto& o : outs) {
-      if (!o.host) continue;
-      SBX_TRY(launch_unpermute<double>(o.dev, id, dev_out ? o.host : stage, n, o.w, c->stream));
-      if (!dev_out)
-        SBX_HIP(hipMemcpyAsync(o.host, stage, sizeof(double) * o.w * n, hipMemcpyDeviceToHost, c->stream));
-      SBX_HIP(hipStreamSynchronize(c->stream));
+    for (int k = k1 - 1; k >= k0; --k) {
+      // positions, sat-out flags and forward fields of cycle k
+      SBX_TRY(copy_set<T>(c, live, xb[k - k0], false, true));
+      SBX_HIP(hipMemcpyAsync(c->grid_block, base + fb_off[k - k0], gbytes, hipMemcpyDeviceToDevice,
+                             c->stream));
+      SBX_TRY(launch_zero<T>((T*)c->adj_block, c->grid_elems, c->stream));
+      SBX_TRY(launch_adj_step<T>(dinst<T>(c), c->d_cur, n, B, live.lost, lx, lv, c->stream));
+      SBX_TRY(plan_run<T>(adj, c->stream));
+      SBX_TRY(launch_adj_gather<T>(dinst<T>(c), c->d_cur, n, B, live.lost, gm, c->stream));
     }
+  }
+  SBX_TRY(copy_set<T>(c, live, cks[nck], true, true));  // back to the final state
+  c->com_fresh = false;
+  c->grids_fields = false;
+  c->step_count += nsteps;
+  // outputs in the caller's order
+  const int32_t* id = live.id;
+  if (loss) SBX_HIP(hipMemcpyAsync(loss, dloss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  struct Out { double* host; double* dev; int w; } outs[3] = {{grad_m, gm, 1}, {grad_x, lx, 3}, {grad_v, lv, 3}};
+  for (auto& o : outs) {
+    if (!o.host) continue;
+    SBX_TRY(launch_unpermute<double>(o.dev, id, dev_out ? o.host : stage, n, o.w, c->stream));
+    if (!dev_out)
+      SBX_HIP(hipMemcpyAsync(o.host, stage, sizeof(double) * o.w * n, hipMemcpyDeviceToHost, c->stream));
     SBX_HIP(hipStreamSynchronize(c->stream));
-    return SBX_OK;
-  };
-  const sbx_status rc = body();
-  (void)hipStreamSynchronize(c->stream);
-  for (void* p : allocs) (void)hipFree(p);
-  return rc;
+  }
+  SBX_HIP(hipStreamSynchronize(c->stream));
+  return SBX_OK;
 }
 
 }  // namespace

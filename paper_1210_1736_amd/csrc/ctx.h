@@ -76,6 +76,8 @@ struct sbx_ctx {
   sbx::SolvePlan<double> plan64;
   // adjoint grids (same layout as the grids) and their solve plan
   void* adj_block = nullptr;
+  void* adj_work = nullptr;      // segment adjoint work arrays, kept between calls
+  size_t adj_work_bytes = 0;
   sbx::SolvePlan<float> adj32;
   sbx::SolvePlan<double> adj64;
   // density-maximum centring: integer cell masses, search scratch, block sums

@@ -31,12 +31,12 @@ def _rng(k):
 
 
 def _galaxy(centring="com", n_out=40):
-    """The small nested galaxy plus particles placed off the global grid (lost
-    at the first step)."""
+    """The small nested galaxy plus particles placed off the global grid (a
+    cube of half-extent 20; they are lost at the first step)."""
     w = T.small_galaxy(scale=0.003, N=32, centring=centring, q=1.0)
     rng = _rng(1)
     xo = rng.normal(size=(n_out, 3))
-    xo = 30.0 * xo / np.linalg.norm(xo, axis=1)[:, None]
+    xo = 25.0 * xo / np.abs(xo).max(axis=1)[:, None]   # outside the cube of half-extent 20
     w.x = np.vstack([w.x, xo]); w.v = np.vstack([w.v, np.zeros((n_out, 3))])
     w.m = np.concatenate([w.m, np.full(n_out, w.m[0])])
     w.comp = np.concatenate([w.comp, np.zeros(n_out, np.int8)])
