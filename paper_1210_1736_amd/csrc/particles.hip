@@ -1146,29 +1146,46 @@ __global__ void __launch_bounds__(256)
 // A particle's slot is the start of its bin (the counts scanned, global over
 // all instances) plus its place in the bin from the key pass; part_base
 // turns it into the instance's own slot.
+//
+// The reorder as a gather: k_sort_perm writes, for every particle, its
+// source index at its destination slot (one scattered 4-byte stream, into
+// the destination set's id array), then k_sort_gather fills each
+// destination slot from its source, so the eleven streams are written
+// whole, in order, and only read scattered.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_sort_perm(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  const int ii = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[ii];
+  const InstDev<T>& I = inst[ii];
+  const int c0 = cur[ii];
+  const PartDev<T> d = I.p[c0 ^ 1];
+  const int64_t q = (int64_t)lb * 256 + threadIdx.x;
+  if (q >= d.n) return;
+  const uint32_t k = glb((const uint32_t*)I.key)[q];
+  const uint32_t r = glb((const uint32_t*)I.rank)[q];
+  const uint32_t j = glb((const uint32_t*)I.count)[k] + r - I.part_base;
+  glb(d.id)[j] = (int32_t)q;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_sort_scatter(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+    k_sort_gather(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
   const int ii = span_inst(sp, blockIdx.x);
   const int lb = blockIdx.x - sp.start[ii];
   const InstDev<T>& I = inst[ii];
   const int c0 = cur[ii];
   const PartDev<T> s = I.p[c0];
   const PartDev<T> d = I.p[c0 ^ 1];
-  const int64_t q = (int64_t)lb * 256 + threadIdx.x;
-  if (q >= s.n) return;
-  // the particle, its key and its place load together, then the start of
-  // its bin
-  const uint32_t k = glb((const uint32_t*)I.key)[q];
-  const uint32_t r = glb((const uint32_t*)I.rank)[q];
+  const int64_t j = (int64_t)lb * 256 + threadIdx.x;
+  if (j >= d.n) return;
+  const int64_t q = glb(d.id)[j];
   const T x0 = glb((const T*)s.x[0])[q], x1 = glb((const T*)s.x[1])[q], x2 = glb((const T*)s.x[2])[q];
   const T v0 = glb((const T*)s.v[0])[q], v1 = glb((const T*)s.v[1])[q], v2 = glb((const T*)s.v[2])[q];
   const T m = glb((const T*)s.m)[q];
   const int8_t comp = glb((const int8_t*)s.comp)[q], gal = glb((const int8_t*)s.gal)[q];
   const uint8_t lost = glb((const uint8_t*)s.lost)[q];
   const int32_t id = glb((const int32_t*)s.id)[q];
-  const uint32_t j = glb((const uint32_t*)I.count)[k] + r - I.part_base;
   glb((T*)d.x[0])[j] = x0;
   glb((T*)d.x[1])[j] = x1;
   glb((T*)d.x[2])[j] = x2;
@@ -1586,7 +1603,8 @@ sbx_status launch_sort(const InstDev<T>* inst, int* cur, const std::vector<InstI
   SBX_HIP(hipGetLastError());
   SBX_TRY(exclusive_scan_u32(counts, total_counts, tmp, s));
   const Span sq = make_span(info, blocks_sort);
-  hipLaunchKernelGGL((k_sort_scatter<T>), dim3(sq.start[sq.ninst]), dim3(256), 0, s, inst, cur, sq);
+  hipLaunchKernelGGL((k_sort_perm<T>), dim3(sq.start[sq.ninst]), dim3(256), 0, s, inst, cur, sq);
+  hipLaunchKernelGGL((k_sort_gather<T>), dim3(sq.start[sq.ninst]), dim3(256), 0, s, inst, cur, sq);
   hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, cur, (int)info.size());
   SBX_HIP(hipGetLastError());
   return SBX_OK;
