@@ -588,6 +588,10 @@ def main():
         / (1e-3 * sum(per_step.get(k, 0.0) for k in FFT_PASSES)) / 1e9 / HBM_PEAK_GBS,
         "roofline": roof,
         "cpu_baseline": cpu,
+        # the launch shapes the tuner chose for the step's five 128^3 solves
+        # (block size, persistent grid, values per thread of a line)
+        "fft_tuning": [l for l in sbx.sbx_fft_tuning_report().splitlines()
+                       if " N=128 x5 " in l],
     }
     print(json.dumps(out), flush=True)
 

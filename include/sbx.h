@@ -436,6 +436,24 @@ sbx_status sbx_poisson_green(sbx_poisson* p, double* out, double* rel_imag);
 /* Device bytes the plan holds. */
 int64_t sbx_poisson_bytes(sbx_poisson* p);
 
+/* Line schedule of the FFT passes of every solve (Eqs. 3-5): a line of
+ * length L = 2n is transformed with 16 or 32 values per thread (radix 16,
+ * then L/16, then 2 if L/16 > 16; or radix 32, then L/32).  In FP32, lines of
+ * 128 points and more (n >= 64) have both, and the launch-shape tuner times
+ * both the first time a precision, grid size and solve count is planned.
+ * v = 16 or 32 pins that schedule for every plan made from now on, in every
+ * context and standalone plan of the process (plans already made keep
+ * theirs); v = 0 (the default) lets the tuner choose.  Lengths with one
+ * schedule ignore the pin.  SBX_EINVAL for other values. */
+sbx_status sbx_set_fft_schedule(int32_t v);
+
+/* The launch shapes the tuner has chosen so far in this process, one line
+ * per precision, grid size, solve count and pass ("fp32 N=128 x5 zpass
+ * nt=256 grid=1024 v=16"; grid=tiles: one block per tile).  Writes at most
+ * cap bytes including a terminating NUL into out (may be NULL when cap is
+ * 0) and returns the length of the whole report. */
+int64_t sbx_fft_tuning_report(char* out, int64_t cap);
+
 #ifdef __cplusplus
 }
 #endif

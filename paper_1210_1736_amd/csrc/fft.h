@@ -14,10 +14,13 @@
 // Zero halves of the padded inputs are never read, unused halves of the
 // outputs never written.  Hhat (real, even per axis) is stored on (N+1)^3.
 //
-// Every pass is one persistent launch over all solves of a plan, whatever
-// their grid sizes: blocks pull (solve, tile) work items from a counter and
-// dispatch on the line length.  Block size and grid size of each pass are
-// chosen by timing candidates the first time a mix of sizes is planned.
+// Every pass is one persistent launch over all solves of one grid size:
+// blocks pull (solve, tile) work items from a counter.  The size groups of a
+// plan are independent and run concurrently, each on a stream of its own
+// forked from and joined back to the caller's stream (concurrent branches
+// when the caller captures a graph).  Line schedule (radix split), block
+// size and grid size of each pass are chosen by timing the candidates the
+// first time a precision, grid size and solve count is planned.
 #pragma once
 
 #include <vector>
@@ -44,6 +47,7 @@ constexpr int kPasses = 5;
 struct PassShape {
   int nt;     // threads per block
   int grid;   // persistent blocks (0: one block per tile)
+  int v = 0;  // values per thread of a line (16 or 32; 0: the length's default)
 };
 
 constexpr int kMaxGroups = 6;  // distinct grid sizes 8..256
@@ -51,7 +55,7 @@ constexpr int kMaxGroups = 6;  // distinct grid sizes 8..256
 // Solves of one grid size inside a plan.
 struct SolveGroup {
   int first = 0, count = 0, N = 0;
-  const void* tw = nullptr;          // twiddle table of line length 2N
+  const void* tw[kPasses] = {};      // twiddle table of line length 2N, per pass's schedule
   PassShape shape[kPasses] = {};
 };
 
@@ -63,6 +67,11 @@ struct SolvePlan {
   int* d_counter = nullptr;          // kPasses * kMaxGroups work counters
   int ngroups = 0;
   SolveGroup groups[kMaxGroups];
+  // with several groups: streams of groups 1.. (group 0 runs on the
+  // caller's stream) and the fork and join events
+  hipStream_t side[kMaxGroups] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kMaxGroups] = {};
 };
 
 // Workspace sizes in elements of C2<T>.
@@ -81,8 +90,11 @@ inline size_t h_elems(int N) { return (size_t)(N + 1) * (N + 1) * (N + 1); }
 template <typename T>
 sbx_status plan_create(SolvePlan<T>& plan, const SolveDesc<T>* descs, int n, hipStream_t s);
 
-// Run all solves of the plan (five launches; each pass clears the work
-// counter of the pass before it, so the counters are zero between runs).
+// Run all solves of the plan (five launches per size group; each pass
+// clears the work counter of the pass before it, so the counters are zero
+// between runs).  With several size groups the groups run on concurrent
+// streams between a fork and a join on s; phase marks are then all taken
+// at the join.
 template <typename T>
 sbx_status plan_run(const SolvePlan<T>& plan, hipStream_t s, Recorder* rec = nullptr);
 
@@ -109,6 +121,10 @@ sbx_status prepare_twiddles(int N, hipStream_t s);
 template <typename T>
 sbx_status run_solves_noalloc(const SolveDesc<T>* d_solves, int nsolves, int N, int* d_counter,
                               hipStream_t s);
+
+// Pin the line schedule of plans tuned from now on to v values per thread
+// (16 or 32, where a line length has both; 0: time both).  Process-wide.
+sbx_status set_fft_schedule(int v);
 
 // Whether launch shapes for this precision and mix of grid sizes are cached.
 bool tuning_cached(int esz, std::vector<int> mix);

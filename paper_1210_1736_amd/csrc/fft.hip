@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <array>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <type_traits>
 
@@ -36,9 +37,9 @@ __device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
 // scatter to the input positions).  The last forward pass reads and writes
 // the same positions, which is what lets the z pass apply the Green's
 // function and the first inverse pass in registers.
-template <typename T, int L>
+template <typename T, int L, int V>
 struct Line {
-  static constexpr int VPT = (L == 512 && sizeof(T) == 4) ? 32 : 16;
+  static constexpr int VPT = V;
   static constexpr int TL = L / VPT;
   static constexpr int NP = L == 16 ? 1 : (L / VPT <= 16 ? 2 : 3);
   template <int p>
@@ -49,6 +50,15 @@ struct Line {
   static constexpr int TW = p == 2 ? 15 * VPT : 0;  // offset of the pass in the twiddle table
 };
 
+// The schedule of a line length unless the autotuner picks the other one:
+// 32 values per thread for L = 512 in FP32, else 16.  In FP32, lines of
+// L >= 128 have both (16: radix 16 then L/16 (then 2); 32: radix 32 then
+// L/32), and the tuner times both.
+template <typename T, int L>
+constexpr int kDefV = (L == 512 && sizeof(T) == 4) ? 32 : 16;
+template <typename T, int L>
+constexpr bool kTwoV = sizeof(T) == 4 && L >= 128;
+
 // Order the LDS accesses of one wavefront (they execute in issue order).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -56,20 +66,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, int L, int p>
+template <typename T, int L, int V, int p>
 __device__ __forceinline__ int pos_in(int j, int r) {
-  return j + r * (L / Line<T, L>::template R<p>);
+  return j + r * (L / Line<T, L, V>::template R<p>);
 }
-template <typename T, int L, int p>
+template <typename T, int L, int V, int p>
 __device__ __forceinline__ int pos_out(int j, int r) {
-  constexpr int NS = Line<T, L>::template NS<p>, R = Line<T, L>::template R<p>;
+  constexpr int NS = Line<T, L, V>::template NS<p>, R = Line<T, L, V>::template R<p>;
   const int k = j & (NS - 1);
   return (j - k) * R + k + r * NS;
 }
 
-template <typename T, int L, int p>
+template <typename T, int L, int V, int p>
 __device__ __forceinline__ void fwd_bfly(C2<T>* v, int t, const C2<T>* __restrict__ tw) {
-  using F = Line<T, L>;
+  using F = Line<T, L, V>;
   constexpr int R = F::template R<p>, NS = F::template NS<p>, BPT = F::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
@@ -83,9 +93,9 @@ __device__ __forceinline__ void fwd_bfly(C2<T>* v, int t, const C2<T>* __restric
   }
 }
 
-template <typename T, int L, int p>
+template <typename T, int L, int V, int p>
 __device__ __forceinline__ void inv_bfly(C2<T>* v, int t, const C2<T>* __restrict__ tw) {
-  using F = Line<T, L>;
+  using F = Line<T, L, V>;
   constexpr int R = F::template R<p>, NS = F::template NS<p>, BPT = F::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
@@ -101,83 +111,83 @@ __device__ __forceinline__ void inv_bfly(C2<T>* v, int t, const C2<T>* __restric
 
 // LDS gathers and scatters of one line (padded by one element per 16).
 // ZHI: the upper half of the line's input is zero (padded input).
-template <typename T, int L, int p, bool ZHI>
+template <typename T, int L, int V, int p, bool ZHI>
 __device__ __forceinline__ void gather_in(const C2<T>* s, int t, C2<T>* v) {
-  constexpr int R = Line<T, L>::template R<p>, BPT = Line<T, L>::VPT / R;
+  constexpr int R = Line<T, L, V>::template R<p>, BPT = Line<T, L, V>::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b)
 #pragma unroll
     for (int r = 0; r < R; ++r)
       v[b * R + r] = (ZHI && r >= R / 2) ? C2<T>{(T)0, (T)0}
-                                         : s[pad(pos_in<T, L, p>(t + b * Line<T, L>::TL, r))];
+                                         : s[pad(pos_in<T, L, V, p>(t + b * Line<T, L, V>::TL, r))];
 }
 // HALF: only positions below L/2 are kept (cropped output).
-template <typename T, int L, int p, bool HALF>
+template <typename T, int L, int V, int p, bool HALF>
 __device__ __forceinline__ void scatter_in(C2<T>* s, int t, const C2<T>* v) {
-  constexpr int R = Line<T, L>::template R<p>, BPT = Line<T, L>::VPT / R;
+  constexpr int R = Line<T, L, V>::template R<p>, BPT = Line<T, L, V>::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b)
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (!HALF || r < R / 2) s[pad(pos_in<T, L, p>(t + b * Line<T, L>::TL, r))] = v[b * R + r];
+      if (!HALF || r < R / 2) s[pad(pos_in<T, L, V, p>(t + b * Line<T, L, V>::TL, r))] = v[b * R + r];
 }
-template <typename T, int L, int p>
+template <typename T, int L, int V, int p>
 __device__ __forceinline__ void gather_out(const C2<T>* s, int t, C2<T>* v) {
-  constexpr int R = Line<T, L>::template R<p>, BPT = Line<T, L>::VPT / R;
+  constexpr int R = Line<T, L, V>::template R<p>, BPT = Line<T, L, V>::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b)
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[b * R + r] = s[pad(pos_out<T, L, p>(t + b * Line<T, L>::TL, r))];
+    for (int r = 0; r < R; ++r) v[b * R + r] = s[pad(pos_out<T, L, V, p>(t + b * Line<T, L, V>::TL, r))];
 }
-template <typename T, int L, int p>
+template <typename T, int L, int V, int p>
 __device__ __forceinline__ void scatter_out(C2<T>* s, int t, const C2<T>* v) {
-  constexpr int R = Line<T, L>::template R<p>, BPT = Line<T, L>::VPT / R;
+  constexpr int R = Line<T, L, V>::template R<p>, BPT = Line<T, L, V>::VPT / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b)
 #pragma unroll
-    for (int r = 0; r < R; ++r) s[pad(pos_out<T, L, p>(t + b * Line<T, L>::TL, r))] = v[b * R + r];
+    for (int r = 0; r < R; ++r) s[pad(pos_out<T, L, V, p>(t + b * Line<T, L, V>::TL, r))] = v[b * R + r];
 }
 
 // Forward passes PS..NP-1 on an LDS line, in place; v holds the inputs of
 // pass PS on entry (already gathered) and the last pass's outputs (natural
 // order, positions j + r L/R) on exit, also written to LDS when STORE.
-template <typename T, int L, int PS, bool STORE>
+template <typename T, int L, int V, int PS, bool STORE>
 __device__ __forceinline__ void fwd_from(C2<T>* s, int t, C2<T>* v, const C2<T>* __restrict__ tw) {
-  constexpr int NP = Line<T, L>::NP;
-  fwd_bfly<T, L, PS>(v, t, tw);
+  constexpr int NP = Line<T, L, V>::NP;
+  fwd_bfly<T, L, V, PS>(v, t, tw);
   if constexpr (PS + 1 < NP) {
-    scatter_out<T, L, PS>(s, t, v);
+    scatter_out<T, L, V, PS>(s, t, v);
     wave_sync();
-    gather_in<T, L, PS + 1, false>(s, t, v);
+    gather_in<T, L, V, PS + 1, false>(s, t, v);
     wave_sync();
-    fwd_from<T, L, PS + 1, STORE>(s, t, v, tw);
+    fwd_from<T, L, V, PS + 1, STORE>(s, t, v, tw);
   } else if constexpr (STORE) {
-    scatter_out<T, L, PS>(s, t, v);
+    scatter_out<T, L, V, PS>(s, t, v);
   }
 }
 
 // Inverse passes PE..0 (conjugate transposes, reverse order); v holds the
 // inputs of pass PE (gathered at its output positions) on entry and the
 // natural-order results of pass 0 (positions t + r TL) on exit.
-template <typename T, int L, int PE>
+template <typename T, int L, int V, int PE>
 __device__ __forceinline__ void inv_down(C2<T>* s, int t, C2<T>* v, const C2<T>* __restrict__ tw) {
-  inv_bfly<T, L, PE>(v, t, tw);
+  inv_bfly<T, L, V, PE>(v, t, tw);
   if constexpr (PE > 0) {
-    scatter_in<T, L, PE, false>(s, t, v);
+    scatter_in<T, L, V, PE, false>(s, t, v);
     wave_sync();
-    gather_out<T, L, PE - 1>(s, t, v);
+    gather_out<T, L, V, PE - 1>(s, t, v);
     wave_sync();
-    inv_down<T, L, PE - 1>(s, t, v, tw);
+    inv_down<T, L, V, PE - 1>(s, t, v, tw);
   }
 }
 
 // Full forward transform of a line held in LDS in natural order (in place).
-template <typename T, int L>
+template <typename T, int L, int V>
 __device__ __forceinline__ void line_fwd_lds(C2<T>* s, int t, const C2<T>* __restrict__ tw) {
-  C2<T> v[Line<T, L>::VPT];
-  gather_in<T, L, 0, false>(s, t, v);
+  C2<T> v[Line<T, L, V>::VPT];
+  gather_in<T, L, V, 0, false>(s, t, v);
   wave_sync();
-  fwd_from<T, L, 0, true>(s, t, v, tw);
+  fwd_from<T, L, V, 0, true>(s, t, v, tw);
   wave_sync();
 }
 
@@ -194,57 +204,76 @@ __global__ void k_twiddle(C2<T>* tw, int R, int NS) {
 // Twiddle table for length L: for every pass after the first, at the
 // pass's offset, entries (r-1)*NS + k = exp(-2 pi i k r / (NS R)),
 // r = 1..R-1, k = 0..NS-1.
-template <typename T, int L, int p>
+template <typename T, int L, int V, int p>
 static int tw_fill(C2<T>* tw, hipStream_t st) {
-  using F = Line<T, L>;
+  using F = Line<T, L, V>;
   if constexpr (p >= F::NP) {
     return F::template TW<p - 1> + (F::template R<p - 1> - 1) * F::template NS<p - 1>;
   } else {
     constexpr int R = F::template R<p>, NS = F::template NS<p>, n = (R - 1) * NS;
     if (tw) hipLaunchKernelGGL(k_twiddle<T>, dim3((n + 255) / 256), dim3(256), 0, st,
                                tw + F::template TW<p>, R, NS);
-    return tw_fill<T, L, p + 1>(tw, st);
+    return tw_fill<T, L, V, p + 1>(tw, st);
   }
 }
 
+template <typename T, int L>
+static int tw_make_l(int V, C2<T>* tw, hipStream_t st) {
+  if constexpr (kTwoV<T, L>) {
+    if (V == 32) return tw_fill<T, L, 32, 1>(tw, st);
+    if (V == 16) return tw_fill<T, L, 16, 1>(tw, st);
+  }
+  return tw_fill<T, L, kDefV<T, L>, 1>(tw, st);
+}
+
 template <typename T>
-static int tw_make(int L, C2<T>* tw, hipStream_t st) {
+static int tw_make(int L, int V, C2<T>* tw, hipStream_t st) {
   switch (L) {
     case 16: return 1;
-    case 32: return tw_fill<T, 32, 1>(tw, st);
-    case 64: return tw_fill<T, 64, 1>(tw, st);
-    case 128: return tw_fill<T, 128, 1>(tw, st);
-    case 256: return tw_fill<T, 256, 1>(tw, st);
-    default: return tw_fill<T, 512, 1>(tw, st);
+    case 32: return tw_make_l<T, 32>(V, tw, st);
+    case 64: return tw_make_l<T, 64>(V, tw, st);
+    case 128: return tw_make_l<T, 128>(V, tw, st);
+    case 256: return tw_make_l<T, 256>(V, tw, st);
+    default: return tw_make_l<T, 512>(V, tw, st);
   }
 }
 
-// Twiddle tables are made once per (device, precision, length) and kept for
-// the life of the process.  With create = false a missing table is not made
-// (nothing is allocated) and null is returned.
+// Schedule actually used for values per thread v of a line length (0 or an
+// unavailable value: the default one).
 template <typename T>
-const C2<T>* twiddles(int L, hipStream_t st, bool create = true) {
+static int eff_v(int L, int v) {
+  const bool two = sizeof(T) == 4 && L >= 128;
+  const int def = (L == 512 && sizeof(T) == 4) ? 32 : 16;
+  return two && (v == 16 || v == 32) ? v : def;
+}
+
+// Twiddle tables are made once per (device, precision, length, schedule)
+// and kept for the life of the process.  With create = false a missing
+// table is not made (nothing is allocated) and null is returned.
+template <typename T>
+const C2<T>* twiddles(int L, int v, hipStream_t st, bool create = true) {
   static std::mutex mu;
-  static C2<T>* cache[64][10] = {};
+  static C2<T>* cache[64][10][2] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
   int lg = 0;
   while ((1 << lg) < L) ++lg;
+  const int V = eff_v<T>(L, v), vi = V == 32 ? 1 : 0;
   std::lock_guard<std::mutex> g(mu);
-  if (cache[dev][lg] || !create) return cache[dev][lg];
+  if (cache[dev][lg][vi] || !create) return cache[dev][lg][vi];
   C2<T>* p = nullptr;
-  if (hipMalloc(&p, sizeof(C2<T>) * tw_make<T>(L, nullptr, st)) != hipSuccess) return nullptr;
-  tw_make<T>(L, p, st);
+  if (hipMalloc(&p, sizeof(C2<T>) * tw_make<T>(L, V, nullptr, st)) != hipSuccess) return nullptr;
+  tw_make<T>(L, V, p, st);
   if (hipStreamSynchronize(st) != hipSuccess) {
     (void)hipFree(p);
     return nullptr;
   }
-  cache[dev][lg] = p;
+  cache[dev][lg][vi] = p;
   return p;
 }
 
-template const C2<float>* twiddles<float>(int, hipStream_t, bool);
-template const C2<double>* twiddles<double>(int, hipStream_t, bool);
+template const C2<float>* twiddles<float>(int, int, hipStream_t, bool);
+template const C2<double>* twiddles<double>(int, int, hipStream_t, bool);
 
 // ------------------------------------------------------------ tile shape ---
 // A block of NT threads covers WT = NT/TL lines at a time.  The z pass takes
@@ -254,10 +283,10 @@ template const C2<double>* twiddles<double>(int, hipStream_t, bool);
 // the LDS budget; a tile's lines are staged in LDS for the strided side.
 constexpr int kLdsCap = 81920;  // two blocks per compute unit
 
-template <typename T, int L, int NT, int PASS>
+template <typename T, int L, int V, int NT, int PASS>
 struct TC {
   static constexpr int N = L / 2;
-  static constexpr int TL = Line<T, L>::TL;
+  static constexpr int TL = Line<T, L, V>::TL;
   static constexpr int P = L + L / 16 + 1;  // LDS pitch of one line
   static constexpr int LB = P * (int)sizeof(C2<T>);
   static constexpr int WT = NT / TL;
@@ -282,19 +311,19 @@ struct TC {
 
 // tiles of each pass for one solve of line length L (the inverse y pass
 // tiles kx = 0..N, the last tile partly)
-template <typename T, int L, int NT>
+template <typename T, int L, int V, int NT>
 __host__ __device__ constexpr int tiles_of(int pass) {
   constexpr int N = L / 2;
-  return pass == 0 ? N * (N / TC<T, L, NT, 0>::W)
-       : pass == 1 ? (N + 1) * (N / TC<T, L, NT, 1>::W)
-       : pass == 2 ? (N + 1) * (L / TC<T, L, NT, 2>::W)
-       : pass == 3 ? N * ((N + TC<T, L, NT, 3>::W) / TC<T, L, NT, 3>::W)
-                   : N * (N / (2 * TC<T, L, NT, 4>::W));
+  return pass == 0 ? N * (N / TC<T, L, V, NT, 0>::W)
+       : pass == 1 ? (N + 1) * (N / TC<T, L, V, NT, 1>::W)
+       : pass == 2 ? (N + 1) * (L / TC<T, L, V, NT, 2>::W)
+       : pass == 3 ? N * ((N + TC<T, L, V, NT, 3>::W) / TC<T, L, V, NT, 3>::W)
+                   : N * (N / (2 * TC<T, L, V, NT, 4>::W));
 }
 
-template <typename T, int L, int NT, int PASS>
+template <typename T, int L, int V, int NT, int PASS>
 __host__ __device__ constexpr bool shape_fits() {
-  return TC<T, L, NT, PASS>::fits;
+  return TC<T, L, V, NT, PASS>::fits;
 }
 
 // ------------------------------------------------------------ the passes ---
@@ -303,10 +332,10 @@ __host__ __device__ constexpr bool shape_fits() {
 // registers); after the transform the two spectra are separated by
 // Hermitian symmetry, X_a = (Z + conj Z(-k)) / 2, X_b = -i (Z - conj Z(-k)) / 2,
 // and stored as X[kx][z][y] (kx <= N) across rows.
-template <typename T, int L, int NT>
+template <typename T, int L, int V, int NT>
 __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT, 0>;
+  using K = TC<T, L, V, NT, 0>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, WL = K::LINES;
   const int tid = threadIdx.x, t = tid % TL;
   const int z = tile / (N / W), y0 = (tile % (N / W)) * W;
@@ -317,7 +346,7 @@ __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T
       const size_t row = ((size_t)z * N + y0 + 2 * j) * N;
       const T* __restrict__ a = d.rho + row;
       const T* __restrict__ b = a + N;
-      constexpr int VPT = Line<T, L>::VPT;
+      constexpr int VPT = Line<T, L, V>::VPT;
       C2<T> v[VPT];
 #pragma unroll
       for (int r = 0; r < VPT; ++r)
@@ -331,7 +360,7 @@ __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T
           v[r].im += b2[t + r * TL];
         }
       }
-      fwd_from<T, L, 0, true>(s + j * P, t, v, tw);
+      fwd_from<T, L, V, 0, true>(s + j * P, t, v, tw);
     }
   }
   __syncthreads();
@@ -348,10 +377,10 @@ __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T
 
 // fwd_y: tile = W consecutive z at one kx; each line (y < N, contiguous) read
 // straight into registers; output C[kx][ky][z] stored across lines.
-template <typename T, int L, int NT>
+template <typename T, int L, int V, int NT>
 __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT, 1>;
+  using K = TC<T, L, V, NT, 1>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL;
   const int tid = threadIdx.x, t = tid % TL;
   const int kx = tile / (N / W), z0 = (tile % (N / W)) * W;
@@ -360,11 +389,11 @@ __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T
     const int w = u * K::WT + tid / TL;
     if (w < W) {
       const C2<T>* __restrict__ src = d.X + ((size_t)kx * N + z0 + w) * N;
-      constexpr int VPT = Line<T, L>::VPT;
+      constexpr int VPT = Line<T, L, V>::VPT;
       C2<T> v[VPT];
 #pragma unroll
       for (int r = 0; r < VPT; ++r) v[r] = r < VPT / 2 ? src[t + r * TL] : C2<T>{(T)0, (T)0};
-      fwd_from<T, L, 0, true>(s + w * P, t, v, tw);
+      fwd_from<T, L, V, 0, true>(s + w * P, t, v, tw);
     }
   }
   __syncthreads();
@@ -378,11 +407,11 @@ __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T
 // zpass: tile = W consecutive ky at one kx, one line per TL threads; forward
 // z (input z < N) from global, times Hhat in registers, inverse z, keep
 // z < N; stored transposed as D[kx][z][ky] through LDS.
-template <typename T, int L, int NT>
+template <typename T, int L, int V, int NT>
 __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT, 2>;
-  using F = Line<T, L>;
+  using K = TC<T, L, V, NT, 2>;
+  using F = Line<T, L, V>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
   constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
   const int tid = threadIdx.x, t = tid % TL, w = tid / TL;
@@ -395,20 +424,20 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
 #pragma unroll
     for (int r = 0; r < F::VPT; ++r) v[r] = r < F::VPT / 2 ? g[t + r * TL] : C2<T>{(T)0, (T)0};
     if constexpr (NP > 1) {
-      fwd_bfly<T, L, 0>(v, t, tw);
-      scatter_out<T, L, 0>(sl, t, v);
+      fwd_bfly<T, L, V, 0>(v, t, tw);
+      scatter_out<T, L, V, 0>(sl, t, v);
       wave_sync();
-      gather_in<T, L, 1, false>(sl, t, v);
+      gather_in<T, L, V, 1, false>(sl, t, v);
       wave_sync();
       if constexpr (NP > 2) {
-        fwd_bfly<T, L, 1>(v, t, tw);
-        scatter_out<T, L, 1>(sl, t, v);
+        fwd_bfly<T, L, V, 1>(v, t, tw);
+        scatter_out<T, L, V, 1>(sl, t, v);
         wave_sync();
-        gather_in<T, L, 2, false>(sl, t, v);
+        gather_in<T, L, V, 2, false>(sl, t, v);
         wave_sync();
       }
     }
-    fwd_bfly<T, L, NP - 1>(v, t, tw);
+    fwd_bfly<T, L, V, NP - 1>(v, t, tw);
     // Hhat at frequencies (kx, ky, e), e = j + r L/R of the last pass
     const T* __restrict__ H = d.H + ((size_t)kx * (N + 1) + (ky <= N ? ky : L - ky)) * (N + 1);
 #pragma unroll
@@ -418,7 +447,7 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
         const int e = t + b * TL + r * NBL;
         v[b * RL + r] = cscale(v[b * RL + r], H[e <= N ? e : L - e]);
       }
-    inv_down<T, L, NP - 1>(sl, t, v, tw);
+    inv_down<T, L, V, NP - 1>(sl, t, v, tw);
     wave_sync();
 #pragma unroll
     for (int r = 0; r < F::VPT / 2; ++r) sl[pad(t + r * TL)] = v[r];
@@ -434,11 +463,11 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
 // inv_y: tile = W consecutive kx (<= N) at one z; lines D[kx][z][0..2N)
 // read straight into registers; output y < N stored transposed as
 // E[z][y][kx] (in the X buffer, rows padded to N + kEPad) through LDS.
-template <typename T, int L, int NT>
+template <typename T, int L, int V, int NT>
 __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT, 3>;
-  using F = Line<T, L>;
+  using K = TC<T, L, V, NT, 3>;
+  using F = Line<T, L, V>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
   constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
   constexpr int NKT = (N + W) / W;  // kx tiles
@@ -456,7 +485,7 @@ __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T
       for (int b = 0; b < F::VPT / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) v[b * RL + r] = src[t + b * TL + r * NBL];
-      inv_down<T, L, NP - 1>(sl, t, v, tw);
+      inv_down<T, L, V, NP - 1>(sl, t, v, tw);
       wave_sync();
 #pragma unroll
       for (int r = 0; r < F::VPT / 2; ++r) sl[pad(t + r * TL)] = v[r];
@@ -475,11 +504,11 @@ __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T
 // into one complex line, read straight into registers; the inverse
 // transform's real and imaginary parts are the two real output rows x < N.
 // No block barrier.
-template <typename T, int L, int NT>
+template <typename T, int L, int V, int NT>
 __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
-  using K = TC<T, L, NT, 4>;
-  using F = Line<T, L>;
+  using K = TC<T, L, V, NT, 4>;
+  using F = Line<T, L, V>;
   constexpr int N = K::N, W = K::W, P = K::P, TL = K::TL, NP = F::NP;
   constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
   const int tid = threadIdx.x, t = tid % TL, j = tid / TL;
@@ -502,7 +531,7 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
         v[b * RL + r] = C2<T>{a.re + q.im, q.re - a.im};
       }
     }
-  inv_down<T, L, NP - 1>(sl, t, v, tw);
+  inv_down<T, L, V, NP - 1>(sl, t, v, tw);
   T* __restrict__ da = d.phi + ((size_t)z * N + y0 + 2 * j) * N;
   T* __restrict__ db = da + N;
 #pragma unroll
@@ -512,14 +541,14 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
   }
 }
 
-template <typename T, int L, int NT, int PASS>
+template <typename T, int L, int V, int NT, int PASS>
 __device__ __forceinline__ void run_tile(const SolveDesc<T>& d, int tile, C2<T>* s,
                                          const C2<T>* __restrict__ tw) {
-  if constexpr (PASS == 0) tile_fwd_x<T, L, NT>(d, tile, s, tw);
-  else if constexpr (PASS == 1) tile_fwd_y<T, L, NT>(d, tile, s, tw);
-  else if constexpr (PASS == 2) tile_zpass<T, L, NT>(d, tile, s, tw);
-  else if constexpr (PASS == 3) tile_inv_y<T, L, NT>(d, tile, s, tw);
-  else tile_inv_x<T, L, NT>(d, tile, s, tw);
+  if constexpr (PASS == 0) tile_fwd_x<T, L, V, NT>(d, tile, s, tw);
+  else if constexpr (PASS == 1) tile_fwd_y<T, L, V, NT>(d, tile, s, tw);
+  else if constexpr (PASS == 2) tile_zpass<T, L, V, NT>(d, tile, s, tw);
+  else if constexpr (PASS == 3) tile_inv_y<T, L, V, NT>(d, tile, s, tw);
+  else tile_inv_x<T, L, V, NT>(d, tile, s, tw);
 }
 
 // Persistent pass over the solves of one grid size: work items are
@@ -528,11 +557,11 @@ __device__ __forceinline__ void run_tile(const SolveDesc<T>& d, int tile, C2<T>*
 // counter is never touched.  `reset` (may be null) is the counter of the
 // pass that ran before this one; it is cleared here for its next use, which
 // saves a launch per solve set.
-template <typename T, int PASS, int NT, int L>
+template <typename T, int PASS, int NT, int L, int V>
 __global__ void __launch_bounds__(NT)
     k_pass(const SolveDesc<T>* __restrict__ solves, int tiles_per_solve, int total,
            int* __restrict__ counter, int* __restrict__ reset, const C2<T>* __restrict__ tw) {
-  __shared__ C2<T> s[TC<T, L, NT, PASS>::LDS];
+  __shared__ C2<T> s[TC<T, L, V, NT, PASS>::LDS];
   __shared__ int item_sh;
   if (reset && blockIdx.x == 0 && threadIdx.x == 0) *reset = 0;
   int next = blockIdx.x;
@@ -542,7 +571,7 @@ __global__ void __launch_bounds__(NT)
     const bool more = (int)gridDim.x < total;
     if (more && threadIdx.x == 0) item_sh = (int)gridDim.x + atomicAdd(counter, 1);
     const int sidx = item / tiles_per_solve;
-    run_tile<T, L, NT, PASS>(solves[sidx], item - sidx * tiles_per_solve, s, tw);
+    run_tile<T, L, V, NT, PASS>(solves[sidx], item - sidx * tiles_per_solve, s, tw);
     if (!more) break;
     __syncthreads();  // LDS free for the next tile; item_sh written
     next = __builtin_amdgcn_readfirstlane(item_sh);
@@ -550,80 +579,79 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-template <typename T, int NT>
-static int tiles_for(int N, int pass) {
-  switch (N) {
-    case 8: return tiles_of<T, 16, NT>(pass);
-    case 16: return tiles_of<T, 32, NT>(pass);
-    case 32: return tiles_of<T, 64, NT>(pass);
-    case 64: return tiles_of<T, 128, NT>(pass);
-    case 128: return tiles_of<T, 256, NT>(pass);
-    default: return tiles_of<T, 512, NT>(pass);
-  }
-}
-
-template <typename T>
-static int tiles_nt(int nt, int N, int pass) {
-  return nt == 128 ? tiles_for<T, 128>(N, pass)
-       : nt == 256 ? tiles_for<T, 256>(N, pass)
-                   : tiles_for<T, 512>(N, pass);
-}
-
-template <typename T, int NT, int PASS>
-static bool fits_nt(int N) {
-  switch (N) {
-    case 8: return shape_fits<T, 16, NT, PASS>();
-    case 16: return shape_fits<T, 32, NT, PASS>();
-    case 32: return shape_fits<T, 64, NT, PASS>();
-    case 64: return shape_fits<T, 128, NT, PASS>();
-    case 128: return shape_fits<T, 256, NT, PASS>();
-    default: return shape_fits<T, 512, NT, PASS>();
-  }
-}
-
-// Whether a block size fits the LDS budget for a pass and grid size.
-template <typename T>
-static bool shape_ok(int nt, int N, int pass) {
-  auto f = [&](auto ntc) {
-    constexpr int NT = decltype(ntc)::value;
-    switch (pass) {
-      case 0: return fits_nt<T, NT, 0>(N);
-      case 1: return fits_nt<T, NT, 1>(N);
-      case 2: return fits_nt<T, NT, 2>(N);
-      case 3: return fits_nt<T, NT, 3>(N);
-      default: return fits_nt<T, NT, 4>(N);
+// Calls f(L, V) (as integral constants) for the line length of N^3 grids
+// and the schedule v (0 or a value the line length does not have: its
+// default schedule).
+template <typename T, typename Fn>
+static auto with_lv(int N, int v, Fn&& f) {
+  auto pick = [&](auto lc) {
+    constexpr int L = decltype(lc)::value;
+    if constexpr (kTwoV<T, L>) {
+      if (v == 16) return f(lc, std::integral_constant<int, 16>());
+      if (v == 32) return f(lc, std::integral_constant<int, 32>());
     }
+    return f(lc, std::integral_constant<int, kDefV<T, L>>());
   };
-  return nt == 128 ? f(std::integral_constant<int, 128>())
-       : nt == 256 ? f(std::integral_constant<int, 256>())
-       : nt == 512 ? f(std::integral_constant<int, 512>())
-                   : false;
+  switch (N) {
+    case 8: return pick(std::integral_constant<int, 16>());
+    case 16: return pick(std::integral_constant<int, 32>());
+    case 32: return pick(std::integral_constant<int, 64>());
+    case 64: return pick(std::integral_constant<int, 128>());
+    case 128: return pick(std::integral_constant<int, 256>());
+    default: return pick(std::integral_constant<int, 512>());
+  }
 }
 
-template <typename T, int PASS, int NT>
-static void launch_nt(const SolveDesc<T>* solves, int N, int tps, int total, int grid, int* counter,
-                      int* reset, const C2<T>* tw, hipStream_t st) {
-  const dim3 g(grid), b(NT);
-  switch (N) {
-    case 8: hipLaunchKernelGGL((k_pass<T, PASS, NT, 16>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
-    case 16: hipLaunchKernelGGL((k_pass<T, PASS, NT, 32>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
-    case 32: hipLaunchKernelGGL((k_pass<T, PASS, NT, 64>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
-    case 64: hipLaunchKernelGGL((k_pass<T, PASS, NT, 128>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
-    case 128: hipLaunchKernelGGL((k_pass<T, PASS, NT, 256>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
-    default: hipLaunchKernelGGL((k_pass<T, PASS, NT, 512>), g, b, 0, st, solves, tps, total, counter, reset, tw); break;
-  }
+// The same for the block size (128, 256 or 512).
+template <typename Fn>
+static auto with_nt(int nt, Fn&& f) {
+  if (nt == 128) return f(std::integral_constant<int, 128>());
+  if (nt == 256) return f(std::integral_constant<int, 256>());
+  return f(std::integral_constant<int, 512>());
+}
+
+template <typename T>
+static int tiles_nt(int nt, int v, int N, int pass) {
+  return with_nt(nt, [&](auto ntc) {
+    return with_lv<T>(N, v, [&](auto lc, auto vc) {
+      return tiles_of<T, decltype(lc)::value, decltype(vc)::value, decltype(ntc)::value>(pass);
+    });
+  });
+}
+
+// Whether a block size and schedule fit the LDS budget for a pass and grid
+// size.
+template <typename T>
+static bool shape_ok(int nt, int v, int N, int pass) {
+  if (nt != 128 && nt != 256 && nt != 512) return false;
+  return with_nt(nt, [&](auto ntc) {
+    return with_lv<T>(N, v, [&](auto lc, auto vc) {
+      constexpr int L = decltype(lc)::value, V = decltype(vc)::value, NT = decltype(ntc)::value;
+      switch (pass) {
+        case 0: return shape_fits<T, L, V, NT, 0>();
+        case 1: return shape_fits<T, L, V, NT, 1>();
+        case 2: return shape_fits<T, L, V, NT, 2>();
+        case 3: return shape_fits<T, L, V, NT, 3>();
+        default: return shape_fits<T, L, V, NT, 4>();
+      }
+    });
+  });
 }
 
 template <typename T, int PASS>
 static void launch_pass(const SolveDesc<T>* solves, int N, int nsolves, PassShape sh, int* counter,
                         int* reset, const C2<T>* tw, hipStream_t st) {
-  if (!shape_ok<T>(sh.nt, N, PASS)) sh.nt = 256;
-  const int tps = tiles_nt<T>(sh.nt, N, PASS);
+  if (!shape_ok<T>(sh.nt, sh.v, N, PASS)) sh = PassShape{256, sh.grid, 0};
+  const int tps = tiles_nt<T>(sh.nt, sh.v, N, PASS);
   const int total = tps * nsolves;
   const int grid = std::max(1, std::min(sh.grid <= 0 ? total : sh.grid, total));
-  if (sh.nt == 128) launch_nt<T, PASS, 128>(solves, N, tps, total, grid, counter, reset, tw, st);
-  else if (sh.nt == 256) launch_nt<T, PASS, 256>(solves, N, tps, total, grid, counter, reset, tw, st);
-  else launch_nt<T, PASS, 512>(solves, N, tps, total, grid, counter, reset, tw, st);
+  with_nt(sh.nt, [&](auto ntc) {
+    with_lv<T>(N, sh.v, [&](auto lc, auto vc) {
+      constexpr int L = decltype(lc)::value, V = decltype(vc)::value, NT = decltype(ntc)::value;
+      hipLaunchKernelGGL((k_pass<T, PASS, NT, L, V>), dim3(grid), dim3(NT), 0, st, solves, tps, total,
+                         counter, reset, tw);
+    });
+  });
 }
 
 template <typename T>
@@ -643,16 +671,34 @@ __global__ void k_zero_int(int* p, int n) {
 }
 
 // ---------------------------------------------------------- the autotuner --
-// Candidate shapes per (precision, grid size, solve count, pass): block size
-// 128, 256 or 512 threads (512 only in FP32, where the longest lines still
-// fit 64 KB of LDS) and a persistent grid of 2, 4 or 8 blocks per compute
-// unit, or one block per tile.  Each candidate runs the pass on the plan's
-// own buffers (zeroed first); the fastest of 5 timed repetitions wins.
-// Results are cached for the life of the process.
+// Candidate shapes per (precision, grid size, solve count, pass): the line
+// schedule (in FP32 for lines of 128 and more: 16 or 32 values per thread,
+// that is radix 16 then L/16 (then 2), or radix 32 then L/32), block size
+// 128, 256 or 512 threads (where the tile fits the LDS budget) and a
+// persistent grid of 2, 4 or 8 blocks per compute unit, or one block per
+// tile.  Each candidate runs the pass on the plan's own buffers (zeroed
+// first); the fastest of 5 timed repetitions wins.  Results are cached for
+// the life of the process.
 struct TuneKey {
   int esz, N, count;
-  bool operator==(const TuneKey& o) const { return esz == o.esz && N == o.N && count == o.count; }
+  int pin = 0;  // the pinned line schedule when the key was tuned (0: none)
+  bool operator==(const TuneKey& o) const {
+    return esz == o.esz && N == o.N && count == o.count && pin == o.pin;
+  }
 };
+
+// Line schedule pinned for plans tuned from now on (0: the tuner times
+// every schedule a line length has).
+static std::atomic<int> g_pin_v{0};
+
+sbx_status set_fft_schedule(int v) {
+  if (v != 0 && v != 16 && v != 32) {
+    set_error("values per thread must be 0 (tuned), 16 or 32");
+    return SBX_EINVAL;
+  }
+  g_pin_v.store(v);
+  return SBX_OK;
+}
 
 static std::mutex g_tune_mu;
 static std::vector<std::pair<TuneKey, std::array<PassShape, kPasses>>> g_tune;
@@ -676,7 +722,11 @@ std::string tuning_report() {
       out += std::string(e.first.esz == 8 ? "fp64" : "fp32") + " N=" + std::to_string(e.first.N) +
              " x" + std::to_string(e.first.count) + " " + names[p] + " nt=" +
              std::to_string(e.second[p].nt) + " grid=" +
-             (e.second[p].grid <= 0 ? std::string("tiles") : std::to_string(e.second[p].grid)) + "\n";
+             (e.second[p].grid <= 0 ? std::string("tiles") : std::to_string(e.second[p].grid)) +
+             " v=" +
+             std::to_string(e.first.esz == 8 ? eff_v<double>(2 * e.first.N, e.second[p].v)
+                                             : eff_v<float>(2 * e.first.N, e.second[p].v)) +
+             "\n";
   return out;
 }
 
@@ -693,7 +743,7 @@ bool tuning_cached(int esz, std::vector<int> mix) {
     size_t j = i;
     while (j < mix.size() && mix[j] == mix[i]) ++j;
     std::array<PassShape, kPasses> a;
-    if (!tune_lookup(TuneKey{esz, mix[i], (int)(j - i)}, a)) return false;
+    if (!tune_lookup(TuneKey{esz, mix[i], (int)(j - i), g_pin_v.load()}, a)) return false;
     i = j;
   }
   return true;
@@ -701,11 +751,25 @@ bool tuning_cached(int esz, std::vector<int> mix) {
 
 template <typename T>
 static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* host, int N, int count,
-                             int* counter, const C2<T>* tw, hipStream_t st,
-                             std::array<PassShape, kPasses>& out) {
+                             int* counter, hipStream_t st, std::array<PassShape, kPasses>& out) {
   const int cus = device_cus();
   const int nts[3] = {128, 256, 512};
   const int bpcs[4] = {2, 4, 8, 0};  // 0: one block per tile
+  // the schedules of this line length (one, or both 16 and 32)
+  const int L = 2 * N;
+  std::vector<int> vs{eff_v<T>(L, 0)};
+  if (eff_v<T>(L, 16) != eff_v<T>(L, 32)) {
+    const int pin = g_pin_v.load();
+    vs = pin ? std::vector<int>{pin} : std::vector<int>{16, 32};
+  }
+  const C2<T>* tws[2] = {nullptr, nullptr};
+  for (size_t i = 0; i < vs.size(); ++i) {
+    tws[i] = twiddles<T>(L, vs[i], st);
+    if (!tws[i]) {
+      set_error("twiddle table allocation failed");
+      return SBX_ENOMEM;
+    }
+  }
   for (int i = 0; i < count; ++i) {
     SBX_HIP(hipMemsetAsync((void*)host[i].rho, 0, sizeof(T) * (size_t)N * N * N, st));
     if (host[i].rho2)
@@ -719,25 +783,27 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
   SBX_HIP(hipEventCreate(&e1));
   for (int pass = 0; pass < kPasses; ++pass) {
     float best = 1e30f;
-    PassShape pick{256, 0};
-    for (int nt : nts) {
-      if (!shape_ok<T>(nt, N, pass)) continue;
-      for (int bpc : bpcs) {
-        const PassShape sh{nt, bpc == 0 ? 0 : cus * bpc};
-        float ms_min = 1e30f;
-        for (int rep = 0; rep < 7; ++rep) {
-          hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, 1);
-          SBX_HIP(hipEventRecord(e0, st));
-          launch_any<T>(pass, d_solves, N, count, sh, counter, nullptr, tw, st);
-          SBX_HIP(hipEventRecord(e1, st));
-          SBX_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          SBX_HIP(hipEventElapsedTime(&ms, e0, e1));
-          if (rep >= 2) ms_min = std::min(ms_min, ms);
-        }
-        if (ms_min < best) {
-          best = ms_min;
-          pick = sh;
+    PassShape pick{256, 0, vs[0]};
+    for (size_t vi = 0; vi < vs.size(); ++vi) {
+      for (int nt : nts) {
+        if (!shape_ok<T>(nt, vs[vi], N, pass)) continue;
+        for (int bpc : bpcs) {
+          const PassShape sh{nt, bpc == 0 ? 0 : cus * bpc, vs[vi]};
+          float ms_min = 1e30f;
+          for (int rep = 0; rep < 7; ++rep) {
+            hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, 1);
+            SBX_HIP(hipEventRecord(e0, st));
+            launch_any<T>(pass, d_solves, N, count, sh, counter, nullptr, tws[vi], st);
+            SBX_HIP(hipEventRecord(e1, st));
+            SBX_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            SBX_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep >= 2) ms_min = std::min(ms_min, ms);
+          }
+          if (ms_min < best) {
+            best = ms_min;
+            pick = sh;
+          }
         }
       }
     }
@@ -786,23 +852,37 @@ sbx_status plan_create(SolvePlan<T>& p, const SolveDesc<T>* descs, int n, hipStr
     g.N = p.host[i].N;
     i = j;
   }
+  if (p.ngroups > 1) {
+    bool ok = hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) == hipSuccess;
+    for (int gi = 1; ok && gi < p.ngroups; ++gi)
+      ok = hipStreamCreateWithFlags(&p.side[gi], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&p.join[gi], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      plan_destroy(p);
+      set_error("stream or event creation failed (solve plan)");
+      return SBX_EDEVICE;
+    }
+  }
   for (int gi = 0; gi < p.ngroups; ++gi) {
     SolveGroup& g = p.groups[gi];
-    const C2<T>* tw = twiddles<T>(2 * g.N, st);
-    if (!tw) {
-      set_error("twiddle table allocation failed");
-      return SBX_ENOMEM;
-    }
-    g.tw = (const void*)tw;
     std::array<PassShape, kPasses> a;
-    const TuneKey key{(int)sizeof(T), g.N, g.count};
+    const TuneKey key{(int)sizeof(T), g.N, g.count, g_pin_v.load()};
     if (!tune_lookup(key, a)) {
       SBX_TRY(tune_group<T>(p.d_solves + g.first, p.host.data() + g.first, g.N, g.count,
-                            p.d_counter, tw, st, a));
+                            p.d_counter, st, a));
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune.push_back({key, a});
     }
-    for (int q = 0; q < kPasses; ++q) g.shape[q] = a[q];
+    for (int q = 0; q < kPasses; ++q) {
+      g.shape[q] = a[q];
+      const C2<T>* tw = twiddles<T>(2 * g.N, a[q].v, st);
+      if (!tw) {
+        set_error("twiddle table allocation failed");
+        return SBX_ENOMEM;
+      }
+      g.tw[q] = (const void*)tw;
+    }
   }
   // work counters start at zero; every pass then clears its predecessor's
   SBX_HIP(hipMemsetAsync(p.d_counter, 0, sizeof(int) * kPasses * kMaxGroups, st));
@@ -815,7 +895,8 @@ sbx_status plan_run_pass(const SolvePlan<T>& p, int q, int group, hipStream_t st
   const SolveGroup& g = p.groups[group];
   launch_any<T>(q, p.d_solves + g.first, g.N, g.count, g.shape[q],
                 p.d_counter + q * kMaxGroups + group,
-                p.d_counter + ((q + kPasses - 1) % kPasses) * kMaxGroups + group, (const C2<T>*)g.tw, st);
+                p.d_counter + ((q + kPasses - 1) % kPasses) * kMaxGroups + group, (const C2<T>*)g.tw[q],
+                st);
   return SBX_OK;
 }
 
@@ -825,9 +906,23 @@ sbx_status plan_run(const SolvePlan<T>& p, hipStream_t st, Recorder* rec) {
   Recorder none;
   Recorder& r = rec ? *rec : none;
   static const int marks[kPasses] = {PH_FWD_X, PH_FWD_Y, PH_ZPASS, PH_INV_Y, PH_INV_X};
-  for (int q = 0; q < kPasses; ++q) {
-    for (int gi = 0; gi < p.ngroups; ++gi) SBX_TRY(plan_run_pass<T>(p, q, gi, st));
-    r.mark(marks[q], st);
+  if (p.ngroups == 1) {
+    for (int q = 0; q < kPasses; ++q) {
+      SBX_TRY(plan_run_pass<T>(p, q, 0, st));
+      r.mark(marks[q], st);
+    }
+  } else {
+    // independent size groups: group 0 on the caller's stream, the others
+    // on their own streams between a fork and a join
+    SBX_HIP(hipEventRecord(p.fork, st));
+    for (int gi = 1; gi < p.ngroups; ++gi) SBX_HIP(hipStreamWaitEvent(p.side[gi], p.fork, 0));
+    for (int gi = 0; gi < p.ngroups; ++gi)
+      for (int q = 0; q < kPasses; ++q) SBX_TRY(plan_run_pass<T>(p, q, gi, gi == 0 ? st : p.side[gi]));
+    for (int gi = 1; gi < p.ngroups; ++gi) {
+      SBX_HIP(hipEventRecord(p.join[gi], p.side[gi]));
+      SBX_HIP(hipStreamWaitEvent(st, p.join[gi], 0));
+    }
+    for (int q = 0; q < kPasses; ++q) r.mark(marks[q], st);
   }
   SBX_HIP(hipGetLastError());
   return SBX_OK;
@@ -835,27 +930,31 @@ sbx_status plan_run(const SolvePlan<T>& p, hipStream_t st, Recorder* rec) {
 
 template <typename T>
 sbx_status prepare_twiddles(int N, hipStream_t st) {
-  if (!twiddles<T>(2 * N, st)) {
-    set_error("twiddle table allocation failed");
-    return SBX_ENOMEM;
-  }
+  for (int v : {16, 32})
+    if (!twiddles<T>(2 * N, v, st)) {
+      set_error("twiddle table allocation failed");
+      return SBX_ENOMEM;
+    }
   return SBX_OK;
 }
 
 template <typename T>
 sbx_status run_solves_noalloc(const SolveDesc<T>* d_solves, int nsolves, int N, int* d_counter,
                               hipStream_t st) {
-  const C2<T>* tw = twiddles<T>(2 * N, st, false);
-  if (!tw) {
-    set_error("no twiddle table for this grid size on this device (create a plan first)");
-    return SBX_ESTATE;
-  }
   std::array<PassShape, kPasses> a;
-  if (!tune_lookup(TuneKey{(int)sizeof(T), N, nsolves}, a))
-    for (auto& sh : a) sh = PassShape{256, 0};
+  if (!tune_lookup(TuneKey{(int)sizeof(T), N, nsolves, g_pin_v.load()}, a))
+    for (auto& sh : a) sh = PassShape{256, 0, 0};
+  const C2<T>* tw[kPasses];
+  for (int q = 0; q < kPasses; ++q) {
+    tw[q] = twiddles<T>(2 * N, a[q].v, st, false);
+    if (!tw[q]) {
+      set_error("no twiddle table for this grid size on this device (create a plan first)");
+      return SBX_ESTATE;
+    }
+  }
   for (int q = 0; q < kPasses; ++q)
     launch_any<T>(q, d_solves, N, nsolves, a[q], d_counter + q, d_counter + (q + kPasses - 1) % kPasses,
-                  tw, st);
+                  tw[q], st);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }
@@ -869,6 +968,11 @@ template <typename T>
 void plan_destroy(SolvePlan<T>& p) {
   if (p.d_solves) (void)hipFree(p.d_solves);
   if (p.d_counter) (void)hipFree(p.d_counter);
+  for (int gi = 0; gi < kMaxGroups; ++gi) {
+    if (p.side[gi]) (void)hipStreamDestroy(p.side[gi]);
+    if (p.join[gi]) (void)hipEventDestroy(p.join[gi]);
+  }
+  if (p.fork) (void)hipEventDestroy(p.fork);
   p = SolvePlan<T>();
 }
 
@@ -906,7 +1010,7 @@ __global__ void k_green_fill(C2<double>* F, int N, double l, double lz, double h
 // staged in LDS, each transformed by TL threads of one wave.
 template <int L>
 struct GreenTile {
-  static constexpr int TL = Line<double, L>::TL, P = L + L / 16 + 1, NT = 256;
+  static constexpr int TL = Line<double, L, kDefV<double, L>>::TL, P = L + L / 16 + 1, NT = 256;
   static constexpr int fit(int w) {
     return (w > 1 && w * P * (int)sizeof(C2<double>) > kLdsCap) ? fit(w / 2) : w;
   }
@@ -930,7 +1034,7 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   if ((int)threadIdx.x < W * TL)
-    line_fwd_lds<double, L>(s + (threadIdx.x / TL) * P, threadIdx.x % TL, tw);
+    line_fwd_lds<double, L, kDefV<double, L>>(s + (threadIdx.x / TL) * P, threadIdx.x % TL, tw);
   __syncthreads();
   for (int i = threadIdx.x; i < W * L; i += NT) {
     const int e = AXIS == 0 ? i % L : i / W, w = AXIS == 0 ? i / L : i % W;
@@ -967,7 +1071,7 @@ __global__ void k_green_fold(const C2<double>* F, T* H, int N, double scale) {
 template <int L>
 static sbx_status green_fft(C2<double>* F, hipStream_t st) {
   using K = GreenTile<L>;
-  const C2<double>* tw = twiddles<double>(L, st);
+  const C2<double>* tw = twiddles<double>(L, 0, st);
   if (!tw) {
     set_error("twiddle table allocation failed");
     return SBX_ENOMEM;

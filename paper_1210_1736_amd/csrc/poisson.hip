@@ -1,5 +1,8 @@
 // C ABI of the standalone isolated Poisson solves (Eqs. 1-5).
+#include <algorithm>
+#include <cstring>
 #include <mutex>
+#include <string>
 
 #include "ctx.h"
 
@@ -341,5 +344,17 @@ sbx_status sbx_poisson_green(sbx_poisson* p, double* out, double* rel_imag) {
 }
 
 int64_t sbx_poisson_bytes(sbx_poisson* p) { return p ? p->bytes : 0; }
+
+sbx_status sbx_set_fft_schedule(int32_t v) { return set_fft_schedule((int)v); }
+
+int64_t sbx_fft_tuning_report(char* out, int64_t cap) {
+  const std::string r = tuning_report();
+  if (out && cap > 0) {
+    const size_t n = std::min((size_t)(cap - 1), r.size());
+    std::memcpy(out, r.data(), n);
+    out[n] = 0;
+  }
+  return (int64_t)r.size();
+}
 
 }  // extern "C"

@@ -126,6 +126,8 @@ def _load():
         "sbx_poisson_solve_noalloc": (S, [P, I32, P, P]),
         "sbx_poisson_green": (S, [P, P, dp]),
         "sbx_poisson_bytes": (I64, [P]),
+        "sbx_set_fft_schedule": (S, [I32]),
+        "sbx_fft_tuning_report": (I64, [C.c_char_p, I64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -181,6 +183,21 @@ def sbx_validate_hierarchies(hs) -> int:
 
 def sbx_q_crit(n, R_core, R_out, R_sys) -> float:
     return _lib.sbx_q_crit(n, R_core, R_out, R_sys)
+
+
+def sbx_set_fft_schedule(values_per_thread):
+    """Pin the FFT line schedule (16 or 32 values per thread) for plans made
+    from now on; 0 lets the launch-shape tuner choose."""
+    _check(_lib.sbx_set_fft_schedule(int(values_per_thread)))
+
+
+def sbx_fft_tuning_report() -> str:
+    """The launch shapes (block size, persistent grid, line schedule) the
+    tuner has chosen so far, one line per precision, size, count and pass."""
+    n = _lib.sbx_fft_tuning_report(None, 0)
+    buf = C.create_string_buffer(int(n) + 1)
+    _lib.sbx_fft_tuning_report(buf, int(n) + 1)
+    return buf.value.decode()
 
 
 class Context:

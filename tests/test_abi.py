@@ -55,3 +55,15 @@ def test_library_agrees_with_oracle_on_qcrit_table():
     from oracle import pm_oracle as O
     for N in (64, 128, 256):
         assert sbx.sbx_q_crit(N, 3.5, 28.0, 105.0) == O.q_crit(N, 3.5, 28.0, 105.0)
+
+
+def test_fft_schedule_pin_host_only():
+    """sbx_set_fft_schedule takes 0, 16 or 32 and rejects anything else (host
+    state only: no device call)."""
+    from paper_1210_1736_amd import sbx
+    for v in (16, 32, 0):
+        sbx.sbx_set_fft_schedule(v)
+    for bad in (-1, 8, 24, 64):
+        with pytest.raises(sbx.SbxError):
+            sbx.sbx_set_fft_schedule(bad)
+    sbx.sbx_set_fft_schedule(0)

@@ -120,6 +120,56 @@ def test_poisson_solve_matches_oracle(sbx, torch, N, q, prec):
         assert np.max(np.abs(g - ref)) <= tol * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("v", [16, 32])
+@pytest.mark.parametrize("N,q", [(64, 0.5), (128, 0.25)])
+def test_fft_schedules_match_oracle(sbx, torch, v, N, q):
+    """Each FFT line schedule pinned in turn (16 or 32 values per thread; FP32
+    lines of 128 and 256 points have both, and the tuner picks per pass)
+    against the oracle's FFT convolution (Eqs. 3-5), FP32 bar 3e-6 of max|Phi|."""
+    rng = _rng(1000 + N + v)
+    R = 2.0
+    Ms = []
+    for b in range(2):
+        M = np.zeros((N, N, N))
+        cells = rng.integers(0, N, size=(N * N // 4, 3))
+        np.add.at(M, tuple(cells.T), rng.uniform(0.1, 1.0, cells.shape[0]))
+        Ms.append(T.rounded(M, sbx.SBX_FP32))
+    sbx.sbx_set_fft_schedule(v)
+    try:
+        got = _solve_gpu(sbx, torch, N, R, q, Ms, sbx.SBX_FP32, G=0.7)
+    finally:
+        sbx.sbx_set_fft_schedule(0)
+    Hh, _ = O.green_hat(O.Level(N, R, q))
+    for M, g in zip(Ms, got):
+        ref = O.solve_fft(M, Hh, G=0.7)
+        assert np.max(np.abs(g - ref)) <= 3e-6 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("v", [16, 32])
+def test_fft_schedules_max_size_sampled(sbx, torch, v):
+    """N = 256 (512-point lines) with each schedule pinned: sampled cells
+    against the direct sum of Eq. 1 (FP32 bar 3e-6)."""
+    N, R, q = 256, 10.0, 1.0
+    L = O.Level(N, R, q)
+    rng = _rng(2560 + v)
+    src = rng.integers(0, N, size=(2000, 3))
+    mass = T.rounded(rng.uniform(0.1, 1.0, 2000), sbx.SBX_FP32)
+    M = np.zeros((N, N, N))
+    np.add.at(M, tuple(src.T), mass)
+    sbx.sbx_set_fft_schedule(v)
+    try:
+        g = _solve_gpu(sbx, torch, N, R, q, [M], sbx.SBX_FP32)[0]
+    finally:
+        sbx.sbx_set_fft_schedule(0)
+    H = O.green_table(L)
+    probes = rng.integers(0, N, size=(200, 3))
+    nz = np.argwhere(M != 0)
+    w = M[tuple(nz.T)]
+    ref = np.array([np.sum(w * H[np.abs(nz[:, 0] - a), np.abs(nz[:, 1] - b), np.abs(nz[:, 2] - c)])
+                    for a, b, c in probes])
+    assert np.max(np.abs(g[tuple(probes.T)] - ref)) <= 3e-6 * np.max(ref)
+
+
 def test_poisson_solve_equals_direct_sum(sbx, torch):
     N, R, q = 16, 1.5, 0.5
     rng = _rng(99)
