@@ -11,6 +11,17 @@
 
 namespace sbx {
 
+// Global-memory views of pointers held in device records: accesses through
+// them compile to global_* instructions instead of flat_* ones (which also
+// count against the LDS/scalar wait counter, so every LDS wait would wait
+// for them too).
+template <typename T>
+using gp = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gp<T> glb(T* p) {
+  return (gp<T>)p;
+}
+
 // ---------------------------------------------------------------- errors ---
 void set_error(const std::string& msg);
 

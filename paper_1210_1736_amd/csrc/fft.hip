@@ -326,7 +326,22 @@ __host__ __device__ constexpr bool shape_fits() {
   return TC<T, L, V, NT, PASS>::fits;
 }
 
+// Complex values through global-memory views (member-wise: the struct's
+// assignment works on generic pointers only).
+template <typename T>
+__device__ __forceinline__ C2<T> gld(gp<const C2<T>> p) {
+  return C2<T>{p->re, p->im};
+}
+template <typename T>
+__device__ __forceinline__ void gst(gp<C2<T>> p, const C2<T>& v) {
+  p->re = v.re;
+  p->im = v.im;
+}
+
 // ------------------------------------------------------------ the passes ---
+// Each pass reads its input lines once: those loads are non-temporal, so
+// they do not displace the lines the pass is writing (the next pass's
+// input) from the caches.
 // fwd_x: tile = W consecutive y at one z; real rows x < N taken two at a
 // time as the real and imaginary parts of one complex line (straight into
 // registers); after the transform the two spectra are separated by
@@ -344,16 +359,16 @@ __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T
     const int j = u * K::WT + tid / TL;
     if (j < WL) {
       const size_t row = ((size_t)z * N + y0 + 2 * j) * N;
-      const T* __restrict__ a = d.rho + row;
-      const T* __restrict__ b = a + N;
+      const gp<const T> __restrict__ a = glb(d.rho + row);
+      const gp<const T> __restrict__ b = a + N;
       constexpr int VPT = Line<T, L, V>::VPT;
       C2<T> v[VPT];
 #pragma unroll
       for (int r = 0; r < VPT; ++r)
-        v[r] = r < VPT / 2 ? C2<T>{a[t + r * TL], b[t + r * TL]} : C2<T>{(T)0, (T)0};
+        v[r] = r < VPT / 2 ? C2<T>{__builtin_nontemporal_load(&a[t + r * TL]), __builtin_nontemporal_load(&b[t + r * TL])} : C2<T>{(T)0, (T)0};
       if (d.rho2) {  // summed grids: the second source is added on the way in
-        const T* __restrict__ a2 = d.rho2 + row;
-        const T* __restrict__ b2 = a2 + N;
+        const gp<const T> __restrict__ a2 = glb(d.rho2 + row);
+        const gp<const T> __restrict__ b2 = a2 + N;
 #pragma unroll
         for (int r = 0; r < VPT / 2; ++r) {
           v[r].re += a2[t + r * TL];
@@ -364,14 +379,14 @@ __device__ __forceinline__ void tile_fwd_x(const SolveDesc<T>& d, int tile, C2<T
     }
   }
   __syncthreads();
-  C2<T>* __restrict__ dst = d.X + (size_t)z * N + y0;
+  const gp<C2<T>> __restrict__ dst = glb(d.X + (size_t)z * N + y0);
   const T h = (T)0.5;
   for (int i = tid; i < W * (N + 1); i += NT) {
     const int e = i / W, w = i - e * W;
     const C2<T>* sl = s + (w >> 1) * P;
     const C2<T> Z = sl[pad(e)], R = sl[pad(e == 0 ? 0 : L - e)];
-    dst[(size_t)e * N * N + w] = (w & 1) ? C2<T>{(Z.im + R.im) * h, (R.re - Z.re) * h}
-                                         : C2<T>{(Z.re + R.re) * h, (Z.im - R.im) * h};
+    gst(dst + (size_t)e * N * N + w, (w & 1) ? C2<T>{(Z.im + R.im) * h, (R.re - Z.re) * h}
+                                            : C2<T>{(Z.re + R.re) * h, (Z.im - R.im) * h});
   }
 }
 
@@ -388,19 +403,19 @@ __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T
   for (int u = 0; u < K::ROUNDS; ++u) {
     const int w = u * K::WT + tid / TL;
     if (w < W) {
-      const C2<T>* __restrict__ src = d.X + ((size_t)kx * N + z0 + w) * N;
+      const gp<const C2<T>> __restrict__ src = glb(d.X + ((size_t)kx * N + z0 + w) * N);
       constexpr int VPT = Line<T, L, V>::VPT;
       C2<T> v[VPT];
 #pragma unroll
-      for (int r = 0; r < VPT; ++r) v[r] = r < VPT / 2 ? src[t + r * TL] : C2<T>{(T)0, (T)0};
+      for (int r = 0; r < VPT; ++r) v[r] = r < VPT / 2 ? C2<T>{__builtin_nontemporal_load(&src[t + r * TL].re), __builtin_nontemporal_load(&src[t + r * TL].im)} : C2<T>{(T)0, (T)0};
       fwd_from<T, L, V, 0, true>(s + w * P, t, v, tw);
     }
   }
   __syncthreads();
-  C2<T>* __restrict__ dst = d.C + (size_t)kx * L * N + z0;
+  const gp<C2<T>> __restrict__ dst = glb(d.C + (size_t)kx * L * N + z0);
   for (int i = tid; i < W * L; i += NT) {
     const int e = i / W, w = i - e * W;
-    dst[(size_t)e * N + w] = s[w * P + pad(e)];
+    gst(dst + (size_t)e * N + w, s[w * P + pad(e)]);
   }
 }
 
@@ -418,11 +433,11 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
   const int kx = tile / (L / W), ky0 = (tile % (L / W)) * W;
   if (w < W) {
     const int ky = ky0 + w;
-    const C2<T>* __restrict__ g = d.C + ((size_t)kx * L + ky) * N;
+    const gp<const C2<T>> __restrict__ g = glb(d.C + ((size_t)kx * L + ky) * N);
     C2<T>* sl = s + w * P;
     C2<T> v[F::VPT];
 #pragma unroll
-    for (int r = 0; r < F::VPT; ++r) v[r] = r < F::VPT / 2 ? g[t + r * TL] : C2<T>{(T)0, (T)0};
+    for (int r = 0; r < F::VPT; ++r) v[r] = r < F::VPT / 2 ? C2<T>{__builtin_nontemporal_load(&g[t + r * TL].re), __builtin_nontemporal_load(&g[t + r * TL].im)} : C2<T>{(T)0, (T)0};
     if constexpr (NP > 1) {
       fwd_bfly<T, L, V, 0>(v, t, tw);
       scatter_out<T, L, V, 0>(sl, t, v);
@@ -439,7 +454,7 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
     }
     fwd_bfly<T, L, V, NP - 1>(v, t, tw);
     // Hhat at frequencies (kx, ky, e), e = j + r L/R of the last pass
-    const T* __restrict__ H = d.H + ((size_t)kx * (N + 1) + (ky <= N ? ky : L - ky)) * (N + 1);
+    const gp<const T> __restrict__ H = glb(d.H + ((size_t)kx * (N + 1) + (ky <= N ? ky : L - ky)) * (N + 1));
 #pragma unroll
     for (int b = 0; b < F::VPT / RL; ++b)
 #pragma unroll
@@ -453,10 +468,10 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
     for (int r = 0; r < F::VPT / 2; ++r) sl[pad(t + r * TL)] = v[r];
   }
   __syncthreads();
-  C2<T>* __restrict__ dst = d.D + (size_t)kx * N * L + ky0;
+  const gp<C2<T>> __restrict__ dst = glb(d.D + (size_t)kx * N * L + ky0);
   for (int i = tid; i < W * N; i += NT) {
     const int z = i / W, ww = i - z * W;
-    dst[(size_t)z * L + ww] = s[ww * P + pad(z)];
+    gst(dst + (size_t)z * L + ww, s[ww * P + pad(z)]);
   }
 }
 
@@ -477,14 +492,14 @@ __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T
   for (int u = 0; u < K::ROUNDS; ++u) {
     const int w = u * K::WT + tid / TL;
     if (w < W && kx0 + w <= N) {
-      const C2<T>* __restrict__ src = d.D + ((size_t)(kx0 + w) * N + z) * L;
+      const gp<const C2<T>> __restrict__ src = glb(d.D + ((size_t)(kx0 + w) * N + z) * L);
       C2<T>* sl = s + w * P;
       C2<T> v[F::VPT];
       // inputs of the first inverse pass: natural positions of the last pass
 #pragma unroll
       for (int b = 0; b < F::VPT / RL; ++b)
 #pragma unroll
-        for (int r = 0; r < RL; ++r) v[b * RL + r] = src[t + b * TL + r * NBL];
+        for (int r = 0; r < RL; ++r) v[b * RL + r] = C2<T>{__builtin_nontemporal_load(&src[t + b * TL + r * NBL].re), __builtin_nontemporal_load(&src[t + b * TL + r * NBL].im)};
       inv_down<T, L, V, NP - 1>(sl, t, v, tw);
       wave_sync();
 #pragma unroll
@@ -492,10 +507,10 @@ __device__ __forceinline__ void tile_inv_y(const SolveDesc<T>& d, int tile, C2<T
     }
   }
   __syncthreads();
-  C2<T>* __restrict__ dst = d.X + (size_t)z * N * (N + kEPad) + kx0;
+  const gp<C2<T>> __restrict__ dst = glb(d.X + (size_t)z * N * (N + kEPad) + kx0);
   for (int i = tid; i < W * N; i += NT) {
     const int y = i / W, w = i - y * W;
-    if (kx0 + w <= N) dst[(size_t)y * (N + kEPad) + w] = s[w * P + pad(y)];
+    if (kx0 + w <= N) gst(dst + (size_t)y * (N + kEPad) + w, s[w * P + pad(y)]);
   }
 }
 
@@ -514,8 +529,8 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
   const int tid = threadIdx.x, t = tid % TL, j = tid / TL;
   const int z = tile / (N / (2 * W)), y0 = (tile % (N / (2 * W))) * 2 * W;
   if (j >= W) return;
-  const C2<T>* __restrict__ A = d.X + ((size_t)z * N + y0 + 2 * j) * (N + kEPad);
-  const C2<T>* __restrict__ B = A + (N + kEPad);
+  const gp<const C2<T>> __restrict__ A = glb(d.X + ((size_t)z * N + y0 + 2 * j) * (N + kEPad));
+  const gp<const C2<T>> __restrict__ B = A + (N + kEPad);
   C2<T>* sl = s + j * P;
   C2<T> v[F::VPT];
 #pragma unroll
@@ -524,16 +539,16 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
     for (int r = 0; r < RL; ++r) {
       const int e = t + b * TL + r * NBL;
       if (e <= N) {
-        const C2<T> a = A[e], q = B[e];
+        const C2<T> a = gld(A + e), q = gld(B + e);
         v[b * RL + r] = C2<T>{a.re - q.im, a.im + q.re};
       } else {
-        const C2<T> a = A[L - e], q = B[L - e];
+        const C2<T> a = gld(A + (L - e)), q = gld(B + (L - e));
         v[b * RL + r] = C2<T>{a.re + q.im, q.re - a.im};
       }
     }
   inv_down<T, L, V, NP - 1>(sl, t, v, tw);
-  T* __restrict__ da = d.phi + ((size_t)z * N + y0 + 2 * j) * N;
-  T* __restrict__ db = da + N;
+  const gp<T> __restrict__ da = glb(d.phi + ((size_t)z * N + y0 + 2 * j) * N);
+  const gp<T> __restrict__ db = da + N;
 #pragma unroll
   for (int r = 0; r < F::VPT / 2; ++r) {
     da[t + r * TL] = v[r].re;

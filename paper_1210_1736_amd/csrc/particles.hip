@@ -12,16 +12,6 @@
 
 namespace sbx {
 
-// Global-memory views of pointers held in device records: accesses through
-// them compile to global_* instructions instead of flat_* ones (which also
-// count against the LDS/scalar wait counter).
-template <typename T>
-using gp = __attribute__((address_space(1))) T*;
-template <typename T>
-__device__ __forceinline__ gp<T> glb(T* p) {
-  return (gp<T>)p;
-}
-
 template <typename T>
 __device__ __forceinline__ void atomic_add_g(gp<T> p, T v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -910,14 +900,17 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
   }
   const int64_t stride = (int64_t)nb * blockDim.x;
-  // the next particle's flag and position are loaded one iteration ahead
+  // The particle streams are read and written once per pass: their loads
+  // and stores are non-temporal, so they do not displace the field rows
+  // that neighbouring particles gather from the caches.
+  // The next particle's flag and position are loaded one iteration ahead.
   int64_t inext = (int64_t)lb * blockDim.x + threadIdx.x;
-  uint8_t lnext = inext < p.n ? LOST[inext] : (uint8_t)1;
+  uint8_t lnext = inext < p.n ? __builtin_nontemporal_load(&LOST[inext]) : (uint8_t)1;
   T xn = (T)0, yn = (T)0, zn = (T)0;
   if (inext < p.n) {
-    xn = X0[inext];
-    yn = X1[inext];
-    zn = X2[inext];
+    xn = __builtin_nontemporal_load(&X0[inext]);
+    yn = __builtin_nontemporal_load(&X1[inext]);
+    zn = __builtin_nontemporal_load(&X2[inext]);
   }
   for (int64_t i0 = (int64_t)lb * blockDim.x; i0 < p.n; i0 += stride) {
     const int64_t i = i0 + threadIdx.x;
@@ -926,10 +919,10 @@ __global__ void __launch_bounds__(256)
     const T xs = xn, ys = yn, zs = zn;
     inext = i + stride;
     if (inext < p.n) {
-      lnext = LOST[inext];
-      xn = X0[inext];
-      yn = X1[inext];
-      zn = X2[inext];
+      lnext = __builtin_nontemporal_load(&LOST[inext]);
+      xn = __builtin_nontemporal_load(&X0[inext]);
+      yn = __builtin_nontemporal_load(&X1[inext]);
+      zn = __builtin_nontemporal_load(&X2[inext]);
     }
     int dc = -1;                        // component for the diagnostic sums
     double dv[DIAG ? kDiagComp : 1];    // this lane's contribution
@@ -949,11 +942,11 @@ __global__ void __launch_bounds__(256)
       T v0 = (T)0, v1 = (T)0, v2 = (T)0, mi = (T)0;
       int gi = 0, ci = 0;
       if constexpr (MOVE || DIAG) {
-        v0 = V0[i];
-        v1 = V1[i];
-        v2 = V2[i];
-        gi = GAL[i];
-        mi = Mv[i];
+        v0 = __builtin_nontemporal_load(&V0[i]);
+        v1 = __builtin_nontemporal_load(&V1[i]);
+        v2 = __builtin_nontemporal_load(&V2[i]);
+        gi = __builtin_nontemporal_load(&GAL[i]);
+        mi = __builtin_nontemporal_load(&Mv[i]);
       }
       if constexpr (DIAG) ci = COMP[i];
       T a[3] = {(T)0, (T)0, (T)0};
@@ -996,12 +989,12 @@ __global__ void __launch_bounds__(256)
         const T vy = v1 + dt * a[1];
         const T vz = v2 + dt * a[2];
         const T nx = xs + dt * vx, ny = ys + dt * vy, nz = zs + dt * vz;
-        V0[i] = vx;
-        V1[i] = vy;
-        V2[i] = vz;
-        X0[i] = nx;
-        X1[i] = ny;
-        X2[i] = nz;
+        __builtin_nontemporal_store(vx, &V0[i]);
+        __builtin_nontemporal_store(vy, &V1[i]);
+        __builtin_nontemporal_store(vz, &V2[i]);
+        __builtin_nontemporal_store(nx, &X0[i]);
+        __builtin_nontemporal_store(ny, &X1[i]);
+        __builtin_nontemporal_store(nz, &X2[i]);
         const double ex = (double)nx, ey = (double)ny, ez = (double)nz;
         if (outside_global(sys, ex, ey, ez)) {
           LOST[i] = 1;
