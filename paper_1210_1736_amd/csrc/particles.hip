@@ -325,6 +325,18 @@ __device__ __forceinline__ int force_blocks_dev(int64_t n) {
 }
 
 
+// Zero n elements at g (a device allocation, 16-byte aligned) with block lb
+// of nb (256 threads each): 16-byte global stores, then the tail.
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ void zero_block(T* g, size_t n, int lb, int nb) {
+  constexpr size_t per = 16 / sizeof(T);
+  const size_t n16 = n / per;
+  const gp<u32x4> G = glb((u32x4*)g);
+  for (size_t k = (size_t)lb * 256 + threadIdx.x; k < n16; k += (size_t)nb * 256) G[k] = u32x4{0u, 0u, 0u, 0u};
+  if (lb == 0 && threadIdx.x < n - n16 * per) glb(g)[n16 * per + threadIdx.x] = (T)0;
+}
+
 // ------------------------------------------------------------- instances --
 __device__ __forceinline__ int span_inst(const Span& sp, int b) {
   int i = 0;
@@ -373,9 +385,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_zero_grids(const InstDev<T>* __restrict__ inst, Span sp) {
   const int i = span_inst(sp, blockIdx.x);
   const int lb = blockIdx.x - sp.start[i], nb = sp.start[i + 1] - sp.start[i];
-  T* g = inst[i].grid_block;
-  const size_t n = inst[i].grid_elems;
-  for (size_t k = (size_t)lb * 256 + threadIdx.x; k < n; k += (size_t)nb * 256) g[k] = (T)0;
+  zero_block(inst[i].grid_block, inst[i].grid_elems, lb, nb);
 }
 
 // ------------------------------------------------------ loss test and COM --
@@ -450,7 +460,7 @@ __device__ __forceinline__ void centres_of(const InstDev<T>& I, int from_com, in
     if (!dm || dm_on) {
       const bool com = from_com && !dm;
       const size_t cs = com ? kForceBlocksMax : kRedBlocks;  // column stride
-      const double* col = (dm ? I.dm_partial : (com ? I.com_partial : I.pre_partial)) + 4 * g * cs;
+      const gp<const double> col = glb((const double*)(dm ? I.dm_partial : (com ? I.com_partial : I.pre_partial)) + 4 * g * cs);
       const int rows = com ? force_blocks_dev(I.n) : kRedBlocks;
       // the galaxy's four columns, eight rows each per round, loads together
       for (int r0 = threadIdx.x; r0 < rows; r0 += 8 * 256) {
@@ -515,9 +525,7 @@ __global__ void __launch_bounds__(256)
   const int i = span_inst(sp, blockIdx.x);
   const int lb = blockIdx.x - sp.start[i], nb = sp.start[i + 1] - sp.start[i];
   if (lb == 0) centres_of(inst[i], 1, 0);
-  T* g = inst[i].grid_block;
-  const size_t n = inst[i].grid_elems;
-  for (size_t k = (size_t)lb * 256 + threadIdx.x; k < n; k += (size_t)nb * 256) g[k] = (T)0;
+  zero_block(inst[i].grid_block, inst[i].grid_elems, lb, nb);
 }
 
 // ------------------------------------------------ density-maximum centring --
@@ -1113,7 +1121,7 @@ __global__ void __launch_bounds__(256)
       const int* id = lev == 0 ? c.idx[0] : (lev == 1 ? c.idx[1] : c.idx[2]);
       k = (uint32_t)(bins_before(sys, g, lev) + ((id[2] * n + id[1]) * n + id[0]));
     }
-    I.key[i] = k;
+    glb(I.key)[i] = k;
   }
   // Each run of equal keys in the wavefront reserves its places in the bin
   // with one atomic from its last lane; every lane keeps its own place, so
@@ -1133,7 +1141,7 @@ __global__ void __launch_bounds__(256)
     if (lane + o < 64) tl = min(tl, t2);
   }
   const uint32_t run_base = __shfl(base, tl & 63, 64);
-  if (i < p.n) I.rank[i] = run_base + rank1 - 1;
+  if (i < p.n) glb(I.rank)[i] = run_base + rank1 - 1;
 }
 
 // A particle's slot is the start of its bin (the counts scanned, global over
