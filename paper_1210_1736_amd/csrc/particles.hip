@@ -7,6 +7,8 @@
 // Cell indices and classes are integers decided by float64 arithmetic with
 // every operation rounded separately (no fused multiply-add), so that any
 // other implementation following the same formulas gets identical integers.
+#include <type_traits>
+
 #include "particles.h"
 #include "scan.h"
 
@@ -1212,11 +1214,21 @@ __global__ void k_flip(int* cur, int n) {
 // Eq. 8 stencil weights transposed).  Adjoint state is kept in float64.
 //
 // The A^T mu contributions of a block's particles (19 cells per field) are
-// summed in an LDS hash table keyed like the deposit (grid slot, cell) and
-// flushed with one global atomic per distinct cell; cell-sorted particles
-// share most of their stencil cells.
+// summed across runs of lanes on the same cell (wavefront sums), then in an
+// LDS hash table keyed like the deposit (grid slot, cell), and flushed with
+// one global atomic per distinct cell; cell-sorted particles share most of
+// their stencil cells.
 constexpr int kAdjTableBits = 12;
 constexpr int kAdjTable = 1 << kAdjTableBits;
+
+// A key's first slot is the key modulo a prime just below the table size:
+// consecutive cells take consecutive slots, so the flush, which walks the
+// slots in order, hands consecutive cells to consecutive lanes and its
+// global atomics coalesce (a scattering hash made them one line each and
+// the flush the larger part of the kernel), while the stencil offsets
+// (+-1, +-N, +-N^2 and their sums) still land on distinct slots.
+constexpr uint32_t kAdjPrime = 4093u;
+static_assert(kAdjPrime <= (uint32_t)kAdjTable, "slot range");
 
 template <typename T>
 struct AdjSink {
@@ -1224,7 +1236,7 @@ struct AdjSink {
   T* tval;
   const GridsDev<T>* B;
   __device__ __forceinline__ void add(uint32_t key, double v) const {
-    uint32_t h = (key * 2654435761u) >> (32 - kAdjTableBits);
+    uint32_t h = key % kAdjPrime;
     for (int q = 0; q < 8; ++q) {
       const uint32_t old = atomicCAS(tkey + h, kNoKey, key);
       if (old == kNoKey || old == key) {
@@ -1237,27 +1249,32 @@ struct AdjSink {
   }
 };
 
+// The A^T mu weights of one field at the particle (Eq. 8 stencil weights
+// transposed) in the order of kAdjOff, and J mu (the field's second
+// differences times mu) added to lx.  taylor = 0: only the six face
+// weights are nonzero and J is not used.
+constexpr int kAdjPts = 19;
 template <typename T>
-__device__ __forceinline__ void eq8_adjoint(const T* __restrict__ F, const AdjSink<T>& sink,
-                                            uint32_t key, const LevelDev& L, const int* id,
-                                            double dx, double dy, double dz, int taylor,
-                                            const double* mu, double* lx) {
+__device__ __forceinline__ void eq8_adjoint_weights(const T* __restrict__ F, const LevelDev& L,
+                                                    const int* id, double dx, double dy, double dz,
+                                                    int taylor, const double* mu, double* lx,
+                                                    double* w) {
   const int sy = L.N, sz = L.N * L.N;
+  const double mx = mu[0], my = mu[1], mz = mu[2];
+  w[0] = mx * L.c_2l;
+  w[1] = -mx * L.c_2l;
+  w[2] = my * L.c_2l;
+  w[3] = -my * L.c_2l;
+  w[4] = mz * L.c_2lz;
+  w[5] = -mz * L.c_2lz;
+#pragma unroll
+  for (int k = 6; k < kAdjPts; ++k) w[k] = 0.0;
+  if (!taylor) return;
   const ptrdiff_t o = (ptrdiff_t)id[2] * sz + (ptrdiff_t)id[1] * sy + id[0];
   const gp<const T> P = glb(F) + o;
   const double Dx = dx - ((double)id[0] - L.half) * L.l;
   const double Dy = dy - ((double)id[1] - L.half) * L.l;
   const double Dz = dz - ((double)id[2] - L.half) * L.lz;
-  const double mx = mu[0], my = mu[1], mz = mu[2];
-  if (!taylor) {
-    sink.add(key + 1, mx * L.c_2l);
-    sink.add(key - 1, -mx * L.c_2l);
-    sink.add(key + sy, my * L.c_2l);
-    sink.add(key - sy, -my * L.c_2l);
-    sink.add(key + sz, mz * L.c_2lz);
-    sink.add(key - sz, -mz * L.c_2lz);
-    return;
-  }
   // J mu from the field's second differences (symmetric)
   const double p0 = (double)P[0];
   const double hxx = ((double)P[1] + (double)P[-1] - 2.0 * p0) * L.c_l2;
@@ -1271,28 +1288,54 @@ __device__ __forceinline__ void eq8_adjoint(const T* __restrict__ F, const AdjSi
   lx[2] += hxz * mx + hyz * my + hzz * mz;
   // A^T mu: faces, centre, edges
   const double wx = mx * Dx * L.c_l2, wy = my * Dy * L.c_l2, wz = mz * Dz * L.c_lz2;
-  sink.add(key + 1, mx * L.c_2l + wx);
-  sink.add(key - 1, -mx * L.c_2l + wx);
-  sink.add(key + sy, my * L.c_2l + wy);
-  sink.add(key - sy, -my * L.c_2l + wy);
-  sink.add(key + sz, mz * L.c_2lz + wz);
-  sink.add(key - sz, -mz * L.c_2lz + wz);
-  sink.add(key, -2.0 * (wx + wy + wz));
+  w[0] += wx;
+  w[1] += wx;
+  w[2] += wy;
+  w[3] += wy;
+  w[4] += wz;
+  w[5] += wz;
+  w[6] = -2.0 * (wx + wy + wz);
   const double exy = (mx * Dy + my * Dx) * L.c_4ll;
   const double exz = (mx * Dz + mz * Dx) * L.c_4llz;
   const double eyz = (my * Dz + mz * Dy) * L.c_4llz;
-  sink.add(key + 1 + sy, exy);
-  sink.add(key - 1 + sy, -exy);
-  sink.add(key - 1 - sy, exy);
-  sink.add(key + 1 - sy, -exy);
-  sink.add(key + 1 + sz, exz);
-  sink.add(key - 1 + sz, -exz);
-  sink.add(key - 1 - sz, exz);
-  sink.add(key + 1 - sz, -exz);
-  sink.add(key + sy + sz, eyz);
-  sink.add(key - sy + sz, -eyz);
-  sink.add(key - sy - sz, eyz);
-  sink.add(key + sy - sz, -eyz);
+  w[7] = exy;
+  w[8] = -exy;
+  w[9] = exy;
+  w[10] = -exy;
+  w[11] = exz;
+  w[12] = -exz;
+  w[13] = exz;
+  w[14] = -exz;
+  w[15] = eyz;
+  w[16] = -eyz;
+  w[17] = eyz;
+  w[18] = -eyz;
+}
+
+// Cell offsets of the weights above on a grid of N cells per axis.
+__device__ __forceinline__ int adj_off(int k, int N) {
+  const int sy = N, sz = N * N;
+  switch (k) {
+    case 0: return 1;
+    case 1: return -1;
+    case 2: return sy;
+    case 3: return -sy;
+    case 4: return sz;
+    case 5: return -sz;
+    case 6: return 0;
+    case 7: return 1 + sy;
+    case 8: return -1 + sy;
+    case 9: return -1 - sy;
+    case 10: return 1 - sy;
+    case 11: return 1 + sz;
+    case 12: return -1 + sz;
+    case 13: return -1 - sz;
+    case 14: return 1 - sz;
+    case 15: return sy + sz;
+    case 16: return -sy + sz;
+    case 17: return -sy - sz;
+    default: return sy - sz;
+  }
 }
 
 // Seed: L = sum over the selected particles of 1/2 m vz^2; dL/dvz = m vz,
@@ -1326,63 +1369,119 @@ __global__ void __launch_bounds__(256)
   __shared__ uint32_t tkey[kAdjTable];
   __shared__ T tval[kAdjTable];
   __shared__ double cen[3 * kMaxGal];  // read from LDS inside the galaxy loop
+  // the adjoint grids' pointers, indexed by each key's slot: in LDS (taken
+  // from the by-value argument with constant indices), not in scratch
+  __shared__ GridsDev<T> Bs;
   const InstDev<T>& I = inst[0];
   for (int k = threadIdx.x; k < kAdjTable; k += 256) {
     tkey[k] = kNoKey;
     tval[k] = (T)0;
   }
   if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = I.centres[threadIdx.x];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int g = 0; g < kMaxGal; ++g)
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) Bs.g[g][k] = Bg.g[g][k];
+  }
   __syncthreads();
-  const AdjSink<T> sink{tkey, tval, &Bg};
+  const AdjSink<T> sink{tkey, tval, &Bs};
   const PartDev<T> p = I.p[cur[0]];
   const SysDev& sys = I.sys;
   const double dt = I.dt;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < p.n && !out[i]) {
-    double l[3] = {lx[3 * i], lx[3 * i + 1], lx[3 * i + 2]};
-    double w[3] = {lv[3 * i] + dt * l[0], lv[3 * i + 1] + dt * l[1], lv[3 * i + 2] + dt * l[2]};
-    lv[3 * i] = w[0];
-    lv[3 * i + 1] = w[1];
-    lv[3 * i + 2] = w[2];
-    const double mu[3] = {dt * w[0], dt * w[1], dt * w[2]};
-    const double x = (double)p.x[0][i], y = (double)p.x[1][i], z = (double)p.x[2][i];
-    const GridsDev<T>& F = I.G;
-    for (int g = 0; g < sys.ngal; ++g) {
-      const HierDev& h = sys.h[g];
-      const double* c = cen + 3 * g;
-      Classified cl;
-      classify(h, c, x, y, z, cl);
-      const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+  // Every lane takes part in the wavefront sums below, with or without a
+  // particle (act); a lane without one carries no key.
+  const bool act = i < p.n && !out[i];
+  double l[3] = {0.0, 0.0, 0.0}, mu[3] = {0.0, 0.0, 0.0};
+  double x = 0.0, y = 0.0, z = 0.0;
+  if (act) {
+    l[0] = lx[3 * i];
+    l[1] = lx[3 * i + 1];
+    l[2] = lx[3 * i + 2];
+    const double w0 = lv[3 * i] + dt * l[0], w1 = lv[3 * i + 1] + dt * l[1], w2 = lv[3 * i + 2] + dt * l[2];
+    lv[3 * i] = w0;
+    lv[3 * i + 1] = w1;
+    lv[3 * i + 2] = w2;
+    mu[0] = dt * w0;
+    mu[1] = dt * w1;
+    mu[2] = dt * w2;
+    x = (double)p.x[0][i];
+    y = (double)p.x[1][i];
+    z = (double)p.x[2][i];
+  }
+  const GridsDev<T>& F = I.G;
+  for (int g = 0; g < sys.ngal; ++g) {
+    const HierDev& h = sys.h[g];
+    const double* c = cen + 3 * g;
+    Classified cl;
+    cl.cls = SBX_LOST;
+    if (act) classify(h, c, x, y, z, cl);
+    const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+    const double ox = x - h.outer_c[0], oy = y - h.outer_c[1], oz = z - h.outer_c[2];
+    // one field per level at most (the grid-selection rule): its slot, in
+    // level order, so that lx sums the fields in the forward's order
+#pragma unroll
+    for (int lev = 0; lev < 3; ++lev) {  // unrolled: the cell arrays are indexed by constants
+      if (lev >= h.n_levels) break;
+      int slot = -1;
       if (h.n_levels == 1) {
-        if (cl.cls == SBX_OUTER)
-          eq8_adjoint(F.g[g][0], sink, dep_key(g, 0, h.lv[0], cl.idx[0]), h.lv[0], cl.idx[0], dx, dy,
-                      dz, sys.taylor, mu, l);
-        continue;
+        if (cl.cls == SBX_OUTER) slot = 0;
+      } else if (lev == 0) {
+        if (cl.cls == SBX_CORE) slot = 0;
+      } else if (lev == 1) {
+        if (cl.cls == SBX_CORE) slot = 1;
+        else if (cl.cls == SBX_RING) slot = 2;
+      } else {
+        if (cl.cls == SBX_CORE || cl.cls == SBX_RING) slot = 3;
+        else if (cl.cls == SBX_OUTER) slot = 4;
       }
-      const double ox = x - h.outer_c[0], oy = y - h.outer_c[1], oz = z - h.outer_c[2];
-      switch (cl.cls) {
-        case SBX_CORE:
-          eq8_adjoint(F.g[g][0], sink, dep_key(g, 0, h.lv[0], cl.idx[0]), h.lv[0], cl.idx[0], dx, dy,
-                      dz, sys.taylor, mu, l);
-          eq8_adjoint(F.g[g][1], sink, dep_key(g, 1, h.lv[1], cl.idx[1]), h.lv[1], cl.idx[1], dx, dy,
-                      dz, sys.taylor, mu, l);
-          eq8_adjoint(F.g[g][3], sink, dep_key(g, 3, h.lv[2], cl.idx[2]), h.lv[2], cl.idx[2], ox, oy,
-                      oz, sys.taylor, mu, l);
-          break;
-        case SBX_RING:
-          eq8_adjoint(F.g[g][2], sink, dep_key(g, 2, h.lv[1], cl.idx[1]), h.lv[1], cl.idx[1], dx, dy,
-                      dz, sys.taylor, mu, l);
-          eq8_adjoint(F.g[g][3], sink, dep_key(g, 3, h.lv[2], cl.idx[2]), h.lv[2], cl.idx[2], ox, oy,
-                      oz, sys.taylor, mu, l);
-          break;
-        case SBX_OUTER:
-          eq8_adjoint(F.g[g][4], sink, dep_key(g, 4, h.lv[2], cl.idx[2]), h.lv[2], cl.idx[2], ox, oy,
-                      oz, sys.taylor, mu, l);
-          break;
-        default:
-          break;
+      const LevelDev& L = h.lv[lev];
+      const bool outer = h.n_levels > 1 && lev == 2;
+      double w[kAdjPts];
+      uint32_t key = kNoKey;
+      if (slot >= 0) {
+        key = dep_key(g, slot, L, cl.idx[lev]);
+        eq8_adjoint_weights(F.g[g][slot], L, cl.idx[lev], outer ? ox : dx, outer ? oy : dy,
+                            outer ? oz : dz, sys.taylor, mu, l, w);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kAdjPts; ++k) w[k] = 0.0;
+      }
+      // A^T mu of runs of lanes on the same cell summed across the
+      // wavefront (cell-sorted particles share cells), then one table add
+      // per run
+      auto put = [&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const uint32_t kk = key == kNoKey ? kNoKey : (uint32_t)((int)key + adj_off(k, L.N));
+        bool tail;
+        const double sum = wave_run_sum<double>(kk, w[k], tail);
+        if (tail && kk != kNoKey) sink.add(kk, sum);
+      };
+      put(std::integral_constant<int, 0>());
+      put(std::integral_constant<int, 1>());
+      put(std::integral_constant<int, 2>());
+      put(std::integral_constant<int, 3>());
+      put(std::integral_constant<int, 4>());
+      put(std::integral_constant<int, 5>());
+      if (sys.taylor) {
+        put(std::integral_constant<int, 6>());
+        put(std::integral_constant<int, 7>());
+        put(std::integral_constant<int, 8>());
+        put(std::integral_constant<int, 9>());
+        put(std::integral_constant<int, 10>());
+        put(std::integral_constant<int, 11>());
+        put(std::integral_constant<int, 12>());
+        put(std::integral_constant<int, 13>());
+        put(std::integral_constant<int, 14>());
+        put(std::integral_constant<int, 15>());
+        put(std::integral_constant<int, 16>());
+        put(std::integral_constant<int, 17>());
+        put(std::integral_constant<int, 18>());
       }
     }
+  }
+  if (act) {
     lx[3 * i] = l[0];
     lx[3 * i + 1] = l[1];
     lx[3 * i + 2] = l[2];
@@ -1390,7 +1489,7 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
   for (int k = threadIdx.x; k < kAdjTable; k += 256) {
     const uint32_t key = tkey[k];
-    if (key != kNoKey) atomic_add_g(glb(slot_ptr(Bg, key)), tval[k]);
+    if (key != kNoKey) atomic_add_g(glb(slot_ptr(Bs, key)), tval[k]);
   }
 }
 
