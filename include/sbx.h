@@ -313,6 +313,29 @@ sbx_status sbx_disc_modes(sbx_ctx* ctx, int32_t comp, int32_t galaxy, int32_t n_
  * alone.  sbx_adjoint_segment rejects a merged context (SBX_EINVAL). */
 sbx_status sbx_set_outer_merge(sbx_ctx* ctx, int32_t merge);
 
+/* Mass assignment form (Sec. 2.1; Eq. 7 cells).  on = 0 (the default):
+ * cell masses are floating-point sums in the context's precision, added in
+ * an order that varies between runs (atomics).  on = 1: fixed-point sums.
+ * Every mass enters as the integer floor(m 2^s), s = 62 - e - b, where the
+ * largest particle mass of the context is below 2^e and b is the bit length
+ * of its particle count, so that every cell total fits in 62 bits; the
+ * integers are summed exactly and each cell mass is (sum converted to
+ * float64 with one rounding) * 2^-s, then rounded to the context's
+ * precision.  Cell masses are then independent of the order of the adds
+ * and equal the oracle's fixed-point assignment bit for bit.  Nothing else
+ * in a step depends on the order of additions except the FP64 sums of the
+ * centre of mass and of the density-maximum centre, which run in particle
+ * order: runs are bitwise reproducible with fixed centres, or with the
+ * reorder off (sbx_set_sort_interval 0; the reorder's slot reservation
+ * leaves the particles of one cell in a varying order).  Each mass loses
+ * less than 2^-s (for 8.5M equal masses of 6.6e-7 that is 3.5e-18, 5e-12
+ * relative).  Costs one 8-byte accumulator per mass-grid
+ * cell and a conversion pass per assignment.  Takes effect for the next
+ * assignment; kept by sbx_save / sbx_load.  SBX_ESTATE while the context
+ * belongs to a batch (the contexts of a batch must share the form,
+ * SBX_EINVAL from sbx_batch_create otherwise). */
+sbx_status sbx_set_deterministic_deposit(sbx_ctx* ctx, int32_t on);
+
 /* Reorder the particles in device memory by the cell of their finest grid
  * every `every` steps (at the start of the step; 0 = never; default 4).  A
  * performance setting only: every output is returned in the caller's
@@ -321,21 +344,23 @@ sbx_status sbx_set_sort_interval(sbx_ctx* ctx, int32_t every);
 
 /* Checkpoint files (Sec. 3.1 and 4.1: models are evolved in isolation, kept
  * and reused).  sbx_save writes the whole state of a context: precision, G,
- * h0_mode, taylor, the hierarchies, the outer-merge and sort settings, the
+ * h0_mode, taylor, the hierarchies, the outer-merge, mass assignment and
+ * sort settings, the
  * step count and last dt, the centres of the last solve (the state density-
  * maximum centring continues from), and the particles in the caller's order
  * (x, staggered v, m, comp, gal, lost).  The diagnostics log is not saved.
  * Synchronises.  SBX_ESTATE without grids or particles, SBX_EINVAL when the
  * file cannot be written.
  * sbx_load restores such a file into a context created with the same
- * precision, G, h0_mode and taylor setting (SBX_EINVAL otherwise, and for a
- * file that is not a version-1 checkpoint, truncated or corrupt): it rebuilds
- * the grids and Green's tables, loads the particles (owned copies) with
- * their lost flags, and restores the step count, dt, centres and settings.
- * Stepping on from a loaded state gives what stepping the saved context
- * would have given, up to the summation order of the mass assignment (bit
- * for bit when every cell total is exact, e.g. dyadic masses, with fixed
- * centres). */
+ * precision, G, h0_mode and taylor setting (SBX_EINVAL otherwise, and for
+ * a file that is not a version 1 or 2 checkpoint, truncated or corrupt): it
+ * rebuilds the grids and Green's tables, loads the particles (owned copies)
+ * with their lost flags, and restores the step count, dt, centres and
+ * settings.  Stepping on from a loaded state gives what stepping the saved
+ * context would have given, up to summation orders (bit for bit with fixed
+ * centres when the mass assignment is fixed-point or every cell total is
+ * exact, e.g. dyadic masses; centre-of-mass sums run in particle order,
+ * which a load resets to the caller's). */
 sbx_status sbx_save(sbx_ctx* ctx, const char* path);
 sbx_status sbx_load(sbx_ctx* ctx, const char* path);
 

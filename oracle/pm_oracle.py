@@ -283,6 +283,21 @@ def deposit(idx, m, N):
     return np.bincount(flat, weights=m, minlength=N ** 3).reshape(N, N, N)
 
 
+def deposit_fixed(idx, m, N, shift):
+    """The fixed-point reading of the same cell masses (reading: cell masses
+    that do not depend on the order of the additions).  Each mass becomes the
+    integer floor(m 2^shift) (exact in float64 for a power-of-two scale),
+    the integers are summed exactly per cell, and each total is converted
+    once to float64 (rounded to nearest) and scaled by 2^-shift.  With shift
+    from density_mass_shift of the whole particle set, no total reaches 2^62.
+    """
+    q = np.floor(np.ldexp(np.asarray(m, np.float64), shift)).astype(np.int64)
+    flat = (idx[:, 0] * N + idx[:, 1]) * N + idx[:, 2]
+    tot = np.zeros(N ** 3, np.int64)
+    np.add.at(tot, flat, q)
+    return np.ldexp(tot.astype(np.float64), -shift).reshape(N, N, N)
+
+
 # --------------------------------------------------------------------------
 # Green's function and the isolated solve (Eqs. 1-5)
 # --------------------------------------------------------------------------
@@ -465,8 +480,9 @@ def leapfrog_kd(x, v, acc, dt):
 class System:
     """Galaxies with their grids, Green's tables and the per-step solve."""
 
-    def __init__(self, hierarchies, G=1.0, h0_mode=0, taylor=True):
+    def __init__(self, hierarchies, G=1.0, h0_mode=0, taylor=True, fixed_deposit=False):
         self.h = list(hierarchies)
+        self.fixed_deposit = fixed_deposit  # cell masses by deposit_fixed
         for g, hh in enumerate(self.h):
             validate_hierarchy(hh, first_galaxy=(g == 0))
         if len(self.h) > 1:
@@ -513,6 +529,11 @@ class System:
         'Phi' = [Phi1..Phi5] (three levels) or [Phi] (one level), plus 'M'.
         """
         out = []
+        if self.fixed_deposit:
+            shift = density_mass_shift(np.asarray(m, np.float64))
+            deposit = lambda i, w, N: deposit_fixed(i, w, N, shift)  # noqa: E731
+        else:
+            deposit = globals()["deposit"]
         for g, hh in enumerate(self.h):
             sel = (gal == g) & ~lost
             xs, ms = x[sel], m[sel]

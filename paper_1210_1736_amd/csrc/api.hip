@@ -205,6 +205,7 @@ InstDev<T> inst_of(const sbx_ctx* c) {
   I.dm_mmax = c->dm_mmax;
   I.dt = c->dt_dev;
   I.n = c->n;
+  I.fix = c->fix;
   return I;
 }
 
@@ -284,6 +285,7 @@ void free_grids(sbx_ctx* c) {
   free_ptr(c->adj_work);
   c->adj_work_bytes = 0;
   free_ptr(c->grid_block);
+  free_typed(c->fix);
   free_typed(c->count);
   free_typed(c->scan_tmp);
   free_typed(c->dm_hist);
@@ -330,6 +332,10 @@ sbx_status build_grids_t(sbx_ctx* c) {
   for (int g = 0; g < c->ngal; ++g)
     if (c->nslots[g] > 1)
       for (int k : {2, 4}) c->grid[g][k] = (T*)c->grid_block + cells * (s++);
+  if (c->fix_on) {
+    SBX_TRY(dev_alloc((void**)&c->fix, sizeof(unsigned long long) * c->mass_elems));
+    SBX_HIP(hipMemsetAsync(c->fix, 0, sizeof(unsigned long long) * c->mass_elems, c->stream));
+  }
   // Green's tables, one per distinct level geometry
   for (int g = 0; g < c->ngal; ++g)
     for (int lv = 0; lv < c->hh[g].n_levels; ++lv) {
@@ -1440,6 +1446,27 @@ sbx_status sbx_set_outer_merge(sbx_ctx* c, int32_t merge) {
   }
   c->merge5 = merge;
   return SBX_OK;
+}
+
+sbx_status sbx_set_deterministic_deposit(sbx_ctx* c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) {
+    set_error("bad argument");
+    return SBX_EINVAL;
+  }
+  if (c->batch) {
+    set_error("the context belongs to a batch");
+    return SBX_ESTATE;
+  }
+  SBX_TRY(set_device(c->cfg.device));
+  c->fix_on = on != 0;
+  if (c->fix_on && !c->fix && c->grid_block) {
+    SBX_TRY(dev_alloc((void**)&c->fix, sizeof(unsigned long long) * c->mass_elems));
+    SBX_HIP(hipMemsetAsync(c->fix, 0, sizeof(unsigned long long) * c->mass_elems, c->stream));
+  } else if (!c->fix_on && c->fix) {
+    SBX_HIP(hipStreamSynchronize(c->stream));  // no kernel in flight still uses them
+    free_typed(c->fix);
+  }
+  return upload_inst(c);
 }
 
 sbx_status sbx_set_sort_interval(sbx_ctx* c, int32_t every) {

@@ -181,6 +181,10 @@ sbx_status sbx_batch_create(sbx_ctx* const* ctxs, int32_t n, void* stream, sbx_b
       set_error("contexts of a batch share device and precision");
       return SBX_EINVAL;
     }
+    if ((c->fix != nullptr) != (ctxs[0]->fix != nullptr)) {
+      set_error("contexts of a batch share the mass assignment form (fixed-point or not)");
+      return SBX_EINVAL;
+    }
     if (c->cur != ctxs[0]->cur || c->com_fresh != ctxs[0]->com_fresh) {
       set_error("contexts of a batch must be in the same state (fresh, or all stepped together)");
       return SBX_ESTATE;

@@ -3,8 +3,9 @@
 // isolation, then combined), so a state is written and read back whole.
 //
 // Format (little-endian, fields written one by one, no padding):
-//   "SBXCKPT1", int32 version (1), int32 prec, double G, int32 h0_mode,
-//   int32 taylor, int32 ngal, int32 merge5, int32 sort_every, int32 solved,
+//   "SBXCKPT1", int32 version (2), int32 prec, double G, int32 h0_mode,
+//   int32 taylor, int32 ngal, int32 merge5, int32 sort_every,
+//   int32 fixed-point mass assignment (version 2 only), int32 solved,
 //   int64 n, int64 step_count, double dt, per galaxy: int32 n_levels,
 //   int32 centring, 3 x (int32 n, double R, double q), double centre[3],
 //   double outer_centre[3]; then double centres[3 * ngal] (the centres of
@@ -21,7 +22,7 @@ namespace {
 
 constexpr char kMagic[8] = {'S', 'B', 'X', 'C', 'K', 'P', 'T', '1'};
 constexpr char kTail[8] = {'S', 'B', 'X', 'E', 'N', 'D', '0', '1'};
-constexpr int32_t kVersion = 1;
+constexpr int32_t kVersion = 2;  // version 1 files (no mass assignment flag) still load
 
 struct Writer {
   FILE* f;
@@ -117,6 +118,7 @@ sbx_status sbx_save(sbx_ctx* c, const char* path) {
   w.put<int32_t>(c->ngal);
   w.put<int32_t>(c->sys.merge5);
   w.put<int32_t>(c->sort_every);
+  w.put<int32_t>(c->fix_on ? 1 : 0);
   w.put<int32_t>(c->solved ? 1 : 0);
   w.put<int64_t>(n);
   w.put<int64_t>(c->step_count);
@@ -170,18 +172,21 @@ sbx_status sbx_load(sbx_ctx* c, const char* path) {
   std::fclose(f);
   char magic[8];
   r.raw(magic, 8);
-  if (!r.ok || std::memcmp(magic, kMagic, 8) != 0 || r.get<int32_t>() != kVersion) {
-    set_error(std::string(path) + " is not a checkpoint of this library (version 1)");
+  const int32_t version = r.ok ? r.get<int32_t>() : 0;
+  if (!r.ok || std::memcmp(magic, kMagic, 8) != 0 || version < 1 || version > kVersion) {
+    set_error(std::string(path) + " is not a checkpoint of this library (versions 1 and 2)");
     return SBX_EINVAL;
   }
   const int32_t prec = r.get<int32_t>();
   const double G = r.get<double>();
   const int32_t h0 = r.get<int32_t>(), taylor = r.get<int32_t>(), ngal = r.get<int32_t>();
-  const int32_t merge5 = r.get<int32_t>(), sort_every = r.get<int32_t>(), solved = r.get<int32_t>();
+  const int32_t merge5 = r.get<int32_t>(), sort_every = r.get<int32_t>();
+  const int32_t fixed = version >= 2 ? r.get<int32_t>() : 0;
+  const int32_t solved = r.get<int32_t>();
   const int64_t n = r.get<int64_t>(), steps = r.get<int64_t>();
   const double dt = r.get<double>();
   if (!r.ok || ngal < 1 || ngal > kMaxGal || n <= 0 || n >= ((int64_t)1 << 31) || sort_every < 0 ||
-      (merge5 != 0 && merge5 != 1)) {
+      (merge5 != 0 && merge5 != 1) || (fixed != 0 && fixed != 1)) {
     set_error(std::string(path) + ": corrupt header");
     return SBX_EINVAL;
   }
@@ -221,6 +226,7 @@ sbx_status sbx_load(sbx_ctx* c, const char* path) {
     return SBX_EINVAL;
   }
   SBX_TRY(sbx_set_outer_merge(c, merge5));
+  SBX_TRY(sbx_set_deterministic_deposit(c, fixed));
   SBX_TRY(sbx_build_grids(c, ngal, hh.data()));
   SBX_TRY(load_impl(c, n, x.data(), v.data(), m.data(), comp.data(), gal.data(), false));
   // load_impl leaves the caller's order (cur = 0): the flags go straight in

@@ -67,6 +67,8 @@ struct sbx_ctx {
   void* grid_block = nullptr;  // all grids back to back
   size_t grid_elems = 0;
   size_t mass_elems = 0;       // the leading part of the block that takes masses
+  bool fix_on = false;         // fixed-point mass assignment requested
+  unsigned long long* fix = nullptr;  // its accumulators (mass_elems), while grids exist
   void* grid[sbx::kMaxGal][sbx::kSlots] = {};
   std::vector<sbx::Green> greens;
   void* X = nullptr;
@@ -161,6 +163,8 @@ sbx_status get_impl(sbx_ctx* c, double* x, double* v, uint8_t* lost, bool dev);
 sbx_status bind_impl(sbx_ctx* c, int64_t n, void* x, void* v, void* m, int8_t* comp, int8_t* gal,
                      uint8_t* lost);
 
-inline InstInfo info_of(const sbx_ctx* c) { return InstInfo{c->n, c->mass_elems, c->dm_elems}; }
+inline InstInfo info_of(const sbx_ctx* c) {
+  return InstInfo{c->n, c->mass_elems, c->dm_elems, c->fix != nullptr};
+}
 
 }  // namespace sbx

@@ -97,6 +97,7 @@ struct InstDev {
   double* pot;              // n (write mode, physical potential)
   T* grid_block;            // all grids of the instance, back to back
   size_t grid_elems;        // the leading grids that take masses (cleared per step)
+  unsigned long long* fix;  // fixed-point mass accumulators, grid_elems of them (null: FP sums)
   uint32_t* key;            // n
   uint32_t* rank;           // n: place of the particle within its sort bin
   uint32_t* count;          // bins + 1: this instance's slice of the shared counts
@@ -137,6 +138,7 @@ struct InstInfo {
   int64_t n;
   size_t grid_elems;  // grid elements cleared per step
   size_t dm_elems;  // density-maximum histogram (0: no galaxy uses it)
+  bool fix;         // fixed-point mass assignment (the same for every instance of a launch)
 };
 
 struct Span {

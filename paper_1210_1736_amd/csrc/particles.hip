@@ -760,11 +760,20 @@ __device__ __forceinline__ T* slot_ptr(const GridsDev<T>& G, uint32_t key) {
   return G.g[g][slot] + (key & 0xFFFFFFu);
 }
 
-template <typename T>
+//
+// FIX: the fixed-point form.  Every mass enters as the integer
+// floor(m 2^s), s = 62 - e - b (the largest mass of the instance is below
+// 2^e, b is the bit length of its particle count; the scale of the
+// density-maximum centring), so every cell total fits in 62 bits; the sums
+// are exact 64-bit integer sums in any order, into the accumulators I.fix
+// (one per mass-grid element), and k_fix_convert turns them into cell
+// masses.  Cell masses then do not depend on the order of the adds.
+template <typename T, bool FIX>
 __global__ void __launch_bounds__(256)
     k_deposit(const InstDev<T>* __restrict__ inst, const int* __restrict__ cur, Span sp) {
+  using V = std::conditional_t<FIX, unsigned long long, T>;
   __shared__ uint32_t tkey[kDepTable];
-  __shared__ T tval[kDepTable];
+  __shared__ V tval[kDepTable];
   // per-galaxy data staged in LDS: lanes index it by their own galaxy
   __shared__ SysDev sys;
   __shared__ GridsDev<T> G;
@@ -782,8 +791,17 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x < 3 * kMaxGal) cen[threadIdx.x] = I.centres[threadIdx.x];
   for (int k = threadIdx.x; k < kDepTable; k += 256) {
     tkey[k] = kNoKey;
-    tval[k] = (T)0;
+    tval[k] = (V)0;
   }
+  int shift = 0;
+  if constexpr (FIX) shift = dm_shift(*I.dm_mmax, I.n);
+  // the accumulator of a deposit key: the mass grid element itself, or its
+  // fixed-point accumulator at the same offset in the grid block
+  auto target = [&](uint32_t key) -> gp<V> {
+    T* cell = slot_ptr(G, key);
+    if constexpr (FIX) return glb(I.fix + (cell - I.grid_block));
+    else return glb(cell);
+  };
   __syncthreads();
   const int64_t base = (int64_t)lb * kDepChunk;
   // The next particle is loaded one iteration ahead, every field whatever
@@ -812,13 +830,14 @@ __global__ void __launch_bounds__(256)
     // fine: key on the finest level, or kNoKey; coarse keys c1, c2 go
     // through the table
     uint32_t fine = kNoKey, c1 = kNoKey, c2 = kNoKey;
-    T m = (T)0;
+    V m = (V)0;
     if (ok) {
       const HierDev& h = sys.h[g];
       const double x = (double)xs, y = (double)ys, z = (double)zs;
       Classified c;
       classify(h, cen + 3 * g, x, y, z, c);
-      m = ms;
+      if constexpr (FIX) m = (V)ldexp((double)ms, shift);  // floor: non-negative, truncated
+      else m = ms;
       if (h.n_levels == 1) {
         if (c.cls == SBX_OUTER) fine = dep_key(g, 0, h.lv[0], c.idx[0]);
       } else if (c.cls == SBX_CORE) {
@@ -834,14 +853,14 @@ __global__ void __launch_bounds__(256)
     }
     {
       bool tail;
-      const T s = wave_run_sum(fine, m, tail);
-      if (tail && fine != kNoKey) atomic_add_g(glb(slot_ptr(G, fine)), s);
+      const V s = wave_run_sum<V>(fine, m, tail);
+      if (tail && fine != kNoKey) atomic_add_g(target(fine), s);
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const uint32_t key = r == 0 ? c1 : c2;
       bool tail;
-      const T s = wave_run_sum(key, m, tail);
+      const V s = wave_run_sum<V>(key, m, tail);
       if (tail && key != kNoKey) {
         uint32_t hslot = (key * 2654435761u) >> (32 - kDepTableBits);
         bool done = false;
@@ -854,14 +873,35 @@ __global__ void __launch_bounds__(256)
             hslot = (hslot + 1) & (kDepTable - 1);
           }
         }
-        if (!done) atomic_add_g(glb(slot_ptr(G, key)), s);
+        if (!done) atomic_add_g(target(key), s);
       }
     }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < kDepTable; k += 256) {
     const uint32_t key = tkey[k];
-    if (key != kNoKey) atomic_add_g(glb(slot_ptr(G, key)), tval[k]);
+    if (key != kNoKey) atomic_add_g(target(key), tval[k]);
+  }
+}
+
+// Fixed-point mass assignment, second step: every accumulator of the
+// instance's mass grids becomes its cell mass (T)(sum 2^-s) (the integer
+// converted to float64 with one rounding, then scaled exactly) and is
+// cleared for the next assignment.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fix_convert(const InstDev<T>* __restrict__ inst, Span sp) {
+  const int i = span_inst(sp, blockIdx.x);
+  const int lb = blockIdx.x - sp.start[i], nb = sp.start[i + 1] - sp.start[i];
+  const InstDev<T>& I = inst[i];
+  const int shift = dm_shift(*I.dm_mmax, I.n);
+  const gp<unsigned long long> F = glb(I.fix);
+  const gp<T> M = glb(I.grid_block);
+  for (size_t k = (size_t)lb * 256 + threadIdx.x; k < I.grid_elems; k += (size_t)nb * 256) {
+    const unsigned long long q = F[k];
+    // both halves exact in float64; their sum rounded once
+    const double d = (double)(uint32_t)(q >> 32) * 4294967296.0 + (double)(uint32_t)q;
+    M[k] = (T)ldexp(d, -shift);
+    F[k] = 0ull;
   }
 }
 
@@ -1661,7 +1701,13 @@ sbx_status launch_deposit(const InstDev<T>* inst, const int* cur, const std::vec
                           hipStream_t s) {
   SBX_TRY(check_span(info));
   const Span sp = make_span(info, blocks_deposit);
-  hipLaunchKernelGGL((k_deposit<T>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
+  if (info[0].fix) {
+    hipLaunchKernelGGL((k_deposit<T, true>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
+    const Span sg = make_span(info, blocks_grid);
+    hipLaunchKernelGGL((k_fix_convert<T>), dim3(sg.start[sg.ninst]), dim3(256), 0, s, inst, sg);
+  } else {
+    hipLaunchKernelGGL((k_deposit<T, false>), dim3(sp.start[sp.ninst]), dim3(256), 0, s, inst, cur, sp);
+  }
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }

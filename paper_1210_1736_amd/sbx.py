@@ -102,6 +102,7 @@ def _load():
         "sbx_sync": (S, [P]),
         "sbx_set_sort_interval": (S, [P, I32]),
         "sbx_set_outer_merge": (S, [P, I32]),
+        "sbx_set_deterministic_deposit": (S, [P, I32]),
         "sbx_adjoint_segment": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
         "sbx_adjoint_segment_device": (S, [P, D, I32, I32, I32, I32, P, P, P, P]),
         "sbx_load_particles_device": (S, [P, I64, P, P, P, P, P]),
@@ -328,6 +329,10 @@ class Context:
 
     def sbx_set_outer_merge(self, merge):
         _check(_lib.sbx_set_outer_merge(self._h, int(merge)))
+
+    def sbx_set_deterministic_deposit(self, on):
+        """Fixed-point (order-independent, bit-reproducible) mass assignment."""
+        _check(_lib.sbx_set_deterministic_deposit(self._h, int(on)))
 
     def sbx_set_sort_interval(self, every):
         _check(_lib.sbx_set_sort_interval(self._h, int(every)))
