@@ -35,22 +35,28 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def phase_bytes(phase, N, nsolves, n_live, esz):
+def phase_bytes(phase, N, nsolves, n_live, esz, form=5):
     """Algorithmic HBM bytes of one launch of a phase (the data it must read
     and write once): FFT passes per the pruned layout, particle kernels per
-    the SoA fields they touch."""
+    the SoA fields they touch.  form 3 (plane-fused solves): the plane
+    forward pass is timed as fwd_x, the plane inverse as inv_y, and the
+    x-transformed planes never reach memory."""
     cplx = 2 * esz
     cells = N ** 3
     X = (N + 1) * N * N * cplx       # half spectrum after the x pass
     Cb = (N + 1) * 2 * N * N * cplx  # after the y pass (z < N kept)
     H = (N + 1) ** 3 * esz
-    per_solve = {
-        "fwd_x": cells * esz + X,
-        "fwd_y": X + Cb,
-        "zpass": 2 * Cb + H,
-        "inv_y": Cb + X,
-        "inv_x": X + cells * esz,
-    }
+    if form == 3:
+        per_solve = {"fwd_x": cells * esz + Cb, "fwd_y": 0, "zpass": 2 * Cb + H,
+                     "inv_y": Cb + cells * esz, "inv_x": 0}
+    else:
+        per_solve = {
+            "fwd_x": cells * esz + X,
+            "fwd_y": X + Cb,
+            "zpass": 2 * Cb + H,
+            "inv_y": Cb + X,
+            "inv_x": X + cells * esz,
+        }
     if phase in per_solve:
         return per_solve[phase] * nsolves
     grids = nsolves * cells * esz
@@ -63,6 +69,16 @@ def phase_bytes(phase, N, nsolves, n_live, esz):
     if phase == "force":    # x, v, gal, lost read; x, v written; fields read once
         return n_live * (12 * esz + 2) + grids
     return 0
+
+
+def fft_form(report, esz, N, count):
+    """The form (3 or 5) the tuner chose for count solves of N^3 grids, from
+    the tuning report of the library (5 when the mix was never planned)."""
+    tag = f"{'fp64' if esz == 8 else 'fp32'} N={N} x{count} form="
+    for line in report.splitlines():
+        if line.startswith(tag):
+            return int(line[len(tag):].split()[0])
+    return 5
 
 
 KERNEL_SOURCES = ["paper_1210_1736_amd/csrc/particles.hip", "paper_1210_1736_amd/csrc/particles.h",
@@ -515,8 +531,9 @@ def main():
         for batch in (5, 20):
             rate, ms = time_solves(sbx, torch, 128, 4.0, 0.25, prec, batch, args.solve_iters)
             esz = 8 if prec == sbx.SBX_FP64 else 4
-            model = sum(phase_bytes(ph, 128, 1, 0, esz) for ph in FFT_PASSES)
-            solves[f"{name}_batch{batch}"] = {"solves_per_s": rate, "ms_per_batch": ms,
+            form = fft_form(sbx.sbx_fft_tuning_report(), esz, 128, batch)
+            model = sum(phase_bytes(ph, 128, 1, 0, esz, form) for ph in FFT_PASSES)
+            solves[f"{name}_batch{batch}"] = {"solves_per_s": rate, "ms_per_batch": ms, "form": form,
                                              "model_bytes_per_solve": model,
                                              "frac_of_hbm_peak": rate * model / 1e9 / HBM_PEAK_GBS}
     torch.cuda.synchronize()
@@ -545,12 +562,13 @@ def main():
     dom = max(per_step, key=per_step.get)
     launches = ph32[dom][1]
     avg_ms = ph32[dom][0] / launches
-    by = phase_bytes(dom, N, nsolves, live32, 4)
+    step_form = fft_form(sbx.sbx_fft_tuning_report(), 4, N, nsolves)
+    by = phase_bytes(dom, N, nsolves, live32, 4, step_form)
     achieved = by / (avg_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
             "bytes_per_launch": by, "avg_launch_ms": avg_ms}
-    step_bytes = sum(phase_bytes(k, N, nsolves, live32, 4) for k in per_step)
+    step_bytes = sum(phase_bytes(k, N, nsolves, live32, 4, step_form) for k in per_step)
     step_roof = step_bytes / (t32 / steps) / 1e9
 
     cpu = None
@@ -584,12 +602,13 @@ def main():
         **extra,
         "step_effective_GBs": step_roof,
         "step_frac_of_hbm_peak": step_roof / HBM_PEAK_GBS,
-        "solves_in_step_frac_of_hbm_peak": sum(phase_bytes(k, N, nsolves, live32, 4) for k in FFT_PASSES)
+        "solves_in_step_frac_of_hbm_peak": sum(phase_bytes(k, N, nsolves, live32, 4, step_form)
+                                               for k in FFT_PASSES)
         / (1e-3 * sum(per_step.get(k, 0.0) for k in FFT_PASSES)) / 1e9 / HBM_PEAK_GBS,
         "roofline": roof,
         "cpu_baseline": cpu,
-        # the launch shapes the tuner chose for the step's five 128^3 solves
-        # (block size, persistent grid, values per thread of a line)
+        # the form and launch shapes the tuner chose for the step's five
+        # 128^3 solves (block size, persistent grid, values per thread)
         "fft_tuning": [l for l in sbx.sbx_fft_tuning_report().splitlines()
                        if " N=128 x5 " in l],
     }

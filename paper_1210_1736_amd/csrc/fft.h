@@ -11,6 +11,12 @@
 //   inv_x : E[z][y][kx]    (kx <= N)    -> phi[z][y][x] (complex-to-real, keep x < N)
 // Every pass reads whole lines (contiguous); the transposes are done on the
 // write side, through LDS, in runs of at least 128 bytes.
+// Where a z plane's half spectrum fits in LDS (N <= 128 in FP32, N <= 64 in
+// FP64) the same solve can run in three passes: plane forward (x and y of
+// one plane in one block) -> P[z][kx][ky'] (in C; ky' = m for ky = 2m,
+// N + m for 2m + 1), the z pass on that layout -> D, plane inverse (inverse
+// y and x of one plane) -> phi.  The tuner times both forms and keeps the
+// faster per precision, grid size and solve count.
 // Zero halves of the padded inputs are never read, unused halves of the
 // outputs never written.  Hhat (real, even per axis) is stored on (N+1)^3.
 //
@@ -55,7 +61,9 @@ constexpr int kMaxGroups = 6;  // distinct grid sizes 8..256
 // Solves of one grid size inside a plan.
 struct SolveGroup {
   int first = 0, count = 0, N = 0;
-  const void* tw[kPasses] = {};      // twiddle table of line length 2N, per pass's schedule
+  int form = 5;                      // 5 line passes, or 3 plane-fused passes
+  const void* tw[kPasses] = {};      // twiddle table of each pass's lines (2N; N for the plane passes)
+  const void* twist = nullptr;       // plane form: exp(-2 pi i n / 2N), n < N
   PassShape shape[kPasses] = {};
 };
 
@@ -125,6 +133,10 @@ sbx_status run_solves_noalloc(const SolveDesc<T>* d_solves, int nsolves, int N, 
 // Pin the line schedule of plans tuned from now on to v values per thread
 // (16 or 32, where a line length has both; 0: time both).  Process-wide.
 sbx_status set_fft_schedule(int v);
+
+// Pin the form of plans tuned from now on: 3 (plane-fused passes, where a
+// plane fits in LDS), 5 (five line passes) or 0 (time both).  Process-wide.
+sbx_status set_fft_form(int f);
 
 // Whether launch shapes for this precision and mix of grid sizes are cached.
 bool tuning_cached(int esz, std::vector<int> mix);

@@ -300,7 +300,7 @@ struct TC {
   // round of lines; inv_x takes one round of complex lines, each two real
   // rows (2 W rows per tile); fwd_y and inv_y at least 128 bytes per run.
   static constexpr int W = PASS == 0   ? fitw2(mn(N, mx(2 * WT, WC)))
-                         : PASS == 2 ? mn(WT, L)
+                         : (PASS == 2 || PASS == 5) ? mn(WT, L)
                          : PASS == 4 ? mn(WT, N / 2)
                                      : fitw(mn(N, mx(WT, WC)));
   static constexpr int LINES = PASS == 0 ? W / 2 : W;  // lines held in LDS
@@ -316,7 +316,7 @@ __host__ __device__ constexpr int tiles_of(int pass) {
   constexpr int N = L / 2;
   return pass == 0 ? N * (N / TC<T, L, V, NT, 0>::W)
        : pass == 1 ? (N + 1) * (N / TC<T, L, V, NT, 1>::W)
-       : pass == 2 ? (N + 1) * (L / TC<T, L, V, NT, 2>::W)
+       : (pass == 2 || pass == 5) ? (N + 1) * (L / TC<T, L, V, NT, 2>::W)
        : pass == 3 ? N * ((N + TC<T, L, V, NT, 3>::W) / TC<T, L, V, NT, 3>::W)
                    : N * (N / (2 * TC<T, L, V, NT, 4>::W));
 }
@@ -422,7 +422,10 @@ __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T
 // zpass: tile = W consecutive ky at one kx, one line per TL threads; forward
 // z (input z < N) from global, times Hhat in registers, inverse z, keep
 // z < N; stored transposed as D[kx][z][ky] through LDS.
-template <typename T, int L, int V, int NT>
+// PLANE: the spectra of the plane-fused passes, P[z][kx][ky'] in and out
+// (ky' = m for ky = 2m, N + m for ky = 2m + 1): a tile's W lines are W
+// consecutive ky' at one kx, gathered along z through LDS in runs of W.
+template <typename T, int L, int V, int NT, bool PLANE>
 __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
   using K = TC<T, L, V, NT, 2>;
@@ -431,13 +434,29 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
   constexpr int RL = F::template R<NP - 1>, NBL = L / RL;
   const int tid = threadIdx.x, t = tid % TL, w = tid / TL;
   const int kx = tile / (L / W), ky0 = (tile % (L / W)) * W;
+  if constexpr (PLANE) {
+    const gp<const C2<T>> __restrict__ g = glb(d.C + (size_t)kx * L + ky0);
+    for (int i = tid; i < W * N; i += NT) {
+      const int z = i / W, ww = i - z * W;
+      const gp<const C2<T>> e = g + (size_t)z * (N + 1) * L + ww;
+      s[ww * P + pad(z)] = C2<T>{__builtin_nontemporal_load(&e->re), __builtin_nontemporal_load(&e->im)};
+    }
+    __syncthreads();
+  }
   if (w < W) {
-    const int ky = ky0 + w;
-    const gp<const C2<T>> __restrict__ g = glb(d.C + ((size_t)kx * L + ky) * N);
+    const int kyl = ky0 + w;
+    // the frequency of line w along y
+    const int ky = PLANE ? (kyl < N ? 2 * kyl : 2 * (kyl - N) + 1) : kyl;
     C2<T>* sl = s + w * P;
     C2<T> v[F::VPT];
+    if constexpr (PLANE) {
 #pragma unroll
-    for (int r = 0; r < F::VPT; ++r) v[r] = r < F::VPT / 2 ? C2<T>{__builtin_nontemporal_load(&g[t + r * TL].re), __builtin_nontemporal_load(&g[t + r * TL].im)} : C2<T>{(T)0, (T)0};
+      for (int r = 0; r < F::VPT; ++r) v[r] = r < F::VPT / 2 ? sl[pad(t + r * TL)] : C2<T>{(T)0, (T)0};
+    } else {
+      const gp<const C2<T>> __restrict__ g = glb(d.C + ((size_t)kx * L + ky) * N);
+#pragma unroll
+      for (int r = 0; r < F::VPT; ++r) v[r] = r < F::VPT / 2 ? C2<T>{__builtin_nontemporal_load(&g[t + r * TL].re), __builtin_nontemporal_load(&g[t + r * TL].im)} : C2<T>{(T)0, (T)0};
+    }
     if constexpr (NP > 1) {
       fwd_bfly<T, L, V, 0>(v, t, tw);
       scatter_out<T, L, V, 0>(sl, t, v);
@@ -468,10 +487,18 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
     for (int r = 0; r < F::VPT / 2; ++r) sl[pad(t + r * TL)] = v[r];
   }
   __syncthreads();
-  const gp<C2<T>> __restrict__ dst = glb(d.D + (size_t)kx * N * L + ky0);
-  for (int i = tid; i < W * N; i += NT) {
-    const int z = i / W, ww = i - z * W;
-    gst(dst + (size_t)z * L + ww, s[ww * P + pad(z)]);
+  if constexpr (PLANE) {
+    const gp<C2<T>> __restrict__ dst = glb(d.D + (size_t)kx * L + ky0);
+    for (int i = tid; i < W * N; i += NT) {
+      const int z = i / W, ww = i - z * W;
+      gst(dst + (size_t)z * (N + 1) * L + ww, s[ww * P + pad(z)]);
+    }
+  } else {
+    const gp<C2<T>> __restrict__ dst = glb(d.D + (size_t)kx * N * L + ky0);
+    for (int i = tid; i < W * N; i += NT) {
+      const int z = i / W, ww = i - z * W;
+      gst(dst + (size_t)z * L + ww, s[ww * P + pad(z)]);
+    }
   }
 }
 
@@ -556,12 +583,355 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
   }
 }
 
+// ------------------------------------------------- plane-fused passes ---
+// When a z plane's half spectrum fits in LDS (N <= 128 in FP32, N <= 64 in
+// FP64) the forward x and y transforms of one plane run in one block, and
+// so do the inverse y and x ones: a solve is three passes (plane forward,
+// z, plane inverse) instead of five, and the x-transformed planes never go
+// to memory.  A length-2N transform of N nonzero inputs is two length-N
+// transforms, F(2m) = DFT_N(f)(m) and F(2m+1) = DFT_N(f w^n)(m) with
+// w = exp(-2 pi i / 2N); the first N outputs of a length-2N inverse are
+// f(n) = IDFT_N(F(2m))(n) + w^-n IDFT_N(F(2m+1))(n).  So every exchange of
+// a line stays within the N slots of LDS the line occupies.
+// The plane's spectrum in LDS is column-major, slot(kx, y) = col(kx) +
+// pad(y) for kx < N; column 0 holds X(0) + i X(N), both real for a real
+// row.  Between the passes the spectra are P[z][kx][ky'] (kx <= N, in the
+// C and D buffers), ky' = m for ky = 2m and N + m for ky = 2m + 1.
+template <typename T>
+struct PadLine {  // one line of LDS in natural order, one pad per 16
+  C2<T>* b;
+  __device__ __forceinline__ C2<T> ld(int pos) const { return b[pad(pos)]; }
+  __device__ __forceinline__ void st(int pos, const C2<T>& x) const { b[pad(pos)] = x; }
+};
+// Start of column kx in the plane: pitch PC, and 8 more slots for every 16
+// columns, so that the lanes of a line that touch positions 16 apart along
+// a row (the first Stockham pass) fall in different LDS banks.
+__device__ __forceinline__ int pl_col(int kx, int pc) { return kx * pc + (kx >> 4) * 8; }
+
+template <typename T>
+struct StrLine {  // one row of the plane: position kx at column kx
+  C2<T>* b;
+  int s;
+  __device__ __forceinline__ C2<T> ld(int pos) const { return b[pl_col(pos, s)]; }
+  __device__ __forceinline__ void st(int pos, const C2<T>& x) const { b[pl_col(pos, s)] = x; }
+};
+
+template <typename T, int L, int V, int p, class S>
+__device__ __forceinline__ void gather_in_g(const S& s, int t, C2<T>* v) {
+  constexpr int R = Line<T, L, V>::template R<p>, BPT = Line<T, L, V>::VPT / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b * R + r] = s.ld(pos_in<T, L, V, p>(t + b * Line<T, L, V>::TL, r));
+}
+template <typename T, int L, int V, int p, class S>
+__device__ __forceinline__ void scatter_out_g(const S& s, int t, const C2<T>* v) {
+  constexpr int R = Line<T, L, V>::template R<p>, BPT = Line<T, L, V>::VPT / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r) s.st(pos_out<T, L, V, p>(t + b * Line<T, L, V>::TL, r), v[b * R + r]);
+}
+
+// Forward transform of a line (inputs in v at positions t + r TL, natural
+// order), the line's LDS slots as exchange space; outputs in v at the last
+// pass's natural positions, also stored to the slots when STORE.
+template <typename T, int L, int V, int PS, bool STORE, class S>
+__device__ __forceinline__ void fwd_from_g(const S& s, int t, C2<T>* v, const C2<T>* __restrict__ tw) {
+  constexpr int NP = Line<T, L, V>::NP;
+  fwd_bfly<T, L, V, PS>(v, t, tw);
+  if constexpr (PS + 1 < NP) {
+    scatter_out_g<T, L, V, PS>(s, t, v);
+    wave_sync();
+    gather_in_g<T, L, V, PS + 1>(s, t, v);
+    wave_sync();
+    fwd_from_g<T, L, V, PS + 1, STORE>(s, t, v, tw);
+  } else if constexpr (STORE) {
+    scatter_out_g<T, L, V, PS>(s, t, v);
+  }
+}
+
+template <typename T, int N>
+struct PL {
+  static constexpr int V = 16;                     // values per lane of a length-N line
+  static constexpr int TL = N / V;                 // lanes per line
+  static constexpr int NPL = Line<T, N, V>::NP;
+  static constexpr int RL = Line<T, N, V>::template R<NPL - 1>;
+  static constexpr int NB = N / RL;                // spacing of the last pass's outputs
+  static constexpr int PC = N + N / 16 + 1;        // column pitch
+  static constexpr int XP = 2 * N + (2 * N) / 16 + 1;
+  static constexpr int XL = N * PC + (N / 16) * 8;  // the plane (skewed columns)
+  static constexpr int LDS = XL + XP;              // and column 0's 2N spectrum
+  static constexpr bool fits = N >= 16 && N <= 128 && LDS * (int)sizeof(C2<T>) <= 160 * 1024;
+};
+
+// Output position of register b * RL + r after a length-N transform.
+template <typename T, int N>
+__device__ __forceinline__ int pl_pos(int t, int b, int r) {
+  return t + b * PL<T, N>::TL + r * PL<T, N>::NB;
+}
+
+// Forward: plane z of solve item / N, rho -> P[z][kx][ky'].
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT)
+    k_plane_fwd(const SolveDesc<T>* __restrict__ solves, int* __restrict__ reset,
+                const C2<T>* __restrict__ tw, const C2<T>* __restrict__ twist) {
+  using G = PL<T, N>;
+  constexpr int V = G::V, TL = G::TL, PC = G::PC, RL = G::RL, L = 2 * N;
+  constexpr int GROUPS = NT / TL;
+  __shared__ C2<T> s[G::LDS];
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) *reset = 0;
+  const SolveDesc<T>& d = solves[blockIdx.x / N];
+  const int z = blockIdx.x % N;
+  const int tid = threadIdx.x, t = tid % TL, grp = tid / TL;
+  // x: rows 2j and 2j+1 as one complex line; task (j, h) takes the even
+  // (h = 0) or odd (h = 1) outputs, with row 2j + h as its exchange space
+  // and the place of its outputs
+  // every round's rows are loaded before the first transform: one round
+  // trip to memory per plane
+  constexpr int XR = (N + GROUPS - 1) / GROUPS;
+  C2<T> xv[XR][V];
+#pragma unroll
+  for (int u = 0; u < XR; ++u) {
+    const int task = grp + u * GROUPS;
+    if (task < N) {
+      const size_t row = ((size_t)z * N + 2 * (task >> 1)) * N;
+      const gp<const T> a = glb(d.rho + row), b = a + N;
+#pragma unroll
+      for (int r = 0; r < V; ++r)
+        xv[u][r] = C2<T>{__builtin_nontemporal_load(&a[t + r * TL]), __builtin_nontemporal_load(&b[t + r * TL])};
+    }
+  }
+  if (d.rho2) {  // summed grids: the second source is added on the way in
+#pragma unroll
+    for (int u = 0; u < XR; ++u) {
+      const int task = grp + u * GROUPS;
+      if (task < N) {
+        const size_t row = ((size_t)z * N + 2 * (task >> 1)) * N;
+        const gp<const T> a2 = glb(d.rho2 + row), b2 = a2 + N;
+#pragma unroll
+        for (int r = 0; r < V; ++r) {
+          xv[u][r].re += __builtin_nontemporal_load(&a2[t + r * TL]);
+          xv[u][r].im += __builtin_nontemporal_load(&b2[t + r * TL]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < XR; ++u) {
+    const int task = grp + u * GROUPS;
+    if (task < N) {
+      const int j = task >> 1, h = task & 1;
+      if (h) {
+#pragma unroll
+        for (int r = 0; r < V; ++r) xv[u][r] = cmul(xv[u][r], twist[t + r * TL]);
+      }
+      fwd_from_g<T, N, V, 0, true>(StrLine<T>{s + pad(2 * j + h), PC}, t, xv[u], tw);
+    }
+  }
+  __syncthreads();
+  // the two rows' spectra from Z = F(rows 2j + i 2j+1):
+  // X_a(k) = (Z(k) + conj Z(-k)) / 2, X_b(k) = -i (Z(k) - conj Z(-k)) / 2;
+  // Z(k) is in row 2j (k even) or 2j + 1 (k odd) at k / 2
+  auto zat = [&](int j, int k) -> C2<T> {
+    return s[pl_col(k >> 1, PC) + pad(2 * j + (k & 1))];
+  };
+  constexpr int SEP = (N * N / 2 + NT - 1) / NT;
+  C2<T> zk[SEP], zm[SEP];
+#pragma unroll
+  for (int q = 0; q < SEP; ++q) {
+    const int i = tid + q * NT;
+    if (i < N * N / 2) {
+      const int j = i / N, kx = i - j * N;
+      zk[q] = zat(j, kx);
+      zm[q] = zat(j, kx == 0 ? N : L - kx);
+    }
+  }
+  __syncthreads();
+  const T hf = (T)0.5;
+#pragma unroll
+  for (int q = 0; q < SEP; ++q) {
+    const int i = tid + q * NT;
+    if (i < N * N / 2) {
+      const int j = i / N, kx = i - j * N;
+      const C2<T> Z = zk[q], R = zm[q];
+      C2<T>* ca = s + pl_col(kx, PC) + pad(2 * j);
+      C2<T>* cb = s + pl_col(kx, PC) + pad(2 * j + 1);
+      if (kx == 0) {  // X(0) and X(N) of both rows, real: packed
+        *ca = C2<T>{Z.re, R.re};
+        *cb = C2<T>{Z.im, R.im};
+      } else {
+        *ca = C2<T>{(Z.re + R.re) * hf, (Z.im - R.im) * hf};
+        *cb = C2<T>{(Z.im + R.im) * hf, (R.re - Z.re) * hf};
+      }
+    }
+  }
+  __syncthreads();
+  // y: column kx (zero-padded to 2N) -> even and odd frequencies; column 0
+  // (X(0) + i X(N)) is separated by symmetry through the extra line
+  C2<T>* const xl = s + G::XL;
+#pragma unroll 1
+  for (int kx = grp; kx < N; kx += GROUPS) {
+    C2<T>* col = s + pl_col(kx, PC);
+    C2<T> u[V], v[V];
+#pragma unroll
+    for (int r = 0; r < V; ++r) {
+      u[r] = col[pad(t + r * TL)];
+      v[r] = u[r];
+    }
+    wave_sync();
+    const gp<C2<T>> out = glb(d.C + ((size_t)z * (N + 1) + kx) * L);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h) {
+#pragma unroll
+        for (int r = 0; r < V; ++r) v[r] = cmul(u[r], twist[t + r * TL]);
+        wave_sync();
+      }
+      fwd_from_g<T, N, V, 0, false>(PadLine<T>{col}, t, v, tw);
+#pragma unroll
+      for (int b = 0; b < V / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const int m = h * N + pl_pos<T, N>(t, b, r);
+          if (kx == 0) xl[pad(m)] = v[b * RL + r];
+          else gst(out + m, v[b * RL + r]);
+        }
+    }
+    if (kx == 0) {
+      wave_sync();
+      const gp<C2<T>> o0 = glb(d.C + (size_t)z * (N + 1) * L), oN = o0 + (size_t)N * L;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < V; ++r) {
+          const int m = t + r * TL;
+          // mirror -ky (mod 2N) of ky = 2m + h
+          const int mm = h ? N - 1 - m : (N - m) & (N - 1);
+          const C2<T> A = xl[pad(h * N + m)], B = xl[pad(h * N + mm)];
+          gst(o0 + h * N + m, C2<T>{(A.re + B.re) * hf, (A.im - B.im) * hf});
+          gst(oN + h * N + m, C2<T>{(A.im + B.im) * hf, (B.re - A.re) * hf});
+        }
+    }
+  }
+}
+
+// Inverse: P[z][kx][ky'] (the z pass's output, D) -> phi plane z (x, y < N).
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT)
+    k_plane_inv(const SolveDesc<T>* __restrict__ solves, int* __restrict__ reset,
+                const C2<T>* __restrict__ tw, const C2<T>* __restrict__ twist) {
+  using G = PL<T, N>;
+  constexpr int V = G::V, TL = G::TL, PC = G::PC, RL = G::RL, L = 2 * N;
+  constexpr int GROUPS = NT / TL;
+  __shared__ C2<T> s[G::LDS];
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) *reset = 0;
+  const SolveDesc<T>& d = solves[blockIdx.x / N];
+  const int z = blockIdx.x % N;
+  const int tid = threadIdx.x, t = tid % TL, grp = tid / TL;
+  // y: column kx from its even and odd frequencies (column 0 from
+  // Q(0) + i Q(N), whose inverse is X(0) + i X(N)); inverse transforms as
+  // conj(F(conj .)), unnormalised
+#pragma unroll 1
+  for (int kx = grp; kx < N; kx += GROUPS) {
+    C2<T>* col = s + pl_col(kx, PC);
+    const gp<const C2<T>> q = glb(d.D + ((size_t)z * (N + 1) + kx) * L);
+    const gp<const C2<T>> qn = glb(d.D + ((size_t)z * (N + 1) + N) * L);
+    // both halves are loaded before the first transform (one round trip)
+    C2<T> a[V], v[V];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        const int m = h * N + t + r * TL;
+        C2<T> e{__builtin_nontemporal_load(&q[m].re), __builtin_nontemporal_load(&q[m].im)};
+        if (kx == 0) {
+          const C2<T> f{__builtin_nontemporal_load(&qn[m].re), __builtin_nontemporal_load(&qn[m].im)};
+          e = C2<T>{e.re - f.im, e.im + f.re};
+        }
+        (h ? a : v)[r] = conjc(e);
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h) {
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const C2<T> e = a[i];
+          a[i] = conjc(v[i]);
+          v[i] = e;
+        }
+      }
+      fwd_from_g<T, N, V, 0, false>(PadLine<T>{col}, t, v, tw);
+    }
+    wave_sync();
+#pragma unroll
+    for (int b = 0; b < V / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int y = pl_pos<T, N>(t, b, r), i = b * RL + r;
+        col[pad(y)] = a[i] + cmul(conjc(twist[y]), conjc(v[i]));
+      }
+  }
+  __syncthreads();
+  // x: rows 2j, 2j+1 as Z = X_a + i X_b, extended to 2N by Hermitian
+  // symmetry; task (j, h) gathers Z(2m + h) and transforms it, rows 2j + h
+  // as exchange space and output place
+  auto xat = [&](int y, int k) -> C2<T> {  // X(k) of row y, 0 <= k <= N
+    const C2<T> c = s[pl_col(k == N ? 0 : k, PC) + pad(y)];
+    return k == 0 ? C2<T>{c.re, (T)0} : (k == N ? C2<T>{c.im, (T)0} : c);
+  };
+  constexpr int XR = (N + GROUPS - 1) / GROUPS;
+  C2<T> v[XR][V];
+#pragma unroll
+  for (int u = 0; u < XR; ++u) {
+    const int task = grp + u * GROUPS;
+    if (task < N) {
+      const int j = task >> 1, h = task & 1;
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        const int k = 2 * (t + r * TL) + h;
+        C2<T> zz;
+        if (k <= N) {
+          const C2<T> A = xat(2 * j, k), B = xat(2 * j + 1, k);
+          zz = C2<T>{A.re - B.im, A.im + B.re};
+        } else {
+          const C2<T> A = xat(2 * j, L - k), B = xat(2 * j + 1, L - k);
+          zz = C2<T>{A.re + B.im, B.re - A.im};
+        }
+        v[u][r] = conjc(zz);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < XR; ++u) {
+    const int task = grp + u * GROUPS;
+    if (task < N) {
+      const int j = task >> 1, h = task & 1;
+      fwd_from_g<T, N, V, 0, true>(StrLine<T>{s + pad(2 * j + h), PC}, t, v[u], tw);
+    }
+  }
+  __syncthreads();
+  // z(n) = IDFT(even)(n) + w^-n IDFT(odd)(n): real part row 2j, imaginary
+  // part row 2j + 1
+  const gp<T> ph = glb(d.phi + (size_t)z * N * N);
+  for (int i = tid; i < N * N / 2; i += NT) {
+    const int j = i / N, n = i - j * N;
+    const C2<T> A = conjc(s[pl_col(n, PC) + pad(2 * j)]), B = conjc(s[pl_col(n, PC) + pad(2 * j + 1)]);
+    const C2<T> zz = A + cmul(conjc(twist[n]), B);
+    ph[(size_t)(2 * j) * N + n] = zz.re;
+    ph[(size_t)(2 * j + 1) * N + n] = zz.im;
+  }
+}
+
 template <typename T, int L, int V, int NT, int PASS>
 __device__ __forceinline__ void run_tile(const SolveDesc<T>& d, int tile, C2<T>* s,
                                          const C2<T>* __restrict__ tw) {
   if constexpr (PASS == 0) tile_fwd_x<T, L, V, NT>(d, tile, s, tw);
   else if constexpr (PASS == 1) tile_fwd_y<T, L, V, NT>(d, tile, s, tw);
-  else if constexpr (PASS == 2) tile_zpass<T, L, V, NT>(d, tile, s, tw);
+  else if constexpr (PASS == 2) tile_zpass<T, L, V, NT, false>(d, tile, s, tw);
+  else if constexpr (PASS == 5) tile_zpass<T, L, V, NT, true>(d, tile, s, tw);
   else if constexpr (PASS == 3) tile_inv_y<T, L, V, NT>(d, tile, s, tw);
   else tile_inv_x<T, L, V, NT>(d, tile, s, tw);
 }
@@ -645,7 +1015,8 @@ static bool shape_ok(int nt, int v, int N, int pass) {
       switch (pass) {
         case 0: return shape_fits<T, L, V, NT, 0>();
         case 1: return shape_fits<T, L, V, NT, 1>();
-        case 2: return shape_fits<T, L, V, NT, 2>();
+        case 2:
+        case 5: return shape_fits<T, L, V, NT, 2>();
         case 3: return shape_fits<T, L, V, NT, 3>();
         default: return shape_fits<T, L, V, NT, 4>();
       }
@@ -677,12 +1048,91 @@ static void launch_any(int pass, const SolveDesc<T>* solves, int N, int nsolves,
     case 1: launch_pass<T, 1>(solves, N, nsolves, sh, counter, reset, tw, st); break;
     case 2: launch_pass<T, 2>(solves, N, nsolves, sh, counter, reset, tw, st); break;
     case 3: launch_pass<T, 3>(solves, N, nsolves, sh, counter, reset, tw, st); break;
+    case 5: launch_pass<T, 5>(solves, N, nsolves, sh, counter, reset, tw, st); break;
     default: launch_pass<T, 4>(solves, N, nsolves, sh, counter, reset, tw, st); break;
   }
 }
 
 __global__ void k_zero_int(int* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// w^n = exp(-2 pi i n / 2N), n < N: the twist between the even and odd
+// halves of a zero-padded length-2N transform (FP64, then rounded).
+template <typename T>
+__global__ void k_twist(C2<T>* w, int N) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double sn, cs;
+  sincospi((double)n / (double)N, &sn, &cs);
+  w[n] = C2<T>{(T)cs, (T)(-sn)};
+}
+
+// Twist tables, like the twiddle tables made once per (device, precision,
+// N) and kept; with create = false a missing one is not made.
+template <typename T>
+static const C2<T>* twist_table(int N, hipStream_t st, bool create = true) {
+  static std::mutex mu;
+  static C2<T>* cache[64][10] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  int lg = 0;
+  while ((1 << lg) < N) ++lg;
+  std::lock_guard<std::mutex> g(mu);
+  if (cache[dev][lg] || !create) return cache[dev][lg];
+  C2<T>* p = nullptr;
+  if (hipMalloc(&p, sizeof(C2<T>) * N) != hipSuccess) return nullptr;
+  hipLaunchKernelGGL(k_twist<T>, dim3((N + 255) / 256), dim3(256), 0, st, p, N);
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipFree(p);
+    return nullptr;
+  }
+  cache[dev][lg] = p;
+  return p;
+}
+
+// Whether the plane-fused form exists for this precision and size, and
+// for this block size.
+template <typename T>
+static bool plane_ok(int N) {
+  return (N == 16 && PL<T, 16>::fits) || (N == 32 && PL<T, 32>::fits) || (N == 64 && PL<T, 64>::fits) ||
+         (N == 128 && PL<T, 128>::fits);
+}
+template <typename T>
+static bool plane_nt_ok(int N, int nt) {
+  // FP64 at 1024 threads would leave too few registers per lane
+  return plane_ok<T>(N) && (nt == 256 || nt == 512 || (nt == 1024 && sizeof(T) == 4));
+}
+
+template <typename T, int N>
+static void launch_plane_n(bool inv, const SolveDesc<T>* solves, int nsolves, int nt, int* reset,
+                           const C2<T>* tw, const C2<T>* twist, hipStream_t st) {
+  if constexpr (PL<T, N>::fits) {
+    auto go = [&](auto ntc) {
+      constexpr int NT = decltype(ntc)::value;
+      if (inv)
+        hipLaunchKernelGGL((k_plane_inv<T, N, NT>), dim3(nsolves * N), dim3(NT), 0, st, solves, reset, tw,
+                           twist);
+      else
+        hipLaunchKernelGGL((k_plane_fwd<T, N, NT>), dim3(nsolves * N), dim3(NT), 0, st, solves, reset, tw,
+                           twist);
+    };
+    if (nt == 256) go(std::integral_constant<int, 256>());
+    else if constexpr (sizeof(T) == 8) go(std::integral_constant<int, 512>());
+    else if (nt == 512) go(std::integral_constant<int, 512>());
+    else go(std::integral_constant<int, 1024>());
+  }
+}
+
+template <typename T>
+static void launch_plane(bool inv, const SolveDesc<T>* solves, int N, int nsolves, int nt, int* reset,
+                         const C2<T>* tw, const C2<T>* twist, hipStream_t st) {
+  switch (N) {
+    case 16: launch_plane_n<T, 16>(inv, solves, nsolves, nt, reset, tw, twist, st); break;
+    case 32: launch_plane_n<T, 32>(inv, solves, nsolves, nt, reset, tw, twist, st); break;
+    case 64: launch_plane_n<T, 64>(inv, solves, nsolves, nt, reset, tw, twist, st); break;
+    default: launch_plane_n<T, 128>(inv, solves, nsolves, nt, reset, tw, twist, st); break;
+  }
 }
 
 // ---------------------------------------------------------- the autotuner --
@@ -696,15 +1146,36 @@ __global__ void k_zero_int(int* p, int n) {
 // the life of the process.
 struct TuneKey {
   int esz, N, count;
-  int pin = 0;  // the pinned line schedule when the key was tuned (0: none)
+  int pin = 0;   // the pinned line schedule when the key was tuned (0: none)
+  int fpin = 0;  // the pinned form (3 or 5 passes; 0: none)
   bool operator==(const TuneKey& o) const {
-    return esz == o.esz && N == o.N && count == o.count && pin == o.pin;
+    return esz == o.esz && N == o.N && count == o.count && pin == o.pin && fpin == o.fpin;
   }
+};
+
+// What the tuner chose: the form (5: the five line passes; 3: plane
+// forward, z pass on the plane layout, plane inverse, whose shapes are
+// sh[0], sh[2] and sh[3]) and the launch shape of each pass.
+struct Tuned {
+  std::array<PassShape, kPasses> sh;
+  int form = 5;
 };
 
 // Line schedule pinned for plans tuned from now on (0: the tuner times
 // every schedule a line length has).
 static std::atomic<int> g_pin_v{0};
+// Form pinned for plans tuned from now on (0: the tuner times both where
+// the plane form exists).
+static std::atomic<int> g_pin_form{0};
+
+sbx_status set_fft_form(int f) {
+  if (f != 0 && f != 3 && f != 5) {
+    set_error("FFT form must be 0 (tuned), 3 (plane-fused passes) or 5 (five line passes)");
+    return SBX_EINVAL;
+  }
+  g_pin_form.store(f);
+  return SBX_OK;
+}
 
 sbx_status set_fft_schedule(int v) {
   if (v != 0 && v != 16 && v != 32) {
@@ -716,9 +1187,13 @@ sbx_status set_fft_schedule(int v) {
 }
 
 static std::mutex g_tune_mu;
-static std::vector<std::pair<TuneKey, std::array<PassShape, kPasses>>> g_tune;
+static std::vector<std::pair<TuneKey, Tuned>> g_tune;
 
-static bool tune_lookup(const TuneKey& k, std::array<PassShape, kPasses>& out) {
+static TuneKey key_now(int esz, int N, int count) {
+  return TuneKey{esz, N, count, g_pin_v.load(), g_pin_form.load()};
+}
+
+static bool tune_lookup(const TuneKey& k, Tuned& out) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   for (auto& e : g_tune)
     if (e.first == k) {
@@ -732,16 +1207,22 @@ std::string tuning_report() {
   std::lock_guard<std::mutex> g(g_tune_mu);
   std::string out;
   static const char* names[kPasses] = {"fwd_x", "fwd_y", "zpass", "inv_y", "inv_x"};
-  for (auto& e : g_tune)
-    for (int p = 0; p < kPasses; ++p)
-      out += std::string(e.first.esz == 8 ? "fp64" : "fp32") + " N=" + std::to_string(e.first.N) +
-             " x" + std::to_string(e.first.count) + " " + names[p] + " nt=" +
-             std::to_string(e.second[p].nt) + " grid=" +
-             (e.second[p].grid <= 0 ? std::string("tiles") : std::to_string(e.second[p].grid)) +
-             " v=" +
-             std::to_string(e.first.esz == 8 ? eff_v<double>(2 * e.first.N, e.second[p].v)
-                                             : eff_v<float>(2 * e.first.N, e.second[p].v)) +
-             "\n";
+  static const char* pnames[kPasses] = {"plane_fwd", "", "zpass", "plane_inv", ""};
+  for (auto& e : g_tune) {
+    const bool pl = e.second.form == 3;
+    for (int p = 0; p < kPasses; ++p) {
+      if (pl && (p == 1 || p == 4)) continue;
+      const PassShape& sh = e.second.sh[p];
+      out += std::string(e.first.esz == 8 ? "fp64" : "fp32") + " N=" + std::to_string(e.first.N) + " x" +
+             std::to_string(e.first.count) + " form=" + std::to_string(e.second.form) + " " +
+             (pl ? pnames[p] : names[p]) + " nt=" + std::to_string(sh.nt);
+      if (!pl || p == 2)
+        out += " grid=" + (sh.grid <= 0 ? std::string("tiles") : std::to_string(sh.grid)) + " v=" +
+               std::to_string(e.first.esz == 8 ? eff_v<double>(2 * e.first.N, sh.v)
+                                               : eff_v<float>(2 * e.first.N, sh.v));
+      out += "\n";
+    }
+  }
   return out;
 }
 
@@ -757,8 +1238,8 @@ bool tuning_cached(int esz, std::vector<int> mix) {
   for (size_t i = 0; i < mix.size();) {
     size_t j = i;
     while (j < mix.size() && mix[j] == mix[i]) ++j;
-    std::array<PassShape, kPasses> a;
-    if (!tune_lookup(TuneKey{esz, mix[i], (int)(j - i), g_pin_v.load()}, a)) return false;
+    Tuned a;
+    if (!tune_lookup(key_now(esz, mix[i], (int)(j - i)), a)) return false;
     i = j;
   }
   return true;
@@ -766,10 +1247,13 @@ bool tuning_cached(int esz, std::vector<int> mix) {
 
 template <typename T>
 static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* host, int N, int count,
-                             int* counter, hipStream_t st, std::array<PassShape, kPasses>& out) {
+                             int* counter, hipStream_t st, Tuned& out) {
   const int cus = device_cus();
   const int nts[3] = {128, 256, 512};
   const int bpcs[4] = {2, 4, 8, 0};  // 0: one block per tile
+  const int fpin = g_pin_form.load();
+  const bool plane = plane_ok<T>(N) && fpin != 5;
+  const bool five = !plane || fpin != 3;
   // the schedules of this line length (one, or both 16 and 32)
   const int L = 2 * N;
   std::vector<int> vs{eff_v<T>(L, 0)};
@@ -785,6 +1269,12 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
       return SBX_ENOMEM;
     }
   }
+  const C2<T>* twh = plane ? twiddles<T>(N, 16, st) : nullptr;
+  const C2<T>* twist = plane ? twist_table<T>(N, st) : nullptr;
+  if (plane && (!twh || !twist)) {
+    set_error("twiddle table allocation failed");
+    return SBX_ENOMEM;
+  }
   for (int i = 0; i < count; ++i) {
     SBX_HIP(hipMemsetAsync((void*)host[i].rho, 0, sizeof(T) * (size_t)N * N * N, st));
     if (host[i].rho2)
@@ -796,34 +1286,72 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
   hipEvent_t e0, e1;
   SBX_HIP(hipEventCreate(&e0));
   SBX_HIP(hipEventCreate(&e1));
-  for (int pass = 0; pass < kPasses; ++pass) {
-    float best = 1e30f;
-    PassShape pick{256, 0, vs[0]};
-    for (size_t vi = 0; vi < vs.size(); ++vi) {
+  // fastest of 5 timed repetitions (after 2 untimed) of one launch
+  auto time_it = [&](auto&& launch, float& ms_min) -> sbx_status {
+    ms_min = 1e30f;
+    for (int rep = 0; rep < 7; ++rep) {
+      hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, 1);
+      SBX_HIP(hipEventRecord(e0, st));
+      launch();
+      SBX_HIP(hipEventRecord(e1, st));
+      SBX_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SBX_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep >= 2) ms_min = std::min(ms_min, ms);
+    }
+    return SBX_OK;
+  };
+  // best shape of one line pass (pass 5: the z pass on the plane layout)
+  auto tune_pass = [&](int pass, PassShape& pick, float& best) -> sbx_status {
+    best = 1e30f;
+    pick = PassShape{256, 0, vs[0]};
+    for (size_t vi = 0; vi < vs.size(); ++vi)
       for (int nt : nts) {
         if (!shape_ok<T>(nt, vs[vi], N, pass)) continue;
         for (int bpc : bpcs) {
           const PassShape sh{nt, bpc == 0 ? 0 : cus * bpc, vs[vi]};
-          float ms_min = 1e30f;
-          for (int rep = 0; rep < 7; ++rep) {
-            hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, 1);
-            SBX_HIP(hipEventRecord(e0, st));
-            launch_any<T>(pass, d_solves, N, count, sh, counter, nullptr, tws[vi], st);
-            SBX_HIP(hipEventRecord(e1, st));
-            SBX_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            SBX_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (rep >= 2) ms_min = std::min(ms_min, ms);
-          }
-          if (ms_min < best) {
-            best = ms_min;
+          float ms = 0.f;
+          SBX_TRY(time_it([&] { launch_any<T>(pass, d_solves, N, count, sh, counter, nullptr, tws[vi], st); },
+                          ms));
+          if (ms < best) {
+            best = ms;
             pick = sh;
           }
         }
       }
+    return SBX_OK;
+  };
+  float t5 = 0.f, t3 = 1e30f;
+  Tuned five_t, plane_t;
+  if (five)
+    for (int pass = 0; pass < kPasses; ++pass) {
+      float b = 0.f;
+      SBX_TRY(tune_pass(pass, five_t.sh[pass], b));
+      t5 += b;
     }
-    out[pass] = pick;
+  if (plane) {
+    plane_t.form = 3;
+    float tz = 0.f;
+    SBX_TRY(tune_pass(5, plane_t.sh[2], tz));
+    t3 = tz;
+    for (int q : {0, 3}) {
+      float best = 1e30f;
+      PassShape pick{256, 0, 0};
+      for (int nt : {256, 512, 1024}) {
+        if (!plane_nt_ok<T>(N, nt)) continue;
+        float ms = 0.f;
+        SBX_TRY(time_it([&] { launch_plane<T>(q == 3, d_solves, N, count, nt, nullptr, twh, twist, st); }, ms));
+        if (ms < best) {
+          best = ms;
+          pick = PassShape{nt, 0, 0};
+        }
+      }
+      plane_t.sh[q] = pick;
+      t3 += best;
+    }
+    plane_t.sh[1] = plane_t.sh[4] = PassShape{0, 0, 0};
   }
+  out = (plane && (!five || t3 < t5)) ? plane_t : five_t;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return SBX_OK;
@@ -881,22 +1409,32 @@ sbx_status plan_create(SolvePlan<T>& p, const SolveDesc<T>* descs, int n, hipStr
   }
   for (int gi = 0; gi < p.ngroups; ++gi) {
     SolveGroup& g = p.groups[gi];
-    std::array<PassShape, kPasses> a;
-    const TuneKey key{(int)sizeof(T), g.N, g.count, g_pin_v.load()};
+    Tuned a;
+    const TuneKey key = key_now((int)sizeof(T), g.N, g.count);
     if (!tune_lookup(key, a)) {
       SBX_TRY(tune_group<T>(p.d_solves + g.first, p.host.data() + g.first, g.N, g.count,
                             p.d_counter, st, a));
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune.push_back({key, a});
     }
+    g.form = a.form;
     for (int q = 0; q < kPasses; ++q) {
-      g.shape[q] = a[q];
-      const C2<T>* tw = twiddles<T>(2 * g.N, a[q].v, st);
+      g.shape[q] = a.sh[q];
+      g.tw[q] = nullptr;
+      if (g.form == 3 && (q == 1 || q == 4)) continue;
+      // the plane passes transform lines of N (16 values per lane)
+      const bool pq = g.form == 3 && q != 2;
+      const C2<T>* tw = pq ? twiddles<T>(g.N, 16, st) : twiddles<T>(2 * g.N, a.sh[q].v, st);
       if (!tw) {
         set_error("twiddle table allocation failed");
         return SBX_ENOMEM;
       }
       g.tw[q] = (const void*)tw;
+    }
+    g.twist = nullptr;
+    if (g.form == 3 && !(g.twist = (const void*)twist_table<T>(g.N, st))) {
+      set_error("twiddle table allocation failed");
+      return SBX_ENOMEM;
     }
   }
   // work counters start at zero; every pass then clears its predecessor's
@@ -905,13 +1443,27 @@ sbx_status plan_create(SolvePlan<T>& p, const SolveDesc<T>* descs, int n, hipStr
   return SBX_OK;
 }
 
+// One pass of a group in either form.  Plane form: pass 0 is the plane
+// forward, 2 the z pass on the plane layout, 3 the plane inverse; 1 and 4
+// launch nothing.  Each launch clears the work counter of the pass before.
+template <typename T>
+static void run_pass(int form, int q, const SolveDesc<T>* solves, int N, int count, const PassShape& sh,
+                     int* ctr, int* prev, const C2<T>* tw, const C2<T>* twist, hipStream_t st) {
+  if (form != 3) {
+    launch_any<T>(q, solves, N, count, sh, ctr, prev, tw, st);
+  } else if (q == 0 || q == 3) {
+    launch_plane<T>(q == 3, solves, N, count, sh.nt, prev, tw, twist, st);
+  } else if (q == 2) {
+    launch_any<T>(5, solves, N, count, sh, ctr, prev, tw, st);
+  }
+}
+
 template <typename T>
 sbx_status plan_run_pass(const SolvePlan<T>& p, int q, int group, hipStream_t st) {
   const SolveGroup& g = p.groups[group];
-  launch_any<T>(q, p.d_solves + g.first, g.N, g.count, g.shape[q],
-                p.d_counter + q * kMaxGroups + group,
-                p.d_counter + ((q + kPasses - 1) % kPasses) * kMaxGroups + group, (const C2<T>*)g.tw[q],
-                st);
+  run_pass<T>(g.form, q, p.d_solves + g.first, g.N, g.count, g.shape[q], p.d_counter + q * kMaxGroups + group,
+              p.d_counter + ((q + kPasses - 1) % kPasses) * kMaxGroups + group, (const C2<T>*)g.tw[q],
+              (const C2<T>*)g.twist, st);
   return SBX_OK;
 }
 
@@ -950,26 +1502,32 @@ sbx_status prepare_twiddles(int N, hipStream_t st) {
       set_error("twiddle table allocation failed");
       return SBX_ENOMEM;
     }
+  if (plane_ok<T>(N) && (!twiddles<T>(N, 16, st) || !twist_table<T>(N, st))) {
+    set_error("twiddle table allocation failed");
+    return SBX_ENOMEM;
+  }
   return SBX_OK;
 }
 
 template <typename T>
 sbx_status run_solves_noalloc(const SolveDesc<T>* d_solves, int nsolves, int N, int* d_counter,
                               hipStream_t st) {
-  std::array<PassShape, kPasses> a;
-  if (!tune_lookup(TuneKey{(int)sizeof(T), N, nsolves, g_pin_v.load()}, a))
-    for (auto& sh : a) sh = PassShape{256, 0, 0};
-  const C2<T>* tw[kPasses];
+  Tuned a;
+  if (!tune_lookup(key_now((int)sizeof(T), N, nsolves), a))
+    for (auto& sh : a.sh) sh = PassShape{256, 0, 0};
+  const C2<T>* tw[kPasses] = {};
+  const C2<T>* twist = a.form == 3 ? twist_table<T>(N, st, false) : nullptr;
   for (int q = 0; q < kPasses; ++q) {
-    tw[q] = twiddles<T>(2 * N, a[q].v, st, false);
-    if (!tw[q]) {
+    if (a.form == 3 && (q == 1 || q == 4)) continue;
+    tw[q] = (a.form == 3 && q != 2) ? twiddles<T>(N, 16, st, false) : twiddles<T>(2 * N, a.sh[q].v, st, false);
+    if (!tw[q] || (a.form == 3 && !twist)) {
       set_error("no twiddle table for this grid size on this device (create a plan first)");
       return SBX_ESTATE;
     }
   }
   for (int q = 0; q < kPasses; ++q)
-    launch_any<T>(q, d_solves, N, nsolves, a[q], d_counter + q, d_counter + (q + kPasses - 1) % kPasses,
-                  tw[q], st);
+    run_pass<T>(a.form, q, d_solves, N, nsolves, a.sh[q], d_counter + q, d_counter + (q + kPasses - 1) % kPasses,
+                tw[q], twist, st);
   SBX_HIP(hipGetLastError());
   return SBX_OK;
 }

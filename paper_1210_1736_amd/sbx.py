@@ -128,6 +128,7 @@ def _load():
         "sbx_poisson_green": (S, [P, P, dp]),
         "sbx_poisson_bytes": (I64, [P]),
         "sbx_set_fft_schedule": (S, [I32]),
+        "sbx_set_fft_form": (S, [I32]),
         "sbx_fft_tuning_report": (I64, [C.c_char_p, I64]),
     }
     for name, (res, args) in sig.items():
@@ -190,6 +191,13 @@ def sbx_set_fft_schedule(values_per_thread):
     """Pin the FFT line schedule (16 or 32 values per thread) for plans made
     from now on; 0 lets the launch-shape tuner choose."""
     _check(_lib.sbx_set_fft_schedule(int(values_per_thread)))
+
+
+def sbx_set_fft_form(form):
+    """Pin the form of the solves for plans made from now on: 3 plane-fused
+    passes (where a plane fits in LDS), 5 line passes, 0 the tuner's
+    choice."""
+    _check(_lib.sbx_set_fft_form(int(form)))
 
 
 def sbx_fft_tuning_report() -> str:

@@ -67,3 +67,15 @@ def test_fft_schedule_pin_host_only():
         with pytest.raises(sbx.SbxError):
             sbx.sbx_set_fft_schedule(bad)
     sbx.sbx_set_fft_schedule(0)
+
+
+def test_fft_form_pin_host_only():
+    """sbx_set_fft_form takes 0, 3 or 5 and rejects anything else (host
+    state only: no device call)."""
+    from paper_1210_1736_amd import sbx
+    for f in (3, 5, 0):
+        sbx.sbx_set_fft_form(f)
+    for bad in (-1, 1, 4, 6):
+        with pytest.raises(sbx.SbxError):
+            sbx.sbx_set_fft_form(bad)
+    sbx.sbx_set_fft_form(0)

@@ -99,3 +99,23 @@ def test_cpu_threads_respects_budget(monkeypatch):
     assert bench.cpu_threads() == 3
     monkeypatch.delenv("OMP_NUM_THREADS")
     assert 1 <= bench.cpu_threads() <= 16
+
+
+def test_plane_form_bytes_and_form_parsing():
+    """The plane-fused form's algorithmic bytes (no x-transformed planes in
+    memory) and the form read from a tuning report."""
+    import bench
+    N, S, esz = 128, 5, 4
+    cells = N ** 3
+    C = (N + 1) * 2 * N * N * 8
+    X = (N + 1) * N * N * 8
+    H = (N + 1) ** 3 * esz
+    three = sum(bench.phase_bytes(p, N, S, 0, esz, 3) for p in bench.FFT_PASSES)
+    five = sum(bench.phase_bytes(p, N, S, 0, esz, 5) for p in bench.FFT_PASSES)
+    assert three == S * (2 * cells * esz + 4 * C + H)
+    assert five - three == S * 4 * X
+    rep = ("fp32 N=128 x5 form=3 plane_fwd nt=1024\nfp32 N=128 x5 form=3 zpass nt=256 grid=tiles v=16\n"
+           "fp64 N=128 x5 form=5 fwd_x nt=256 grid=tiles v=16\n")
+    assert bench.fft_form(rep, 4, 128, 5) == 3
+    assert bench.fft_form(rep, 8, 128, 5) == 5
+    assert bench.fft_form(rep, 4, 64, 5) == 5

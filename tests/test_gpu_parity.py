@@ -145,6 +145,71 @@ def test_fft_schedules_match_oracle(sbx, torch, v, N, q):
         assert np.max(np.abs(g - ref)) <= 3e-6 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("form", [3, 5])
+@pytest.mark.parametrize("N,q,prec", [(16, 1.0, 1), (32, 0.25, 0), (32, 0.25, 1), (64, 0.5, 0),
+                                      (64, 0.5, 1), (128, 0.25, 0), (128, 0.25, 1)])
+def test_fft_forms_match_oracle(sbx, torch, form, N, q, prec):
+    """Each form of the solve pinned in turn: three plane-fused passes (x
+    and y of one plane in LDS; even and odd frequencies of each padded line
+    as two half-length transforms) or five line passes, against the oracle's
+    FFT convolution (Eqs. 3-5), three solves per batch.  FP64 at N = 128 has
+    no plane form (its plane does not fit in LDS) and runs five passes under
+    either pin."""
+    rng = _rng(3000 + N + form + 10 * prec)
+    R = 2.0
+    Ms = []
+    for b in range(3):
+        M = np.zeros((N, N, N))
+        cells = rng.integers(0, N, size=(max(50, N * N // 4), 3))
+        np.add.at(M, tuple(cells.T), rng.uniform(0.1, 1.0, cells.shape[0]))
+        Ms.append(T.rounded(M, prec))
+    sbx.sbx_set_fft_form(form)
+    try:
+        got = _solve_gpu(sbx, torch, N, R, q, Ms, prec, G=0.7)
+        rep = sbx.sbx_fft_tuning_report()
+    finally:
+        sbx.sbx_set_fft_form(0)
+    want = form if (prec == sbx.SBX_FP32 or N <= 64) else 5
+    esz = "fp64" if prec == sbx.SBX_FP64 else "fp32"
+    assert f"{esz} N={N} x3 form={want} " in rep
+    Hh, _ = O.green_hat(O.Level(N, R, q))
+    tol = 1e-11 if prec == sbx.SBX_FP64 else 3e-6
+    for M, g in zip(Ms, got):
+        ref = O.solve_fft(M, Hh, G=0.7)
+        assert np.max(np.abs(g - ref)) <= tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_plane_form_in_the_step(sbx, prec):
+    """The galaxy's fields and forces with the plane-fused form pinned (its
+    summed grids 2+3 and 4+5 add their second mass grid in the plane
+    forward pass) against the oracle, to the bars of the five-pass form."""
+    w = T.small_galaxy(scale=0.005, N=64, q=0.5)
+    sysm, x, v, m, lost, centres, pots = _state_oracle(w, prec)
+    sbx.sbx_set_fft_form(3)
+    try:
+        ctx = T.make_ctx(w, prec)
+        acc, pot = ctx.sbx_compute_forces()
+        rep = sbx.sbx_fft_tuning_report()
+    finally:
+        sbx.sbx_set_fft_form(0)
+    assert ("fp64" if prec == sbx.SBX_FP64 else "fp32") + " N=64 x5 form=3 plane_fwd" in rep
+    cg = ctx.sbx_get_centres()
+    cls_ref, idx_ref = O.classify(x, sysm.h[0], cg[0])
+    pots = sysm.potentials(x, m, w.gal, lost, cg)
+    ftol = 1e-11 if prec == sbx.SBX_FP64 else 3e-6
+    for k, ref in enumerate(_slots(pots[0]["Phi"])):
+        g = ctx.sbx_get_grid(0, k, 1).transpose(2, 1, 0)
+        assert np.max(np.abs(g - ref)) <= ftol * np.max(np.abs(ref)), k
+    a_ref, P_ref = sysm.accel(x, m, w.gal, lost, cg, pots, want_pot=True)
+    e = T.rel_err_vec(acc, a_ref)
+    if prec == sbx.SBX_FP64:
+        assert e.max() < 1e-9
+    else:
+        assert np.percentile(e, 99) < 1e-4 and e.max() < 1e-3
+    ctx.close()
+
+
 @pytest.mark.parametrize("v", [16, 32])
 def test_fft_schedules_max_size_sampled(sbx, torch, v):
     """N = 256 (512-point lines) with each schedule pinned: sampled cells
