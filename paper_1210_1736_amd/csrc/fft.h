@@ -11,7 +11,7 @@
 //   inv_x : E[z][y][kx]    (kx <= N)    -> phi[z][y][x] (complex-to-real, keep x < N)
 // Every pass reads whole lines (contiguous); the transposes are done on the
 // write side, through LDS, in runs of at least 128 bytes.
-// Where a z plane's half spectrum fits in LDS (N <= 128 in FP32, N <= 64 in
+// Where a z plane's half spectrum fits in LDS (32 <= N <= 128 in FP32, N <= 64 in
 // FP64) the same solve can run in three passes: plane forward (x and y of
 // one plane in one block) -> P[z][kx][ky'] (in C; ky' = m for ky = 2m,
 // N + m for 2m + 1), the z pass on that layout -> D, plane inverse (inverse

@@ -422,9 +422,10 @@ __device__ __forceinline__ void tile_fwd_y(const SolveDesc<T>& d, int tile, C2<T
 // zpass: tile = W consecutive ky at one kx, one line per TL threads; forward
 // z (input z < N) from global, times Hhat in registers, inverse z, keep
 // z < N; stored transposed as D[kx][z][ky] through LDS.
-// PLANE: the spectra of the plane-fused passes, P[z][kx][ky'] in and out
+// PLANE: the spectra of the plane-fused passes, P[kx][z][ky'] in and out
 // (ky' = m for ky = 2m, N + m for ky = 2m + 1): a tile's W lines are W
-// consecutive ky' at one kx, gathered along z through LDS in runs of W.
+// consecutive ky' at one kx, gathered along z through LDS in runs of W
+// from one kx slab.
 template <typename T, int L, int V, int NT, bool PLANE>
 __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T>* s,
                                            const C2<T>* __restrict__ tw) {
@@ -435,10 +436,10 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
   const int tid = threadIdx.x, t = tid % TL, w = tid / TL;
   const int kx = tile / (L / W), ky0 = (tile % (L / W)) * W;
   if constexpr (PLANE) {
-    const gp<const C2<T>> __restrict__ g = glb(d.C + (size_t)kx * L + ky0);
+    const gp<const C2<T>> __restrict__ g = glb(d.C + (size_t)kx * N * L + ky0);
     for (int i = tid; i < W * N; i += NT) {
       const int z = i / W, ww = i - z * W;
-      const gp<const C2<T>> e = g + (size_t)z * (N + 1) * L + ww;
+      const gp<const C2<T>> e = g + (size_t)z * L + ww;
       s[ww * P + pad(z)] = C2<T>{__builtin_nontemporal_load(&e->re), __builtin_nontemporal_load(&e->im)};
     }
     __syncthreads();
@@ -488,10 +489,10 @@ __device__ __forceinline__ void tile_zpass(const SolveDesc<T>& d, int tile, C2<T
   }
   __syncthreads();
   if constexpr (PLANE) {
-    const gp<C2<T>> __restrict__ dst = glb(d.D + (size_t)kx * L + ky0);
+    const gp<C2<T>> __restrict__ dst = glb(d.D + (size_t)kx * N * L + ky0);
     for (int i = tid; i < W * N; i += NT) {
       const int z = i / W, ww = i - z * W;
-      gst(dst + (size_t)z * (N + 1) * L + ww, s[ww * P + pad(z)]);
+      gst(dst + (size_t)z * L + ww, s[ww * P + pad(z)]);
     }
   } else {
     const gp<C2<T>> __restrict__ dst = glb(d.D + (size_t)kx * N * L + ky0);
@@ -584,7 +585,7 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
 }
 
 // ------------------------------------------------- plane-fused passes ---
-// When a z plane's half spectrum fits in LDS (N <= 128 in FP32, N <= 64 in
+// When a z plane's half spectrum fits in LDS (32 <= N <= 128 in FP32, N <= 64 in
 // FP64) the forward x and y transforms of one plane run in one block, and
 // so do the inverse y and x ones: a solve is three passes (plane forward,
 // z, plane inverse) instead of five, and the x-transformed planes never go
@@ -595,8 +596,9 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
 // a line stays within the N slots of LDS the line occupies.
 // The plane's spectrum in LDS is column-major, slot(kx, y) = col(kx) +
 // pad(y) for kx < N; column 0 holds X(0) + i X(N), both real for a real
-// row.  Between the passes the spectra are P[z][kx][ky'] (kx <= N, in the
-// C and D buffers), ky' = m for ky = 2m and N + m for ky = 2m + 1.
+// row.  Between the passes the spectra are P[kx][z][ky'] (kx <= N, in the
+// C and D buffers), ky' = m for ky = 2m and N + m for ky = 2m + 1: a plane
+// writes one 2N run per kx, and a z tile reads within one kx slab.
 template <typename T>
 struct PadLine {  // one line of LDS in natural order, one pad per 16
   C2<T>* b;
@@ -662,7 +664,7 @@ struct PL {
   static constexpr int XP = 2 * N + (2 * N) / 16 + 1;
   static constexpr int XL = N * PC + (N / 16) * 8;  // the plane (skewed columns)
   static constexpr int LDS = XL + XP;              // and column 0's 2N spectrum
-  static constexpr bool fits = N >= 16 && N <= 128 && LDS * (int)sizeof(C2<T>) <= 160 * 1024;
+  static constexpr bool fits = N >= 32 && N <= 128 && LDS * (int)sizeof(C2<T>) <= 160 * 1024;
 };
 
 // Output position of register b * RL + r after a length-N transform.
@@ -671,7 +673,7 @@ __device__ __forceinline__ int pl_pos(int t, int b, int r) {
   return t + b * PL<T, N>::TL + r * PL<T, N>::NB;
 }
 
-// Forward: plane z of solve item / N, rho -> P[z][kx][ky'].
+// Forward: plane z of solve item / N, rho -> P[kx][z][ky'].
 template <typename T, int N, int NT>
 __global__ void __launch_bounds__(NT)
     k_plane_fwd(const SolveDesc<T>* __restrict__ solves, int* __restrict__ reset,
@@ -686,47 +688,91 @@ __global__ void __launch_bounds__(NT)
   const int tid = threadIdx.x, t = tid % TL, grp = tid / TL;
   // x: rows 2j and 2j+1 as one complex line; task (j, h) takes the even
   // (h = 0) or odd (h = 1) outputs, with row 2j + h as its exchange space
-  // and the place of its outputs
-  // every round's rows are loaded before the first transform: one round
-  // trip to memory per plane
+  // and the place of its outputs.  Below N = 128 the rows of a wavefront's
+  // tasks (GPW rows, 1024 values, contiguous) are loaded by the whole
+  // wavefront, 16 consecutive values per lane, and staged as
+  // z = row 2j + i row 2j+1 in row 2j's slots, where both tasks of the pair
+  // take their inputs.  Every round is loaded before the first transform.
+  constexpr int GPW = 64 / TL;  // tasks of one wavefront: GPW / 2 row pairs
   constexpr int XR = (N + GROUPS - 1) / GROUPS;
-  C2<T> xv[XR][V];
-#pragma unroll
-  for (int u = 0; u < XR; ++u) {
-    const int task = grp + u * GROUPS;
-    if (task < N) {
-      const size_t row = ((size_t)z * N + 2 * (task >> 1)) * N;
-      const gp<const T> a = glb(d.rho + row), b = a + N;
-#pragma unroll
-      for (int r = 0; r < V; ++r)
-        xv[u][r] = C2<T>{__builtin_nontemporal_load(&a[t + r * TL]), __builtin_nontemporal_load(&b[t + r * TL])};
-    }
-  }
-  if (d.rho2) {  // summed grids: the second source is added on the way in
+  const int lane = tid & 63, wt0 = (tid >> 6) * GPW;
+  if constexpr (N >= 128) {
+    // at N = 128 each task loads its own pair of rows (measured faster:
+    // the staging's strided LDS writes cost more than the shorter loads save)
+    C2<T> xv[XR][V];
 #pragma unroll
     for (int u = 0; u < XR; ++u) {
       const int task = grp + u * GROUPS;
       if (task < N) {
         const size_t row = ((size_t)z * N + 2 * (task >> 1)) * N;
-        const gp<const T> a2 = glb(d.rho2 + row), b2 = a2 + N;
+        const gp<const T> a = glb(d.rho + row), b = a + N;
 #pragma unroll
-        for (int r = 0; r < V; ++r) {
-          xv[u][r].re += __builtin_nontemporal_load(&a2[t + r * TL]);
-          xv[u][r].im += __builtin_nontemporal_load(&b2[t + r * TL]);
+        for (int r = 0; r < V; ++r)
+          xv[u][r] = C2<T>{__builtin_nontemporal_load(&a[t + r * TL]), __builtin_nontemporal_load(&b[t + r * TL])};
+        if (d.rho2) {  // summed grids: the second source is added on the way in
+          const gp<const T> a2 = glb(d.rho2 + row), b2 = a2 + N;
+#pragma unroll
+          for (int r = 0; r < V; ++r) {
+            xv[u][r].re += __builtin_nontemporal_load(&a2[t + r * TL]);
+            xv[u][r].im += __builtin_nontemporal_load(&b2[t + r * TL]);
+          }
         }
       }
     }
-  }
 #pragma unroll
-  for (int u = 0; u < XR; ++u) {
-    const int task = grp + u * GROUPS;
-    if (task < N) {
-      const int j = task >> 1, h = task & 1;
-      if (h) {
+    for (int u = 0; u < XR; ++u) {
+      const int task = grp + u * GROUPS;
+      if (task < N) {
+        const int j = task >> 1, h = task & 1;
+        if (h) {
 #pragma unroll
-        for (int r = 0; r < V; ++r) xv[u][r] = cmul(xv[u][r], twist[t + r * TL]);
+          for (int r = 0; r < V; ++r) xv[u][r] = cmul(xv[u][r], twist[t + r * TL]);
+        }
+        fwd_from_g<T, N, V, 0, true>(StrLine<T>{s + pad(2 * j + h), PC}, t, xv[u], tw);
       }
-      fwd_from_g<T, N, V, 0, true>(StrLine<T>{s + pad(2 * j + h), PC}, t, xv[u], tw);
+    }
+  } else {
+    typedef T t4 __attribute__((ext_vector_type(4)));
+    t4 raw[XR][4];
+    const int rr = (16 * lane) / N, n0 = (16 * lane) % N;  // row in the wave's block, first column
+#pragma unroll
+    for (int u = 0; u < XR; ++u) {
+      const int y0 = wt0 + u * GROUPS;  // first row of the wave's block (tasks 2 per row pair)
+      if (y0 < N) {
+        const gp<const t4> a = (gp<const t4>)glb(d.rho + ((size_t)z * N + y0 + rr) * N + n0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) raw[u][k] = __builtin_nontemporal_load(&a[k]);
+        if (d.rho2) {  // summed grids: the second source is added on the way in
+          const gp<const t4> a2 = (gp<const t4>)glb(d.rho2 + ((size_t)z * N + y0 + rr) * N + n0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) raw[u][k] += __builtin_nontemporal_load(&a2[k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < XR; ++u) {
+      const int y0 = wt0 + u * GROUPS;
+      const int task = grp + u * GROUPS;
+      if (y0 < N) {
+        // stage: row y0 + rr holds the real (even row) or imaginary (odd row)
+        // part of its pair's line
+        const int yr = y0 + rr;
+        T* line = (T*)(s + pad(yr & ~1)) + (yr & 1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) line[2 * pl_col(n0 + 4 * k + e, PC)] = raw[u][k][e];
+        wave_sync();
+        const int j = task >> 1, h = task & 1;
+        C2<T> v[V];
+#pragma unroll
+        for (int r = 0; r < V; ++r) {
+          v[r] = s[pl_col(t + r * TL, PC) + pad(2 * j)];
+          if (h) v[r] = cmul(v[r], twist[t + r * TL]);
+        }
+        wave_sync();
+        fwd_from_g<T, N, V, 0, true>(StrLine<T>{s + pad(2 * j + h), PC}, t, v, tw);
+      }
     }
   }
   __syncthreads();
@@ -769,9 +815,15 @@ __global__ void __launch_bounds__(NT)
   __syncthreads();
   // y: column kx (zero-padded to 2N) -> even and odd frequencies; column 0
   // (X(0) + i X(N)) is separated by symmetry through the extra line
+  // Each half spectrum of a column is staged in the column's own slots and
+  // the wavefront writes its columns out whole, 64 lanes in one run, rather
+  // than each line's lanes writing their own scattered 64-byte pieces.
   C2<T>* const xl = s + G::XL;
+  const int wc0 = wt0;  // first column of the wavefront (GPW columns)
 #pragma unroll 1
-  for (int kx = grp; kx < N; kx += GROUPS) {
+  for (int k0 = 0; k0 < N; k0 += GROUPS) {
+    if (k0 + wc0 >= N) break;  // the whole wavefront is past the last column
+    const int kx = k0 + grp;
     C2<T>* col = s + pl_col(kx, PC);
     C2<T> u[V], v[V];
 #pragma unroll
@@ -780,7 +832,6 @@ __global__ void __launch_bounds__(NT)
       v[r] = u[r];
     }
     wave_sync();
-    const gp<C2<T>> out = glb(d.C + ((size_t)z * (N + 1) + kx) * L);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (h) {
@@ -789,18 +840,28 @@ __global__ void __launch_bounds__(NT)
         wave_sync();
       }
       fwd_from_g<T, N, V, 0, false>(PadLine<T>{col}, t, v, tw);
+      wave_sync();
 #pragma unroll
       for (int b = 0; b < V / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
-          const int m = h * N + pl_pos<T, N>(t, b, r);
-          if (kx == 0) xl[pad(m)] = v[b * RL + r];
-          else gst(out + m, v[b * RL + r]);
+          const int m = pl_pos<T, N>(t, b, r);
+          if (kx == 0) xl[pad(h * N + m)] = v[b * RL + r];
+          else col[pad(m)] = v[b * RL + r];
         }
+      wave_sync();
+      for (int c = 0; c < GPW; ++c) {
+        const int kc = k0 + wc0 + c;
+        if (kc == 0) continue;  // column 0 is separated below
+        const C2<T>* cc = s + pl_col(kc, PC);
+        const gp<C2<T>> o = glb(d.C + ((size_t)kc * N + z) * L + h * N);
+        for (int q = lane; q < N; q += 64) gst(o + q, cc[pad(q)]);
+      }
+      wave_sync();
     }
     if (kx == 0) {
       wave_sync();
-      const gp<C2<T>> o0 = glb(d.C + (size_t)z * (N + 1) * L), oN = o0 + (size_t)N * L;
+      const gp<C2<T>> o0 = glb(d.C + (size_t)z * L), oN = o0 + (size_t)N * N * L;
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -816,7 +877,7 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-// Inverse: P[z][kx][ky'] (the z pass's output, D) -> phi plane z (x, y < N).
+// Inverse: P[kx][z][ky'] (the z pass's output, D) -> phi plane z (x, y < N).
 template <typename T, int N, int NT>
 __global__ void __launch_bounds__(NT)
     k_plane_inv(const SolveDesc<T>* __restrict__ solves, int* __restrict__ reset,
@@ -832,37 +893,57 @@ __global__ void __launch_bounds__(NT)
   // y: column kx from its even and odd frequencies (column 0 from
   // Q(0) + i Q(N), whose inverse is X(0) + i X(N)); inverse transforms as
   // conj(F(conj .)), unnormalised
+  // The wavefront loads its columns' inputs whole, 64 lanes in one run
+  // (both halves before the first transform), and stages each half in the
+  // columns' slots, from where each line takes its own values.
+  constexpr int GPW = 64 / TL;
+  constexpr int QPL = (N + 63) / 64;  // values per lane of one column half
+  const int lane = tid & 63, wc0 = (tid >> 6) * GPW;
 #pragma unroll 1
-  for (int kx = grp; kx < N; kx += GROUPS) {
+  for (int k0 = 0; k0 < N; k0 += GROUPS) {
+    if (k0 + wc0 >= N) break;  // the whole wavefront is past the last column
+    const int kx = k0 + grp;
     C2<T>* col = s + pl_col(kx, PC);
-    const gp<const C2<T>> q = glb(d.D + ((size_t)z * (N + 1) + kx) * L);
-    const gp<const C2<T>> qn = glb(d.D + ((size_t)z * (N + 1) + N) * L);
-    // both halves are loaded before the first transform (one round trip)
+    C2<T> pre[2][GPW][QPL];
+#pragma unroll
+    for (int c = 0; c < GPW; ++c) {
+      const int kc = k0 + wc0 + c;
+      const gp<const C2<T>> q = glb(d.D + ((size_t)kc * N + z) * L);
+      const gp<const C2<T>> qn = glb(d.D + ((size_t)N * N + z) * L);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) {
+          const int m = lane + 64 * k;
+          if (m < N) {
+            C2<T> e{__builtin_nontemporal_load(&q[h * N + m].re), __builtin_nontemporal_load(&q[h * N + m].im)};
+            if (kc == 0) {  // Q(0) + i Q(N)
+              const C2<T> f{__builtin_nontemporal_load(&qn[h * N + m].re),
+                            __builtin_nontemporal_load(&qn[h * N + m].im)};
+              e = C2<T>{e.re - f.im, e.im + f.re};
+            }
+            pre[h][c][k] = e;
+          }
+        }
+    }
     C2<T> a[V], v[V];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int r = 0; r < V; ++r) {
-        const int m = h * N + t + r * TL;
-        C2<T> e{__builtin_nontemporal_load(&q[m].re), __builtin_nontemporal_load(&q[m].im)};
-        if (kx == 0) {
-          const C2<T> f{__builtin_nontemporal_load(&qn[m].re), __builtin_nontemporal_load(&qn[m].im)};
-          e = C2<T>{e.re - f.im, e.im + f.re};
-        }
-        (h ? a : v)[r] = conjc(e);
-      }
-#pragma unroll
     for (int h = 0; h < 2; ++h) {
-      if (h) {
-        wave_sync();
+      if (h) wave_sync();
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-          const C2<T> e = a[i];
-          a[i] = conjc(v[i]);
-          v[i] = e;
-        }
-      }
+      for (int c = 0; c < GPW; ++c)
+#pragma unroll
+        for (int k = 0; k < QPL; ++k)
+          if (lane + 64 * k < N) s[pl_col(k0 + wc0 + c, PC) + pad(lane + 64 * k)] = pre[h][c][k];
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < V; ++r) v[r] = conjc(col[pad(t + r * TL)]);
+      wave_sync();
       fwd_from_g<T, N, V, 0, false>(PadLine<T>{col}, t, v, tw);
+      if (!h) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) a[i] = conjc(v[i]);
+      }
     }
     wave_sync();
 #pragma unroll
@@ -1095,8 +1176,7 @@ static const C2<T>* twist_table(int N, hipStream_t st, bool create = true) {
 // for this block size.
 template <typename T>
 static bool plane_ok(int N) {
-  return (N == 16 && PL<T, 16>::fits) || (N == 32 && PL<T, 32>::fits) || (N == 64 && PL<T, 64>::fits) ||
-         (N == 128 && PL<T, 128>::fits);
+  return (N == 32 && PL<T, 32>::fits) || (N == 64 && PL<T, 64>::fits) || (N == 128 && PL<T, 128>::fits);
 }
 template <typename T>
 static bool plane_nt_ok(int N, int nt) {
@@ -1128,7 +1208,6 @@ template <typename T>
 static void launch_plane(bool inv, const SolveDesc<T>* solves, int N, int nsolves, int nt, int* reset,
                          const C2<T>* tw, const C2<T>* twist, hipStream_t st) {
   switch (N) {
-    case 16: launch_plane_n<T, 16>(inv, solves, nsolves, nt, reset, tw, twist, st); break;
     case 32: launch_plane_n<T, 32>(inv, solves, nsolves, nt, reset, tw, twist, st); break;
     case 64: launch_plane_n<T, 64>(inv, solves, nsolves, nt, reset, tw, twist, st); break;
     default: launch_plane_n<T, 128>(inv, solves, nsolves, nt, reset, tw, twist, st); break;
@@ -1159,6 +1238,7 @@ struct TuneKey {
 struct Tuned {
   std::array<PassShape, kPasses> sh;
   int form = 5;
+  float ms5 = 0.f, ms3 = 0.f;  // the tuner's time of a whole solve set in each form (0: not timed)
 };
 
 // Line schedule pinned for plans tuned from now on (0: the tuner times
@@ -1222,6 +1302,11 @@ std::string tuning_report() {
                                                : eff_v<float>(2 * e.first.N, sh.v));
       out += "\n";
     }
+    if (e.second.ms5 > 0.f && e.second.ms3 > 0.f)
+      out += std::string(e.first.esz == 8 ? "fp64" : "fp32") + " N=" + std::to_string(e.first.N) + " x" +
+             std::to_string(e.first.count) + " form=" + std::to_string(e.second.form) +
+             " timed five-pass " + std::to_string(e.second.ms5) + " ms, plane " + std::to_string(e.second.ms3) +
+             " ms\n";
   }
   return out;
 }
@@ -1243,6 +1328,21 @@ bool tuning_cached(int esz, std::vector<int> mix) {
     i = j;
   }
   return true;
+}
+
+// One pass of a group in either form.  Plane form: pass 0 is the plane
+// forward, 2 the z pass on the plane layout, 3 the plane inverse; 1 and 4
+// launch nothing.  Each launch clears the work counter of the pass before.
+template <typename T>
+static void run_pass(int form, int q, const SolveDesc<T>* solves, int N, int count, const PassShape& sh,
+                     int* ctr, int* prev, const C2<T>* tw, const C2<T>* twist, hipStream_t st) {
+  if (form != 3) {
+    launch_any<T>(q, solves, N, count, sh, ctr, prev, tw, st);
+  } else if (q == 0 || q == 3) {
+    launch_plane<T>(q == 3, solves, N, count, sh.nt, prev, tw, twist, st);
+  } else if (q == 2) {
+    launch_any<T>(5, solves, N, count, sh, ctr, prev, tw, st);
+  }
 }
 
 template <typename T>
@@ -1351,7 +1451,55 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
     }
     plane_t.sh[1] = plane_t.sh[4] = PassShape{0, 0, 0};
   }
+  if (plane && five) {
+    // The forms are compared as whole solves, the way a step runs them:
+    // the last-level cache is first overwritten (other work of a step
+    // streams far more than its 256 MB between two solve sets) and then the
+    // inputs are written, as the mass assignment does.  Passes timed alone
+    // or back to back find their inputs, intermediates and Green's tables
+    // in the caches, which favours the form with more passes.  Repetitions
+    // are interleaved so that drifts reach both forms alike: fastest of 10
+    // after 2 each.
+    const size_t flush_bytes = (size_t)512 << 20;
+    void* flush = nullptr;
+    if (hipMalloc(&flush, flush_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      flush = nullptr;  // compared with warm caches instead
+    }
+    auto whole = [&](const Tuned& f, float& ms) -> sbx_status {
+      if (flush) SBX_HIP(hipMemsetAsync(flush, 0, flush_bytes, st));
+      for (int i = 0; i < count; ++i) {
+        SBX_HIP(hipMemsetAsync((void*)host[i].rho, 0, sizeof(T) * (size_t)N * N * N, st));
+        if (host[i].rho2) SBX_HIP(hipMemsetAsync((void*)host[i].rho2, 0, sizeof(T) * (size_t)N * N * N, st));
+      }
+      hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, counter, kPasses);
+      SBX_HIP(hipEventRecord(e0, st));
+      for (int q = 0; q < kPasses; ++q) {
+        const bool pq = f.form == 3 && q != 2;
+        const C2<T>* tq = pq ? twh : tws[f.sh[q].v == vs[0] || vs.size() == 1 ? 0 : 1];
+        run_pass<T>(f.form, q, d_solves, N, count, f.sh[q], counter + q, nullptr, tq, twist, st);
+      }
+      SBX_HIP(hipEventRecord(e1, st));
+      SBX_HIP(hipEventSynchronize(e1));
+      SBX_HIP(hipEventElapsedTime(&ms, e0, e1));
+      return SBX_OK;
+    };
+    t5 = t3 = 1e30f;
+    sbx_status rc = SBX_OK;
+    for (int rep = 0; rep < 12 && rc == SBX_OK; ++rep) {
+      float a = 0.f, b = 0.f;
+      if ((rc = whole(five_t, a)) == SBX_OK) rc = whole(plane_t, b);
+      if (rep >= 2) {
+        t5 = std::min(t5, a);
+        t3 = std::min(t3, b);
+      }
+    }
+    if (flush) (void)hipFree(flush);
+    SBX_TRY(rc);
+  }
   out = (plane && (!five || t3 < t5)) ? plane_t : five_t;
+  out.ms5 = five ? t5 : 0.f;
+  out.ms3 = plane ? t3 : 0.f;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return SBX_OK;
@@ -1441,21 +1589,6 @@ sbx_status plan_create(SolvePlan<T>& p, const SolveDesc<T>* descs, int n, hipStr
   SBX_HIP(hipMemsetAsync(p.d_counter, 0, sizeof(int) * kPasses * kMaxGroups, st));
   SBX_HIP(hipStreamSynchronize(st));
   return SBX_OK;
-}
-
-// One pass of a group in either form.  Plane form: pass 0 is the plane
-// forward, 2 the z pass on the plane layout, 3 the plane inverse; 1 and 4
-// launch nothing.  Each launch clears the work counter of the pass before.
-template <typename T>
-static void run_pass(int form, int q, const SolveDesc<T>* solves, int N, int count, const PassShape& sh,
-                     int* ctr, int* prev, const C2<T>* tw, const C2<T>* twist, hipStream_t st) {
-  if (form != 3) {
-    launch_any<T>(q, solves, N, count, sh, ctr, prev, tw, st);
-  } else if (q == 0 || q == 3) {
-    launch_plane<T>(q == 3, solves, N, count, sh.nt, prev, tw, twist, st);
-  } else if (q == 2) {
-    launch_any<T>(5, solves, N, count, sh, ctr, prev, tw, st);
-  }
 }
 
 template <typename T>

@@ -153,8 +153,8 @@ def test_fft_forms_match_oracle(sbx, torch, form, N, q, prec):
     and y of one plane in LDS; even and odd frequencies of each padded line
     as two half-length transforms) or five line passes, against the oracle's
     FFT convolution (Eqs. 3-5), three solves per batch.  FP64 at N = 128 has
-    no plane form (its plane does not fit in LDS) and runs five passes under
-    either pin."""
+    no plane form (its plane does not fit in LDS), nor has N = 16; they run
+    five passes under either pin."""
     rng = _rng(3000 + N + form + 10 * prec)
     R = 2.0
     Ms = []
@@ -169,7 +169,7 @@ def test_fft_forms_match_oracle(sbx, torch, form, N, q, prec):
         rep = sbx.sbx_fft_tuning_report()
     finally:
         sbx.sbx_set_fft_form(0)
-    want = form if (prec == sbx.SBX_FP32 or N <= 64) else 5
+    want = form if ((prec == sbx.SBX_FP32 or N <= 64) and N >= 32) else 5
     esz = "fp64" if prec == sbx.SBX_FP64 else "fp32"
     assert f"{esz} N={N} x3 form={want} " in rep
     Hh, _ = O.green_hat(O.Level(N, R, q))
