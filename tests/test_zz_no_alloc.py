@@ -75,3 +75,22 @@ def test_noalloc_rejects_batches_beyond_the_work_space(sbx, torch):
     p.close()
     r, o = ref.cpu().numpy(), phi.cpu().numpy()
     assert np.abs(o - r).max() <= 1e-11 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("form", [3, 5])
+def test_noalloc_in_each_form(sbx, torch, form):
+    """With each form of the solve pinned (plane-fused passes, five line
+    passes), the no-alloc solve runs the same form as the allocating one
+    and matches it, on two calls in a row, the second smaller."""
+    sbx.sbx_set_fft_form(form)
+    try:
+        print(f"no-alloc form {form}: FP32 128^3 x 1", flush=True)
+        ref, out = _solve_both(sbx, torch, 128, sbx.SBX_FP32, 1, 10 + form)
+        assert np.abs(out - ref).max() <= 3e-6 * np.abs(ref).max()
+        print(f"no-alloc form {form}: FP32 64^3 x 2", flush=True)
+        ref, out = _solve_both(sbx, torch, 64, sbx.SBX_FP32, 2, 20 + form)
+        assert np.abs(out - ref).max() <= 3e-6 * np.abs(ref).max()
+        rep = sbx.sbx_fft_tuning_report()
+    finally:
+        sbx.sbx_set_fft_form(0)
+    assert f"fp32 N=128 x1 form={form} " in rep and f"fp32 N=64 x2 form={form} " in rep
