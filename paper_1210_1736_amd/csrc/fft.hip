@@ -776,61 +776,51 @@ __global__ void __launch_bounds__(NT)
     }
   }
   __syncthreads();
-  // the two rows' spectra from Z = F(rows 2j + i 2j+1):
-  // X_a(k) = (Z(k) + conj Z(-k)) / 2, X_b(k) = -i (Z(k) - conj Z(-k)) / 2;
-  // Z(k) is in row 2j (k even) or 2j + 1 (k odd) at k / 2
+  // y: column kx (zero-padded to 2N) -> even and odd frequencies; column 0
+  // (X(0) + i X(N)) is separated by symmetry through the extra line.
+  // A column's values come straight from the two rows' spectra Z of the
+  // x transforms (Z = F(row 2j + i row 2j+1)):
+  // X_2j(k) = (Z(k) + conj Z(-k)) / 2, X_2j+1(k) = -i (Z(k) - conj Z(-k)) / 2,
+  // Z(k) in row 2j (k even) or 2j + 1 (k odd) at k / 2.  Every column reads
+  // its values before any column's transform uses its slots.
+  // Each half spectrum of a column is staged in the column's own slots and
+  // the wavefront writes its columns out whole, 64 lanes in one run, rather
+  // than each line's lanes writing their own scattered 64-byte pieces.
   auto zat = [&](int j, int k) -> C2<T> {
     return s[pl_col(k >> 1, PC) + pad(2 * j + (k & 1))];
   };
-  constexpr int SEP = (N * N / 2 + NT - 1) / NT;
-  C2<T> zk[SEP], zm[SEP];
-#pragma unroll
-  for (int q = 0; q < SEP; ++q) {
-    const int i = tid + q * NT;
-    if (i < N * N / 2) {
-      const int j = i / N, kx = i - j * N;
-      zk[q] = zat(j, kx);
-      zm[q] = zat(j, kx == 0 ? N : L - kx);
-    }
-  }
-  __syncthreads();
   const T hf = (T)0.5;
+  constexpr int YR = (N + GROUPS - 1) / GROUPS;
+  const int wc0 = wt0;  // first column of the wavefront (GPW columns)
+  C2<T> uy[YR][V];
 #pragma unroll
-  for (int q = 0; q < SEP; ++q) {
-    const int i = tid + q * NT;
-    if (i < N * N / 2) {
-      const int j = i / N, kx = i - j * N;
-      const C2<T> Z = zk[q], R = zm[q];
-      C2<T>* ca = s + pl_col(kx, PC) + pad(2 * j);
-      C2<T>* cb = s + pl_col(kx, PC) + pad(2 * j + 1);
-      if (kx == 0) {  // X(0) and X(N) of both rows, real: packed
-        *ca = C2<T>{Z.re, R.re};
-        *cb = C2<T>{Z.im, R.im};
-      } else {
-        *ca = C2<T>{(Z.re + R.re) * hf, (Z.im - R.im) * hf};
-        *cb = C2<T>{(Z.im + R.im) * hf, (R.re - Z.re) * hf};
+  for (int yr = 0; yr < YR; ++yr) {
+    const int kx = yr * GROUPS + grp;
+    if (yr * GROUPS + wc0 < N) {
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        const int y = t + r * TL, j = y >> 1;
+        const C2<T> Z = zat(j, kx), R = zat(j, kx == 0 ? N : L - kx);
+        if (kx == 0)  // X(0) and X(N) of the row, real: packed
+          uy[yr][r] = (y & 1) ? C2<T>{Z.im, R.im} : C2<T>{Z.re, R.re};
+        else
+          uy[yr][r] = (y & 1) ? C2<T>{(Z.im + R.im) * hf, (R.re - Z.re) * hf}
+                              : C2<T>{(Z.re + R.re) * hf, (Z.im - R.im) * hf};
       }
     }
   }
   __syncthreads();
-  // y: column kx (zero-padded to 2N) -> even and odd frequencies; column 0
-  // (X(0) + i X(N)) is separated by symmetry through the extra line
-  // Each half spectrum of a column is staged in the column's own slots and
-  // the wavefront writes its columns out whole, 64 lanes in one run, rather
-  // than each line's lanes writing their own scattered 64-byte pieces.
   C2<T>* const xl = s + G::XL;
-  const int wc0 = wt0;  // first column of the wavefront (GPW columns)
-#pragma unroll 1
-  for (int k0 = 0; k0 < N; k0 += GROUPS) {
+#pragma unroll
+  for (int yr = 0; yr < YR; ++yr) {
+    const int k0 = yr * GROUPS;
     if (k0 + wc0 >= N) break;  // the whole wavefront is past the last column
     const int kx = k0 + grp;
     C2<T>* col = s + pl_col(kx, PC);
-    C2<T> u[V], v[V];
+    C2<T>* u = uy[yr];
+    C2<T> v[V];
 #pragma unroll
-    for (int r = 0; r < V; ++r) {
-      u[r] = col[pad(t + r * TL)];
-      v[r] = u[r];
-    }
+    for (int r = 0; r < V; ++r) v[r] = u[r];
     wave_sync();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
