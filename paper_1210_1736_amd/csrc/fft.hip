@@ -1559,6 +1559,10 @@ sbx_status plan_create(SolvePlan<T>& p, const SolveDesc<T>* descs, int n, hipStr
       g_tune.push_back({key, a});
     }
     g.form = a.form;
+    if (g.form == 3 && !plane_ok<T>(g.N)) {
+      set_error("internal: plane-fused form chosen for a size without one");
+      return SBX_EINVAL;
+    }
     for (int q = 0; q < kPasses; ++q) {
       g.shape[q] = a.sh[q];
       g.tw[q] = nullptr;
