@@ -310,3 +310,19 @@ def test_adjoint_particles_lost_mid_segment_fp32(sbx, kind):
     assert L == pytest.approx(Lr, rel=1e-6)
     assert errs[0] < 1e-5 and errs[1] < 1e-4 and errs[2] < 1e-5
     assert e_esc.max() < 1e-3
+
+
+def test_adjoint_with_fixed_point_assignment_fp64(sbx):
+    """The segment with the fixed-point mass assignment: its forward and
+    checkpoint re-solves assign masses as exact integer sums; loss and
+    gradients agree with the oracle's (float assignment) to the same bars,
+    the two assignments differing only by the truncation (2^-s per mass)."""
+    w = _workload("nested")
+    ctx = T.make_ctx(w, sbx.SBX_FP64)
+    ctx.sbx_set_deterministic_deposit(1)
+    L, gm, gx, gv = ctx.sbx_adjoint_segment(w.dt, w.steps, 2, 1, 0)
+    Lr, gmr, gxr, gvr = O.segment_loss_and_grads(T.oracle_system(w), w.x, w.v, w.m, w.comp, w.gal,
+                                                  w.dt, w.steps, 1, 0)
+    assert L == pytest.approx(Lr, rel=1e-12)
+    for a, b in ((gm, gmr), (gx, gxr), (gv, gvr)):
+        assert _maxrel(a, b) < 1e-9
