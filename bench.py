@@ -339,8 +339,8 @@ def disc_analysis_rate(sbx, torch, w):
 
 def cpu_threads():
     """Threads the CPU baseline may use: the process's thread budget
-    (OMP_NUM_THREADS) when set, else the usable cores, at most 16 (the CPU
-    share of one GPU on the GPU machines)."""
+    (OMP_NUM_THREADS) when set, else the usable cores, at most 16 (a
+    one-GPU host's share of the CPU)."""
     env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
     aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     return env or min(aff, 16)
