@@ -860,7 +860,16 @@ __global__ void __launch_bounds__(256)
     for (int r = 0; r < 2; ++r) {
       const uint32_t key = r == 0 ? c1 : c2;
       bool tail;
-      const V s = wave_run_sum<V>(key, m, tail);
+      V s;
+      // a coarse cell is usually the same for the whole wavefront: then a
+      // plain wavefront sum (in lane 63) replaces the segmented one
+      const uint32_t k0 = __builtin_amdgcn_readfirstlane(key);
+      if (__ballot(key != k0) == 0ull) {
+        s = wave_total63<V>(m);
+        tail = (threadIdx.x & 63) == 63;
+      } else {
+        s = wave_run_sum<V>(key, m, tail);
+      }
       if (tail && key != kNoKey) {
         uint32_t hslot = (key * 2654435761u) >> (32 - kDepTableBits);
         bool done = false;
