@@ -179,3 +179,26 @@ def test_fixed_assignment_survives_checkpoint(sbx, tmp_path, prec):
     assert back[12:44] == data[12:44]
     for o in (a, b, c, d):
         o.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fixed_cell_masses_six_galaxies(sbx, prec):
+    """Six galaxies (a disc and five satellites with different particle
+    masses): every galaxy's cell masses bit-exact against the oracle's
+    fixed-point assignment, all on the one scale of the whole particle set
+    (its largest mass and count), at the library's own centres."""
+    from tests.test_gpu_manygal import _system
+    w = _system()
+    x, v, m = T.oracle_inputs(w, prec)
+    sysm = T.oracle_system(w)
+    sysm.fixed_deposit = True
+    lost = sysm.lost_now(x)
+    ctx = _fixed_ctx(sbx, w, prec)
+    ctx.sbx_compute_forces()
+    cg = ctx.sbx_get_centres()
+    pots = sysm.potentials(x, m, w.gal, lost, cg)
+    for g in range(len(w.hier)):
+        for k, ref in enumerate(_mass_slots(pots[g]["M"], prec)):
+            got = ctx.sbx_get_grid(g, k, 0).transpose(2, 1, 0)
+            assert np.array_equal(got, ref), (g, k, np.abs(got - ref).max())
+    ctx.close()
