@@ -202,3 +202,24 @@ def test_fixed_cell_masses_six_galaxies(sbx, prec):
             got = ctx.sbx_get_grid(g, k, 0).transpose(2, 1, 0)
             assert np.array_equal(got, ref), (g, k, np.abs(got - ref).max())
     ctx.close()
+
+
+def test_fixed_cell_masses_full_size(sbx):
+    """The benchmark galaxy at full size (8.5M particles, 3 x 128^3, FP32):
+    cell masses of the fixed-point assignment bit-exact against the oracle's
+    (scale s = 62 - e - 24 for 8.5M particles), at the library's centres."""
+    import synth
+    w = synth.disc_galaxy(scale=1.0)
+    x, v, m = T.oracle_inputs(w, sbx.SBX_FP32)
+    sysm = T.oracle_system(w)
+    sysm.fixed_deposit = True
+    lost = sysm.lost_now(x)
+    ctx = _fixed_ctx(sbx, w, sbx.SBX_FP32)
+    ctx.sbx_compute_forces()
+    cg = ctx.sbx_get_centres()
+    pots = sysm.potentials(x, m, w.gal, lost, cg)
+    for k, ref in enumerate(_mass_slots(pots[0]["M"], sbx.SBX_FP32)):
+        got = ctx.sbx_get_grid(0, k, 0).transpose(2, 1, 0)
+        assert np.array_equal(got, ref), (k, np.abs(got - ref).max())
+    assert np.sum(ref) > 0
+    ctx.close()
