@@ -146,10 +146,12 @@ def make_ctx(sbx, w, prec, merge=False):
 
 
 def timed_steps(sbx, torch, w, prec, steps, warmup, diag_every, profile=True, sort_every=None,
-                merge=False):
+                merge=False, fixed=False):
     ctx = make_ctx(sbx, w, prec, merge)
     if sort_every is not None:
         ctx.sbx_set_sort_interval(sort_every)
+    if fixed:
+        ctx.sbx_set_deterministic_deposit(1)
     ctx.sbx_step(w.dt, warmup, diag_every)
     ctx.sbx_sync()
     live0 = ctx.sbx_count_live()
@@ -229,6 +231,16 @@ def density_centring_rate(sbx, torch, w, steps, warmup, diag_every):
             "steps": steps, "particles_live": live, "ms_per_step": 1e3 * t / steps,
             "particle_steps_per_s": live * steps / t,
             "centring_ms_per_step": ph["pre"][0] / steps if "pre" in ph else None}
+
+
+def fixed_point_rate(sbx, torch, w, steps, warmup, diag_every):
+    """The main workload with the fixed-point (bit-reproducible) mass
+    assignment: exact 64-bit integer cell sums and one conversion pass."""
+    t, live, ph = timed_steps(sbx, torch, w, sbx.SBX_FP32, steps, warmup, diag_every, fixed=True)
+    return {"workload": "the FP32 disc-galaxy step with the fixed-point mass assignment",
+            "steps": steps, "particles_live": live, "ms_per_step": 1e3 * t / steps,
+            "particle_steps_per_s": live * steps / t,
+            "deposit_ms_per_step": ph["deposit"][0] / steps if "deposit" in ph else None}
 
 
 def heating_experiment(sbx, torch, w, steps=400, every=100):
@@ -545,6 +557,8 @@ def main():
         _log("density-maximum centring")
         extra["density_centring"] = density_centring_rate(sbx, torch, w, args.extra_steps, 2,
                                                           args.diag_every)
+        _log("fixed-point mass assignment")
+        extra["fixed_point_deposit"] = fixed_point_rate(sbx, torch, w, args.extra_steps, 2, args.diag_every)
         _log("galaxy + satellite")
         extra["galaxy_satellite"] = galaxy_satellite_rate(sbx, torch, args.extra_steps, 2)
         _log("ensemble of 16 instances")
