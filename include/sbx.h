@@ -480,7 +480,9 @@ sbx_status sbx_set_fft_schedule(int32_t v);
  * and the inverse y and x transforms of one plane in one block, so the
  * x-transformed planes never go to device memory (about 30% fewer bytes
  * per solve); each padded length-2n line transform is done as two
- * length-n transforms of its even and odd frequencies.  form = 0 (the
+ * length-n transforms of its even and odd frequencies (at n = 128 in FP32
+ * the forward plane pass takes the even and the odd x frequencies of a
+ * plane in two blocks, "plane_fwd nt=512" at most).  form = 0 (the
  * default): the tuner times both the first time a precision, grid size and
  * solve count is planned and keeps the faster.  Like the schedule pin,
  * process-wide, for plans made from now on; sizes without the plane form
@@ -490,7 +492,7 @@ sbx_status sbx_set_fft_form(int32_t form);
 /* The launch shapes the tuner has chosen so far in this process, one line
  * per precision, grid size, solve count and pass ("fp32 N=128 x5 form=5
  * zpass nt=256 grid=1024 v=16"; grid=tiles: one block per tile; the plane
- * passes of form 3 are "plane_fwd nt=1024" and "plane_inv nt=1024"), and
+ * passes of form 3 are "plane_fwd nt=512" and "plane_inv nt=1024"), and
  * where both forms were timed, one more line with the tuner's time of the
  * whole solve set in each ("... timed five-pass 0.247 ms, plane 0.233 ms").
  * Writes at most cap bytes including a terminating NUL into out (may be

@@ -867,6 +867,159 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
+// Forward over half a plane per block.  The columns kx of one parity take
+// their row spectra from only one of the two length-N transforms of each
+// row pair (the even outputs F(2m) or the odd ones F(2m+1) of the 2N
+// line), and the mirror -kx has the same parity; so block parity hp
+// transforms every row pair once, for its own outputs, and then the N/2
+// columns kx = 2 kx' + hp along y.  The two blocks of a plane share the
+// rows' loads only.  A block needs about half the LDS of the whole plane,
+// so two run on one CU and one's loads and stores overlap the other's
+// transforms.  Blocks 8 apart (one XCD) take the two halves of a plane, so
+// the second finds the rows in that XCD's L2.
+template <typename T, int N>
+struct PH {
+  static constexpr int V = 16, TL = N / V;
+  static constexpr int H = N / 2;                // row pairs; columns per block
+  static constexpr int PCX = H + H / 16 + 1;     // x: column m holds the pairs' outputs m
+  static constexpr int PC = PL<T, N>::PC;        // y: column kx' holds y = 0..N-1
+  static constexpr int XLX = N * PCX + (N / 16) * 8;
+  static constexpr int XLY = H * PC + (H / 16) * 8;
+  static constexpr int XL = XLX > XLY ? XLX : XLY;
+  static constexpr int XP = PL<T, N>::XP;
+  static constexpr int LDS = XL + XP;
+  static constexpr bool fits = N == 128 && sizeof(T) == 4 && 2 * LDS * (int)sizeof(C2<T>) <= 160 * 1024;
+};
+
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT)
+    k_plane_fwd_h(const SolveDesc<T>* __restrict__ solves, int* __restrict__ reset,
+                  const C2<T>* __restrict__ tw, const C2<T>* __restrict__ twist) {
+  using G = PH<T, N>;
+  constexpr int V = G::V, TL = G::TL, H = G::H, PCX = G::PCX, PC = G::PC, L = 2 * N;
+  constexpr int RL = PL<T, N>::RL, GROUPS = NT / TL, GPW = 64 / TL;
+  static_assert(H % GPW == 0 && GROUPS % GPW == 0, "a wavefront's columns lie in one round");
+  __shared__ C2<T> s[G::LDS];
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) *reset = 0;
+  const int bq = blockIdx.x >> 3, hp = bq & 1;
+  const int plane = (bq >> 1) * 8 + (blockIdx.x & 7);
+  const SolveDesc<T>& d = solves[plane / N];
+  const int z = plane % N;
+  const int tid = threadIdx.x, t = tid % TL, grp = tid / TL, lane = tid & 63;
+  const int wc0 = (tid >> 6) * GPW;  // first column of the wavefront in a round
+  // x: task j, rows 2j + i row 2j+1 (times w^n for the odd outputs); its
+  // outputs m go to position j of column m
+  constexpr int XR = (H + GROUPS - 1) / GROUPS;
+  C2<T> xv[XR][V];
+#pragma unroll
+  for (int u = 0; u < XR; ++u) {
+    const int j = grp + u * GROUPS;
+    if (j < H) {
+      const size_t row = ((size_t)z * N + 2 * j) * N;
+      const gp<const T> a = glb(d.rho + row), b = a + N;
+#pragma unroll
+      for (int r = 0; r < V; ++r) xv[u][r] = C2<T>{a[t + r * TL], b[t + r * TL]};
+      if (d.rho2) {  // summed grids: the second source is added on the way in
+        const gp<const T> a2 = glb(d.rho2 + row), b2 = a2 + N;
+#pragma unroll
+        for (int r = 0; r < V; ++r) {
+          xv[u][r].re += a2[t + r * TL];
+          xv[u][r].im += b2[t + r * TL];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < XR; ++u) {
+    const int j = grp + u * GROUPS;
+    if (j < H) {
+      if (hp) {
+#pragma unroll
+        for (int r = 0; r < V; ++r) xv[u][r] = cmul(xv[u][r], twist[t + r * TL]);
+      }
+      fwd_from_g<T, N, V, 0, true>(StrLine<T>{s + pad(j), PCX}, t, xv[u], tw);
+    }
+  }
+  __syncthreads();
+  // y: as in the whole-plane form, Z(k) of pair j is at position j of
+  // column k / 2 (k of parity hp, as is its mirror 2N - k)
+  auto zat = [&](int j, int k) -> C2<T> { return s[pl_col(k >> 1, PCX) + pad(j)]; };
+  const T hf = (T)0.5;
+  constexpr int YR = (H + GROUPS - 1) / GROUPS;
+  C2<T> uy[YR][V];
+#pragma unroll
+  for (int yr = 0; yr < YR; ++yr) {
+    const int kx = 2 * (yr * GROUPS + grp) + hp;
+    if (yr * GROUPS + wc0 < H) {
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        const int y = t + r * TL, j = y >> 1;
+        const C2<T> Z = zat(j, kx), R = zat(j, kx == 0 ? N : L - kx);
+        if (kx == 0)  // X(0) and X(N) of the row, real: packed
+          uy[yr][r] = (y & 1) ? C2<T>{Z.im, R.im} : C2<T>{Z.re, R.re};
+        else
+          uy[yr][r] = (y & 1) ? C2<T>{(Z.im + R.im) * hf, (R.re - Z.re) * hf}
+                              : C2<T>{(Z.re + R.re) * hf, (Z.im - R.im) * hf};
+      }
+    }
+  }
+  __syncthreads();
+  C2<T>* const xl = s + G::XL;
+#pragma unroll
+  for (int yr = 0; yr < YR; ++yr) {
+    const int k0 = yr * GROUPS;
+    if (k0 + wc0 >= H) break;  // the whole wavefront is past the last column
+    const int kq = k0 + grp, kx = 2 * kq + hp;
+    C2<T>* col = s + pl_col(kq, PC);
+    C2<T>* u = uy[yr];
+    C2<T> v[V];
+#pragma unroll
+    for (int r = 0; r < V; ++r) v[r] = u[r];
+    wave_sync();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h) {
+#pragma unroll
+        for (int r = 0; r < V; ++r) v[r] = cmul(u[r], twist[t + r * TL]);
+        wave_sync();
+      }
+      fwd_from_g<T, N, V, 0, false>(PadLine<T>{col}, t, v, tw);
+      wave_sync();
+#pragma unroll
+      for (int b = 0; b < V / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const int m = pl_pos<T, N>(t, b, r);
+          if (kx == 0) xl[pad(h * N + m)] = v[b * RL + r];
+          else col[pad(m)] = v[b * RL + r];
+        }
+      wave_sync();
+      for (int c = 0; c < GPW; ++c) {
+        const int cq = k0 + wc0 + c, kc = 2 * cq + hp;
+        if (kc == 0) continue;  // column 0 is separated below
+        const C2<T>* cc = s + pl_col(cq, PC);
+        const gp<C2<T>> o = glb(d.C + ((size_t)kc * N + z) * L + h * N);
+        for (int q = lane; q < N; q += 64) gst(o + q, cc[pad(q)]);
+      }
+      wave_sync();
+    }
+    if (kx == 0) {
+      wave_sync();
+      const gp<C2<T>> o0 = glb(d.C + (size_t)z * L), oN = o0 + (size_t)N * N * L;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < V; ++r) {
+          const int m = t + r * TL;
+          const int mm = h ? N - 1 - m : (N - m) & (N - 1);
+          const C2<T> A = xl[pad(h * N + m)], B = xl[pad(h * N + mm)];
+          gst(o0 + h * N + m, C2<T>{(A.re + B.re) * hf, (A.im - B.im) * hf});
+          gst(oN + h * N + m, C2<T>{(A.im + B.im) * hf, (B.re - A.re) * hf});
+        }
+    }
+  }
+}
+
 // Inverse: P[kx][z][ky'] (the z pass's output, D) -> phi plane z (x, y < N).
 template <typename T, int N, int NT>
 __global__ void __launch_bounds__(NT)
@@ -1169,8 +1322,10 @@ static bool plane_ok(int N) {
   return (N == 32 && PL<T, 32>::fits) || (N == 64 && PL<T, 64>::fits) || (N == 128 && PL<T, 128>::fits);
 }
 template <typename T>
-static bool plane_nt_ok(int N, int nt) {
-  // FP64 at 1024 threads would leave too few registers per lane
+static bool plane_nt_ok(int N, int nt, bool inv) {
+  // FP64 at 1024 threads would leave too few registers per lane; the
+  // half-plane forward has 256 or 512
+  if (!inv && N == 128 && PH<T, 128>::fits) return nt == 256 || nt == 512;
   return plane_ok<T>(N) && (nt == 256 || nt == 512 || (nt == 1024 && sizeof(T) == 4));
 }
 
@@ -1178,6 +1333,16 @@ template <typename T, int N>
 static void launch_plane_n(bool inv, const SolveDesc<T>* solves, int nsolves, int nt, int* reset,
                            const C2<T>* tw, const C2<T>* twist, hipStream_t st) {
   if constexpr (PL<T, N>::fits) {
+    if constexpr (PH<T, N>::fits) {
+      if (!inv) {  // half a plane per block; 1024 threads would idle half the groups
+        const dim3 grid(2 * nsolves * N);
+        if (nt == 256)
+          hipLaunchKernelGGL((k_plane_fwd_h<T, N, 256>), grid, dim3(256), 0, st, solves, reset, tw, twist);
+        else
+          hipLaunchKernelGGL((k_plane_fwd_h<T, N, 512>), grid, dim3(512), 0, st, solves, reset, tw, twist);
+        return;
+      }
+    }
     auto go = [&](auto ntc) {
       constexpr int NT = decltype(ntc)::value;
       if (inv)
@@ -1428,7 +1593,7 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
       float best = 1e30f;
       PassShape pick{256, 0, 0};
       for (int nt : {256, 512, 1024}) {
-        if (!plane_nt_ok<T>(N, nt)) continue;
+        if (!plane_nt_ok<T>(N, nt, q == 3)) continue;
         float ms = 0.f;
         SBX_TRY(time_it([&] { launch_plane<T>(q == 3, d_solves, N, count, nt, nullptr, twh, twist, st); }, ms));
         if (ms < best) {
