@@ -482,7 +482,9 @@ sbx_status sbx_set_fft_schedule(int32_t v);
  * per solve); each padded length-2n line transform is done as two
  * length-n transforms of its even and odd frequencies (at n = 128 in FP32
  * the forward plane pass takes the even and the odd x frequencies of a
- * plane in two blocks, "plane_fwd nt=512" at most).  form = 0 (the
+ * plane in two blocks, with 256 or 512 threads; the inverse takes the even
+ * and the odd rows of a plane in two blocks with 256 or 512 threads, or a
+ * whole plane with 1024).  form = 0 (the
  * default): the tuner times both the first time a precision, grid size and
  * solve count is planned and keeps the faster.  Like the schedule pin,
  * process-wide, for plans made from now on; sizes without the plane form

@@ -15,10 +15,12 @@
 // FP64) the same solve can run in three passes: plane forward (x and y of
 // one plane in one block) -> P[z][kx][ky'] (in C; ky' = m for ky = 2m,
 // N + m for 2m + 1), the z pass on that layout -> D, plane inverse (inverse
-// y and x of one plane) -> phi.  At N = 128 in FP32 the plane forward
-// runs as two blocks per plane, one for the even and one for the odd kx
-// columns, each in half the LDS.  The tuner times both forms and keeps the
-// faster per precision, grid size and solve count.
+// y and x of one plane) -> phi.  At N = 128 in FP32 the plane passes can
+// run as two blocks per plane, each in half the LDS: the forward one for
+// the even and one for the odd kx columns, the inverse one for the even
+// and one for the odd rows y.  The tuner times both forms (and for the
+// inverse, whole or half planes) and keeps the faster per precision, grid
+// size and solve count.
 // Zero halves of the padded inputs are never read, unused halves of the
 // outputs never written.  Hhat (real, even per axis) is stored on (N+1)^3.
 //

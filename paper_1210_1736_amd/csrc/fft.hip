@@ -1149,6 +1149,138 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
+// Inverse over half a plane per block: block parity hp makes the rows
+// y = 2p + hp.  Those outputs of a column's length-2N inverse along y come
+// from two length-N/2 inverses.  With E and O the column's even and odd ky
+// halves and s = (-1)^hp, row 2p + hp is a(p) + w^-(2p+hp) b(p), where
+// a = IDFT_{N/2}((E(m) + s E(m + N/2)) e^{2 pi i m hp / N}) and b is the
+// same of O.  So a block does half the plane's y transforms (no transform
+// is done by both blocks), its N/2 rows pair up for the x phase as in the
+// whole-plane form, and only the D columns are read by both blocks of a
+// plane (8 apart, on one XCD, so the second mostly reads them from L2).
+// The y lines (N/2) use the table twh; the x lines (N) use tw.
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT)
+    k_plane_inv_h(const SolveDesc<T>* __restrict__ solves, int* __restrict__ reset,
+                  const C2<T>* __restrict__ tw, const C2<T>* __restrict__ twist,
+                  const C2<T>* __restrict__ twh) {
+  using G = PH<T, N>;
+  constexpr int V = G::V, TL = G::TL, H = G::H, PCX = G::PCX, L = 2 * N;
+  static_assert(H == 64, "one lane per value of a y line half");
+  constexpr int TLH = H / V, GH = NT / TLH, GPWH = 64 / TLH, RLH = PL<T, H>::RL;
+  constexpr int GROUPS = NT / TL;
+  __shared__ C2<T> s[G::XLX];
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) *reset = 0;
+  const int bq = blockIdx.x >> 3, hp = bq & 1;
+  const int plane = (bq >> 1) * 8 + (blockIdx.x & 7);
+  const SolveDesc<T>& d = solves[plane / N];
+  const int z = plane % N;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // y: column kx at slots col(kx) + pad(p), p = 0..N/2-1.  The wavefront
+  // loads its columns whole (lane m takes m and m + N/2 of both halves,
+  // column 0 as Q(0) + i Q(N)), folds them, and stages each folded half in
+  // the column's slots, from where each line takes its own values.
+  {
+    const int th = tid % TLH, gh = tid / TLH, wc0 = (tid >> 6) * GPWH;
+    const T sg = hp ? (T)-1 : (T)1;
+    const C2<T> tm = hp ? conjc(twist[2 * lane]) : C2<T>{(T)1, (T)0};
+#pragma unroll 1
+    for (int k0 = 0; k0 < N; k0 += GH) {
+      if (k0 + wc0 >= N) break;  // the whole wavefront is past the last column
+      const int kx = k0 + gh;
+      C2<T>* col = s + pl_col(kx, PCX);
+      C2<T> pre[2][GPWH];
+#pragma unroll
+      for (int c = 0; c < GPWH; ++c) {
+        const int kc = k0 + wc0 + c;
+        const gp<const C2<T>> q = glb(d.D + ((size_t)kc * N + z) * L);
+        const gp<const C2<T>> qn = glb(d.D + ((size_t)N * N + z) * L);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          C2<T> e0 = gld(q + (h * N + lane)), e1 = gld(q + (h * N + H + lane));
+          if (kc == 0) {  // Q(0) + i Q(N)
+            const C2<T> f0 = gld(qn + (h * N + lane)), f1 = gld(qn + (h * N + H + lane));
+            e0 = C2<T>{e0.re - f0.im, e0.im + f0.re};
+            e1 = C2<T>{e1.re - f1.im, e1.im + f1.re};
+          }
+          const C2<T> x{e0.re + sg * e1.re, e0.im + sg * e1.im};
+          pre[h][c] = hp ? cmul(x, tm) : x;
+        }
+      }
+      C2<T> a[V], v[V];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h) wave_sync();
+#pragma unroll
+        for (int c = 0; c < GPWH; ++c) s[pl_col(k0 + wc0 + c, PCX) + pad(lane)] = pre[h][c];
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < V; ++r) v[r] = conjc(col[pad(th + r * TLH)]);
+        wave_sync();
+        fwd_from_g<T, H, V, 0, false>(PadLine<T>{col}, th, v, twh);
+        if (!h) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) a[i] = conjc(v[i]);
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int b = 0; b < V / RLH; ++b)
+#pragma unroll
+        for (int r = 0; r < RLH; ++r) {
+          const int pp = pl_pos<T, H>(th, b, r), i = b * RLH + r;
+          col[pad(pp)] = a[i] + cmul(conjc(twist[2 * pp + hp]), conjc(v[i]));
+        }
+    }
+  }
+  __syncthreads();
+  // x: the block's rows 2j and 2j+1 (y = 4j + hp and 4j + 2 + hp) as
+  // Z = X_a + i X_b, as in the whole-plane form; task 2j + h its exchange
+  // space and output place
+  const int t = tid % TL, grp = tid / TL;
+  auto xat = [&](int p, int k) -> C2<T> {  // X(k) of block row p, 0 <= k <= N
+    const C2<T> c = s[pl_col(k == N ? 0 : k, PCX) + pad(p)];
+    return k == 0 ? C2<T>{c.re, (T)0} : (k == N ? C2<T>{c.im, (T)0} : c);
+  };
+  constexpr int XR = (H + GROUPS - 1) / GROUPS;
+  C2<T> v[XR][V];
+#pragma unroll
+  for (int u = 0; u < XR; ++u) {
+    const int task = grp + u * GROUPS;
+    if (task < H) {
+      const int j = task >> 1, h = task & 1;
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        const int k = 2 * (t + r * TL) + h;
+        C2<T> zz;
+        if (k <= N) {
+          const C2<T> A = xat(2 * j, k), B = xat(2 * j + 1, k);
+          zz = C2<T>{A.re - B.im, A.im + B.re};
+        } else {
+          const C2<T> A = xat(2 * j, L - k), B = xat(2 * j + 1, L - k);
+          zz = C2<T>{A.re + B.im, B.re - A.im};
+        }
+        v[u][r] = conjc(zz);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < XR; ++u) {
+    const int task = grp + u * GROUPS;
+    if (task < H) fwd_from_g<T, N, V, 0, true>(StrLine<T>{s + pad(task), PCX}, t, v[u], tw);
+  }
+  __syncthreads();
+  const gp<T> ph = glb(d.phi + (size_t)z * N * N);
+  for (int i = tid; i < (H / 2) * N; i += NT) {
+    const int j = i / N, n = i - j * N;
+    const C2<T> A = conjc(s[pl_col(n, PCX) + pad(2 * j)]), B = conjc(s[pl_col(n, PCX) + pad(2 * j + 1)]);
+    const C2<T> zz = A + cmul(conjc(twist[n]), B);
+    ph[(size_t)(4 * j + hp) * N + n] = zz.re;
+    ph[(size_t)(4 * j + 2 + hp) * N + n] = zz.im;
+  }
+}
+
 template <typename T, int L, int V, int NT, int PASS>
 __device__ __forceinline__ void run_tile(const SolveDesc<T>& d, int tile, C2<T>* s,
                                          const C2<T>* __restrict__ tw) {
@@ -1324,9 +1456,17 @@ static bool plane_ok(int N) {
 template <typename T>
 static bool plane_nt_ok(int N, int nt, bool inv) {
   // FP64 at 1024 threads would leave too few registers per lane; the
-  // half-plane forward has 256 or 512
+  // half-plane passes have 256 or 512 (the inverse at 1024: whole planes)
   if (!inv && N == 128 && PH<T, 128>::fits) return nt == 256 || nt == 512;
   return plane_ok<T>(N) && (nt == 256 || nt == 512 || (nt == 1024 && sizeof(T) == 4));
+}
+
+// Tables of the plane passes: lines of N (16 values per lane), the twist,
+// and where the half-plane passes run, the lines of N/2 of the inverse.
+template <typename T>
+static bool plane_tables(int N, hipStream_t st) {
+  if (!twiddles<T>(N, 16, st) || !twist_table<T>(N, st)) return false;
+  return !(N == 128 && PH<T, 128>::fits) || twiddles<T>(N / 2, 16, st);
 }
 
 template <typename T, int N>
@@ -1334,12 +1474,23 @@ static void launch_plane_n(bool inv, const SolveDesc<T>* solves, int nsolves, in
                            const C2<T>* tw, const C2<T>* twist, hipStream_t st) {
   if constexpr (PL<T, N>::fits) {
     if constexpr (PH<T, N>::fits) {
-      if (!inv) {  // half a plane per block; 1024 threads would idle half the groups
-        const dim3 grid(2 * nsolves * N);
+      const dim3 grid(2 * nsolves * N);  // half a plane per block
+      if (!inv) {  // 256 or 512 threads: 1024 would idle half the groups
         if (nt == 256)
           hipLaunchKernelGGL((k_plane_fwd_h<T, N, 256>), grid, dim3(256), 0, st, solves, reset, tw, twist);
         else
           hipLaunchKernelGGL((k_plane_fwd_h<T, N, 512>), grid, dim3(512), 0, st, solves, reset, tw, twist);
+        return;
+      }
+      // the inverse: 256 or 512 threads take half a plane (its y lines of
+      // N/2 need their own table, made with the plan; without it the
+      // whole-plane inverse runs), 1024 the whole plane
+      const C2<T>* twh = nt == 1024 ? nullptr : twiddles<T>(N / 2, 16, st, false);
+      if (twh) {
+        if (nt == 256)
+          hipLaunchKernelGGL((k_plane_inv_h<T, N, 256>), grid, dim3(256), 0, st, solves, reset, tw, twist, twh);
+        else
+          hipLaunchKernelGGL((k_plane_inv_h<T, N, 512>), grid, dim3(512), 0, st, solves, reset, tw, twist, twh);
         return;
       }
     }
@@ -1526,7 +1677,7 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
   }
   const C2<T>* twh = plane ? twiddles<T>(N, 16, st) : nullptr;
   const C2<T>* twist = plane ? twist_table<T>(N, st) : nullptr;
-  if (plane && (!twh || !twist)) {
+  if (plane && (!twh || !twist || !plane_tables<T>(N, st))) {
     set_error("twiddle table allocation failed");
     return SBX_ENOMEM;
   }
@@ -1742,7 +1893,7 @@ sbx_status plan_create(SolvePlan<T>& p, const SolveDesc<T>* descs, int n, hipStr
       g.tw[q] = (const void*)tw;
     }
     g.twist = nullptr;
-    if (g.form == 3 && !(g.twist = (const void*)twist_table<T>(g.N, st))) {
+    if (g.form == 3 && (!(g.twist = (const void*)twist_table<T>(g.N, st)) || !plane_tables<T>(g.N, st))) {
       set_error("twiddle table allocation failed");
       return SBX_ENOMEM;
     }
@@ -1797,7 +1948,7 @@ sbx_status prepare_twiddles(int N, hipStream_t st) {
       set_error("twiddle table allocation failed");
       return SBX_ENOMEM;
     }
-  if (plane_ok<T>(N) && (!twiddles<T>(N, 16, st) || !twist_table<T>(N, st))) {
+  if (plane_ok<T>(N) && !plane_tables<T>(N, st)) {
     set_error("twiddle table allocation failed");
     return SBX_ENOMEM;
   }

@@ -154,7 +154,8 @@ def test_fft_forms_match_oracle(sbx, torch, form, N, q, prec):
     as two half-length transforms) or five line passes, against the oracle's
     FFT convolution (Eqs. 3-5), three solves per batch (at N = 128 in FP32
     the plane forward takes the even and the odd kx columns of a plane in
-    two blocks).  FP64 at N = 128 has
+    two blocks, the inverse the even and the odd rows, or whole planes,
+    as the tuner times them).  FP64 at N = 128 has
     no plane form (its plane does not fit in LDS), nor has N = 16; they run
     five passes under either pin."""
     rng = _rng(3000 + N + form + 10 * prec)
