@@ -491,6 +491,15 @@ sbx_status sbx_set_fft_schedule(int32_t v);
  * use five passes whatever the pin.  SBX_EINVAL for other values. */
 sbx_status sbx_set_fft_form(int32_t form);
 
+/* Block size of the plane-fused passes (form 3, Eqs. 3-5) for plans made
+ * from now on: 256, 512 or 1024 threads, or 0 (the default: the tuner times
+ * every block size a pass has and keeps the fastest).  At n = 128 in FP32,
+ * 256 and 512 run the half-plane passes (two blocks per plane), and 1024
+ * the whole-plane inverse; the forward pass there has no 1024 and, like
+ * every pass without the pinned size, is still tuned over its own.
+ * Process-wide, like the other pins.  SBX_EINVAL for other values. */
+sbx_status sbx_set_plane_threads(int32_t nt);
+
 /* The launch shapes the tuner has chosen so far in this process, one line
  * per precision, grid size, solve count and pass ("fp32 N=128 x5 form=5
  * zpass nt=256 grid=1024 v=16"; grid=tiles: one block per tile; the plane

@@ -141,6 +141,9 @@ sbx_status set_fft_schedule(int v);
 // Pin the form of plans tuned from now on: 3 (plane-fused passes, where a
 // plane fits in LDS), 5 (five line passes) or 0 (time both).  Process-wide.
 sbx_status set_fft_form(int f);
+// Pin the block size of the plane passes tuned from now on: 256, 512, 1024
+// or 0 (time all).  Process-wide.
+sbx_status set_plane_threads(int nt);
 
 // Whether launch shapes for this precision and mix of grid sizes are cached.
 bool tuning_cached(int esz, std::vector<int> mix);

@@ -1533,8 +1533,9 @@ struct TuneKey {
   int esz, N, count;
   int pin = 0;   // the pinned line schedule when the key was tuned (0: none)
   int fpin = 0;  // the pinned form (3 or 5 passes; 0: none)
+  int npin = 0;  // the pinned block size of the plane passes (0: none)
   bool operator==(const TuneKey& o) const {
-    return esz == o.esz && N == o.N && count == o.count && pin == o.pin && fpin == o.fpin;
+    return esz == o.esz && N == o.N && count == o.count && pin == o.pin && fpin == o.fpin && npin == o.npin;
   }
 };
 
@@ -1553,6 +1554,19 @@ static std::atomic<int> g_pin_v{0};
 // Form pinned for plans tuned from now on (0: the tuner times both where
 // the plane form exists).
 static std::atomic<int> g_pin_form{0};
+// Block size of the plane passes pinned for plans tuned from now on (0: the
+// tuner times every one a pass has; a pass without the pinned one still
+// times its own).
+static std::atomic<int> g_pin_nt{0};
+
+sbx_status set_plane_threads(int nt) {
+  if (nt != 0 && nt != 256 && nt != 512 && nt != 1024) {
+    set_error("plane block size must be 0 (tuned), 256, 512 or 1024");
+    return SBX_EINVAL;
+  }
+  g_pin_nt.store(nt);
+  return SBX_OK;
+}
 
 sbx_status set_fft_form(int f) {
   if (f != 0 && f != 3 && f != 5) {
@@ -1576,7 +1590,7 @@ static std::mutex g_tune_mu;
 static std::vector<std::pair<TuneKey, Tuned>> g_tune;
 
 static TuneKey key_now(int esz, int N, int count) {
-  return TuneKey{esz, N, count, g_pin_v.load(), g_pin_form.load()};
+  return TuneKey{esz, N, count, g_pin_v.load(), g_pin_form.load(), g_pin_nt.load()};
 }
 
 static bool tune_lookup(const TuneKey& k, Tuned& out) {
@@ -1740,11 +1754,13 @@ static sbx_status tune_group(const SolveDesc<T>* d_solves, const SolveDesc<T>* h
     float tz = 0.f;
     SBX_TRY(tune_pass(5, plane_t.sh[2], tz));
     t3 = tz;
+    const int npin = g_pin_nt.load();
     for (int q : {0, 3}) {
       float best = 1e30f;
       PassShape pick{256, 0, 0};
+      const bool pinned = npin && plane_nt_ok<T>(N, npin, q == 3);
       for (int nt : {256, 512, 1024}) {
-        if (!plane_nt_ok<T>(N, nt, q == 3)) continue;
+        if (!plane_nt_ok<T>(N, nt, q == 3) || (pinned && nt != npin)) continue;
         float ms = 0.f;
         SBX_TRY(time_it([&] { launch_plane<T>(q == 3, d_solves, N, count, nt, nullptr, twh, twist, st); }, ms));
         if (ms < best) {

@@ -349,6 +349,8 @@ sbx_status sbx_set_fft_schedule(int32_t v) { return set_fft_schedule((int)v); }
 
 sbx_status sbx_set_fft_form(int32_t f) { return set_fft_form((int)f); }
 
+sbx_status sbx_set_plane_threads(int32_t nt) { return set_plane_threads((int)nt); }
+
 int64_t sbx_fft_tuning_report(char* out, int64_t cap) {
   const std::string r = tuning_report();
   if (out && cap > 0) {

@@ -128,6 +128,7 @@ def _load():
         "sbx_poisson_green": (S, [P, P, dp]),
         "sbx_poisson_bytes": (I64, [P]),
         "sbx_set_fft_schedule": (S, [I32]),
+        "sbx_set_plane_threads": (S, [I32]),
         "sbx_set_fft_form": (S, [I32]),
         "sbx_fft_tuning_report": (I64, [C.c_char_p, I64]),
     }
@@ -198,6 +199,12 @@ def sbx_set_fft_form(form):
     passes (where a plane fits in LDS), 5 line passes, 0 the tuner's
     choice."""
     _check(_lib.sbx_set_fft_form(int(form)))
+
+
+def sbx_set_plane_threads(nt):
+    """Pin the block size of the plane-fused passes (256, 512 or 1024) for
+    plans made from now on; 0 lets the tuner choose."""
+    _check(_lib.sbx_set_plane_threads(int(nt)))
 
 
 def sbx_fft_tuning_report() -> str:

@@ -79,3 +79,16 @@ def test_fft_form_pin_host_only():
         with pytest.raises(sbx.SbxError):
             sbx.sbx_set_fft_form(bad)
     sbx.sbx_set_fft_form(0)
+
+
+def test_plane_threads_pin_host_only():
+    """sbx_set_plane_threads takes 0, 256, 512 or 1024 and rejects anything
+    else with SBX_EINVAL (host state only: no device call)."""
+    from paper_1210_1736_amd import sbx
+    for nt in (256, 512, 1024, 0):
+        sbx.sbx_set_plane_threads(nt)
+    for bad in (-1, 64, 128, 300, 2048):
+        with pytest.raises(sbx.SbxError) as e:
+            sbx.sbx_set_plane_threads(bad)
+        assert e.value.status == sbx.SBX_EINVAL
+    sbx.sbx_set_plane_threads(0)

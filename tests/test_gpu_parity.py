@@ -182,6 +182,38 @@ def test_fft_forms_match_oracle(sbx, torch, form, N, q, prec):
         assert np.max(np.abs(g - ref)) <= tol * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("nt", [256, 512, 1024])
+def test_plane_block_sizes_match_oracle(sbx, torch, nt):
+    """128^3 FP32 with the plane form and each block size pinned in turn:
+    256 and 512 threads run both half-plane passes (even and odd kx columns
+    forward, even and odd rows y inverse), 1024 the whole-plane inverse
+    after the half-plane forward (which has no 1024); three solves of
+    different fill against the oracle's FFT convolution (Eqs. 3-5)."""
+    N, R, q = 128, 2.0, 0.25
+    rng = _rng(4100 + nt)
+    Ms = []
+    for b in range(3):
+        M = np.zeros((N, N, N))
+        cells = rng.integers(0, N, size=(N * N // (2 + b), 3))
+        np.add.at(M, tuple(cells.T), rng.uniform(0.1, 1.0, cells.shape[0]))
+        Ms.append(T.rounded(M, 0))
+    sbx.sbx_set_fft_form(3)
+    sbx.sbx_set_plane_threads(nt)
+    try:
+        got = _solve_gpu(sbx, torch, N, R, q, Ms, 0, G=0.7)
+        rep = sbx.sbx_fft_tuning_report()
+    finally:
+        sbx.sbx_set_fft_form(0)
+        sbx.sbx_set_plane_threads(0)
+    assert f"fp32 N={N} x3 form=3 plane_inv nt={nt}" in rep
+    if nt != 1024:
+        assert f"fp32 N={N} x3 form=3 plane_fwd nt={nt}" in rep
+    Hh, _ = O.green_hat(O.Level(N, R, q))
+    for M, g in zip(Ms, got):
+        ref = O.solve_fft(M, Hh, G=0.7)
+        assert np.max(np.abs(g - ref)) <= 3e-6 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_plane_form_in_the_step(sbx, prec):
     """The galaxy's fields and forces with the plane-fused form pinned (its
