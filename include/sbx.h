@@ -475,16 +475,16 @@ sbx_status sbx_set_fft_schedule(int32_t v);
 /* Form of the solves (Eqs. 3-5).  form = 5: five passes of line
  * transforms (x, y, z with the Green's multiply, inverse y, inverse x).
  * form = 3: where one z plane's half spectrum fits in the 160 KB of LDS of
- * a compute unit (n <= 128 in FP32, n <= 64 in FP64, n >= 32), three
+ * a compute unit (32 <= n <= 128; at n = 128 half a plane per block), three
  * passes: the x and y transforms of one plane in one block, the z pass,
  * and the inverse y and x transforms of one plane in one block, so the
  * x-transformed planes never go to device memory (about 30% fewer bytes
  * per solve); each padded length-2n line transform is done as two
- * length-n transforms of its even and odd frequencies (at n = 128 in FP32
+ * length-n transforms of its even and odd frequencies (at n = 128
  * the forward plane pass takes the even and the odd x frequencies of a
  * plane in two blocks, with 256 or 512 threads; the inverse takes the even
- * and the odd rows of a plane in two blocks with 256 or 512 threads, or a
- * whole plane with 1024).  form = 0 (the
+ * and the odd rows of a plane in two blocks with 256 or 512 threads, or in
+ * FP32 also a whole plane with 1024).  form = 0 (the
  * default): the tuner times both the first time a precision, grid size and
  * solve count is planned and keeps the faster.  Like the schedule pin,
  * process-wide, for plans made from now on; sizes without the plane form
@@ -493,9 +493,9 @@ sbx_status sbx_set_fft_form(int32_t form);
 
 /* Block size of the plane-fused passes (form 3, Eqs. 3-5) for plans made
  * from now on: 256, 512 or 1024 threads, or 0 (the default: the tuner times
- * every block size a pass has and keeps the fastest).  At n = 128 in FP32,
- * 256 and 512 run the half-plane passes (two blocks per plane), and 1024
- * the whole-plane inverse; the forward pass there has no 1024 and, like
+ * every block size a pass has and keeps the fastest).  At n = 128, 256
+ * and 512 run the half-plane passes (two blocks per plane), and 1024 the
+ * whole-plane inverse (FP32 only); the forward pass there has no 1024 and, like
  * every pass without the pinned size, is still tuned over its own.
  * Process-wide, like the other pins.  SBX_EINVAL for other values. */
 sbx_status sbx_set_plane_threads(int32_t nt);

@@ -11,12 +11,13 @@
 //   inv_x : E[z][y][kx]    (kx <= N)    -> phi[z][y][x] (complex-to-real, keep x < N)
 // Every pass reads whole lines (contiguous); the transposes are done on the
 // write side, through LDS, in runs of at least 128 bytes.
-// Where a z plane's half spectrum fits in LDS (32 <= N <= 128 in FP32, N <= 64 in
-// FP64) the same solve can run in three passes: plane forward (x and y of
+// Where a z plane's half spectrum fits in LDS (32 <= N <= 64; at N = 128
+// half of it, in FP32 and FP64) the same solve can run in three passes: plane forward (x and y of
 // one plane in one block) -> P[z][kx][ky'] (in C; ky' = m for ky = 2m,
 // N + m for 2m + 1), the z pass on that layout -> D, plane inverse (inverse
-// y and x of one plane) -> phi.  At N = 128 in FP32 the plane passes can
-// run as two blocks per plane, each in half the LDS: the forward one for
+// y and x of one plane) -> phi.  At N = 128 the plane passes can run as
+// two blocks per plane, each in half the LDS (two such blocks per CU in
+// FP32, one in FP64, whose whole plane does not fit): the forward one for
 // the even and one for the odd kx columns, the inverse one for the even
 // and one for the odd rows y.  The tuner times both forms (and for the
 // inverse, whole or half planes) and keeps the faster per precision, grid

@@ -586,8 +586,8 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
 
 // ------------------------------------------------- plane-fused passes ---
 // When a z plane's half spectrum fits in LDS (32 <= N <= 128 in FP32, N <= 64 in
-// FP64) the forward x and y transforms of one plane run in one block, and
-// so do the inverse y and x ones: a solve is three passes (plane forward,
+// FP64; at N = 128 half a plane, below) the forward x and y transforms of
+// one plane run in one block, and so do the inverse y and x ones: a solve is three passes (plane forward,
 // z, plane inverse) instead of five, and the x-transformed planes never go
 // to memory.  A length-2N transform of N nonzero inputs is two length-N
 // transforms, F(2m) = DFT_N(f)(m) and F(2m+1) = DFT_N(f w^n)(m) with
@@ -888,7 +888,8 @@ struct PH {
   static constexpr int XL = XLX > XLY ? XLX : XLY;
   static constexpr int XP = PL<T, N>::XP;
   static constexpr int LDS = XL + XP;
-  static constexpr bool fits = N == 128 && sizeof(T) == 4 && 2 * LDS * (int)sizeof(C2<T>) <= 160 * 1024;
+  // FP32: two blocks per CU; FP64 (whose whole plane does not fit): one
+  static constexpr bool fits = N == 128 && LDS * (int)sizeof(C2<T>) * (sizeof(T) == 4 ? 2 : 1) <= 160 * 1024;
 };
 
 template <typename T, int N, int NT>
@@ -1451,7 +1452,8 @@ static const C2<T>* twist_table(int N, hipStream_t st, bool create = true) {
 // for this block size.
 template <typename T>
 static bool plane_ok(int N) {
-  return (N == 32 && PL<T, 32>::fits) || (N == 64 && PL<T, 64>::fits) || (N == 128 && PL<T, 128>::fits);
+  return (N == 32 && PL<T, 32>::fits) || (N == 64 && PL<T, 64>::fits) ||
+         (N == 128 && (PL<T, 128>::fits || PH<T, 128>::fits));
 }
 template <typename T>
 static bool plane_nt_ok(int N, int nt, bool inv) {
@@ -1472,7 +1474,7 @@ static bool plane_tables(int N, hipStream_t st) {
 template <typename T, int N>
 static void launch_plane_n(bool inv, const SolveDesc<T>* solves, int nsolves, int nt, int* reset,
                            const C2<T>* tw, const C2<T>* twist, hipStream_t st) {
-  if constexpr (PL<T, N>::fits) {
+  if constexpr (PL<T, N>::fits || PH<T, N>::fits) {
     if constexpr (PH<T, N>::fits) {
       const dim3 grid(2 * nsolves * N);  // half a plane per block
       if (!inv) {  // 256 or 512 threads: 1024 would idle half the groups
@@ -1494,19 +1496,21 @@ static void launch_plane_n(bool inv, const SolveDesc<T>* solves, int nsolves, in
         return;
       }
     }
-    auto go = [&](auto ntc) {
-      constexpr int NT = decltype(ntc)::value;
-      if (inv)
-        hipLaunchKernelGGL((k_plane_inv<T, N, NT>), dim3(nsolves * N), dim3(NT), 0, st, solves, reset, tw,
-                           twist);
-      else
-        hipLaunchKernelGGL((k_plane_fwd<T, N, NT>), dim3(nsolves * N), dim3(NT), 0, st, solves, reset, tw,
-                           twist);
-    };
-    if (nt == 256) go(std::integral_constant<int, 256>());
-    else if constexpr (sizeof(T) == 8) go(std::integral_constant<int, 512>());
-    else if (nt == 512) go(std::integral_constant<int, 512>());
-    else go(std::integral_constant<int, 1024>());
+    if constexpr (PL<T, N>::fits) {  // whole planes (FP64 at N = 128 has none)
+      auto go = [&](auto ntc) {
+        constexpr int NT = decltype(ntc)::value;
+        if (inv)
+          hipLaunchKernelGGL((k_plane_inv<T, N, NT>), dim3(nsolves * N), dim3(NT), 0, st, solves, reset, tw,
+                             twist);
+        else
+          hipLaunchKernelGGL((k_plane_fwd<T, N, NT>), dim3(nsolves * N), dim3(NT), 0, st, solves, reset, tw,
+                             twist);
+      };
+      if (nt == 256) go(std::integral_constant<int, 256>());
+      else if constexpr (sizeof(T) == 8) go(std::integral_constant<int, 512>());
+      else if (nt == 512) go(std::integral_constant<int, 512>());
+      else go(std::integral_constant<int, 1024>());
+    }
   }
 }
 
@@ -1979,6 +1983,10 @@ sbx_status run_solves_noalloc(const SolveDesc<T>* d_solves, int nsolves, int N, 
     for (auto& sh : a.sh) sh = PassShape{256, 0, 0};
   const C2<T>* tw[kPasses] = {};
   const C2<T>* twist = a.form == 3 ? twist_table<T>(N, st, false) : nullptr;
+  if (a.form == 3 && N == 128 && PH<T, 128>::fits && !twiddles<T>(N / 2, 16, st, false)) {
+    set_error("no twiddle table for this grid size on this device (create a plan first)");
+    return SBX_ESTATE;
+  }
   for (int q = 0; q < kPasses; ++q) {
     if (a.form == 3 && (q == 1 || q == 4)) continue;
     tw[q] = (a.form == 3 && q != 2) ? twiddles<T>(N, 16, st, false) : twiddles<T>(2 * N, a.sh[q].v, st, false);

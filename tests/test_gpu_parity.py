@@ -152,12 +152,11 @@ def test_fft_forms_match_oracle(sbx, torch, form, N, q, prec):
     """Each form of the solve pinned in turn: three plane-fused passes (x
     and y of one plane in LDS; even and odd frequencies of each padded line
     as two half-length transforms) or five line passes, against the oracle's
-    FFT convolution (Eqs. 3-5), three solves per batch (at N = 128 in FP32
-    the plane forward takes the even and the odd kx columns of a plane in
-    two blocks, the inverse the even and the odd rows, or whole planes,
-    as the tuner times them).  FP64 at N = 128 has
-    no plane form (its plane does not fit in LDS), nor has N = 16; they run
-    five passes under either pin."""
+    FFT convolution (Eqs. 3-5), three solves per batch (at N = 128 the
+    plane forward takes the even and the odd kx columns of a plane in two
+    blocks, the inverse the even and the odd rows, or in FP32 whole planes,
+    as the tuner times them).  N = 16 has no plane form and runs five
+    passes under either pin."""
     rng = _rng(3000 + N + form + 10 * prec)
     R = 2.0
     Ms = []
@@ -172,7 +171,7 @@ def test_fft_forms_match_oracle(sbx, torch, form, N, q, prec):
         rep = sbx.sbx_fft_tuning_report()
     finally:
         sbx.sbx_set_fft_form(0)
-    want = form if ((prec == sbx.SBX_FP32 or N <= 64) and N >= 32) else 5
+    want = form if N >= 32 else 5
     esz = "fp64" if prec == sbx.SBX_FP64 else "fp32"
     assert f"{esz} N={N} x3 form={want} " in rep
     Hh, _ = O.green_hat(O.Level(N, R, q))
@@ -182,36 +181,39 @@ def test_fft_forms_match_oracle(sbx, torch, form, N, q, prec):
         assert np.max(np.abs(g - ref)) <= tol * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("nt", [256, 512, 1024])
-def test_plane_block_sizes_match_oracle(sbx, torch, nt):
-    """128^3 FP32 with the plane form and each block size pinned in turn:
-    256 and 512 threads run both half-plane passes (even and odd kx columns
-    forward, even and odd rows y inverse), 1024 the whole-plane inverse
-    after the half-plane forward (which has no 1024); three solves of
-    different fill against the oracle's FFT convolution (Eqs. 3-5)."""
+@pytest.mark.parametrize("nt,prec", [(256, 0), (512, 0), (1024, 0), (256, 1), (512, 1)])
+def test_plane_block_sizes_match_oracle(sbx, torch, nt, prec):
+    """128^3 with the plane form and each block size pinned in turn: 256
+    and 512 threads run both half-plane passes (even and odd kx columns
+    forward, even and odd rows y inverse; in FP64 the only plane form at
+    this size), 1024 the FP32 whole-plane inverse after the half-plane
+    forward (which has no 1024); three solves of different fill against
+    the oracle's FFT convolution (Eqs. 3-5)."""
     N, R, q = 128, 2.0, 0.25
-    rng = _rng(4100 + nt)
+    rng = _rng(4100 + nt + prec)
     Ms = []
     for b in range(3):
         M = np.zeros((N, N, N))
         cells = rng.integers(0, N, size=(N * N // (2 + b), 3))
         np.add.at(M, tuple(cells.T), rng.uniform(0.1, 1.0, cells.shape[0]))
-        Ms.append(T.rounded(M, 0))
+        Ms.append(T.rounded(M, prec))
     sbx.sbx_set_fft_form(3)
     sbx.sbx_set_plane_threads(nt)
     try:
-        got = _solve_gpu(sbx, torch, N, R, q, Ms, 0, G=0.7)
+        got = _solve_gpu(sbx, torch, N, R, q, Ms, prec, G=0.7)
         rep = sbx.sbx_fft_tuning_report()
     finally:
         sbx.sbx_set_fft_form(0)
         sbx.sbx_set_plane_threads(0)
-    assert f"fp32 N={N} x3 form=3 plane_inv nt={nt}" in rep
+    esz = "fp64" if prec == sbx.SBX_FP64 else "fp32"
+    assert f"{esz} N={N} x3 form=3 plane_inv nt={nt}" in rep
     if nt != 1024:
-        assert f"fp32 N={N} x3 form=3 plane_fwd nt={nt}" in rep
+        assert f"{esz} N={N} x3 form=3 plane_fwd nt={nt}" in rep
     Hh, _ = O.green_hat(O.Level(N, R, q))
+    tol = 1e-11 if prec == sbx.SBX_FP64 else 3e-6
     for M, g in zip(Ms, got):
         ref = O.solve_fft(M, Hh, G=0.7)
-        assert np.max(np.abs(g - ref)) <= 3e-6 * np.max(np.abs(ref))
+        assert np.max(np.abs(g - ref)) <= tol * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("prec", PRECS)
