@@ -85,7 +85,7 @@ KERNEL_SOURCES = ["paper_1210_1736_amd/csrc/particles.hip", "paper_1210_1736_amd
                   "paper_1210_1736_amd/csrc/common.h", "paper_1210_1736_amd/csrc/fft.hip",
                   "paper_1210_1736_amd/csrc/fft.h"]
 PROFILE = "profiles/step_kernels_disc_galaxy_3x128_fp32.md"
-PHASE_KERNEL = {"deposit": "k_deposit<float>", "force": "k_force<float, 1>", "pre": "k_pre<float>"}
+PHASE_KERNEL = {"deposit": "k_deposit<float, false>", "force": "k_force<float, 1>", "pre": "k_pre<float>"}
 
 
 def measured_traffic(phase):

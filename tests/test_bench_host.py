@@ -44,7 +44,7 @@ def _summary(tmp_path, digest, force_total):
         "| kernel | dispatches | read MB/dispatch | written MB/dispatch | total MB/dispatch |",
         "|---|---|---|---|---|",
         f"| k_force<float, 1> | 9 | 300.00 | 200.00 | {force_total:.2f} |",
-        "| k_deposit<float> | 11 | 150.00 | 50.00 | 200.00 |",
+        "| k_deposit<float, false> | 11 | 150.00 | 50.00 | 200.00 |",
     ])
     p = tmp_path / "summary.md"
     p.write_text(text + "\n")
@@ -70,6 +70,17 @@ def test_measured_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     assert bench.measured_traffic("zpass") is None        # no kernel mapped to the phase
     src.write_text("kernel source, changed\n")              # counters no longer describe it
     assert bench.measured_traffic("force") is None
+
+
+def test_phase_kernels_named_in_the_committed_profile():
+    """Every kernel the bench maps a phase to has a row (5 cells) in the
+    committed counter summary, under the name the profiler gives it."""
+    import os
+    text = open(os.path.join(bench.ROOT, bench.PROFILE)).read()
+    rows = {[c.strip() for c in l.strip("|").split("|")][0] for l in text.splitlines()
+            if l.startswith("|") and len(l.strip("|").split("|")) == 5}
+    for phase, name in bench.PHASE_KERNEL.items():
+        assert name in rows, (phase, name)
 
 
 def test_measured_traffic_missing_files(tmp_path, monkeypatch):
