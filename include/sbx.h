@@ -503,7 +503,7 @@ sbx_status sbx_set_plane_threads(int32_t nt);
 /* The launch shapes the tuner has chosen so far in this process, one line
  * per precision, grid size, solve count and pass ("fp32 N=128 x5 form=5
  * zpass nt=256 grid=1024 v=16"; grid=tiles: one block per tile; the plane
- * passes of form 3 are "plane_fwd nt=512" and "plane_inv nt=1024"), and
+ * passes of form 3 are "plane_fwd nt=512" and "plane_inv nt=512"), and
  * where both forms were timed, one more line with the tuner's time of the
  * whole solve set in each ("... timed five-pass 0.247 ms, plane 0.233 ms").
  * Writes at most cap bytes including a terminating NUL into out (may be
