@@ -216,12 +216,15 @@ def test_plane_block_sizes_match_oracle(sbx, torch, nt, prec):
         assert np.max(np.abs(g - ref)) <= tol * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("N", [64, 128])
 @pytest.mark.parametrize("prec", PRECS)
-def test_plane_form_in_the_step(sbx, prec):
+def test_plane_form_in_the_step(sbx, prec, N):
     """The galaxy's fields and forces with the plane-fused form pinned (its
     summed grids 2+3 and 4+5 add their second mass grid in the plane
-    forward pass) against the oracle, to the bars of the five-pass form."""
-    w = T.small_galaxy(scale=0.005, N=64, q=0.5)
+    forward pass) against the oracle, to the bars of the five-pass form;
+    at 128^3 through the half-plane passes (in FP64 the tuner would keep
+    five passes for this solve count)."""
+    w = T.small_galaxy(scale=0.005, N=N, q=0.5)
     sysm, x, v, m, lost, centres, pots = _state_oracle(w, prec)
     sbx.sbx_set_fft_form(3)
     try:
@@ -230,7 +233,7 @@ def test_plane_form_in_the_step(sbx, prec):
         rep = sbx.sbx_fft_tuning_report()
     finally:
         sbx.sbx_set_fft_form(0)
-    assert ("fp64" if prec == sbx.SBX_FP64 else "fp32") + " N=64 x5 form=3 plane_fwd" in rep
+    assert ("fp64" if prec == sbx.SBX_FP64 else "fp32") + f" N={N} x5 form=3 plane_fwd" in rep
     cg = ctx.sbx_get_centres()
     cls_ref, idx_ref = O.classify(x, sysm.h[0], cg[0])
     pots = sysm.potentials(x, m, w.gal, lost, cg)
