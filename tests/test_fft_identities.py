@@ -2,8 +2,10 @@
 with numpy's FFT as the reference (no GPU, no oracle): a zero-padded
 length-2N transform of N inputs as two length-N transforms, the first N
 outputs of a length-2N inverse from its two halves, two real rows packed
-as one complex line and separated by symmetry, and the padded 2D/3D
-convolution assembled from these pieces in the kernels' layouts."""
+as one complex line and separated by symmetry, the padded 2D/3D
+convolution assembled from these pieces in the kernels' layouts, and the
+two splits of a plane over two blocks (forward by kx parity, inverse by
+row parity)."""
 import numpy as np
 
 
@@ -101,3 +103,52 @@ def test_plane_pipeline_equals_padded_convolution():
             zz = np.fft.ifft(Zs[0::2]) * N + np.conj(w) * np.fft.ifft(Zs[1::2]) * N
             out[z, 2 * j], out[z, 2 * j + 1] = zz.real, zz.imag
     assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_half_plane_forward_by_kx_parity():
+    """Columns kx of one parity take their row spectra from one of the two
+    length-N transforms of each packed row pair only: for kx = 2m + h the
+    padded row spectrum is that transform's output m (times w^n before it
+    for h = 1), and so is the mirror 2N - kx (same parity), so the
+    separation of the packed rows needs nothing from the other parity."""
+    rng = _rng(3)
+    N = 32
+    L = 2 * N
+    w = np.exp(-2j * np.pi * np.arange(N) / L)
+    a, b = rng.standard_normal(N), rng.standard_normal(N)
+    Fa = np.fft.fft(np.concatenate([a, np.zeros(N)]))
+    Fb = np.fft.fft(np.concatenate([b, np.zeros(N)]))
+    z = a + 1j * b
+    for h in (0, 1):
+        Zh = np.fft.fft(z * w ** h)          # the outputs m of parity h
+        for kx in range(h, N, 2):
+            Z = Zh[kx >> 1]
+            R = Zh[(N if kx == 0 else L - kx) >> 1]
+            if kx == 0:                      # X(0) + i X(N) of each row
+                assert np.isclose(Z.real, Fa[0].real) and np.isclose(R.real, Fa[N].real)
+                assert np.isclose(Z.imag, Fb[0].real) and np.isclose(R.imag, Fb[N].real)
+            else:
+                assert np.isclose((Z + np.conj(R)) / 2, Fa[kx])
+                assert np.isclose(-1j * (Z - np.conj(R)) / 2, Fb[kx])
+
+
+def test_half_plane_inverse_by_row_parity():
+    """Rows y = 2p + hp of the first N outputs of a length-2N inverse come
+    from two length-N/2 inverses of folded halves: with E and O the even
+    and odd inputs and s = (-1)^hp, a = IDFT((E(m) + s E(m + N/2))
+    e^{2 pi i m hp / N}), b the same of O, and row 2p + hp is
+    a(p) + w^-(2p+hp) b(p)."""
+    rng = _rng(4)
+    for N in (16, 128):
+        L, H = 2 * N, N // 2
+        w = np.exp(-2j * np.pi * np.arange(N) / L)
+        Q = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+        full = (np.fft.ifft(Q) * L)[:N]
+        E, O = Q[0::2], Q[1::2]
+        for hp in (0, 1):
+            s = -1.0 if hp else 1.0
+            t = np.exp(2j * np.pi * np.arange(H) * hp / N)
+            a = np.fft.ifft((E[:H] + s * E[H:]) * t) * H
+            bb = np.fft.ifft((O[:H] + s * O[H:]) * t) * H
+            y = 2 * np.arange(H) + hp
+            assert np.allclose(a + np.conj(w[y]) * bb, full[y], atol=1e-9)
