@@ -874,8 +874,8 @@ __global__ void __launch_bounds__(NT)
 // transforms every row pair once, for its own outputs, and then the N/2
 // columns kx = 2 kx' + hp along y.  The two blocks of a plane share the
 // rows' loads only.  A block needs about half the LDS of the whole plane,
-// so two run on one CU and one's loads and stores overlap the other's
-// transforms.  Blocks 8 apart (one XCD) take the two halves of a plane, so
+// so in FP32 two run on one CU and one's loads and stores overlap the
+// other's transforms (in FP64, whose whole plane does not fit, one runs).  Blocks 8 apart (one XCD) take the two halves of a plane, so
 // the second finds the rows in that XCD's L2.
 template <typename T, int N>
 struct PH {
