@@ -585,12 +585,13 @@ __device__ __forceinline__ void tile_inv_x(const SolveDesc<T>& d, int tile, C2<T
 }
 
 // ------------------------------------------------- plane-fused passes ---
-// When a z plane's half spectrum fits in LDS (32 <= N <= 128 in FP32, N <= 64 in
-// FP64; at N = 128 half a plane, below) the forward x and y transforms of
-// one plane run in one block, and so do the inverse y and x ones: a solve is three passes (plane forward,
-// z, plane inverse) instead of five, and the x-transformed planes never go
-// to memory.  A length-2N transform of N nonzero inputs is two length-N
-// transforms, F(2m) = DFT_N(f)(m) and F(2m+1) = DFT_N(f w^n)(m) with
+// When a z plane's half spectrum fits in LDS (32 <= N <= 128 in FP32,
+// N <= 64 in FP64; at N = 128 half a plane, below) the forward x and y
+// transforms of one plane run in one block, and so do the inverse y and x
+// ones: a solve is three passes (plane forward, z, plane inverse) instead
+// of five, and the x-transformed planes never go to memory.  A length-2N
+// transform of N nonzero inputs is two length-N transforms,
+// F(2m) = DFT_N(f)(m) and F(2m+1) = DFT_N(f w^n)(m) with
 // w = exp(-2 pi i / 2N); the first N outputs of a length-2N inverse are
 // f(n) = IDFT_N(F(2m))(n) + w^-n IDFT_N(F(2m+1))(n).  So every exchange of
 // a line stays within the N slots of LDS the line occupies.
@@ -875,8 +876,9 @@ __global__ void __launch_bounds__(NT)
 // columns kx = 2 kx' + hp along y.  The two blocks of a plane share the
 // rows' loads only.  A block needs about half the LDS of the whole plane,
 // so in FP32 two run on one CU and one's loads and stores overlap the
-// other's transforms (in FP64, whose whole plane does not fit, one runs).  Blocks 8 apart (one XCD) take the two halves of a plane, so
-// the second finds the rows in that XCD's L2.
+// other's transforms (in FP64, whose whole plane does not fit, one runs).
+// Blocks 8 apart (one XCD) take the two halves of a plane, so the second
+// finds the rows in that XCD's L2.
 template <typename T, int N>
 struct PH {
   static constexpr int V = 16, TL = N / V;
