@@ -383,11 +383,14 @@ static int64_t blocks_grid(const InstInfo& f) {
 }
 
 // ------------------------------------------------------------ zero grids --
+// With the fixed-point assignment the cell masses are not summed in place:
+// the conversion pass writes every one of them after the assignment (and
+// leaves the accumulators cleared), so there is nothing to clear.
 template <typename T>
 __global__ void __launch_bounds__(256) k_zero_grids(const InstDev<T>* __restrict__ inst, Span sp) {
   const int i = span_inst(sp, blockIdx.x);
   const int lb = blockIdx.x - sp.start[i], nb = sp.start[i + 1] - sp.start[i];
-  zero_block(inst[i].grid_block, inst[i].grid_elems, lb, nb);
+  if (!inst[i].fix) zero_block(inst[i].grid_block, inst[i].grid_elems, lb, nb);
 }
 
 // ------------------------------------------------------ loss test and COM --
@@ -527,7 +530,7 @@ __global__ void __launch_bounds__(256)
   const int i = span_inst(sp, blockIdx.x);
   const int lb = blockIdx.x - sp.start[i], nb = sp.start[i + 1] - sp.start[i];
   if (lb == 0) centres_of(inst[i], 1, 0);
-  zero_block(inst[i].grid_block, inst[i].grid_elems, lb, nb);
+  if (!inst[i].fix) zero_block(inst[i].grid_block, inst[i].grid_elems, lb, nb);
 }
 
 // ------------------------------------------------ density-maximum centring --
